@@ -1,0 +1,69 @@
+/*
+ * oracle.h -- declarations of the FP64 CPU oracle (test infrastructure only;
+ * never included by the product library).
+ */
+#ifndef MIHYDRO_ORACLE_H
+#define MIHYDRO_ORACLE_H
+
+#include <stdint.h>
+
+enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1 };
+enum { OR_LIM_MINMOD = 0, OR_LIM_NONE = 1, OR_LIM_VANLEER = 2, OR_LIM_MC = 3,
+       OR_LIM_SUPERBEE = 4 };
+enum { OR_RS_HLLC = 0, OR_RS_HLL = 1, OR_RS_RUSANOV = 2 };
+enum { OR_SRC_COOLING = 1u, OR_SRC_FORCING = 2u, OR_SRC_GRAVITY = 4u };
+#define OR_OU_MAXMODES 64
+
+/* Everything one step needs.  Mirrored field for field by a ctypes Structure
+ * in oracle/__init__.py. */
+typedef struct {
+  int32_t n[3];
+  int32_t bc[3];
+  double h[3];
+  double gamma;
+  double cfl;
+  int32_t limiter;
+  int32_t riemann;
+  uint32_t flags;
+  int32_t ou_every;
+  double cool_lambda0, cool_tc, cool_ts, cool_tfloor;
+  uint64_t ou_seed;
+  double ou_tau, ou_arms, ou_zeta, ou_kmin, ou_kmax;
+  double grav_G;
+  int32_t mg_pre, mg_post, mg_max_cycles, mg_coarsest;
+  double mg_tol;
+  int32_t mg_coarse_sweeps;
+  int32_t pad_;
+} or_config;
+
+void or_primitives(const or_config *c, const double *U, double *W);
+double or_cfl_dt(const or_config *c, const double *U);
+void or_rhs(const or_config *c, const double *U, double *L);
+void or_rk2(const or_config *c, double *U, double dt);
+void or_euler(const or_config *c, double *U, double dt);
+
+double or_cool_temperature(double rho, double T, double dt, double gamma,
+                           double L0, double Tc, double Ts, double Tfloor);
+void or_cool(const or_config *c, double *U, double dt);
+
+void or_ou_gauss(uint64_t seed, int64_t group, int mode, int comp, double out[2]);
+int or_ou_modes(double kmin, double kmax, int32_t *nvec);
+void or_ou_init(const or_config *c, int nmodes, const int32_t *nvec, double *ahat);
+void or_ou_advance(const or_config *c, int nmodes, const int32_t *nvec,
+                   double *ahat, int64_t group, double dt);
+double or_ou_scale(const or_config *c, int nmodes, const double *ahat);
+void or_ou_accel(const or_config *c, int nmodes, const int32_t *nvec,
+                 const double *ahat, double *acc);
+void or_kick(const or_config *c, double *U, const double *acc, double dt);
+
+/* multigrid self-gravity (oracle_mg.c) */
+void or_laplacian(int n, double h, const double *phi, double *out);
+void or_mg_vcycle(const or_config *c, int n, double h, double *phi, const double *F);
+int or_mg_solve(const or_config *c, int n, double h, double *phi, const double *F);
+int or_gravity_accel(const or_config *c, const double *U, double *phi, double *acc);
+
+double or_step(const or_config *c, double *U, double dt_fixed, double dt_cap,
+               int64_t step, int nmodes, const int32_t *nvec, double *ou_ahat,
+               double *phi, int *mg_cycles);
+
+#endif

@@ -1,0 +1,195 @@
+"""Pins of the oracle's source terms (paper Sec. 3.1.1 OU forcing, Sec. 4
+cooling, Sec. 2.1 force-listing kick) against independent facts:
+
+* cooling: the closed form against a high-accuracy adaptive ODE integration
+  (scipy DOP853) of dT/dt = -(gamma-1) rho Lambda(T); monotonicity; floor;
+* OU: the solenoidal/compressive projection (k . a = 0 / k x a = 0), the
+  Parseval normalisation against the grid rms, the DFT of the real-space field
+  (only the forced modes, divergence free), Gaussian statistics of the noise,
+  the stationary variance and e^{-s/tau} autocorrelation of the OU process;
+* kick: exact momentum / energy bookkeeping.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+import oracle
+import workloads as wl
+
+CC = wl.COOLING_CURVE
+
+
+def lam(T):
+    if T >= CC["tc"]:
+        return CC["lambda0"] * math.sqrt(T / CC["tc"])
+    return CC["lambda0"] * math.exp((T - CC["tc"]) / CC["ts"])
+
+
+@pytest.mark.parametrize("rho", [0.1, 1.0, 7.0])
+def test_cooling_closed_form_matches_ode_integration(rho):
+    gam = 5.0 / 3.0
+    for T0 in (10.0, 1.0, 0.05, 0.0101, 0.01, 0.0099, 5e-3, 1e-3, 2e-4):
+        for dt in (1e-4, 1e-2, 0.3, 2.0):
+            Tn = oracle.cool_temperature(rho, T0, dt, gam, CC["lambda0"], CC["tc"], CC["ts"], 0.0)
+            sol = solve_ivp(lambda t, y: [-(gam - 1.0) * rho * lam(y[0])], (0.0, dt), [T0],
+                            method="DOP853", rtol=1e-13, atol=1e-16)
+            Tref = sol.y[0, -1]
+            # the closed form may legitimately go below 0 only far past the floor
+            assert Tn == pytest.approx(Tref, rel=2e-9, abs=1e-13), (T0, dt, Tn, Tref)
+
+
+def test_cooling_monotone_and_floor():
+    gam = 5.0 / 3.0
+    T0 = 3.0
+    prev = T0
+    for dt in np.linspace(0.0, 200.0, 800):
+        Tn = oracle.cool_temperature(2.0, T0, dt, gam, CC["lambda0"], CC["tc"], CC["ts"], CC["tfloor"])
+        assert Tn <= prev + 1e-15
+        assert Tn >= CC["tfloor"]
+        prev = Tn
+    assert prev == CC["tfloor"]
+    assert oracle.cool_temperature(2.0, T0, 0.0, gam, CC["lambda0"], CC["tc"], CC["ts"],
+                                   CC["tfloor"]) == pytest.approx(T0, rel=1e-15)
+
+
+def test_cooling_changes_only_thermal_energy():
+    grid = wl.cube(6)
+    U = wl.random_state(grid.shape, seed=4)
+    c = oracle.make_config(grid.shape, grid.h, flags=oracle.SRC_COOLING)
+    out = oracle.cool(c, U, 0.05)
+    assert np.array_equal(out[:4], U[:4])
+    gam = 5.0 / 3.0
+    ek = 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]
+    T0 = (gam - 1) * (U[4] - ek) / U[0]
+    T1 = (gam - 1) * (out[4] - ek) / U[0]
+    assert np.all(T1 < T0)
+    for q in [(0, 0, 0), (3, 2, 1), (5, 5, 5)]:
+        Tq = oracle.cool_temperature(U[0][q], T0[q], 0.05, gam, CC["lambda0"], CC["tc"], CC["ts"],
+                                     CC["tfloor"])
+        assert T1[q] == pytest.approx(Tq, rel=1e-13)
+
+
+# ------------------------------------------------------------------ OU forcing
+
+def test_ou_mode_set():
+    nv = oracle.ou_modes(1.0, 2.0)
+    assert len(nv) == 16  # 32 integer vectors with 1 <= |n| <= 2, one per +- pair
+    k = np.sqrt((nv ** 2).sum(1))
+    assert np.all((k >= 1) & (k <= 2))
+    full = {tuple(v) for v in nv} | {tuple(-v) for v in nv}
+    assert len(full) == 32
+
+
+def test_ou_noise_statistics():
+    vals = np.array([oracle.ou_gauss(123, g, m, c) for g in range(200) for m in range(16)
+                     for c in range(3)])
+    assert abs(vals.real.mean()) < 0.02 and abs(vals.imag.mean()) < 0.02
+    assert vals.real.var() == pytest.approx(0.5, rel=0.04)
+    assert vals.imag.var() == pytest.approx(0.5, rel=0.04)
+    assert abs(np.corrcoef(vals.real, vals.imag)[0, 1]) < 0.03
+    # the stream depends on the seed
+    assert oracle.ou_gauss(1, 0, 0, 0) != oracle.ou_gauss(2, 0, 0, 0)
+
+
+@pytest.mark.parametrize("zeta", [1.0, 0.0, 0.4])
+def test_ou_projection(zeta):
+    grid = wl.cube(8)
+    c = oracle.make_config(grid.shape, grid.h, flags=oracle.SRC_FORCING, ou_zeta=zeta)
+    nv = oracle.ou_modes(1.0, 2.0)
+    a = oracle.ou_advance(c, nv, oracle.ou_init(c, nv), 0, 0.1)
+    ah = (a[0::2] + 1j * a[1::2]).reshape(-1, 3)
+    div = np.abs((ah * nv).sum(1))
+    curl = np.abs(np.cross(ah, nv)).sum(1)
+    if zeta == 1.0:
+        assert div.max() < 1e-14
+    elif zeta == 0.0:
+        assert curl.max() < 1e-14
+    else:
+        assert div.max() > 1e-3 and curl.max() > 1e-3
+
+
+def test_ou_realspace_field_parseval_and_spectrum():
+    shape = (6, 7, 8)
+    grid = wl.Grid(shape, (1 / 8, 1 / 7, 1 / 6))
+    c = oracle.make_config(shape, grid.h, flags=oracle.SRC_FORCING, ou_arms=1.7)
+    nv = oracle.ou_modes(1.0, 2.0)
+    a = oracle.ou_init(c, nv)
+    acc = oracle.ou_accel(c, nv, a)
+    rms = math.sqrt(np.mean((acc ** 2).sum(0)))
+    assert rms == pytest.approx(1.7, rel=1e-13)
+    # the DFT holds exactly the forced modes and is divergence free
+    F = [np.fft.fftn(acc[i]) for i in range(3)]
+    nz, ny, nx = shape
+    kz, ky, kx = np.meshgrid(np.fft.fftfreq(nz, 1 / nz), np.fft.fftfreq(ny, 1 / ny),
+                             np.fft.fftfreq(nx, 1 / nx), indexing="ij")
+    power = sum(np.abs(f) ** 2 for f in F)
+    forced = np.zeros(shape, bool)
+    for v in nv:
+        for s in (1, -1):
+            forced[(s * v[2]) % nz, (s * v[1]) % ny, (s * v[0]) % nx] = True
+    assert power[~forced].max() < 1e-20 * power.max()
+    div = np.abs(kx * F[0] + ky * F[1] + kz * F[2])
+    assert div.max() < 1e-11 * math.sqrt(power.max())
+    # every component of every mode: coefficient = scale * ahat * (half-cell phase)
+    scale = oracle.ou_scale(c, a)
+    for m, v in enumerate(nv):
+        shift = np.exp(1j * np.pi * (v[0] / nx + v[1] / ny + v[2] / nz))
+        for comp in range(3):
+            ah = complex(a[6 * m + 2 * comp], a[6 * m + 2 * comp + 1])
+            coeff = F[comp][v[2] % nz, v[1] % ny, v[0] % nx] / (nx * ny * nz)
+            assert coeff == pytest.approx(scale * ah * shift, rel=1e-11, abs=1e-14)
+
+
+def test_ou_stationary_variance_and_autocorrelation():
+    grid = wl.cube(8)
+    c = oracle.make_config(grid.shape, grid.h, flags=oracle.SRC_FORCING, ou_seed=9)
+    nv = oracle.ou_modes(1.0, 2.0)
+    a = oracle.ou_init(c, nv)
+    dt, nstep = 0.05, 6000
+    hist = np.empty((nstep, a.size))
+    for s in range(nstep):
+        a = oracle.ou_advance(c, nv, a, s, dt)
+        hist[s] = a
+    # stationary: E|P eta|^2 = trace(P) = 2 per mode (Re and Im each 1/2 per comp)
+    per_mode = (hist ** 2).reshape(nstep, 16, 6).sum(2).mean(0)
+    assert per_mode.mean() == pytest.approx(2.0, rel=0.05)
+    # autocorrelation at lag s*dt follows exp(-s dt / tau)
+    for lag in (2, 10):
+        x, y = hist[:-lag].ravel(), hist[lag:].ravel()
+        r = (x * y).mean() / (x * x).mean()
+        assert r == pytest.approx(math.exp(-lag * dt / 0.5), abs=0.04)
+
+
+def test_kick_bookkeeping():
+    grid = wl.cube(5)
+    U = wl.random_state(grid.shape, seed=8)
+    rng = np.random.default_rng(0)
+    acc = rng.standard_normal((3,) + grid.shape)
+    c = oracle.make_config(grid.shape, grid.h)
+    dt = 0.03
+    out = oracle.kick(c, U, acc, dt)
+    assert np.array_equal(out[0], U[0])
+    for i in range(3):
+        assert np.allclose(out[1 + i] - U[1 + i], U[0] * acc[i] * dt, rtol=0, atol=1e-15)
+    dE = (U[1] * acc[0] + U[2] * acc[1] + U[3] * acc[2]) * dt
+    assert np.allclose(out[4] - U[4], dE, rtol=0, atol=1e-14)
+
+
+def test_step_source_order_forcing_then_cooling():
+    """A full step with forcing and cooling equals RK2, then the kick with the
+    advanced OU modes, then cooling, each on the previous result."""
+    grid = wl.cube(6)
+    U = wl.smooth_random_state(grid.shape, seed=1)
+    c = oracle.make_config(grid.shape, grid.h, flags=oracle.SRC_FORCING | oracle.SRC_COOLING)
+    sim = oracle.Simulation(c, U)
+    a0 = sim.ahat.copy()
+    dt = 0.01
+    sim.advance(1, dt)
+    V = oracle.rk2(c, U, dt)
+    a1 = oracle.ou_advance(c, sim.nvec, a0, 0, dt)
+    V = oracle.kick(c, V, oracle.ou_accel(c, sim.nvec, a1), dt)
+    V = oracle.cool(c, V, dt)
+    assert np.array_equal(sim.U, V)
+    assert np.array_equal(sim.ahat, a1)
