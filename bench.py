@@ -1,0 +1,184 @@
+"""Benchmark of the hot path: one MI355X, the driven-turbulence workload at
+512^3 in fp32 (OU forcing on 1 <= |n| <= 2 with tau = 0.5, exact optically
+thin cooling, CFL 0.4, from rest with rho = 1, p = 1, gamma = 5/3).
+
+A step is one full pass of the method: per-step dt/OU kernel, RK stage 1,
+RK stage 2 with forcing, cooling and the CFL reduction fused.  The timed
+region holds exactly --steps steps, bracketed by device synchronisation; the
+state is resident in HBM before it starts.  Prints one JSON line.
+
+value            cell-updates/s = cells * steps / seconds of the timed region
+roofline         the dominant kernel (RK stage 2) against the MI355X HBM peak:
+                 algorithmic bytes per launch (60 B per cell in fp32: read U1,
+                 read U^n, write U^{n+1}) over its mean duration from HIP events
+                 recorded around every launch on the library's stream
+cpu_baseline     the FP64 oracle on the same physics at 128^3 for 8 steps
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_k_stage_512_fp32.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2512_13403_amd", "csrc", "hydro_kernels.hip")
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stage-2 launch from the committed rocprofv3 PMC summary,
+    or None when missing or when the kernel source changed since."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    rec = {}
+    for line in open(PMC_FILE):
+        if line.startswith("traffic-record:"):
+            for kv in line.split(":", 1)[1].split():
+                k, v = kv.split("=")
+                rec[k] = v
+    if rec.get("kernel_sha256_16") != kernel_hash() or "stage2_bytes" not in rec:
+        return None
+    return float(rec["stage2_bytes"])
+
+
+def cpu_baseline(n=128, steps=8):
+    import numpy as np
+
+    import oracle
+    import workloads as wl
+
+    shape = (n, n, n)
+    c = oracle.make_config(shape, (1.0 / n,) * 3, gamma=5.0 / 3.0, cfl=0.4,
+                           flags=oracle.SRC_FORCING | oracle.SRC_COOLING)
+    sim = oracle.Simulation(c, wl.rest_state(shape))
+    t0 = time.perf_counter()
+    sim.advance(steps)
+    dt = time.perf_counter() - t0
+    threads = oracle.num_threads()
+    return {"value": n ** 3 * steps / dt, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"same physics (forcing + cooling, from rest) at {n}^3 for {steps} steps, "
+                      f"fp64, OpenMP over {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2512_13403_amd as mh
+
+    n = args.n
+    shape = (n, n, n)
+    N = n ** 3
+    gamma = 5.0 / 3.0
+    grid = mh.grid_desc(shape, (1.0 / n,) * 3, dtype=args.dtype, gamma=gamma, cfl=0.4)
+    phys = mh.physics_desc(flags=mh.SRC_FORCING | mh.SRC_COOLING, cool=(0.3, 1e-2, 1e-3, 1e-4),
+                           ou_seed=0, ou_tau=0.5, ou_arms=1.0, ou_zeta=1.0, ou_kmin=1.0,
+                           ou_kmax=2.0)
+    s = mh.Solver(grid, phys)
+    tdt = torch.float32 if args.dtype == "f32" else torch.float64
+    U0 = torch.zeros((5,) + shape, dtype=tdt, device="cuda:0")
+    U0[0] = 1.0
+    U0[4] = 1.0 / (gamma - 1.0)  # rest, rho = 1, p = 1
+    s.set_state(U0)
+    torch.cuda.synchronize()
+    del U0
+    print(f"# warmup {args.warmup} steps at {n}^3 {args.dtype}", file=sys.stderr, flush=True)
+    s.step(args.warmup, 0.0)
+    torch.cuda.synchronize()
+
+    s.set_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(s.stream)
+    s.step(args.steps, 0.0)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms, launches = s.timing()
+    s.set_timing(False)
+    bad, first = s.check()
+    t_sim, nstep = s.clock()
+    print(f"# timed {args.steps} steps: {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms), t = {t_sim:.4f}, "
+          f"bad cells {bad}", file=sys.stderr, flush=True)
+    if bad:
+        raise SystemExit(f"unphysical cells after the run (first at {first})")
+
+    seconds = gpu_ms / 1e3
+    value = N * args.steps / seconds
+    es = 4 if args.dtype == "f32" else 8
+    st2_ms = ms[mh.TIME_STAGE2] / max(launches[mh.TIME_STAGE2], 1)
+    st1_ms = ms[mh.TIME_STAGE1] / max(launches[mh.TIME_STAGE1], 1)
+    bytes2 = 15 * es * N  # read U1, read U^n, write U^{n+1}: 3 x 5 fields
+    bytes1 = 10 * es * N  # read U^n, write U1
+    ach2 = bytes2 / (st2_ms / 1e3) / 1e9
+    ach1 = bytes1 / (st1_ms / 1e3) / 1e9
+    traffic = measured_traffic() if args.dtype == "f32" and n == 512 else None
+    rec = {
+        "metric": "cell-updates/s & %HBM BW at 512^3 fp32",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"driven turbulence {n}^3 {args.dtype}: PLM minmod + HLLC + SSP-RK2, "
+                        "CFL 0.4, solenoidal OU forcing 1<=|n|<=2 tau=0.5, exact cooling, "
+                        "from rest rho=1 p=1 gamma=5/3",
+            "cells": N,
+            "bytes_per_cell_update": 25 * es,
+            "effective_GBps": 25 * es * value / 1e9,
+            "stage1_ms": st1_ms,
+            "stage2_ms": st2_ms,
+            "prologue_ms": ms[mh.TIME_PROLOGUE] / max(launches[mh.TIME_PROLOGUE], 1),
+            "stage1_GBps": ach1,
+            "t_end": t_sim,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stage<2> (RK stage 2 + forcing + cooling + CFL max)",
+            "achieved": ach2,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach2 / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

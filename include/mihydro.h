@@ -1,0 +1,195 @@
+/*
+ * mihydro.h -- C ABI of libmihydro.so, an MI355X (gfx950) implementation of
+ * the finite-volume step of "diffhydro" (Horowitz, Lukic, Nagamine & Oku,
+ * arXiv 2512.13403): MUSCL/PLM reconstruction on primitive variables with a
+ * minmod limiter (App. A.1), HLLC fluxes with Davis wave speeds (App. A.2),
+ * unsplit conservative differencing and two-stage RK2 (App. A.3), the CFL
+ * step (App. A.4), and operator-split sources after each step: OU turbulent
+ * forcing (Sec. 3.1.1), multigrid self-gravity (Sec. 6, 6.2) and optically
+ * thin cooling integrated exactly per cell (Sec. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State layout: U is a dense array [5][nz][ny][nx] (x fastest) of the
+ *   conserved fields (rho, m_x, m_y, m_z, E), the state vector of the paper's
+ *   Sec. 2.1 listing, in the precision chosen by mh_grid_desc.dtype (float or
+ *   double).
+ * Memory: the caller owns all device memory.  The library only owns its host
+ *   context.  The workspace passed to mh_init must stay valid (and untouched
+ *   by the caller) until mh_destroy; it holds the state, the stage buffer, the
+ *   device clock, the OU mode state and the multigrid hierarchy.
+ * Streams: every call enqueues its work on the HIP stream given to mh_init
+ *   and returns without waiting, except where stated ("synchronises").
+ * Errors: every call returns an mh_status; nothing throws across the ABI.  On
+ *   an error the context keeps its previous state unless stated otherwise, and
+ *   mh_last_error() returns a message (valid until the next call on ctx).
+ * Threads: a context must not be used from two host threads at once.
+ */
+#ifndef MIHYDRO_H
+#define MIHYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mh_status {
+  MH_OK = 0,
+  MH_E_INVALID = 1,     /* null pointer, bad enum, non-positive size/spacing */
+  MH_E_SHAPE = 2,       /* grid shape not supported by the requested physics */
+  MH_E_DTYPE = 3,       /* unknown precision */
+  MH_E_DEVICE = 4,      /* a HIP call failed; mh_last_error has its text */
+  MH_E_NONFINITE = 5,   /* non-finite value or rho <= 0 or P <= 0 detected */
+  MH_E_UNSUPPORTED = 6, /* valid option that this build does not implement */
+  MH_E_WORKSPACE = 7    /* workspace too small or misaligned */
+} mh_status;
+
+enum { MH_BC_PERIODIC = 0, MH_BC_OUTFLOW = 1 };
+enum { MH_F32 = 0, MH_F64 = 1 };
+enum { MH_LIM_MINMOD = 0, MH_LIM_NONE = 1 };
+enum { MH_RS_HLLC = 0 };
+enum { MH_SRC_COOLING = 1u, MH_SRC_FORCING = 2u, MH_SRC_GRAVITY = 4u };
+enum { MH_HOST = 0, MH_DEVICE = 1 };
+
+/* Grid and scheme.
+ * n[3]    cells along x, y, z (each >= 1).
+ * bc[3]   MH_BC_PERIODIC (wrap) or MH_BC_OUTFLOW (zero-gradient copy of the
+ *         edge cell) per axis.
+ * h[3]    cell spacing per axis (> 0).
+ * dtype   MH_F32 or MH_F64: storage and arithmetic precision of the state.
+ * limiter MH_LIM_MINMOD (App. A.1; a tie |a| = |b| takes the forward
+ *         difference) or MH_LIM_NONE (piecewise constant).
+ * riemann MH_RS_HLLC (App. A.2).
+ * gamma   adiabatic index (> 1).
+ * cfl     Courant number C of dt = C min_a dx_a / (|v_a| + c_s) (App. A.4). */
+typedef struct mh_grid_desc {
+  int32_t n[3];
+  int32_t bc[3];
+  double h[3];
+  int32_t dtype;
+  int32_t limiter;
+  int32_t riemann;
+  int32_t reserved0;
+  double gamma;
+  double cfl;
+} mh_grid_desc;
+
+/* Source terms, applied after each RK2 step in the order forcing -> gravity
+ * -> cooling, each on the state left by the previous one.
+ * flags           OR of MH_SRC_*.
+ * cool_*          cooling curve in code units with T = P/rho:
+ *                 Lambda = lambda0 (T/tc)^(1/2) for T >= tc,
+ *                 Lambda = lambda0 exp((T - tc)/ts) for T < tc;
+ *                 dT/dt = -(gamma-1) rho Lambda(T) is integrated exactly over
+ *                 dt, then T is floored at tfloor (Sec. 4 and 4.3).
+ * ou_*            OU forcing (Sec. 3.1.1): seed of the counter-based noise,
+ *                 correlation time tau, target rms acceleration arms,
+ *                 solenoidal fraction zeta, forced band kmin <= |n| <= kmax
+ *                 (integer mode numbers), and update period every (the mode
+ *                 amplitudes advance once every `every` steps by every*dt).
+ * grav_G          gravitational constant of lap(phi) = 4 pi G (rho - <rho>).
+ * mg_*            multigrid V-cycle (Sec. 6.2, App. C): pre/post weighted
+ *                 Jacobi sweeps, maximum cycles per step, coarsest grid size,
+ *                 relative residual tolerance (0 runs exactly max_cycles
+ *                 cycles), and Jacobi sweeps used to solve the coarsest grid. */
+typedef struct mh_physics_desc {
+  uint32_t flags;
+  int32_t ou_every;
+  double cool_lambda0, cool_tc, cool_ts, cool_tfloor;
+  uint64_t ou_seed;
+  double ou_tau, ou_arms, ou_zeta, ou_kmin, ou_kmax;
+  double grav_G;
+  int32_t mg_pre, mg_post, mg_max_cycles, mg_coarsest;
+  double mg_tol;
+  int32_t mg_coarse_sweeps;
+  int32_t reserved0;
+} mh_physics_desc;
+
+typedef struct mh_ctx mh_ctx;
+
+/* Bytes of device workspace that mh_init needs for this grid and physics.
+ * Returns MH_E_INVALID / MH_E_SHAPE / MH_E_DTYPE / MH_E_UNSUPPORTED for
+ * descriptors that mh_init would reject. */
+mh_status mh_query_workspace(const mh_grid_desc *grid, const mh_physics_desc *phys,
+                             size_t *bytes);
+
+/* Creates a context on the current HIP device.  `workspace` is device memory
+ * of at least mh_query_workspace bytes, 256-byte aligned, owned by the caller.
+ * `stream` is a hipStream_t (NULL = the default stream).  The clock starts at
+ * t = 0, step 0; the OU modes start from their stationary draw (Sec. 3.1.1).
+ * Uploads the grid-only tables; synchronises. */
+mh_status mh_init(const mh_grid_desc *grid, const mh_physics_desc *phys, void *workspace,
+                  size_t workspace_bytes, void *stream, mh_ctx **out);
+
+/* Copies a state [5][nz][ny][nx] of the context's dtype into the context.
+ * where = MH_HOST (synchronises) or MH_DEVICE (device pointer, asynchronous;
+ * the source must stay valid until the stream reaches this copy). */
+mh_status mh_set_state(mh_ctx *ctx, const void *U, int where);
+
+/* Copies the current state out; MH_HOST synchronises. */
+mh_status mh_get_state(mh_ctx *ctx, void *U, int where);
+
+/* Advances nsteps steps.  dt > 0: fixed step; dt <= 0: CFL step computed on
+ * the device from the current state.  Each step's dt is capped so that the
+ * clock does not pass t_stop (pass +INFINITY for no cap; a step that starts
+ * at t_stop has dt = 0).  dt_out (nsteps doubles) and t_out (one double) are
+ * optional host pointers; when either is non-NULL the call synchronises. */
+mh_status mh_step(mh_ctx *ctx, int32_t nsteps, double dt, double t_stop, double *dt_out,
+                  double *t_out);
+
+/* Reads the device clock (t, global step index); synchronises. */
+mh_status mh_get_clock(mh_ctx *ctx, double *t, int64_t *step);
+
+/* Sets the device clock, e.g. to resume from a checkpoint. */
+mh_status mh_set_clock(mh_ctx *ctx, double t, int64_t step);
+
+/* Number of OU modes and copy of their amplitudes ahat[m][comp][re,im]
+ * (6 doubles per mode) to or from host memory (checkpoint / resume);
+ * synchronise. */
+mh_status mh_get_ou_state(mh_ctx *ctx, int32_t *nmodes, double *ahat);
+mh_status mh_set_ou_state(mh_ctx *ctx, const double *ahat);
+
+/* Health of the last mh_step call: number of cells flagged (non-finite, or
+ * rho <= 0, or P <= 0) after any step, and the flat index q = (k ny + j) nx + i
+ * of the lowest flagged cell (-1 if none).  Synchronises.  Returns
+ * MH_E_NONFINITE when any cell was flagged. */
+mh_status mh_check(mh_ctx *ctx, int64_t *bad_cells, int64_t *first_bad);
+
+/* Multigrid cycles run by the last step with gravity (0 without gravity);
+ * synchronises. */
+mh_status mh_last_mg_cycles(mh_ctx *ctx, int32_t *cycles);
+
+/* Copies the gravitational potential [nz][ny][nx] (dtype of the context)
+ * solved by the last step with gravity; where = MH_HOST (synchronises) or
+ * MH_DEVICE. */
+mh_status mh_get_potential(mh_ctx *ctx, void *phi, int where);
+
+/* Kernel timing with HIP events.  While enabled, mh_step records an event pair
+ * on the context stream around every kernel launch it makes, by kind:
+ *   MH_TIME_STAGE1, MH_TIME_STAGE2 (the fused stage kernels),
+ *   MH_TIME_PROLOGUE (per-step dt / OU kernel), MH_TIME_OTHER (CFL reduction
+ *   after set_state, multigrid and gravity kernels, bookkeeping).
+ * mh_get_timing synchronises, returns per kind the summed milliseconds and
+ * the number of timed launches (arrays of MH_TIME_KINDS), and clears the
+ * records.  At most 65536 launches are timed between two reads; later ones
+ * are counted in MH_TIME_OTHER's count only.  Timing adds the event records'
+ * small cost to every launch; it is off by default. */
+enum { MH_TIME_STAGE1 = 0, MH_TIME_STAGE2 = 1, MH_TIME_PROLOGUE = 2, MH_TIME_OTHER = 3,
+       MH_TIME_KINDS = 4 };
+mh_status mh_set_timing(mh_ctx *ctx, int enable);
+mh_status mh_get_timing(mh_ctx *ctx, double *ms, int64_t *launches);
+
+/* Message of the last failed call on ctx (empty string if none). */
+const char *mh_last_error(const mh_ctx *ctx);
+
+/* Waits for the context's stream, then frees the host context (not the
+ * workspace, which the caller owns). */
+void mh_destroy(mh_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

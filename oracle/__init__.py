@@ -95,11 +95,14 @@ def lib():
             "or_ou_advance": (None, [cp, ctypes.c_int, ip, dp, ctypes.c_int64, ctypes.c_double]),
             "or_ou_scale": (ctypes.c_double, [cp, ctypes.c_int, dp]),
             "or_ou_accel": (None, [cp, ctypes.c_int, ip, dp, dp]),
+            "or_ou_accel_at": (None, [cp, ctypes.c_int, ip, dp, ctypes.c_long, ctypes.c_long,
+                                      ctypes.c_long, dp]),
             "or_kick": (None, [cp, dp, dp, ctypes.c_double]),
             "or_laplacian": (None, [ctypes.c_int, ctypes.c_double, dp, dp]),
             "or_mg_vcycle": (None, [cp, ctypes.c_int, ctypes.c_double, dp, dp]),
             "or_mg_solve": (ctypes.c_int, [cp, ctypes.c_int, ctypes.c_double, dp, dp]),
             "or_gravity_accel": (ctypes.c_int, [cp, dp, dp, dp]),
+            "or_num_threads": (ctypes.c_int, []),
             "or_step": (ctypes.c_double, [cp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                           ctypes.c_int, ip, dp, dp, ip]),
         }
@@ -144,6 +147,10 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
 
 def _shape(c: Config):
     return (c.n[2], c.n[1], c.n[0])
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
 
 
 def primitives(c, U):
@@ -226,6 +233,15 @@ def ou_accel(c, nvec, ahat):
     acc = np.zeros((3,) + _shape(c))
     lib().or_ou_accel(ctypes.byref(c), len(nvec), _ip(nvec), _dp(a), _dp(acc))
     return acc
+
+
+def ou_accel_at(c, nvec, ahat, i, j, k):
+    """Acceleration at the centre of cell (i, j, k) (x index first)."""
+    nvec = np.ascontiguousarray(nvec, dtype=np.int32)
+    a = np.ascontiguousarray(ahat, dtype=np.float64)
+    out = np.zeros(3)
+    lib().or_ou_accel_at(ctypes.byref(c), len(nvec), _ip(nvec), _dp(a), i, j, k, _dp(out))
+    return out
 
 
 def kick(c, U, acc, dt):

@@ -526,28 +526,35 @@ double or_ou_scale(const or_config *c, int nmodes, const double *ahat) {
   return c->ou_arms / sqrt(2.0 * s);
 }
 
-/* real-space acceleration at cell centres x_a = (i_a + 1/2) L_a / n_a */
+/* real-space acceleration at the centre of cell (i, j, k), x_a = (i_a + 1/2) L_a / n_a:
+ * a(x) = s sum_m 2 Re(ahat_m exp(2 pi i n_m . x / L)) */
+void or_ou_accel_at(const or_config *c, int nmodes, const int32_t *nvec,
+                    const double *ahat, long i, long j, long k, double out[3]) {
+  double s = or_ou_scale(c, nmodes, ahat);
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int m = 0; m < nmodes; ++m) {
+    const int32_t *n = nvec + 3 * m;
+    double th = 2.0 * M_PI *
+                (n[0] * (i + 0.5) / c->n[0] + n[1] * (j + 0.5) / c->n[1] +
+                 n[2] * (k + 0.5) / c->n[2]);
+    double cr = cos(th), ci = sin(th);
+    for (int comp = 0; comp < 3; ++comp)
+      a[comp] += 2.0 * (ahat[6 * m + 2 * comp] * cr - ahat[6 * m + 2 * comp + 1] * ci);
+  }
+  for (int comp = 0; comp < 3; ++comp) out[comp] = s * a[comp];
+}
+
 void or_ou_accel(const or_config *c, int nmodes, const int32_t *nvec,
                  const double *ahat, double *acc /* [3][N] */) {
   long N = or_cells(c);
-  double s = or_ou_scale(c, nmodes, ahat);
 #pragma omp parallel for schedule(static)
   for (long k = 0; k < c->n[2]; ++k)
     for (long j = 0; j < c->n[1]; ++j)
       for (long i = 0; i < c->n[0]; ++i) {
-        double a[3] = {0.0, 0.0, 0.0};
-        for (int m = 0; m < nmodes; ++m) {
-          const int32_t *n = nvec + 3 * m;
-          double th = 2.0 * M_PI *
-                      (n[0] * (i + 0.5) / c->n[0] + n[1] * (j + 0.5) / c->n[1] +
-                       n[2] * (k + 0.5) / c->n[2]);
-          double cr = cos(th), ci = sin(th);
-          for (int comp = 0; comp < 3; ++comp)
-            a[comp] += 2.0 * (ahat[6 * m + 2 * comp] * cr -
-                              ahat[6 * m + 2 * comp + 1] * ci);
-        }
+        double a[3];
+        or_ou_accel_at(c, nmodes, nvec, ahat, i, j, k, a);
         long q = or_idx(c, i, j, k);
-        for (int comp = 0; comp < 3; ++comp) acc[comp * N + q] = s * a[comp];
+        for (int comp = 0; comp < 3; ++comp) acc[comp * N + q] = a[comp];
       }
 }
 
@@ -600,3 +607,7 @@ double or_step(const or_config *c, double *U, double dt_fixed, double dt_cap,
   if (c->flags & OR_SRC_COOLING) or_cool(c, U, dt);
   return dt;
 }
+
+/* threads the OpenMP loops above run on (reported with CPU timings) */
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }

@@ -52,6 +52,8 @@ void or_ou_init(const or_config *c, int nmodes, const int32_t *nvec, double *aha
 void or_ou_advance(const or_config *c, int nmodes, const int32_t *nvec,
                    double *ahat, int64_t group, double dt);
 double or_ou_scale(const or_config *c, int nmodes, const double *ahat);
+void or_ou_accel_at(const or_config *c, int nmodes, const int32_t *nvec,
+                    const double *ahat, long i, long j, long k, double out[3]);
 void or_ou_accel(const or_config *c, int nmodes, const int32_t *nvec,
                  const double *ahat, double *acc);
 void or_kick(const or_config *c, double *U, const double *acc, double dt);
@@ -61,6 +63,8 @@ void or_laplacian(int n, double h, const double *phi, double *out);
 void or_mg_vcycle(const or_config *c, int n, double h, double *phi, const double *F);
 int or_mg_solve(const or_config *c, int n, double h, double *phi, const double *F);
 int or_gravity_accel(const or_config *c, const double *U, double *phi, double *acc);
+
+int or_num_threads(void);
 
 double or_step(const or_config *c, double *U, double dt_fixed, double dt_cap,
                int64_t step, int nmodes, const int32_t *nvec, double *ou_ahat,

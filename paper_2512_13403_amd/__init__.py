@@ -1,0 +1,299 @@
+"""mihydro: MI355X (gfx950) finite-volume step of diffhydro (arXiv 2512.13403).
+
+Thin Python binding of the C ABI in ``include/mihydro.h`` (``libmihydro.so``,
+built in-tree by ``build.py``).  The binding only marshals arguments: every
+step of the method runs in the library's HIP kernels.  PyTorch provides the
+device memory (the workspace is a torch uint8 tensor) and the stream.  There
+is no CPU fallback: constructing a ``Solver`` without the built library or
+without a GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmihydro.so")
+
+OK, E_INVALID, E_SHAPE, E_DTYPE, E_DEVICE, E_NONFINITE, E_UNSUPPORTED, E_WORKSPACE = range(8)
+STATUS_NAMES = ["MH_OK", "MH_E_INVALID", "MH_E_SHAPE", "MH_E_DTYPE", "MH_E_DEVICE",
+                "MH_E_NONFINITE", "MH_E_UNSUPPORTED", "MH_E_WORKSPACE"]
+BC_PERIODIC, BC_OUTFLOW = 0, 1
+F32, F64 = 0, 1
+LIM_MINMOD, LIM_NONE = 0, 1
+RS_HLLC = 0
+SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
+HOST, DEVICE = 0, 1
+
+EXPORTED = [
+    "mh_query_workspace", "mh_init", "mh_set_state", "mh_get_state", "mh_step", "mh_get_clock",
+    "mh_set_clock", "mh_get_ou_state", "mh_set_ou_state", "mh_check", "mh_last_mg_cycles",
+    "mh_get_potential", "mh_set_timing", "mh_get_timing", "mh_last_error", "mh_destroy",
+]
+TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3), ("bc", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3),
+        ("dtype", ctypes.c_int32), ("limiter", ctypes.c_int32), ("riemann", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+    ]
+
+
+class PhysicsDesc(ctypes.Structure):
+    _fields_ = [
+        ("flags", ctypes.c_uint32), ("ou_every", ctypes.c_int32),
+        ("cool_lambda0", ctypes.c_double), ("cool_tc", ctypes.c_double),
+        ("cool_ts", ctypes.c_double), ("cool_tfloor", ctypes.c_double),
+        ("ou_seed", ctypes.c_uint64), ("ou_tau", ctypes.c_double), ("ou_arms", ctypes.c_double),
+        ("ou_zeta", ctypes.c_double), ("ou_kmin", ctypes.c_double), ("ou_kmax", ctypes.c_double),
+        ("grav_G", ctypes.c_double), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
+        ("mg_max_cycles", ctypes.c_int32), ("mg_coarsest", ctypes.c_int32),
+        ("mg_tol", ctypes.c_double), ("mg_coarse_sweeps", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+    ]
+
+
+class MHError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {msg}")
+
+
+_lib = None
+
+
+def load_library():
+    """Loads libmihydro.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        sig = {
+            "mh_query_workspace": [ctypes.POINTER(GridDesc), ctypes.POINTER(PhysicsDesc),
+                                   ctypes.POINTER(ctypes.c_size_t)],
+            "mh_init": [ctypes.POINTER(GridDesc), ctypes.POINTER(PhysicsDesc), vp, ctypes.c_size_t,
+                        vp, ctypes.POINTER(vp)],
+            "mh_set_state": [vp, vp, ctypes.c_int],
+            "mh_get_state": [vp, vp, ctypes.c_int],
+            "mh_step": [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, dp, dp],
+            "mh_get_clock": [vp, dp, i64p],
+            "mh_set_clock": [vp, ctypes.c_double, ctypes.c_int64],
+            "mh_get_ou_state": [vp, ctypes.POINTER(ctypes.c_int32), dp],
+            "mh_set_ou_state": [vp, dp],
+            "mh_check": [vp, i64p, i64p],
+            "mh_last_mg_cycles": [vp, ctypes.POINTER(ctypes.c_int32)],
+            "mh_get_potential": [vp, vp, ctypes.c_int],
+            "mh_set_timing": [vp, ctypes.c_int],
+            "mh_get_timing": [vp, dp, i64p],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.mh_last_error.argtypes = [vp]
+        L.mh_last_error.restype = ctypes.c_char_p
+        L.mh_destroy.argtypes = [vp]
+        L.mh_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def grid_desc(shape, h, bc=(BC_PERIODIC,) * 3, dtype="f32", gamma=5.0 / 3.0, cfl=0.4,
+              limiter=LIM_MINMOD, riemann=RS_HLLC) -> GridDesc:
+    """shape = (nz, ny, nx); h and bc per (x, y, z)."""
+    g = GridDesc()
+    nz, ny, nx = shape
+    g.n[:] = [nx, ny, nz]
+    g.bc[:] = list(bc)
+    g.h[:] = list(h)
+    g.dtype = F64 if dtype in ("f64", "float64", F64) else F32
+    g.limiter, g.riemann, g.gamma, g.cfl = limiter, riemann, gamma, cfl
+    return g
+
+
+def physics_desc(flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, ou_arms=1.0,
+                 ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0, ou_every=1, grav_G=0.0, mg_pre=2,
+                 mg_post=2, mg_max_cycles=20, mg_coarsest=4, mg_tol=1e-10,
+                 mg_coarse_sweeps=200) -> PhysicsDesc:
+    p = PhysicsDesc()
+    p.flags = flags
+    p.cool_lambda0, p.cool_tc, p.cool_ts, p.cool_tfloor = cool
+    p.ou_seed, p.ou_tau, p.ou_arms, p.ou_zeta = ou_seed, ou_tau, ou_arms, ou_zeta
+    p.ou_kmin, p.ou_kmax, p.ou_every = ou_kmin, ou_kmax, ou_every
+    p.grav_G = grav_G
+    p.mg_pre, p.mg_post, p.mg_max_cycles, p.mg_coarsest = mg_pre, mg_post, mg_max_cycles, mg_coarsest
+    p.mg_tol, p.mg_coarse_sweeps = mg_tol, mg_coarse_sweeps
+    return p
+
+
+def query_workspace(grid: GridDesc, phys: PhysicsDesc) -> int:
+    L = load_library()
+    n = ctypes.c_size_t(0)
+    st = L.mh_query_workspace(ctypes.byref(grid), ctypes.byref(phys), ctypes.byref(n))
+    if st != OK:
+        raise MHError(st, "mh_query_workspace rejected the descriptors")
+    return n.value
+
+
+class Solver:
+    """One simulation on one GPU: owns a torch workspace tensor and an mh_ctx."""
+
+    def __init__(self, grid: GridDesc, phys: PhysicsDesc | None = None, device="cuda:0"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("mihydro needs a GPU (no CPU fallback)")
+        self._torch = torch
+        self.lib = load_library()
+        self.grid = grid
+        self.phys = phys if phys is not None else physics_desc()
+        self.device = torch.device(device)
+        self.shape = (grid.n[2], grid.n[1], grid.n[0])
+        self.np_dtype = np.float64 if grid.dtype == F64 else np.float32
+        self.torch_dtype = torch.float64 if grid.dtype == F64 else torch.float32
+        nbytes = query_workspace(grid, self.phys)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            self.stream = torch.cuda.current_stream(self.device)
+            ctx = ctypes.c_void_p()
+            st = self.lib.mh_init(ctypes.byref(grid), ctypes.byref(self.phys),
+                                  ctypes.c_void_p(aligned), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if st != OK:
+            raise MHError(st, "mh_init failed")
+        self.ctx = ctx
+
+    # -- helpers
+    def _check(self, st, what):
+        if st != OK:
+            raise MHError(st, f"{what}: {self.lib.mh_last_error(self.ctx).decode()}")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.mh_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state
+    def set_state(self, U):
+        torch = self._torch
+        if isinstance(U, torch.Tensor) and U.is_cuda:
+            t = U.to(self.torch_dtype).contiguous()
+            assert tuple(t.shape) == (5,) + self.shape
+            self._keep = t  # keep alive until the copy has run
+            self._check(self.lib.mh_set_state(self.ctx, ctypes.c_void_p(t.data_ptr()), DEVICE),
+                        "mh_set_state")
+        else:
+            a = np.ascontiguousarray(np.asarray(U), dtype=self.np_dtype)
+            assert a.shape == (5,) + self.shape, (a.shape, self.shape)
+            self._check(self.lib.mh_set_state(self.ctx, a.ctypes.data_as(ctypes.c_void_p), HOST),
+                        "mh_set_state")
+
+    def get_state(self) -> np.ndarray:
+        out = np.empty((5,) + self.shape, dtype=self.np_dtype)
+        self._check(self.lib.mh_get_state(self.ctx, out.ctypes.data_as(ctypes.c_void_p), HOST),
+                    "mh_get_state")
+        return out
+
+    def get_state_device(self):
+        torch = self._torch
+        out = torch.empty((5,) + self.shape, dtype=self.torch_dtype, device=self.device)
+        self._check(self.lib.mh_get_state(self.ctx, ctypes.c_void_p(out.data_ptr()), DEVICE),
+                    "mh_get_state")
+        return out
+
+    # -- stepping
+    def step(self, nsteps: int = 1, dt: float = 0.0, t_stop: float = math.inf,
+             record: bool = False):
+        """Advances nsteps; dt > 0 fixed, else CFL.  With record=True returns
+        the per-step dt array (synchronises)."""
+        dts = np.zeros(max(nsteps, 1)) if record else None
+        st = self.lib.mh_step(self.ctx, nsteps, dt, t_stop,
+                              dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if record else None,
+                              None)
+        self._check(st, "mh_step")
+        return dts[:nsteps] if record else None
+
+    def run_to(self, t_stop: float, max_steps: int = 1_000_000):
+        """Steps under CFL until the clock reaches t_stop; returns the dt list."""
+        dts = []
+        while True:
+            t, _ = self.clock()
+            if t >= t_stop or len(dts) >= max_steps:
+                return np.array(dts)
+            dts.extend(self.step(1, 0.0, t_stop, record=True))
+
+    def clock(self):
+        t = ctypes.c_double()
+        s = ctypes.c_int64()
+        self._check(self.lib.mh_get_clock(self.ctx, ctypes.byref(t), ctypes.byref(s)), "mh_get_clock")
+        return t.value, s.value
+
+    def set_clock(self, t: float, step: int):
+        self._check(self.lib.mh_set_clock(self.ctx, t, step), "mh_set_clock")
+
+    def ou_state(self) -> np.ndarray:
+        n = ctypes.c_int32()
+        self._check(self.lib.mh_get_ou_state(self.ctx, ctypes.byref(n), None), "mh_get_ou_state")
+        a = np.zeros(6 * n.value)
+        if n.value:
+            self._check(self.lib.mh_get_ou_state(self.ctx, ctypes.byref(n),
+                                                 a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                        "mh_get_ou_state")
+        return a
+
+    def set_ou_state(self, ahat):
+        a = np.ascontiguousarray(ahat, dtype=np.float64)
+        self._check(self.lib.mh_set_ou_state(self.ctx, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "mh_set_ou_state")
+
+    def check(self):
+        """(bad_cells, first_bad_flat_index) of the last step call."""
+        b = ctypes.c_int64()
+        f = ctypes.c_int64()
+        st = self.lib.mh_check(self.ctx, ctypes.byref(b), ctypes.byref(f))
+        if st not in (OK, E_NONFINITE):
+            self._check(st, "mh_check")
+        return b.value, f.value
+
+    def mg_cycles(self) -> int:
+        c = ctypes.c_int32()
+        self._check(self.lib.mh_last_mg_cycles(self.ctx, ctypes.byref(c)), "mh_last_mg_cycles")
+        return c.value
+
+    def set_timing(self, enable: bool):
+        """Records HIP events around every kernel launch of step()."""
+        self._check(self.lib.mh_set_timing(self.ctx, 1 if enable else 0), "mh_set_timing")
+
+    def timing(self):
+        """(ms, launches) per kind (stage 1, stage 2, prologue, other) since
+        the last read; synchronises and clears the records."""
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.int64)
+        self._check(self.lib.mh_get_timing(self.ctx, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+                    "mh_get_timing")
+        return ms, n
+
+    def potential(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=self.np_dtype)
+        self._check(self.lib.mh_get_potential(self.ctx, out.ctypes.data_as(ctypes.c_void_p), HOST),
+                    "mh_get_potential")
+        return out

@@ -1,0 +1,525 @@
+// api.hip -- the C ABI of libmihydro (declared in include/mihydro.h): argument
+// checking, the device-workspace layout, and the per-step launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mihydro.h"
+#include "mg.h"
+#include "mh_device.h"
+#include "mh_launch.h"
+
+using namespace mh;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Layout {
+  size_t U = 0, U1 = 0, clk = 0, dtlog = 0, ou_n = 0, ou_ahat = 0, ou_coef = 0;
+  size_t tab[3] = {0, 0, 0};
+  MGLayout mg;
+  size_t total = 0;
+};
+
+int ou_enumerate(double kmin, double kmax, std::vector<int>& nv) {
+  // integer n with kmin <= |n| <= kmax, one of each +-n pair (first non-zero
+  // component positive), lexicographic in (nx, ny, nz); same rule as the
+  // reference order of the noise stream
+  nv.clear();
+  const int r = (int)std::ceil(kmax);
+  for (int a = -r; a <= r; ++a)
+    for (int b = -r; b <= r; ++b)
+      for (int d = -r; d <= r; ++d) {
+        const double k = std::sqrt((double)(a * a + b * b + d * d));
+        if (k < kmin || k > kmax || k == 0.0) continue;
+        const int first = a != 0 ? a : (b != 0 ? b : d);
+        if (first <= 0) continue;
+        nv.push_back(a);
+        nv.push_back(b);
+        nv.push_back(d);
+      }
+  return (int)(nv.size() / 3);
+}
+
+mh_status validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string& err,
+                   int* nmodes_out) {
+  auto fail = [&](mh_status s, const char* m) {
+    err = m;
+    return s;
+  };
+  if (!g || !p) return fail(MH_E_INVALID, "null descriptor");
+  for (int a = 0; a < 3; ++a) {
+    if (g->n[a] < 1) return fail(MH_E_INVALID, "grid size must be >= 1 along every axis");
+    if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a]))
+      return fail(MH_E_INVALID, "cell spacing must be positive and finite");
+    if (g->bc[a] != MH_BC_PERIODIC && g->bc[a] != MH_BC_OUTFLOW)
+      return fail(MH_E_INVALID, "unknown boundary kind");
+  }
+  const long long N = (long long)g->n[0] * g->n[1] * g->n[2];
+  if (N > (1ll << 31)) return fail(MH_E_SHAPE, "more than 2^31 cells");
+  if (g->dtype != MH_F32 && g->dtype != MH_F64) return fail(MH_E_DTYPE, "dtype must be F32 or F64");
+  if (g->limiter != MH_LIM_MINMOD && g->limiter != MH_LIM_NONE)
+    return fail(MH_E_UNSUPPORTED, "limiter not implemented on the GPU (minmod or none)");
+  if (g->riemann != MH_RS_HLLC) return fail(MH_E_UNSUPPORTED, "only the HLLC Riemann solver");
+  if (!(g->gamma > 1.0)) return fail(MH_E_INVALID, "gamma must exceed 1");
+  if (!(g->cfl > 0.0)) return fail(MH_E_INVALID, "CFL number must be positive");
+  const uint32_t known = MH_SRC_COOLING | MH_SRC_FORCING | MH_SRC_GRAVITY;
+  if (p->flags & ~known) return fail(MH_E_INVALID, "unknown source flag");
+  if (p->flags & MH_SRC_COOLING) {
+    if (!(p->cool_lambda0 >= 0.0) || !(p->cool_tc > 0.0) || !(p->cool_ts > 0.0) ||
+        !(p->cool_tfloor >= 0.0))
+      return fail(MH_E_INVALID, "cooling constants must be positive");
+  }
+  int nm = 0;
+  if (p->flags & MH_SRC_FORCING) {
+    if (!(p->ou_tau > 0.0) || !(p->ou_arms >= 0.0) || !(p->ou_zeta >= 0.0 && p->ou_zeta <= 1.0))
+      return fail(MH_E_INVALID, "OU tau > 0, arms >= 0, 0 <= zeta <= 1 required");
+    if (!(p->ou_kmin > 0.0) || !(p->ou_kmax >= p->ou_kmin) || p->ou_kmax > 8.0)
+      return fail(MH_E_INVALID, "OU band needs 0 < kmin <= kmax <= 8");
+    if (p->ou_every < 0) return fail(MH_E_INVALID, "OU update period must be >= 0");
+    std::vector<int> nv;
+    nm = ou_enumerate(p->ou_kmin, p->ou_kmax, nv);
+    if (nm < 1) return fail(MH_E_INVALID, "OU band holds no integer mode");
+    if (nm > MAX_MODES) return fail(MH_E_UNSUPPORTED, "more than 64 OU modes");
+  }
+  if (p->flags & MH_SRC_GRAVITY) {
+    mh_status s = mg_validate(g, p, err);
+    if (s != MH_OK) return s;
+  }
+  if (nmodes_out) *nmodes_out = nm;
+  return MH_OK;
+}
+
+Layout make_layout(const mh_grid_desc* g, const mh_physics_desc* p, int nmodes) {
+  Layout L;
+  const size_t es = g->dtype == MH_F64 ? 8 : 4;
+  const size_t N = (size_t)g->n[0] * g->n[1] * g->n[2];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.U = take(5 * N * es);
+  L.U1 = take(5 * N * es);
+  L.clk = take(sizeof(DevClock));
+  L.dtlog = take(DTLOG_CAP * sizeof(double));
+  if (p->flags & MH_SRC_FORCING) {
+    const int R = (int)std::floor(p->ou_kmax);
+    L.ou_n = take(3 * MAX_MODES * sizeof(int));
+    L.ou_ahat = take(6 * MAX_MODES * sizeof(double));
+    L.ou_coef = take(6 * MAX_MODES * es);
+    for (int a = 0; a < 3; ++a) L.tab[a] = take((size_t)(R + 1) * g->n[a] * 2 * es);
+  }
+  if (p->flags & MH_SRC_GRAVITY) off = mg_layout(g, p, off, es, L.mg);
+  L.total = off;
+  (void)nmodes;
+  return L;
+}
+
+}  // namespace
+
+struct mh_ctx {
+  mh_grid_desc g;
+  mh_physics_desc p;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout L;
+  int nmodes = 0;
+  bool smax_valid = false;
+  std::string err;
+  // kernel timing (mh_set_timing): event pairs and the kind of each pair
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kinds;
+  int64_t untimed = 0;
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+  long long cells() const { return (long long)g.n[0] * g.n[1] * g.n[2]; }
+  size_t esize() const { return g.dtype == MH_F64 ? 8 : 4; }
+  DevClock* clk() const { return at<DevClock>(L.clk); }
+};
+
+static constexpr size_t MAX_TIMED = 65536;
+
+// begins a timed launch of the given kind; returns the pair index or -1
+static long time_begin(mh_ctx* c, int kind) {
+  if (!c->timing) return -1;
+  if (c->kinds.size() >= MAX_TIMED) {
+    ++c->untimed;
+    return -1;
+  }
+  const size_t i = c->kinds.size();
+  while (c->ev.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    c->ev.push_back(e);
+  }
+  if (hipEventRecord(c->ev[2 * i], c->stream) != hipSuccess) return -1;
+  c->kinds.push_back(kind);
+  return (long)i;
+}
+
+static void time_end(mh_ctx* c, long i) {
+  if (i >= 0) (void)hipEventRecord(c->ev[2 * i + 1], c->stream);
+}
+
+static mh_status set_err(mh_ctx* c, mh_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define MH_HIP(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(ctx, MH_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" mh_status mh_query_workspace(const mh_grid_desc* grid, const mh_physics_desc* phys,
+                                        size_t* bytes) {
+  std::string err;
+  int nm = 0;
+  if (!bytes) return MH_E_INVALID;
+  mh_status s = validate(grid, phys, err, &nm);
+  if (s != MH_OK) return s;
+  *bytes = make_layout(grid, phys, nm).total;
+  return MH_OK;
+}
+
+template <typename T>
+static mh_status upload_tables(mh_ctx* c) {
+  const mh_physics_desc& p = c->p;
+  if (!(p.flags & MH_SRC_FORCING)) return MH_OK;
+  std::vector<int> nv;
+  ou_enumerate(p.ou_kmin, p.ou_kmax, nv);
+  MH_HIP(c, hipMemcpyAsync(c->ws + c->L.ou_n, nv.data(), nv.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+  const int R = (int)std::floor(p.ou_kmax);
+  for (int a = 0; a < 3; ++a) {
+    const int n = c->g.n[a];
+    std::vector<T> tab((size_t)(R + 1) * n * 2);
+    for (int k = 0; k <= R; ++k)
+      for (int i = 0; i < n; ++i) {
+        const double th = 2.0 * M_PI * k * (i + 0.5) / n;
+        tab[2 * ((size_t)k * n + i)] = (T)std::cos(th);
+        tab[2 * ((size_t)k * n + i) + 1] = (T)std::sin(th);
+      }
+    MH_HIP(c, hipMemcpyAsync(c->ws + c->L.tab[a], tab.data(), tab.size() * sizeof(T),
+                             hipMemcpyHostToDevice, c->stream));
+    MH_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return MH_OK;
+}
+
+static mh::OUArgs ou_args(const mh_ctx* c) {
+  mh::OUArgs o{};
+  o.clk = c->clk();
+  o.ahat = c->at<double>(c->L.ou_ahat);
+  o.nvec = c->at<int>(c->L.ou_n);
+  o.coef = c->ws + c->L.ou_coef;
+  o.f64 = c->g.dtype == MH_F64;
+  o.nmodes = c->nmodes;
+  o.every = c->p.ou_every > 0 ? c->p.ou_every : 1;
+  o.seed = c->p.ou_seed;
+  o.tau = c->p.ou_tau;
+  o.arms = c->p.ou_arms;
+  o.zeta = c->p.ou_zeta;
+  return o;
+}
+
+extern "C" mh_status mh_init(const mh_grid_desc* grid, const mh_physics_desc* phys,
+                             void* workspace, size_t workspace_bytes, void* stream,
+                             mh_ctx** out) {
+  if (!out) return MH_E_INVALID;
+  *out = nullptr;
+  std::string err;
+  int nm = 0;
+  mh_status s = validate(grid, phys, err, &nm);
+  if (s != MH_OK) return s;
+  Layout L = make_layout(grid, phys, nm);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0)
+    return MH_E_WORKSPACE;
+  mh_ctx* c = new mh_ctx();
+  c->g = *grid;
+  c->p = *phys;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = workspace_bytes;
+  c->L = L;
+  c->nmodes = nm;
+  DevClock hc{};
+  hc.bad_first = ~0ull;
+  auto fail = [&](mh_status st) {
+    delete c;
+    return st;
+  };
+  if (hipMemcpyAsync(c->clk(), &hc, sizeof hc, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return fail(MH_E_DEVICE);
+  s = grid->dtype == MH_F64 ? upload_tables<double>(c) : upload_tables<float>(c);
+  if (s != MH_OK) return fail(s);
+  if (phys->flags & MH_SRC_FORCING) {
+    if (launch_ou_init(ou_args(c), c->stream) != hipSuccess) return fail(MH_E_DEVICE);
+  }
+  if (phys->flags & MH_SRC_GRAVITY) {
+    if (mg_init(c->ws, L.mg, grid, c->stream) != hipSuccess) return fail(MH_E_DEVICE);
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(MH_E_DEVICE);
+  *out = c;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_set_state(mh_ctx* c, const void* U, int where) {
+  if (!c) return MH_E_INVALID;
+  if (!U || (where != MH_HOST && where != MH_DEVICE))
+    return set_err(c, MH_E_INVALID, "mh_set_state: null pointer or bad location");
+  const size_t bytes = 5 * (size_t)c->cells() * c->esize();
+  MH_HIP(c, hipMemcpyAsync(c->ws + c->L.U, U, bytes,
+                           where == MH_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (where == MH_HOST) MH_HIP(c, hipStreamSynchronize(c->stream));
+  c->smax_valid = false;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_get_state(mh_ctx* c, void* U, int where) {
+  if (!c) return MH_E_INVALID;
+  if (!U || (where != MH_HOST && where != MH_DEVICE))
+    return set_err(c, MH_E_INVALID, "mh_get_state: null pointer or bad location");
+  const size_t bytes = 5 * (size_t)c->cells() * c->esize();
+  MH_HIP(c, hipMemcpyAsync(U, c->ws + c->L.U, bytes,
+                           where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (where == MH_HOST) MH_HIP(c, hipStreamSynchronize(c->stream));
+  return MH_OK;
+}
+
+template <typename T>
+static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, double* dt_out) {
+  const mh_grid_desc& g = c->g;
+  const mh_physics_desc& p = c->p;
+  StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
+  const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
+  const bool force = (p.flags & MH_SRC_FORCING) != 0;
+  const bool grav = (p.flags & MH_SRC_GRAVITY) != 0;
+  const bool cool = (p.flags & MH_SRC_COOLING) != 0;
+  T* U = c->at<T>(c->L.U);
+  T* U1 = c->at<T>(c->L.U1);
+  DevClock* clk = c->clk();
+
+  StageArgs<T> a{};
+  a.clk = clk;
+  a.gamma = (T)g.gamma;
+  a.gm1 = (T)(g.gamma - 1.0);
+  a.gm1inv = (T)(1.0 / (g.gamma - 1.0));
+  a.ihx = (T)ih[0];
+  a.ihy = (T)ih[1];
+  a.ihz = (T)ih[2];
+  a.cool.l0 = (T)p.cool_lambda0;
+  a.cool.tc = (T)p.cool_tc;
+  a.cool.ts = (T)p.cool_ts;
+  a.cool.tfloor = (T)p.cool_tfloor;
+  a.cool.sqrt_tc = (T)std::sqrt(p.cool_tc);
+  if (force) {
+    a.ou_coef = c->at<T>(c->L.ou_coef);
+    a.ou_n = c->at<int>(c->L.ou_n);
+    for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
+    a.ou_modes = c->nmodes;
+  }
+
+  PrologueArgs pa{};
+  pa.clk = clk;
+  pa.dt_log = c->at<double>(c->L.dtlog);
+  pa.f64 = g.dtype == MH_F64;
+  pa.dt_fixed = dt;
+  pa.cfl = g.cfl;
+  pa.t_stop = t_stop;
+  pa.forcing = force;
+  if (force) pa.ou = ou_args(c);
+
+  MH_HIP(c, launch_clock_reset_health(clk, c->stream));
+  for (int s = 0; s < nsteps; ++s) {
+    if (!c->smax_valid && !(dt > 0.0)) {
+      const long tk = time_begin(c, MH_TIME_OTHER);
+      MH_HIP(c, launch_smax<T>(U, geom, (T)g.gamma, ih, clk, c->stream));
+      time_end(c, tk);
+      c->smax_valid = true;
+    }
+    pa.log_index = s % DTLOG_CAP;
+    long tk = time_begin(c, MH_TIME_PROLOGUE);
+    MH_HIP(c, launch_prologue(pa, c->stream));
+    time_end(c, tk);
+    a.uin = U;
+    a.un = nullptr;
+    a.uout = U1;
+    tk = time_begin(c, MH_TIME_STAGE1);
+    MH_HIP(c, launch_stage<T>(1, g.limiter, false, false, a, geom, c->stream));
+    time_end(c, tk);
+    a.uin = U1;
+    a.un = U;
+    a.uout = U;
+    if (grav) {
+      // forcing fused into stage 2; gravity needs the new density everywhere
+      // first, then the kick, cooling and CFL run in the sources kernel
+      tk = time_begin(c, MH_TIME_STAGE2);
+      MH_HIP(c, launch_stage<T>(2, g.limiter, force, false, a, geom, c->stream));
+      time_end(c, tk);
+      tk = time_begin(c, MH_TIME_OTHER);
+      MH_HIP(c, mg_gravity_step<T>(c->ws, c->L.mg, c->g, c->p, U, clk, c->stream));
+      time_end(c, tk);
+    } else {
+      tk = time_begin(c, MH_TIME_STAGE2);
+      MH_HIP(c, launch_stage<T>(2, g.limiter, force, cool, a, geom, c->stream));
+      time_end(c, tk);
+    }
+    c->smax_valid = true;
+    if (dt_out && ((s + 1) % DTLOG_CAP == 0 || s + 1 == nsteps)) {
+      const int n0 = (s / DTLOG_CAP) * DTLOG_CAP;
+      MH_HIP(c, hipMemcpyAsync(dt_out + n0, pa.dt_log, (size_t)(s + 1 - n0) * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+      MH_HIP(c, hipStreamSynchronize(c->stream));
+    }
+  }
+  return MH_OK;
+}
+
+extern "C" mh_status mh_step(mh_ctx* c, int32_t nsteps, double dt, double t_stop,
+                             double* dt_out, double* t_out) {
+  if (!c) return MH_E_INVALID;
+  if (nsteps < 0) return set_err(c, MH_E_INVALID, "mh_step: nsteps < 0");
+  if (std::isnan(dt) || std::isnan(t_stop)) return set_err(c, MH_E_INVALID, "mh_step: NaN dt");
+  mh_status s = c->g.dtype == MH_F64 ? step_impl<double>(c, nsteps, dt, t_stop, dt_out)
+                                     : step_impl<float>(c, nsteps, dt, t_stop, dt_out);
+  if (s != MH_OK) return s;
+  if (t_out) {
+    DevClock hc;
+    MH_HIP(c, hipMemcpyAsync(&hc, c->clk(), sizeof hc, hipMemcpyDeviceToHost, c->stream));
+    MH_HIP(c, hipStreamSynchronize(c->stream));
+    *t_out = hc.t;
+  }
+  return MH_OK;
+}
+
+extern "C" mh_status mh_get_clock(mh_ctx* c, double* t, int64_t* step) {
+  if (!c) return MH_E_INVALID;
+  DevClock hc;
+  MH_HIP(c, hipMemcpyAsync(&hc, c->clk(), sizeof hc, hipMemcpyDeviceToHost, c->stream));
+  MH_HIP(c, hipStreamSynchronize(c->stream));
+  if (t) *t = hc.t;
+  if (step) *step = hc.step;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_set_clock(mh_ctx* c, double t, int64_t step) {
+  if (!c) return MH_E_INVALID;
+  if (!std::isfinite(t) || step < 0) return set_err(c, MH_E_INVALID, "mh_set_clock: bad value");
+  MH_HIP(c, launch_clock_set(c->clk(), t, step, c->stream));
+  return MH_OK;
+}
+
+extern "C" mh_status mh_get_ou_state(mh_ctx* c, int32_t* nmodes, double* ahat) {
+  if (!c) return MH_E_INVALID;
+  if (nmodes) *nmodes = c->nmodes;
+  if (ahat && c->nmodes > 0) {
+    MH_HIP(c, hipMemcpyAsync(ahat, c->ws + c->L.ou_ahat, 6 * c->nmodes * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    MH_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return MH_OK;
+}
+
+extern "C" mh_status mh_set_ou_state(mh_ctx* c, const double* ahat) {
+  if (!c) return MH_E_INVALID;
+  if (c->nmodes == 0) return set_err(c, MH_E_INVALID, "mh_set_ou_state: forcing is off");
+  if (!ahat) return set_err(c, MH_E_INVALID, "mh_set_ou_state: null pointer");
+  MH_HIP(c, hipMemcpyAsync(c->ws + c->L.ou_ahat, ahat, 6 * c->nmodes * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  MH_HIP(c, hipStreamSynchronize(c->stream));
+  return MH_OK;
+}
+
+extern "C" mh_status mh_check(mh_ctx* c, int64_t* bad_cells, int64_t* first_bad) {
+  if (!c) return MH_E_INVALID;
+  DevClock hc;
+  MH_HIP(c, hipMemcpyAsync(&hc, c->clk(), sizeof hc, hipMemcpyDeviceToHost, c->stream));
+  MH_HIP(c, hipStreamSynchronize(c->stream));
+  if (bad_cells) *bad_cells = (int64_t)hc.bad_count;
+  const int64_t fb = hc.bad_count ? (int64_t)hc.bad_first : -1;
+  if (first_bad) *first_bad = fb;
+  if (hc.bad_count)
+    return set_err(c, MH_E_NONFINITE, "%llu unphysical cell(s); first at flat index %lld",
+                   (unsigned long long)hc.bad_count, (long long)fb);
+  return MH_OK;
+}
+
+extern "C" mh_status mh_last_mg_cycles(mh_ctx* c, int32_t* cycles) {
+  if (!c || !cycles) return MH_E_INVALID;
+  DevClock hc;
+  MH_HIP(c, hipMemcpyAsync(&hc, c->clk(), sizeof hc, hipMemcpyDeviceToHost, c->stream));
+  MH_HIP(c, hipStreamSynchronize(c->stream));
+  *cycles = hc.mg_cycles;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_get_potential(mh_ctx* c, void* phi, int where) {
+  if (!c) return MH_E_INVALID;
+  if (!(c->p.flags & MH_SRC_GRAVITY))
+    return set_err(c, MH_E_INVALID, "mh_get_potential: gravity is off");
+  if (!phi || (where != MH_HOST && where != MH_DEVICE))
+    return set_err(c, MH_E_INVALID, "mh_get_potential: null pointer or bad location");
+  MH_HIP(c, hipMemcpyAsync(phi, c->ws + mg_phi_offset(c->L.mg), (size_t)c->cells() * c->esize(),
+                           where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (where == MH_HOST) MH_HIP(c, hipStreamSynchronize(c->stream));
+  return MH_OK;
+}
+
+extern "C" mh_status mh_set_timing(mh_ctx* c, int enable) {
+  if (!c) return MH_E_INVALID;
+  c->timing = enable != 0;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_get_timing(mh_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return MH_E_INVALID;
+  MH_HIP(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < MH_TIME_KINDS; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (size_t i = 0; i < c->kinds.size(); ++i) {
+    float t = 0.0f;
+    MH_HIP(c, hipEventElapsedTime(&t, c->ev[2 * i], c->ev[2 * i + 1]));
+    ms[c->kinds[i]] += (double)t;
+    launches[c->kinds[i]] += 1;
+  }
+  launches[MH_TIME_OTHER] += c->untimed;
+  c->kinds.clear();
+  c->untimed = 0;
+  return MH_OK;
+}
+
+extern "C" const char* mh_last_error(const mh_ctx* c) { return c ? c->err.c_str() : ""; }
+
+extern "C" void mh_destroy(mh_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}

@@ -1,0 +1,457 @@
+// hydro_kernels.hip -- fused finite-volume stage kernels for gfx950.
+//
+// One launch of k_stage performs one Runge-Kutta stage of the unsplit
+// method-of-lines update of diffhydro (arXiv 2512.13403, App. A.3):
+//   stage 1:  U1     = U^n + dt L(U^n)
+//   stage 2:  U^{n+1} = U^n / 2 + (U1 + dt L(U1)) / 2
+// with L(U) = -sum_a (F_{a,i+1/2} - F_{a,i-1/2}) / dx_a, the face fluxes F
+// from HLLC (App. A.2) on MUSCL face states of the primitive variables with a
+// minmod-limited slope (App. A.1).  Stage 2 also applies, per cell and in
+// registers, the operator-split sources in the order forcing -> cooling
+// (Sec. 3.1.1, Sec. 4), flags unphysical cells, and reduces the CFL signal
+// speed max_a (|v_a| + c_s)/dx_a of the new state (App. A.4) into the device
+// clock, so the next step's dt never leaves the GPU.
+//
+// Data movement per stage (fp32): each cell is read once from HBM for its own
+// column and written once; the x/y stencil halos of a 64 x 8 tile come from
+// neighbouring tiles through L2.  Primitive variables of the current z-plane
+// live in LDS (with a 2-cell x/y halo); the z-stencil is a register ring of
+// four planes per thread, so the kernel marches along z and touches each
+// plane once.  Every face flux is computed exactly once per tile: x faces by
+// the thread on their left (plus the tile's left edge), y faces likewise, z
+// faces by the column's thread, carried from one plane to the next.
+#include "mh_device.h"
+#include "mh_launch.h"
+
+namespace mh {
+
+template <typename T, int LIM>
+__device__ __forceinline__ T limited_slope(T wm, T w0, T wp) {
+  if (LIM == LIM_NONE) return T(0);
+  // minmod(a, b) with a = W_{i+1} - W_i and b = W_i - W_{i-1}: the smaller
+  // magnitude when both share a sign, else 0; a tie takes a.
+  T a = wp - w0, b = w0 - wm;
+  T m = (fabs(a) <= fabs(b)) ? a : b;
+  return (a * b > T(0)) ? m : T(0);
+}
+
+// HLLC flux through a face with normal velocity component `n` (0, 1, 2) of
+// the primitive face states wl, wr = (rho, vx, vy, vz, P).  Davis speeds
+// S_L = min(vL - cL, vR - cR), S_R = max(vL + cL, vR + cR); contact speed
+// S* and star states as in the standard HLLC construction.  Only the side
+// K that the face falls on is assembled: F = F_K + S_K (U*_K - U_K) inside
+// the star fan, F = F_K outside it, with
+//   U*_K = q (d_K, d_K S*, d_K vt1, d_K vt2, (S_K - v_K) E_K + (S* - v_K)(d_K S* + P_K)),
+//   d_K = rho_K (S_K - v_K), q = 1 / (S_K - S*),
+// which is the usual star state with the common factor rho_K (S_K - v_K) /
+// (S_K - S*) multiplied through (one reciprocal instead of three divides).
+template <typename T, int N>
+__device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T gamma, T gm1inv,
+                                          T (&F)[5]) {
+  constexpr int t1 = 1 + (N + 1) % 3, t2 = 1 + (N + 2) % 3, vn = 1 + N;
+  const T rl = wl[0], ul = wl[vn], pl = wl[4];
+  const T rr = wr[0], ur = wr[vn], pr = wr[4];
+  const T irl = dev_rcp(rl), irr = dev_rcp(rr);
+  const T cl = dev_sqrt(gamma * pl * irl), cr = dev_sqrt(gamma * pr * irr);
+  const T SL = fmin(ul - cl, ur - cr), SR = fmax(ul + cl, ur + cr);
+  const T kel = T(0.5) * rl * (ul * ul + wl[t1] * wl[t1] + wl[t2] * wl[t2]);
+  const T ker = T(0.5) * rr * (ur * ur + wr[t1] * wr[t1] + wr[t2] * wr[t2]);
+  const T El = pl * gm1inv + kel, Er = pr * gm1inv + ker;
+  const T dl = rl * (SL - ul), dr = rr * (SR - ur);
+  const T sstar = (pr - pl + ul * dl - ur * dr) * dev_rcp(dl - dr);
+  // side: the oracle's region order (0 <= S_L, 0 <= S*, 0 < S_R, else R)
+  const bool left = (SL >= T(0)) || (sstar >= T(0));
+  const T rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
+  const T aK = left ? wl[t1] : wr[t1], bK = left ? wl[t2] : wr[t2];
+  const T EK = left ? El : Er, SK = left ? SL : SR, dK = left ? dl : dr;
+  const bool fan = left ? (SL < T(0)) : (SR > T(0));
+  const T mK = rK * uK;
+  const T FK0 = mK, FK1 = mK * uK + pK, FK2 = mK * aK, FK3 = mK * bK, FK4 = uK * (EK + pK);
+  const T q = dev_rcp(SK - sstar);
+  const T qd = q * dK;
+  const T s0 = qd, s1 = qd * sstar, s2 = qd * aK, s3 = qd * bK;
+  const T s4 = q * ((SK - uK) * EK + (sstar - uK) * (dK * sstar + pK));
+  const T f0 = FK0 + SK * (s0 - rK);
+  const T f1 = FK1 + SK * (s1 - mK);
+  const T f2 = FK2 + SK * (s2 - rK * aK);
+  const T f3 = FK3 + SK * (s3 - rK * bK);
+  const T f4 = FK4 + SK * (s4 - EK);
+  F[0] = fan ? f0 : FK0;
+  F[vn] = fan ? f1 : FK1;
+  F[t1] = fan ? f2 : FK2;
+  F[t2] = fan ? f3 : FK3;
+  F[4] = fan ? f4 : FK4;
+}
+
+// flux through the face between cells i and i+1 from W_{i-1}, W_i, W_{i+1},
+// W_{i+2}: W^L = W_i + dW_i/2, W^R = W_{i+1} - dW_{i+1}/2 (App. A.1)
+template <typename T, int LIM, int N>
+__device__ __forceinline__ void face_flux(const T (&wm)[5], const T (&w0)[5], const T (&w1)[5],
+                                          const T (&w2)[5], T gamma, T gm1inv, T (&F)[5]) {
+  T wl[5], wr[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    wl[f] = w0[f] + T(0.5) * limited_slope<T, LIM>(wm[f], w0[f], w1[f]);
+    wr[f] = w1[f] - T(0.5) * limited_slope<T, LIM>(w0[f], w1[f], w2[f]);
+  }
+  hllc_flux<T, N>(wl, wr, gamma, gm1inv, F);
+}
+
+template <typename T, int STAGE, int LIM, bool FORCE, bool COOL>
+__global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
+  __shared__ T sW[5][TY + 4][TX + 4];
+  __shared__ T sFx[5][TY][TX + 1];
+  __shared__ T sFy[5][TY + 1][TX];
+  __shared__ T sRed[NTHREADS / 64];
+
+  // XCD-aware tile order: consecutive hardware workgroups go round-robin to
+  // the 8 XCDs, so give each XCD a contiguous range of tiles (x fastest, then
+  // y, then z) and the x/y halos of neighbouring tiles stay in one L2.
+  const int b = blockIdx.x;
+  const int logical = (b & 7) * a.nb_per_xcd + (b >> 3);
+  if (logical >= a.nbx * a.nby * a.nbz) return;
+  const int bx = logical % a.nbx;
+  const int rest = logical / a.nbx;
+  const int by = rest % a.nby, bz = rest / a.nby;
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * a.zc;
+  const int zend = min(z0 + a.zc, a.nz);
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool inside = gx < a.nx && gy < a.ny;
+  const long long N = a.ncell;
+  const long long plane = (long long)a.nx * a.ny;
+  const long long col = (long long)bc_map(gy, a.ny, a.bcy) * a.nx + bc_map(gx, a.nx, a.bcx);
+  const T gamma = a.gamma, gm1 = a.gm1, gm1inv = a.gm1inv;
+  const T dt = (T)a.clk->dt;
+
+  // halo cells of the current plane this thread loads into LDS (if any):
+  // 4 columns x TY rows left/right of the tile, TX columns x 4 rows below/above
+  int h_lx = -1, h_ly = -1;
+  long long h_col = 0;
+  if (tid < 4 * TY) {
+    const int hy = tid >> 2, hi = tid & 3;
+    h_lx = hi < 2 ? hi : TX + hi;
+    h_ly = hy + 2;
+    h_col = (long long)bc_map(y0 + hy, a.ny, a.bcy) * a.nx + bc_map(x0 - 2 + h_lx, a.nx, a.bcx);
+  } else if (tid < 4 * TY + 4 * TX) {
+    const int t2 = tid - 4 * TY;
+    const int hx = t2 % TX, hj = t2 / TX;
+    h_ly = hj < 2 ? hj : TY + hj;
+    h_lx = hx + 2;
+    h_col = (long long)bc_map(y0 - 2 + h_ly, a.ny, a.bcy) * a.nx + bc_map(x0 + hx, a.nx, a.bcx);
+  }
+
+  // z ring: W at z-1, z, z+1, z+2; U at z, z+1, z+2; z-flux at z-1/2
+  T w[4][5], u[3][5], fzm[5];
+  {
+    T tmp[5], wz[5];
+    load_cell(a.uin, N, (long long)bc_map(z0 - 2, a.nz, a.bcz) * plane + col, tmp);
+    to_prim(tmp, gm1, wz);
+    load_cell(a.uin, N, (long long)bc_map(z0 - 1, a.nz, a.bcz) * plane + col, tmp);
+    to_prim(tmp, gm1, w[0]);
+    load_cell(a.uin, N, (long long)bc_map(z0, a.nz, a.bcz) * plane + col, u[0]);
+    to_prim(u[0], gm1, w[1]);
+    load_cell(a.uin, N, (long long)bc_map(z0 + 1, a.nz, a.bcz) * plane + col, u[1]);
+    to_prim(u[1], gm1, w[2]);
+    face_flux<T, LIM, 2>(wz, w[0], w[1], w[2], gamma, gm1inv, fzm);
+  }
+
+  T smax = T(0);
+  unsigned long long nbad = 0, first_bad = ~0ull;
+
+  for (int z = z0; z < zend; ++z) {
+    load_cell(a.uin, N, (long long)bc_map(z + 2, a.nz, a.bcz) * plane + col, u[2]);
+    to_prim(u[2], gm1, w[3]);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) sW[f][ty + 2][tx + 2] = w[1][f];
+    if (h_lx >= 0) {
+      T hu[5], hw[5];
+      load_cell(a.uin, N, (long long)z * plane + h_col, hu);
+      to_prim(hu, gm1, hw);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) sW[f][h_ly][h_lx] = hw[f];
+    }
+    __syncthreads();
+
+    {
+      T c0[5], c1[5], c2[5], c3[5], F[5];
+      // x face at x + 1/2
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        c0[f] = sW[f][ty + 2][tx + 1];
+        c1[f] = sW[f][ty + 2][tx + 2];
+        c2[f] = sW[f][ty + 2][tx + 3];
+        c3[f] = sW[f][ty + 2][tx + 4];
+      }
+      face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, F);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) sFx[f][ty][tx + 1] = F[f];
+      if (tx == 0) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          c0[f] = sW[f][ty + 2][0];
+          c1[f] = sW[f][ty + 2][1];
+          c2[f] = sW[f][ty + 2][2];
+          c3[f] = sW[f][ty + 2][3];
+        }
+        face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, F);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) sFx[f][ty][0] = F[f];
+      }
+      // y face at y + 1/2
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        c0[f] = sW[f][ty + 1][tx + 2];
+        c1[f] = sW[f][ty + 2][tx + 2];
+        c2[f] = sW[f][ty + 3][tx + 2];
+        c3[f] = sW[f][ty + 4][tx + 2];
+      }
+      face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, F);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) sFy[f][ty + 1][tx] = F[f];
+      if (ty == 0) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          c0[f] = sW[f][0][tx + 2];
+          c1[f] = sW[f][1][tx + 2];
+          c2[f] = sW[f][2][tx + 2];
+          c3[f] = sW[f][3][tx + 2];
+        }
+        face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, F);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) sFy[f][0][tx] = F[f];
+      }
+    }
+    T fzp[5];
+    face_flux<T, LIM, 2>(w[0], w[1], w[2], w[3], gamma, gm1inv, fzp);
+    __syncthreads();
+
+    T un[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      T L = -(sFx[f][ty][tx + 1] - sFx[f][ty][tx]) * a.ihx;
+      L -= (sFy[f][ty + 1][tx] - sFy[f][ty][tx]) * a.ihy;
+      L -= (fzp[f] - fzm[f]) * a.ihz;
+      un[f] = u[0][f] + dt * L;
+    }
+    const long long q = (long long)z * plane + col;
+    if (STAGE == 1) {
+      if (inside) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
+      }
+    } else {
+      T u0[5];
+      if (inside) load_cell(a.un, N, q, u0);
+      else {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u0[f] = u[0][f];
+      }
+#pragma unroll
+      for (int f = 0; f < 5; ++f) un[f] = T(0.5) * u0[f] + T(0.5) * un[f];
+
+      if (FORCE) {
+        // a(x) = scale sum_m 2 Re(ahat_m exp(2 pi i n_m . x / L)) at the cell
+        // centre; coef = 2 scale ahat (T), phase tables per axis for n >= 0,
+        // complex conjugate for n < 0.
+        T acc[3] = {T(0), T(0), T(0)};
+        const int ix = gx < a.nx ? gx : 0, iy = gy < a.ny ? gy : 0;
+        for (int m = 0; m < a.ou_modes; ++m) {
+          const int nxm = a.ou_n[3 * m], nym = a.ou_n[3 * m + 1], nzm = a.ou_n[3 * m + 2];
+          const T* ex = a.ou_tab[0] + 2 * ((long long)abs(nxm) * a.nx + ix);
+          const T* ey = a.ou_tab[1] + 2 * ((long long)abs(nym) * a.ny + iy);
+          const T* ez = a.ou_tab[2] + 2 * ((long long)abs(nzm) * a.nz + z);
+          const T xr = ex[0], xi = nxm < 0 ? -ex[1] : ex[1];
+          const T yr = ey[0], yi = nym < 0 ? -ey[1] : ey[1];
+          const T zr = ez[0], zi = nzm < 0 ? -ez[1] : ez[1];
+          const T pr = xr * yr - xi * yi, pi = xr * yi + xi * yr;
+          const T er = pr * zr - pi * zi, ei = pr * zi + pi * zr;
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            acc[c] += a.ou_coef[6 * m + 2 * c] * er - a.ou_coef[6 * m + 2 * c + 1] * ei;
+        }
+        // m += rho a dt, E += (m_old . a) dt  (Sec. 3.1.1, Sec. 2.1 listing)
+        const T dE = un[1] * acc[0] + un[2] * acc[1] + un[3] * acc[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) un[1 + c] += un[0] * acc[c] * dt;
+        un[4] += dE * dt;
+      }
+      if (COOL) {
+        const T ek = T(0.5) * (un[1] * un[1] + un[2] * un[2] + un[3] * un[3]) / un[0];
+        const T Tin = gm1 * (un[4] - ek) / un[0];
+        const T Tn = cool_T(un[0], Tin, dt, gm1, a.cool);
+        un[4] = ek + un[0] * Tn * gm1inv;
+      }
+      if (inside) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
+        // CFL signal speed of the new state and the health check
+        T wn[5];
+        to_prim(un, gm1, wn);
+        const T cs = dev_sqrt(gamma * wn[4] * dev_rcp(wn[0]));
+        const T s = fmax(fmax((fabs(wn[1]) + cs) * a.ihx, (fabs(wn[2]) + cs) * a.ihy),
+                         (fabs(wn[3]) + cs) * a.ihz);
+        smax = fmax(smax, s);
+        const bool ok = (wn[0] > T(0)) && (wn[4] > T(0)) && isfinite(un[1]) &&
+                        isfinite(un[2]) && isfinite(un[3]) && isfinite(un[4]) && isfinite(s);
+        if (!ok) {
+          ++nbad;
+          if ((unsigned long long)q < first_bad) first_bad = (unsigned long long)q;
+        }
+      }
+    }
+
+    // advance the z ring
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      fzm[f] = fzp[f];
+      w[0][f] = w[1][f];
+      w[1][f] = w[2][f];
+      w[2][f] = w[3][f];
+      u[0][f] = u[1][f];
+      u[1][f] = u[2][f];
+    }
+  }
+
+  if (STAGE == 2) {
+    T m = wave_max(smax);
+    if ((tid & 63) == 0) sRed[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+      T bm = sRed[0];
+      for (int i = 1; i < NTHREADS / 64; ++i) bm = fmax(bm, sRed[i]);
+      atomicMax(&a.clk->smax, pos_bits(bm));
+    }
+    if (nbad) {
+      atomicAdd(&a.clk->bad_count, nbad);
+      atomicMin(&a.clk->bad_first, first_bad);
+    }
+  }
+}
+
+// CFL signal-speed max of a state (used when no stage-2 epilogue produced it,
+// i.e. right after the state was set).
+template <typename T>
+__global__ __launch_bounds__(256) void k_smax(const T* __restrict__ U, long long N, T gm1, T gamma,
+                                              T ihx, T ihy, T ihz, DevClock* clk) {
+  __shared__ T sRed[4];
+  T smax = T(0);
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+       q += (long long)gridDim.x * blockDim.x) {
+    T u[5], w[5];
+    load_cell(U, N, q, u);
+    to_prim(u, gm1, w);
+    const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
+    smax = fmax(smax, fmax(fmax((fabs(w[1]) + cs) * ihx, (fabs(w[2]) + cs) * ihy),
+                           (fabs(w[3]) + cs) * ihz));
+  }
+  T m = wave_max(smax);
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T bm = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
+    atomicMax(&clk->smax, pos_bits(bm));
+  }
+}
+
+__global__ void k_clock_reset_smax(DevClock* clk) {
+  if (threadIdx.x == 0) clk->smax = 0ull;
+}
+
+__global__ void k_clock_reset_health(DevClock* clk) {
+  if (threadIdx.x == 0) {
+    clk->bad_count = 0ull;
+    clk->bad_first = ~0ull;
+  }
+}
+
+__global__ void k_clock_set(DevClock* clk, double t, long long step) {
+  if (threadIdx.x == 0) {
+    clk->t = t;
+    clk->step = step;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int z_chunk(const StageGeom& g) {
+  // enough workgroups to fill 256 CUs several times over, long z-marches
+  // otherwise (each chunk re-reads 4 planes of prologue)
+  const long long tiles_xy = (long long)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+  int zc = 64;
+  while (zc > 4 && tiles_xy * ((g.nz + zc - 1) / zc) < 4096) zc >>= 1;
+  return zc < g.nz ? zc : g.nz;
+}
+
+template <typename T>
+static void fill_geom(StageArgs<T>& a, const StageGeom& g) {
+  a.nx = g.nx; a.ny = g.ny; a.nz = g.nz;
+  a.bcx = g.bc[0]; a.bcy = g.bc[1]; a.bcz = g.bc[2];
+  a.ncell = (long long)g.nx * g.ny * g.nz;
+  a.zc = z_chunk(g);
+  a.nbx = (g.nx + TX - 1) / TX;
+  a.nby = (g.ny + TY - 1) / TY;
+  a.nbz = (g.nz + a.zc - 1) / a.zc;
+  const int nb = a.nbx * a.nby * a.nbz;
+  a.nb_per_xcd = (nb + 7) / 8;
+}
+
+template <typename T>
+hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs<T> a,
+                        const StageGeom& g, hipStream_t s) {
+  fill_geom(a, g);
+  dim3 block(TX, TY);
+  dim3 grid(8 * a.nb_per_xcd);
+#define MH_LAUNCH(ST, LM, FO, CO) \
+  hipLaunchKernelGGL((k_stage<T, ST, LM, FO, CO>), grid, block, 0, s, a)
+  if (stage == 1) {
+    if (limiter == LIM_NONE) MH_LAUNCH(1, LIM_NONE, false, false);
+    else MH_LAUNCH(1, LIM_MINMOD, false, false);
+  } else if (limiter == LIM_NONE) {
+    if (force && cool) MH_LAUNCH(2, LIM_NONE, true, true);
+    else if (force) MH_LAUNCH(2, LIM_NONE, true, false);
+    else if (cool) MH_LAUNCH(2, LIM_NONE, false, true);
+    else MH_LAUNCH(2, LIM_NONE, false, false);
+  } else {
+    if (force && cool) MH_LAUNCH(2, LIM_MINMOD, true, true);
+    else if (force) MH_LAUNCH(2, LIM_MINMOD, true, false);
+    else if (cool) MH_LAUNCH(2, LIM_MINMOD, false, true);
+    else MH_LAUNCH(2, LIM_MINMOD, false, false);
+  }
+#undef MH_LAUNCH
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_smax(const T* U, const StageGeom& g, T gamma, const double* ih, DevClock* clk,
+                       hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  long long blocks = (N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_clock_reset_smax, dim3(1), dim3(64), 0, s, clk);
+  hipLaunchKernelGGL((k_smax<T>), dim3((unsigned)blocks), dim3(256), 0, s, U, N, gamma - T(1),
+                     gamma, (T)ih[0], (T)ih[1], (T)ih[2], clk);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_reset_health(DevClock* clk, hipStream_t s) {
+  hipLaunchKernelGGL(k_clock_reset_health, dim3(1), dim3(64), 0, s, clk);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_set(DevClock* clk, double t, long long step, hipStream_t s) {
+  hipLaunchKernelGGL(k_clock_set, dim3(1), dim3(64), 0, s, clk, t, step);
+  return hipGetLastError();
+}
+
+template hipError_t launch_stage<float>(int, int, bool, bool, StageArgs<float>, const StageGeom&,
+                                        hipStream_t);
+template hipError_t launch_stage<double>(int, int, bool, bool, StageArgs<double>, const StageGeom&,
+                                         hipStream_t);
+template hipError_t launch_smax<float>(const float*, const StageGeom&, float, const double*,
+                                       DevClock*, hipStream_t);
+template hipError_t launch_smax<double>(const double*, const StageGeom&, double, const double*,
+                                        DevClock*, hipStream_t);
+
+}  // namespace mh

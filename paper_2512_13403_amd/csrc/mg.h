@@ -1,0 +1,46 @@
+// mg.h -- multigrid self-gravity on the device (internal to libmihydro).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/mihydro.h"
+#include "mh_device.h"
+
+namespace mh {
+
+constexpr int MG_MAX_LEVELS = 16;
+constexpr int MG_PARTIALS = 1024;       // blocks of the two-stage reductions
+constexpr int MG_COARSE_MAX_CELLS = 2048;
+
+struct MGLevel {
+  int n;
+  double h;
+  size_t phi[2];  // ping-pong buffers of the Jacobi sweeps
+  size_t F;       // right-hand side
+  size_t r;       // residual
+};
+
+struct MGLayout {
+  int nlev = 0;
+  MGLevel lev[MG_MAX_LEVELS];
+  size_t partial = 0;  // MG_PARTIALS doubles
+  int cur0 = 0;        // which fine-level phi buffer holds the solution
+};
+
+mh_status mg_validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string& err);
+size_t mg_layout(const mh_grid_desc* g, const mh_physics_desc* p, size_t off, size_t es,
+                 MGLayout& L);
+hipError_t mg_init(char* ws, const MGLayout& L, const mh_grid_desc* g, hipStream_t s);
+size_t mg_phi_offset(const MGLayout& L);
+
+// Solves lap(phi) = 4 pi G (rho - <rho>) for the density of U (warm start from
+// the previous solution), then applies the gravity kick, cooling (if on), the
+// CFL reduction and the health check to U.  Synchronises once per V-cycle to
+// test convergence.
+template <typename T>
+hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
+                           T* U, DevClock* clk, hipStream_t s);
+
+}  // namespace mh

@@ -1,0 +1,469 @@
+// mg_kernels.hip -- geometric multigrid Poisson solver and gravity source on
+// the device (arXiv 2512.13403, Sec. 6, 6.2 and App. C).
+//
+// The discrete problem is A phi = F on the periodic n^3 cube, A the
+// seven-point Laplacian, F = 4 pi G (rho - <rho>).  One V-cycle: nu1 weighted
+// Jacobi sweeps (omega = 2/3), residual, restriction by the mean of the 8
+// children, the coarse error equation solved recursively from zero,
+// cell-centred trilinear prolongation (per axis 3/4 parent + 1/4 neighbour on
+// the child's side) and correction, nu2 sweeps; the coarsest grid is solved
+// by many Jacobi sweeps inside one workgroup.  Means are removed from every
+// restricted right-hand side and from phi after every cycle (gauge <phi> = 0).
+// All reductions are two-stage with fixed block counts, so results do not
+// depend on scheduling.  Every kernel here is memory-bound (about 2 field
+// reads and 1 write per cell per sweep).
+#include <cmath>
+
+#include "mg.h"
+#include "mh_device.h"
+#include "mh_launch.h"
+
+namespace mh {
+
+namespace {
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T>
+__device__ __forceinline__ T nb6(const T* __restrict__ p, int n, int i, int j, int k) {
+  const long long n2 = (long long)n * n;
+  const int im = wrapi(i - 1, n), ip = wrapi(i + 1, n);
+  const int jm = wrapi(j - 1, n), jp = wrapi(j + 1, n);
+  const int km = wrapi(k - 1, n), kp = wrapi(k + 1, n);
+  const long long row = (long long)k * n2 + (long long)j * n;
+  return p[row + im] + p[row + ip] + p[(long long)k * n2 + (long long)jm * n + i] +
+         p[(long long)k * n2 + (long long)jp * n + i] + p[(long long)km * n2 + (long long)j * n + i] +
+         p[(long long)kp * n2 + (long long)j * n + i];
+}
+
+// block sum in double with a fixed tree (blockDim = 256)
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <typename T, bool SQUARE>
+__global__ __launch_bounds__(256) void k_sum_partial(const T* __restrict__ x, long long n,
+                                                     double* __restrict__ partial) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long long)gridDim.x * 256) {
+    const double v = (double)x[q];
+    s += SQUARE ? v * v : v;
+  }
+  const double b = block_sum256(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+
+// out = sum(partial[0..nb)) * scale, written to a clock field
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ partial, int nb,
+                                                   double scale, double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+  const double b = block_sum256(s, sh);
+  if (threadIdx.x == 0) *out = b * scale;
+}
+
+// y = scale * (x - *mean)   (in place allowed)
+template <typename T>
+__global__ __launch_bounds__(256) void k_shift_scale(T* y, const T* x, long long n,
+                                                     const double* mean, double scale) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) y[q] = (T)(scale * ((double)x[q] - *mean));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sub_mean(T* y, long long n, const double* mean) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) y[q] = y[q] - (T)(*mean);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(T* y, long long n) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) y[q] = T(0);
+}
+
+// phi' = (1 - w) phi + (w/6)(sum of neighbours - h^2 F), w = 2/3
+template <typename T>
+__global__ __launch_bounds__(256) void k_jacobi(int n, T h2, const T* __restrict__ phi,
+                                                const T* __restrict__ F, T* __restrict__ out) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
+  const T w = T(2) / T(3);
+  out[q] = (T(1) - w) * phi[q] + (w / T(6)) * (nb6(phi, n, i, j, k) - h2 * F[q]);
+}
+
+// r = F - A phi
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual(int n, T ih2, const T* __restrict__ phi,
+                                                  const T* __restrict__ F, T* __restrict__ r) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
+  r[q] = F[q] - (nb6(phi, n, i, j, k) - T(6) * phi[q]) * ih2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(int nc, const T* __restrict__ rf, T* __restrict__ rc) {
+  const long long Nc = (long long)nc * nc * nc;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= Nc) return;
+  const int I = (int)(q % nc), J = (int)((q / nc) % nc), K = (int)(q / ((long long)nc * nc));
+  const int nf = 2 * nc;
+  const long long nf2 = (long long)nf * nf;
+  T s = T(0);
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a)
+        s += rf[(long long)(2 * K + c) * nf2 + (long long)(2 * J + b) * nf + (2 * I + a)];
+  rc[q] = T(0.125) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(int nc, const T* __restrict__ ec, T* __restrict__ phif) {
+  const int nf = 2 * nc;
+  const long long Nf = (long long)nf * nf * nf;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= Nf) return;
+  const int i = (int)(q % nf), j = (int)((q / nf) % nf), k = (int)(q / ((long long)nf * nf));
+  const int I = i >> 1, J = j >> 1, K = k >> 1;
+  const int I2 = wrapi(I + ((i & 1) ? 1 : -1), nc);
+  const int J2 = wrapi(J + ((j & 1) ? 1 : -1), nc);
+  const int K2 = wrapi(K + ((k & 1) ? 1 : -1), nc);
+  const long long nc2 = (long long)nc * nc;
+  auto at = [&](int a, int b, int c) { return ec[(long long)c * nc2 + (long long)b * nc + a]; };
+  const T w0 = T(0.75), w1 = T(0.25);
+  T e = T(0);
+  e += w0 * w0 * w0 * at(I, J, K);
+  e += w1 * w0 * w0 * at(I2, J, K);
+  e += w0 * w1 * w0 * at(I, J2, K);
+  e += w1 * w1 * w0 * at(I2, J2, K);
+  e += w0 * w0 * w1 * at(I, J, K2);
+  e += w1 * w0 * w1 * at(I2, J, K2);
+  e += w0 * w1 * w1 * at(I, J2, K2);
+  e += w1 * w1 * w1 * at(I2, J2, K2);
+  phif[q] += e;
+}
+
+// coarsest grid: phi = 0, `sweeps` Jacobi sweeps, remove the mean; one
+// workgroup of 256 threads, the whole grid (<= 4096 cells) in LDS
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_solve(int n, T h2, const T* __restrict__ F,
+                                                      T* __restrict__ phi, int sweeps) {
+  __shared__ T a[MG_COARSE_MAX_CELLS], b[MG_COARSE_MAX_CELLS];
+  __shared__ double sh[256];
+  const int N = n * n * n;
+  for (int q = threadIdx.x; q < N; q += 256) a[q] = T(0);
+  __syncthreads();
+  const T w = T(2) / T(3);
+  T* src = a;
+  T* dst = b;
+  for (int s = 0; s < sweeps; ++s) {
+    for (int q = threadIdx.x; q < N; q += 256) {
+      const int i = q % n, j = (q / n) % n, k = q / (n * n);
+      dst[q] = (T(1) - w) * src[q] + (w / T(6)) * (nb6(src, n, i, j, k) - h2 * F[q]);
+    }
+    __syncthreads();
+    T* t = src;
+    src = dst;
+    dst = t;
+  }
+  double s = 0.0;
+  for (int q = threadIdx.x; q < N; q += 256) s += (double)src[q];
+  const double mean = block_sum256(s, sh) / (double)N;
+  for (int q = threadIdx.x; q < N; q += 256) phi[q] = src[q] - (T)mean;
+}
+
+// gravity kick g = -(phi_{i+1} - phi_{i-1}) / (2h) with m += rho g dt,
+// E += (m_old . g) dt; then cooling; then the CFL max and the health check
+template <typename T, bool COOL>
+__global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict__ phi, int n, T i2h,
+                                                      T gamma, T ihx, CoolParams<T> cool, DevClock* clk) {
+  __shared__ T sRed[4];
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  const T dt = (T)clk->dt;
+  const T gm1 = gamma - T(1);
+  T s = T(0);
+  unsigned long long bad = 0;
+  if (q < N) {
+    const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
+    const long long n2 = (long long)n * n;
+    const long long row = (long long)k * n2 + (long long)j * n;
+    const T gx = -(phi[row + wrapi(i + 1, n)] - phi[row + wrapi(i - 1, n)]) * i2h;
+    const T gy = -(phi[(long long)k * n2 + (long long)wrapi(j + 1, n) * n + i] -
+                   phi[(long long)k * n2 + (long long)wrapi(j - 1, n) * n + i]) * i2h;
+    const T gz = -(phi[(long long)wrapi(k + 1, n) * n2 + (long long)j * n + i] -
+                   phi[(long long)wrapi(k - 1, n) * n2 + (long long)j * n + i]) * i2h;
+    T u[5];
+    load_cell(U, N, q, u);
+    const T dE = u[1] * gx + u[2] * gy + u[3] * gz;
+    u[1] += u[0] * gx * dt;
+    u[2] += u[0] * gy * dt;
+    u[3] += u[0] * gz * dt;
+    u[4] += dE * dt;
+    if (COOL) {
+      const T ek = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+      const T Tin = gm1 * (u[4] - ek) / u[0];
+      const T Tn = cool_T(u[0], Tin, dt, gm1, cool);
+      u[4] = ek + u[0] * Tn / gm1;
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) U[f * N + q] = u[f];
+    T w[5];
+    to_prim(u, gm1, w);
+    const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
+    s = (fmax(fmax(fabs(w[1]), fabs(w[2])), fabs(w[3])) + cs) * ihx;
+    const bool ok = (w[0] > T(0)) && (w[4] > T(0)) && isfinite(u[1]) && isfinite(u[2]) &&
+                    isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
+    if (!ok) bad = 1;
+  }
+  const T m = wave_max(s);
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(&clk->smax, pos_bits(fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]))));
+  if (bad) {
+    atomicAdd(&clk->bad_count, 1ull);
+    atomicMin(&clk->bad_first, (unsigned long long)q);
+  }
+}
+
+__global__ void k_set_cycles(DevClock* clk, int cycles) {
+  if (threadIdx.x == 0) clk->mg_cycles = cycles;
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+hipError_t sum_to(const T* x, long long n, bool square, double* partial, double scale, double* out,
+                  hipStream_t s) {
+  int nb = (int)((n + 255) / 256);
+  if (nb > MG_PARTIALS) nb = MG_PARTIALS;
+  if (square) hipLaunchKernelGGL((k_sum_partial<T, true>), dim3(nb), dim3(256), 0, s, x, n, partial);
+  else hipLaunchKernelGGL((k_sum_partial<T, false>), dim3(nb), dim3(256), 0, s, x, n, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, scale, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t remove_mean(T* x, long long n, double* partial, double* mean_slot, hipStream_t s) {
+  hipError_t e = sum_to(x, n, false, partial, 1.0 / (double)n, mean_slot, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sub_mean<T>), dim3(nblk(n)), dim3(256), 0, s, x, n, mean_slot);
+  return hipGetLastError();
+}
+
+template <typename T>
+T* P(char* ws, size_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+// one V-cycle on level 0; phi of level 0 is lev[0].phi[cur]
+template <typename T>
+hipError_t vcycle(char* ws, MGLayout& L, const mh_physics_desc& p, double* partial,
+                  double* mean_slot, hipStream_t s) {
+  const int nl = L.nlev;
+  int cur[MG_MAX_LEVELS];
+  cur[0] = L.cur0;
+  for (int l = 0; l < nl - 1; ++l) {
+    MGLevel& lv = L.lev[l];
+    const long long N = (long long)lv.n * lv.n * lv.n;
+    const T h2 = (T)(lv.h * lv.h);
+    if (l > 0) {
+      cur[l] = 0;
+      hipLaunchKernelGGL((k_zero<T>), dim3(nblk(N)), dim3(256), 0, s, P<T>(ws, lv.phi[0]), N);
+    }
+    for (int it = 0; it < p.mg_pre; ++it) {
+      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
+                         P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.phi[1 - cur[l]]));
+      cur[l] = 1 - cur[l];
+    }
+    hipLaunchKernelGGL((k_residual<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, (T)(1.0 / (lv.h * lv.h)),
+                       P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.r));
+    MGLevel& cv = L.lev[l + 1];
+    const long long Nc = (long long)cv.n * cv.n * cv.n;
+    hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(Nc)), dim3(256), 0, s, cv.n, P<T>(ws, lv.r),
+                       P<T>(ws, cv.F));
+    hipError_t e = remove_mean(P<T>(ws, cv.F), Nc, partial, mean_slot, s);
+    if (e != hipSuccess) return e;
+  }
+  {
+    MGLevel& cv = L.lev[nl - 1];
+    if (nl == 1) {
+      // the whole grid is the coarsest grid: plain sweeps from the warm start
+      const long long N = (long long)cv.n * cv.n * cv.n;
+      for (int it = 0; it < p.mg_coarse_sweeps; ++it) {
+        hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n, (T)(cv.h * cv.h),
+                           P<T>(ws, cv.phi[cur[0]]), P<T>(ws, cv.F), P<T>(ws, cv.phi[1 - cur[0]]));
+        cur[0] = 1 - cur[0];
+      }
+      hipError_t e = remove_mean(P<T>(ws, cv.phi[cur[0]]), N, partial, mean_slot, s);
+      if (e != hipSuccess) return e;
+    } else {
+      cur[nl - 1] = 0;
+      hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(256), 0, s, cv.n, (T)(cv.h * cv.h),
+                         P<T>(ws, cv.F), P<T>(ws, cv.phi[0]), p.mg_coarse_sweeps);
+    }
+  }
+  for (int l = nl - 2; l >= 0; --l) {
+    MGLevel& lv = L.lev[l];
+    MGLevel& cv = L.lev[l + 1];
+    const long long N = (long long)lv.n * lv.n * lv.n;
+    const T h2 = (T)(lv.h * lv.h);
+    hipLaunchKernelGGL((k_prolong_add<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n,
+                       P<T>(ws, cv.phi[cur[l + 1]]), P<T>(ws, lv.phi[cur[l]]));
+    for (int it = 0; it < p.mg_post; ++it) {
+      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
+                         P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.phi[1 - cur[l]]));
+      cur[l] = 1 - cur[l];
+    }
+  }
+  L.cur0 = cur[0];
+  return hipGetLastError();
+}
+
+}  // namespace
+
+mh_status mg_validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string& err) {
+  for (int a = 0; a < 3; ++a)
+    if (g->bc[a] != MH_BC_PERIODIC) {
+      err = "gravity needs periodic boundaries on every axis";
+      return MH_E_SHAPE;
+    }
+  if (g->n[0] != g->n[1] || g->n[0] != g->n[2] || g->h[0] != g->h[1] || g->h[0] != g->h[2]) {
+    err = "gravity needs a cubic grid with equal spacing";
+    return MH_E_SHAPE;
+  }
+  if (!(p->grav_G >= 0.0) || p->mg_pre < 0 || p->mg_post < 0 || p->mg_max_cycles < 0 ||
+      p->mg_coarsest < 1 || !(p->mg_tol >= 0.0) || p->mg_coarse_sweeps < 0) {
+    err = "bad multigrid parameters";
+    return MH_E_INVALID;
+  }
+  int n = g->n[0], levels = 1;
+  while (!(n <= p->mg_coarsest || (n % 2) != 0)) {
+    n /= 2;
+    ++levels;
+  }
+  if ((long long)n * n * n > MG_COARSE_MAX_CELLS && levels > 1) {
+    err = "coarsest multigrid grid exceeds 2048 cells";
+    return MH_E_SHAPE;
+  }
+  if (levels > MG_MAX_LEVELS) {
+    err = "too many multigrid levels";
+    return MH_E_SHAPE;
+  }
+  return MH_OK;
+}
+
+size_t mg_layout(const mh_grid_desc* g, const mh_physics_desc* p, size_t off, size_t es,
+                 MGLayout& L) {
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  // levels halve n while n > coarsest and n is even (the rule of mg_validate)
+  L = MGLayout();
+  L.partial = take(MG_PARTIALS * sizeof(double));
+  int n = g->n[0];
+  double h = g->h[0];
+  for (;;) {
+    MGLevel& lv = L.lev[L.nlev++];
+    const size_t bytes = (size_t)n * n * n * es;
+    lv.n = n;
+    lv.h = h;
+    lv.phi[0] = take(bytes);
+    lv.phi[1] = take(bytes);
+    lv.F = take(bytes);
+    lv.r = take(bytes);
+    if (n <= p->mg_coarsest || (n % 2) != 0 || L.nlev == MG_MAX_LEVELS) break;
+    n /= 2;
+    h *= 2.0;
+  }
+  return off;
+}
+
+hipError_t mg_init(char* ws, const MGLayout& L, const mh_grid_desc* g, hipStream_t s) {
+  const bool f64 = g->dtype == MH_F64;
+  for (int l = 0; l < L.nlev; ++l) {
+    const MGLevel& lv = L.lev[l];
+    const long long N = (long long)lv.n * lv.n * lv.n;
+    const size_t offs[4] = {lv.phi[0], lv.phi[1], lv.F, lv.r};
+    for (size_t o : offs) {
+      if (f64) hipLaunchKernelGGL((k_zero<double>), dim3(nblk(N)), dim3(256), 0, s, P<double>(ws, o), N);
+      else hipLaunchKernelGGL((k_zero<float>), dim3(nblk(N)), dim3(256), 0, s, P<float>(ws, o), N);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
+                           T* U, DevClock* clk, hipStream_t s) {
+  MGLevel& f = L.lev[0];
+  const int n = f.n;
+  const long long N = (long long)n * n * n;
+  double* partial = P<double>(ws, L.partial);
+  hipError_t e;
+#define MG_CHECK(x)            \
+  do {                         \
+    e = (x);                   \
+    if (e != hipSuccess) return e; \
+  } while (0)
+  // F = 4 pi G (rho - <rho>)
+  MG_CHECK(sum_to(U, N, false, partial, 1.0 / (double)N, &clk->mean, s));
+  hipLaunchKernelGGL((k_shift_scale<T>), dim3(nblk(N)), dim3(256), 0, s, P<T>(ws, f.F), U, N,
+                     &clk->mean, 4.0 * M_PI * p.grav_G);
+  MG_CHECK(sum_to(P<T>(ws, f.F), N, true, partial, 1.0, &clk->mg_fnorm2, s));
+  MG_CHECK(remove_mean(P<T>(ws, f.phi[L.cur0]), N, partial, &clk->mean, s));
+  int cycles = 0;
+  for (;;) {
+    hipLaunchKernelGGL((k_residual<T>), dim3(nblk(N)), dim3(256), 0, s, n, (T)(1.0 / (f.h * f.h)),
+                       P<T>(ws, f.phi[L.cur0]), P<T>(ws, f.F), P<T>(ws, f.r));
+    MG_CHECK(sum_to(P<T>(ws, f.r), N, true, partial, 1.0, &clk->mg_rnorm2, s));
+    double norms[2];
+    MG_CHECK(hipMemcpyAsync(norms, &clk->mg_fnorm2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MG_CHECK(hipStreamSynchronize(s));
+    if (std::sqrt(norms[1]) <= p.mg_tol * std::sqrt(norms[0]) || cycles >= p.mg_max_cycles) break;
+    MG_CHECK(vcycle<T>(ws, L, p, partial, &clk->mean, s));
+    MG_CHECK(remove_mean(P<T>(ws, f.phi[L.cur0]), N, partial, &clk->mean, s));
+    ++cycles;
+  }
+  hipLaunchKernelGGL(k_set_cycles, dim3(1), dim3(64), 0, s, clk, cycles);
+  CoolParams<T> cp;
+  cp.l0 = (T)p.cool_lambda0;
+  cp.tc = (T)p.cool_tc;
+  cp.ts = (T)p.cool_ts;
+  cp.tfloor = (T)p.cool_tfloor;
+  cp.sqrt_tc = (T)std::sqrt(p.cool_tc);
+  const T i2h = (T)(1.0 / (2.0 * f.h));
+  if (p.flags & MH_SRC_COOLING)
+    hipLaunchKernelGGL((k_grav_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U,
+                       P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk);
+  else
+    hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
+                       P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk);
+#undef MG_CHECK
+  return hipGetLastError();
+}
+
+template hipError_t mg_gravity_step<float>(char*, MGLayout&, const mh_grid_desc&,
+                                           const mh_physics_desc&, float*, DevClock*, hipStream_t);
+template hipError_t mg_gravity_step<double>(char*, MGLayout&, const mh_grid_desc&,
+                                            const mh_physics_desc&, double*, DevClock*, hipStream_t);
+
+size_t mg_phi_offset(const MGLayout& L) { return L.lev[0].phi[L.cur0]; }
+
+}  // namespace mh

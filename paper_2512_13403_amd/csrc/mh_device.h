@@ -1,0 +1,139 @@
+// mh_device.h -- device-side types and helpers shared by the HIP kernels of
+// libmihydro (gfx950 only).  Internal: not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mh {
+
+// Tile of the fused stage kernel: one thread per (x, y) column of a 64 x 8
+// tile (one wave64 per row), marching along z through a chunk of planes.
+constexpr int TX = 64;
+constexpr int TY = 8;
+constexpr int NTHREADS = TX * TY;
+constexpr int MAX_MODES = 64;   // OU modes
+constexpr int DTLOG_CAP = 4096; // per-step dt records kept on the device
+
+// Device clock and per-step scalars, written by one thread of the prologue
+// kernel and read by every stage kernel of the same step.
+struct DevClock {
+  double t;                 // simulated time at the start of the next step
+  double dt;                // dt of the step in flight
+  int64_t step;             // global index of the next step
+  unsigned long long smax;  // bit pattern of max_a (|v_a|+c)/h_a (float or double)
+  unsigned long long bad_count;
+  unsigned long long bad_first;
+  double ou_scale;
+  int32_t mg_cycles;
+  int32_t pad;
+  double mg_fnorm2;         // ||F||^2 of the current gravity solve
+  double mg_rnorm2;         // ||r||^2 of the last residual
+  double mean;              // scratch: mean of a field
+};
+
+enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1 };
+enum : int { LIM_MINMOD = 0, LIM_NONE = 1 };
+
+__device__ __forceinline__ int bc_map(int i, int n, int bc) {
+  if ((unsigned)i < (unsigned)n) return i;
+  if (bc == BC_PERIODIC) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+  }
+  return i < 0 ? 0 : n - 1;
+}
+
+template <typename T> __device__ __forceinline__ T dev_rcp(T x);
+template <> __device__ __forceinline__ float dev_rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <> __device__ __forceinline__ double dev_rcp<double>(double x) { return 1.0 / x; }
+
+template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
+template <> __device__ __forceinline__ float dev_sqrt<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+template <> __device__ __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
+
+// accurate versions for the once-per-cell source terms
+__device__ __forceinline__ float acc_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double acc_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float acc_log(float x) { return logf(x); }
+__device__ __forceinline__ double acc_log(double x) { return log(x); }
+__device__ __forceinline__ float acc_exp(float x) { return expf(x); }
+__device__ __forceinline__ double acc_exp(double x) { return exp(x); }
+
+// order-preserving bit pattern of a non-negative value, for atomicMax
+__device__ __forceinline__ unsigned long long pos_bits(float v) {
+  return (unsigned long long)__float_as_uint(v);
+}
+__device__ __forceinline__ unsigned long long pos_bits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+__host__ __device__ inline double bits_to_double_f32(unsigned long long b) {
+  union { uint32_t u; float f; } c;
+  c.u = (uint32_t)b;
+  return (double)c.f;
+}
+__host__ __device__ inline double bits_to_double_f64(unsigned long long b) {
+  union { unsigned long long u; double d; } c;
+  c.u = b;
+  return c.d;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <typename T>
+struct CoolParams {
+  T l0, tc, ts, tfloor, sqrt_tc;
+};
+
+template <typename T>
+__device__ __forceinline__ void to_prim(const T (&u)[5], T gm1, T (&w)[5]) {
+  const T ir = dev_rcp(u[0]);
+  const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+  w[0] = u[0];
+  w[1] = vx;
+  w[2] = vy;
+  w[3] = vz;
+  w[4] = gm1 * (u[4] - T(0.5) * u[0] * (vx * vx + vy * vy + vz * vz));
+}
+
+template <typename T>
+__device__ __forceinline__ void load_cell(const T* __restrict__ U, long long N, long long q,
+                                          T (&u)[5]) {
+#pragma unroll
+  for (int f = 0; f < 5; ++f) u[f] = U[f * N + q];
+}
+
+// Exact isochoric cooling of one cell over dt (closed form on each branch of
+// the two-branch curve), then the temperature floor; returns the new T.
+template <typename T>
+__device__ __forceinline__ T cool_T(T rho, T Tin, T dt, T gm1, const CoolParams<T>& c) {
+  const T k2 = gm1 * rho * c.l0 / c.ts;
+  T Tn;
+  if (Tin >= c.tc) {
+    const T k1 = gm1 * rho * c.l0 / (T(2) * c.sqrt_tc);
+    const T st = acc_sqrt(Tin);
+    const T t1 = (st - c.sqrt_tc) / k1;
+    if (dt <= t1) {
+      const T s = st - k1 * dt;
+      Tn = s * s;
+    } else {
+      Tn = c.tc - c.ts * acc_log(T(1) + k2 * (dt - t1));
+    }
+  } else {
+    Tn = c.tc - c.ts * acc_log(acc_exp(-(Tin - c.tc) / c.ts) + k2 * dt);
+  }
+  return fmax(Tn, c.tfloor);
+}
+
+}  // namespace mh

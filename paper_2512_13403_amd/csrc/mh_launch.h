@@ -1,0 +1,68 @@
+// mh_launch.h -- kernel argument structs and launcher declarations used by the
+// C-ABI layer (api.hip).  Internal to libmihydro.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mh_device.h"
+
+namespace mh {
+
+struct StageGeom {
+  int nx, ny, nz;
+  int bc[3];
+};
+
+template <typename T>
+struct StageArgs {
+  const T* __restrict__ uin;  // stage input (read with halo)
+  const T* un;                // U^n at the cell itself (stage 2; may alias uout)
+  T* uout;                    // stage output
+  DevClock* clk;
+  const T* __restrict__ ou_coef;  // [M][3][re, im] = 2 * scale * ahat
+  const int* __restrict__ ou_n;   // [M][3] integer mode vectors
+  const T* ou_tab[3];             // per axis [R+1][n_a][cos, sin] of 2 pi n (i + 1/2) / n_a
+  int ou_modes;
+  int nx, ny, nz, bcx, bcy, bcz;
+  long long ncell;
+  T gamma, gm1, gm1inv, ihx, ihy, ihz;
+  CoolParams<T> cool;
+  int zc, nbx, nby, nbz, nb_per_xcd;
+};
+
+struct OUArgs {
+  DevClock* clk;
+  double* ahat;    // [M][3][re, im]
+  const int* nvec; // [M][3]
+  void* coef;      // [M][3][re, im] in the state precision
+  int f64;         // coef is double (1) or float (0)
+  int nmodes;
+  int every;
+  unsigned long long seed;
+  double tau, arms, zeta;
+};
+
+struct PrologueArgs {
+  DevClock* clk;
+  double* dt_log;
+  int log_index;
+  int f64;
+  double dt_fixed;  // > 0: fixed dt
+  double cfl;
+  double t_stop;
+  int forcing;
+  OUArgs ou;
+};
+
+template <typename T>
+hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs<T> a,
+                        const StageGeom& g, hipStream_t s);
+template <typename T>
+hipError_t launch_smax(const T* U, const StageGeom& g, T gamma, const double* ih, DevClock* clk,
+                       hipStream_t s);
+hipError_t launch_clock_reset_health(DevClock* clk, hipStream_t s);
+hipError_t launch_clock_set(DevClock* clk, double t, long long step, hipStream_t s);
+hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s);
+hipError_t launch_ou_init(const OUArgs& a, hipStream_t s);
+
+}  // namespace mh

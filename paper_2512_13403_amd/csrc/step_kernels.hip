@@ -1,0 +1,138 @@
+// step_kernels.hip -- per-step scalar work on the device: the CFL dt of the
+// step, the device clock, and the Ornstein-Uhlenbeck forcing modes
+// (arXiv 2512.13403, App. A.4 and Sec. 3.1.1).  One tiny workgroup per step,
+// so a run of steps never synchronises with the host.
+#include "mh_device.h"
+#include "mh_launch.h"
+
+namespace mh {
+
+// Counter-based normal draws for the OU noise.  SplitMix64 (Steele, Lea &
+// Flood, OOPSLA 2014): output c of the stream seeded with s is
+// mix(s + (c + 1) * 0x9E3779B97F4A7C15).  Two outputs give two uniforms
+// (53-bit), the Box-Muller transform gives one complex normal with real and
+// imaginary parts ~ N(0, 1/2).  Draw index: ((group + 1) * 64 + mode) * 3 + comp.
+__device__ inline unsigned long long sm64(unsigned long long seed, unsigned long long c) {
+  unsigned long long z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ inline void complex_normal(unsigned long long seed, long long group, int mode, int comp,
+                                      double& re, double& im) {
+  const unsigned long long d =
+      ((unsigned long long)(group + 1) * MAX_MODES + (unsigned long long)mode) * 3ull +
+      (unsigned long long)comp;
+  const unsigned long long x1 = sm64(seed, 2ull * d), x2 = sm64(seed, 2ull * d + 1ull);
+  const double u1 = (double)((x1 >> 11) + 1ull) * 0x1.0p-53;
+  const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double th = 6.283185307179586 * u2;
+  re = r * cos(th) * sqrt(0.5);
+  im = r * sin(th) * sqrt(0.5);
+}
+
+// M eta with M = zeta P + (1 - zeta) C, P = I - n n^T/|n|^2, C = n n^T/|n|^2
+__device__ inline void projected_noise(const OUArgs& a, long long group, int mode,
+                                       double (&out)[3][2]) {
+  const int* n = a.nvec + 3 * mode;
+  double er[3], ei[3];
+  for (int c = 0; c < 3; ++c) complex_normal(a.seed, group, mode, c, er[c], ei[c]);
+  const double k2 = (double)(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int i = 0; i < 3; ++i) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      const double C = (double)n[i] * n[j] / k2;
+      const double P = (i == j ? 1.0 : 0.0) - C;
+      const double m = a.zeta * P + (1.0 - a.zeta) * C;
+      sr += m * er[j];
+      si += m * ei[j];
+    }
+    out[i][0] = sr;
+    out[i][1] = si;
+  }
+}
+
+__global__ void k_ou_init(const OUArgs a) {
+  const int m = threadIdx.x;
+  if (m < a.nmodes) {
+    double pe[3][2];
+    projected_noise(a, -1, m, pe);
+    for (int c = 0; c < 3; ++c) {
+      a.ahat[6 * m + 2 * c] = pe[c][0];
+      a.ahat[6 * m + 2 * c + 1] = pe[c][1];
+    }
+  }
+}
+
+// dt of this step, OU update a <- e^{-dt/tau} a + sqrt(1 - e^{-2dt/tau}) M eta,
+// the rms normalisation a_rms / sqrt(2 sum |ahat|^2), and the clock advance.
+__global__ void k_prologue(const PrologueArgs a) {
+  __shared__ double s_dt, s_scale;
+  const int t = threadIdx.x;
+  DevClock* clk = a.clk;
+  if (t == 0) {
+    double dt;
+    if (a.dt_fixed > 0.0) {
+      dt = a.dt_fixed;
+    } else {
+      const double smax = a.f64 ? bits_to_double_f64(clk->smax) : bits_to_double_f32(clk->smax);
+      dt = a.cfl / smax;
+    }
+    const double cap = a.t_stop - clk->t;
+    if (dt > cap) dt = cap;
+    clk->dt = dt;
+    a.dt_log[a.log_index] = dt;
+    s_dt = dt;
+  }
+  __syncthreads();
+  if (a.forcing) {
+    const OUArgs& o = a.ou;
+    const long long step = clk->step;
+    if (step % o.every == 0 && t < o.nmodes) {
+      const double dte = s_dt * o.every;
+      const double f = exp(-dte / o.tau);
+      const double g = sqrt(1.0 - exp(-2.0 * dte / o.tau));
+      double pe[3][2];
+      projected_noise(o, step / o.every, t, pe);
+      for (int c = 0; c < 3; ++c) {
+        o.ahat[6 * t + 2 * c] = f * o.ahat[6 * t + 2 * c] + g * pe[c][0];
+        o.ahat[6 * t + 2 * c + 1] = f * o.ahat[6 * t + 2 * c + 1] + g * pe[c][1];
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int q = 0; q < 6 * o.nmodes; ++q) s += o.ahat[q] * o.ahat[q];
+      s_scale = o.arms / sqrt(2.0 * s);
+      clk->ou_scale = s_scale;
+    }
+    __syncthreads();
+    if (t < o.nmodes) {
+      for (int q = 0; q < 6; ++q) {
+        const double v = 2.0 * s_scale * o.ahat[6 * t + q];
+        if (o.f64) ((double*)o.coef)[6 * t + q] = v;
+        else ((float*)o.coef)[6 * t + q] = (float)v;
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    clk->t += s_dt;
+    clk->step += 1;
+    clk->smax = 0ull;
+  }
+}
+
+hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(MAX_MODES), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ou_init(const OUArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_ou_init, dim3(1), dim3(MAX_MODES), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace mh

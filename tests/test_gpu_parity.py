@@ -1,0 +1,313 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.  Tolerances (relative field norm of parity.rel_err):
+1e-12 for fp64, 1e-5 for fp32.  Sizes span several 64 x 8 tiles with ragged
+edges; the full workload sizes are checked on sampled cells."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2512_13403_amd as mh
+import workloads as wl
+from parity import TOL, as_input, oracle_step_sampled, pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield
+
+
+def run_both(shape, h, U0, dtype, nsteps, dt=None, bc=(0, 0, 0), **kw):
+    s, oc = pair(shape, h, bc, dtype, **kw)
+    Uin = as_input(U0, dtype)
+    if dt is None:
+        dt = 0.8 * oracle.cfl_dt(oc, Uin)
+    s.set_state(Uin)
+    s.step(nsteps, dt)
+    sim = oracle.Simulation(oc, Uin).advance(nsteps, dt)
+    return s, sim
+
+
+# ---------------------------------------------------------------- hydro
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_random_state_ragged_periodic(dtype, nsteps):
+    shape = (19, 21, 77)  # (nz, ny, nx): x spans 2 tiles, y 3, both ragged
+    h = (1 / 77, 1 / 21, 1 / 19)
+    U0 = wl.random_state(shape, seed=1, vmax=0.6)
+    s, sim = run_both(shape, h, U0, dtype, nsteps)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [(1, 1, 1), (1, 0, 0), (0, 1, 0), (0, 0, 1)])
+def test_outflow_boundaries(dtype, bc):
+    shape = (12, 10, 70)
+    h = (1 / 70, 1 / 10, 1 / 12)
+    U0 = wl.random_state(shape, seed=2, vmax=0.8)
+    s, sim = run_both(shape, h, U0, dtype, 3, bc=bc)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_first_order_reconstruction(dtype):
+    shape = (9, 17, 33)
+    U0 = wl.random_state(shape, seed=3)
+    s, sim = run_both(shape, (1 / 33, 1 / 17, 1 / 9), U0, dtype, 4, limiter=oracle.LIM_NONE)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+def test_cfl_steps_fp64_match_dt_sequence():
+    shape = (16, 24, 40)
+    h = (1 / 40, 1 / 24, 1 / 16)
+    U0 = wl.smooth_random_state(shape, seed=4)
+    s, oc = pair(shape, h, dtype="f64")
+    s.set_state(U0)
+    dts = s.step(10, 0.0, record=True)
+    sim = oracle.Simulation(oc, U0).advance(10, 0.0)
+    assert np.allclose(dts, sim.dts, rtol=1e-13, atol=0)
+    assert rel_err(s.get_state(), sim.U) < 1e-12
+    t, step = s.clock()
+    assert step == 10 and t == pytest.approx(sum(sim.dts), rel=1e-14)
+
+
+def test_cfl_dt_fp32_close_to_oracle():
+    shape = (16, 16, 64)
+    U0 = as_input(wl.smooth_random_state(shape, seed=5), "f32")
+    s, oc = pair(shape, (1 / 64, 1 / 16, 1 / 16), dtype="f32")
+    s.set_state(U0)
+    dts = s.step(1, 0.0, record=True)
+    assert dts[0] == pytest.approx(oracle.cfl_dt(oc, U0), rel=1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_uniform_state_is_bitwise_fixed_point(dtype):
+    shape = (8, 9, 70)
+    U0 = as_input(wl.rest_state(shape, rho=1.3, p=0.9, v=(0.3, -0.2, 0.5)), dtype)
+    s, _ = pair(shape, (0.1, 0.1, 0.1), dtype=dtype)
+    s.set_state(U0)
+    s.step(5, 0.01)
+    assert np.array_equal(s.get_state().astype(np.float64), U0)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-6)])
+def test_conservation_periodic(dtype, tol):
+    shape = (24, 20, 66)
+    U0 = as_input(wl.random_state(shape, seed=6, vmax=0.5), dtype)
+    s, oc = pair(shape, (1 / 66, 1 / 20, 1 / 24), dtype=dtype)
+    s.set_state(U0)
+    s.step(10, 0.0)
+    U = s.get_state().astype(np.float64)
+    for f in range(5):
+        s0, s1 = math.fsum(U0[f].ravel()), math.fsum(U[f].ravel())
+        assert abs(s1 - s0) / math.fsum(np.abs(U0[f]).ravel()) < tol, f
+
+
+def test_sod_full_run_fp64():
+    grid = wl.sod_grid(128, 16, 16)
+    U0 = wl.sod_state(grid)
+    s, oc = pair(grid.shape, grid.h, grid.bc, "f64", gamma=1.4)
+    s.set_state(U0)
+    dts = s.run_to(0.2)
+    sim = oracle.Simulation(oc, U0)
+    n = sim.run_to(0.2)
+    assert len(dts) == n
+    assert np.allclose(dts, sim.dts, rtol=1e-12, atol=1e-16)
+    U = s.get_state()
+    assert rel_err(U, sim.U) < 1e-12
+    # transverse invariance on the GPU: all pencils bitwise identical, m_y = m_z = 0
+    assert np.array_equal(U, np.broadcast_to(U[:, :1, :1, :], U.shape))
+    assert np.all(U[2] == 0.0) and np.all(U[3] == 0.0)
+    t, _ = s.clock()
+    assert t == pytest.approx(0.2, abs=1e-15)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_kelvin_helmholtz_64(dtype, nsteps):
+    n = 64
+    U0 = as_input(wl.kh_state(n, seed=0), dtype)
+    s, oc = pair((n, n, n), (1 / n,) * 3, dtype=dtype)
+    # fp64 runs the device CFL step on both sides; an fp32 CFL step differs
+    # from the oracle's in its last bits, so fp32 replays the oracle's dt
+    dt = 0.0 if dtype == "f64" else oracle.cfl_dt(oc, U0)
+    s.set_state(U0)
+    s.step(nsteps, dt)
+    sim = oracle.Simulation(oc, U0).advance(nsteps, dt)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+def test_deterministic_repeat():
+    shape = (20, 20, 70)
+    U0 = wl.random_state(shape, seed=8)
+    outs = []
+    for _ in range(2):
+        s, _ = pair(shape, (1 / 70, 1 / 20, 1 / 20), dtype="f32")
+        s.set_state(U0)
+        s.step(5, 0.0)
+        outs.append(s.get_state())
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 64), (1, 64, 1), (64, 1, 1), (1, 1, 1), (3, 2, 5)])
+def test_degenerate_shapes(shape):
+    h = tuple(1.0 / max(n, 1) for n in shape[::-1])
+    U0 = wl.random_state(shape, seed=9, vmax=0.5)
+    s, sim = run_both(shape, h, U0, "f64", 3)
+    assert rel_err(s.get_state(), sim.U) < 1e-12
+
+
+def test_zero_steps_and_t_stop_cap():
+    shape = (8, 8, 64)
+    U0 = wl.smooth_random_state(shape, seed=10)
+    s, oc = pair(shape, (1 / 64, 1 / 8, 1 / 8), dtype="f64")
+    s.set_state(U0)
+    s.step(0, 0.0)
+    assert np.array_equal(s.get_state(), U0)
+    dts = s.step(3, 1.0, t_stop=0.004, record=True)
+    assert dts[0] == pytest.approx(0.004) and dts[1] == 0.0 and dts[2] == 0.0
+    sim = oracle.Simulation(oc, U0).advance(1, 0.004)
+    assert rel_err(s.get_state(), sim.U) < 1e-12
+
+
+def test_health_check_flags_negative_pressure():
+    shape = (8, 8, 64)
+    U0 = wl.smooth_random_state(shape, seed=11)
+    U0[4, 3, 2, 10] = 0.1 * U0[4, 3, 2, 10] - 5.0  # E below kinetic energy: P < 0
+    s, _ = pair(shape, (1 / 64, 1 / 8, 1 / 8), dtype="f64")
+    s.set_state(U0)
+    s.step(1, 1e-4)
+    bad, first = s.check()
+    assert bad >= 1 and 0 <= first < 8 * 8 * 64
+    s.set_state(wl.smooth_random_state(shape, seed=11))
+    s.step(1, 1e-4)
+    assert s.check() == (0, -1)
+
+
+# ---------------------------------------------------------------- sources
+
+SRC = {
+    "cool": oracle.SRC_COOLING,
+    "force": oracle.SRC_FORCING,
+    "force+cool": oracle.SRC_FORCING | oracle.SRC_COOLING,
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("src", list(SRC))
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_sources(dtype, src, nsteps):
+    shape = (12, 14, 66)
+    h = (1 / 66, 1 / 14, 1 / 12)
+    U0 = wl.smooth_random_state(shape, seed=12)
+    s, sim = run_both(shape, h, U0, dtype, nsteps, flags=SRC[src], ou_seed=7)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+    if "force" in src:
+        assert np.allclose(s.ou_state(), sim.ahat, rtol=0, atol=1e-13 * np.abs(sim.ahat).max())
+
+
+def test_ou_update_every_four_steps():
+    shape = (8, 8, 64)
+    U0 = wl.smooth_random_state(shape, seed=13)
+    s, sim = run_both(shape, (1 / 64, 1 / 8, 1 / 8), U0, "f64", 9, flags=oracle.SRC_FORCING,
+                      ou_every=4)
+    assert rel_err(s.get_state(), sim.U) < 1e-12
+    assert np.allclose(s.ou_state(), sim.ahat, rtol=0, atol=1e-13 * np.abs(sim.ahat).max())
+
+
+def test_ou_resume_from_saved_state():
+    shape = (8, 8, 64)
+    U0 = wl.smooth_random_state(shape, seed=14)
+    s, oc = pair(shape, (1 / 64, 1 / 8, 1 / 8), dtype="f64", flags=oracle.SRC_FORCING)
+    s.set_state(U0)
+    s.step(3, 1e-3)
+    U3, a3, (t3, k3) = s.get_state(), s.ou_state(), s.clock()
+    s.step(2, 1e-3)
+    ref = s.get_state()
+    s2, _ = pair(shape, (1 / 64, 1 / 8, 1 / 8), dtype="f64", flags=oracle.SRC_FORCING)
+    s2.set_state(U3)
+    s2.set_ou_state(a3)
+    s2.set_clock(t3, k3)
+    s2.step(2, 1e-3)
+    assert np.array_equal(s2.get_state(), ref)
+
+
+# ---------------------------------------------------------------- gravity
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("cool", [False, True])
+def test_gravity_fixed_cycles(dtype, cool):
+    n = 32
+    U0 = wl.grf_density_state(n, seed=0)
+    flags = oracle.SRC_GRAVITY | (oracle.SRC_COOLING if cool else 0)
+    s, sim = run_both((n, n, n), (1 / n,) * 3, U0, dtype, 3, flags=flags, grav_G=wl.JEANS_G,
+                      mg_tol=0.0, mg_max_cycles=3)
+    assert s.mg_cycles() == 3
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+    phi = s.potential().astype(np.float64)
+    assert np.abs(phi - sim.phi).max() < 10 * TOL[dtype] * np.abs(sim.phi).max()
+
+
+def test_gravity_tolerance_cycle_counts():
+    n = 32
+    U0 = wl.grf_density_state(n, seed=1)
+    s, oc = pair((n, n, n), (1 / n,) * 3, dtype="f64", flags=oracle.SRC_GRAVITY,
+                 grav_G=wl.JEANS_G, mg_tol=1e-9, mg_max_cycles=30)
+    s.set_state(U0)
+    sim = oracle.Simulation(oc, U0)
+    for _ in range(3):
+        s.step(1, 2e-3)
+        sim.advance(1, 2e-3)
+        assert s.mg_cycles() == sim.mg_cycles[-1]
+    assert rel_err(s.get_state(), sim.U) < 1e-12
+
+
+# ---------------------------------------------------------------- full sizes, sampled
+
+def _sample_cells(shape, count, seed):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    cells = [(0, 0, 0), (nx - 1, ny - 1, nz - 1)]
+    cells += [tuple(int(v) for v in (rng.integers(nx), rng.integers(ny), rng.integers(nz)))
+              for _ in range(count - 2)]
+    return cells
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_kelvin_helmholtz_256_sampled(dtype):
+    n = 256
+    U0 = as_input(wl.kh_state(n, seed=0), dtype)
+    s, oc = pair((n, n, n), (1 / n,) * 3, dtype=dtype)
+    dt = oracle.cfl_dt(oc, U0)
+    s.set_state(U0)
+    s.step(1, dt)
+    U = s.get_state()
+    cells = _sample_cells(U0.shape[1:], 48, 0)
+    ref = oracle_step_sampled(oc, U0, cells, dt)
+    got = np.array([[U[f, k, j, i] for (i, j, k) in cells] for f in range(5)], dtype=np.float64)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+def test_driven_turbulence_512_sampled_fp32():
+    """The benchmarked configuration: 512^3, fp32, forcing + cooling, on a
+    rough random state so every branch occurs; one CFL step."""
+    n = 512
+    shape = (n, n, n)
+    U0 = as_input(wl.random_state(shape, seed=3, vmax=0.7), "f32")
+    flags = oracle.SRC_FORCING | oracle.SRC_COOLING
+    s, oc = pair(shape, (1 / n,) * 3, dtype="f32", flags=flags)
+    dt = oracle.cfl_dt(oc, U0)
+    s.set_state(U0)
+    s.step(1, dt)
+    U = s.get_state()
+    nvec = oracle.ou_modes(1.0, 2.0)
+    ahat = oracle.ou_advance(oc, nvec, oracle.ou_init(oc, nvec), 0, dt)
+    cells = _sample_cells(shape, 48, 1)
+    ref = oracle_step_sampled(oc, U0, cells, dt, ahat=ahat, nvec=nvec)
+    got = np.array([[U[f, k, j, i] for (i, j, k) in cells] for f in range(5)], dtype=np.float64)
+    assert rel_err(got, ref) < TOL["f32"]

@@ -1,0 +1,97 @@
+"""Host-only checks of the C-ABI library: it loads without a GPU, exports
+every entry point that include/mihydro.h declares, and its argument
+validation (mh_query_workspace is pure host code) rejects bad descriptors
+with the documented status codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2512_13403_amd as mh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    text = open(os.path.join(ROOT, "include", "mihydro.h")).read()
+    return sorted(set(re.findall(r"\b(mh_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mh.load_library()
+    names = declared_entry_points()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(mh.EXPORTED) == names
+
+
+def ws(grid, phys):
+    n = ctypes.c_size_t(0)
+    st = mh.load_library().mh_query_workspace(ctypes.byref(grid), ctypes.byref(phys), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_of_valid_grids():
+    g = mh.grid_desc((16, 16, 128), (1 / 128,) * 3, (1, 0, 0), "f64", 1.4)
+    st, n = ws(g, mh.physics_desc())
+    assert st == mh.OK and n >= 2 * 5 * 128 * 16 * 16 * 8
+    g32 = mh.grid_desc((64, 64, 64), (1 / 64,) * 3, dtype="f32")
+    st, n32 = ws(g32, mh.physics_desc(flags=mh.SRC_FORCING | mh.SRC_COOLING))
+    assert st == mh.OK and n32 >= 2 * 5 * 64 ** 3 * 4
+    st, ng = ws(g32, mh.physics_desc(flags=mh.SRC_GRAVITY, grav_G=1.0))
+    assert st == mh.OK and ng > n32  # the multigrid hierarchy adds > 4 fields
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda g, p: setattr(g, "dtype", 7), mh.E_DTYPE),
+    (lambda g, p: g.n.__setitem__(0, 0), mh.E_INVALID),
+    (lambda g, p: g.h.__setitem__(1, -1.0), mh.E_INVALID),
+    (lambda g, p: g.bc.__setitem__(2, 5), mh.E_INVALID),
+    (lambda g, p: setattr(g, "gamma", 1.0), mh.E_INVALID),
+    (lambda g, p: setattr(g, "cfl", 0.0), mh.E_INVALID),
+    (lambda g, p: setattr(g, "limiter", 9), mh.E_UNSUPPORTED),
+    (lambda g, p: setattr(g, "riemann", 2), mh.E_UNSUPPORTED),
+    (lambda g, p: setattr(p, "flags", 64), mh.E_INVALID),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_tau", 0.0)), mh.E_INVALID),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_kmin", 3.0),
+                   setattr(p, "ou_kmax", 2.0)), mh.E_INVALID),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_kmax", 3.5)), mh.E_UNSUPPORTED),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_COOLING), setattr(p, "cool_ts", 0.0)), mh.E_INVALID),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.bc.__setitem__(0, 1)), mh.E_SHAPE),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.n.__setitem__(0, 32)), mh.E_SHAPE),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "mg_coarsest", 0)), mh.E_INVALID),
+])
+def test_validation_rejects(mutate, status):
+    g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f64")
+    p = mh.physics_desc()
+    mutate(g, p)
+    st, _ = ws(g, p)
+    assert st == status
+
+
+def test_gravity_coarsest_grid_limit():
+    # 3 * 2^k grids coarsen to 3^3; 25 * 4 = 100 coarsens to 25^3 > 2048 cells
+    g = mh.grid_desc((96, 96, 96), (1 / 96,) * 3, dtype="f64")
+    assert ws(g, mh.physics_desc(flags=mh.SRC_GRAVITY))[0] == mh.OK
+    g = mh.grid_desc((100, 100, 100), (1 / 100,) * 3, dtype="f64")
+    assert ws(g, mh.physics_desc(flags=mh.SRC_GRAVITY))[0] == mh.E_SHAPE
+
+
+def test_null_arguments():
+    lib = mh.load_library()
+    assert lib.mh_query_workspace(None, None, None) == mh.E_INVALID
+    assert lib.mh_step(None, 1, 0.0, 1.0, None, None) == mh.E_INVALID
+    assert lib.mh_set_state(None, None, 0) == mh.E_INVALID
+    assert lib.mh_last_error(None) == b""
+    lib.mh_destroy(None)
+
+
+def test_solver_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    g = mh.grid_desc((8, 8, 8), (1 / 8,) * 3)
+    with pytest.raises(RuntimeError):
+        mh.Solver(g)
