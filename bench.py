@@ -12,7 +12,7 @@ roofline         the dominant kernel (RK stage 2) against the MI355X HBM peak:
                  algorithmic bytes per launch (60 B per cell in fp32: read U1,
                  read U^n, write U^{n+1}) over its mean duration from HIP events
                  recorded around every launch on the library's stream
-cpu_baseline     the FP64 oracle on the same physics at 128^3 for 8 steps
+cpu_baseline     the FP64 oracle on the same physics at 192^3 for 16 steps
 """
 import argparse
 import hashlib
@@ -50,7 +50,7 @@ def measured_traffic():
     return float(rec["stage2_bytes"])
 
 
-def cpu_baseline(n=128, steps=8):
+def cpu_baseline(n=192, steps=16):
     import numpy as np
 
     import oracle
@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one plain 1 GiB device copy (torch copy_ of 2^28 fp32), "
+                         "the reference for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -87,6 +90,14 @@ def main():
     import torch
 
     import paper_2512_13403_amd as mh
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     n = args.n
     shape = (n, n, n)

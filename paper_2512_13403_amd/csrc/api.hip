@@ -22,7 +22,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-  size_t U = 0, U1 = 0, clk = 0, dtlog = 0, ou_n = 0, ou_ahat = 0, ou_coef = 0;
+  size_t U = 0, U1 = 0, clk = 0, dtlog = 0, ou_n = 0, ou_ahat = 0, ou_coef = 0, ou_rows = 0;
   size_t tab[3] = {0, 0, 0};
   MGLayout mg;
   size_t total = 0;
@@ -117,6 +117,7 @@ Layout make_layout(const mh_grid_desc* g, const mh_physics_desc* p, int nmodes) 
     L.ou_ahat = take(6 * MAX_MODES * sizeof(double));
     L.ou_coef = take(6 * MAX_MODES * es);
     for (int a = 0; a < 3; ++a) L.tab[a] = take((size_t)(R + 1) * g->n[a] * 2 * es);
+    L.ou_rows = take((size_t)g->n[1] * g->n[2] * (R + 1) * 6 * es);
   }
   if (p->flags & MH_SRC_GRAVITY) off = mg_layout(g, p, off, es, L.mg);
   L.total = off;
@@ -311,6 +312,19 @@ extern "C" mh_status mh_get_state(mh_ctx* c, void* U, int where) {
 }
 
 template <typename T>
+static CoolParams<T> cool_params(const mh_grid_desc& g, const mh_physics_desc& p) {
+  CoolParams<T> c;
+  c.tc = (T)p.cool_tc;
+  c.ts = (T)p.cool_ts;
+  c.its = (T)(1.0 / p.cool_ts);
+  c.tfloor = (T)p.cool_tfloor;
+  c.sqrt_tc = (T)std::sqrt(p.cool_tc);
+  c.k1r = (T)((g.gamma - 1.0) * p.cool_lambda0 / (2.0 * std::sqrt(p.cool_tc)));
+  c.k2r = (T)((g.gamma - 1.0) * p.cool_lambda0 / p.cool_ts);
+  return c;
+}
+
+template <typename T>
 static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, double* dt_out) {
   const mh_grid_desc& g = c->g;
   const mh_physics_desc& p = c->p;
@@ -331,16 +345,12 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
   a.ihx = (T)ih[0];
   a.ihy = (T)ih[1];
   a.ihz = (T)ih[2];
-  a.cool.l0 = (T)p.cool_lambda0;
-  a.cool.tc = (T)p.cool_tc;
-  a.cool.ts = (T)p.cool_ts;
-  a.cool.tfloor = (T)p.cool_tfloor;
-  a.cool.sqrt_tc = (T)std::sqrt(p.cool_tc);
+  a.cool = cool_params<T>(g, p);
   if (force) {
-    a.ou_coef = c->at<T>(c->L.ou_coef);
-    a.ou_n = c->at<int>(c->L.ou_n);
+    a.ou_rows = c->at<T>(c->L.ou_rows);
     for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
     a.ou_modes = c->nmodes;
+    a.ou_R = (int)std::floor(p.ou_kmax);
   }
 
   PrologueArgs pa{};
@@ -364,6 +374,10 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
     pa.log_index = s % DTLOG_CAP;
     long tk = time_begin(c, MH_TIME_PROLOGUE);
     MH_HIP(c, launch_prologue(pa, c->stream));
+    if (force)
+      MH_HIP(c, launch_force_rows<T>(c->at<T>(c->L.ou_coef), c->at<int>(c->L.ou_n), c->nmodes,
+                                     a.ou_tab[1], a.ou_tab[2], g.n[1], g.n[2], a.ou_R,
+                                     c->at<T>(c->L.ou_rows), c->stream));
     time_end(c, tk);
     a.uin = U;
     a.un = nullptr;
@@ -381,7 +395,7 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
       MH_HIP(c, launch_stage<T>(2, g.limiter, force, false, a, geom, c->stream));
       time_end(c, tk);
       tk = time_begin(c, MH_TIME_OTHER);
-      MH_HIP(c, mg_gravity_step<T>(c->ws, c->L.mg, c->g, c->p, U, clk, c->stream));
+      MH_HIP(c, mg_gravity_step<T>(c->ws, c->L.mg, c->g, c->p, a.cool, U, clk, c->stream));
       time_end(c, tk);
     } else {
       tk = time_begin(c, MH_TIME_STAGE2);

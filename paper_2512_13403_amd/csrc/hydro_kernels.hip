@@ -25,15 +25,28 @@
 
 namespace mh {
 
+// minmod(a, b): the smaller magnitude when a and b share a sign, else 0 --
+// which is the median of (a, b, 0): one v_med3_f32 in fp32.
+__device__ __forceinline__ float minmod(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
+__device__ __forceinline__ double minmod(double a, double b) {
+  return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// limited slope of W_i from W_{i-1}, W_i, W_{i+1} (App. A.1)
 template <typename T, int LIM>
 __device__ __forceinline__ T limited_slope(T wm, T w0, T wp) {
   if (LIM == LIM_NONE) return T(0);
-  // minmod(a, b) with a = W_{i+1} - W_i and b = W_i - W_{i-1}: the smaller
-  // magnitude when both share a sign, else 0; a tie takes a.
-  T a = wp - w0, b = w0 - wm;
-  T m = (fabs(a) <= fabs(b)) ? a : b;
-  return (a * b > T(0)) ? m : T(0);
+  return minmod(wp - w0, w0 - wm);
 }
+
+// c = sqrt(gamma P / rho) from gp = gamma P: in fp32 as gp * rsq(gp rho), one
+// transcendental instead of a reciprocal and a square root
+__device__ __forceinline__ float sound_speed(float gp, float rho) {
+  return gp * __builtin_amdgcn_rsqf(gp * rho);
+}
+__device__ __forceinline__ double sound_speed(double gp, double rho) { return sqrt(gp / rho); }
 
 // HLLC flux through a face with normal velocity component `n` (0, 1, 2) of
 // the primitive face states wl, wr = (rho, vx, vy, vz, P).  Davis speeds
@@ -51,8 +64,7 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   constexpr int t1 = 1 + (N + 1) % 3, t2 = 1 + (N + 2) % 3, vn = 1 + N;
   const T rl = wl[0], ul = wl[vn], pl = wl[4];
   const T rr = wr[0], ur = wr[vn], pr = wr[4];
-  const T irl = dev_rcp(rl), irr = dev_rcp(rr);
-  const T cl = dev_sqrt(gamma * pl * irl), cr = dev_sqrt(gamma * pr * irr);
+  const T cl = sound_speed(gamma * pl, rl), cr = sound_speed(gamma * pr, rr);
   const T SL = fmin(ul - cl, ur - cr), SR = fmax(ul + cl, ur + cr);
   const T kel = T(0.5) * rl * (ul * ul + wl[t1] * wl[t1] + wl[t2] * wl[t2]);
   const T ker = T(0.5) * rr * (ur * ur + wr[t1] * wr[t1] + wr[t2] * wr[t2]);
@@ -98,11 +110,15 @@ __device__ __forceinline__ void face_flux(const T (&wm)[5], const T (&w0)[5], co
 }
 
 template <typename T, int STAGE, int LIM, bool FORCE, bool COOL>
-__global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
+__global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(const StageArgs<T> a) {
   __shared__ T sW[5][TY + 4][TX + 4];
   __shared__ T sFx[5][TY][TX + 1];
   __shared__ T sFy[5][TY + 1][TX];
   __shared__ T sRed[NTHREADS / 64];
+  // separable forcing: the row sums P_n, Q_n (see k_force_rows) of the tile's
+  // rows, three planes in flight, and the x phase factors X_n of its columns
+  __shared__ T sPQ[FORCE ? 3 : 1][TY][FORCE ? 6 * (MAX_R + 1) : 1];
+  __shared__ T sX[FORCE ? MAX_R + 1 : 1][2][TX];
 
   // XCD-aware tile order: consecutive hardware workgroups go round-robin to
   // the 8 XCDs, so give each XCD a contiguous range of tiles (x fastest, then
@@ -142,6 +158,31 @@ __global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
     h_col = (long long)bc_map(y0 - 2 + h_ly, a.ny, a.bcy) * a.nx + bc_map(x0 + hx, a.nx, a.bcx);
   }
 
+  // forcing rows: thread tid < TY * 6(R+1) owns element `pq_e` of its row's
+  // record; the record of plane z+1 is loaded during plane z-1 and stored to
+  // LDS during plane z (slot (z - z0) mod 3), read during plane z+1
+  const int nr6 = FORCE ? 6 * (a.ou_R + 1) : 1;
+  const bool pq_thread = FORCE && tid < TY * nr6;
+  const int pq_r = pq_thread ? tid / nr6 : 0, pq_e = pq_thread ? tid % nr6 : 0;
+  const long long pq_row = (y0 + pq_r) < a.ny ? (y0 + pq_r) : 0;
+  T pq_ahead = T(0);
+  if (FORCE) {
+    if (ty == 0) {
+      const int ix = gx < a.nx ? gx : 0;
+      for (int n = 0; n <= a.ou_R; ++n) {
+        sX[n][0][tx] = a.ou_tab[0][2 * ((long long)n * a.nx + ix)];
+        sX[n][1][tx] = a.ou_tab[0][2 * ((long long)n * a.nx + ix) + 1];
+      }
+    }
+    if (pq_thread) {
+      sPQ[0][pq_r][pq_e] = a.ou_rows[((long long)z0 * a.ny + pq_row) * nr6 + pq_e];
+      if (z0 + 1 < zend)
+        pq_ahead = a.ou_rows[((long long)(z0 + 1) * a.ny + pq_row) * nr6 + pq_e];
+    }
+    __syncthreads();
+  }
+  int pq_slot = 0;
+
   // z ring: W at z-1, z, z+1, z+2; U at z, z+1, z+2; z-flux at z-1/2
   T w[4][5], u[3][5], fzm[5];
   {
@@ -160,17 +201,36 @@ __global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
   T smax = T(0);
   unsigned long long nbad = 0, first_bad = ~0ull;
 
+  // software pipeline: the column cell two planes ahead and this thread's halo
+  // cell of the current plane are loaded one iteration early
+  T u_ahead[5], h_ahead[5] = {T(0), T(0), T(0), T(0), T(0)};
+  load_cell(a.uin, N, (long long)bc_map(z0 + 2, a.nz, a.bcz) * plane + col, u_ahead);
+  if (h_lx >= 0) load_cell(a.uin, N, (long long)z0 * plane + h_col, h_ahead);
+
   for (int z = z0; z < zend; ++z) {
-    load_cell(a.uin, N, (long long)bc_map(z + 2, a.nz, a.bcz) * plane + col, u[2]);
+    T hu[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      u[2][f] = u_ahead[f];
+      hu[f] = h_ahead[f];
+    }
+    if (z + 1 < zend) {
+      load_cell(a.uin, N, (long long)bc_map(z + 3, a.nz, a.bcz) * plane + col, u_ahead);
+      if (h_lx >= 0) load_cell(a.uin, N, (long long)(z + 1) * plane + h_col, h_ahead);
+    }
     to_prim(u[2], gm1, w[3]);
 #pragma unroll
     for (int f = 0; f < 5; ++f) sW[f][ty + 2][tx + 2] = w[1][f];
     if (h_lx >= 0) {
-      T hu[5], hw[5];
-      load_cell(a.uin, N, (long long)z * plane + h_col, hu);
+      T hw[5];
       to_prim(hu, gm1, hw);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sW[f][h_ly][h_lx] = hw[f];
+    }
+    if (pq_thread) {
+      if (z + 1 < zend) sPQ[pq_slot == 2 ? 0 : pq_slot + 1][pq_r][pq_e] = pq_ahead;
+      if (z + 2 < zend)
+        pq_ahead = a.ou_rows[((long long)(z + 2) * a.ny + pq_row) * nr6 + pq_e];
     }
     __syncthreads();
 
@@ -255,21 +315,15 @@ __global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
         // a(x) = scale sum_m 2 Re(ahat_m exp(2 pi i n_m . x / L)) at the cell
         // centre; coef = 2 scale ahat (T), phase tables per axis for n >= 0,
         // complex conjugate for n < 0.
-        T acc[3] = {T(0), T(0), T(0)};
-        const int ix = gx < a.nx ? gx : 0, iy = gy < a.ny ? gy : 0;
-        for (int m = 0; m < a.ou_modes; ++m) {
-          const int nxm = a.ou_n[3 * m], nym = a.ou_n[3 * m + 1], nzm = a.ou_n[3 * m + 2];
-          const T* ex = a.ou_tab[0] + 2 * ((long long)abs(nxm) * a.nx + ix);
-          const T* ey = a.ou_tab[1] + 2 * ((long long)abs(nym) * a.ny + iy);
-          const T* ez = a.ou_tab[2] + 2 * ((long long)abs(nzm) * a.nz + z);
-          const T xr = ex[0], xi = nxm < 0 ? -ex[1] : ex[1];
-          const T yr = ey[0], yi = nym < 0 ? -ey[1] : ey[1];
-          const T zr = ez[0], zi = nzm < 0 ? -ez[1] : ez[1];
-          const T pr = xr * yr - xi * yi, pi = xr * yi + xi * yr;
-          const T er = pr * zr - pi * zi, ei = pr * zi + pi * zr;
+        // separable form: a_c = P_0 + sum_{n>=1} (Re X_n P_n - Im X_n Q_n)
+        const T* pq = sPQ[pq_slot][ty];
+        T acc[3];
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            acc[c] += a.ou_coef[6 * m + 2 * c] * er - a.ou_coef[6 * m + 2 * c + 1] * ei;
+        for (int c = 0; c < 3; ++c) acc[c] = pq[2 * c];
+        for (int n = 1; n <= a.ou_R; ++n) {
+          const T xr = sX[n][0][tx], xi = sX[n][1][tx];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[c] += xr * pq[6 * n + 2 * c] - xi * pq[6 * n + 2 * c + 1];
         }
         // m += rho a dt, E += (m_old . a) dt  (Sec. 3.1.1, Sec. 2.1 listing)
         const T dE = un[1] * acc[0] + un[2] * acc[1] + un[3] * acc[2];
@@ -277,19 +331,21 @@ __global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
         for (int c = 0; c < 3; ++c) un[1 + c] += un[0] * acc[c] * dt;
         un[4] += dE * dt;
       }
+      const T ir = dev_rcp(un[0]);
+      const T vx = un[1] * ir, vy = un[2] * ir, vz = un[3] * ir;
+      const T ek = T(0.5) * un[0] * (vx * vx + vy * vy + vz * vz);
+      T pn = gm1 * (un[4] - ek);
       if (COOL) {
-        const T ek = T(0.5) * (un[1] * un[1] + un[2] * un[2] + un[3] * un[3]) / un[0];
-        const T Tin = gm1 * (un[4] - ek) / un[0];
-        const T Tn = cool_T(un[0], Tin, dt, gm1, a.cool);
+        const T Tn = cool_T(un[0], pn * ir, dt, a.cool);
         un[4] = ek + un[0] * Tn * gm1inv;
+        pn = gm1 * (un[4] - ek);
       }
       if (inside) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
         // CFL signal speed of the new state and the health check
-        T wn[5];
-        to_prim(un, gm1, wn);
-        const T cs = dev_sqrt(gamma * wn[4] * dev_rcp(wn[0]));
+        T wn[5] = {un[0], vx, vy, vz, pn};
+        const T cs = sound_speed(gamma * pn, un[0]);
         const T s = fmax(fmax((fabs(wn[1]) + cs) * a.ihx, (fabs(wn[2]) + cs) * a.ihy),
                          (fabs(wn[3]) + cs) * a.ihz);
         smax = fmax(smax, s);
@@ -303,6 +359,7 @@ __global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
     }
 
     // advance the z ring
+    pq_slot = pq_slot == 2 ? 0 : pq_slot + 1;
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       fzm[f] = fzp[f];
@@ -329,6 +386,65 @@ __global__ __launch_bounds__(NTHREADS) void k_stage(const StageArgs<T> a) {
     }
   }
 }
+
+// Forcing row records, once per step.  The OU acceleration
+//   a_c(x, y, z) = sum_m Re(coef_{m,c} X_{n_x}(x) Y_{n_y}(y) Z_{n_z}(z)),
+// coef = 2 * scale * ahat and X_n(x) = exp(2 pi i n (x + 1/2) / n_x) (the
+// complex conjugate for n < 0), separates over x: with
+//   B_{n,c}(y, z) = sum over modes with n_x = n of coef_{m,c} Y(y) Z(z),
+//   P_{n,c} = Re(B_{n,c} + B_{-n,c}),  Q_{n,c} = Im(B_{n,c} - B_{-n,c}),
+// a_c = P_{0,c} + sum_{n >= 1} (Re X_n P_{n,c} - Im X_n Q_{n,c}).  One thread
+// per (row (y, z), n) writes [n][c][P, Q] of the row's record (6 (R+1) values).
+template <typename T>
+__global__ __launch_bounds__(256) void k_force_rows(const T* __restrict__ coef,
+                                                    const int* __restrict__ nvec, int nmodes,
+                                                    const T* __restrict__ tabY,
+                                                    const T* __restrict__ tabZ, int ny, int nz,
+                                                    int R, T* __restrict__ rows) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)ny * nz * (R + 1)) return;
+  const int n = (int)(t % (R + 1));
+  const long long row = t / (R + 1);  // z * ny + y
+  const int y = (int)(row % ny), z = (int)(row / ny);
+  T P[3] = {T(0), T(0), T(0)}, Q[3] = {T(0), T(0), T(0)};
+  for (int m = 0; m < nmodes; ++m) {
+    const int nxm = nvec[3 * m];
+    if (nxm != n && nxm != -n) continue;
+    const int nym = nvec[3 * m + 1], nzm = nvec[3 * m + 2];
+    const T* ey = tabY + 2 * ((long long)abs(nym) * ny + y);
+    const T* ez = tabZ + 2 * ((long long)abs(nzm) * nz + z);
+    const T yr = ey[0], yi = nym < 0 ? -ey[1] : ey[1];
+    const T zr = ez[0], zi = nzm < 0 ? -ez[1] : ez[1];
+    const T er = yr * zr - yi * zi, ei = yr * zi + yi * zr;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T cr = coef[6 * m + 2 * c], ci = coef[6 * m + 2 * c + 1];
+      const T br = cr * er - ci * ei, bi = cr * ei + ci * er;
+      P[c] += br;
+      Q[c] += (nxm == n) ? bi : -bi;
+    }
+  }
+  T* out = rows + row * 6 * (R + 1) + 6 * n;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    out[2 * c] = P[c];
+    out[2 * c + 1] = Q[c];
+  }
+}
+
+template <typename T>
+hipError_t launch_force_rows(const T* coef, const int* nvec, int nmodes, const T* tabY,
+                             const T* tabZ, int ny, int nz, int R, T* rows, hipStream_t s) {
+  const long long total = (long long)ny * nz * (R + 1);
+  hipLaunchKernelGGL((k_force_rows<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     coef, nvec, nmodes, tabY, tabZ, ny, nz, R, rows);
+  return hipGetLastError();
+}
+
+template hipError_t launch_force_rows<float>(const float*, const int*, int, const float*,
+                                             const float*, int, int, int, float*, hipStream_t);
+template hipError_t launch_force_rows<double>(const double*, const int*, int, const double*,
+                                              const double*, int, int, int, double*, hipStream_t);
 
 // CFL signal-speed max of a state (used when no stage-2 epilogue produced it,
 // i.e. right after the state was set).

@@ -41,6 +41,6 @@ size_t mg_phi_offset(const MGLayout& L);
 // test convergence.
 template <typename T>
 hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
-                           T* U, DevClock* clk, hipStream_t s);
+                           const CoolParams<T>& cool, T* U, DevClock* clk, hipStream_t s);
 
 }  // namespace mh

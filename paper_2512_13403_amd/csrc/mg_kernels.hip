@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict_
     if (COOL) {
       const T ek = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
       const T Tin = gm1 * (u[4] - ek) / u[0];
-      const T Tn = cool_T(u[0], Tin, dt, gm1, cool);
+      const T Tn = cool_T(u[0], Tin, dt, cool);
       u[4] = ek + u[0] * Tn / gm1;
     }
 #pragma unroll
@@ -411,7 +411,7 @@ hipError_t mg_init(char* ws, const MGLayout& L, const mh_grid_desc* g, hipStream
 
 template <typename T>
 hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
-                           T* U, DevClock* clk, hipStream_t s) {
+                           const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s) {
   MGLevel& f = L.lev[0];
   const int n = f.n;
   const long long N = (long long)n * n * n;
@@ -442,12 +442,6 @@ hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const m
     ++cycles;
   }
   hipLaunchKernelGGL(k_set_cycles, dim3(1), dim3(64), 0, s, clk, cycles);
-  CoolParams<T> cp;
-  cp.l0 = (T)p.cool_lambda0;
-  cp.tc = (T)p.cool_tc;
-  cp.ts = (T)p.cool_ts;
-  cp.tfloor = (T)p.cool_tfloor;
-  cp.sqrt_tc = (T)std::sqrt(p.cool_tc);
   const T i2h = (T)(1.0 / (2.0 * f.h));
   if (p.flags & MH_SRC_COOLING)
     hipLaunchKernelGGL((k_grav_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U,
@@ -460,9 +454,11 @@ hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const m
 }
 
 template hipError_t mg_gravity_step<float>(char*, MGLayout&, const mh_grid_desc&,
-                                           const mh_physics_desc&, float*, DevClock*, hipStream_t);
+                                           const mh_physics_desc&, const CoolParams<float>&, float*,
+                                           DevClock*, hipStream_t);
 template hipError_t mg_gravity_step<double>(char*, MGLayout&, const mh_grid_desc&,
-                                            const mh_physics_desc&, double*, DevClock*, hipStream_t);
+                                            const mh_physics_desc&, const CoolParams<double>&,
+                                            double*, DevClock*, hipStream_t);
 
 size_t mg_phi_offset(const MGLayout& L) { return L.lev[0].phi[L.cur0]; }
 

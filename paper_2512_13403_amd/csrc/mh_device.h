@@ -13,6 +13,8 @@ constexpr int TX = 64;
 constexpr int TY = 8;
 constexpr int NTHREADS = TX * TY;
 constexpr int MAX_MODES = 64;   // OU modes
+constexpr int MAX_R = 8;        // largest |n_a| of a forced OU mode
+constexpr int MAX_ZC = 64;      // longest z-chunk of the stage kernel
 constexpr int DTLOG_CAP = 4096; // per-step dt records kept on the device
 
 // Device clock and per-step scalars, written by one thread of the prologue
@@ -56,12 +58,14 @@ template <> __device__ __forceinline__ float dev_sqrt<float>(float x) {
 }
 template <> __device__ __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
 
-// accurate versions for the once-per-cell source terms
-__device__ __forceinline__ float acc_sqrt(float x) { return sqrtf(x); }
+// transcendentals of the cooling source: the hardware instructions in fp32
+// (about 1 ulp for sqrt, a few ulp for log/exp, far inside the fp32 parity
+// tolerance), correctly rounded library calls in fp64
+__device__ __forceinline__ float acc_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double acc_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float acc_log(float x) { return logf(x); }
+__device__ __forceinline__ float acc_log(float x) { return __logf(x); }
 __device__ __forceinline__ double acc_log(double x) { return log(x); }
-__device__ __forceinline__ float acc_exp(float x) { return expf(x); }
+__device__ __forceinline__ float acc_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double acc_exp(double x) { return exp(x); }
 
 // order-preserving bit pattern of a non-negative value, for atomicMax
@@ -91,9 +95,12 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Cooling constants.  k1r = (gamma-1) L0 / (2 sqrt(tc)) and k2r = (gamma-1) L0 / ts
+// are the per-unit-density rates at which sqrt(T) falls above tc and
+// exp(-(T - tc)/ts) rises below tc.
 template <typename T>
 struct CoolParams {
-  T l0, tc, ts, tfloor, sqrt_tc;
+  T tc, ts, its, tfloor, sqrt_tc, k1r, k2r;  // its = 1 / ts
 };
 
 template <typename T>
@@ -117,13 +124,13 @@ __device__ __forceinline__ void load_cell(const T* __restrict__ U, long long N, 
 // Exact isochoric cooling of one cell over dt (closed form on each branch of
 // the two-branch curve), then the temperature floor; returns the new T.
 template <typename T>
-__device__ __forceinline__ T cool_T(T rho, T Tin, T dt, T gm1, const CoolParams<T>& c) {
-  const T k2 = gm1 * rho * c.l0 / c.ts;
+__device__ __forceinline__ T cool_T(T rho, T Tin, T dt, const CoolParams<T>& c) {
+  const T k2 = c.k2r * rho;
   T Tn;
   if (Tin >= c.tc) {
-    const T k1 = gm1 * rho * c.l0 / (T(2) * c.sqrt_tc);
+    const T k1 = c.k1r * rho;
     const T st = acc_sqrt(Tin);
-    const T t1 = (st - c.sqrt_tc) / k1;
+    const T t1 = (st - c.sqrt_tc) * dev_rcp(k1);
     if (dt <= t1) {
       const T s = st - k1 * dt;
       Tn = s * s;
@@ -131,7 +138,7 @@ __device__ __forceinline__ T cool_T(T rho, T Tin, T dt, T gm1, const CoolParams<
       Tn = c.tc - c.ts * acc_log(T(1) + k2 * (dt - t1));
     }
   } else {
-    Tn = c.tc - c.ts * acc_log(acc_exp(-(Tin - c.tc) / c.ts) + k2 * dt);
+    Tn = c.tc - c.ts * acc_log(acc_exp((c.tc - Tin) * c.its) + k2 * dt);
   }
   return fmax(Tn, c.tfloor);
 }

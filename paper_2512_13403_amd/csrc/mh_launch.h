@@ -19,10 +19,10 @@ struct StageArgs {
   const T* un;                // U^n at the cell itself (stage 2; may alias uout)
   T* uout;                    // stage output
   DevClock* clk;
-  const T* __restrict__ ou_coef;  // [M][3][re, im] = 2 * scale * ahat
-  const int* __restrict__ ou_n;   // [M][3] integer mode vectors
+  const T* __restrict__ ou_rows;  // [nz][ny][R+1][3][P, Q] forcing row records
   const T* ou_tab[3];             // per axis [R+1][n_a][cos, sin] of 2 pi n (i + 1/2) / n_a
   int ou_modes;
+  int ou_R;  // largest |n_a| among the modes (floor of kmax)
   int nx, ny, nz, bcx, bcy, bcz;
   long long ncell;
   T gamma, gm1, gm1inv, ihx, ihy, ihz;
@@ -57,6 +57,9 @@ struct PrologueArgs {
 template <typename T>
 hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs<T> a,
                         const StageGeom& g, hipStream_t s);
+template <typename T>
+hipError_t launch_force_rows(const T* coef, const int* nvec, int nmodes, const T* tabY,
+                             const T* tabZ, int ny, int nz, int R, T* rows, hipStream_t s);
 template <typename T>
 hipError_t launch_smax(const T* U, const StageGeom& g, T gamma, const double* ih, DevClock* clk,
                        hipStream_t s);
