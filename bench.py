@@ -27,11 +27,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_k_stage_512_fp32.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2512_13403_amd", "csrc", "hydro_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2512_13403_amd", "csrc", f)
+               for f in ("hydro_kernels.hip", "mh_device.h")]
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the stage kernels are compiled from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
