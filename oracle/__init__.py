@@ -103,6 +103,13 @@ def lib():
             "or_mg_solve": (ctypes.c_int, [cp, ctypes.c_int, ctypes.c_double, dp, dp]),
             "or_gravity_accel": (ctypes.c_int, [cp, dp, dp, dp]),
             "or_num_threads": (ctypes.c_int, []),
+            "or_rhs_vjp": (None, [cp, dp, dp, dp]),
+            "or_rk2_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
+            "or_kick_vjp": (None, [cp, dp, dp, ctypes.c_double, dp, dp, dp]),
+            "or_cool_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
+            "or_gravity_vjp": (ctypes.c_int, [cp, dp, ctypes.c_double, dp, dp, dp]),
+            "or_step_vjp": (None, [cp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int, ip, dp, dp,
+                                   dp, dp]),
             "or_step": (ctypes.c_double, [cp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                           ctypes.c_int, ip, dp, dp, ip]),
         }
@@ -278,6 +285,70 @@ def gravity_accel(c, U, phi):
     acc = np.zeros((3,) + _shape(c))
     cyc = lib().or_gravity_accel(ctypes.byref(c), _dp(U), _dp(phi), _dp(acc))
     return acc, phi, cyc
+
+
+# ---------------------------------------------------------------- adjoints
+# Reverse-mode derivatives with dt held fixed (oracle_adjoint.c).
+
+def rhs_vjp(c, U, v):
+    """(dL/dU)^T v for L = rhs (App. A.1-A.3)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty_like(U)
+    lib().or_rhs_vjp(ctypes.byref(c), _dp(U), _dp(v), _dp(out))
+    return out
+
+
+def rk2_vjp(c, U, dt, lam):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.empty_like(U)
+    lib().or_rk2_vjp(ctypes.byref(c), _dp(U), dt, _dp(lam), _dp(out))
+    return out
+
+
+def kick_vjp(c, U, acc, dt, lam):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    acc = np.ascontiguousarray(acc, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.empty_like(U)
+    accb = np.empty_like(acc)
+    lib().or_kick_vjp(ctypes.byref(c), _dp(U), _dp(acc), dt, _dp(lam), _dp(out), _dp(accb))
+    return out, accb
+
+
+def cool_vjp(c, U, dt, lam):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.empty_like(U)
+    lib().or_cool_vjp(ctypes.byref(c), _dp(U), dt, _dp(lam), _dp(out))
+    return out
+
+
+def gravity_vjp(c, U, dt, phi, lam):
+    """Reverse of U' = kick(U, -grad A^+ 4 pi G (rho - <rho>)); phi = warm start."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    out = np.empty_like(U)
+    lib().or_gravity_vjp(ctypes.byref(c), _dp(U), dt, _dp(phi), _dp(lam), _dp(out))
+    return out
+
+
+def step_vjp(c, Un, dt, step, nvec, ahat, phi, lam):
+    """(dU^{n+1}/dU^n)^T lam for one full step at fixed dt; ahat and phi are
+    the OU modes and potential before the step."""
+    Un = np.ascontiguousarray(Un, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    nv = np.ascontiguousarray(nvec, dtype=np.int32).reshape(-1)
+    if nv.size == 0:
+        nv = np.zeros(3, dtype=np.int32)
+    a = np.array(ahat, dtype=np.float64, copy=True)
+    ph = np.array(phi, dtype=np.float64, copy=True)
+    out = np.empty_like(Un)
+    lib().or_step_vjp(ctypes.byref(c), _dp(Un), dt, step, len(nvec), _ip(nv), _dp(a), _dp(ph),
+                      _dp(lam), _dp(out))
+    return out
 
 
 @dataclass

@@ -66,6 +66,22 @@ int or_gravity_accel(const or_config *c, const double *U, double *phi, double *a
 
 int or_num_threads(void);
 
+/* reverse-mode derivatives (oracle_adjoint.c) */
+void or_hllc_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],
+                 double wlb[5], double wrb[5]);
+void or_rhs_vjp(const or_config *c, const double *U, const double *v, double *out);
+void or_rk2_vjp(const or_config *c, const double *U, double dt, const double *lam2,
+                double *lam);
+void or_kick_vjp(const or_config *c, const double *U, const double *acc, double dt,
+                 const double *lamp, double *lam, double *accb);
+void or_cool_vjp(const or_config *c, const double *U, double dt, const double *lamp,
+                 double *lam);
+int or_gravity_vjp(const or_config *c, const double *U, double dt, double *phi,
+                   const double *lamp, double *lam);
+void or_step_vjp(const or_config *c, const double *Un, double dt, int64_t step, int nmodes,
+                 const int32_t *nvec, const double *ou_ahat, double *phi,
+                 const double *lam_np1, double *lam_n);
+
 double or_step(const or_config *c, double *U, double dt_fixed, double dt_cap,
                int64_t step, int nmodes, const int32_t *nvec, double *ou_ahat,
                double *phi, int *mg_cycles);

@@ -1,0 +1,182 @@
+"""Pins of the oracle's hand-written adjoint (reverse-mode derivative at fixed
+dt, paper Sec. 2.3 and Sec. 6.2.4) against fp64 central finite differences of
+the oracle's own forward maps: the dot-product identity
+w . (J v) = (J^T w) . v with J v from central differences, and single entries
+of J^T w against difference quotients along unit vectors.  Inputs are
+cell-wise random states, whose minmod decisions have margins of order 1e-4
+(a smooth field puts many cells at the |a| = |b| kink, and a state at rest at
+the ab = 0 kink, where the one-sided derivatives differ and a difference
+quotient straddles them), or perturbations that keep the kinked fields fixed."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+
+def fd_jvp(f, U, v, eps):
+    """Central difference (f(U + eps v) - f(U - eps v)) / (2 eps)."""
+    return (f(U + eps * v) - f(U - eps * v)) / (2.0 * eps)
+
+
+def check_dot(f, vjp, U, seed, eps=1e-6, rtol=2e-7, trials=3, fields=None):
+    """fields: indices of the state fields to perturb (default all)."""
+    rng = np.random.default_rng(seed)
+    for _ in range(trials):
+        v = rng.standard_normal(U.shape) * np.abs(U).mean(axis=tuple(range(1, U.ndim)), keepdims=True)
+        if fields is not None:
+            mask = np.zeros(U.shape[0])
+            mask[list(fields)] = 1.0
+            v = v * mask.reshape((-1,) + (1,) * (U.ndim - 1))
+        w = rng.standard_normal(U.shape)
+        jv = fd_jvp(f, U, v, eps)
+        lhs = float((w * jv).sum())
+        rhs = float((vjp(w) * v).sum())
+        assert lhs == pytest.approx(rhs, rel=rtol), (lhs, rhs)
+
+
+def check_entries(f, vjp, U, seed, count=12, eps=1e-6, rtol=2e-6):
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(U.shape)
+    g = vjp(w)
+    flat = rng.choice(U.size, count, replace=False)
+    for q in flat:
+        e = np.zeros(U.size)
+        e[q] = 1.0
+        e = e.reshape(U.shape)
+        d = float((w * fd_jvp(f, U, e, eps * max(abs(U.flat[q]), 1.0))).sum())
+        assert g.flat[q] == pytest.approx(d, rel=rtol, abs=1e-7 * (abs(d) + 1.0)), q
+
+
+GRIDS = [
+    ("periodic", wl.Grid((6, 7, 8), (1 / 8, 1 / 7, 1 / 6))),
+    ("outflow", wl.Grid((5, 6, 9), (1 / 9, 1 / 6, 1 / 5), (1, 1, 1))),
+    ("mixed", wl.Grid((4, 1, 10), (1 / 10, 1.0, 1 / 4), (1, 0, 0))),
+]
+
+
+@pytest.mark.parametrize("name,grid", GRIDS)
+@pytest.mark.parametrize("limiter", [oracle.LIM_MINMOD, oracle.LIM_NONE])
+def test_rhs_vjp_dot_product(name, grid, limiter):
+    U = wl.random_state(grid.shape, seed=3, vmax=0.7)
+    c = oracle.make_config(grid.shape, grid.h, grid.bc, limiter=limiter)
+    check_dot(lambda X: oracle.rhs(c, X), lambda w: oracle.rhs_vjp(c, U, w), U, seed=1)
+
+
+def test_rhs_vjp_entries_rough_state():
+    """Cell-wise random state: shocks, every HLLC region and minmod branch."""
+    grid = wl.Grid((4, 5, 6), (1 / 6, 1 / 5, 1 / 4))
+    U = wl.random_state(grid.shape, seed=21, vmax=1.5)
+    c = oracle.make_config(grid.shape, grid.h)
+    check_entries(lambda X: oracle.rhs(c, X), lambda w: oracle.rhs_vjp(c, U, w), U, seed=2,
+                  count=40, eps=1e-7)
+
+
+def test_rhs_vjp_supersonic_regions():
+    """Uniform supersonic flow plus a small smooth perturbation: every face is
+    in the one-sided regions (S_L >= 0), which the dot test then covers."""
+    grid = wl.Grid((4, 4, 8), (1 / 8, 1 / 4, 1 / 4))
+    U = wl.random_state(grid.shape, seed=4, vmax=0.2)
+    U[4] += 0.5 * ((U[1] + 3.0 * U[0]) ** 2 - U[1] ** 2) / U[0]
+    U[1] += 3.0 * U[0]  # +3 in vx: Mach > 2
+    c = oracle.make_config(grid.shape, grid.h)
+    check_dot(lambda X: oracle.rhs(c, X), lambda w: oracle.rhs_vjp(c, U, w), U, seed=5)
+
+
+def test_rk2_vjp():
+    grid = wl.Grid((5, 6, 7), (1 / 7, 1 / 6, 1 / 5))
+    U = wl.random_state(grid.shape, seed=6, vmax=0.6)
+    c = oracle.make_config(grid.shape, grid.h)
+    dt = 0.5 * oracle.cfl_dt(c, U)
+    check_dot(lambda X: oracle.rk2(c, X, dt), lambda w: oracle.rk2_vjp(c, U, dt, w), U, seed=7)
+    check_entries(lambda X: oracle.rk2(c, X, dt), lambda w: oracle.rk2_vjp(c, U, dt, w), U, seed=8)
+
+
+@pytest.mark.parametrize("T0", [3.0, 0.02, 0.005])
+def test_cool_vjp(T0):
+    """Three regimes: stays above Tc, crosses Tc within dt, starts below Tc."""
+    grid = wl.cube(4)
+    rng = np.random.default_rng(9)
+    shape = grid.shape
+    rho = rng.uniform(0.5, 1.5, shape)
+    v = rng.uniform(-0.5, 0.5, (3,) + shape)
+    T = T0 * rng.uniform(0.9, 1.1, shape)
+    U = wl.conserved(rho, v[0], v[1], v[2], rho * T, 5 / 3)
+    c = oracle.make_config(shape, grid.h, flags=oracle.SRC_COOLING)
+    dt = {3.0: 0.2, 0.02: 0.05, 0.005: 0.01}[T0]
+    Tn = [oracle.cool_temperature(rho.flat[i], T.flat[i], dt, 5 / 3, 0.3, 1e-2, 1e-3, 1e-4)
+          for i in range(rho.size)]
+    assert min(Tn) > 2e-4  # away from the floor
+    check_dot(lambda X: oracle.cool(c, X, dt), lambda w: oracle.cool_vjp(c, U, dt, w), U, seed=10)
+    check_entries(lambda X: oracle.cool(c, X, dt), lambda w: oracle.cool_vjp(c, U, dt, w), U,
+                  seed=11)
+
+
+def test_kick_vjp():
+    grid = wl.cube(4)
+    U = wl.random_state(grid.shape, seed=12)
+    acc = np.random.default_rng(13).standard_normal((3,) + grid.shape)
+    c = oracle.make_config(grid.shape, grid.h)
+    check_dot(lambda X: oracle.kick(c, X, acc, 0.1), lambda w: oracle.kick_vjp(c, U, acc, 0.1, w)[0],
+              U, seed=14)
+    # derivative with respect to the acceleration
+    w = np.random.default_rng(15).standard_normal(U.shape)
+    _, accb = oracle.kick_vjp(c, U, acc, 0.1, w)
+    da = np.random.default_rng(16).standard_normal(acc.shape)
+    jv = fd_jvp(lambda A: oracle.kick(c, U, A, 0.1), acc, da, 1e-6)
+    assert float((w * jv).sum()) == pytest.approx(float((accb * da).sum()), rel=1e-8)
+
+
+def test_gravity_vjp():
+    n = 16
+    U = wl.grf_density_state(n, seed=2)
+    c = oracle.make_config((n, n, n), (1 / n,) * 3, flags=oracle.SRC_GRAVITY, grav_G=wl.JEANS_G,
+                           mg_tol=1e-13, mg_max_cycles=80)
+    dt = 1e-3
+    phi0 = np.zeros((n, n, n))
+
+    def fwd(X):
+        acc, _, _ = oracle.gravity_accel(c, X, phi0)
+        return oracle.kick(c, X, acc, dt)
+
+    check_dot(fwd, lambda w: oracle.gravity_vjp(c, U, dt, phi0, w), U, seed=17, rtol=1e-6)
+
+
+@pytest.mark.parametrize("flags", [0, oracle.SRC_FORCING | oracle.SRC_COOLING])
+def test_step_vjp_against_full_steps(flags):
+    grid = wl.cube(8)
+    U = wl.random_state(grid.shape, seed=18, vmax=0.5)
+    c = oracle.make_config(grid.shape, grid.h, flags=flags)
+    dt = 0.6 * oracle.cfl_dt(c, U)
+    nvec = oracle.ou_modes(1.0, 2.0) if flags & oracle.SRC_FORCING else np.zeros((0, 3), np.int32)
+    ahat = oracle.ou_init(c, nvec) if flags & oracle.SRC_FORCING else np.zeros(6)
+    phi = np.zeros(grid.shape)
+
+    def fwd(X):
+        sim = oracle.Simulation(c, X, nvec=nvec, ahat=ahat.copy(), phi=phi.copy())
+        sim.step_index = 4
+        return sim.advance(1, dt).U
+
+    check_dot(fwd, lambda w: oracle.step_vjp(c, U, dt, 4, nvec, ahat, phi, w), U, seed=19)
+
+
+def test_step_vjp_gravity():
+    n = 8
+    U = wl.grf_density_state(n, seed=3)
+    c = oracle.make_config((n, n, n), (1 / n,) * 3,
+                           flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING, grav_G=wl.JEANS_G,
+                           mg_tol=1e-13, mg_max_cycles=80)
+    dt = 0.5 * oracle.cfl_dt(c, U)
+    phi = np.zeros((n, n, n))
+
+    def fwd(X):
+        return oracle.Simulation(c, X, phi=phi.copy()).advance(1, dt).U
+
+    nv = np.zeros((0, 3), np.int32)
+    # perturb the density only: the state is at rest with uniform pressure, so
+    # velocity and pressure slopes sit exactly on the minmod kink at 0; density
+    # perturbations leave them there in both difference runs
+    check_dot(fwd, lambda w: oracle.step_vjp(c, U, dt, 0, nv, np.zeros(6), phi, w), U, seed=20,
+              rtol=1e-6, fields=[0])
