@@ -203,3 +203,17 @@ OU_DRIVE = dict(seed=0, tau=0.5, arms=1.0, zeta=1.0, kmin=1.0, kmax=2.0)
 JEANS_G = 9.0 * math.pi * (5.0 / 3.0)
 """G for a Jeans length of one third of the unit box at rho=1, p=1,
 gamma=5/3: lambda_J = c_s sqrt(pi/(G rho)) = 1/3  =>  G = 9 pi gamma p / rho^2."""
+
+
+def corrector_init_params(seed: int = 0, out_scale: float = 1e-3):
+    """Seeded initial parameters of the 5 -> 32 -> 32 -> 5 conv corrector in
+    its canonical flat order W1[32][5][27], b1[32], W2[32][32][27], b2[32],
+    W3[5][32][27], b3[5]: He-normal hidden layers, a last layer scaled by
+    out_scale (the corrector starts close to the identity map), zero biases."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal((32, 5, 27)) * math.sqrt(2.0 / (5 * 27))
+    w2 = rng.standard_normal((32, 32, 27)) * math.sqrt(2.0 / (32 * 27))
+    w3 = rng.standard_normal((5, 32, 27)) * out_scale * math.sqrt(1.0 / (32 * 27))
+    return np.concatenate([w1.ravel(), np.zeros(32), w2.ravel(), np.zeros(32), w3.ravel(),
+                           np.zeros(5)])
+
