@@ -166,6 +166,103 @@ mh_status mh_last_mg_cycles(mh_ctx *ctx, int32_t *cycles);
  * MH_DEVICE. */
 mh_status mh_get_potential(mh_ctx *ctx, void *phi, int where);
 
+/* Reverse-mode derivative of one step (paper Sec. 2.3; the adjoint of the
+ * Poisson solve is a second solve with the same symmetric operator,
+ * Sec. 6.2.4), with dt held fixed (the gradient stop of App. A.4):
+ *   lam_n = (dU^{n+1}/dU^n)^T lam_np1
+ * for the step taken from the state U_n with time step dt, at global step
+ * index `step` (it keys the OU noise).  At every non-smooth point the
+ * derivative of the branch the forward took is used: minmod the argument it
+ * returned (0 when it returned 0), the wave-speed min/max the selected
+ * argument (the first on ties), HLLC the side and fan the face fell in, the
+ * cooling branch and floor those taken.
+ * U_n, lam_np1, lam_n: device arrays [5][nz][ny][nx] of the context dtype;
+ *   lam_n may alias lam_np1.
+ * ou_ahat: host array of the OU amplitudes before the step (6 doubles per mode,
+ *   as from mh_get_ou_state); required when forcing is on, else ignored.
+ * phi_n: device array [nz][ny][nx], the potential before the step (the warm
+ *   start of the forward solve), or NULL for a zero start; used with gravity.
+ * adj_workspace: device memory of at least mh_query_adjoint_workspace bytes,
+ *   256-byte aligned, owned by the caller; it holds the recomputed forward
+ *   intermediates and the scratch of the reverse sweep.  The context's own
+ *   state, clock, OU amplitudes and potential are not touched.
+ * Enqueued on the context stream; with gravity it synchronises once per
+ * multigrid cycle.  Every grid, limiter and source the context accepts is
+ * supported.  Errors: MH_E_INVALID (null pointer, or ou_ahat missing with
+ * forcing on), MH_E_WORKSPACE, MH_E_DEVICE. */
+mh_status mh_query_adjoint_workspace(mh_ctx *ctx, size_t *bytes);
+mh_status mh_adjoint_step(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace_bytes,
+                          const void *U_n, double dt, int64_t step, const double *ou_ahat,
+                          const void *phi_n, const void *lam_np1, void *lam_n);
+
+/* ------------------------------------------------------------------------ */
+/* Learned state corrector (solver in the loop, paper Sec. 8)               */
+/* ------------------------------------------------------------------------ */
+/* A 3D convolutional network applied to a batch of coarse states after a
+ * step:  x = (U - mean)/std;  h1 = GELU(conv(x; W1) + b1) (5 -> 32);
+ * h2 = GELU(conv(h1; W2) + b2) (32 -> 32);  y = conv(h2; W3) + b3 (32 -> 5);
+ * U' = U + scale * y.  conv is a 3x3x3 cross-correlation with periodic
+ * padding (the paper pads its network periodically), GELU the erf form.
+ * Operands are bf16 with fp32 accumulation on the matrix cores; the fp32
+ * master parameters are trained with ADAM (Sec. 7) on the loss
+ * L = sum_c w_c mean((U'_c - T_c)^2) / std_c^2 (density weighted up).
+ * Parameters, flat fp32 in this order: W1[32][5][27], b1[32],
+ * W2[32][32][27], b2[32], W3[5][32][27], b3[5] (36 357 values); tap
+ * t = 9(dz+1) + 3(dy+1) + (dx+1) reads the input at (x+dx, y+dy, z+dz).
+ * States are device arrays [batch][5][n][n][n] of dtype MH_F32 or MH_F64.
+ * n must be a multiple of 16. */
+typedef struct mh_corr_desc {
+  int32_t n;          /* cells per axis of each (cubic, periodic) state */
+  int32_t batch;      /* states per call */
+  int32_t dtype;      /* MH_F32 or MH_F64 */
+  int32_t reserved0;
+  double gamma;       /* adiabatic index (for the positivity floor) */
+  double mean[5];     /* per-channel standardisation of the network input */
+  double std[5];
+  double scale[5];    /* per-channel scale of the network output */
+  double loss_w[5];   /* per-channel loss weights */
+  double floor_rel;   /* floor: rho >= floor_rel <rho>, P >= floor_rel <P> */
+  double fallback_frac; /* fall back to the uncorrected state above this
+                           fraction of floored cells */
+} mh_corr_desc;
+
+typedef struct mh_corr mh_corr;
+
+mh_status mh_corr_query_workspace(const mh_corr_desc *desc, size_t *bytes);
+/* Creates a corrector on the current device in caller-owned workspace (256-
+ * byte aligned), enqueuing on `stream`; parameters start at zero. */
+mh_status mh_corr_init(const mh_corr_desc *desc, void *workspace, size_t bytes, void *stream,
+                       mh_corr **out);
+/* Sets the fp32 parameters (host or device, MH_HOST synchronises) and clears
+ * the ADAM moments and iteration count. */
+mh_status mh_corr_set_params(mh_corr *c, const float *theta, int where);
+mh_status mh_corr_get_params(mh_corr *c, float *theta, int where);
+/* U_out = floor(U + scale * Net(U)); when any value is non-finite or more
+ * than fallback_frac of the cells needed the floor, U_out = U instead
+ * (the plain coarse state).  U_out must not alias U.  floored / fell_back
+ * are optional host outputs; synchronises. */
+mh_status mh_corr_apply(mh_corr *c, const void *U, void *U_out, int64_t *floored,
+                        int32_t *fell_back);
+/* Loss against the target batch and its gradient in the parameters (to host
+ * or device memory); synchronises. */
+mh_status mh_corr_loss_grad(mh_corr *c, const void *U, const void *target, double *loss,
+                            float *grad, int where);
+/* One ADAM iteration (learning rate lr) on the loss against target; returns
+ * the loss before the update when loss is non-null (then synchronises). */
+mh_status mh_corr_train_step(mh_corr *c, const void *U, const void *target, float lr,
+                             double *loss);
+/* Copies an activation of the last forward pass: 0 x (bf16, [cells][32]),
+ * 1 z1 (fp32, [cells][32]), 2 h1 (bf16), 3 z2 (fp32), 4 h2 (bf16),
+ * 5 y (fp32, [cells][16]); cells = batch n^3.  MH_HOST synchronises. */
+mh_status mh_corr_get_activation(mh_corr *c, int which, void *dst, int where);
+void mh_corr_destroy(mh_corr *c);
+
+/* Conservative r^3 block average of a fine state [5][nf^3] onto
+ * [5][(nf/r)^3] (targets of the corrector from a fine run); device arrays of
+ * dtype, enqueued on `stream`. */
+mh_status mh_block_average(const void *fine, int32_t nf, int32_t r, void *coarse, int32_t dtype,
+                           void *stream);
+
 /* Kernel timing with HIP events.  While enabled, mh_step records an event pair
  * on the context stream around every kernel launch it makes, by kind:
  *   MH_TIME_STAGE1, MH_TIME_STAGE2 (the fused stage kernels),
@@ -180,6 +277,11 @@ enum { MH_TIME_STAGE1 = 0, MH_TIME_STAGE2 = 1, MH_TIME_PROLOGUE = 2, MH_TIME_OTH
        MH_TIME_KINDS = 4 };
 mh_status mh_set_timing(mh_ctx *ctx, int enable);
 mh_status mh_get_timing(mh_ctx *ctx, double *ms, int64_t *launches);
+
+/* Sets the gravitational potential [nz][ny][nx] (dtype of the context) that
+ * the next step's multigrid solve starts from (resume from a checkpoint);
+ * where = MH_HOST (synchronises) or MH_DEVICE.  MH_E_INVALID without gravity. */
+mh_status mh_set_potential(mh_ctx *ctx, const void *phi, int where);
 
 /* Message of the last failed call on ctx (empty string if none). */
 const char *mh_last_error(const mh_ctx *ctx);

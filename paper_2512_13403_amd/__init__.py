@@ -31,7 +31,11 @@ HOST, DEVICE = 0, 1
 EXPORTED = [
     "mh_query_workspace", "mh_init", "mh_set_state", "mh_get_state", "mh_step", "mh_get_clock",
     "mh_set_clock", "mh_get_ou_state", "mh_set_ou_state", "mh_check", "mh_last_mg_cycles",
-    "mh_get_potential", "mh_set_timing", "mh_get_timing", "mh_last_error", "mh_destroy",
+    "mh_get_potential", "mh_set_potential", "mh_set_timing", "mh_get_timing",
+    "mh_query_adjoint_workspace", "mh_adjoint_step", "mh_last_error", "mh_destroy",
+    "mh_corr_query_workspace", "mh_corr_init", "mh_corr_set_params", "mh_corr_get_params",
+    "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
+    "mh_corr_destroy", "mh_block_average",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -55,6 +59,16 @@ class PhysicsDesc(ctypes.Structure):
         ("mg_max_cycles", ctypes.c_int32), ("mg_coarsest", ctypes.c_int32),
         ("mg_tol", ctypes.c_double), ("mg_coarse_sweeps", ctypes.c_int32),
         ("reserved0", ctypes.c_int32),
+    ]
+
+
+class CorrDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("batch", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32), ("gamma", ctypes.c_double),
+        ("mean", ctypes.c_double * 5), ("std", ctypes.c_double * 5),
+        ("scale", ctypes.c_double * 5), ("loss_w", ctypes.c_double * 5),
+        ("floor_rel", ctypes.c_double), ("fallback_frac", ctypes.c_double),
     ]
 
 
@@ -95,6 +109,20 @@ def load_library():
             "mh_get_potential": [vp, vp, ctypes.c_int],
             "mh_set_timing": [vp, ctypes.c_int],
             "mh_get_timing": [vp, dp, i64p],
+            "mh_set_potential": [vp, vp, ctypes.c_int],
+            "mh_query_adjoint_workspace": [vp, ctypes.POINTER(ctypes.c_size_t)],
+            "mh_adjoint_step": [vp, vp, ctypes.c_size_t, vp, ctypes.c_double, ctypes.c_int64, dp,
+                                vp, vp, vp],
+            "mh_corr_query_workspace": [ctypes.POINTER(CorrDesc), ctypes.POINTER(ctypes.c_size_t)],
+            "mh_corr_init": [ctypes.POINTER(CorrDesc), vp, ctypes.c_size_t, vp,
+                             ctypes.POINTER(vp)],
+            "mh_corr_set_params": [vp, vp, ctypes.c_int],
+            "mh_corr_get_params": [vp, vp, ctypes.c_int],
+            "mh_corr_apply": [vp, vp, vp, i64p, ctypes.POINTER(ctypes.c_int32)],
+            "mh_corr_loss_grad": [vp, vp, vp, dp, vp, ctypes.c_int],
+            "mh_corr_train_step": [vp, vp, vp, ctypes.c_float, dp],
+            "mh_corr_get_activation": [vp, ctypes.c_int, vp, ctypes.c_int],
+            "mh_block_average": [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -104,6 +132,8 @@ def load_library():
         L.mh_last_error.restype = ctypes.c_char_p
         L.mh_destroy.argtypes = [vp]
         L.mh_destroy.restype = None
+        L.mh_corr_destroy.argtypes = [vp]
+        L.mh_corr_destroy.restype = None
         _lib = L
     return _lib
 
@@ -292,8 +322,211 @@ class Solver:
                     "mh_get_timing")
         return ms, n
 
+    def set_potential(self, phi):
+        """Multigrid warm start for the next step (torch CUDA tensor or host array)."""
+        torch = self._torch
+        if isinstance(phi, torch.Tensor) and phi.is_cuda:
+            t = phi.to(self.torch_dtype).contiguous()
+            self._keep_phi = t
+            self._check(self.lib.mh_set_potential(self.ctx, ctypes.c_void_p(t.data_ptr()), DEVICE),
+                        "mh_set_potential")
+        else:
+            a = np.ascontiguousarray(np.asarray(phi), dtype=self.np_dtype)
+            self._check(self.lib.mh_set_potential(self.ctx, a.ctypes.data_as(ctypes.c_void_p), HOST),
+                        "mh_set_potential")
+
+    def potential_device(self):
+        out = self._torch.empty(self.shape, dtype=self.torch_dtype, device=self.device)
+        self._check(self.lib.mh_get_potential(self.ctx, ctypes.c_void_p(out.data_ptr()), DEVICE),
+                    "mh_get_potential")
+        return out
+
+    def adjoint_step(self, U_n, dt: float, step: int, lam, ou_ahat=None, phi_n=None, out=None):
+        """lam_n = (dU^{n+1}/dU^n)^T lam for the step from U_n (CUDA tensors of
+        the solver's shape and dtype) with fixed dt at global index `step`;
+        ou_ahat: OU amplitudes before the step (host), phi_n: potential before
+        the step (CUDA tensor) or None.  Returns lam_n (a new tensor unless
+        `out` is given; `out` may be `lam`)."""
+        torch = self._torch
+        if getattr(self, "_adj_ws", None) is None:
+            n = ctypes.c_size_t(0)
+            self._check(self.lib.mh_query_adjoint_workspace(self.ctx, ctypes.byref(n)),
+                        "mh_query_adjoint_workspace")
+            self._adj_bytes = n.value
+            self._adj_ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = (self._adj_ws.data_ptr() + 255) // 256 * 256
+        U_n = U_n.contiguous()
+        lam = lam.contiguous()
+        if out is None:
+            out = torch.empty_like(lam)
+        ah = None
+        if ou_ahat is not None:
+            # kept alive on self until the next call: the copy is enqueued
+            self._keep_ahat = np.ascontiguousarray(ou_ahat, dtype=np.float64)
+            ah = self._keep_ahat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._keep_adj = (U_n, lam, phi_n)
+        ph = ctypes.c_void_p(phi_n.contiguous().data_ptr()) if phi_n is not None else None
+        st = self.lib.mh_adjoint_step(self.ctx, ctypes.c_void_p(base), self._adj_bytes,
+                                      ctypes.c_void_p(U_n.data_ptr()), dt, step, ah, ph,
+                                      ctypes.c_void_p(lam.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()))
+        self._check(st, "mh_adjoint_step")
+        return out
+
     def potential(self) -> np.ndarray:
         out = np.empty(self.shape, dtype=self.np_dtype)
         self._check(self.lib.mh_get_potential(self.ctx, out.ctypes.data_as(ctypes.c_void_p), HOST),
                     "mh_get_potential")
         return out
+
+
+# ---------------------------------------------------------------- corrector
+
+NPARAM_CORRECTOR = 36357
+
+
+def corr_desc(n: int, batch: int, dtype="f32", gamma=5.0 / 3.0, mean=(0.0,) * 5, std=(1.0,) * 5,
+              scale=(1.0,) * 5, loss_w=(1.0,) * 5, floor_rel=1e-6,
+              fallback_frac=1e-3) -> CorrDesc:
+    d = CorrDesc()
+    d.n, d.batch = n, batch
+    d.dtype = F64 if dtype in ("f64", "float64", F64) else F32
+    d.gamma = gamma
+    d.mean[:], d.std[:], d.scale[:], d.loss_w[:] = list(mean), list(std), list(scale), list(loss_w)
+    d.floor_rel, d.fallback_frac = floor_rel, fallback_frac
+    return d
+
+
+class Corrector:
+    """The learned state corrector on one GPU (mh_corr_*): a torch workspace
+    tensor and an mh_corr handle; states are CUDA tensors [batch][5][n][n][n]."""
+
+    def __init__(self, desc: CorrDesc, device="cuda:0"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("mihydro needs a GPU (no CPU fallback)")
+        self._torch = torch
+        self.lib = load_library()
+        self.desc = desc
+        self.device = torch.device(device)
+        self.torch_dtype = torch.float64 if desc.dtype == F64 else torch.float32
+        self.cells = desc.batch * desc.n ** 3
+        n = ctypes.c_size_t(0)
+        st = self.lib.mh_corr_query_workspace(ctypes.byref(desc), ctypes.byref(n))
+        if st != OK:
+            raise MHError(st, "mh_corr_query_workspace rejected the descriptor")
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+            self.stream = torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            st = self.lib.mh_corr_init(ctypes.byref(desc), ctypes.c_void_p(aligned), n.value,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise MHError(st, "mh_corr_init failed")
+        self.h = h
+
+    def _check(self, st, what):
+        if st != OK:
+            raise MHError(st, what)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mh_corr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _state(self, U):
+        U = U.contiguous()
+        if U.dtype != self.torch_dtype or U.device != self.device or U.numel() != 5 * self.cells:
+            raise ValueError("state must be a contiguous CUDA tensor [batch][5][n][n][n] of the "
+                             "corrector's dtype")
+        return U
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(np.asarray(theta), dtype=np.float32)
+        if a.size != NPARAM_CORRECTOR:
+            raise ValueError(f"expected {NPARAM_CORRECTOR} parameters")
+        self._check(self.lib.mh_corr_set_params(self.h, a.ctypes.data_as(ctypes.c_void_p), HOST),
+                    "mh_corr_set_params")
+
+    def params(self) -> np.ndarray:
+        out = np.empty(NPARAM_CORRECTOR, dtype=np.float32)
+        self._check(self.lib.mh_corr_get_params(self.h, out.ctypes.data_as(ctypes.c_void_p), HOST),
+                    "mh_corr_get_params")
+        return out
+
+    def apply(self, U, out=None):
+        """Returns (U_corrected, floored_cells, fell_back)."""
+        U = self._state(U)
+        if out is None:
+            out = self._torch.empty_like(U)
+        fl = ctypes.c_int64(0)
+        fb = ctypes.c_int32(0)
+        self._check(self.lib.mh_corr_apply(self.h, ctypes.c_void_p(U.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), ctypes.byref(fl),
+                                           ctypes.byref(fb)), "mh_corr_apply")
+        return out, fl.value, bool(fb.value)
+
+    def loss_grad(self, U, target):
+        """Returns (loss, gradient as a float32 numpy array in canonical order)."""
+        U, target = self._state(U), self._state(target)
+        loss = ctypes.c_double(0.0)
+        g = np.empty(NPARAM_CORRECTOR, dtype=np.float32)
+        self._check(self.lib.mh_corr_loss_grad(self.h, ctypes.c_void_p(U.data_ptr()),
+                                               ctypes.c_void_p(target.data_ptr()),
+                                               ctypes.byref(loss),
+                                               g.ctypes.data_as(ctypes.c_void_p), HOST),
+                    "mh_corr_loss_grad")
+        return loss.value, g
+
+    def train_step(self, U, target, lr: float, want_loss: bool = True):
+        U, target = self._state(U), self._state(target)
+        self._keep = (U, target)
+        loss = ctypes.c_double(0.0)
+        self._check(self.lib.mh_corr_train_step(self.h, ctypes.c_void_p(U.data_ptr()),
+                                                ctypes.c_void_p(target.data_ptr()), lr,
+                                                ctypes.byref(loss) if want_loss else None),
+                    "mh_corr_train_step")
+        return loss.value if want_loss else None
+
+    def activation(self, which: int) -> np.ndarray:
+        """0 x, 1 z1, 2 h1, 3 z2, 4 h2, 5 y of the last forward pass, as float64
+        arrays [cells][channels] (bf16 ones widened exactly)."""
+        ch = 16 if which == 5 else 32
+        if which in (0, 2, 4):
+            raw = np.empty((self.cells, ch), dtype=np.uint16)
+        else:
+            raw = np.empty((self.cells, ch), dtype=np.float32)
+        self._check(self.lib.mh_corr_get_activation(self.h, which,
+                                                    raw.ctypes.data_as(ctypes.c_void_p), HOST),
+                    "mh_corr_get_activation")
+        if raw.dtype == np.uint16:
+            return (raw.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        return raw.astype(np.float64)
+
+
+def block_average(fine, r: int):
+    """Conservative r^3 block average of a fine CUDA state [5][nf][nf][nf]."""
+    import torch
+
+    lib = load_library()
+    fine = fine.contiguous()
+    nf = fine.shape[-1]
+    if fine.shape != (5, nf, nf, nf) or nf % r:
+        raise ValueError("fine state must be [5][nf][nf][nf] with nf divisible by r")
+    nc = nf // r
+    out = torch.empty((5, nc, nc, nc), dtype=fine.dtype, device=fine.device)
+    dt = F64 if fine.dtype == torch.float64 else F32
+    st = lib.mh_block_average(ctypes.c_void_p(fine.data_ptr()), nf, r,
+                              ctypes.c_void_p(out.data_ptr()), dt,
+                              ctypes.c_void_p(torch.cuda.current_stream(fine.device).cuda_stream))
+    if st != OK:
+        raise MHError(st, "mh_block_average")
+    return out

@@ -1,0 +1,634 @@
+// adjoint_kernels.hip -- reverse-mode derivative of the finite-volume step
+// (arXiv 2512.13403, Sec. 2.3 and 6.2.4) for gfx950.
+//
+// With dt held fixed, the derivative of one step U^n -> U^{n+1} is applied in
+// transposed form, lam^n = (dU^{n+1}/dU^n)^T lam^{n+1}, source by source in
+// reverse order and then through the two RK stages:
+//   lam1 = lam_a/2 + (dt/2) J(U1)^T lam_a,   lam^n = lam_a/2 + lam1 + dt J(U^n)^T lam1.
+// J(U)^T v for L(U) = -sum_a (F_{a,i+1/2} - F_{a,i-1/2}) / h_a runs in two
+// deterministic passes per axis (no floating-point atomics):
+//   k_face_vjp    one thread per face: Fb = (v_right - v_left)/h, the HLLC
+//                 reverse sweep gives the face-state adjoints W^L_b, W^R_b, and
+//                 the minmod selections of the two slopes the face used;
+//   k_cell_gather one thread per cell: sums, over the (at most four) faces
+//                 whose stencil reads the cell, the reverse of
+//                 W^L = W_i + minmod(..)/2, W^R = W_{i+1} - minmod(..)/2;
+// and k_jtv_finish applies (dW/dU)^T per cell.  At every kink the derivative
+// of the branch the forward took is used (minmod: the returned argument, or 0;
+// wave-speed min/max: the selected argument, the first on ties; HLLC: the
+// side and fan the face fell in).
+#include "mg.h"
+#include "mh_adjoint.h"
+#include "mh_device.h"
+
+namespace mh {
+
+namespace {
+
+__device__ __forceinline__ int minmod_sel(float a, float b) {
+  return (a * b <= 0.0f) ? 0 : (fabsf(a) <= fabsf(b) ? 1 : 2);
+}
+__device__ __forceinline__ int minmod_sel(double a, double b) {
+  return (a * b <= 0.0) ? 0 : (fabs(a) <= fabs(b) ? 1 : 2);
+}
+template <typename T>
+__device__ __forceinline__ T sel_value(int s, T a, T b) {
+  return s == 1 ? a : (s == 2 ? b : T(0));
+}
+
+template <typename T>
+__device__ __forceinline__ void prim_at(const T* __restrict__ U, long long N, long long q, T gm1,
+                                        T (&w)[5]) {
+  T u[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) u[f] = U[f * N + q];
+  const T ir = T(1) / u[0];
+  w[0] = u[0];
+  w[1] = u[1] * ir;
+  w[2] = u[2] * ir;
+  w[3] = u[3] * ir;
+  w[4] = gm1 * (u[4] - T(0.5) * u[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]));
+}
+
+// Reverse of the one-sided HLLC assembly of the stage kernel, for face states
+// wl, wr = (rho, v_n, v_t1, v_t2, P) in the face frame.  Fb = dL/dF; writes
+// dL/dwl and dL/dwr.
+template <typename T>
+__device__ void hllc_reverse(const T (&wl)[5], const T (&wr)[5], T g, const T (&Fb)[5],
+                             T (&wlb)[5], T (&wrb)[5]) {
+  const T gm1 = g - T(1);
+  const T rl = wl[0], ul = wl[1], al = wl[2], bl = wl[3], pl = wl[4];
+  const T rr = wr[0], ur = wr[1], ar = wr[2], br = wr[3], pr = wr[4];
+  const T cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+  const bool minL = (ul - cl) <= (ur - cr);
+  const bool maxL = (ul + cl) >= (ur + cr);
+  const T SL = minL ? ul - cl : ur - cr;
+  const T SR = maxL ? ul + cl : ur + cr;
+  const T El = pl / gm1 + T(0.5) * rl * (ul * ul + al * al + bl * bl);
+  const T Er = pr / gm1 + T(0.5) * rr * (ur * ur + ar * ar + br * br);
+  const T dl = rl * (SL - ul), dr = rr * (SR - ur);
+  const T num = pr - pl + ul * dl - ur * dr, den = dl - dr;
+  const T ss = num / den;
+  const bool left = (SL >= T(0)) || (ss >= T(0));
+  const bool fan = left ? (SL < T(0)) : (SR > T(0));
+  const T rK = left ? rl : rr, uK = left ? ul : ur, aK = left ? al : ar, bK = left ? bl : br;
+  const T pK = left ? pl : pr, EK = left ? El : Er, SK = left ? SL : SR, dK = left ? dl : dr;
+  const T mK = rK * uK;
+
+  T rKb = 0, uKb = 0, aKb = 0, bKb = 0, pKb = 0, EKb = 0, SKb = 0, dKb = 0, mKb = 0, ssb = 0;
+  if (fan) {
+    const T q = T(1) / (SK - ss);
+    const T qd = q * dK;
+    const T H = dK * ss + pK;
+    const T G4 = (SK - uK) * EK + (ss - uK) * H;
+    const T s[5] = {qd, qd * ss, qd * aK, qd * bK, q * G4};
+    const T UK[5] = {rK, mK, rK * aK, rK * bK, EK};
+    T sb[5], UKb[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      SKb += Fb[f] * (s[f] - UK[f]);
+      sb[f] = SK * Fb[f];
+      UKb[f] = -SK * Fb[f];
+    }
+    T qb = sb[4] * G4;
+    const T G4b = sb[4] * q;
+    SKb += G4b * EK;
+    uKb -= G4b * EK;
+    EKb += G4b * (SK - uK);
+    ssb += G4b * H;
+    uKb -= G4b * H;
+    const T Hb = G4b * (ss - uK);
+    dKb += Hb * ss;
+    ssb += Hb * dK;
+    pKb += Hb;
+    const T qdb = sb[0] + sb[1] * ss + sb[2] * aK + sb[3] * bK;
+    ssb += sb[1] * qd;
+    aKb += sb[2] * qd;
+    bKb += sb[3] * qd;
+    qb += qdb * dK;
+    dKb += qdb * q;
+    const T Zb = -qb * q * q;  // q = 1/Z, Z = SK - ss
+    SKb += Zb;
+    ssb -= Zb;
+    rKb += UKb[0] + UKb[2] * aK + UKb[3] * bK;
+    mKb += UKb[1];
+    aKb += UKb[2] * rK;
+    bKb += UKb[3] * rK;
+    EKb += UKb[4];
+  }
+  // F_K = (mK, mK uK + pK, mK aK, mK bK, uK (EK + pK))
+  mKb += Fb[0] + Fb[1] * uK + Fb[2] * aK + Fb[3] * bK;
+  uKb += Fb[1] * mK + Fb[4] * (EK + pK);
+  pKb += Fb[1] + Fb[4] * uK;
+  aKb += Fb[2] * mK;
+  bKb += Fb[3] * mK;
+  EKb += Fb[4] * uK;
+  rKb += mKb * uK;
+  uKb += mKb * rK;
+
+  T rlb = 0, ulb = 0, alb = 0, blb = 0, plb = 0, Elb = 0, SLb = 0, dlb = 0;
+  T rrb = 0, urb = 0, arb = 0, brb = 0, prb = 0, Erb = 0, SRb = 0, drb = 0;
+  if (left) {
+    rlb = rKb; ulb = uKb; alb = aKb; blb = bKb; plb = pKb; Elb = EKb; SLb = SKb; dlb = dKb;
+  } else {
+    rrb = rKb; urb = uKb; arb = aKb; brb = bKb; prb = pKb; Erb = EKb; SRb = SKb; drb = dKb;
+  }
+  const T numb = ssb / den, denb = -ssb * ss / den;
+  prb += numb;
+  plb -= numb;
+  ulb += numb * dl;
+  dlb += numb * ul;
+  urb -= numb * dr;
+  drb -= numb * ur;
+  dlb += denb;
+  drb -= denb;
+  rlb += dlb * (SL - ul);
+  SLb += dlb * rl;
+  ulb -= dlb * rl;
+  rrb += drb * (SR - ur);
+  SRb += drb * rr;
+  urb -= drb * rr;
+  plb += Elb / gm1;
+  rlb += Elb * T(0.5) * (ul * ul + al * al + bl * bl);
+  ulb += Elb * rl * ul;
+  alb += Elb * rl * al;
+  blb += Elb * rl * bl;
+  prb += Erb / gm1;
+  rrb += Erb * T(0.5) * (ur * ur + ar * ar + br * br);
+  urb += Erb * rr * ur;
+  arb += Erb * rr * ar;
+  brb += Erb * rr * br;
+  T clb = 0, crb = 0;
+  if (minL) { ulb += SLb; clb -= SLb; } else { urb += SLb; crb -= SLb; }
+  if (maxL) { ulb += SRb; clb += SRb; } else { urb += SRb; crb += SRb; }
+  plb += clb * g / (T(2) * cl * rl);
+  rlb -= clb * cl / (T(2) * rl);
+  prb += crb * g / (T(2) * cr * rr);
+  rrb -= crb * cr / (T(2) * rr);
+  wlb[0] = rlb; wlb[1] = ulb; wlb[2] = alb; wlb[3] = blb; wlb[4] = plb;
+  wrb[0] = rrb; wrb[1] = urb; wrb[2] = arb; wrb[3] = brb; wrb[4] = prb;
+}
+
+struct AxisGeom {
+  int n[3];   // cells along x, y, z
+  int bc;     // boundary kind of the axis
+  int nf;     // faces along the axis: n (periodic) or n + 1 (outflow)
+};
+
+// cell index of (along-axis coordinate c, the other two coordinates) and the
+// face record index of (face f along the axis, the other two coordinates)
+template <int AX>
+__device__ __forceinline__ long long cell_of(const AxisGeom& g, int c, int o1, int o2) {
+  if (AX == 0) return ((long long)o2 * g.n[1] + o1) * g.n[0] + c;
+  if (AX == 1) return ((long long)o2 * g.n[1] + c) * g.n[0] + o1;
+  return ((long long)c * g.n[1] + o2) * g.n[0] + o1;
+}
+template <int AX>
+__device__ __forceinline__ long long face_of(const AxisGeom& g, int f, int o1, int o2) {
+  if (AX == 0) return ((long long)o2 * g.n[1] + o1) * g.nf + f;
+  if (AX == 1) return ((long long)o2 * g.nf + f) * g.n[0] + o1;
+  return ((long long)f * g.n[1] + o2) * g.n[0] + o1;
+}
+// the two other coordinates of axis AX: AX=0 -> (y, z), AX=1 -> (x, z), AX=2 -> (x, y)
+template <int AX>
+__device__ __forceinline__ void other_dims(const AxisGeom& g, int& d1, int& d2) {
+  d1 = AX == 0 ? g.n[1] : g.n[0];
+  d2 = AX == 2 ? g.n[1] : g.n[2];
+}
+
+template <typename T, int LIM, int AX>
+__global__ __launch_bounds__(256) void k_face_vjp(const T* __restrict__ U, const T* __restrict__ v,
+                                                  AxisGeom g, T gamma, T ih, T* __restrict__ wbar,
+                                                  int* __restrict__ flags, long long nfaces) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nfaces) return;
+  int d1, d2;
+  other_dims<AX>(g, d1, d2);
+  const int f = (int)(t % g.nf);
+  const long long rest = t / g.nf;
+  const int o1 = (int)(rest % d1), o2 = (int)(rest / d1);
+  const int n = g.n[AX];
+  const int i = g.bc == BC_PERIODIC ? f : f - 1;  // left cell position of the face
+  const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+  const T gm1 = gamma - T(1);
+  constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
+  const int perm[5] = {0, vn, t1, t2, 4};
+  T w[4][5];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T wc[5];
+    prim_at(U, N, cell_of<AX>(g, bc_map(i - 1 + k, n, g.bc), o1, o2), gm1, wc);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) w[k][s] = wc[perm[s]];
+  }
+  T wl[5], wr[5];
+  int fl = 0;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const T a0 = w[2][s] - w[1][s], b0 = w[1][s] - w[0][s];
+    const T a1 = w[3][s] - w[2][s], b1 = w[2][s] - w[1][s];
+    const int s0 = LIM == LIM_NONE ? 0 : minmod_sel(a0, b0);
+    const int s1 = LIM == LIM_NONE ? 0 : minmod_sel(a1, b1);
+    wl[s] = w[1][s] + T(0.5) * sel_value(s0, a0, b0);
+    wr[s] = w[2][s] - T(0.5) * sel_value(s1, a1, b1);
+    fl |= (s0 << (2 * s)) | (s1 << (10 + 2 * s));
+  }
+  // Fb = (v of the face's right cell - v of its left cell) / h, real cells only
+  const bool has_right = g.bc == BC_PERIODIC || i + 1 <= n - 1;
+  const bool has_left = g.bc == BC_PERIODIC || i >= 0;
+  const long long qr = cell_of<AX>(g, bc_map(i + 1, n, g.bc), o1, o2);
+  const long long ql = cell_of<AX>(g, bc_map(i, n, g.bc), o1, o2);
+  T Fb[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const T vr = has_right ? v[perm[s] * N + qr] : T(0);
+    const T vl = has_left ? v[perm[s] * N + ql] : T(0);
+    Fb[s] = (vr - vl) * ih;
+  }
+  T wlb[5], wrb[5];
+  hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+  const long long rec = face_of<AX>(g, f, o1, o2);
+  const long long NF = (long long)g.nf * d1 * d2;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    wbar[s * NF + rec] = wlb[s];
+    wbar[(5 + s) * NF + rec] = wrb[s];
+  }
+  flags[rec] = fl;
+}
+
+// contribution of the face with left cell position i to the stencil slot k
+// (position i - 1 + k), field s (face frame), from the reverse of
+// W^L = W_i + minmod_i/2 and W^R = W_{i+1} - minmod_{i+1}/2
+template <typename T>
+__device__ __forceinline__ T slot_contrib(int k, int fl, int s, T WLb, T WRb) {
+  const int s0 = (fl >> (2 * s)) & 3, s1 = (fl >> (10 + 2 * s)) & 3;
+  const T a0 = s0 == 1 ? T(1) : T(0), b0 = s0 == 2 ? T(1) : T(0);
+  const T a1 = s1 == 1 ? T(1) : T(0), b1 = s1 == 2 ? T(1) : T(0);
+  switch (k) {
+    case 0: return -T(0.5) * b0 * WLb;
+    case 1: return WLb + T(0.5) * (b0 - a0) * WLb + T(0.5) * b1 * WRb;
+    case 2: return T(0.5) * a0 * WLb + WRb - T(0.5) * (b1 - a1) * WRb;
+    default: return -T(0.5) * a1 * WRb;
+  }
+}
+
+template <typename T, int AX>
+__global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
+                                                     const int* __restrict__ flags, AxisGeom g,
+                                                     T* __restrict__ Wacc) {
+  const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= N) return;
+  int d1, d2;
+  other_dims<AX>(g, d1, d2);
+  const int n = g.n[AX];
+  const int c = (int)(t % n);
+  const long long rest = t / n;
+  const int o1 = (int)(rest % d1), o2 = (int)(rest / d1);
+  const long long NF = (long long)g.nf * d1 * d2;
+  constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
+  const int perm[5] = {0, vn, t1, t2, 4};
+  T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
+  auto add_face = [&](int f, int i) {  // record f, left cell position i
+    const long long rec = face_of<AX>(g, f, o1, o2);
+    const int fl = flags[rec];
+    for (int k = 0; k < 4; ++k) {
+      if (bc_map(i - 1 + k, n, g.bc) != c) continue;
+#pragma unroll
+      for (int s = 0; s < 5; ++s)
+        acc[s] += slot_contrib<T>(k, fl, s, wbar[s * NF + rec], wbar[(5 + s) * NF + rec]);
+    }
+  };
+  if (g.bc == BC_PERIODIC) {
+    if (n < 4) {
+      for (int f = 0; f < n; ++f) add_face(f, f);
+    } else {
+      for (int i = c - 2; i <= c + 1; ++i) {
+        const int f = i < 0 ? i + n : (i >= n ? i - n : i);
+        add_face(f, f + (i - f));  // positions relative to c keep the slot unique
+      }
+    }
+  } else {
+    for (int i = max(-1, c - 2); i <= min(n - 1, c + 1); ++i) add_face(i + 1, i);
+  }
+  const long long q = cell_of<AX>(g, c, o1, o2);
+#pragma unroll
+  for (int s = 0; s < 5; ++s) Wacc[perm[s] * N + q] += acc[s];
+}
+
+// out = c0 x0 + c1 x1 + beta (dW/dU)^T Wacc, W = (rho, v, P) of U
+template <typename T>
+__global__ __launch_bounds__(256) void k_jtv_finish(const T* __restrict__ U,
+                                                    const T* __restrict__ Wacc, long long N, T gm1,
+                                                    T beta, T c0, const T* x0, T c1, const T* x1,
+                                                    T* out) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const T rho = U[q];
+  const T ir = T(1) / rho;
+  const T vx = U[N + q] * ir, vy = U[2 * N + q] * ir, vz = U[3 * N + q] * ir;
+  const T wr = Wacc[q], wx = Wacc[N + q], wy = Wacc[2 * N + q], wz = Wacc[3 * N + q],
+          wp = Wacc[4 * N + q];
+  T g[5];
+  g[0] = wr - (wx * vx + wy * vy + wz * vz) * ir + wp * gm1 * T(0.5) * (vx * vx + vy * vy + vz * vz);
+  g[1] = wx * ir - wp * gm1 * vx;
+  g[2] = wy * ir - wp * gm1 * vy;
+  g[3] = wz * ir - wp * gm1 * vz;
+  g[4] = wp * gm1;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    T o = beta * g[f];
+    if (x0) o += c0 * x0[f * N + q];
+    if (x1) o += c1 * x1[f * N + q];
+    out[f * N + q] = o;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* y, long long n, T v) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) y[q] = v;
+}
+
+// ---------------------------------------------------------------- sources
+
+// OU acceleration at (x, y, z) from the row records and X phase factors,
+// the same separable sum the stage kernel evaluates
+template <typename T>
+__device__ __forceinline__ void ou_accel(const T* __restrict__ rows, const T* __restrict__ tabx,
+                                         int R, int nx, int ny, int x, int y, int z, T (&a)[3]) {
+  const T* pq = rows + ((long long)z * ny + y) * 6 * (R + 1);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a[c] = pq[2 * c];
+  for (int n = 1; n <= R; ++n) {
+    const T xr = tabx[2 * ((long long)n * nx + x)], xi = tabx[2 * ((long long)n * nx + x) + 1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] += xr * pq[6 * n + 2 * c] - xi * pq[6 * n + 2 * c + 1];
+  }
+}
+
+// forward kick m += rho a dt, E += (m_old . a) dt with the OU acceleration
+template <typename T>
+__global__ __launch_bounds__(256) void k_force_kick(T* U, const T* __restrict__ rows,
+                                                    const T* __restrict__ tabx, int R, int nx,
+                                                    int ny, int nz, T dt) {
+  const long long N = (long long)nx * ny * nz;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((long long)nx * ny));
+  T a[3];
+  ou_accel(rows, tabx, R, nx, ny, x, y, z, a);
+  const T rho = U[q];
+  const T dE = U[N + q] * a[0] + U[2 * N + q] * a[1] + U[3 * N + q] * a[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) U[(1 + c) * N + q] += rho * a[c] * dt;
+  U[4 * N + q] += dE * dt;
+}
+
+// reverse of the kick: lam_rho += sum_c lam_m_c a_c dt, lam_m_c += lam_E a_c dt
+template <typename T>
+__global__ __launch_bounds__(256) void k_force_kick_vjp(const T* __restrict__ rows,
+                                                        const T* __restrict__ tabx, int R, int nx,
+                                                        int ny, int nz, T dt,
+                                                        const T* __restrict__ lin, T* lout) {
+  const long long N = (long long)nx * ny * nz;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((long long)nx * ny));
+  T a[3];
+  ou_accel(rows, tabx, R, nx, ny, x, y, z, a);
+  const T Eb = lin[4 * N + q];
+  T rb = lin[q];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T mb = lin[(1 + c) * N + q];
+    rb += mb * a[c] * dt;
+    lout[(1 + c) * N + q] = mb + Eb * a[c] * dt;
+  }
+  lout[q] = rb;
+  lout[4 * N + q] = Eb;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// reverse of the gravity kick at U (before the kick) with g = -grad phi:
+// lam as for any kick, and accb_c = lam_m_c rho dt + lam_E m_c dt
+template <typename T>
+__global__ __launch_bounds__(256) void k_grav_kick_vjp(const T* __restrict__ U,
+                                                       const T* __restrict__ phi, int n, T i2h,
+                                                       T dt, const T* __restrict__ lin, T* lout,
+                                                       T* __restrict__ accb) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
+  const long long n2 = (long long)n * n;
+  const long long row = (long long)k * n2 + (long long)j * n;
+  T a[3];
+  a[0] = -(phi[row + wrapi(i + 1, n)] - phi[row + wrapi(i - 1, n)]) * i2h;
+  a[1] = -(phi[(long long)k * n2 + (long long)wrapi(j + 1, n) * n + i] -
+           phi[(long long)k * n2 + (long long)wrapi(j - 1, n) * n + i]) * i2h;
+  a[2] = -(phi[(long long)wrapi(k + 1, n) * n2 + (long long)j * n + i] -
+           phi[(long long)wrapi(k - 1, n) * n2 + (long long)j * n + i]) * i2h;
+  const T rho = U[q], Eb = lin[4 * N + q];
+  T rb = lin[q];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T mb = lin[(1 + c) * N + q];
+    rb += mb * a[c] * dt;
+    lout[(1 + c) * N + q] = mb + Eb * a[c] * dt;
+    accb[c * N + q] = mb * rho * dt + Eb * U[(1 + c) * N + q] * dt;
+  }
+  lout[q] = rb;
+  lout[4 * N + q] = Eb;
+}
+
+// reverse of g_c,i = -(phi_{i+1} - phi_{i-1}) / (2h): phib_j = sum_c (accb_c,j+1 - accb_c,j-1) / (2h)
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_adjoint(const T* __restrict__ accb, int n, T i2h,
+                                                      T* __restrict__ phib) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
+  const long long n2 = (long long)n * n;
+  const long long row = (long long)k * n2 + (long long)j * n;
+  phib[q] = ((accb[row + wrapi(i + 1, n)] - accb[row + wrapi(i - 1, n)]) +
+             (accb[N + (long long)k * n2 + (long long)wrapi(j + 1, n) * n + i] -
+              accb[N + (long long)k * n2 + (long long)wrapi(j - 1, n) * n + i]) +
+             (accb[2 * N + (long long)wrapi(k + 1, n) * n2 + (long long)j * n + i] -
+              accb[2 * N + (long long)wrapi(k - 1, n) * n2 + (long long)j * n + i])) * i2h;
+}
+
+// lam_rho += s x
+template <typename T>
+__global__ __launch_bounds__(256) void k_axpy(T* y, const T* __restrict__ x, long long n, T s) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) y[q] += s * x[q];
+}
+
+// reverse of exact cooling E' = ek + rho Tn(rho, T)/(g-1), T = (g-1)(E - ek)/rho,
+// ek = |m|^2/(2 rho), using the partial derivatives of the branch taken
+template <typename T>
+__global__ __launch_bounds__(256) void k_cool_vjp(const T* __restrict__ U, long long N, T gm1, T dt,
+                                                  CoolParams<T> c, const T* __restrict__ lin,
+                                                  T* lout) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const T rho = U[q], mx = U[N + q], my = U[2 * N + q], mz = U[3 * N + q], E = U[4 * N + q];
+  const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / rho;
+  const T Tin = gm1 * (E - ek) / rho;
+  // the forward map (same branch decisions as the forward kernel) and its partials
+  const T k2 = c.k2r * rho;
+  T Tn, dT, dr;
+  if (Tin >= c.tc) {
+    const T k1 = c.k1r * rho;
+    const T st = sqrt(Tin);
+    const T t1 = (st - c.sqrt_tc) / k1;
+    if (dt <= t1) {
+      const T s = st - k1 * dt;
+      Tn = s * s;
+      dT = s / st;
+      dr = -T(2) * s * c.k1r * dt;
+    } else {
+      const T w = T(1) + k2 * (dt - t1);
+      Tn = c.tc - c.ts * log(w);
+      dT = c.ts * k2 / (w * T(2) * st * k1);
+      dr = -c.ts / w * (c.k2r * (dt - t1) + k2 * t1 / rho);
+    }
+  } else {
+    const T e = exp((c.tc - Tin) * c.its);
+    const T w = e + k2 * dt;
+    Tn = c.tc - c.ts * log(w);
+    dT = e / w;
+    dr = -c.ts / w * c.k2r * dt;
+  }
+  if (Tn < c.tfloor) {
+    Tn = c.tfloor;
+    dT = T(0);
+    dr = T(0);
+  }
+  const T Eb = lin[4 * N + q];
+  T ekb = Eb;
+  T rhob = lin[q] + Eb * Tn / gm1;
+  const T Tnb = Eb * rho / gm1;
+  const T Tb = Tnb * dT;
+  rhob += Tnb * dr;
+  const T Einb = Tb * gm1 / rho;
+  ekb -= Tb * gm1 / rho;
+  rhob -= Tb * Tin / rho;
+  rhob -= ekb * ek / rho;
+  lout[q] = rhob;
+  lout[N + q] = lin[N + q] + ekb * mx / rho;
+  lout[2 * N + q] = lin[2 * N + q] + ekb * my / rho;
+  lout[3 * N + q] = lin[3 * N + q] + ekb * mz / rho;
+  lout[4 * N + q] = Einb;
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// J(U)^T v into out = c0 x0 + c1 x1 + beta J^T v (x0, x1 may be NULL)
+template <typename T>
+hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, T gamma,
+                   const double* h, const T* U, const T* v, T beta, T c0, const T* x0, T c1,
+                   const T* x1, T* out, hipStream_t s) {
+  const long long N = (long long)geom.nx * geom.ny * geom.nz;
+  hipLaunchKernelGGL((k_fill<T>), dim3(nblk(5 * N)), dim3(256), 0, s, B.Wacc, 5 * N, T(0));
+  const int nn[3] = {geom.nx, geom.ny, geom.nz};
+  for (int ax = 0; ax < 3; ++ax) {
+    AxisGeom ag{{geom.nx, geom.ny, geom.nz}, geom.bc[ax], 0};
+    ag.nf = geom.bc[ax] == BC_PERIODIC ? nn[ax] : nn[ax] + 1;
+    if (geom.bc[ax] == BC_PERIODIC && nn[ax] == 1) continue;  // the axis' fluxes cancel exactly
+    const long long nfaces = (long long)ag.nf * (N / nn[ax]);
+    const T ih = (T)(1.0 / h[ax]);
+#define MH_FACE(AX)                                                                          \
+  do {                                                                                       \
+    if (limiter == LIM_NONE)                                                                 \
+      hipLaunchKernelGGL((k_face_vjp<T, LIM_NONE, AX>), dim3(nblk(nfaces)), dim3(256), 0, s, \
+                         U, v, ag, gamma, ih, B.wbar, B.flags, nfaces);                      \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_face_vjp<T, LIM_MINMOD, AX>), dim3(nblk(nfaces)), dim3(256), 0,  \
+                         s, U, v, ag, gamma, ih, B.wbar, B.flags, nfaces);                   \
+    hipLaunchKernelGGL((k_cell_gather<T, AX>), dim3(nblk(N)), dim3(256), 0, s, B.wbar,       \
+                       B.flags, ag, B.Wacc);                                                 \
+  } while (0)
+    if (ax == 0) MH_FACE(0);
+    else if (ax == 1) MH_FACE(1);
+    else MH_FACE(2);
+#undef MH_FACE
+  }
+  hipLaunchKernelGGL((k_jtv_finish<T>), dim3(nblk(N)), dim3(256), 0, s, U, B.Wacc, N,
+                     gamma - T(1), beta, c0, x0, c1, x1, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t adj_force_kick(T* U, const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
+                          hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL((k_force_kick<T>), dim3(nblk(N)), dim3(256), 0, s, U, rows, tabx, R, g.nx,
+                     g.ny, g.nz, dt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t adj_force_kick_vjp(const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
+                              const T* lin, T* lout, hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL((k_force_kick_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, rows, tabx, R, g.nx,
+                     g.ny, g.nz, dt, lin, lout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t adj_cool_vjp(const T* U, long long N, T gm1, T dt, const CoolParams<T>& c, const T* lin,
+                        T* lout, hipStream_t s) {
+  hipLaunchKernelGGL((k_cool_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, U, N, gm1, dt, c, lin, lout);
+  return hipGetLastError();
+}
+
+// reverse of the gravity step at Ub (the state the kick acted on), with the
+// potential phi solved from Ub: lout from lin, using a second multigrid solve
+// with the same operator for the adjoint of A^+ (Sec. 6.2.4)
+template <typename T>
+hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws,
+                           const mh_physics_desc& p, const T* Ub, const T* phi, int n, double h,
+                           T dt, const T* lin, T* lout, DevClock* clk, hipStream_t s) {
+  const long long N = (long long)n * n * n;
+  const T i2h = (T)(1.0 / (2.0 * h));
+  hipLaunchKernelGGL((k_grav_kick_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, Ub, phi, n, i2h, dt,
+                     lin, lout, B.accb);
+  hipLaunchKernelGGL((k_grad_adjoint<T>), dim3(nblk(N)), dim3(256), 0, s, B.accb, n, i2h, B.phib);
+  hipError_t e = mg_set_rhs<T>(mgws, mgL, B.phib, 1.0, clk, s);
+  if (e != hipSuccess) return e;
+  e = mg_set_guess<T>(mgws, mgL, (const T*)nullptr, s);
+  if (e != hipSuccess) return e;
+  e = mg_solve<T>(mgws, mgL, p, clk, nullptr, s);
+  if (e != hipSuccess) return e;
+  const T* x = reinterpret_cast<const T*>(mgws + mg_phi_offset(mgL));
+  hipLaunchKernelGGL((k_axpy<T>), dim3(nblk(N)), dim3(256), 0, s, lout, x, N,
+                     (T)(4.0 * M_PI * p.grav_G));
+  return hipGetLastError();
+}
+
+#define ADJ_INSTANTIATE(T)                                                                       \
+  template hipError_t adj_jtv<T>(const AdjointBuffers<T>&, const StageGeom&, int, T,             \
+                                 const double*, const T*, const T*, T, T, const T*, T, const T*, \
+                                 T*, hipStream_t);                                               \
+  template hipError_t adj_force_kick<T>(T*, const T*, const T*, int, const StageGeom&, T,        \
+                                        hipStream_t);                                            \
+  template hipError_t adj_force_kick_vjp<T>(const T*, const T*, int, const StageGeom&, T,        \
+                                            const T*, T*, hipStream_t);                          \
+  template hipError_t adj_cool_vjp<T>(const T*, long long, T, T, const CoolParams<T>&, const T*, \
+                                      T*, hipStream_t);                                          \
+  template hipError_t adj_gravity_vjp<T>(const AdjointBuffers<T>&, MGLayout&, char*,             \
+                                         const mh_physics_desc&, const T*, const T*, int, double, \
+                                         T, const T*, T*, DevClock*, hipStream_t);
+ADJ_INSTANTIATE(float)
+ADJ_INSTANTIATE(double)
+#undef ADJ_INSTANTIATE
+
+}  // namespace mh

@@ -11,6 +11,7 @@
 
 #include "../../include/mihydro.h"
 #include "mg.h"
+#include "mh_adjoint.h"
 #include "mh_device.h"
 #include "mh_launch.h"
 
@@ -324,6 +325,30 @@ static CoolParams<T> cool_params(const mh_grid_desc& g, const mh_physics_desc& p
   return c;
 }
 
+// stage-kernel arguments shared by mh_step and mh_adjoint_step (everything
+// but the state pointers)
+template <typename T>
+static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) {
+  const mh_grid_desc& g = c->g;
+  const mh_physics_desc& p = c->p;
+  StageArgs<T> a{};
+  a.clk = clk;
+  a.gamma = (T)g.gamma;
+  a.gm1 = (T)(g.gamma - 1.0);
+  a.gm1inv = (T)(1.0 / (g.gamma - 1.0));
+  a.ihx = (T)(1.0 / g.h[0]);
+  a.ihy = (T)(1.0 / g.h[1]);
+  a.ihz = (T)(1.0 / g.h[2]);
+  a.cool = cool_params<T>(g, p);
+  if (p.flags & MH_SRC_FORCING) {
+    a.ou_rows = ou_rows;
+    for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
+    a.ou_modes = c->nmodes;
+    a.ou_R = (int)std::floor(p.ou_kmax);
+  }
+  return a;
+}
+
 template <typename T>
 static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, double* dt_out) {
   const mh_grid_desc& g = c->g;
@@ -336,22 +361,7 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
   T* U = c->at<T>(c->L.U);
   T* U1 = c->at<T>(c->L.U1);
   DevClock* clk = c->clk();
-
-  StageArgs<T> a{};
-  a.clk = clk;
-  a.gamma = (T)g.gamma;
-  a.gm1 = (T)(g.gamma - 1.0);
-  a.gm1inv = (T)(1.0 / (g.gamma - 1.0));
-  a.ihx = (T)ih[0];
-  a.ihy = (T)ih[1];
-  a.ihz = (T)ih[2];
-  a.cool = cool_params<T>(g, p);
-  if (force) {
-    a.ou_rows = c->at<T>(c->L.ou_rows);
-    for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
-    a.ou_modes = c->nmodes;
-    a.ou_R = (int)std::floor(p.ou_kmax);
-  }
+  StageArgs<T> a = base_stage_args<T>(c, clk, c->at<T>(c->L.ou_rows));
 
   PrologueArgs pa{};
   pa.clk = clk;
@@ -504,6 +514,183 @@ extern "C" mh_status mh_get_potential(mh_ctx* c, void* phi, int where) {
   return MH_OK;
 }
 
+// ------------------------------------------------------------------ adjoint
+
+namespace {
+
+struct AdjLayout {
+  size_t clk = 0, dtlog = 0, U1 = 0, Ua = 0, Ub = 0, Uc = 0, lamA = 0, lamB = 0, lam1 = 0;
+  size_t Wacc = 0, wbar = 0, flags = 0, accb = 0, phib = 0, ahat = 0, coef = 0, rows = 0;
+  MGLayout mg;
+  size_t total = 0;
+};
+
+AdjLayout make_adj_layout(const mh_grid_desc& g, const mh_physics_desc& p) {
+  AdjLayout A;
+  const size_t es = g.dtype == MH_F64 ? 8 : 4;
+  const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+  size_t faces = 0;
+  for (int a = 0; a < 3; ++a) {
+    const size_t nf = g.bc[a] == MH_BC_PERIODIC ? g.n[a] : g.n[a] + 1;
+    const size_t f = nf * (N / g.n[a]);
+    if (f > faces) faces = f;
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  A.clk = take(sizeof(DevClock));
+  A.dtlog = take(sizeof(double));
+  A.U1 = take(5 * N * es);
+  A.Ua = take(5 * N * es);
+  A.Ub = take(5 * N * es);
+  A.Uc = take(5 * N * es);
+  A.lamA = take(5 * N * es);
+  A.lamB = take(5 * N * es);
+  A.lam1 = take(5 * N * es);
+  A.Wacc = take(5 * N * es);
+  A.wbar = take(10 * faces * es);
+  A.flags = take(faces * sizeof(int));
+  if (p.flags & MH_SRC_FORCING) {
+    const int R = (int)std::floor(p.ou_kmax);
+    A.ahat = take(6 * MAX_MODES * sizeof(double));
+    A.coef = take(6 * MAX_MODES * es);
+    A.rows = take((size_t)g.n[1] * g.n[2] * (R + 1) * 6 * es);
+  }
+  if (p.flags & MH_SRC_GRAVITY) {
+    A.accb = take(3 * N * es);
+    A.phib = take(N * es);
+    off = mg_layout(&g, &p, off, es, A.mg);
+  }
+  A.total = off;
+  return A;
+}
+
+}  // namespace
+
+extern "C" mh_status mh_query_adjoint_workspace(mh_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return MH_E_INVALID;
+  *bytes = make_adj_layout(c->g, c->p).total;
+  return MH_OK;
+}
+
+template <typename T>
+static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, double dt,
+                              int64_t step, const double* ou_ahat, const T* phi_n,
+                              const T* lam_np1, T* lam_n) {
+  const mh_grid_desc& g = c->g;
+  const mh_physics_desc& p = c->p;
+  const bool force = (p.flags & MH_SRC_FORCING) != 0;
+  const bool grav = (p.flags & MH_SRC_GRAVITY) != 0;
+  const bool cool = (p.flags & MH_SRC_COOLING) != 0;
+  const long long N = c->cells();
+  const size_t sbytes = 5 * (size_t)N * sizeof(T);
+  StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
+  auto at = [&](size_t off) { return reinterpret_cast<T*>(ws + off); };
+  DevClock* aclk = reinterpret_cast<DevClock*>(ws + A.clk);
+  T *U1 = at(A.U1), *Ua = at(A.Ua), *Ub = at(A.Ub), *Uc = at(A.Uc);
+  T *lamA = at(A.lamA), *lamB = at(A.lamB), *lam1 = at(A.lam1);
+  AdjointBuffers<T> B{at(A.Wacc), at(A.wbar), reinterpret_cast<int*>(ws + A.flags),
+                      grav ? at(A.accb) : nullptr, grav ? at(A.phib) : nullptr};
+
+  // private clock at the step being differentiated; the OU amplitudes of the
+  // step start from the caller's copy
+  DevClock hc{};
+  hc.step = step;
+  hc.bad_first = ~0ull;
+  MH_HIP(c, hipMemcpyAsync(aclk, &hc, sizeof hc, hipMemcpyHostToDevice, c->stream));
+  PrologueArgs pa{};
+  pa.clk = aclk;
+  pa.dt_log = reinterpret_cast<double*>(ws + A.dtlog);
+  pa.f64 = g.dtype == MH_F64;
+  pa.dt_fixed = dt;
+  pa.cfl = g.cfl;
+  pa.t_stop = INFINITY;
+  pa.forcing = force;
+  if (force) {
+    MH_HIP(c, hipMemcpyAsync(ws + A.ahat, ou_ahat, 6 * c->nmodes * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    pa.ou = ou_args(c);
+    pa.ou.clk = aclk;
+    pa.ou.ahat = reinterpret_cast<double*>(ws + A.ahat);
+    pa.ou.coef = ws + A.coef;
+  }
+  MH_HIP(c, launch_prologue(pa, c->stream));
+  StageArgs<T> a = base_stage_args<T>(c, aclk, force ? at(A.rows) : nullptr);
+  if (force)
+    MH_HIP(c, launch_force_rows<T>(at(A.coef), c->at<int>(c->L.ou_n), c->nmodes, a.ou_tab[1],
+                                   a.ou_tab[2], g.n[1], g.n[2], a.ou_R, at(A.rows), c->stream));
+
+  // forward recomputation: U1, Ua (RK2), Ub (forcing), Uc (gravity)
+  a.uin = Un;
+  a.un = nullptr;
+  a.uout = U1;
+  MH_HIP(c, launch_stage<T>(1, g.limiter, false, false, a, geom, c->stream));
+  a.uin = U1;
+  a.un = Un;
+  a.uout = Ua;
+  MH_HIP(c, launch_stage<T>(2, g.limiter, false, false, a, geom, c->stream));
+  MH_HIP(c, hipMemcpyAsync(Ub, Ua, sbytes, hipMemcpyDeviceToDevice, c->stream));
+  if (force)
+    MH_HIP(c, adj_force_kick<T>(Ub, at(A.rows), a.ou_tab[0], a.ou_R, geom, (T)dt, c->stream));
+  MH_HIP(c, hipMemcpyAsync(Uc, Ub, sbytes, hipMemcpyDeviceToDevice, c->stream));
+  const T* phi_sol = nullptr;
+  if (grav) {
+    MH_HIP(c, mg_set_guess<T>(ws, A.mg, phi_n, c->stream));
+    MH_HIP(c, mg_set_rhs<T>(ws, A.mg, Ub, 4.0 * M_PI * p.grav_G, aclk, c->stream));
+    MH_HIP(c, mg_solve<T>(ws, A.mg, p, aclk, nullptr, c->stream));
+    MH_HIP(c, mg_kick<T>(ws, A.mg, g, Uc, aclk, c->stream));
+    phi_sol = reinterpret_cast<const T*>(ws + mg_phi_offset(A.mg));
+  }
+
+  // reverse sweep: cooling, gravity, forcing, then RK2
+  const T* cur = lam_np1;
+  if (cool) {
+    MH_HIP(c, adj_cool_vjp<T>(Uc, N, (T)(g.gamma - 1.0), (T)dt, a.cool, cur, lamA, c->stream));
+    cur = lamA;
+  }
+  if (grav) {
+    MH_HIP(c, adj_gravity_vjp<T>(B, A.mg, ws, p, Ub, phi_sol, g.n[0], g.h[0], (T)dt, cur, lamB,
+                                 aclk, c->stream));
+    cur = lamB;
+  }
+  if (force) {
+    T* dst = cur == lamA ? lamB : lamA;
+    MH_HIP(c, adj_force_kick_vjp<T>(at(A.rows), a.ou_tab[0], a.ou_R, geom, (T)dt, cur, dst,
+                                    c->stream));
+    cur = dst;
+  }
+  // lam1 = cur/2 + (dt/2) J(U1)^T cur;  lam_n = cur/2 + lam1 + dt J(U^n)^T lam1
+  MH_HIP(c, adj_jtv<T>(B, geom, g.limiter, (T)g.gamma, g.h, U1, cur, (T)(0.5 * dt), T(0.5), cur,
+                       T(0), nullptr, lam1, c->stream));
+  MH_HIP(c, adj_jtv<T>(B, geom, g.limiter, (T)g.gamma, g.h, Un, lam1, (T)dt, T(0.5), cur, T(1),
+                       lam1, lam_n, c->stream));
+  return MH_OK;
+}
+
+extern "C" mh_status mh_adjoint_step(mh_ctx* c, void* adj_workspace, size_t adj_workspace_bytes,
+                                     const void* U_n, double dt, int64_t step,
+                                     const double* ou_ahat, const void* phi_n,
+                                     const void* lam_np1, void* lam_n) {
+  if (!c) return MH_E_INVALID;
+  if (!U_n || !lam_np1 || !lam_n)
+    return set_err(c, MH_E_INVALID, "mh_adjoint_step: null state or adjoint pointer");
+  if ((c->p.flags & MH_SRC_FORCING) && !ou_ahat)
+    return set_err(c, MH_E_INVALID, "mh_adjoint_step: forcing is on but ou_ahat is NULL");
+  if (!(dt >= 0.0) || step < 0) return set_err(c, MH_E_INVALID, "mh_adjoint_step: bad dt or step");
+  AdjLayout A = make_adj_layout(c->g, c->p);
+  if (!adj_workspace || adj_workspace_bytes < A.total || ((uintptr_t)adj_workspace % ALIGN) != 0)
+    return set_err(c, MH_E_WORKSPACE, "mh_adjoint_step: adjoint workspace too small or misaligned");
+  char* ws = (char*)adj_workspace;
+  if (c->g.dtype == MH_F64)
+    return adjoint_impl<double>(c, ws, A, (const double*)U_n, dt, step, ou_ahat,
+                                (const double*)phi_n, (const double*)lam_np1, (double*)lam_n);
+  return adjoint_impl<float>(c, ws, A, (const float*)U_n, dt, step, ou_ahat, (const float*)phi_n,
+                             (const float*)lam_np1, (float*)lam_n);
+}
+
 extern "C" mh_status mh_set_timing(mh_ctx* c, int enable) {
   if (!c) return MH_E_INVALID;
   c->timing = enable != 0;
@@ -526,6 +713,19 @@ extern "C" mh_status mh_get_timing(mh_ctx* c, double* ms, int64_t* launches) {
   launches[MH_TIME_OTHER] += c->untimed;
   c->kinds.clear();
   c->untimed = 0;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_set_potential(mh_ctx* c, const void* phi, int where) {
+  if (!c) return MH_E_INVALID;
+  if (!(c->p.flags & MH_SRC_GRAVITY))
+    return set_err(c, MH_E_INVALID, "mh_set_potential: gravity is off");
+  if (!phi || (where != MH_HOST && where != MH_DEVICE))
+    return set_err(c, MH_E_INVALID, "mh_set_potential: null pointer or bad location");
+  MH_HIP(c, hipMemcpyAsync(c->ws + mg_phi_offset(c->L.mg), phi, (size_t)c->cells() * c->esize(),
+                           where == MH_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (where == MH_HOST) MH_HIP(c, hipStreamSynchronize(c->stream));
   return MH_OK;
 }
 

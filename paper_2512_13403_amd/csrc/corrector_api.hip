@@ -1,0 +1,276 @@
+// corrector_api.hip -- C ABI of the learned state corrector (include/mihydro.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mihydro.h"
+#include "mh_corrector.h"
+
+using namespace mh;
+
+namespace {
+
+constexpr size_t CALIGN = 256;
+inline size_t calign(size_t x) { return (x + CALIGN - 1) & ~(CALIGN - 1); }
+
+struct CorrLayout {
+  size_t theta, m, v, grad, w1, w2, w3, w1t, w2t, w3t, x0, z1, h1, z2, h2, y, dy16, dy32, dz2, dz1;
+  size_t wpart, bpart, dpart, loss, counters, total;
+};
+
+CorrLayout corr_layout(const mh_corr_desc* d) {
+  CorrLayout L{};
+  const size_t cells = (size_t)d->batch * d->n * d->n * d->n;
+  const size_t nchunk = (cells + CORR_CHUNK - 1) / CORR_CHUNK;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = calign(off + bytes);
+    return o;
+  };
+  const size_t P = CORR_NPARAM * sizeof(float);
+  L.theta = take(P);
+  L.m = take(P);
+  L.v = take(P);
+  L.grad = take(P);
+  L.w1 = take(27 * 32 * 32 * 2);
+  L.w2 = take(27 * 32 * 32 * 2);
+  L.w3 = take(27 * 16 * 32 * 2);
+  L.w1t = take(27 * 16 * 32 * 2);
+  L.w2t = take(27 * 32 * 32 * 2);
+  L.w3t = take(27 * 32 * 32 * 2);
+  L.x0 = take(cells * 32 * 2);
+  L.z1 = take(cells * 32 * 4);
+  L.h1 = take(cells * 32 * 2);
+  L.z2 = take(cells * 32 * 4);
+  L.h2 = take(cells * 32 * 2);
+  L.y = take(cells * 16 * 4);
+  L.dy16 = take(cells * 16 * 2);
+  L.dy32 = take(cells * 32 * 2);
+  L.dz2 = take(cells * 32 * 2);
+  L.dz1 = take(cells * 32 * 2);
+  L.wpart = take(27 * nchunk * 32 * 32 * 4);
+  L.bpart = take(nchunk * 32 * 4);
+  const size_t nd = std::max((cells + 255) / 256, (size_t)d->batch * 64 * 2);
+  L.dpart = take(nd * sizeof(double));
+  L.loss = take(sizeof(double));
+  L.counters = take(2 * sizeof(unsigned long long));
+  L.total = off;
+  return L;
+}
+
+mh_status corr_validate(const mh_corr_desc* d) {
+  if (!d) return MH_E_INVALID;
+  if (d->n < 16 || d->n % 16 != 0 || d->batch < 1) return MH_E_SHAPE;
+  if (d->dtype != MH_F32 && d->dtype != MH_F64) return MH_E_DTYPE;
+  if (!(d->gamma > 1.0)) return MH_E_INVALID;
+  for (int c = 0; c < 5; ++c)
+    if (!(d->std[c] > 0.0) || !std::isfinite(d->mean[c]) || !std::isfinite(d->scale[c]))
+      return MH_E_INVALID;
+  if (!(d->floor_rel >= 0.0) || !(d->fallback_frac >= 0.0)) return MH_E_INVALID;
+  return MH_OK;
+}
+
+__global__ void k_zero_bytes(unsigned char* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+struct mh_corr {
+  mh_corr_desc d;
+  hipStream_t stream;
+  char* ws;
+  CorrLayout L;
+  CorrBuffers B;
+  CorrStats st;
+  int it = 0;
+  long long cells() const { return (long long)d.batch * d.n * d.n * d.n; }
+};
+
+#define MH_CHK(call)                           \
+  do {                                         \
+    if ((call) != hipSuccess) return MH_E_DEVICE; \
+  } while (0)
+
+extern "C" mh_status mh_corr_query_workspace(const mh_corr_desc* d, size_t* bytes) {
+  if (!bytes) return MH_E_INVALID;
+  mh_status s = corr_validate(d);
+  if (s != MH_OK) return s;
+  *bytes = corr_layout(d).total;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_init(const mh_corr_desc* d, void* workspace, size_t bytes,
+                                  void* stream, mh_corr** out) {
+  if (!out) return MH_E_INVALID;
+  *out = nullptr;
+  mh_status s = corr_validate(d);
+  if (s != MH_OK) return s;
+  CorrLayout L = corr_layout(d);
+  if (!workspace || bytes < L.total || ((uintptr_t)workspace % CALIGN) != 0) return MH_E_WORKSPACE;
+  mh_corr* c = new mh_corr();
+  c->d = *d;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace;
+  c->L = L;
+  char* w = c->ws;
+  auto F = [&](size_t o) { return reinterpret_cast<float*>(w + o); };
+  auto H = [&](size_t o) { return reinterpret_cast<unsigned short*>(w + o); };
+  c->B = CorrBuffers{F(L.theta), F(L.m), F(L.v), F(L.grad), H(L.w1), H(L.w2), H(L.w3), H(L.w1t),
+                     H(L.w2t), H(L.w3t), H(L.x0), H(L.h1), H(L.h2), H(L.dy16), H(L.dy32),
+                     H(L.dz2), H(L.dz1), F(L.z1), F(L.z2), F(L.y), F(L.wpart), F(L.bpart),
+                     reinterpret_cast<double*>(w + L.dpart), reinterpret_cast<double*>(w + L.loss),
+                     reinterpret_cast<unsigned long long*>(w + L.counters)};
+  for (int k = 0; k < 5; ++k) {
+    c->st.mean[k] = d->mean[k];
+    c->st.std[k] = d->std[k];
+    c->st.scale[k] = d->scale[k];
+    c->st.lw[k] = d->loss_w[k];
+  }
+  // parameters, moments and weight operands start at zero (padded weight
+  // rows must be zero: they meet zero activations in the products)
+  const size_t zero_span = L.x0;  // theta .. w3t are laid out first
+  hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)((zero_span + 255) / 256)), dim3(256), 0,
+                     c->stream, (unsigned char*)w, zero_span);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    delete c;
+    return MH_E_DEVICE;
+  }
+  *out = c;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_set_params(mh_corr* c, const float* theta, int where) {
+  if (!c || !theta || (where != MH_HOST && where != MH_DEVICE)) return MH_E_INVALID;
+  MH_CHK(hipMemcpyAsync(c->B.theta, theta, CORR_NPARAM * sizeof(float),
+                        where == MH_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                        c->stream));
+  const size_t mom = c->L.grad - c->L.m;  // m and v
+  hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)((mom + 255) / 256)), dim3(256), 0, c->stream,
+                     (unsigned char*)c->B.m, mom);
+  MH_CHK(hipGetLastError());
+  MH_CHK(corr_pack_weights(c->B, c->stream));
+  if (where == MH_HOST) MH_CHK(hipStreamSynchronize(c->stream));
+  c->it = 0;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_get_params(mh_corr* c, float* theta, int where) {
+  if (!c || !theta || (where != MH_HOST && where != MH_DEVICE)) return MH_E_INVALID;
+  MH_CHK(hipMemcpyAsync(theta, c->B.theta, CORR_NPARAM * sizeof(float),
+                        where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                        c->stream));
+  if (where == MH_HOST) MH_CHK(hipStreamSynchronize(c->stream));
+  return MH_OK;
+}
+
+template <typename T>
+static mh_status apply_impl(mh_corr* c, const T* U, T* out, int64_t* floored, int32_t* fell) {
+  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, out, c->stream));
+  MH_CHK(hipMemsetAsync(c->B.counters, 0, 2 * sizeof(unsigned long long), c->stream));
+  MH_CHK(corr_floor<T>(c->B, U, out, c->d.n, c->d.batch, c->d.gamma, c->d.floor_rel, c->stream));
+  unsigned long long cnt[2];
+  MH_CHK(hipMemcpyAsync(cnt, c->B.counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+  MH_CHK(hipStreamSynchronize(c->stream));
+  const bool fb = cnt[1] > 0 || (double)cnt[0] > c->d.fallback_frac * (double)c->cells();
+  if (fb) {
+    MH_CHK(hipMemcpyAsync(out, U, (size_t)c->cells() * 5 * sizeof(T), hipMemcpyDeviceToDevice,
+                          c->stream));
+    MH_CHK(hipStreamSynchronize(c->stream));
+  }
+  if (floored) *floored = (int64_t)cnt[0];
+  if (fell) *fell = fb ? 1 : 0;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_apply(mh_corr* c, const void* U, void* U_out, int64_t* floored,
+                                   int32_t* fell_back) {
+  if (!c || !U || !U_out || U == U_out) return MH_E_INVALID;
+  if (c->d.dtype == MH_F64)
+    return apply_impl<double>(c, (const double*)U, (double*)U_out, floored, fell_back);
+  return apply_impl<float>(c, (const float*)U, (float*)U_out, floored, fell_back);
+}
+
+template <typename T>
+static mh_status loss_grad_impl(mh_corr* c, const T* U, const T* tgt, double* loss) {
+  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, (T*)nullptr, c->stream));
+  MH_CHK(corr_loss_backward<T>(c->B, c->st, c->d.n, c->d.batch, U, tgt, c->stream));
+  if (loss) {
+    double l;
+    MH_CHK(hipMemcpyAsync(&l, c->B.loss, sizeof l, hipMemcpyDeviceToHost, c->stream));
+    MH_CHK(hipStreamSynchronize(c->stream));
+    *loss = l / (double)c->cells();
+  }
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_loss_grad(mh_corr* c, const void* U, const void* target, double* loss,
+                                       float* grad, int where) {
+  if (!c || !U || !target || (grad && where != MH_HOST && where != MH_DEVICE)) return MH_E_INVALID;
+  mh_status s = c->d.dtype == MH_F64
+                    ? loss_grad_impl<double>(c, (const double*)U, (const double*)target, loss)
+                    : loss_grad_impl<float>(c, (const float*)U, (const float*)target, loss);
+  if (s != MH_OK) return s;
+  if (grad) {
+    MH_CHK(hipMemcpyAsync(grad, c->B.grad, CORR_NPARAM * sizeof(float),
+                          where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                          c->stream));
+    MH_CHK(hipStreamSynchronize(c->stream));
+  }
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_train_step(mh_corr* c, const void* U, const void* target, float lr,
+                                        double* loss) {
+  if (!c || !U || !target || !(lr >= 0.0f)) return MH_E_INVALID;
+  mh_status s = mh_corr_loss_grad(c, U, target, loss, nullptr, MH_DEVICE);
+  if (s != MH_OK) return s;
+  c->it += 1;
+  MH_CHK(corr_adam(c->B, c->it, lr, c->stream));
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_get_activation(mh_corr* c, int which, void* dst, int where) {
+  if (!c || !dst || which < 0 || which > 5 || (where != MH_HOST && where != MH_DEVICE))
+    return MH_E_INVALID;
+  const size_t cells = (size_t)c->cells();
+  const void* src = nullptr;
+  size_t bytes = 0;
+  switch (which) {
+    case 0: src = c->B.x0; bytes = cells * 32 * 2; break;
+    case 1: src = c->B.z1; bytes = cells * 32 * 4; break;
+    case 2: src = c->B.h1; bytes = cells * 32 * 2; break;
+    case 3: src = c->B.z2; bytes = cells * 32 * 4; break;
+    case 4: src = c->B.h2; bytes = cells * 32 * 2; break;
+    default: src = c->B.y; bytes = cells * 16 * 4; break;
+  }
+  MH_CHK(hipMemcpyAsync(dst, src, bytes,
+                        where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                        c->stream));
+  if (where == MH_HOST) MH_CHK(hipStreamSynchronize(c->stream));
+  return MH_OK;
+}
+
+extern "C" void mh_corr_destroy(mh_corr* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+extern "C" mh_status mh_block_average(const void* fine, int32_t nf, int32_t r, void* coarse,
+                                      int32_t dtype, void* stream) {
+  if (!fine || !coarse || r < 1 || nf < r || nf % r != 0) return MH_E_INVALID;
+  if (dtype == MH_F64)
+    MH_CHK(launch_block_average<double>((const double*)fine, nf, r, (double*)coarse,
+                                        (hipStream_t)stream));
+  else if (dtype == MH_F32)
+    MH_CHK(launch_block_average<float>((const float*)fine, nf, r, (float*)coarse,
+                                       (hipStream_t)stream));
+  else
+    return MH_E_DTYPE;
+  return MH_OK;
+}

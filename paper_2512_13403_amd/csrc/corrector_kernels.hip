@@ -1,0 +1,530 @@
+// corrector_kernels.hip -- the learned state corrector on gfx950 matrix cores.
+//
+// The corrector is a 3D convolutional network applied after a coarse step,
+// trained through the solver (the solver-in-the-loop setting of arXiv
+// 2512.13403 Sec. 8): x = (U - mean)/std, h1 = GELU(conv(x)), h2 =
+// GELU(conv(h1)), y = conv(h2), U' = U + scale * y, with 3x3x3 periodic
+// cross-correlations of 5 -> 32 -> 32 -> 5 channels.
+//
+// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16: a wave
+// owns 16 consecutive cells along x (the MFMA rows) and 16 output channels per
+// tile (the MFMA columns); for each of the 27 taps it multiplies the 16 x 32
+// block of shifted input activations (bf16, channels contiguous: one 16-byte
+// load per lane) by the 32 x 16 weight block of that tap, accumulating in
+// fp32.  Activations are stored cell-major with 32 channels (the network input
+// is zero-padded from 5 to 32, the last layer's 5 outputs sit in 16).  The
+// same kernel serves the input-gradient pass: there the weights are packed
+// transposed with the taps mirrored, so reading at cell + off_tap applies the
+// transpose of the forward map.  Weight gradients are GEMMs over cells: one workgroup
+// per (tap, chunk of 4096 cells) writes a 32 x 32 partial product, and a
+// second kernel adds the chunks in a fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include "mh_corrector.h"
+
+namespace mh {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  // round to nearest even
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const unsigned short* p) {
+  bf16x8 v;
+  __builtin_memcpy(&v, p, 16);
+  return v;
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+enum : int { EPI_GELU = 0, EPI_LINEAR = 1, EPI_GELU_BWD = 2, EPI_RAW = 3 };
+
+// out[cell][co] for COT output channels (16 or 32) from in[cell][32]; the tap
+// t reads in at cell + sign * off_t.  w: [27][COT][32] bf16.
+template <int COT, int EPI>
+__global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__ in,
+                                              const unsigned short* __restrict__ w,
+                                              const float* __restrict__ bias, int nbias, int n,
+                                              long long cells, int sign, const float* __restrict__ zin,
+                                              float* __restrict__ fout,
+                                              unsigned short* __restrict__ hout) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long cell0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  if (cell0 >= cells) return;
+  const long long n3 = (long long)n * n * n;
+  const long long b = cell0 / n3, r = cell0 % n3;
+  const int z = (int)(r / ((long long)n * n)), y = (int)((r / n) % n), x0 = (int)(r % n);
+  const int row = lane & 15, grp = lane >> 4;
+  f32x4 acc[COT / 16];
+#pragma unroll
+  for (int t = 0; t < COT / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < 27; ++tap) {
+    const int dx = sign * (tap % 3 - 1), dy = sign * ((tap / 3) % 3 - 1), dz = sign * (tap / 9 - 1);
+    const long long src = b * n3 + ((long long)wrap(z + dz, n) * n + wrap(y + dy, n)) * n +
+                          wrap(x0 + row + dx, n);
+    const bf16x8 a = load8(in + src * 32 + 8 * grp);
+#pragma unroll
+    for (int nt = 0; nt < COT / 16; ++nt) {
+      const bf16x8 bv = load8(w + ((long long)(tap * COT + nt * 16 + row) * 32 + 8 * grp));
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[nt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < COT / 16; ++nt) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long cell = cell0 + 4 * grp + q;
+      const int co = nt * 16 + row;
+      const float v = acc[nt][q];
+      const long long o = cell * COT + co;
+      if (EPI == EPI_GELU) {
+        const float zz = v + bias[co];
+        if (fout) fout[o] = zz;
+        hout[o] = f2bf(gelu(zz));
+      } else if (EPI == EPI_LINEAR) {
+        fout[o] = v + (co < nbias ? bias[co] : 0.f);
+      } else if (EPI == EPI_GELU_BWD) {
+        hout[o] = f2bf(v * gelu_grad(zin[o]));
+      } else {
+        fout[o] = v;
+      }
+    }
+  }
+}
+
+// partial[tap][chunk][COT][32] = sum over the chunk's cells of
+// dz[cell][co] * x[cell + off_tap][ci]; one workgroup per (tap, chunk)
+template <int COT>
+__global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict__ dz,
+                                               const unsigned short* __restrict__ x, int n,
+                                               long long cells, int chunk,
+                                               float* __restrict__ partial) {
+  __shared__ float red[4][COT][32];
+  const int tap = blockIdx.x % 27;
+  const long long ch = blockIdx.x / 27;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, grp = lane >> 4;
+  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dzz = tap / 9 - 1;
+  const long long n3 = (long long)n * n * n;
+  f32x4 acc[COT / 16][2];
+#pragma unroll
+  for (int i = 0; i < COT / 16; ++i) acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const long long begin = ch * chunk + (long long)wave * (chunk / 4);
+  const long long end = begin + chunk / 4;
+  for (long long k0 = begin; k0 < end && k0 < cells; k0 += 32) {
+    unsigned short av[COT / 16][8], bv[2][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const long long cell = k0 + 8 * grp + e;
+      const long long b = cell / n3, r = cell % n3;
+      const int z = (int)(r / ((long long)n * n)), y = (int)((r / n) % n), xx = (int)(r % n);
+      const long long src = b * n3 + ((long long)wrap(z + dzz, n) * n + wrap(y + dy, n)) * n +
+                            wrap(xx + dx, n);
+#pragma unroll
+      for (int mt = 0; mt < COT / 16; ++mt) av[mt][e] = dz[cell * COT + mt * 16 + row];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) bv[ct][e] = x[src * 32 + ct * 16 + row];
+    }
+#pragma unroll
+    for (int mt = 0; mt < COT / 16; ++mt) {
+      bf16x8 a;
+      __builtin_memcpy(&a, av[mt], 16);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        bf16x8 bb;
+        __builtin_memcpy(&bb, bv[ct], 16);
+        acc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[mt][ct], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < COT / 16; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[wave][mt * 16 + 4 * grp + q][ct * 16 + row] = acc[mt][ct][q];
+  __syncthreads();
+  for (int i = threadIdx.x; i < COT * 32; i += 256) {
+    const int co = i / 32, ci = i % 32;
+    const float s = ((red[0][co][ci] + red[1][co][ci]) + red[2][co][ci]) + red[3][co][ci];
+    partial[((long long)tap * gridDim.x / 27 + ch) * (COT * 32) + i] = s;
+  }
+}
+
+// gtheta[off + (co * ci_real + ci) * 27 + tap] = sum over chunks (fixed order)
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int cot,
+                                                      int nchunk, int co_real, int ci_real,
+                                                      float* __restrict__ g) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= 27 * co_real * ci_real) return;
+  const int tap = i % 27, ci = (i / 27) % ci_real, co = i / (27 * ci_real);
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += partial[((long long)tap * nchunk + c) * (cot * 32) + co * 32 + ci];
+  g[i] = s;
+}
+
+// per-chunk column sums of dz[cell][co] (bias gradients), then the fixed-order total
+__global__ __launch_bounds__(256) void k_colsum_partial(const unsigned short* __restrict__ dz, int cot,
+                                                        long long cells, int chunk,
+                                                        float* __restrict__ partial) {
+  const int co = threadIdx.x;
+  if (co >= cot) return;
+  const long long c0 = (long long)blockIdx.x * chunk;
+  float s = 0.f;
+  for (long long c = c0; c < c0 + chunk && c < cells; ++c) s += bf2f(dz[c * cot + co]);
+  partial[(long long)blockIdx.x * cot + co] = s;
+}
+
+__global__ __launch_bounds__(64) void k_colsum_final(const float* __restrict__ partial, int cot,
+                                                     int nchunk, int co_real, float* __restrict__ g) {
+  const int co = threadIdx.x;
+  if (co >= co_real) return;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += partial[(long long)c * cot + co];
+  g[co] = s;
+}
+
+// network input: x[cell][c] = bf16(float((U_c - mean_c) / std_c)) for c < 5, 0 above
+template <typename T>
+__global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ U, int n, long long cells,
+                                                     CorrStats st, unsigned short* __restrict__ x) {
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= cells) return;
+  const long long n3 = (long long)n * n * n;
+  const long long b = cell / n3, q = cell % n3;
+  unsigned short v[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) v[c] = 0;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double s = ((double)U[(b * 5 + c) * n3 + q] - st.mean[c]) / st.std[c];
+    v[c] = f2bf((float)s);
+  }
+#pragma unroll
+  for (int c = 0; c < 32; c += 8) __builtin_memcpy(x + cell * 32 + c, v + c, 16);
+}
+
+// U' = U + scale * y (y: [cell][16] fp32, first 5 channels)
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const float* __restrict__ y,
+                                                  int n, long long cells, CorrStats st,
+                                                  T* __restrict__ out) {
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= cells) return;
+  const long long n3 = (long long)n * n * n;
+  const long long b = cell / n3, q = cell % n3;
+#pragma unroll
+  for (int c = 0; c < 5; ++c)
+    out[(b * 5 + c) * n3 + q] = U[(b * 5 + c) * n3 + q] + (T)(st.scale[c] * (double)y[cell * 16 + c]);
+}
+
+// per-sample sums of rho and P of the uncorrected state (two-stage, fixed order)
+template <typename T>
+__global__ __launch_bounds__(256) void k_rho_p_partial(const T* __restrict__ U, long long n3, double gm1,
+                                                       int blocks_per_sample, double* __restrict__ part) {
+  __shared__ double sr[256], sp[256];
+  const int b = blockIdx.x / blocks_per_sample, blk = blockIdx.x % blocks_per_sample;
+  double r = 0.0, p = 0.0;
+  for (long long q = (long long)blk * 256 + threadIdx.x; q < n3; q += (long long)blocks_per_sample * 256) {
+    const double rho = (double)U[(b * 5) * n3 + q];
+    const double mx = (double)U[(b * 5 + 1) * n3 + q], my = (double)U[(b * 5 + 2) * n3 + q],
+                 mz = (double)U[(b * 5 + 3) * n3 + q], E = (double)U[(b * 5 + 4) * n3 + q];
+    r += rho;
+    p += gm1 * (E - 0.5 * (mx * mx + my * my + mz * mz) / rho);
+  }
+  sr[threadIdx.x] = r;
+  sp[threadIdx.x] = p;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      sp[threadIdx.x] += sp[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr[0];
+    part[2 * blockIdx.x + 1] = sp[0];
+  }
+}
+
+// positivity floor: rho >= f <rho>, then P >= f <P> by raising E at fixed m;
+// counts floored and non-finite cells
+template <typename T>
+__global__ __launch_bounds__(256) void k_floor(T* __restrict__ U, long long n3, long long cells, double gm1,
+                                               double frel, const double* __restrict__ part,
+                                               int blocks_per_sample,
+                                               unsigned long long* __restrict__ counters) {
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= cells) return;
+  const long long b = cell / n3, q = cell % n3;
+  double sr = 0.0, sp = 0.0;
+  for (int k = 0; k < blocks_per_sample; ++k) {
+    sr += part[2 * (b * blocks_per_sample + k)];
+    sp += part[2 * (b * blocks_per_sample + k) + 1];
+  }
+  const double rf = frel * sr / (double)n3, pf = frel * sp / (double)n3;
+  T* u = U + b * 5 * n3 + q;
+  bool fl = false;
+  double rho = (double)u[0];
+  if (rho < rf) {
+    rho = rf;
+    u[0] = (T)rf;
+    fl = true;
+  }
+  const double mx = (double)u[n3], my = (double)u[2 * n3], mz = (double)u[3 * n3];
+  const double ek = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+  const double p = gm1 * ((double)u[4 * n3] - ek);
+  if (p < pf) {
+    u[4 * n3] = (T)(ek + pf / gm1);
+    fl = true;
+  }
+  const bool bad = !(isfinite(rho) && isfinite(mx) && isfinite(my) && isfinite(mz) &&
+                     isfinite((double)u[4 * n3]));
+  if (fl) atomicAdd(&counters[0], 1ull);
+  if (bad) atomicAdd(&counters[1], 1ull);
+}
+
+// loss L = sum_c w_c mean((U'_c - T_c)^2) / sigma_c^2 (per-block partials) and
+// dY[cell][c] = bf16(scale_c * 2 w_c (U'_c - T_c) / (sigma_c^2 cells))
+template <typename T>
+__global__ __launch_bounds__(256) void k_loss(const T* __restrict__ U, const float* __restrict__ y,
+                                              const T* __restrict__ tgt, int n, long long cells,
+                                              CorrStats st, double* __restrict__ part,
+                                              unsigned short* __restrict__ dy) {
+  __shared__ double sl[256];
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (cell < cells) {
+    const long long n3 = (long long)n * n * n;
+    const long long b = cell / n3, q = cell % n3;
+    unsigned short v[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = 0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const double uc = (double)U[(b * 5 + c) * n3 + q] + st.scale[c] * (double)y[cell * 16 + c];
+      const double d = uc - (double)tgt[(b * 5 + c) * n3 + q];
+      const double s2 = st.std[c] * st.std[c];
+      l += st.lw[c] * d * d / s2;
+      v[c] = f2bf((float)(st.scale[c] * (2.0 * st.lw[c] * d / s2 / (double)cells)));
+    }
+    __builtin_memcpy(dy + cell * 16, v, 16);
+    __builtin_memcpy(dy + cell * 16 + 8, v + 8, 16);
+  }
+  sl[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sl[threadIdx.x] += sl[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sl[0];
+}
+
+// dY of 16 channels -> 32-channel operand layout for the next MFMA pass
+__global__ __launch_bounds__(256) void k_pad16to32(const unsigned short* __restrict__ a, long long cells,
+                                                   unsigned short* __restrict__ b) {
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= cells) return;
+  unsigned short v[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) v[c] = c < 16 ? a[cell * 16 + c] : 0;
+#pragma unroll
+  for (int c = 0; c < 32; c += 8) __builtin_memcpy(b + cell * 32 + c, v + c, 16);
+}
+
+__global__ __launch_bounds__(256) void k_dsum(const double* __restrict__ part, int n, double* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s;
+  }
+}
+
+// ADAM on the fp32 master parameters, then the bf16 operand layouts:
+// forward weights [27][COT][32] and mirrored-transposed input-gradient weights
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ th, float* __restrict__ m,
+                                              float* __restrict__ v, const float* __restrict__ g,
+                                              int count, float lr, float c1, float c2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float mi = b1 * m[i] + (1.f - b1) * g[i];
+  const float vi = b2 * v[i] + (1.f - b2) * g[i] * g[i];
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ th, int off, int co_real,
+                                              int ci_real, int cot, unsigned short* __restrict__ wf,
+                                              int cit_t, unsigned short* __restrict__ wt) {
+  // forward: wf[tap][co][ci] (co < cot, ci < 32); transposed-mirrored:
+  // wt[26 - tap][ci][co] (ci < cit_t rows, co < 32)
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= 27 * cot * 32) return;
+  const int tap = i / (cot * 32), co = (i / 32) % cot, ci = i % 32;
+  float val = 0.f;
+  if (co < co_real && ci < ci_real) val = th[off + (co * ci_real + ci) * 27 + tap];
+  const unsigned short h = f2bf(val);
+  wf[i] = h;
+  if (wt && ci < cit_t) wt[((long long)(26 - tap) * cit_t + ci) * 32 + co] = h;
+}
+
+// conservative block average of a fine state [5][nf^3] onto [5][(nf/r)^3]
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_average(const T* __restrict__ fine, int nf, int r,
+                                                       T* __restrict__ coarse) {
+  const int nc = nf / r;
+  const long long Nc = (long long)nc * nc * nc, Nf = (long long)nf * nf * nf;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= 5 * Nc) return;
+  const int f = (int)(t / Nc);
+  const long long q = t % Nc;
+  const int I = (int)(q % nc), J = (int)((q / nc) % nc), K = (int)(q / ((long long)nc * nc));
+  double s = 0.0;
+  for (int c = 0; c < r; ++c)
+    for (int b = 0; b < r; ++b)
+      for (int a = 0; a < r; ++a)
+        s += (double)fine[f * Nf + ((long long)(K * r + c) * nf + (J * r + b)) * nf + (I * r + a)];
+  coarse[t] = (T)(s / (double)(r * r * r));
+}
+
+inline unsigned blocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
+                     CORR_OFF_W1, 32, 5, 32, B.w1, 16, B.w1t);
+  hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
+                     CORR_OFF_W2, 32, 32, 32, B.w2, 32, B.w2t);
+  hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 16 * 32, 256)), dim3(256), 0, s, B.theta,
+                     CORR_OFF_W3, 5, 32, 16, B.w3, 32, B.w3t);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
+                        T* out, hipStream_t s) {
+  const long long cells = (long long)batch * n * n * n;
+  const unsigned seg_blocks = blocks(cells / 16, 4);
+  hipLaunchKernelGGL((k_standardize<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, n, cells, st,
+                     B.x0);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(seg_blocks), dim3(256), 0, s, B.x0, B.w1,
+                     B.theta + CORR_OFF_B1, 32, n, cells, 1, (const float*)nullptr, B.z1, B.h1);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(seg_blocks), dim3(256), 0, s, B.h1, B.w2,
+                     B.theta + CORR_OFF_B2, 32, n, cells, 1, (const float*)nullptr, B.z2, B.h2);
+  hipLaunchKernelGGL((k_conv<16, EPI_LINEAR>), dim3(seg_blocks), dim3(256), 0, s, B.h2, B.w3,
+                     B.theta + CORR_OFF_B3, 5, n, cells, 1, (const float*)nullptr, B.y,
+                     (unsigned short*)nullptr);
+  if (out)
+    hipLaunchKernelGGL((k_residual<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, B.y, n, cells,
+                       st, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch, double gamma,
+                      double frel, hipStream_t s) {
+  const long long n3 = (long long)n * n * n, cells = batch * n3;
+  const int bps = 64;
+  hipLaunchKernelGGL((k_rho_p_partial<T>), dim3(batch * bps), dim3(256), 0, s, U, n3, gamma - 1.0,
+                     bps, B.dpart);
+  hipLaunchKernelGGL((k_floor<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, out, n3, cells,
+                     gamma - 1.0, frel, B.dpart, bps, B.counters);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch,
+                              const T* U, const T* tgt, hipStream_t s) {
+  const long long cells = (long long)batch * n * n * n;
+  const unsigned seg_blocks = blocks(cells / 16, 4);
+  const unsigned lb = blocks(cells, 256);
+  hipLaunchKernelGGL((k_loss<T>), dim3(lb), dim3(256), 0, s, U, B.y, tgt, n, cells, st, B.dpart,
+                     B.dy16);
+  hipLaunchKernelGGL(k_dsum, dim3(1), dim3(64), 0, s, B.dpart, (int)lb, B.loss);
+  hipLaunchKernelGGL(k_pad16to32, dim3(lb), dim3(256), 0, s, B.dy16, cells, B.dy32);
+  const int chunk = CORR_CHUNK;
+  const int nchunk = (int)((cells + chunk - 1) / chunk);
+  // layer 3: dW3, db3; dH2 -> dZ2 = dH2 * GELU'(Z2)
+  hipLaunchKernelGGL((k_wgrad<16>), dim3(27 * nchunk), dim3(256), 0, s, B.dy16, B.h2, n, cells, chunk,
+                     B.wpart);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32, 256)), dim3(256), 0, s, B.wpart, 16,
+                     nchunk, 5, 32, B.grad + CORR_OFF_W3);
+  hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dy16, 16, cells, chunk,
+                     B.bpart);
+  hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 16, nchunk, 5,
+                     B.grad + CORR_OFF_B3);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(seg_blocks), dim3(256), 0, s, B.dy32, B.w3t,
+                     (const float*)nullptr, 0, n, cells, 1, B.z2, (float*)nullptr, B.dz2);
+  // layer 2
+  hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz2, B.h1, n, cells, chunk,
+                     B.wpart);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.wpart, 32,
+                     nchunk, 32, 32, B.grad + CORR_OFF_W2);
+  hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz2, 32, cells, chunk,
+                     B.bpart);
+  hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
+                     B.grad + CORR_OFF_B2);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(seg_blocks), dim3(256), 0, s, B.dz2, B.w2t,
+                     (const float*)nullptr, 0, n, cells, 1, B.z1, (float*)nullptr, B.dz1);
+  // layer 1
+  hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz1, B.x0, n, cells, chunk,
+                     B.wpart);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5, 256)), dim3(256), 0, s, B.wpart, 32,
+                     nchunk, 32, 5, B.grad + CORR_OFF_W1);
+  hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz1, 32, cells, chunk,
+                     B.bpart);
+  hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
+                     B.grad + CORR_OFF_B1);
+  return hipGetLastError();
+}
+
+hipError_t corr_adam(const CorrBuffers& B, int it, float lr, hipStream_t s) {
+  const float c1 = 1.0f - powf(0.9f, (float)it), c2 = 1.0f - powf(0.999f, (float)it);
+  hipLaunchKernelGGL(k_adam, dim3(blocks(CORR_NPARAM, 256)), dim3(256), 0, s, B.theta, B.m, B.v,
+                     B.grad, CORR_NPARAM, lr, c1, c2);
+  return corr_pack_weights(B, s);
+}
+
+template <typename T>
+hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStream_t s) {
+  const long long nc = nf / r;
+  hipLaunchKernelGGL((k_block_average<T>), dim3(blocks(5 * nc * nc * nc, 256)), dim3(256), 0, s,
+                     fine, nf, r, coarse);
+  return hipGetLastError();
+}
+
+#define CORR_INSTANTIATE(T)                                                                       \
+  template hipError_t corr_forward<T>(const CorrBuffers&, const CorrStats&, int, int, const T*, T*, \
+                                      hipStream_t);                                               \
+  template hipError_t corr_floor<T>(const CorrBuffers&, const T*, T*, int, int, double, double,    \
+                                    hipStream_t);                                                 \
+  template hipError_t corr_loss_backward<T>(const CorrBuffers&, const CorrStats&, int, int,        \
+                                            const T*, const T*, hipStream_t);                      \
+  template hipError_t launch_block_average<T>(const T*, int, int, T*, hipStream_t);
+CORR_INSTANTIATE(float)
+CORR_INSTANTIATE(double)
+#undef CORR_INSTANTIATE
+
+}  // namespace mh

@@ -43,4 +43,20 @@ template <typename T>
 hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
                            const CoolParams<T>& cool, T* U, DevClock* clk, hipStream_t s);
 
+// Pieces of the solve for the adjoint step: F = scale (x - <x>) on the fine
+// level; the initial guess (a copy of phi0, or zero when phi0 is NULL); the
+// V-cycle loop on the loaded F (cycles run returned in *cycles_out); and the
+// gravity kick alone from the current fine-level potential.
+template <typename T>
+hipError_t mg_set_rhs(char* ws, MGLayout& L, const T* x, double scale, DevClock* clk,
+                      hipStream_t s);
+template <typename T>
+hipError_t mg_set_guess(char* ws, MGLayout& L, const T* phi0, hipStream_t s);
+template <typename T>
+hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* clk, int* cycles_out,
+                    hipStream_t s);
+template <typename T>
+hipError_t mg_kick(char* ws, MGLayout& L, const mh_grid_desc& g, T* U, DevClock* clk,
+                   hipStream_t s);
+
 }  // namespace mh

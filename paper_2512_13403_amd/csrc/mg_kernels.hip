@@ -409,23 +409,46 @@ hipError_t mg_init(char* ws, const MGLayout& L, const mh_grid_desc* g, hipStream
   return hipGetLastError();
 }
 
+#define MG_CHECK(x)                \
+  do {                             \
+    hipError_t e_ = (x);           \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+// F = scale (x - <x>) on the fine level
 template <typename T>
-hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
-                           const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s) {
+hipError_t mg_set_rhs(char* ws, MGLayout& L, const T* x, double scale, DevClock* clk,
+                      hipStream_t s) {
+  MGLevel& f = L.lev[0];
+  const long long N = (long long)f.n * f.n * f.n;
+  double* partial = P<double>(ws, L.partial);
+  MG_CHECK(sum_to(x, N, false, partial, 1.0 / (double)N, &clk->mean, s));
+  hipLaunchKernelGGL((k_shift_scale<T>), dim3(nblk(N)), dim3(256), 0, s, P<T>(ws, f.F), x, N,
+                     &clk->mean, scale);
+  return hipGetLastError();
+}
+
+// fine-level initial guess: a copy of phi0, or zero
+template <typename T>
+hipError_t mg_set_guess(char* ws, MGLayout& L, const T* phi0, hipStream_t s) {
+  MGLevel& f = L.lev[0];
+  const long long N = (long long)f.n * f.n * f.n;
+  if (phi0)
+    return hipMemcpyAsync(P<T>(ws, f.phi[L.cur0]), phi0, N * sizeof(T), hipMemcpyDeviceToDevice, s);
+  hipLaunchKernelGGL((k_zero<T>), dim3(nblk(N)), dim3(256), 0, s, P<T>(ws, f.phi[L.cur0]), N);
+  return hipGetLastError();
+}
+
+// V-cycles on A phi = F (F already mean-free on the fine level) from the
+// current guess until ||F - A phi||_2 <= tol ||F||_2 or max_cycles cycles;
+// the mean of phi is removed before the first and after every cycle.
+template <typename T>
+hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* clk, int* cycles_out,
+                    hipStream_t s) {
   MGLevel& f = L.lev[0];
   const int n = f.n;
   const long long N = (long long)n * n * n;
   double* partial = P<double>(ws, L.partial);
-  hipError_t e;
-#define MG_CHECK(x)            \
-  do {                         \
-    e = (x);                   \
-    if (e != hipSuccess) return e; \
-  } while (0)
-  // F = 4 pi G (rho - <rho>)
-  MG_CHECK(sum_to(U, N, false, partial, 1.0 / (double)N, &clk->mean, s));
-  hipLaunchKernelGGL((k_shift_scale<T>), dim3(nblk(N)), dim3(256), 0, s, P<T>(ws, f.F), U, N,
-                     &clk->mean, 4.0 * M_PI * p.grav_G);
   MG_CHECK(sum_to(P<T>(ws, f.F), N, true, partial, 1.0, &clk->mg_fnorm2, s));
   MG_CHECK(remove_mean(P<T>(ws, f.phi[L.cur0]), N, partial, &clk->mean, s));
   int cycles = 0;
@@ -442,6 +465,19 @@ hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const m
     ++cycles;
   }
   hipLaunchKernelGGL(k_set_cycles, dim3(1), dim3(64), 0, s, clk, cycles);
+  if (cycles_out) *cycles_out = cycles;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
+                           const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s) {
+  MGLevel& f = L.lev[0];
+  const int n = f.n;
+  const long long N = (long long)n * n * n;
+  // F = 4 pi G (rho - <rho>), solve from the previous potential
+  MG_CHECK(mg_set_rhs<T>(ws, L, U, 4.0 * M_PI * p.grav_G, clk, s));
+  MG_CHECK(mg_solve<T>(ws, L, p, clk, nullptr, s));
   const T i2h = (T)(1.0 / (2.0 * f.h));
   if (p.flags & MH_SRC_COOLING)
     hipLaunchKernelGGL((k_grav_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U,
@@ -449,16 +485,37 @@ hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const m
   else
     hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
                        P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk);
-#undef MG_CHECK
   return hipGetLastError();
 }
 
-template hipError_t mg_gravity_step<float>(char*, MGLayout&, const mh_grid_desc&,
-                                           const mh_physics_desc&, const CoolParams<float>&, float*,
-                                           DevClock*, hipStream_t);
-template hipError_t mg_gravity_step<double>(char*, MGLayout&, const mh_grid_desc&,
-                                            const mh_physics_desc&, const CoolParams<double>&,
-                                            double*, DevClock*, hipStream_t);
+// gravity kick alone from the fine-level potential (no cooling), for the
+// forward recomputation inside the adjoint step
+template <typename T>
+hipError_t mg_kick(char* ws, MGLayout& L, const mh_grid_desc& g, T* U, DevClock* clk,
+                   hipStream_t s) {
+  MGLevel& f = L.lev[0];
+  const long long N = (long long)f.n * f.n * f.n;
+  CoolParams<T> none{};
+  hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
+                     P<T>(ws, f.phi[L.cur0]), f.n, (T)(1.0 / (2.0 * f.h)), (T)g.gamma,
+                     (T)(1.0 / f.h), none, clk);
+  return hipGetLastError();
+}
+
+#undef MG_CHECK
+
+#define MG_INSTANTIATE(T)                                                                      \
+  template hipError_t mg_gravity_step<T>(char*, MGLayout&, const mh_grid_desc&,                \
+                                         const mh_physics_desc&, const CoolParams<T>&, T*,     \
+                                         DevClock*, hipStream_t);                               \
+  template hipError_t mg_set_rhs<T>(char*, MGLayout&, const T*, double, DevClock*, hipStream_t); \
+  template hipError_t mg_set_guess<T>(char*, MGLayout&, const T*, hipStream_t);                 \
+  template hipError_t mg_solve<T>(char*, MGLayout&, const mh_physics_desc&, DevClock*, int*,    \
+                                  hipStream_t);                                                 \
+  template hipError_t mg_kick<T>(char*, MGLayout&, const mh_grid_desc&, T*, DevClock*, hipStream_t);
+MG_INSTANTIATE(float)
+MG_INSTANTIATE(double)
+#undef MG_INSTANTIATE
 
 size_t mg_phi_offset(const MGLayout& L) { return L.lev[0].phi[L.cur0]; }
 

@@ -1,0 +1,40 @@
+// mh_adjoint.h -- launchers of the adjoint kernels (internal to libmihydro).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mg.h"
+#include "mh_device.h"
+#include "mh_launch.h"
+
+namespace mh {
+
+// scratch arrays of one adjoint step, carved from the adjoint workspace
+template <typename T>
+struct AdjointBuffers {
+  T* Wacc;     // [5][N] primitive-variable adjoint accumulator
+  T* wbar;     // [10][faces] face-state adjoints W^L_b, W^R_b of one axis
+  int* flags;  // [faces] minmod selections of the two slopes of each face
+  T* accb;     // [3][N] adjoint of the gravitational acceleration
+  T* phib;     // [N] adjoint of the potential
+};
+
+template <typename T>
+hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, T gamma,
+                   const double* h, const T* U, const T* v, T beta, T c0, const T* x0, T c1,
+                   const T* x1, T* out, hipStream_t s);
+template <typename T>
+hipError_t adj_force_kick(T* U, const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
+                          hipStream_t s);
+template <typename T>
+hipError_t adj_force_kick_vjp(const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
+                              const T* lin, T* lout, hipStream_t s);
+template <typename T>
+hipError_t adj_cool_vjp(const T* U, long long N, T gm1, T dt, const CoolParams<T>& c, const T* lin,
+                        T* lout, hipStream_t s);
+template <typename T>
+hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws,
+                           const mh_physics_desc& p, const T* Ub, const T* phi, int n, double h,
+                           T dt, const T* lin, T* lout, DevClock* clk, hipStream_t s);
+
+}  // namespace mh

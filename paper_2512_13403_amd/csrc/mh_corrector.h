@@ -1,0 +1,46 @@
+// mh_corrector.h -- corrector buffers and launchers (internal to libmihydro).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mh {
+
+// canonical parameter order: W1[32][5][27], b1[32], W2[32][32][27], b2[32],
+// W3[5][32][27], b3[5]
+constexpr int CORR_OFF_W1 = 0;
+constexpr int CORR_OFF_B1 = 4320;
+constexpr int CORR_OFF_W2 = 4352;
+constexpr int CORR_OFF_B2 = 32000;
+constexpr int CORR_OFF_W3 = 32032;
+constexpr int CORR_OFF_B3 = 36352;
+constexpr int CORR_NPARAM = 36357;
+constexpr int CORR_CHUNK = 4096;  // cells per weight-gradient workgroup
+
+struct CorrStats {
+  double mean[5], std[5], scale[5], lw[5];
+};
+
+struct CorrBuffers {
+  float *theta, *m, *v, *grad;
+  unsigned short *w1, *w2, *w3, *w1t, *w2t, *w3t;
+  unsigned short *x0, *h1, *h2, *dy16, *dy32, *dz2, *dz1;
+  float *z1, *z2, *y, *wpart, *bpart;
+  double *dpart, *loss;
+  unsigned long long* counters;
+};
+
+hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s);
+template <typename T>
+hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
+                        T* out, hipStream_t s);
+template <typename T>
+hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch, double gamma,
+                      double frel, hipStream_t s);
+template <typename T>
+hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch,
+                              const T* U, const T* tgt, hipStream_t s);
+hipError_t corr_adam(const CorrBuffers& B, int it, float lr, hipStream_t s);
+template <typename T>
+hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStream_t s);
+
+}  // namespace mh

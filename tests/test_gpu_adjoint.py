@@ -1,0 +1,140 @@
+"""GPU parity of the hand-written adjoint step (mh_adjoint_step) against the
+oracle's independent adjoint (oracle_adjoint.c, itself pinned by finite
+differences), and of the checkpointed rollout gradient.  Tolerances as for
+the forward (relative field norm on lambda): fp64 1e-12, fp32 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2512_13403_amd as mh
+import workloads as wl
+from paper_2512_13403_amd import rollout as ro
+from parity import TOL, as_input, pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield
+
+
+def torch_dev(a, dtype):
+    import torch
+
+    return torch.tensor(np.asarray(a), dtype=torch.float64 if dtype == "f64" else torch.float32,
+                        device="cuda:0")
+
+
+def gpu_vs_oracle_adjoint(shape, h, U0, dtype, bc=(0, 0, 0), step=3, **kw):
+    s, oc = pair(shape, h, bc, dtype, **kw)
+    Uin = as_input(U0, dtype)
+    dt = 0.6 * oracle.cfl_dt(oc, Uin)
+    lam = np.random.default_rng(5).standard_normal(Uin.shape)
+    lam_in = as_input(lam, dtype)
+    nvec = oracle.ou_modes(oc.ou_kmin, oc.ou_kmax) if oc.flags & oracle.SRC_FORCING else \
+        np.zeros((0, 3), np.int32)
+    ahat = oracle.ou_init(oc, nvec) if len(nvec) else np.zeros(6)
+    phi = np.zeros(shape)
+    ref = oracle.step_vjp(oc, Uin, dt, step, nvec, ahat, phi, lam_in)
+    got = s.adjoint_step(torch_dev(Uin, dtype), dt, step, torch_dev(lam_in, dtype),
+                         ou_ahat=ahat if len(nvec) else None).cpu().numpy()
+    return got, ref
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (1, 0, 0)])
+def test_adjoint_hydro_ragged(dtype, bc):
+    shape = (9, 11, 70)
+    U0 = wl.random_state(shape, seed=31, vmax=0.7)
+    got, ref = gpu_vs_oracle_adjoint(shape, (1 / 70, 1 / 11, 1 / 9), U0, dtype, bc)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_first_order(dtype):
+    shape = (8, 9, 17)
+    U0 = wl.random_state(shape, seed=32)
+    got, ref = gpu_vs_oracle_adjoint(shape, (1 / 17, 1 / 9, 1 / 8), U0, dtype,
+                                     limiter=oracle.LIM_NONE)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_forcing_cooling(dtype):
+    shape = (12, 14, 66)
+    U0 = wl.random_state(shape, seed=33, vmax=0.5)
+    got, ref = gpu_vs_oracle_adjoint(shape, (1 / 66, 1 / 14, 1 / 12), U0, dtype,
+                                     flags=oracle.SRC_FORCING | oracle.SRC_COOLING, ou_seed=4)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_gravity_cooling(dtype):
+    n = 16
+    U0 = wl.grf_density_state(n, seed=5)
+    U0[1:4] += 0.05 * np.random.default_rng(6).standard_normal((3, n, n, n)) * U0[0]
+    got, ref = gpu_vs_oracle_adjoint((n, n, n), (1 / n,) * 3, U0, dtype,
+                                     flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING,
+                                     grav_G=wl.JEANS_G, mg_tol=0.0, mg_max_cycles=12)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 32), (3, 2, 5), (1, 4, 4)])
+def test_adjoint_small_shapes(shape):
+    U0 = wl.random_state(shape, seed=34, vmax=0.5)
+    h = tuple(1.0 / n for n in shape[::-1])
+    got, ref = gpu_vs_oracle_adjoint(shape, h, U0, "f64")
+    assert rel_err(got, ref) < 1e-12
+
+
+def oracle_rollout_vjp(oc, U0, dts, lam):
+    """Chain of oracle step adjoints over the recorded run."""
+    nvec = oracle.ou_modes(oc.ou_kmin, oc.ou_kmax) if oc.flags & oracle.SRC_FORCING else \
+        np.zeros((0, 3), np.int32)
+    sim = oracle.Simulation(oc, U0)
+    states = []
+    for dt in dts:
+        states.append((sim.U.copy(), sim.ahat.copy(), sim.phi.copy(), sim.step_index))
+        sim.advance(1, dt)
+    for (U, ahat, phi, k), dt in zip(reversed(states), reversed(list(dts))):
+        lam = oracle.step_vjp(oc, U, dt, k, nvec, ahat, phi, lam)
+    return sim.U, lam
+
+
+@pytest.mark.parametrize("flags", [0, oracle.SRC_FORCING | oracle.SRC_COOLING])
+def test_rollout_gradient_and_checkpoint_invariance(flags):
+    import torch
+
+    shape = (10, 12, 20)
+    h = (1 / 20, 1 / 12, 1 / 10)
+    U0 = wl.random_state(shape, seed=35, vmax=0.5)
+    nsteps = 7
+    grads = {}
+    for K in (1, 3, nsteps):
+        s, oc = pair(shape, h, dtype="f64", flags=flags)
+        Uf, dts, cks = ro.rollout_forward(s, torch_dev(U0, "f64"), nsteps, K)
+        lam = torch_dev(np.ones_like(U0) * 0.5 + np.arange(U0.size).reshape(U0.shape) % 7, "f64")
+        grads[K] = ro.rollout_backward(s, cks, dts, K, lam).cpu().numpy()
+    assert np.array_equal(grads[1], grads[3]) and np.array_equal(grads[1], grads[nsteps])
+    Uref, gref = oracle_rollout_vjp(oc, U0, dts, lam.cpu().numpy())
+    assert rel_err(Uf.cpu().numpy(), Uref) < 1e-12
+    assert rel_err(grads[1], gref) < 1e-11
+
+
+def test_autograd_function():
+    import torch
+
+    shape = (8, 8, 16)
+    U0 = wl.random_state(shape, seed=36, vmax=0.4)
+    s, oc = pair(shape, (1 / 16, 1 / 8, 1 / 8), dtype="f64")
+    HydroRollout = ro.make_rollout_function()
+    x = torch_dev(U0, "f64").requires_grad_(True)
+    y = HydroRollout.apply(x, s, 4, 2, None)
+    loss = 0.5 * (y[0] ** 2).sum()
+    loss.backward()
+    _, gref = oracle_rollout_vjp(oc, U0, oracle.Simulation(oc, U0).advance(4).dts,
+                                 np.concatenate([y[0:1].detach().cpu().numpy(),
+                                                 np.zeros((4,) + shape)]))
+    assert rel_err(x.grad.cpu().numpy(), gref) < 1e-11

@@ -1,0 +1,229 @@
+"""GPU parity of the learned state corrector (mh_corr_*) against the oracle
+of oracle/corrector.py, which takes the same bf16-rounded operands at the same
+points and accumulates in float64.
+
+Layer by layer, each GPU layer is compared with the oracle layer fed the GPU's
+own input activations, so every comparison sees one layer's arithmetic only:
+fp32-accumulated products within 1e-5 of the fp64 sum (relative to the
+layer's largest value), and bf16-rounded activations equal except for
+elements that sit on a rounding boundary, which may differ by one bf16 ulp
+(at most 0.1 % of them).  The end-to-end correction and the gradients, where
+such flips propagate, are compared in norm."""
+import numpy as np
+import pytest
+
+import oracle.corrector as oc
+import paper_2512_13403_amd as mh
+import workloads as wl
+from parity import as_input
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 5.0 / 3.0
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield
+
+
+def torch_dev(a, dtype):
+    import torch
+
+    return torch.tensor(np.asarray(a), dtype=torch.float64 if dtype == "f64" else torch.float32,
+                        device="cuda:0")
+
+
+def batch_state(n, batch, seed, dtype):
+    U = np.stack([wl.smooth_random_state((n, n, n), seed=seed + b, kmax=4) for b in range(batch)])
+    return as_input(U, dtype)
+
+
+def stats(U):
+    mean = U.mean(axis=(0, 2, 3, 4))
+    std = U.std(axis=(0, 2, 3, 4)) + 1e-3
+    return mean, std
+
+
+def params(seed=1, bias=0.1):
+    theta = wl.corrector_init_params(seed=seed, out_scale=1.0)
+    rng = np.random.default_rng(seed + 100)
+    p = oc.unpack(theta)
+    for k in ("b1", "b2", "b3"):
+        p[k] = bias * rng.standard_normal(p[k].shape)
+    return oc.pack(p).astype(np.float32).astype(np.float64)
+
+
+def make(n, batch, dtype, U, scale=(1e-2,) * 5, loss_w=(4.0, 1.0, 1.0, 1.0, 1.0),
+         fallback_frac=1e-3, theta=None):
+    mean, std = stats(U)
+    d = mh.corr_desc(n, batch, dtype, GAMMA, mean, std, scale, loss_w, 1e-6, fallback_frac)
+    c = mh.Corrector(d)
+    th = params() if theta is None else theta
+    c.set_params(th)
+    return c, th, mean, std, np.asarray(scale)
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def check_bf16_activation(got, ref):
+    """Equal except one-ulp flips on at most 0.1 % of the elements."""
+    diff = got != ref
+    assert diff.mean() <= 1e-3, diff.mean()
+    if diff.any():
+        assert np.all(np.abs(got[diff] - ref[diff]) <= 2.0 ** -7 * np.abs(ref[diff]) + 1e-30)
+
+
+def to_oracle(a, batch, n):
+    return a.reshape(batch, n, n, n, a.shape[-1])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n,batch", [(16, 2), (32, 1)])
+def test_forward_layers(dtype, n, batch):
+    U = batch_state(n, batch, 10, dtype)
+    c, th, mean, std, scale = make(n, batch, dtype, U)
+    out, nfl, fb = c.apply(torch_dev(U, dtype))
+    out = out.cpu().numpy()
+    p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
+    # network input: bitwise
+    x0 = c.activation(0)
+    xref = oc.bf16_round((np.moveaxis(U, 1, -1) - mean) / std).reshape(-1, 5)
+    assert np.array_equal(x0[:, :5], xref) and not x0[:, 5:].any()
+    # each layer from the GPU's own input activations
+    z1 = c.activation(1)
+    assert rel_inf(z1, oc.conv3(to_oracle(x0[:, :5], batch, n), p["W1"], p["b1"]).reshape(-1, 32)) < 1e-5
+    h1 = c.activation(2)
+    check_bf16_activation(h1, oc.bf16_round(oc.gelu(z1)))
+    z2 = c.activation(3)
+    assert rel_inf(z2, oc.conv3(to_oracle(h1, batch, n), p["W2"], p["b2"]).reshape(-1, 32)) < 1e-5
+    h2 = c.activation(4)
+    check_bf16_activation(h2, oc.bf16_round(oc.gelu(z2)))
+    y = c.activation(5)
+    assert not y[:, 5:].any()
+    yref = oc.conv3(to_oracle(h2, batch, n), p["W3"], p["b3"]).reshape(-1, 5)
+    assert rel_inf(y[:, :5], yref) < 1e-5
+    # residual update from the GPU's y, then the floor (none needed here)
+    Uc = U + np.moveaxis(to_oracle(y[:, :5], batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
+    ref, nref, bad = oc.floor_and_check(U, Uc, GAMMA)
+    assert nfl == nref == 0 and not fb and not bad
+    tol = 1e-15 if dtype == "f64" else 2e-7
+    assert rel_inf(out, ref) < tol
+    # end to end against the oracle's own forward: the correction agrees in norm
+    oref, _ = oc.forward(U, th, mean, std, scale)
+    dc, dr = out - U, oref - U
+    assert np.linalg.norm(dc - dr) / np.linalg.norm(dr) < 1e-2
+
+
+def test_batch_members_are_independent():
+    n = 16
+    U = batch_state(n, 2, 20, "f32")
+    c2, th, mean, std, scale = make(n, 2, "f32", U)
+    out2 = c2.apply(torch_dev(U, "f32"))[0].cpu().numpy()
+    for b in range(2):
+        d = mh.corr_desc(n, 1, "f32", GAMMA, mean, std, scale, (1.0,) * 5, 1e-6, 1e-3)
+        c1 = mh.Corrector(d)
+        c1.set_params(th)
+        out1 = c1.apply(torch_dev(U[b:b + 1], "f32"))[0].cpu().numpy()
+        assert np.array_equal(out1[0], out2[b])
+
+
+def oracle_grad_from_gpu(c, U, T, th, std, scale, loss_w, batch, n):
+    """The oracle's backward pass on the GPU's forward activations."""
+    p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
+    y = c.activation(5)[:, :5]
+    cache = dict(x=to_oracle(c.activation(0)[:, :5], batch, n),
+                 z1=to_oracle(c.activation(1), batch, n), h1=to_oracle(c.activation(2), batch, n),
+                 z2=to_oracle(c.activation(3), batch, n), h2=to_oracle(c.activation(4), batch, n),
+                 y=to_oracle(y, batch, n), p=p, rd=oc.bf16_round)
+    Uc = U + np.moveaxis(to_oracle(y, batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
+    L, gUc = oc.loss_and_grad_y(Uc, T, loss_w, std)
+    return L, oc.backward(gUc, cache, scale)
+
+
+BLOCKS = [("W1", 0, 4320), ("b1", 4320, 4352), ("W2", 4352, 32000), ("b2", 32000, 32032),
+          ("W3", 32032, 36352), ("b3", 36352, 36357)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_loss_and_gradient(dtype):
+    n, batch = 16, 2
+    U = batch_state(n, batch, 30, dtype)
+    T = as_input(U + 0.02 * batch_state(n, batch, 40, "f64"), dtype)
+    loss_w = np.array([4.0, 1.0, 1.0, 1.0, 1.0])
+    c, th, mean, std, scale = make(n, batch, dtype, U, scale=(5e-2,) * 5, loss_w=loss_w)
+    Ud, Td = torch_dev(U, dtype), torch_dev(T, dtype)
+    L, g = c.loss_grad(Ud, Td)
+    L2, g2 = c.loss_grad(Ud, Td)
+    assert L == L2 and np.array_equal(g, g2)  # deterministic reductions
+    Lref, gref = oracle_grad_from_gpu(c, U, T, th, std, scale, loss_w, batch, n)
+    assert L == pytest.approx(Lref, rel=1e-9)
+    for name, a, b in BLOCKS:
+        tol = 1e-4 if name in ("W3", "b3") else 2e-3
+        err = np.linalg.norm(g[a:b] - gref[a:b]) / np.linalg.norm(gref[a:b])
+        assert err < tol, (name, err)
+    # against the oracle's own forward + backward: same direction
+    Uc, cache = oc.forward(U, th, mean, std, scale)
+    _, gUc = oc.loss_and_grad_y(Uc, T, loss_w, std)
+    gown = oc.backward(gUc, cache, scale)
+    cos = float(g @ gown / (np.linalg.norm(g) * np.linalg.norm(gown)))
+    assert cos > 0.9999
+
+
+def test_adam_step_and_training_reduces_loss():
+    n, batch = 16, 2
+    U = batch_state(n, batch, 50, "f32")
+    T = as_input(U + 0.02 * batch_state(n, batch, 60, "f64"), "f32")
+    c, th, mean, std, scale = make(n, batch, "f32", U, scale=(5e-2,) * 5)
+    Ud, Td = torch_dev(U, "f32"), torch_dev(T, "f32")
+    L0, g = c.loss_grad(Ud, Td)
+    lr = 1e-3
+    L0b = c.train_step(Ud, Td, lr)
+    assert L0b == L0
+    ref, _, _ = oc.adam(th, np.zeros_like(th), np.zeros_like(th), g.astype(np.float64), 1, lr)
+    assert np.abs(c.params() - ref).max() < 1e-6
+    losses = [c.train_step(Ud, Td, lr) for _ in range(30)]
+    assert losses[-1] < 0.5 * L0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_floor_and_fallback(dtype):
+    n, batch = 16, 2
+    U = batch_state(n, batch, 70, dtype)
+    scale = np.array([2.0, 0.0, 0.0, 0.0, 2.0])
+    # no fallback: the floored state against the oracle floor on the GPU's y
+    c, th, mean, std, _ = make(n, batch, dtype, U, scale=scale, fallback_frac=1.0)
+    out, nfl, fb = c.apply(torch_dev(U, dtype))
+    y = c.activation(5)[:, :5]
+    Uc = U + np.moveaxis(to_oracle(y, batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
+    Uc = as_input(Uc, dtype)
+    ref, nref, bad = oc.floor_and_check(U, Uc, GAMMA)
+    assert nref > 0 and nfl == nref and not fb and not bad
+    tol = 1e-15 if dtype == "f64" else 2e-7
+    assert rel_inf(out.cpu().numpy(), ref) < tol
+    # too many floored cells: the plain state comes back unchanged
+    c2, *_ = make(n, batch, dtype, U, scale=scale, fallback_frac=1e-3, theta=th)
+    out2, nfl2, fb2 = c2.apply(torch_dev(U, dtype))
+    assert fb2 and nfl2 == nref and np.array_equal(out2.cpu().numpy(), U)
+    # non-finite parameters: fallback as well
+    bad_th = th.copy()
+    bad_th[-1] = np.nan
+    c3, *_ = make(n, batch, dtype, U, fallback_frac=1.0, theta=bad_th)
+    out3, _, fb3 = c3.apply(torch_dev(U, dtype))
+    assert fb3 and np.array_equal(out3.cpu().numpy(), U)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("r", [2, 4])
+def test_block_average(dtype, r):
+    nf = 32
+    F = as_input(wl.random_state((nf, nf, nf), seed=80), dtype)
+    got = mh.block_average(torch_dev(F, dtype), r).cpu().numpy()
+    nc = nf // r
+    ref = F.reshape(5, nc, r, nc, r, nc, r).mean(axis=(2, 4, 6))
+    assert rel_inf(got, ref) < (1e-15 if dtype == "f64" else 2e-7)
+    # conservation: the coarse totals times r^3 are the fine totals
+    assert np.allclose(got.sum(axis=(1, 2, 3)) * r ** 3, F.sum(axis=(1, 2, 3)), rtol=1e-6)

@@ -95,3 +95,43 @@ def test_solver_refuses_without_gpu():
     g = mh.grid_desc((8, 8, 8), (1 / 8,) * 3)
     with pytest.raises(RuntimeError):
         mh.Solver(g)
+
+
+def corr_ws(d):
+    n = ctypes.c_size_t(0)
+    st = mh.load_library().mh_corr_query_workspace(ctypes.byref(d), ctypes.byref(n))
+    return st, n.value
+
+
+def test_corrector_workspace_and_validation():
+    st, n = corr_ws(mh.corr_desc(64, 2, "f32"))
+    cells = 2 * 64 ** 3
+    # activations alone: x, h1, h2, dY, dZ (bf16, 32 ch) + z1, z2 (fp32) + y
+    assert st == mh.OK and n >= cells * (32 * 2 * 6 + 32 * 4 * 2 + 16 * 4)
+    bad = [
+        (lambda d: setattr(d, "n", 24), mh.E_SHAPE),
+        (lambda d: setattr(d, "n", 8), mh.E_SHAPE),
+        (lambda d: setattr(d, "batch", 0), mh.E_SHAPE),
+        (lambda d: setattr(d, "dtype", 3), mh.E_DTYPE),
+        (lambda d: setattr(d, "gamma", 0.5), mh.E_INVALID),
+        (lambda d: d.std.__setitem__(2, 0.0), mh.E_INVALID),
+        (lambda d: setattr(d, "floor_rel", -1.0), mh.E_INVALID),
+    ]
+    for mutate, status in bad:
+        d = mh.corr_desc(32, 1, "f64")
+        mutate(d)
+        assert corr_ws(d)[0] == status
+    lib = mh.load_library()
+    assert lib.mh_corr_query_workspace(None, None) == mh.E_INVALID
+    assert lib.mh_corr_apply(None, None, None, None, None) == mh.E_INVALID
+    assert lib.mh_corr_train_step(None, None, None, 1e-3, None) == mh.E_INVALID
+    assert lib.mh_block_average(None, 8, 2, None, mh.F32, None) == mh.E_INVALID
+    lib.mh_corr_destroy(None)
+
+
+def test_corrector_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        mh.Corrector(mh.corr_desc(16, 1))
