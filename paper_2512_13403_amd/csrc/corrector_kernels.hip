@@ -6,16 +6,18 @@
 // GELU(conv(h1)), y = conv(h2), U' = U + scale * y, with 3x3x3 periodic
 // cross-correlations of 5 -> 32 -> 32 -> 5 channels.
 //
-// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16: a wave
-// owns 16 consecutive cells along x (the MFMA rows) and 16 output channels per
-// tile (the MFMA columns); for each of the 27 taps it multiplies the 16 x 32
-// block of shifted input activations (bf16, channels contiguous: one 16-byte
-// load per lane) by the 32 x 16 weight block of that tap, accumulating in
-// fp32.  Activations are stored cell-major with 32 channels (the network input
-// is zero-padded from 5 to 32, the last layer's 5 outputs sit in 16).  The
-// same kernel serves the input-gradient pass: there the weights are packed
-// transposed with the taps mirrored, so reading at cell + off_tap applies the
-// transpose of the forward map.  Weight gradients are GEMMs over cells: one workgroup
+// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16.  A
+// workgroup stages a 16 x 4 x 4 block of cells plus its one-cell periodic halo
+// in LDS (bf16, 32 channels per cell, channels contiguous); each of its four
+// waves owns four rows of 16 cells along x (the MFMA rows) and all output
+// channels (the MFMA columns, 16 per tile).  For each of the 27 taps a wave
+// loads that tap's weight block once and multiplies it into its four rows,
+// whose shifted inputs it reads from LDS, accumulating in fp32.  Activations
+// are stored cell-major with 32 channels (the network input is zero-padded
+// from 5 to 32, the last layer's 5 outputs sit in 16).  The same kernel
+// serves the input-gradient pass: there the weights are packed transposed
+// with the taps mirrored, so reading at cell + off_tap applies the transpose
+// of the forward map.  Weight gradients are GEMMs over cells: one workgroup
 // per (tap, chunk of 4096 cells) writes a 32 x 32 partial product, and a
 // second kernel adds the chunks in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
@@ -45,64 +47,117 @@ __device__ __forceinline__ bf16x8 load8(const unsigned short* p) {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// GELU(z) = z Phi(z) with Phi(z) = erfc(-z / sqrt 2) / 2: the erfc form keeps
+// its relative accuracy for negative z, where 1 + erf(z / sqrt 2) cancels
 __device__ __forceinline__ float gelu(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+  return 0.5f * z * erfcf(-z * 0.70710678118654752f);
 }
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+  return 0.5f * erfcf(-z * 0.70710678118654752f) +
          z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 enum : int { EPI_GELU = 0, EPI_LINEAR = 1, EPI_GELU_BWD = 2, EPI_RAW = 3 };
 
-// out[cell][co] for COT output channels (16 or 32) from in[cell][32]; the tap
-// t reads in at cell + sign * off_t.  w: [27][COT][32] bf16.
+// Halo tile of the tiled convolution: 16 cells along x (the MFMA rows) by
+// CTY x CTZ rows in (y, z), with a one-cell periodic halo, staged in LDS.
+constexpr int CTX = 16, CTY = 4, CTZ = 4;
+constexpr int CHX = CTX + 2, CHY = CTY + 2, CHZ = CTZ + 2, CNH = CHX * CHY * CHZ;
+constexpr int CROWS = CTY * CTZ / 4;  // rows per wave (4 waves)
+
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
+
+// 16-byte channel chunk c of halo cell (hx, ...) sits in slot c ^ ((hx >> 2) & 3):
+// the 16 lanes of a row read 16 consecutive hx and so 16 distinct bank groups.
+__device__ __forceinline__ int cslot(int h, int hx, int c) { return h * 4 + (c ^ ((hx >> 2) & 3)); }
+
+// out[cell][co] for COT output channels (16 or 32) from in[cell][32] (bf16):
+// per tap, the wave's CROWS rows of 16 cells read their shifted inputs from
+// the LDS tile and multiply them by the tap's 32 x COT weight block (bf16
+// [27][COT][32]), loaded once per tap and prefetched one tap ahead.
 template <int COT, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__ in,
                                               const unsigned short* __restrict__ w,
                                               const float* __restrict__ bias, int nbias, int n,
-                                              long long cells, int sign, const float* __restrict__ zin,
+                                              const float* __restrict__ zin,
                                               float* __restrict__ fout,
                                               unsigned short* __restrict__ hout) {
+  __shared__ u32x4 tile[CNH * 4];
+  const int ntx = n / CTX, nty = n / CTY, ntz = n / CTZ;
+  int t = blockIdx.x;
+  const int bx = t % ntx;
+  t /= ntx;
+  const int by = t % nty;
+  t /= nty;
+  const int bz = t % ntz;
+  const long long b = t / ntz;
+  const int x0 = bx * CTX, y0 = by * CTY, z0 = bz * CTZ;
+  const long long base = b * n * n * (long long)n;
+  for (int i = threadIdx.x; i < CNH * 4; i += 256) {
+    const int h = i >> 2, c = i & 3;
+    const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
+    const long long src = base + ((long long)wrap(z0 - 1 + hz, n) * n + wrap(y0 - 1 + hy, n)) * n +
+                          wrap(x0 - 1 + hx, n);
+    u32x4 v;
+    __builtin_memcpy(&v, in + src * 32 + c * 8, 16);
+    tile[cslot(h, hx, c)] = v;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long cell0 = ((long long)blockIdx.x * 4 + wave) * 16;
-  if (cell0 >= cells) return;
-  const long long n3 = (long long)n * n * n;
-  const long long b = cell0 / n3, r = cell0 % n3;
-  const int z = (int)(r / ((long long)n * n)), y = (int)((r / n) % n), x0 = (int)(r % n);
   const int row = lane & 15, grp = lane >> 4;
-  f32x4 acc[COT / 16];
+  f32x4 acc[CROWS][COT / 16];
 #pragma unroll
-  for (int t = 0; t < COT / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < CROWS; ++r)
+#pragma unroll
+    for (int nt = 0; nt < COT / 16; ++nt) acc[r][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 bw[COT / 16], bn[COT / 16];
+#pragma unroll
+  for (int nt = 0; nt < COT / 16; ++nt) bn[nt] = load8(w + ((nt * 16 + row) * 32 + 8 * grp));
   for (int tap = 0; tap < 27; ++tap) {
-    const int dx = sign * (tap % 3 - 1), dy = sign * ((tap / 3) % 3 - 1), dz = sign * (tap / 9 - 1);
-    const long long src = b * n3 + ((long long)wrap(z + dz, n) * n + wrap(y + dy, n)) * n +
-                          wrap(x0 + row + dx, n);
-    const bf16x8 a = load8(in + src * 32 + 8 * grp);
 #pragma unroll
-    for (int nt = 0; nt < COT / 16; ++nt) {
-      const bf16x8 bv = load8(w + ((long long)(tap * COT + nt * 16 + row) * 32 + 8 * grp));
-      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[nt], 0, 0, 0);
+    for (int nt = 0; nt < COT / 16; ++nt) bw[nt] = bn[nt];
+    if (tap + 1 < 27) {
+#pragma unroll
+      for (int nt = 0; nt < COT / 16; ++nt)
+        bn[nt] = load8(w + (((tap + 1) * COT + nt * 16 + row) * 32 + 8 * grp));
+    }
+    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+    const int hx = row + 1 + dx;
+#pragma unroll
+    for (int r = 0; r < CROWS; ++r) {
+      const int j = wave * CROWS + r;
+      const int hy = j % CTY + 1 + dy, hz = j / CTY + 1 + dz;
+      const u32x4 raw = tile[cslot((hz * CHY + hy) * CHX + hx, hx, grp)];
+      bf16x8 a;
+      __builtin_memcpy(&a, &raw, 16);
+#pragma unroll
+      for (int nt = 0; nt < COT / 16; ++nt)
+        acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nt], acc[r][nt], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int nt = 0; nt < COT / 16; ++nt) {
+  for (int r = 0; r < CROWS; ++r) {
+    const int j = wave * CROWS + r;
+    const long long rowcell = base + ((long long)(z0 + j / CTY) * n + (y0 + j % CTY)) * n + x0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long long cell = cell0 + 4 * grp + q;
-      const int co = nt * 16 + row;
-      const float v = acc[nt][q];
-      const long long o = cell * COT + co;
-      if (EPI == EPI_GELU) {
-        const float zz = v + bias[co];
-        if (fout) fout[o] = zz;
-        hout[o] = f2bf(gelu(zz));
-      } else if (EPI == EPI_LINEAR) {
-        fout[o] = v + (co < nbias ? bias[co] : 0.f);
-      } else if (EPI == EPI_GELU_BWD) {
-        hout[o] = f2bf(v * gelu_grad(zin[o]));
-      } else {
-        fout[o] = v;
+    for (int nt = 0; nt < COT / 16; ++nt) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long cell = rowcell + 4 * grp + q;
+        const int co = nt * 16 + row;
+        const float v = acc[r][nt][q];
+        const long long o = cell * COT + co;
+        if (EPI == EPI_GELU) {
+          const float zz = v + bias[co];
+          if (fout) fout[o] = zz;
+          hout[o] = f2bf(gelu(zz));
+        } else if (EPI == EPI_LINEAR) {
+          fout[o] = v + (co < nbias ? bias[co] : 0.f);
+        } else if (EPI == EPI_GELU_BWD) {
+          hout[o] = f2bf(v * gelu_grad(zin[o]));
+        } else {
+          fout[o] = v;
+        }
       }
     }
   }
@@ -408,6 +463,10 @@ __global__ __launch_bounds__(256) void k_block_average(const T* __restrict__ fin
 
 inline unsigned blocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
+inline unsigned conv_grid(int n, int batch) {
+  return (unsigned)((long long)(n / CTX) * (n / CTY) * (n / CTZ) * batch);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -426,15 +485,15 @@ template <typename T>
 hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
                         T* out, hipStream_t s) {
   const long long cells = (long long)batch * n * n * n;
-  const unsigned seg_blocks = blocks(cells / 16, 4);
+  const unsigned conv_blocks = conv_grid(n, batch);
   hipLaunchKernelGGL((k_standardize<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, n, cells, st,
                      B.x0);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(seg_blocks), dim3(256), 0, s, B.x0, B.w1,
-                     B.theta + CORR_OFF_B1, 32, n, cells, 1, (const float*)nullptr, B.z1, B.h1);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(seg_blocks), dim3(256), 0, s, B.h1, B.w2,
-                     B.theta + CORR_OFF_B2, 32, n, cells, 1, (const float*)nullptr, B.z2, B.h2);
-  hipLaunchKernelGGL((k_conv<16, EPI_LINEAR>), dim3(seg_blocks), dim3(256), 0, s, B.h2, B.w3,
-                     B.theta + CORR_OFF_B3, 5, n, cells, 1, (const float*)nullptr, B.y,
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_blocks), dim3(256), 0, s, B.x0, B.w1,
+                     B.theta + CORR_OFF_B1, 32, n, (const float*)nullptr, B.z1, B.h1);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_blocks), dim3(256), 0, s, B.h1, B.w2,
+                     B.theta + CORR_OFF_B2, 32, n, (const float*)nullptr, B.z2, B.h2);
+  hipLaunchKernelGGL((k_conv<16, EPI_LINEAR>), dim3(conv_blocks), dim3(256), 0, s, B.h2, B.w3,
+                     B.theta + CORR_OFF_B3, 5, n, (const float*)nullptr, B.y,
                      (unsigned short*)nullptr);
   if (out)
     hipLaunchKernelGGL((k_residual<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, B.y, n, cells,
@@ -458,7 +517,7 @@ template <typename T>
 hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch,
                               const T* U, const T* tgt, hipStream_t s) {
   const long long cells = (long long)batch * n * n * n;
-  const unsigned seg_blocks = blocks(cells / 16, 4);
+  const unsigned conv_blocks = conv_grid(n, batch);
   const unsigned lb = blocks(cells, 256);
   hipLaunchKernelGGL((k_loss<T>), dim3(lb), dim3(256), 0, s, U, B.y, tgt, n, cells, st, B.dpart,
                      B.dy16);
@@ -475,8 +534,8 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 16, nchunk, 5,
                      B.grad + CORR_OFF_B3);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(seg_blocks), dim3(256), 0, s, B.dy32, B.w3t,
-                     (const float*)nullptr, 0, n, cells, 1, B.z2, (float*)nullptr, B.dz2);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dy32, B.w3t,
+                     (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2);
   // layer 2
   hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz2, B.h1, n, cells, chunk,
                      B.wpart);
@@ -486,8 +545,8 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
                      B.grad + CORR_OFF_B2);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(seg_blocks), dim3(256), 0, s, B.dz2, B.w2t,
-                     (const float*)nullptr, 0, n, cells, 1, B.z1, (float*)nullptr, B.dz1);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dz2, B.w2t,
+                     (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1);
   // layer 1
   hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz1, B.x0, n, cells, chunk,
                      B.wpart);

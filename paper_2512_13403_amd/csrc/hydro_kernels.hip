@@ -20,6 +20,14 @@
 // plane once.  Every face flux is computed exactly once per tile: x faces by
 // the thread on their left (plus the tile's left edge), y faces likewise, z
 // faces by the column's thread, carried from one plane to the next.
+// Floating-point contraction is off in this file and every fused multiply-add
+// is written out: the compiler may not fuse a product into a sum at one call
+// site of the face flux and not at another, so each face gets bit-identical
+// arithmetic wherever it is computed (interior faces, the tile's edge faces,
+// the first z face of a column), and a state that is uniform along an axis
+// stays exactly uniform.
+#pragma clang fp contract(off)
+
 #include "mh_device.h"
 #include "mh_launch.h"
 
@@ -66,11 +74,11 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   const T rr = wr[0], ur = wr[vn], pr = wr[4];
   const T cl = sound_speed(gamma * pl, rl), cr = sound_speed(gamma * pr, rr);
   const T SL = fmin(ul - cl, ur - cr), SR = fmax(ul + cl, ur + cr);
-  const T kel = T(0.5) * rl * (ul * ul + wl[t1] * wl[t1] + wl[t2] * wl[t2]);
-  const T ker = T(0.5) * rr * (ur * ur + wr[t1] * wr[t1] + wr[t2] * wr[t2]);
-  const T El = pl * gm1inv + kel, Er = pr * gm1inv + ker;
+  const T kel = (T(0.5) * rl) * fmad(ul, ul, fmad(wl[t1], wl[t1], wl[t2] * wl[t2]));
+  const T ker = (T(0.5) * rr) * fmad(ur, ur, fmad(wr[t1], wr[t1], wr[t2] * wr[t2]));
+  const T El = fmad(pl, gm1inv, kel), Er = fmad(pr, gm1inv, ker);
   const T dl = rl * (SL - ul), dr = rr * (SR - ur);
-  const T sstar = (pr - pl + ul * dl - ur * dr) * dev_rcp(dl - dr);
+  const T sstar = fmad(-ur, dr, fmad(ul, dl, pr - pl)) * dev_rcp(dl - dr);
   // side: the oracle's region order (0 <= S_L, 0 <= S*, 0 < S_R, else R)
   const bool left = (SL >= T(0)) || (sstar >= T(0));
   const T rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
@@ -78,16 +86,16 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   const T EK = left ? El : Er, SK = left ? SL : SR, dK = left ? dl : dr;
   const bool fan = left ? (SL < T(0)) : (SR > T(0));
   const T mK = rK * uK;
-  const T FK0 = mK, FK1 = mK * uK + pK, FK2 = mK * aK, FK3 = mK * bK, FK4 = uK * (EK + pK);
+  const T FK0 = mK, FK1 = fmad(mK, uK, pK), FK2 = mK * aK, FK3 = mK * bK, FK4 = uK * (EK + pK);
   const T q = dev_rcp(SK - sstar);
   const T qd = q * dK;
   const T s0 = qd, s1 = qd * sstar, s2 = qd * aK, s3 = qd * bK;
-  const T s4 = q * ((SK - uK) * EK + (sstar - uK) * (dK * sstar + pK));
-  const T f0 = FK0 + SK * (s0 - rK);
-  const T f1 = FK1 + SK * (s1 - mK);
-  const T f2 = FK2 + SK * (s2 - rK * aK);
-  const T f3 = FK3 + SK * (s3 - rK * bK);
-  const T f4 = FK4 + SK * (s4 - EK);
+  const T s4 = q * fmad(SK - uK, EK, (sstar - uK) * fmad(dK, sstar, pK));
+  const T f0 = fmad(SK, s0 - rK, FK0);
+  const T f1 = fmad(SK, s1 - mK, FK1);
+  const T f2 = fmad(SK, fmad(-rK, aK, s2), FK2);
+  const T f3 = fmad(SK, fmad(-rK, bK, s3), FK3);
+  const T f4 = fmad(SK, s4 - EK, FK4);
   F[0] = fan ? f0 : FK0;
   F[vn] = fan ? f1 : FK1;
   F[t1] = fan ? f2 : FK2;
@@ -103,11 +111,28 @@ __device__ __forceinline__ void face_flux(const T (&wm)[5], const T (&w0)[5], co
   T wl[5], wr[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
-    wl[f] = w0[f] + T(0.5) * limited_slope<T, LIM>(wm[f], w0[f], w1[f]);
-    wr[f] = w1[f] - T(0.5) * limited_slope<T, LIM>(w0[f], w1[f], w2[f]);
+    wl[f] = fmad(T(0.5), limited_slope<T, LIM>(wm[f], w0[f], w1[f]), w0[f]);
+    wr[f] = fmad(T(-0.5), limited_slope<T, LIM>(w0[f], w1[f], w2[f]), w1[f]);
   }
   hllc_flux<T, N>(wl, wr, gamma, gm1inv, F);
 }
+
+// the same flux from precomputed limited slopes d0 of W_i and d1 of W_{i+1}
+template <typename T, int N>
+__device__ __forceinline__ void face_flux_sl(const T (&w0)[5], const T (&d0)[5], const T (&w1)[5],
+                                             const T (&d1)[5], T gamma, T gm1inv, T (&F)[5]) {
+  T wl[5], wr[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    wl[f] = fmad(T(0.5), d0[f], w0[f]);
+    wr[f] = fmad(T(-0.5), d1[f], w1[f]);
+  }
+  hllc_flux<T, N>(wl, wr, gamma, gm1inv, F);
+}
+
+// Each row of the tile (fixed ty) is exactly one wave, so the lower-edge
+// faces below can be given to whole waves.
+static_assert(TX == 64 && TY <= TX, "one wave per tile row");
 
 template <typename T, int STAGE, int LIM, bool FORCE, bool COOL>
 __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(const StageArgs<T> a) {
@@ -183,10 +208,11 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
   }
   int pq_slot = 0;
 
-  // z ring: W at z-1, z, z+1, z+2; U at z, z+1, z+2; z-flux at z-1/2
-  T w[4][5], u[3][5], fzm[5];
+  // z ring: W at z-1, z, z+1, z+2; U at z, z+1, z+2; z-flux at z-1/2; the
+  // limited z slope of W at z (each cell's slope is computed once)
+  T w[4][5], u[3][5], fzm[5], dz1[5];
   {
-    T tmp[5], wz[5];
+    T tmp[5], wz[5], dz0[5];
     load_cell(a.uin, N, (long long)bc_map(z0 - 2, a.nz, a.bcz) * plane + col, tmp);
     to_prim(tmp, gm1, wz);
     load_cell(a.uin, N, (long long)bc_map(z0 - 1, a.nz, a.bcz) * plane + col, tmp);
@@ -195,7 +221,12 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
     to_prim(u[0], gm1, w[1]);
     load_cell(a.uin, N, (long long)bc_map(z0 + 1, a.nz, a.bcz) * plane + col, u[1]);
     to_prim(u[1], gm1, w[2]);
-    face_flux<T, LIM, 2>(wz, w[0], w[1], w[2], gamma, gm1inv, fzm);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      dz0[f] = limited_slope<T, LIM>(wz[f], w[0][f], w[1][f]);
+      dz1[f] = limited_slope<T, LIM>(w[0][f], w[1][f], w[2][f]);
+    }
+    face_flux_sl<T, 2>(w[0], dz0, w[1], dz1, gamma, gm1inv, fzm);
   }
 
   T smax = T(0);
@@ -247,18 +278,6 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, F);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sFx[f][ty][tx + 1] = F[f];
-      if (tx == 0) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          c0[f] = sW[f][ty + 2][0];
-          c1[f] = sW[f][ty + 2][1];
-          c2[f] = sW[f][ty + 2][2];
-          c3[f] = sW[f][ty + 2][3];
-        }
-        face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, F);
-#pragma unroll
-        for (int f = 0; f < 5; ++f) sFx[f][ty][0] = F[f];
-      }
       // y face at y + 1/2
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
@@ -270,6 +289,9 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, F);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sFy[f][ty + 1][tx] = F[f];
+      // the tile's lower-edge faces: the TX y faces at y0 - 1/2 by the wave
+      // of row 0, the TY x faces at x0 - 1/2 by lanes of the wave of row 1,
+      // so two waves (not every wave) carry the extra flux
       if (ty == 0) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
@@ -281,19 +303,32 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, F);
 #pragma unroll
         for (int f = 0; f < 5; ++f) sFy[f][0][tx] = F[f];
+      } else if (ty == 1 && tx < TY) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          c0[f] = sW[f][tx + 2][0];
+          c1[f] = sW[f][tx + 2][1];
+          c2[f] = sW[f][tx + 2][2];
+          c3[f] = sW[f][tx + 2][3];
+        }
+        face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, F);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) sFx[f][tx][0] = F[f];
       }
     }
-    T fzp[5];
-    face_flux<T, LIM, 2>(w[0], w[1], w[2], w[3], gamma, gm1inv, fzp);
+    T fzp[5], dz2[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) dz2[f] = limited_slope<T, LIM>(w[1][f], w[2][f], w[3][f]);
+    face_flux_sl<T, 2>(w[1], dz1, w[2], dz2, gamma, gm1inv, fzp);
     __syncthreads();
 
     T un[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       T L = -(sFx[f][ty][tx + 1] - sFx[f][ty][tx]) * a.ihx;
-      L -= (sFy[f][ty + 1][tx] - sFy[f][ty][tx]) * a.ihy;
-      L -= (fzp[f] - fzm[f]) * a.ihz;
-      un[f] = u[0][f] + dt * L;
+      L = fmad(-(sFy[f][ty + 1][tx] - sFy[f][ty][tx]), a.ihy, L);
+      L = fmad(-(fzp[f] - fzm[f]), a.ihz, L);
+      un[f] = fmad(dt, L, u[0][f]);
     }
     const long long q = (long long)z * plane + col;
     if (STAGE == 1) {
@@ -309,7 +344,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         for (int f = 0; f < 5; ++f) u0[f] = u[0][f];
       }
 #pragma unroll
-      for (int f = 0; f < 5; ++f) un[f] = T(0.5) * u0[f] + T(0.5) * un[f];
+      for (int f = 0; f < 5; ++f) un[f] = fmad(T(0.5), u0[f], T(0.5) * un[f]);
 
       if (FORCE) {
         // a(x) = scale sum_m 2 Re(ahat_m exp(2 pi i n_m . x / L)) at the cell
@@ -323,21 +358,22 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         for (int n = 1; n <= a.ou_R; ++n) {
           const T xr = sX[n][0][tx], xi = sX[n][1][tx];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) acc[c] += xr * pq[6 * n + 2 * c] - xi * pq[6 * n + 2 * c + 1];
+          for (int c = 0; c < 3; ++c)
+            acc[c] += fmad(xr, pq[6 * n + 2 * c], -xi * pq[6 * n + 2 * c + 1]);
         }
         // m += rho a dt, E += (m_old . a) dt  (Sec. 3.1.1, Sec. 2.1 listing)
-        const T dE = un[1] * acc[0] + un[2] * acc[1] + un[3] * acc[2];
+        const T dE = fmad(un[1], acc[0], fmad(un[2], acc[1], un[3] * acc[2]));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) un[1 + c] += un[0] * acc[c] * dt;
-        un[4] += dE * dt;
+        for (int c = 0; c < 3; ++c) un[1 + c] = fmad(un[0] * acc[c], dt, un[1 + c]);
+        un[4] = fmad(dE, dt, un[4]);
       }
       const T ir = dev_rcp(un[0]);
       const T vx = un[1] * ir, vy = un[2] * ir, vz = un[3] * ir;
-      const T ek = T(0.5) * un[0] * (vx * vx + vy * vy + vz * vz);
+      const T ek = (T(0.5) * un[0]) * fmad(vx, vx, fmad(vy, vy, vz * vz));
       T pn = gm1 * (un[4] - ek);
       if (COOL) {
         const T Tn = cool_T(un[0], pn * ir, dt, a.cool);
-        un[4] = ek + un[0] * Tn * gm1inv;
+        un[4] = fmad(un[0] * Tn, gm1inv, ek);
         pn = gm1 * (un[4] - ek);
       }
       if (inside) {
@@ -363,6 +399,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       fzm[f] = fzp[f];
+      dz1[f] = dz2[f];
       w[0][f] = w[1][f];
       w[1][f] = w[2][f];
       w[2][f] = w[3][f];

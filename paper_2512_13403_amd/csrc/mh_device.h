@@ -103,6 +103,12 @@ struct CoolParams {
   T tc, ts, its, tfloor, sqrt_tc, k1r, k2r;  // its = 1 / ts
 };
 
+// a * b + c in one rounding (v_fma_f32 / v_fma_f64), written out where a
+// fused multiply-add is wanted, so that results do not depend on whether the
+// compiler contracts the expression at a given call site
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ void to_prim(const T (&u)[5], T gm1, T (&w)[5]) {
   const T ir = dev_rcp(u[0]);
@@ -111,7 +117,7 @@ __device__ __forceinline__ void to_prim(const T (&u)[5], T gm1, T (&w)[5]) {
   w[1] = vx;
   w[2] = vy;
   w[3] = vz;
-  w[4] = gm1 * (u[4] - T(0.5) * u[0] * (vx * vx + vy * vy + vz * vz));
+  w[4] = gm1 * fmad(-(T(0.5) * u[0]), fmad(vx, vx, fmad(vy, vy, vz * vz)), u[4]);
 }
 
 template <typename T>
@@ -132,13 +138,13 @@ __device__ __forceinline__ T cool_T(T rho, T Tin, T dt, const CoolParams<T>& c) 
     const T st = acc_sqrt(Tin);
     const T t1 = (st - c.sqrt_tc) * dev_rcp(k1);
     if (dt <= t1) {
-      const T s = st - k1 * dt;
+      const T s = fmad(-k1, dt, st);
       Tn = s * s;
     } else {
-      Tn = c.tc - c.ts * acc_log(T(1) + k2 * (dt - t1));
+      Tn = fmad(-c.ts, acc_log(fmad(k2, dt - t1, T(1))), c.tc);
     }
   } else {
-    Tn = c.tc - c.ts * acc_log(acc_exp((c.tc - Tin) * c.its) + k2 * dt);
+    Tn = fmad(-c.ts, acc_log(fmad(k2, dt, acc_exp((c.tc - Tin) * c.its))), c.tc);
   }
   return fmax(Tn, c.tfloor);
 }

@@ -1,0 +1,261 @@
+"""Solver-in-the-loop study of the learned corrector on driven turbulence.
+
+A fine run (256^3 by default) and coarse runs (64^3, a factor r = 4 coarser)
+share one clock and one forcing path; the corrector is trained so that a
+coarse step followed by the correction reproduces the block average of the
+fine run (the paper's Sec. 8 setting, here in 3D on the conserved state).
+
+Alignment.  The fine run computes its CFL step dt_f at the first of each
+group of r substeps and holds it for the group; its OU amplitudes advance once
+per group with r dt_f (``ou_every = r``).  A coarse step of dt_c = r dt_f then
+covers one fine group at identical times, and the coarse run (``ou_every =
+1``) draws the same OU noise for coarse step k as the fine run for group k,
+because both index the draw by the group.  Targets are conservative r^3
+block averages of the fine conserved state after each group.
+
+Training (500 ADAM iterations, learning rate decaying geometrically from 1e-3
+to 1e-4 as in the paper's Sec. 8): each iteration takes a batch of (trajectory,
+time) pairs k, starts a coarse step from the block-averaged fine state T_k
+with the fine run's OU amplitudes, and fits U' = P_{k+1} + s Net(P_{k+1}) to
+T_{k+1}, where P_{k+1} is the plain coarse step.  Evaluation runs plain and
+corrected coarse rollouts from T_0 of held-out seeds and reports the density
+L2 error against the block-averaged fine run, and the wall-clock cost of each.
+
+Every arithmetic step runs in the HIP library (mh_step, mh_corr_*,
+mh_block_average); this module orders the calls.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import (BC_PERIODIC, Corrector, SRC_FORCING, Solver, block_average, corr_desc, grid_desc,
+               physics_desc)
+
+DRIVE = dict(ou_tau=0.5, ou_arms=1.0, ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0)
+GAMMA = 5.0 / 3.0
+
+
+def make_solver(n: int, seed: int, every: int, dtype="f32") -> Solver:
+    g = grid_desc((n, n, n), (1.0 / n,) * 3, (BC_PERIODIC,) * 3, dtype, GAMMA, 0.4)
+    p = physics_desc(flags=SRC_FORCING, ou_seed=seed, ou_every=every, **DRIVE)
+    return Solver(g, p)
+
+
+def rest_state_device(n: int, torch_dtype):
+    """rho = 1, v = 0, P = 1 (E = 1/(gamma - 1)), made on the device."""
+    import torch
+
+    U = torch.zeros((5, n, n, n), dtype=torch_dtype, device="cuda:0")
+    U[0].fill_(1.0)
+    U[4].fill_(1.0 / (GAMMA - 1.0))
+    return U
+
+
+def fine_group(s: Solver, r: int) -> float:
+    """One group of r fine substeps at the group's CFL step; returns dt_f."""
+    dt = float(s.step(1, 0.0, record=True)[0])
+    if r > 1:
+        s.step(r - 1, dt)
+    return dt
+
+
+@dataclass
+class Trajectory:
+    seed: int
+    T: object                      # [nsteps+1][5][nc][nc][nc] block-averaged fine states
+    dts: np.ndarray                # coarse steps dt_c = r dt_f
+    ahat: list                     # OU amplitudes before each coarse step
+    t: np.ndarray                  # clock before each coarse step
+    step: np.ndarray               # coarse step index (= fine group index)
+    fine_seconds: float = 0.0      # wall clock of the recorded fine groups
+    fine_steps: int = 0
+
+
+def record_trajectory(seed: int, nf: int = 256, r: int = 4, t_spinup: float = 1.0,
+                      nsteps: int = 100) -> Trajectory:
+    import torch
+
+    s = make_solver(nf, seed, r)
+    s.set_state(rest_state_device(nf, s.torch_dtype))
+    t, fstep = s.clock()
+    while t < t_spinup:
+        fine_group(s, r)
+        t, fstep = s.clock()
+    T, dts, ahat, ts, steps = [], [], [], [], []
+
+    def snap():
+        T.append(block_average(s.get_state_device(), r))
+        ahat.append(s.ou_state())
+        tt, st = s.clock()
+        ts.append(tt)
+        steps.append(st // r)
+
+    snap()
+    torch.cuda.synchronize()
+    fine_time = 0.0
+    for _ in range(nsteps):
+        t0 = time.perf_counter()
+        dts.append(r * fine_group(s, r))
+        torch.cuda.synchronize()
+        fine_time += time.perf_counter() - t0
+        snap()
+    s.close()
+    return Trajectory(seed, torch.stack(T), np.array(dts), ahat, np.array(ts),
+                      np.array(steps, dtype=np.int64), fine_time, nsteps * r)
+
+
+def coarse_step_from(c: Solver, traj: Trajectory, k: int):
+    """The plain coarse step from T_k with the fine run's forcing state."""
+    c.set_state(traj.T[k])
+    c.set_ou_state(traj.ahat[k])
+    c.set_clock(float(traj.t[k]), int(traj.step[k]))
+    c.step(1, float(traj.dts[k]))
+    return c.get_state_device()
+
+
+@dataclass
+class TrainResult:
+    theta: np.ndarray
+    losses: list = field(default_factory=list)
+    stats: dict = field(default_factory=dict)
+    seconds: float = 0.0
+
+
+def train(trajs, nc: int, iters: int = 500, batch: int = 4, lr0: float = 1e-3, lr1: float = 1e-4,
+          loss_w=(4.0, 1.0, 1.0, 1.0, 1.0), seed: int = 0, init_scale: float = 1e-2) -> TrainResult:
+    """Fits the corrector on the single-step pairs of the training trajectories."""
+    import torch
+
+    from workloads import corrector_init_params
+
+    P, T = [], []
+    for tr in trajs:
+        cs = make_solver(nc, tr.seed, 1)
+        for k in range(len(tr.dts)):
+            P.append(coarse_step_from(cs, tr, k))
+            T.append(tr.T[k + 1])
+        cs.close()
+    P = torch.stack(P)
+    T = torch.stack(T)
+    d = (T - P).double()
+    Pd = P.double()
+    mean = Pd.mean(dim=(0, 2, 3, 4)).cpu().numpy()
+    std = Pd.std(dim=(0, 2, 3, 4)).cpu().numpy() + 1e-12
+    scale = d.std(dim=(0, 2, 3, 4)).cpu().numpy() + 1e-12
+    stats = dict(mean=mean, std=std, scale=scale, loss_w=np.asarray(loss_w, dtype=np.float64))
+    corr = Corrector(corr_desc(nc, batch, "f32", GAMMA, mean, std, scale, loss_w, 1e-6, 1.0))
+    corr.set_params(corrector_init_params(seed=seed, out_scale=init_scale))
+    rng = np.random.default_rng(seed)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(iters):
+        lr = lr0 * (lr1 / lr0) ** (it / max(iters - 1, 1))
+        idx = torch.as_tensor(rng.integers(0, P.shape[0], batch), device=P.device)
+        losses.append(corr.train_step(P[idx], T[idx], lr))
+    torch.cuda.synchronize()
+    return TrainResult(corr.params(), losses, stats, time.perf_counter() - t0)
+
+
+def rel_l2(a, b) -> float:
+    return float(((a - b).double().norm() / b.double().norm()).item())
+
+
+def evaluate(traj: Trajectory, nc: int, res: TrainResult, nsteps: int | None = None) -> dict:
+    """Plain and corrected coarse rollouts from T_0 against the fine run."""
+    import torch
+
+    n = len(traj.dts) if nsteps is None else nsteps
+    st = res.stats
+    corr = Corrector(corr_desc(nc, 1, "f32", GAMMA, st["mean"], st["std"], st["scale"],
+                               st["loss_w"], 1e-6, 1e-3))
+    corr.set_params(res.theta)
+    out = {}
+    for mode in ("plain", "corrected"):
+        c = make_solver(nc, traj.seed, 1)
+        c.set_state(traj.T[0])
+        c.set_ou_state(traj.ahat[0])
+        c.set_clock(float(traj.t[0]), int(traj.step[0]))
+        errs, fallbacks = [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n):
+            c.step(1, float(traj.dts[k]))
+            if mode == "corrected":
+                U = c.get_state_device().view(1, 5, nc, nc, nc)
+                Uc, _, fb = corr.apply(U)
+                fallbacks += int(fb)
+                c.set_state(Uc.view(5, nc, nc, nc))
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        # errors from a replay (kept out of the timed loop)
+        c.set_state(traj.T[0])
+        c.set_ou_state(traj.ahat[0])
+        c.set_clock(float(traj.t[0]), int(traj.step[0]))
+        for k in range(n):
+            c.step(1, float(traj.dts[k]))
+            if mode == "corrected":
+                Uc, _, _ = corr.apply(c.get_state_device().view(1, 5, nc, nc, nc))
+                c.set_state(Uc.view(5, nc, nc, nc))
+            errs.append(rel_l2(c.get_state_device()[0], traj.T[k + 1][0]))
+        c.close()
+        out[mode] = dict(rho_rel_l2=errs, seconds=secs, fallbacks=fallbacks)
+    fine_secs = traj.fine_seconds * n / len(traj.dts)
+    out["fine_seconds"] = fine_secs
+    out["cost_ratio"] = fine_secs / out["corrected"]["seconds"]
+    return out
+
+
+def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256, r: int = 4,
+              t_spinup: float = 1.0, nsteps: int = 100, iters: int = 500, batch: int = 4,
+              log=print) -> dict:
+    nc = nf // r
+    t0 = time.perf_counter()
+    trajs = [record_trajectory(s, nf, r, t_spinup, nsteps) for s in train_seeds]
+    log(f"[sil] recorded {len(trajs)} training trajectories in {time.perf_counter() - t0:.1f} s")
+    res = train(trajs, nc, iters, batch)
+    log(f"[sil] trained {iters} iterations in {res.seconds:.1f} s: loss {res.losses[0]:.4g} -> "
+        f"{np.mean(res.losses[-20:]):.4g}")
+    del trajs
+    evals = []
+    for s in eval_seeds:
+        tr = record_trajectory(s, nf, r, t_spinup, nsteps)
+        ev = evaluate(tr, nc, res)
+        log(f"[sil] seed {s}: rho L2 plain {ev['plain']['rho_rel_l2'][-1]:.4e} corrected "
+            f"{ev['corrected']['rho_rel_l2'][-1]:.4e} cost ratio {ev['cost_ratio']:.1f}")
+        evals.append(ev)
+    plain = float(np.mean([e["plain"]["rho_rel_l2"][-1] for e in evals]))
+    corrected = float(np.mean([e["corrected"]["rho_rel_l2"][-1] for e in evals]))
+    return dict(
+        fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch,
+        rho_rel_l2_plain=plain, rho_rel_l2_corrected=corrected,
+        error_ratio=corrected / plain,
+        cost_ratio=float(np.mean([e["cost_ratio"] for e in evals])),
+        fallbacks=int(sum(e["corrected"]["fallbacks"] for e in evals)),
+        train_loss_first=float(res.losses[0]), train_loss_last=float(np.mean(res.losses[-20:])),
+        seconds=time.perf_counter() - t0,
+    )
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--fine", type=int, default=256)
+    ap.add_argument("--ratio", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--iters", type=int, default=500)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--train-seeds", type=int, default=12)
+    ap.add_argument("--eval-seeds", type=int, default=4)
+    ap.add_argument("--spinup", type=float, default=1.0)
+    a = ap.parse_args()
+    out = run_study(range(a.train_seeds), range(a.train_seeds, a.train_seeds + a.eval_seeds),
+                    a.fine, a.ratio, a.spinup, a.steps, a.iters, a.batch,
+                    log=lambda m: print(m, flush=True))
+    print(json.dumps(out))

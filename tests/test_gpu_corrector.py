@@ -226,4 +226,5 @@ def test_block_average(dtype, r):
     ref = F.reshape(5, nc, r, nc, r, nc, r).mean(axis=(2, 4, 6))
     assert rel_inf(got, ref) < (1e-15 if dtype == "f64" else 2e-7)
     # conservation: the coarse totals times r^3 are the fine totals
-    assert np.allclose(got.sum(axis=(1, 2, 3)) * r ** 3, F.sum(axis=(1, 2, 3)), rtol=1e-6)
+    assert np.allclose(got.astype(np.float64).sum(axis=(1, 2, 3)) * r ** 3, F.sum(axis=(1, 2, 3)),
+                       rtol=1e-6)
