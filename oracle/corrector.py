@@ -14,8 +14,13 @@ built here is a 3D state corrector applied after each coarse step:
 conv3 is a 3x3x3 cross-correlation with periodic padding; GELU is the erf
 form x (1 + erf(x / sqrt 2)) / 2.  The GPU computes with bf16 operands and
 fp32 accumulation; this oracle rounds the same operands to bf16 (round to
-nearest even) at the same points -- the network input x, the weights, and the
-stored activations h1, h2 -- and accumulates in float64.
+nearest even) at the same points -- the weights, the stored activations h1,
+h2 -- and accumulates in float64.  The standardised input is carried as the
+sum of two bf16 numbers, x = x_hi + x_lo with x_hi = bf16(x32) and x_lo =
+bf16(x32 - x_hi), x32 the float32 value: about 16 significant bits, so the
+first layer sees the state's small-scale structure (a single bf16 would round
+it away at 2^-8 of the channel's spread).  Both parts go through the same
+first-layer weights.
 
 Tap order: t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1), reading input at
 (x + dx, y + dy, z + dz).  Arrays are [batch][z][y][x][channel].
@@ -43,6 +48,20 @@ def bf16_round(x):
     lsb = (u >> 16) & 1
     r = ((u + 0x7FFF + lsb) & 0xFFFF0000).astype(np.uint32)
     return r.view(np.float32).astype(np.float64)
+
+
+def split_parts(x):
+    """(x_hi, x_lo) of the two-part bf16 input: x_hi = bf16(x32), x_lo =
+    bf16(x32 - x_hi) with x32 = float32(x) (the difference is exact in
+    float32)."""
+    x32 = np.asarray(x, dtype=np.float32).astype(np.float64)
+    hi = bf16_round(x32)
+    return hi, bf16_round(x32 - hi)
+
+
+def split_bf16(x):
+    hi, lo = split_parts(x)
+    return hi + lo
 
 
 def unpack(theta):
@@ -105,8 +124,9 @@ def forward(U, theta, mean, std, scale, rounding=True):
     skips the bf16 roundings (exact arithmetic, for derivative checks)."""
     rd = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
     p = {k: rd(v) if k.startswith("W") else v for k, v in unpack(theta).items()}
-    x = np.moveaxis(U, 1, -1)
-    x = rd((x - np.asarray(mean)) / np.asarray(std))
+    x = (np.moveaxis(U, 1, -1) - np.asarray(mean)) / np.asarray(std)
+    if rounding:
+        x = split_bf16(x)
     z1 = conv3(x, p["W1"], p["b1"])
     h1 = rd(gelu(z1))
     z2 = conv3(h1, p["W2"], p["b2"])

@@ -99,6 +99,24 @@ def test_backward_matches_finite_differences():
         assert g[q] == pytest.approx(fd, rel=1e-5, abs=1e-12)
 
 
+def test_split_input_carries_sixteen_bits():
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.standard_normal(20000) * 10 ** rng.uniform(-3, 1, 20000),
+                        np.array([0.0, 1.0, -2.5, 1.0 + 2 ** -9 + 2 ** -20])])
+    hi, lo = oc.split_parts(x)
+    # each part is a bf16 value (torch's float32 -> bfloat16 rounding is exact on them)
+    for part in (hi, lo):
+        t = torch.from_numpy(part.astype(np.float32)).to(torch.bfloat16).to(torch.float32)
+        assert np.array_equal(t.numpy().astype(np.float64), part)
+    x32 = x.astype(np.float32).astype(np.float64)
+    assert np.array_equal(hi, oc.bf16_round(x))
+    # |x - (hi + lo)| <= 2^-16 |x| (two 8-bit significands, round to nearest)
+    assert np.all(np.abs(x32 - (hi + lo)) <= 2.0 ** -16 * np.abs(x32))
+    # the low part keeps 8 bits of the remainder: 1 + 2^-9 + 2^-20 -> 1 + 2^-9
+    assert np.array_equal(oc.split_bf16(np.array([1.0 + 2 ** -9 + 2 ** -20])),
+                          np.array([1.0 + 2 ** -9]))
+
+
 def test_rounded_forward_close_to_exact():
     U, T, theta, mean, std, scale = _setup()
     a, _ = oc.forward(U, theta, mean, std, scale, rounding=True)
