@@ -203,6 +203,8 @@ mh_status mh_adjoint_step(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace
  * h2 = GELU(conv(h1; W2) + b2) (32 -> 32);  y = conv(h2; W3) + b3 (32 -> 5);
  * U' = U + scale * y.  conv is a 3x3x3 cross-correlation with periodic
  * padding (the paper pads its network periodically), GELU the erf form.
+ * The standardised input enters as two bf16 parts per field (hi + lo, about
+ * 16 significant bits) that share the first layer's weights.
  * Operands are bf16 with fp32 accumulation on the matrix cores; the fp32
  * master parameters are trained with ADAM (Sec. 7) on the loss
  * L = sum_c w_c mean((U'_c - T_c)^2) / std_c^2 (density weighted up).
@@ -239,8 +241,11 @@ mh_status mh_corr_set_params(mh_corr *c, const float *theta, int where);
 mh_status mh_corr_get_params(mh_corr *c, float *theta, int where);
 /* U_out = floor(U + scale * Net(U)); when any value is non-finite or more
  * than fallback_frac of the cells needed the floor, U_out = U instead
- * (the plain coarse state).  U_out must not alias U.  floored / fell_back
- * are optional host outputs; synchronises. */
+ * (the plain coarse state; the choice is made on the device).  U_out must
+ * not alias U.  floored / fell_back are optional host outputs: when either
+ * is non-null the call synchronises, otherwise it only enqueues.  Inference
+ * does not store z1 and z2 (activations 1 and 3 keep the last training
+ * pass's values). */
 mh_status mh_corr_apply(mh_corr *c, const void *U, void *U_out, int64_t *floored,
                         int32_t *fell_back);
 /* Loss against the target batch and its gradient in the parameters (to host
@@ -251,7 +256,8 @@ mh_status mh_corr_loss_grad(mh_corr *c, const void *U, const void *target, doubl
  * the loss before the update when loss is non-null (then synchronises). */
 mh_status mh_corr_train_step(mh_corr *c, const void *U, const void *target, float lr,
                              double *loss);
-/* Copies an activation of the last forward pass: 0 x (bf16, [cells][32]),
+/* Copies an activation of the last forward pass: 0 x (bf16, [cells][32]:
+ * channel c < 5 holds hi = bf16(x_c), channel 5 + c holds bf16(x_c - hi)),
  * 1 z1 (fp32, [cells][32]), 2 h1 (bf16), 3 z2 (fp32), 4 h2 (bf16),
  * 5 y (fp32, [cells][16]); cells = batch n^3.  MH_HOST synchronises. */
 mh_status mh_corr_get_activation(mh_corr *c, int which, void *dst, int where);

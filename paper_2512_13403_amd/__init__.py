@@ -242,6 +242,14 @@ class Solver:
                     "mh_get_state")
         return out
 
+    def get_state_into(self, out):
+        """Copies the state into an existing CUDA tensor (enqueued)."""
+        assert out.is_contiguous() and out.dtype == self.torch_dtype and out.numel() == 5 * int(
+            np.prod(self.shape))
+        self._check(self.lib.mh_get_state(self.ctx, ctypes.c_void_p(out.data_ptr()), DEVICE),
+                    "mh_get_state")
+        return out
+
     def get_state_device(self):
         torch = self._torch
         out = torch.empty((5,) + self.shape, dtype=self.torch_dtype, device=self.device)
@@ -462,16 +470,21 @@ class Corrector:
                     "mh_corr_get_params")
         return out
 
-    def apply(self, U, out=None):
-        """Returns (U_corrected, floored_cells, fell_back)."""
+    def apply(self, U, out=None, stats: bool = True):
+        """Returns (U_corrected, floored_cells, fell_back); with stats=False the
+        call only enqueues and the two counts are None."""
         U = self._state(U)
         if out is None:
             out = self._torch.empty_like(U)
         fl = ctypes.c_int64(0)
         fb = ctypes.c_int32(0)
+        self._keep_apply = (U, out)
         self._check(self.lib.mh_corr_apply(self.h, ctypes.c_void_p(U.data_ptr()),
-                                           ctypes.c_void_p(out.data_ptr()), ctypes.byref(fl),
-                                           ctypes.byref(fb)), "mh_corr_apply")
+                                           ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.byref(fl) if stats else None,
+                                           ctypes.byref(fb) if stats else None), "mh_corr_apply")
+        if not stats:
+            return out, None, None
         return out, fl.value, bool(fb.value)
 
     def loss_grad(self, U, target):

@@ -16,7 +16,7 @@ constexpr size_t CALIGN = 256;
 inline size_t calign(size_t x) { return (x + CALIGN - 1) & ~(CALIGN - 1); }
 
 struct CorrLayout {
-  size_t theta, m, v, grad, w1, w2, w3, w1t, w2t, w3t, x0, z1, h1, z2, h2, y, dy16, dy32, dz2, dz1;
+  size_t theta, m, v, grad, w1, w2, w3, w2t, w3t, x0, z1, h1, z2, h2, y, dy16, dy32, dz2, dz1;
   size_t wpart, bpart, dpart, loss, counters, total;
 };
 
@@ -38,7 +38,6 @@ CorrLayout corr_layout(const mh_corr_desc* d) {
   L.w1 = take(27 * 32 * 32 * 2);
   L.w2 = take(27 * 32 * 32 * 2);
   L.w3 = take(27 * 16 * 32 * 2);
-  L.w1t = take(27 * 16 * 32 * 2);
   L.w2t = take(27 * 32 * 32 * 2);
   L.w3t = take(27 * 32 * 32 * 2);
   L.x0 = take(cells * 32 * 2);
@@ -120,8 +119,8 @@ extern "C" mh_status mh_corr_init(const mh_corr_desc* d, void* workspace, size_t
   char* w = c->ws;
   auto F = [&](size_t o) { return reinterpret_cast<float*>(w + o); };
   auto H = [&](size_t o) { return reinterpret_cast<unsigned short*>(w + o); };
-  c->B = CorrBuffers{F(L.theta), F(L.m), F(L.v), F(L.grad), H(L.w1), H(L.w2), H(L.w3), H(L.w1t),
-                     H(L.w2t), H(L.w3t), H(L.x0), H(L.h1), H(L.h2), H(L.dy16), H(L.dy32),
+  c->B = CorrBuffers{F(L.theta), F(L.m), F(L.v), F(L.grad), H(L.w1), H(L.w2), H(L.w3), H(L.w2t),
+                     H(L.w3t), H(L.x0), H(L.h1), H(L.h2), H(L.dy16), H(L.dy32),
                      H(L.dz2), H(L.dz1), F(L.z1), F(L.z2), F(L.y), F(L.wpart), F(L.bpart),
                      reinterpret_cast<double*>(w + L.dpart), reinterpret_cast<double*>(w + L.loss),
                      reinterpret_cast<unsigned long long*>(w + L.counters)};
@@ -170,20 +169,17 @@ extern "C" mh_status mh_corr_get_params(mh_corr* c, float* theta, int where) {
 
 template <typename T>
 static mh_status apply_impl(mh_corr* c, const T* U, T* out, int64_t* floored, int32_t* fell) {
-  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, out, c->stream));
-  MH_CHK(hipMemsetAsync(c->B.counters, 0, 2 * sizeof(unsigned long long), c->stream));
-  MH_CHK(corr_floor<T>(c->B, U, out, c->d.n, c->d.batch, c->d.gamma, c->d.floor_rel, c->stream));
-  unsigned long long cnt[2];
-  MH_CHK(hipMemcpyAsync(cnt, c->B.counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
-  MH_CHK(hipStreamSynchronize(c->stream));
-  const bool fb = cnt[1] > 0 || (double)cnt[0] > c->d.fallback_frac * (double)c->cells();
-  if (fb) {
-    MH_CHK(hipMemcpyAsync(out, U, (size_t)c->cells() * 5 * sizeof(T), hipMemcpyDeviceToDevice,
-                          c->stream));
+  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, out, false, c->stream));
+  MH_CHK(corr_floor<T>(c->B, U, out, c->d.n, c->d.batch, c->d.gamma, c->d.floor_rel,
+                       c->d.fallback_frac, c->stream));
+  if (floored || fell) {
+    unsigned long long cnt[2];
+    MH_CHK(hipMemcpyAsync(cnt, c->B.counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
     MH_CHK(hipStreamSynchronize(c->stream));
+    if (floored) *floored = (int64_t)cnt[0];
+    if (fell)
+      *fell = (cnt[1] > 0 || (double)cnt[0] > c->d.fallback_frac * (double)c->cells()) ? 1 : 0;
   }
-  if (floored) *floored = (int64_t)cnt[0];
-  if (fell) *fell = fb ? 1 : 0;
   return MH_OK;
 }
 
@@ -197,7 +193,7 @@ extern "C" mh_status mh_corr_apply(mh_corr* c, const void* U, void* U_out, int64
 
 template <typename T>
 static mh_status loss_grad_impl(mh_corr* c, const T* U, const T* tgt, double* loss) {
-  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, (T*)nullptr, c->stream));
+  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, (T*)nullptr, true, c->stream));
   MH_CHK(corr_loss_backward<T>(c->B, c->st, c->d.n, c->d.batch, U, tgt, c->stream));
   if (loss) {
     double l;

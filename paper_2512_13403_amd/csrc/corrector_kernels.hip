@@ -13,8 +13,10 @@
 // channels (the MFMA columns, 16 per tile).  For each of the 27 taps a wave
 // loads that tap's weight block once and multiplies it into its four rows,
 // whose shifted inputs it reads from LDS, accumulating in fp32.  Activations
-// are stored cell-major with 32 channels (the network input is zero-padded
-// from 5 to 32, the last layer's 5 outputs sit in 16).  The same kernel
+// are stored cell-major with 32 channels (the network input fills 10 of them:
+// each of the 5 standardised fields as two bf16 parts, hi + lo, which meet
+// the same first-layer weights, so the input keeps about 16 bits at no extra
+// matrix-core work; the last layer's 5 outputs sit in 16).  The same kernel
 // serves the input-gradient pass: there the weights are packed transposed
 // with the taps mirrored, so reading at cell + off_tap applies the transpose
 // of the forward map.  Weight gradients are GEMMs over cells: one workgroup
@@ -64,6 +66,7 @@ enum : int { EPI_GELU = 0, EPI_LINEAR = 1, EPI_GELU_BWD = 2, EPI_RAW = 3 };
 constexpr int CTX = 16, CTY = 4, CTZ = 4;
 constexpr int CHX = CTX + 2, CHY = CTY + 2, CHZ = CTZ + 2, CNH = CHX * CHY * CHZ;
 constexpr int CROWS = CTY * CTZ / 4;  // rows per wave (4 waves)
+constexpr int CPD = 4;                // weight prefetch distance, in taps
 
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
 
@@ -74,7 +77,7 @@ __device__ __forceinline__ int cslot(int h, int hx, int c) { return h * 4 + (c ^
 // out[cell][co] for COT output channels (16 or 32) from in[cell][32] (bf16):
 // per tap, the wave's CROWS rows of 16 cells read their shifted inputs from
 // the LDS tile and multiply them by the tap's 32 x COT weight block (bf16
-// [27][COT][32]), loaded once per tap and prefetched one tap ahead.
+// [27][COT][32]), loaded once per tap and prefetched CPD taps ahead.
 template <int COT, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__ in,
                                               const unsigned short* __restrict__ w,
@@ -110,16 +113,23 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
   for (int r = 0; r < CROWS; ++r)
 #pragma unroll
     for (int nt = 0; nt < COT / 16; ++nt) acc[r][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bf16x8 bw[COT / 16], bn[COT / 16];
+  // weights: CPD taps in flight (a register ring), so the load of a tap's
+  // block is issued CPD taps before its MFMAs
+  const unsigned short* wl = w + row * 32 + 8 * grp;
+  bf16x8 bq[CPD][COT / 16];
 #pragma unroll
-  for (int nt = 0; nt < COT / 16; ++nt) bn[nt] = load8(w + ((nt * 16 + row) * 32 + 8 * grp));
+  for (int p = 0; p < CPD; ++p)
+#pragma unroll
+    for (int nt = 0; nt < COT / 16; ++nt) bq[p][nt] = load8(wl + (p * COT + nt * 16) * 32);
+#pragma unroll
   for (int tap = 0; tap < 27; ++tap) {
+    bf16x8 bw[COT / 16];
 #pragma unroll
-    for (int nt = 0; nt < COT / 16; ++nt) bw[nt] = bn[nt];
-    if (tap + 1 < 27) {
+    for (int nt = 0; nt < COT / 16; ++nt) bw[nt] = bq[tap % CPD][nt];
+    if (tap + CPD < 27) {
 #pragma unroll
       for (int nt = 0; nt < COT / 16; ++nt)
-        bn[nt] = load8(w + (((tap + 1) * COT + nt * 16 + row) * 32 + 8 * grp));
+        bq[tap % CPD][nt] = load8(wl + ((tap + CPD) * COT + nt * 16) * 32);
     }
     const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
     const int hx = row + 1 + dx;
@@ -222,15 +232,20 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
   }
 }
 
-// gtheta[off + (co * ci_real + ci) * 27 + tap] = sum over chunks (fixed order)
+// gtheta[off + (co * ci_real + ci) * 27 + tap] = sum over chunks (fixed
+// order); with `fold`, input channel ci also collects channel ci + ci_real
+// (the two bf16 parts of the network input share the first layer's weights)
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int cot,
                                                       int nchunk, int co_real, int ci_real,
-                                                      float* __restrict__ g) {
+                                                      int fold, float* __restrict__ g) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= 27 * co_real * ci_real) return;
   const int tap = i % 27, ci = (i / 27) % ci_real, co = i / (27 * ci_real);
   float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += partial[((long long)tap * nchunk + c) * (cot * 32) + co * 32 + ci];
+  for (int c = 0; c < nchunk; ++c) {
+    const float* pc = partial + ((long long)tap * nchunk + c) * (cot * 32) + co * 32;
+    s += fold ? pc[ci] + pc[ci + ci_real] : pc[ci];
+  }
   g[i] = s;
 }
 
@@ -255,7 +270,9 @@ __global__ __launch_bounds__(64) void k_colsum_final(const float* __restrict__ p
   g[co] = s;
 }
 
-// network input: x[cell][c] = bf16(float((U_c - mean_c) / std_c)) for c < 5, 0 above
+// network input, two bf16 parts per channel: with x32 = float((U_c - mean_c) /
+// std_c), x[cell][c] = hi = bf16(x32) and x[cell][5 + c] = bf16(x32 - hi)
+// (the difference is exact in fp32); channels 10..31 are 0
 template <typename T>
 __global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ U, int n, long long cells,
                                                      CorrStats st, unsigned short* __restrict__ x) {
@@ -268,8 +285,9 @@ __global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ U, in
   for (int c = 0; c < 32; ++c) v[c] = 0;
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    const double s = ((double)U[(b * 5 + c) * n3 + q] - st.mean[c]) / st.std[c];
-    v[c] = f2bf((float)s);
+    const float s = (float)(((double)U[(b * 5 + c) * n3 + q] - st.mean[c]) / st.std[c]);
+    v[c] = f2bf(s);
+    v[5 + c] = f2bf(s - bf2f(v[c]));
   }
 #pragma unroll
   for (int c = 0; c < 32; c += 8) __builtin_memcpy(x + cell * 32 + c, v + c, 16);
@@ -356,6 +374,21 @@ __global__ __launch_bounds__(256) void k_floor(T* __restrict__ U, long long n3, 
   if (bad) atomicAdd(&counters[1], 1ull);
 }
 
+// fallback on the device: when any value was non-finite or more than `limit`
+// cells were floored, out = U (the plain state); counters as k_floor left them
+template <typename T>
+__global__ __launch_bounds__(256) void k_fallback(const T* __restrict__ U, T* __restrict__ out,
+                                                  long long count, double limit,
+                                                  const unsigned long long* __restrict__ counters) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  if (counters[1] > 0 || (double)counters[0] > limit) out[i] = U[i];
+}
+
+__global__ __launch_bounds__(64) void k_zero_counters(unsigned long long* c) {
+  if (threadIdx.x < 2) c[threadIdx.x] = 0;
+}
+
 // loss L = sum_c w_c mean((U'_c - T_c)^2) / sigma_c^2 (per-block partials) and
 // dY[cell][c] = bf16(scale_c * 2 w_c (U'_c - T_c) / (sigma_c^2 cells))
 template <typename T>
@@ -428,15 +461,18 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ th, float* __r
 }
 
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ th, int off, int co_real,
-                                              int ci_real, int cot, unsigned short* __restrict__ wf,
-                                              int cit_t, unsigned short* __restrict__ wt) {
-  // forward: wf[tap][co][ci] (co < cot, ci < 32); transposed-mirrored:
-  // wt[26 - tap][ci][co] (ci < cit_t rows, co < 32)
+                                              int ci_real, int dup, int cot,
+                                              unsigned short* __restrict__ wf, int cit_t,
+                                              unsigned short* __restrict__ wt) {
+  // forward: wf[tap][co][ci] (co < cot, ci < 32), with `dup` the input
+  // channels ci_real..2 ci_real-1 repeating 0..ci_real-1; transposed-mirrored
+  // (when wt is given): wt[26 - tap][ci][co] (ci < cit_t rows, co < 32)
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= 27 * cot * 32) return;
   const int tap = i / (cot * 32), co = (i / 32) % cot, ci = i % 32;
+  const int cs = (dup && ci >= ci_real) ? ci - ci_real : ci;
   float val = 0.f;
-  if (co < co_real && ci < ci_real) val = th[off + (co * ci_real + ci) * 27 + tap];
+  if (co < co_real && cs < ci_real) val = th[off + (co * ci_real + cs) * 27 + tap];
   const unsigned short h = f2bf(val);
   wf[i] = h;
   if (wt && ci < cit_t) wt[((long long)(26 - tap) * cit_t + ci) * 32 + co] = h;
@@ -473,25 +509,27 @@ inline unsigned conv_grid(int n, int batch) {
 
 hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
-                     CORR_OFF_W1, 32, 5, 32, B.w1, 16, B.w1t);
+                     CORR_OFF_W1, 32, 5, 1, 32, B.w1, 0, (unsigned short*)nullptr);
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
-                     CORR_OFF_W2, 32, 32, 32, B.w2, 32, B.w2t);
+                     CORR_OFF_W2, 32, 32, 0, 32, B.w2, 32, B.w2t);
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 16 * 32, 256)), dim3(256), 0, s, B.theta,
-                     CORR_OFF_W3, 5, 32, 16, B.w3, 32, B.w3t);
+                     CORR_OFF_W3, 5, 32, 0, 16, B.w3, 32, B.w3t);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
-                        T* out, hipStream_t s) {
+                        T* out, bool store_z, hipStream_t s) {
   const long long cells = (long long)batch * n * n * n;
   const unsigned conv_blocks = conv_grid(n, batch);
   hipLaunchKernelGGL((k_standardize<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, n, cells, st,
                      B.x0);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_blocks), dim3(256), 0, s, B.x0, B.w1,
-                     B.theta + CORR_OFF_B1, 32, n, (const float*)nullptr, B.z1, B.h1);
+                     B.theta + CORR_OFF_B1, 32, n, (const float*)nullptr,
+                     store_z ? B.z1 : (float*)nullptr, B.h1);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_blocks), dim3(256), 0, s, B.h1, B.w2,
-                     B.theta + CORR_OFF_B2, 32, n, (const float*)nullptr, B.z2, B.h2);
+                     B.theta + CORR_OFF_B2, 32, n, (const float*)nullptr,
+                     store_z ? B.z2 : (float*)nullptr, B.h2);
   hipLaunchKernelGGL((k_conv<16, EPI_LINEAR>), dim3(conv_blocks), dim3(256), 0, s, B.h2, B.w3,
                      B.theta + CORR_OFF_B3, 5, n, (const float*)nullptr, B.y,
                      (unsigned short*)nullptr);
@@ -503,13 +541,16 @@ hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int ba
 
 template <typename T>
 hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch, double gamma,
-                      double frel, hipStream_t s) {
+                      double frel, double fallback_frac, hipStream_t s) {
   const long long n3 = (long long)n * n * n, cells = batch * n3;
   const int bps = 64;
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, B.counters);
   hipLaunchKernelGGL((k_rho_p_partial<T>), dim3(batch * bps), dim3(256), 0, s, U, n3, gamma - 1.0,
                      bps, B.dpart);
   hipLaunchKernelGGL((k_floor<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, out, n3, cells,
                      gamma - 1.0, frel, B.dpart, bps, B.counters);
+  hipLaunchKernelGGL((k_fallback<T>), dim3(blocks(5 * cells, 256)), dim3(256), 0, s, U, out,
+                     5 * cells, fallback_frac * (double)cells, B.counters);
   return hipGetLastError();
 }
 
@@ -529,7 +570,7 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
   hipLaunchKernelGGL((k_wgrad<16>), dim3(27 * nchunk), dim3(256), 0, s, B.dy16, B.h2, n, cells, chunk,
                      B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32, 256)), dim3(256), 0, s, B.wpart, 16,
-                     nchunk, 5, 32, B.grad + CORR_OFF_W3);
+                     nchunk, 5, 32, 0, B.grad + CORR_OFF_W3);
   hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dy16, 16, cells, chunk,
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 16, nchunk, 5,
@@ -540,7 +581,7 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
   hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz2, B.h1, n, cells, chunk,
                      B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.wpart, 32,
-                     nchunk, 32, 32, B.grad + CORR_OFF_W2);
+                     nchunk, 32, 32, 0, B.grad + CORR_OFF_W2);
   hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz2, 32, cells, chunk,
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
@@ -551,7 +592,7 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
   hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz1, B.x0, n, cells, chunk,
                      B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5, 256)), dim3(256), 0, s, B.wpart, 32,
-                     nchunk, 32, 5, B.grad + CORR_OFF_W1);
+                     nchunk, 32, 5, 1, B.grad + CORR_OFF_W1);
   hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz1, 32, cells, chunk,
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
@@ -576,9 +617,9 @@ hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStre
 
 #define CORR_INSTANTIATE(T)                                                                       \
   template hipError_t corr_forward<T>(const CorrBuffers&, const CorrStats&, int, int, const T*, T*, \
-                                      hipStream_t);                                               \
+                                      bool, hipStream_t);                                         \
   template hipError_t corr_floor<T>(const CorrBuffers&, const T*, T*, int, int, double, double,    \
-                                    hipStream_t);                                                 \
+                                    double, hipStream_t);                                         \
   template hipError_t corr_loss_backward<T>(const CorrBuffers&, const CorrStats&, int, int,        \
                                             const T*, const T*, hipStream_t);                      \
   template hipError_t launch_block_average<T>(const T*, int, int, T*, hipStream_t);

@@ -22,7 +22,7 @@ struct CorrStats {
 
 struct CorrBuffers {
   float *theta, *m, *v, *grad;
-  unsigned short *w1, *w2, *w3, *w1t, *w2t, *w3t;
+  unsigned short *w1, *w2, *w3, *w2t, *w3t;
   unsigned short *x0, *h1, *h2, *dy16, *dy32, *dz2, *dz1;
   float *z1, *z2, *y, *wpart, *bpart;
   double *dpart, *loss;
@@ -32,10 +32,10 @@ struct CorrBuffers {
 hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s);
 template <typename T>
 hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
-                        T* out, hipStream_t s);
+                        T* out, bool store_z, hipStream_t s);
 template <typename T>
 hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch, double gamma,
-                      double frel, hipStream_t s);
+                      double frel, double fallback_frac, hipStream_t s);
 template <typename T>
 hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch,
                               const T* U, const T* tgt, hipStream_t s);

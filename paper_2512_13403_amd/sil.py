@@ -125,7 +125,7 @@ class TrainResult:
     seconds: float = 0.0
 
 
-def train(trajs, nc: int, iters: int = 500, batch: int = 4, lr0: float = 1e-3, lr1: float = 1e-4,
+def train(trajs, nc: int, iters: int = 500, batch: int = 8, lr0: float = 1e-3, lr1: float = 1e-4,
           loss_w=(4.0, 1.0, 1.0, 1.0, 1.0), seed: int = 0, init_scale: float = 1e-2) -> TrainResult:
     """Fits the corrector on the single-step pairs of the training trajectories."""
     import torch
@@ -146,8 +146,12 @@ def train(trajs, nc: int, iters: int = 500, batch: int = 4, lr0: float = 1e-3, l
     mean = Pd.mean(dim=(0, 2, 3, 4)).cpu().numpy()
     std = Pd.std(dim=(0, 2, 3, 4)).cpu().numpy() + 1e-12
     scale = d.std(dim=(0, 2, 3, 4)).cpu().numpy() + 1e-12
-    stats = dict(mean=mean, std=std, scale=scale, loss_w=np.asarray(loss_w, dtype=np.float64))
-    corr = Corrector(corr_desc(nc, batch, "f32", GAMMA, mean, std, scale, loss_w, 1e-6, 1.0))
+    # relative MSE: the library divides channel c's squared error by std_c^2;
+    # weights w_c std_c^2 / scale_c^2 make it sum_c w_c mean(d_c^2) / scale_c^2,
+    # i.e. relative to the spread of the residual the network has to predict
+    lw = np.asarray(loss_w, dtype=np.float64) * std ** 2 / scale ** 2
+    stats = dict(mean=mean, std=std, scale=scale, loss_w=lw)
+    corr = Corrector(corr_desc(nc, batch, "f32", GAMMA, mean, std, scale, lw, 1e-6, 1.0))
     corr.set_params(corrector_init_params(seed=seed, out_scale=init_scale))
     rng = np.random.default_rng(seed)
     losses = []
@@ -181,26 +185,29 @@ def evaluate(traj: Trajectory, nc: int, res: TrainResult, nsteps: int | None = N
         c.set_ou_state(traj.ahat[0])
         c.set_clock(float(traj.t[0]), int(traj.step[0]))
         errs, fallbacks = [], 0
+        buf = torch.empty((1, 5, nc, nc, nc), dtype=c.torch_dtype, device=c.device)
+        cor = torch.empty_like(buf)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(n):
             c.step(1, float(traj.dts[k]))
             if mode == "corrected":
-                U = c.get_state_device().view(1, 5, nc, nc, nc)
-                Uc, _, fb = corr.apply(U)
-                fallbacks += int(fb)
-                c.set_state(Uc.view(5, nc, nc, nc))
+                c.get_state_into(buf)
+                corr.apply(buf, cor, stats=False)
+                c.set_state(cor.view(5, nc, nc, nc))
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
-        # errors from a replay (kept out of the timed loop)
+        # errors and fallback counts from a replay (kept out of the timed loop)
         c.set_state(traj.T[0])
         c.set_ou_state(traj.ahat[0])
         c.set_clock(float(traj.t[0]), int(traj.step[0]))
         for k in range(n):
             c.step(1, float(traj.dts[k]))
             if mode == "corrected":
-                Uc, _, _ = corr.apply(c.get_state_device().view(1, 5, nc, nc, nc))
-                c.set_state(Uc.view(5, nc, nc, nc))
+                c.get_state_into(buf)
+                _, _, fb = corr.apply(buf, cor)
+                fallbacks += int(fb)
+                c.set_state(cor.view(5, nc, nc, nc))
             errs.append(rel_l2(c.get_state_device()[0], traj.T[k + 1][0]))
         c.close()
         out[mode] = dict(rho_rel_l2=errs, seconds=secs, fallbacks=fallbacks)
@@ -211,7 +218,7 @@ def evaluate(traj: Trajectory, nc: int, res: TrainResult, nsteps: int | None = N
 
 
 def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256, r: int = 4,
-              t_spinup: float = 1.0, nsteps: int = 100, iters: int = 500, batch: int = 4,
+              t_spinup: float = 1.0, nsteps: int = 100, iters: int = 500, batch: int = 8,
               log=print) -> dict:
     nc = nf // r
     t0 = time.perf_counter()
@@ -230,10 +237,14 @@ def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256,
         evals.append(ev)
     plain = float(np.mean([e["plain"]["rho_rel_l2"][-1] for e in evals]))
     corrected = float(np.mean([e["corrected"]["rho_rel_l2"][-1] for e in evals]))
+    plain_avg = float(np.mean([np.mean(e["plain"]["rho_rel_l2"]) for e in evals]))
+    corr_avg = float(np.mean([np.mean(e["corrected"]["rho_rel_l2"]) for e in evals]))
     return dict(
         fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch,
         rho_rel_l2_plain=plain, rho_rel_l2_corrected=corrected,
         error_ratio=corrected / plain,
+        rho_rel_l2_plain_mean_over_steps=plain_avg,
+        rho_rel_l2_corrected_mean_over_steps=corr_avg,
         cost_ratio=float(np.mean([e["cost_ratio"] for e in evals])),
         fallbacks=int(sum(e["corrected"]["fallbacks"] for e in evals)),
         train_loss_first=float(res.losses[0]), train_loss_last=float(np.mean(res.losses[-20:])),
@@ -250,7 +261,7 @@ if __name__ == "__main__":
     ap.add_argument("--ratio", type=int, default=4)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--iters", type=int, default=500)
-    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--train-seeds", type=int, default=12)
     ap.add_argument("--eval-seeds", type=int, default=4)
     ap.add_argument("--spinup", type=float, default=1.0)

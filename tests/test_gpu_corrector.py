@@ -86,16 +86,22 @@ def to_oracle(a, batch, n):
 def test_forward_layers(dtype, n, batch):
     U = batch_state(n, batch, 10, dtype)
     c, th, mean, std, scale = make(n, batch, dtype, U)
-    out, nfl, fb = c.apply(torch_dev(U, dtype))
+    Ud = torch_dev(U, dtype)
+    out, nfl, fb = c.apply(Ud)
     out = out.cpu().numpy()
+    h1_apply, y_apply = c.activation(2), c.activation(5)
+    c.loss_grad(Ud, Ud)  # the training forward also stores z1 and z2
+    assert np.array_equal(c.activation(2), h1_apply) and np.array_equal(c.activation(5), y_apply)
     p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
-    # network input: bitwise
+    # network input, both bf16 parts: bitwise
     x0 = c.activation(0)
-    xref = oc.bf16_round((np.moveaxis(U, 1, -1) - mean) / std).reshape(-1, 5)
-    assert np.array_equal(x0[:, :5], xref) and not x0[:, 5:].any()
+    hi, lo = oc.split_parts((np.moveaxis(U, 1, -1) - mean) / std)
+    assert np.array_equal(x0[:, :5], hi.reshape(-1, 5))
+    assert np.array_equal(x0[:, 5:10], lo.reshape(-1, 5)) and not x0[:, 10:].any()
     # each layer from the GPU's own input activations
     z1 = c.activation(1)
-    assert rel_inf(z1, oc.conv3(to_oracle(x0[:, :5], batch, n), p["W1"], p["b1"]).reshape(-1, 32)) < 1e-5
+    xin = to_oracle(x0[:, :5] + x0[:, 5:10], batch, n)
+    assert rel_inf(z1, oc.conv3(xin, p["W1"], p["b1"]).reshape(-1, 32)) < 1e-5
     h1 = c.activation(2)
     check_bf16_activation(h1, oc.bf16_round(oc.gelu(z1)))
     z2 = c.activation(3)
@@ -135,7 +141,8 @@ def oracle_grad_from_gpu(c, U, T, th, std, scale, loss_w, batch, n):
     """The oracle's backward pass on the GPU's forward activations."""
     p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
     y = c.activation(5)[:, :5]
-    cache = dict(x=to_oracle(c.activation(0)[:, :5], batch, n),
+    x0 = c.activation(0)
+    cache = dict(x=to_oracle(x0[:, :5] + x0[:, 5:10], batch, n),
                  z1=to_oracle(c.activation(1), batch, n), h1=to_oracle(c.activation(2), batch, n),
                  z2=to_oracle(c.activation(3), batch, n), h2=to_oracle(c.activation(4), batch, n),
                  y=to_oracle(y, batch, n), p=p, rd=oc.bf16_round)
@@ -208,6 +215,9 @@ def test_floor_and_fallback(dtype):
     c2, *_ = make(n, batch, dtype, U, scale=scale, fallback_frac=1e-3, theta=th)
     out2, nfl2, fb2 = c2.apply(torch_dev(U, dtype))
     assert fb2 and nfl2 == nref and np.array_equal(out2.cpu().numpy(), U)
+    # the enqueue-only form makes the same choice on the device
+    out2b, none1, none2 = c2.apply(torch_dev(U, dtype), stats=False)
+    assert none1 is None and none2 is None and np.array_equal(out2b.cpu().numpy(), U)
     # non-finite parameters: fallback as well
     bad_th = th.copy()
     bad_th[-1] = np.nan
