@@ -13,6 +13,9 @@ roofline         the dominant kernel (RK stage 2) against the MI355X HBM peak:
                  read U^n, write U^{n+1}) over its mean duration from HIP events
                  recorded around every launch on the library's stream
 cpu_baseline     the FP64 oracle on the same physics at 192^3 for 16 steps
+corrector        the solver-in-the-loop study: density L2 error of the plain and
+                 the corrected 64^3 runs against the block-averaged 256^3 run,
+                 and the cost ratio (fine run time / corrected coarse run time)
 """
 import argparse
 import hashlib
@@ -75,6 +78,18 @@ def cpu_baseline(n=192, steps=16):
                       f"fp64, OpenMP over {threads} threads, {dt:.1f} s"}
 
 
+def corrector_study():
+    """Second half of the metric: 16 driven-turbulence trajectories (forcing
+    only, seeds 0..15), fine 256^3 block-averaged to 64^3 as targets; the
+    corrector is trained on seeds 0..11 (500 ADAM iterations) and the plain and
+    corrected 64^3 runs are compared over 100 coarse steps on seeds 12..15."""
+    from paper_2512_13403_amd import sil
+
+    out = sil.run_study(log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    out["metric"] = "density rel. L2 error vs block-averaged 256^3 after 100 coarse steps"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +98,8 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-corrector-study", action="store_true",
+                    help="skip the solver-in-the-loop study (fine 256^3 vs corrected 64^3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (torch copy_ of 2^28 fp32), "
                          "the reference for scaling HBM counters")
@@ -155,7 +172,7 @@ def main():
     ach1 = bytes1 / (st1_ms / 1e3) / 1e9
     traffic = measured_traffic() if args.dtype == "f32" and n == 512 else None
     rec = {
-        "metric": "cell-updates/s & %HBM BW at 512^3 fp32",
+        "metric": "cell-updates/s & %HBM BW at 512^3 fp32; corrected-64^3 L2 err vs plain",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -190,6 +207,11 @@ def main():
             "traffic": traffic,
         },
     }
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_corrector_study:
+        print("# solver-in-the-loop study: fine 256^3, coarse 64^3", file=sys.stderr, flush=True)
+        rec["corrector"] = corrector_study()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()

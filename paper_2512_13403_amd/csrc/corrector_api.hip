@@ -50,7 +50,7 @@ CorrLayout corr_layout(const mh_corr_desc* d) {
   L.dy32 = take(cells * 32 * 2);
   L.dz2 = take(cells * 32 * 2);
   L.dz1 = take(cells * 32 * 2);
-  L.wpart = take(27 * nchunk * 32 * 32 * 4);
+  L.wpart = take((size_t)27 * corr_wgrad_groups((long long)cells) * 32 * 32 * 4);
   L.bpart = take(nchunk * 32 * 4);
   const size_t nd = std::max((cells + 255) / 256, (size_t)d->batch * 64 * 2);
   L.dpart = take(nd * sizeof(double));

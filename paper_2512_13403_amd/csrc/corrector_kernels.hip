@@ -67,6 +67,7 @@ constexpr int CTX = 16, CTY = 4, CTZ = 4;
 constexpr int CHX = CTX + 2, CHY = CTY + 2, CHZ = CTZ + 2, CNH = CHX * CHY * CHZ;
 constexpr int CROWS = CTY * CTZ / 4;  // rows per wave (4 waves)
 constexpr int CPD = 4;                // weight prefetch distance, in taps
+static_assert(CTX * CTY * CTZ == CORR_BLOCK_CELLS, "tile size");
 
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
 
@@ -173,77 +174,136 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
   }
 }
 
-// partial[tap][chunk][COT][32] = sum over the chunk's cells of
-// dz[cell][co] * x[cell + off_tap][ci]; one workgroup per (tap, chunk)
+// Weight gradient of one layer, dW[tap][co][ci] = sum over cells of
+// dz[cell][co] x[cell + off_tap][ci], on the same 16 x 4 x 4 halo tiles as
+// k_conv.  A persistent workgroup takes every gridDim.x-th block of cells; per
+// block it stages the layer input with its halo and the block's output
+// gradients in LDS, and wave w accumulates taps w, w + 4, ... in registers
+// over all its blocks: per MFMA the reduction runs over 32 cells (16 along x
+// in two rows), dz^T is the A operand (rows: output channels) and the shifted
+// input the B operand (columns: input channels).  Each workgroup writes its
+// partial [27][COT][32]; k_wgrad_reduce adds them in a fixed order
+// (deterministic, no atomics).
+constexpr int WTAPS = 7;  // taps per wave: ceil(27 / 4)
+
 template <int COT>
 __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict__ dz,
                                                const unsigned short* __restrict__ x, int n,
-                                               long long cells, int chunk,
-                                               float* __restrict__ partial) {
-  __shared__ float red[4][COT][32];
-  const int tap = blockIdx.x % 27;
-  const long long ch = blockIdx.x / 27;
+                                               int nblocks, float* __restrict__ partial) {
+  constexpr int CB = CTX * CTY * CTZ;  // cells per block
+  __shared__ u32x4 tile[CNH * 4];
+  __shared__ u32x4 dzt[CB * COT / 8];
+  const unsigned short* tile16 = reinterpret_cast<const unsigned short*>(tile);
+  const unsigned short* dzt16 = reinterpret_cast<const unsigned short*>(dzt);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, grp = lane >> 4;
-  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dzz = tap / 9 - 1;
-  const long long n3 = (long long)n * n * n;
-  f32x4 acc[COT / 16][2];
+  const int ntx = n / CTX, nty = n / CTY, ntz = n / CTZ;
+  f32x4 acc[WTAPS][COT / 16][2];
 #pragma unroll
-  for (int i = 0; i < COT / 16; ++i) acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const long long begin = ch * chunk + (long long)wave * (chunk / 4);
-  const long long end = begin + chunk / 4;
-  for (long long k0 = begin; k0 < end && k0 < cells; k0 += 32) {
-    unsigned short av[COT / 16][8], bv[2][8];
+  for (int tt = 0; tt < WTAPS; ++tt)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const long long cell = k0 + 8 * grp + e;
-      const long long b = cell / n3, r = cell % n3;
-      const int z = (int)(r / ((long long)n * n)), y = (int)((r / n) % n), xx = (int)(r % n);
-      const long long src = b * n3 + ((long long)wrap(z + dzz, n) * n + wrap(y + dy, n)) * n +
-                            wrap(xx + dx, n);
-#pragma unroll
-      for (int mt = 0; mt < COT / 16; ++mt) av[mt][e] = dz[cell * COT + mt * 16 + row];
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) bv[ct][e] = x[src * 32 + ct * 16 + row];
+    for (int mt = 0; mt < COT / 16; ++mt)
+      acc[tt][mt][0] = acc[tt][mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    int t = blk;
+    const int bx = t % ntx;
+    t /= ntx;
+    const int by = t % nty;
+    t /= nty;
+    const int bz = t % ntz;
+    const long long b = t / ntz;
+    const int x0 = bx * CTX, y0 = by * CTY, z0 = bz * CTZ;
+    const long long base = b * n * n * (long long)n;
+    for (int i = threadIdx.x; i < CNH * 4; i += 256) {
+      const int h = i >> 2, c = i & 3;
+      const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
+      const long long src = base +
+                            ((long long)wrap(z0 - 1 + hz, n) * n + wrap(y0 - 1 + hy, n)) * n +
+                            wrap(x0 - 1 + hx, n);
+      u32x4 v;
+      __builtin_memcpy(&v, x + src * 32 + c * 8, 16);
+      tile[cslot(h, hx, c)] = v;
     }
+    for (int i = threadIdx.x; i < CB * COT / 8; i += 256) {
+      const int cl = i / (COT / 8), c = i % (COT / 8);
+      const int r = cl / CTX;
+      const long long cell =
+          base + ((long long)(z0 + r / CTY) * n + (y0 + r % CTY)) * n + x0 + cl % CTX;
+      u32x4 v;
+      __builtin_memcpy(&v, dz + cell * COT + c * 8, 16);
+      dzt[i] = v;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int ks = 0; ks < CB / 32; ++ks) {
+      // this lane's 8 cells of the 32-cell step: x = xs .. xs + 7 of row r
+      const int r = 2 * ks + (grp >> 1), xs = 8 * (grp & 1);
+      const int ty = r % CTY, tz = r / CTY;
+      bf16x8 a[COT / 16];
 #pragma unroll
-    for (int mt = 0; mt < COT / 16; ++mt) {
-      bf16x8 a;
-      __builtin_memcpy(&a, av[mt], 16);
+      for (int mt = 0; mt < COT / 16; ++mt) {
+        unsigned short v[8];
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        bf16x8 bb;
-        __builtin_memcpy(&bb, bv[ct], 16);
-        acc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[mt][ct], 0, 0, 0);
+        for (int j = 0; j < 8; ++j) v[j] = dzt16[(r * CTX + xs + j) * COT + mt * 16 + row];
+        __builtin_memcpy(&a[mt], v, 16);
+      }
+#pragma unroll
+      for (int tt = 0; tt < WTAPS; ++tt) {
+        const int tap = wave + 4 * tt;
+        if (tap < 27) {
+          const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dzz = tap / 9 - 1;
+          const int hrow = ((tz + 1 + dzz) * CHY + (ty + 1 + dy)) * CHX;
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const int ci = ct * 16 + row;
+            unsigned short v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int hx = xs + j + 1 + dx;
+              v[j] = tile16[cslot(hrow + hx, hx, ci >> 3) * 8 + (ci & 7)];
+            }
+            bf16x8 bv;
+            __builtin_memcpy(&bv, v, 16);
+#pragma unroll
+            for (int mt = 0; mt < COT / 16; ++mt)
+              acc[tt][mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc[tt][mt][ct],
+                                                                        0, 0, 0);
+          }
+        }
       }
     }
+    __syncthreads();
   }
 #pragma unroll
-  for (int mt = 0; mt < COT / 16; ++mt)
+  for (int tt = 0; tt < WTAPS; ++tt) {
+    const int tap = wave + 4 * tt;
+    if (tap < 27) {
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+      for (int mt = 0; mt < COT / 16; ++mt)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) red[wave][mt * 16 + 4 * grp + q][ct * 16 + row] = acc[mt][ct][q];
-  __syncthreads();
-  for (int i = threadIdx.x; i < COT * 32; i += 256) {
-    const int co = i / 32, ci = i % 32;
-    const float s = ((red[0][co][ci] + red[1][co][ci]) + red[2][co][ci]) + red[3][co][ci];
-    partial[((long long)tap * gridDim.x / 27 + ch) * (COT * 32) + i] = s;
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int co = mt * 16 + 4 * grp + q, ci = ct * 16 + row;
+            partial[(((long long)blockIdx.x * 27 + tap) * COT + co) * 32 + ci] = acc[tt][mt][ct][q];
+          }
+    }
   }
 }
 
-// gtheta[off + (co * ci_real + ci) * 27 + tap] = sum over chunks (fixed
-// order); with `fold`, input channel ci also collects channel ci + ci_real
-// (the two bf16 parts of the network input share the first layer's weights)
+// gtheta[off + (co * ci_real + ci) * 27 + tap] = sum of the nwg partials
+// [nwg][27][cot][32] in a fixed order; with `fold`, input channel ci also
+// collects channel ci + ci_real (the two bf16 parts of the network input share
+// the first layer's weights)
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int cot,
-                                                      int nchunk, int co_real, int ci_real,
+                                                      int nwg, int co_real, int ci_real,
                                                       int fold, float* __restrict__ g) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= 27 * co_real * ci_real) return;
   const int tap = i % 27, ci = (i / 27) % ci_real, co = i / (27 * ci_real);
   float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) {
-    const float* pc = partial + ((long long)tap * nchunk + c) * (cot * 32) + co * 32;
+  for (int c = 0; c < nwg; ++c) {
+    const float* pc = partial + (((long long)c * 27 + tap) * cot + co) * 32;
     s += fold ? pc[ci] + pc[ci + ci_real] : pc[ci];
   }
   g[i] = s;
@@ -566,11 +626,12 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
   hipLaunchKernelGGL(k_pad16to32, dim3(lb), dim3(256), 0, s, B.dy16, cells, B.dy32);
   const int chunk = CORR_CHUNK;
   const int nchunk = (int)((cells + chunk - 1) / chunk);
+  const int nblk = (int)(cells / (CTX * CTY * CTZ));
+  const int nwg = corr_wgrad_groups(cells);
   // layer 3: dW3, db3; dH2 -> dZ2 = dH2 * GELU'(Z2)
-  hipLaunchKernelGGL((k_wgrad<16>), dim3(27 * nchunk), dim3(256), 0, s, B.dy16, B.h2, n, cells, chunk,
-                     B.wpart);
+  hipLaunchKernelGGL((k_wgrad<16>), dim3(nwg), dim3(256), 0, s, B.dy16, B.h2, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32, 256)), dim3(256), 0, s, B.wpart, 16,
-                     nchunk, 5, 32, 0, B.grad + CORR_OFF_W3);
+                     nwg, 5, 32, 0, B.grad + CORR_OFF_W3);
   hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dy16, 16, cells, chunk,
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 16, nchunk, 5,
@@ -578,10 +639,9 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dy32, B.w3t,
                      (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2);
   // layer 2
-  hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz2, B.h1, n, cells, chunk,
-                     B.wpart);
+  hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz2, B.h1, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.wpart, 32,
-                     nchunk, 32, 32, 0, B.grad + CORR_OFF_W2);
+                     nwg, 32, 32, 0, B.grad + CORR_OFF_W2);
   hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz2, 32, cells, chunk,
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
@@ -589,10 +649,9 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dz2, B.w2t,
                      (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1);
   // layer 1
-  hipLaunchKernelGGL((k_wgrad<32>), dim3(27 * nchunk), dim3(256), 0, s, B.dz1, B.x0, n, cells, chunk,
-                     B.wpart);
+  hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5, 256)), dim3(256), 0, s, B.wpart, 32,
-                     nchunk, 32, 5, 1, B.grad + CORR_OFF_W1);
+                     nwg, 32, 5, 1, B.grad + CORR_OFF_W1);
   hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz1, 32, cells, chunk,
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,

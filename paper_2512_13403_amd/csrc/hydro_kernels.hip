@@ -74,16 +74,15 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   const T rr = wr[0], ur = wr[vn], pr = wr[4];
   const T cl = sound_speed(gamma * pl, rl), cr = sound_speed(gamma * pr, rr);
   const T SL = fmin(ul - cl, ur - cr), SR = fmax(ul + cl, ur + cr);
-  const T kel = (T(0.5) * rl) * fmad(ul, ul, fmad(wl[t1], wl[t1], wl[t2] * wl[t2]));
-  const T ker = (T(0.5) * rr) * fmad(ur, ur, fmad(wr[t1], wr[t1], wr[t2] * wr[t2]));
-  const T El = fmad(pl, gm1inv, kel), Er = fmad(pr, gm1inv, ker);
   const T dl = rl * (SL - ul), dr = rr * (SR - ur);
   const T sstar = fmad(-ur, dr, fmad(ul, dl, pr - pl)) * dev_rcp(dl - dr);
   // side: the oracle's region order (0 <= S_L, 0 <= S*, 0 < S_R, else R)
   const bool left = (SL >= T(0)) || (sstar >= T(0));
   const T rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
   const T aK = left ? wl[t1] : wr[t1], bK = left ? wl[t2] : wr[t2];
-  const T EK = left ? El : Er, SK = left ? SL : SR, dK = left ? dl : dr;
+  const T SK = left ? SL : SR, dK = left ? dl : dr;
+  // total energy of the selected side only (the other side's is never used)
+  const T EK = fmad(pK, gm1inv, (T(0.5) * rK) * fmad(uK, uK, fmad(aK, aK, bK * bK)));
   const bool fan = left ? (SL < T(0)) : (SR > T(0));
   const T mK = rK * uK;
   const T FK0 = mK, FK1 = fmad(mK, uK, pK), FK2 = mK * aK, FK3 = mK * bK, FK4 = uK * (EK + pK);

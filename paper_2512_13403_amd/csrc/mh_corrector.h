@@ -14,7 +14,15 @@ constexpr int CORR_OFF_B2 = 32000;
 constexpr int CORR_OFF_W3 = 32032;
 constexpr int CORR_OFF_B3 = 36352;
 constexpr int CORR_NPARAM = 36357;
-constexpr int CORR_CHUNK = 4096;  // cells per weight-gradient workgroup
+constexpr int CORR_CHUNK = 4096;  // cells per bias-gradient partial sum
+constexpr int CORR_BLOCK_CELLS = 256;  // cells per convolution tile (16 x 4 x 4)
+constexpr int CORR_WG_MAX = 512;       // persistent weight-gradient workgroups
+
+// workgroups of the weight-gradient kernel (each writes a [27][32][32] partial)
+inline int corr_wgrad_groups(long long cells) {
+  const long long nb = cells / CORR_BLOCK_CELLS;
+  return (int)(nb < CORR_WG_MAX ? nb : CORR_WG_MAX);
+}
 
 struct CorrStats {
   double mean[5], std[5], scale[5], lw[5];

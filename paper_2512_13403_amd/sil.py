@@ -169,51 +169,67 @@ def rel_l2(a, b) -> float:
     return float(((a - b).double().norm() / b.double().norm()).item())
 
 
-def evaluate(traj: Trajectory, nc: int, res: TrainResult, nsteps: int | None = None) -> dict:
-    """Plain and corrected coarse rollouts from T_0 against the fine run."""
+def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dict:
+    """Plain and corrected coarse rollouts from T_0 of each held-out trajectory
+    against its fine run.  The trajectories advance together, one coarse solver
+    each, and the corrector takes all of them in one batched launch per step.
+    Cost = wall clock of the batched rollout; the fine cost is the summed wall
+    clock of the same trajectories' fine groups."""
     import torch
 
-    n = len(traj.dts) if nsteps is None else nsteps
+    B = len(trajs)
+    n = min(len(t.dts) for t in trajs) if nsteps is None else nsteps
     st = res.stats
-    corr = Corrector(corr_desc(nc, 1, "f32", GAMMA, st["mean"], st["std"], st["scale"],
+    corr = Corrector(corr_desc(nc, B, "f32", GAMMA, st["mean"], st["std"], st["scale"],
                                st["loss_w"], 1e-6, 1e-3))
     corr.set_params(res.theta)
+    solvers = [make_solver(nc, t.seed, 1) for t in trajs]
+    buf = torch.empty((B, 5, nc, nc, nc), dtype=solvers[0].torch_dtype, device=solvers[0].device)
+    cor = torch.empty_like(buf)
+
+    def reset():
+        for c, t in zip(solvers, trajs):
+            c.set_state(t.T[0])
+            c.set_ou_state(t.ahat[0])
+            c.set_clock(float(t.t[0]), int(t.step[0]))
+
+    def advance(k, corrected, stats):
+        for c, t in zip(solvers, trajs):
+            c.step(1, float(t.dts[k]))
+        if not corrected:
+            return 0
+        for i, c in enumerate(solvers):
+            c.get_state_into(buf[i])
+        _, _, fb = corr.apply(buf, cor, stats=stats)
+        for i, c in enumerate(solvers):
+            c.set_state(cor[i])
+        return int(fb) if stats else 0
+
     out = {}
     for mode in ("plain", "corrected"):
-        c = make_solver(nc, traj.seed, 1)
-        c.set_state(traj.T[0])
-        c.set_ou_state(traj.ahat[0])
-        c.set_clock(float(traj.t[0]), int(traj.step[0]))
-        errs, fallbacks = [], 0
-        buf = torch.empty((1, 5, nc, nc, nc), dtype=c.torch_dtype, device=c.device)
-        cor = torch.empty_like(buf)
+        corrected = mode == "corrected"
+        reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(n):
-            c.step(1, float(traj.dts[k]))
-            if mode == "corrected":
-                c.get_state_into(buf)
-                corr.apply(buf, cor, stats=False)
-                c.set_state(cor.view(5, nc, nc, nc))
+            advance(k, corrected, False)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         # errors and fallback counts from a replay (kept out of the timed loop)
-        c.set_state(traj.T[0])
-        c.set_ou_state(traj.ahat[0])
-        c.set_clock(float(traj.t[0]), int(traj.step[0]))
+        reset()
+        errs = [[] for _ in trajs]
+        fallbacks = 0
         for k in range(n):
-            c.step(1, float(traj.dts[k]))
-            if mode == "corrected":
-                c.get_state_into(buf)
-                _, _, fb = corr.apply(buf, cor)
-                fallbacks += int(fb)
-                c.set_state(cor.view(5, nc, nc, nc))
-            errs.append(rel_l2(c.get_state_device()[0], traj.T[k + 1][0]))
-        c.close()
+            fallbacks += advance(k, corrected, True)
+            for i, (c, t) in enumerate(zip(solvers, trajs)):
+                errs[i].append(rel_l2(c.get_state_device()[0], t.T[k + 1][0]))
         out[mode] = dict(rho_rel_l2=errs, seconds=secs, fallbacks=fallbacks)
-    fine_secs = traj.fine_seconds * n / len(traj.dts)
-    out["fine_seconds"] = fine_secs
-    out["cost_ratio"] = fine_secs / out["corrected"]["seconds"]
+    for c in solvers:
+        c.close()
+    fine = sum(t.fine_seconds * n / len(t.dts) for t in trajs)
+    out["fine_seconds"] = fine
+    out["cost_ratio"] = fine / out["corrected"]["seconds"]
+    out["seeds"] = [t.seed for t in trajs]
     return out
 
 
@@ -228,25 +244,30 @@ def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256,
     log(f"[sil] trained {iters} iterations in {res.seconds:.1f} s: loss {res.losses[0]:.4g} -> "
         f"{np.mean(res.losses[-20:]):.4g}")
     del trajs
-    evals = []
-    for s in eval_seeds:
-        tr = record_trajectory(s, nf, r, t_spinup, nsteps)
-        ev = evaluate(tr, nc, res)
-        log(f"[sil] seed {s}: rho L2 plain {ev['plain']['rho_rel_l2'][-1]:.4e} corrected "
-            f"{ev['corrected']['rho_rel_l2'][-1]:.4e} cost ratio {ev['cost_ratio']:.1f}")
-        evals.append(ev)
-    plain = float(np.mean([e["plain"]["rho_rel_l2"][-1] for e in evals]))
-    corrected = float(np.mean([e["corrected"]["rho_rel_l2"][-1] for e in evals]))
-    plain_avg = float(np.mean([np.mean(e["plain"]["rho_rel_l2"]) for e in evals]))
-    corr_avg = float(np.mean([np.mean(e["corrected"]["rho_rel_l2"]) for e in evals]))
+    evt = [record_trajectory(s, nf, r, t_spinup, nsteps) for s in eval_seeds]
+    ev = evaluate(evt, nc, res)
+    fin_p = [e[-1] for e in ev["plain"]["rho_rel_l2"]]
+    fin_c = [e[-1] for e in ev["corrected"]["rho_rel_l2"]]
+    for sd, a, b in zip(ev["seeds"], fin_p, fin_c):
+        log(f"[sil] seed {sd}: rho L2 after {nsteps} coarse steps: plain {a:.4e} corrected {b:.4e}")
+    plain = float(np.mean(fin_p))
+    corrected = float(np.mean(fin_c))
+    plain_avg = float(np.mean(ev["plain"]["rho_rel_l2"]))
+    corr_avg = float(np.mean(ev["corrected"]["rho_rel_l2"]))
+    log(f"[sil] cost: fine {ev['fine_seconds']:.3f} s, corrected coarse "
+        f"{ev['corrected']['seconds']:.3f} s, plain coarse {ev['plain']['seconds']:.3f} s "
+        f"(ratio {ev['cost_ratio']:.1f})")
     return dict(
         fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch,
         rho_rel_l2_plain=plain, rho_rel_l2_corrected=corrected,
         error_ratio=corrected / plain,
         rho_rel_l2_plain_mean_over_steps=plain_avg,
         rho_rel_l2_corrected_mean_over_steps=corr_avg,
-        cost_ratio=float(np.mean([e["cost_ratio"] for e in evals])),
-        fallbacks=int(sum(e["corrected"]["fallbacks"] for e in evals)),
+        cost_ratio=float(ev["cost_ratio"]),
+        fine_seconds=float(ev["fine_seconds"]),
+        corrected_seconds=float(ev["corrected"]["seconds"]),
+        plain_seconds=float(ev["plain"]["seconds"]),
+        fallbacks=int(ev["corrected"]["fallbacks"]),
         train_loss_first=float(res.losses[0]), train_loss_last=float(np.mean(res.losses[-20:])),
         seconds=time.perf_counter() - t0,
     )

@@ -41,8 +41,12 @@ def test_short_study_trains_and_evaluates():
     res = sil.train(trajs, 16, iters=40, batch=2)
     assert np.isfinite(res.losses).all()
     assert np.mean(res.losses[-5:]) < res.losses[0]
-    ev = sil.evaluate(trajs[0], 16, res)
+    ev = sil.evaluate(trajs, 16, res)
     for mode in ("plain", "corrected"):
-        assert len(ev[mode]["rho_rel_l2"]) == 4
-        assert np.isfinite(ev[mode]["rho_rel_l2"]).all()
-    assert ev["cost_ratio"] > 0
+        errs = np.array(ev[mode]["rho_rel_l2"])
+        assert errs.shape == (2, 4) and np.isfinite(errs).all()
+    assert ev["cost_ratio"] > 0 and ev["seeds"] == [0, 1]
+    # the batched corrected rollout equals trajectory-by-trajectory rollouts
+    one = sil.evaluate(trajs[1:], 16, res)
+    assert np.array_equal(np.array(one["corrected"]["rho_rel_l2"][0]),
+                          np.array(ev["corrected"]["rho_rel_l2"][1]))
