@@ -147,10 +147,10 @@ def loss_and_grad_y(Uc, T, weights, sigma):
 
 
 def backward(gUc, cache, scale):
-    """Gradients of the loss w.r.t. the parameters (canonical flat order) and
-    w.r.t. the network input state U (through x only; the residual path adds
-    gUc itself).  Activation gradients are rounded to bf16 where the GPU feeds
-    them to its matrix cores (dY, dZ2, dZ1), weights as in the forward."""
+    """Gradient of the loss w.r.t. the parameters (canonical flat order) from
+    gUc = dL/dU'.  Activation gradients are rounded to bf16 where the GPU feeds
+    them to its matrix cores (dY, dZ2, dZ1), weights as in the forward; dZ1 is
+    left in the cache for input_grad."""
     p, rd = cache["p"], cache["rd"]
     gy = rd(np.moveaxis(gUc, 1, -1) * np.asarray(scale))
     g = {}
@@ -164,7 +164,17 @@ def backward(gUc, cache, scale):
     gz1 = rd(gh1 * gelu_grad(cache["z1"]))
     g["W1"] = conv3_weight_grad(gz1, cache["x"])
     g["b1"] = gz1.sum(axis=(0, 1, 2, 3))
+    cache["gz1"] = gz1
     return pack(g)
+
+
+def input_grad(gUc, cache, std):
+    """dL/dU after backward(): the residual path gUc plus the network path
+    (W1^T conv of dZ1) divided by the standardisation std.  The two-part bf16
+    split of the input is passed through as the identity (its parts sum to x
+    up to rounding)."""
+    gx = conv3_input_grad(cache["gz1"], cache["p"]["W1"])
+    return gUc + np.moveaxis(gx, -1, 1) / np.asarray(std).reshape(1, 5, 1, 1, 1)
 
 
 def adam(theta, m, v, grad, it, lr, b1=0.9, b2=0.999, eps=1e-8):

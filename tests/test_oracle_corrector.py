@@ -99,6 +99,30 @@ def test_backward_matches_finite_differences():
         assert g[q] == pytest.approx(fd, rel=1e-5, abs=1e-12)
 
 
+def test_input_gradient_matches_finite_differences():
+    U, T, theta, mean, std, scale = _setup()
+    w, sig = (4.0, 1.0, 1.0, 1.0, 1.0), std
+
+    def loss(u):
+        Uc, _ = oc.forward(u, theta, mean, std, scale, rounding=False)
+        return oc.loss_and_grad_y(Uc, T, w, sig)[0]
+
+    Uc, cache = oc.forward(U, theta, mean, std, scale, rounding=False)
+    _, gUc = oc.loss_and_grad_y(Uc, T, w, sig)
+    oc.backward(gUc, cache, scale)
+    gU = oc.input_grad(gUc, cache, std)
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        d = rng.standard_normal(U.shape)
+        eps = 1e-6
+        fd = (loss(U + eps * d) - loss(U - eps * d)) / (2 * eps)
+        assert float((gU * d).sum()) == pytest.approx(fd, rel=1e-6)
+    # the network path matters: without it the directional derivative is off
+    d = rng.standard_normal(U.shape)
+    fd = (loss(U + 1e-6 * d) - loss(U - 1e-6 * d)) / 2e-6
+    assert abs(float((gUc * d).sum()) - fd) > 1e-3 * abs(fd)
+
+
 def test_split_input_carries_sixteen_bits():
     rng = np.random.default_rng(7)
     x = np.concatenate([rng.standard_normal(20000) * 10 ** rng.uniform(-3, 1, 20000),
