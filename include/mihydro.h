@@ -249,13 +249,32 @@ mh_status mh_corr_get_params(mh_corr *c, float *theta, int where);
 mh_status mh_corr_apply(mh_corr *c, const void *U, void *U_out, int64_t *floored,
                         int32_t *fell_back);
 /* Loss against the target batch and its gradient in the parameters (to host
- * or device memory); synchronises. */
+ * or device memory): zero_grad + backward(U, target) + get_grad;
+ * synchronises. */
 mh_status mh_corr_loss_grad(mh_corr *c, const void *U, const void *target, double *loss,
                             float *grad, int where);
 /* One ADAM iteration (learning rate lr) on the loss against target; returns
  * the loss before the update when loss is non-null (then synchronises). */
 mh_status mh_corr_train_step(mh_corr *c, const void *U, const void *target, float lr,
                              double *loss);
+/* Sets the accumulated parameter gradient to zero. */
+mh_status mh_corr_zero_grad(mh_corr *c);
+/* Reverse pass at U (the forward pass is recomputed first).  The upstream
+ * gradient dL/dU' is the loss gradient against `target` (when non-NULL; the
+ * loss value goes to *loss when loss is non-NULL, and then the call
+ * synchronises) plus gUc (when non-NULL, a device array like U); at least one
+ * must be given.  The parameter gradient is added to the accumulated one.
+ * When gU is non-NULL it receives dL/dU (device array like U, aliasing
+ * neither U nor gUc): the upstream gradient (residual path) plus the network
+ * path; the positivity floor and the two-part input split pass the gradient
+ * through unchanged.  Used to unroll training through several solver steps
+ * together with mh_adjoint_step. */
+mh_status mh_corr_backward(mh_corr *c, const void *U, const void *target, const void *gUc,
+                           double *loss, void *gU);
+/* One ADAM iteration with the accumulated gradient (learning rate lr). */
+mh_status mh_corr_adam_step(mh_corr *c, float lr);
+/* Copies the accumulated parameter gradient (canonical order). */
+mh_status mh_corr_get_grad(mh_corr *c, float *grad, int where);
 /* Copies an activation of the last forward pass: 0 x (bf16, [cells][32]:
  * channel c < 5 holds hi = bf16(x_c), channel 5 + c holds bf16(x_c - hi)),
  * 1 z1 (fp32, [cells][32]), 2 h1 (bf16), 3 z2 (fp32), 4 h2 (bf16),

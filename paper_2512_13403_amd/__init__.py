@@ -35,7 +35,8 @@ EXPORTED = [
     "mh_query_adjoint_workspace", "mh_adjoint_step", "mh_last_error", "mh_destroy",
     "mh_corr_query_workspace", "mh_corr_init", "mh_corr_set_params", "mh_corr_get_params",
     "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
-    "mh_corr_destroy", "mh_block_average",
+    "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
+    "mh_corr_adam_step", "mh_corr_get_grad",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -123,6 +124,10 @@ def load_library():
             "mh_corr_train_step": [vp, vp, vp, ctypes.c_float, dp],
             "mh_corr_get_activation": [vp, ctypes.c_int, vp, ctypes.c_int],
             "mh_block_average": [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32, vp],
+            "mh_corr_zero_grad": [vp],
+            "mh_corr_backward": [vp, vp, vp, vp, dp, vp],
+            "mh_corr_adam_step": [vp, ctypes.c_float],
+            "mh_corr_get_grad": [vp, vp, ctypes.c_int],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -508,6 +513,34 @@ class Corrector:
                                                 ctypes.byref(loss) if want_loss else None),
                     "mh_corr_train_step")
         return loss.value if want_loss else None
+
+    def zero_grad(self):
+        self._check(self.lib.mh_corr_zero_grad(self.h), "mh_corr_zero_grad")
+
+    def backward(self, U, target=None, gUc=None, want_loss: bool = False,
+                 input_grad: bool = False):
+        """Adds the parameter gradient of one reverse pass at U to the
+        accumulated one; returns (loss or None, dL/dU tensor or None)."""
+        U = self._state(U)
+        tg = self._state(target) if target is not None else None
+        gu = self._state(gUc) if gUc is not None else None
+        gU = self._torch.empty_like(U) if input_grad else None
+        self._keep_bw = (U, tg, gu, gU)
+        loss = ctypes.c_double(0.0)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        self._check(self.lib.mh_corr_backward(self.h, ptr(U), ptr(tg), ptr(gu),
+                                              ctypes.byref(loss) if want_loss else None, ptr(gU)),
+                    "mh_corr_backward")
+        return (loss.value if want_loss else None), gU
+
+    def adam_step(self, lr: float):
+        self._check(self.lib.mh_corr_adam_step(self.h, lr), "mh_corr_adam_step")
+
+    def grad(self) -> np.ndarray:
+        out = np.empty(NPARAM_CORRECTOR, dtype=np.float32)
+        self._check(self.lib.mh_corr_get_grad(self.h, out.ctypes.data_as(ctypes.c_void_p), HOST),
+                    "mh_corr_get_grad")
+        return out
 
     def activation(self, which: int) -> np.ndarray:
         """0 x, 1 z1, 2 h1, 3 z2, 4 h2, 5 y of the last forward pass, as float64

@@ -16,7 +16,8 @@ constexpr size_t CALIGN = 256;
 inline size_t calign(size_t x) { return (x + CALIGN - 1) & ~(CALIGN - 1); }
 
 struct CorrLayout {
-  size_t theta, m, v, grad, w1, w2, w3, w2t, w3t, x0, z1, h1, z2, h2, y, dy16, dy32, dz2, dz1;
+  size_t theta, m, v, grad, w1, w2, w3, w1t, w2t, w3t, x0, z1, h1, z2, h2, y, gx, dy16, dy32, dz2,
+      dz1;
   size_t wpart, bpart, dpart, loss, counters, total;
 };
 
@@ -38,6 +39,7 @@ CorrLayout corr_layout(const mh_corr_desc* d) {
   L.w1 = take(27 * 32 * 32 * 2);
   L.w2 = take(27 * 32 * 32 * 2);
   L.w3 = take(27 * 16 * 32 * 2);
+  L.w1t = take(27 * 16 * 32 * 2);
   L.w2t = take(27 * 32 * 32 * 2);
   L.w3t = take(27 * 32 * 32 * 2);
   L.x0 = take(cells * 32 * 2);
@@ -46,6 +48,7 @@ CorrLayout corr_layout(const mh_corr_desc* d) {
   L.z2 = take(cells * 32 * 4);
   L.h2 = take(cells * 32 * 2);
   L.y = take(cells * 16 * 4);
+  L.gx = take(cells * 16 * 4);
   L.dy16 = take(cells * 16 * 2);
   L.dy32 = take(cells * 32 * 2);
   L.dz2 = take(cells * 32 * 2);
@@ -119,9 +122,9 @@ extern "C" mh_status mh_corr_init(const mh_corr_desc* d, void* workspace, size_t
   char* w = c->ws;
   auto F = [&](size_t o) { return reinterpret_cast<float*>(w + o); };
   auto H = [&](size_t o) { return reinterpret_cast<unsigned short*>(w + o); };
-  c->B = CorrBuffers{F(L.theta), F(L.m), F(L.v), F(L.grad), H(L.w1), H(L.w2), H(L.w3), H(L.w2t),
-                     H(L.w3t), H(L.x0), H(L.h1), H(L.h2), H(L.dy16), H(L.dy32),
-                     H(L.dz2), H(L.dz1), F(L.z1), F(L.z2), F(L.y), F(L.wpart), F(L.bpart),
+  c->B = CorrBuffers{F(L.theta), F(L.m), F(L.v), F(L.grad), H(L.w1), H(L.w2), H(L.w3), H(L.w1t),
+                     H(L.w2t), H(L.w3t), H(L.x0), H(L.h1), H(L.h2), H(L.dy16), H(L.dy32),
+                     H(L.dz2), H(L.dz1), F(L.z1), F(L.z2), F(L.y), F(L.gx), F(L.wpart), F(L.bpart),
                      reinterpret_cast<double*>(w + L.dpart), reinterpret_cast<double*>(w + L.loss),
                      reinterpret_cast<unsigned long long*>(w + L.counters)};
   for (int k = 0; k < 5; ++k) {
@@ -192,10 +195,11 @@ extern "C" mh_status mh_corr_apply(mh_corr* c, const void* U, void* U_out, int64
 }
 
 template <typename T>
-static mh_status loss_grad_impl(mh_corr* c, const T* U, const T* tgt, double* loss) {
+static mh_status backward_impl(mh_corr* c, const T* U, const T* tgt, const T* gup, double* loss,
+                               T* gU) {
   MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, (T*)nullptr, true, c->stream));
-  MH_CHK(corr_loss_backward<T>(c->B, c->st, c->d.n, c->d.batch, U, tgt, c->stream));
-  if (loss) {
+  MH_CHK(corr_backward<T>(c->B, c->st, c->d.n, c->d.batch, U, tgt, gup, gU, c->stream));
+  if (loss && tgt) {
     double l;
     MH_CHK(hipMemcpyAsync(&l, c->B.loss, sizeof l, hipMemcpyDeviceToHost, c->stream));
     MH_CHK(hipStreamSynchronize(c->stream));
@@ -204,19 +208,50 @@ static mh_status loss_grad_impl(mh_corr* c, const T* U, const T* tgt, double* lo
   return MH_OK;
 }
 
+static mh_status backward_any(mh_corr* c, const void* U, const void* tgt, const void* gup,
+                              double* loss, void* gU) {
+  if (c->d.dtype == MH_F64)
+    return backward_impl<double>(c, (const double*)U, (const double*)tgt, (const double*)gup, loss,
+                                 (double*)gU);
+  return backward_impl<float>(c, (const float*)U, (const float*)tgt, (const float*)gup, loss,
+                              (float*)gU);
+}
+
+extern "C" mh_status mh_corr_zero_grad(mh_corr* c) {
+  if (!c) return MH_E_INVALID;
+  MH_CHK(corr_zero_grad(c->B, c->stream));
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_backward(mh_corr* c, const void* U, const void* target,
+                                      const void* gUc, double* loss, void* gU) {
+  if (!c || !U || (!target && !gUc) || (gU && (gU == U || gU == gUc))) return MH_E_INVALID;
+  return backward_any(c, U, target, gUc, loss, gU);
+}
+
+extern "C" mh_status mh_corr_adam_step(mh_corr* c, float lr) {
+  if (!c || !(lr >= 0.0f)) return MH_E_INVALID;
+  c->it += 1;
+  MH_CHK(corr_adam(c->B, c->it, lr, c->stream));
+  return MH_OK;
+}
+
+extern "C" mh_status mh_corr_get_grad(mh_corr* c, float* grad, int where) {
+  if (!c || !grad || (where != MH_HOST && where != MH_DEVICE)) return MH_E_INVALID;
+  MH_CHK(hipMemcpyAsync(grad, c->B.grad, CORR_NPARAM * sizeof(float),
+                        where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                        c->stream));
+  if (where == MH_HOST) MH_CHK(hipStreamSynchronize(c->stream));
+  return MH_OK;
+}
+
 extern "C" mh_status mh_corr_loss_grad(mh_corr* c, const void* U, const void* target, double* loss,
                                        float* grad, int where) {
   if (!c || !U || !target || (grad && where != MH_HOST && where != MH_DEVICE)) return MH_E_INVALID;
-  mh_status s = c->d.dtype == MH_F64
-                    ? loss_grad_impl<double>(c, (const double*)U, (const double*)target, loss)
-                    : loss_grad_impl<float>(c, (const float*)U, (const float*)target, loss);
+  MH_CHK(corr_zero_grad(c->B, c->stream));
+  mh_status s = backward_any(c, U, target, nullptr, loss, nullptr);
   if (s != MH_OK) return s;
-  if (grad) {
-    MH_CHK(hipMemcpyAsync(grad, c->B.grad, CORR_NPARAM * sizeof(float),
-                          where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                          c->stream));
-    MH_CHK(hipStreamSynchronize(c->stream));
-  }
+  if (grad) return mh_corr_get_grad(c, grad, where);
   return MH_OK;
 }
 
@@ -225,9 +260,7 @@ extern "C" mh_status mh_corr_train_step(mh_corr* c, const void* U, const void* t
   if (!c || !U || !target || !(lr >= 0.0f)) return MH_E_INVALID;
   mh_status s = mh_corr_loss_grad(c, U, target, loss, nullptr, MH_DEVICE);
   if (s != MH_OK) return s;
-  c->it += 1;
-  MH_CHK(corr_adam(c->B, c->it, lr, c->stream));
-  return MH_OK;
+  return mh_corr_adam_step(c, lr);
 }
 
 extern "C" mh_status mh_corr_get_activation(mh_corr* c, int which, void* dst, int where) {

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
   }
 }
 
-// gtheta[off + (co * ci_real + ci) * 27 + tap] = sum of the nwg partials
+// gtheta[off + (co * ci_real + ci) * 27 + tap] += sum of the nwg partials
 // [nwg][27][cot][32] in a fixed order; with `fold`, input channel ci also
 // collects channel ci + ci_real (the two bf16 parts of the network input share
 // the first layer's weights)
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     const float* pc = partial + (((long long)c * 27 + tap) * cot + co) * 32;
     s += fold ? pc[ci] + pc[ci + ci_real] : pc[ci];
   }
-  g[i] = s;
+  g[i] += s;
 }
 
 // per-chunk column sums of dz[cell][co] (bias gradients), then the fixed-order total
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(64) void k_colsum_final(const float* __restrict__ p
   if (co >= co_real) return;
   float s = 0.f;
   for (int c = 0; c < nchunk; ++c) s += partial[(long long)c * cot + co];
-  g[co] = s;
+  g[co] += s;
 }
 
 // network input, two bf16 parts per channel: with x32 = float((U_c - mean_c) /
@@ -445,17 +445,27 @@ __global__ __launch_bounds__(256) void k_fallback(const T* __restrict__ U, T* __
   if (counters[1] > 0 || (double)counters[0] > limit) out[i] = U[i];
 }
 
+__global__ __launch_bounds__(256) void k_fill_f32(float* p, int count, float v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
 __global__ __launch_bounds__(64) void k_zero_counters(unsigned long long* c) {
   if (threadIdx.x < 2) c[threadIdx.x] = 0;
 }
 
-// loss L = sum_c w_c mean((U'_c - T_c)^2) / sigma_c^2 (per-block partials) and
-// dY[cell][c] = bf16(scale_c * 2 w_c (U'_c - T_c) / (sigma_c^2 cells))
+// upstream gradient of the network output: with a target T, the loss
+// L = sum_c w_c mean((U'_c - T_c)^2) / sigma_c^2 (per-block partials) and its
+// gradient 2 w_c (U'_c - T_c) / (sigma_c^2 cells); plus gUc = dL/dU' from the
+// caller when given; dY[cell][c] = bf16(scale_c * (sum of both)); the sum
+// itself goes to gfull when given (the residual path of dL/dU)
 template <typename T>
 __global__ __launch_bounds__(256) void k_loss(const T* __restrict__ U, const float* __restrict__ y,
-                                              const T* __restrict__ tgt, int n, long long cells,
+                                              const T* __restrict__ tgt,
+                                              const T* __restrict__ gup, int n, long long cells,
                                               CorrStats st, double* __restrict__ part,
-                                              unsigned short* __restrict__ dy) {
+                                              unsigned short* __restrict__ dy,
+                                              T* __restrict__ gfull) {
   __shared__ double sl[256];
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
   double l = 0.0;
@@ -467,11 +477,17 @@ __global__ __launch_bounds__(256) void k_loss(const T* __restrict__ U, const flo
     for (int c = 0; c < 16; ++c) v[c] = 0;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      const double uc = (double)U[(b * 5 + c) * n3 + q] + st.scale[c] * (double)y[cell * 16 + c];
-      const double d = uc - (double)tgt[(b * 5 + c) * n3 + q];
-      const double s2 = st.std[c] * st.std[c];
-      l += st.lw[c] * d * d / s2;
-      v[c] = f2bf((float)(st.scale[c] * (2.0 * st.lw[c] * d / s2 / (double)cells)));
+      double g = 0.0;
+      if (tgt) {
+        const double uc = (double)U[(b * 5 + c) * n3 + q] + st.scale[c] * (double)y[cell * 16 + c];
+        const double d = uc - (double)tgt[(b * 5 + c) * n3 + q];
+        const double s2 = st.std[c] * st.std[c];
+        l += st.lw[c] * d * d / s2;
+        g = 2.0 * st.lw[c] * d / s2 / (double)cells;
+      }
+      if (gup) g += (double)gup[(b * 5 + c) * n3 + q];
+      if (gfull) gfull[(b * 5 + c) * n3 + q] = (T)g;
+      v[c] = f2bf((float)(st.scale[c] * g));
     }
     __builtin_memcpy(dy + cell * 16, v, 16);
     __builtin_memcpy(dy + cell * 16 + 8, v + 8, 16);
@@ -483,6 +499,25 @@ __global__ __launch_bounds__(256) void k_loss(const T* __restrict__ U, const flo
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sl[0];
+}
+
+// dL/dU += gx_c / std_c (gU holds the upstream gradient of U', the residual
+// path; gx: [cell][16] fp32, the first layer's transposed convolution of dZ1;
+// the two-part input split and the positivity floor pass the gradient
+// through unchanged)
+template <typename T>
+__global__ __launch_bounds__(256) void k_input_grad(const float* __restrict__ gx, int n,
+                                                    long long cells, CorrStats st,
+                                                    T* __restrict__ gU) {
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= cells) return;
+  const long long n3 = (long long)n * n * n;
+  const long long b = cell / n3, q = cell % n3;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const long long o = (b * 5 + c) * n3 + q;
+    gU[o] = (T)((double)gU[o] + (double)gx[cell * 16 + c] / st.std[c]);
+  }
 }
 
 // dY of 16 channels -> 32-channel operand layout for the next MFMA pass
@@ -569,7 +604,7 @@ inline unsigned conv_grid(int n, int batch) {
 
 hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
-                     CORR_OFF_W1, 32, 5, 1, 32, B.w1, 0, (unsigned short*)nullptr);
+                     CORR_OFF_W1, 32, 5, 1, 32, B.w1, 16, B.w1t);
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
                      CORR_OFF_W2, 32, 32, 0, 32, B.w2, 32, B.w2t);
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 16 * 32, 256)), dim3(256), 0, s, B.theta,
@@ -615,13 +650,13 @@ hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch
 }
 
 template <typename T>
-hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch,
-                              const T* U, const T* tgt, hipStream_t s) {
+hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
+                         const T* tgt, const T* gup, T* gU, hipStream_t s) {
   const long long cells = (long long)batch * n * n * n;
   const unsigned conv_blocks = conv_grid(n, batch);
   const unsigned lb = blocks(cells, 256);
-  hipLaunchKernelGGL((k_loss<T>), dim3(lb), dim3(256), 0, s, U, B.y, tgt, n, cells, st, B.dpart,
-                     B.dy16);
+  hipLaunchKernelGGL((k_loss<T>), dim3(lb), dim3(256), 0, s, U, B.y, tgt, gup, n, cells, st,
+                     B.dpart, B.dy16, gU);
   hipLaunchKernelGGL(k_dsum, dim3(1), dim3(64), 0, s, B.dpart, (int)lb, B.loss);
   hipLaunchKernelGGL(k_pad16to32, dim3(lb), dim3(256), 0, s, B.dy16, cells, B.dy32);
   const int chunk = CORR_CHUNK;
@@ -656,6 +691,18 @@ hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, 
                      B.bpart);
   hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
                      B.grad + CORR_OFF_B1);
+  if (gU) {
+    hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_blocks), dim3(256), 0, s, B.dz1, B.w1t,
+                       (const float*)nullptr, 0, n, (const float*)nullptr, B.gx,
+                       (unsigned short*)nullptr);
+    hipLaunchKernelGGL((k_input_grad<T>), dim3(lb), dim3(256), 0, s, B.gx, n, cells, st, gU);
+  }
+  return hipGetLastError();
+}
+
+hipError_t corr_zero_grad(const CorrBuffers& B, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks(CORR_NPARAM, 256)), dim3(256), 0, s, B.grad,
+                     CORR_NPARAM, 0.0f);
   return hipGetLastError();
 }
 
@@ -679,8 +726,8 @@ hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStre
                                       bool, hipStream_t);                                         \
   template hipError_t corr_floor<T>(const CorrBuffers&, const T*, T*, int, int, double, double,    \
                                     double, hipStream_t);                                         \
-  template hipError_t corr_loss_backward<T>(const CorrBuffers&, const CorrStats&, int, int,        \
-                                            const T*, const T*, hipStream_t);                      \
+  template hipError_t corr_backward<T>(const CorrBuffers&, const CorrStats&, int, int, const T*,  \
+                                       const T*, const T*, T*, hipStream_t);                      \
   template hipError_t launch_block_average<T>(const T*, int, int, T*, hipStream_t);
 CORR_INSTANTIATE(float)
 CORR_INSTANTIATE(double)

@@ -30,9 +30,9 @@ struct CorrStats {
 
 struct CorrBuffers {
   float *theta, *m, *v, *grad;
-  unsigned short *w1, *w2, *w3, *w2t, *w3t;
+  unsigned short *w1, *w2, *w3, *w1t, *w2t, *w3t;
   unsigned short *x0, *h1, *h2, *dy16, *dy32, *dz2, *dz1;
-  float *z1, *z2, *y, *wpart, *bpart;
+  float *z1, *z2, *y, *gx, *wpart, *bpart;
   double *dpart, *loss;
   unsigned long long* counters;
 };
@@ -45,8 +45,9 @@ template <typename T>
 hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch, double gamma,
                       double frel, double fallback_frac, hipStream_t s);
 template <typename T>
-hipError_t corr_loss_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch,
-                              const T* U, const T* tgt, hipStream_t s);
+hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
+                         const T* tgt, const T* gup, T* gU, hipStream_t s);
+hipError_t corr_zero_grad(const CorrBuffers& B, hipStream_t s);
 hipError_t corr_adam(const CorrBuffers& B, int it, float lr, hipStream_t s);
 template <typename T>
 hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStream_t s);

@@ -126,19 +126,26 @@ class TrainResult:
 
 
 def train(trajs, nc: int, iters: int = 500, batch: int = 8, lr0: float = 1e-3, lr1: float = 1e-4,
-          loss_w=(4.0, 1.0, 1.0, 1.0, 1.0), seed: int = 0, init_scale: float = 1e-2) -> TrainResult:
-    """Fits the corrector on the single-step pairs of the training trajectories."""
+          loss_w=(4.0, 1.0, 1.0, 1.0, 1.0), seed: int = 0, init_scale: float = 1e-2,
+          unroll: int = 1, unroll_from: float = 0.6) -> TrainResult:
+    """Fits the corrector.  The first iterations use single-step pairs (the
+    plain coarse step from T_k against T_{k+1}); with unroll = m > 1 the
+    iterations after the fraction `unroll_from` run m corrected coarse steps
+    from T_k and back-propagate the summed loss against T_{k+1..k+m} through
+    the corrector (mh_corr_backward) and the hydro step (mh_adjoint_step),
+    solver in the loop.  The learning rate decays geometrically over all
+    iterations."""
     import torch
 
     from workloads import corrector_init_params
 
     P, T = [], []
+    solvers = {}
     for tr in trajs:
-        cs = make_solver(nc, tr.seed, 1)
+        cs = solvers.setdefault(tr.seed, make_solver(nc, tr.seed, 1))
         for k in range(len(tr.dts)):
             P.append(coarse_step_from(cs, tr, k))
             T.append(tr.T[k + 1])
-        cs.close()
     P = torch.stack(P)
     T = torch.stack(T)
     d = (T - P).double()
@@ -146,6 +153,7 @@ def train(trajs, nc: int, iters: int = 500, batch: int = 8, lr0: float = 1e-3, l
     mean = Pd.mean(dim=(0, 2, 3, 4)).cpu().numpy()
     std = Pd.std(dim=(0, 2, 3, 4)).cpu().numpy() + 1e-12
     scale = d.std(dim=(0, 2, 3, 4)).cpu().numpy() + 1e-12
+    del d, Pd
     # relative MSE: the library divides channel c's squared error by std_c^2;
     # weights w_c std_c^2 / scale_c^2 make it sum_c w_c mean(d_c^2) / scale_c^2,
     # i.e. relative to the spread of the residual the network has to predict
@@ -155,13 +163,58 @@ def train(trajs, nc: int, iters: int = 500, batch: int = 8, lr0: float = 1e-3, l
     corr.set_params(corrector_init_params(seed=seed, out_scale=init_scale))
     rng = np.random.default_rng(seed)
     losses = []
+    nk = [len(tr.dts) for tr in trajs]
+    offs = np.cumsum([0] + nk)
+    switch = int(unroll_from * iters) if unroll > 1 else iters
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(iters):
         lr = lr0 * (lr1 / lr0) ** (it / max(iters - 1, 1))
-        idx = torch.as_tensor(rng.integers(0, P.shape[0], batch), device=P.device)
-        losses.append(corr.train_step(P[idx], T[idx], lr))
+        if it < switch:
+            idx = torch.as_tensor(rng.integers(0, P.shape[0], batch), device=P.device)
+            losses.append(corr.train_step(P[idx], T[idx], lr))
+            continue
+        # solver in the loop: m corrected steps from T_k of `batch` windows
+        m = unroll
+        picks = []
+        for _ in range(batch):
+            i = int(rng.integers(0, len(trajs)))
+            picks.append((i, int(rng.integers(0, nk[i] - m + 1))))
+        states = []      # U_{j-1} per step j (list over j of [batch] tensors)
+        preds = []       # P_j = H(U_{j-1})
+        U = torch.stack([trajs[i].T[k] for i, k in picks])
+        for j in range(1, m + 1):
+            states.append(U)
+            Pj = torch.empty_like(U)
+            for b, (i, k) in enumerate(picks):
+                tr = trajs[i]
+                cs = solvers[tr.seed]
+                cs.set_state(U[b])
+                cs.set_ou_state(tr.ahat[k + j - 1])
+                cs.set_clock(float(tr.t[k + j - 1]), int(tr.step[k + j - 1]))
+                cs.step(1, float(tr.dts[k + j - 1]))
+                cs.get_state_into(Pj[b])
+            preds.append(Pj)
+            U, _, _ = corr.apply(Pj, stats=False)
+        corr.zero_grad()
+        lam = None
+        total = 0.0
+        for j in range(m, 0, -1):
+            tgt = torch.stack([trajs[i].T[k + j] for i, k in picks])
+            L, gP = corr.backward(preds[j - 1], tgt, lam, want_loss=True, input_grad=j > 1)
+            total += L
+            if j > 1:
+                lam = torch.empty_like(gP)
+                for b, (i, k) in enumerate(picks):
+                    tr = trajs[i]
+                    solvers[tr.seed].adjoint_step(states[j - 1][b], float(tr.dts[k + j - 1]),
+                                                  int(tr.step[k + j - 1]), gP[b],
+                                                  ou_ahat=tr.ahat[k + j - 1], out=lam[b])
+        corr.adam_step(lr)
+        losses.append(total / m)
     torch.cuda.synchronize()
+    for cs in solvers.values():
+        cs.close()
     return TrainResult(corr.params(), losses, stats, time.perf_counter() - t0)
 
 
@@ -235,12 +288,12 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
 
 def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256, r: int = 4,
               t_spinup: float = 1.0, nsteps: int = 100, iters: int = 500, batch: int = 8,
-              log=print) -> dict:
+              unroll: int = 4, log=print) -> dict:
     nc = nf // r
     t0 = time.perf_counter()
     trajs = [record_trajectory(s, nf, r, t_spinup, nsteps) for s in train_seeds]
     log(f"[sil] recorded {len(trajs)} training trajectories in {time.perf_counter() - t0:.1f} s")
-    res = train(trajs, nc, iters, batch)
+    res = train(trajs, nc, iters, batch, unroll=unroll)
     log(f"[sil] trained {iters} iterations in {res.seconds:.1f} s: loss {res.losses[0]:.4g} -> "
         f"{np.mean(res.losses[-20:]):.4g}")
     del trajs
@@ -258,7 +311,7 @@ def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256,
         f"{ev['corrected']['seconds']:.3f} s, plain coarse {ev['plain']['seconds']:.3f} s "
         f"(ratio {ev['cost_ratio']:.1f})")
     return dict(
-        fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch,
+        fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch, unroll=unroll,
         rho_rel_l2_plain=plain, rho_rel_l2_corrected=corrected,
         error_ratio=corrected / plain,
         rho_rel_l2_plain_mean_over_steps=plain_avg,
@@ -286,8 +339,9 @@ if __name__ == "__main__":
     ap.add_argument("--train-seeds", type=int, default=12)
     ap.add_argument("--eval-seeds", type=int, default=4)
     ap.add_argument("--spinup", type=float, default=1.0)
+    ap.add_argument("--unroll", type=int, default=4)
     a = ap.parse_args()
     out = run_study(range(a.train_seeds), range(a.train_seeds, a.train_seeds + a.eval_seeds),
-                    a.fine, a.ratio, a.spinup, a.steps, a.iters, a.batch,
+                    a.fine, a.ratio, a.spinup, a.steps, a.iters, a.batch, a.unroll,
                     log=lambda m: print(m, flush=True))
     print(json.dumps(out))

@@ -180,6 +180,43 @@ def test_loss_and_gradient(dtype):
     assert cos > 0.9999
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_input_gradient_and_accumulation(dtype):
+    n, batch = 16, 2
+    U = batch_state(n, batch, 90, dtype)
+    T = as_input(U + 0.02 * batch_state(n, batch, 91, "f64"), dtype)
+    gup = as_input(1e-3 * np.random.default_rng(92).standard_normal(U.shape), dtype)
+    loss_w = np.array([4.0, 1.0, 1.0, 1.0, 1.0])
+    c, th, mean, std, scale = make(n, batch, dtype, U, scale=(5e-2,) * 5, loss_w=loss_w)
+    Ud, Td, Gd = torch_dev(U, dtype), torch_dev(T, dtype), torch_dev(gup, dtype)
+    c.zero_grad()
+    L, gU = c.backward(Ud, Td, Gd, want_loss=True, input_grad=True)
+    g1 = c.grad()
+    # the oracle's reverse pass on the GPU's activations, upstream = loss + gup
+    p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
+    x0 = c.activation(0)
+    y = c.activation(5)[:, :5]
+    cache = dict(x=to_oracle(x0[:, :5] + x0[:, 5:10], batch, n),
+                 z1=to_oracle(c.activation(1), batch, n), h1=to_oracle(c.activation(2), batch, n),
+                 z2=to_oracle(c.activation(3), batch, n), h2=to_oracle(c.activation(4), batch, n),
+                 y=to_oracle(y, batch, n), p=p, rd=oc.bf16_round)
+    Uc = U + np.moveaxis(to_oracle(y, batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
+    Lref, gl = oc.loss_and_grad_y(Uc, T, loss_w, std)
+    gref = oc.backward(gl + gup, cache, scale)
+    gUref = oc.input_grad(gl + gup, cache, std)
+    assert L == pytest.approx(Lref, rel=1e-9)
+    assert np.linalg.norm(g1 - gref) / np.linalg.norm(gref) < 2e-3
+    gU = gU.cpu().numpy()
+    assert np.linalg.norm(gU - gUref) / np.linalg.norm(gUref) < 2e-3
+    # the network path is a visible part of dL/dU
+    assert np.linalg.norm(gUref - (gl + gup)) > 1e-2 * np.linalg.norm(gUref)
+    # a second pass accumulates: exactly twice the gradient
+    c.backward(Ud, Td, Gd)
+    assert np.array_equal(c.grad(), 2 * g1)
+    c.zero_grad()
+    assert not c.grad().any()
+
+
 def test_adam_step_and_training_reduces_loss():
     n, batch = 16, 2
     U = batch_state(n, batch, 50, "f32")

@@ -50,3 +50,14 @@ def test_short_study_trains_and_evaluates():
     one = sil.evaluate(trajs[1:], 16, res)
     assert np.array_equal(np.array(one["corrected"]["rho_rel_l2"][0]),
                           np.array(ev["corrected"]["rho_rel_l2"][1]))
+
+
+def test_unrolled_training_through_the_adjoint():
+    """Solver-in-the-loop iterations (3 corrected steps, back-propagated through
+    the corrector and mh_adjoint_step) run and keep the loss finite."""
+    from paper_2512_13403_amd import sil
+
+    trajs = [sil.record_trajectory(seed=s, nf=64, r=4, t_spinup=0.05, nsteps=5) for s in (2, 3)]
+    res = sil.train(trajs, 16, iters=12, batch=2, unroll=3, unroll_from=0.5)
+    assert len(res.losses) == 12 and np.isfinite(res.losses).all()
+    assert np.isfinite(res.theta).all()
