@@ -18,13 +18,12 @@ inline size_t calign(size_t x) { return (x + CALIGN - 1) & ~(CALIGN - 1); }
 struct CorrLayout {
   size_t theta, m, v, grad, w1, w2, w3, w1t, w2t, w3t, x0, z1, h1, z2, h2, y, gx, dy16, dy32, dz2,
       dz1;
-  size_t wpart, bpart, dpart, loss, counters, total;
+  size_t wpart, dpart, loss, counters, total;
 };
 
 CorrLayout corr_layout(const mh_corr_desc* d) {
   CorrLayout L{};
   const size_t cells = (size_t)d->batch * d->n * d->n * d->n;
-  const size_t nchunk = (cells + CORR_CHUNK - 1) / CORR_CHUNK;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -53,8 +52,7 @@ CorrLayout corr_layout(const mh_corr_desc* d) {
   L.dy32 = take(cells * 32 * 2);
   L.dz2 = take(cells * 32 * 2);
   L.dz1 = take(cells * 32 * 2);
-  L.wpart = take((size_t)27 * corr_wgrad_groups((long long)cells) * 32 * 32 * 4);
-  L.bpart = take(nchunk * 32 * 4);
+  L.wpart = take((size_t)28 * corr_wgrad_groups((long long)cells) * 32 * 32 * 4);
   const size_t nd = std::max((cells + 255) / 256, (size_t)d->batch * 64 * 2);
   L.dpart = take(nd * sizeof(double));
   L.loss = take(sizeof(double));
@@ -124,7 +122,7 @@ extern "C" mh_status mh_corr_init(const mh_corr_desc* d, void* workspace, size_t
   auto H = [&](size_t o) { return reinterpret_cast<unsigned short*>(w + o); };
   c->B = CorrBuffers{F(L.theta), F(L.m), F(L.v), F(L.grad), H(L.w1), H(L.w2), H(L.w3), H(L.w1t),
                      H(L.w2t), H(L.w3t), H(L.x0), H(L.h1), H(L.h2), H(L.dy16), H(L.dy32),
-                     H(L.dz2), H(L.dz1), F(L.z1), F(L.z2), F(L.y), F(L.gx), F(L.wpart), F(L.bpart),
+                     H(L.dz2), H(L.dz1), F(L.z1), F(L.z2), F(L.y), F(L.gx), F(L.wpart),
                      reinterpret_cast<double*>(w + L.dpart), reinterpret_cast<double*>(w + L.loss),
                      reinterpret_cast<unsigned long long*>(w + L.counters)};
   for (int k = 0; k < 5; ++k) {

@@ -181,8 +181,9 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
 // gradients in LDS, and wave w accumulates taps w, w + 4, ... in registers
 // over all its blocks: per MFMA the reduction runs over 32 cells (16 along x
 // in two rows), dz^T is the A operand (rows: output channels) and the shifted
-// input the B operand (columns: input channels).  Each workgroup writes its
-// partial [27][COT][32]; k_wgrad_reduce adds them in a fixed order
+// input the B operand (columns: input channels).  Wave 3, which has one tap
+// fewer, also forms the bias gradient (slot 27).  Each workgroup writes its
+// partial [28][COT][32]; k_wgrad_reduce adds them in a fixed order
 // (deterministic, no atomics).
 constexpr int WTAPS = 7;  // taps per wave: ceil(27 / 4)
 
@@ -250,7 +251,18 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
 #pragma unroll
       for (int tt = 0; tt < WTAPS; ++tt) {
         const int tap = wave + 4 * tt;
-        if (tap < 27) {
+        if (tap == 27) {
+          // the bias gradient, sum over cells of dz, as one more product with a
+          // B operand of ones (column 0 of the result is kept)
+          bf16x8 ones;
+          const unsigned short one[8] = {0x3F80, 0x3F80, 0x3F80, 0x3F80,
+                                         0x3F80, 0x3F80, 0x3F80, 0x3F80};
+          __builtin_memcpy(&ones, one, 16);
+#pragma unroll
+          for (int mt = 0; mt < COT / 16; ++mt)
+            acc[tt][mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], ones, acc[tt][mt][0],
+                                                                     0, 0, 0);
+        } else if (tap < 27) {
           const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dzz = tap / 9 - 1;
           const int hrow = ((tz + 1 + dzz) * CHY + (ty + 1 + dy)) * CHX;
 #pragma unroll
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
 #pragma unroll
   for (int tt = 0; tt < WTAPS; ++tt) {
     const int tap = wave + 4 * tt;
-    if (tap < 27) {
+    if (tap < 28) {
 #pragma unroll
       for (int mt = 0; mt < COT / 16; ++mt)
 #pragma unroll
@@ -285,49 +297,52 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int co = mt * 16 + 4 * grp + q, ci = ct * 16 + row;
-            partial[(((long long)blockIdx.x * 27 + tap) * COT + co) * 32 + ci] = acc[tt][mt][ct][q];
+            partial[(((long long)blockIdx.x * 28 + tap) * COT + co) * 32 + ci] = acc[tt][mt][ct][q];
           }
     }
   }
 }
 
 // gtheta[off + (co * ci_real + ci) * 27 + tap] += sum of the nwg partials
-// [nwg][27][cot][32] in a fixed order; with `fold`, input channel ci also
-// collects channel ci + ci_real (the two bf16 parts of the network input share
-// the first layer's weights)
+// [nwg][28][cot][32] in a fixed order (eight interleaved running sums, then
+// their sum); with `fold`, input channel ci also collects channel ci + ci_real
+// (the two bf16 parts of the network input share the first layer's weights).
+// The co_real entries after the weights take the bias gradient (slot 27,
+// column 0) into gb.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int cot,
                                                       int nwg, int co_real, int ci_real,
-                                                      int fold, float* __restrict__ g) {
+                                                      int fold, float* __restrict__ g,
+                                                      float* __restrict__ gb) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= 27 * co_real * ci_real) return;
-  const int tap = i % 27, ci = (i / 27) % ci_real, co = i / (27 * ci_real);
-  float s = 0.f;
-  for (int c = 0; c < nwg; ++c) {
-    const float* pc = partial + (((long long)c * 27 + tap) * cot + co) * 32;
-    s += fold ? pc[ci] + pc[ci + ci_real] : pc[ci];
+  const int nw = 27 * co_real * ci_real;
+  if (i >= nw + co_real) return;
+  int tap, ci, co;
+  if (i < nw) {
+    tap = i % 27;
+    ci = (i / 27) % ci_real;
+    co = i / (27 * ci_real);
+  } else {
+    tap = 27;
+    ci = 0;
+    co = i - nw;
   }
-  g[i] += s;
-}
-
-// per-chunk column sums of dz[cell][co] (bias gradients), then the fixed-order total
-__global__ __launch_bounds__(256) void k_colsum_partial(const unsigned short* __restrict__ dz, int cot,
-                                                        long long cells, int chunk,
-                                                        float* __restrict__ partial) {
-  const int co = threadIdx.x;
-  if (co >= cot) return;
-  const long long c0 = (long long)blockIdx.x * chunk;
-  float s = 0.f;
-  for (long long c = c0; c < c0 + chunk && c < cells; ++c) s += bf2f(dz[c * cot + co]);
-  partial[(long long)blockIdx.x * cot + co] = s;
-}
-
-__global__ __launch_bounds__(64) void k_colsum_final(const float* __restrict__ partial, int cot,
-                                                     int nchunk, int co_real, float* __restrict__ g) {
-  const int co = threadIdx.x;
-  if (co >= co_real) return;
-  float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += partial[(long long)c * cot + co];
-  g[co] += s;
+  const bool two = fold && tap < 27;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int c = 0;
+  for (; c + 8 <= nwg; c += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float* pc = partial + (((long long)(c + u) * 28 + tap) * cot + co) * 32;
+      acc[u] += two ? pc[ci] + pc[ci + ci_real] : pc[ci];
+    }
+  }
+  for (; c < nwg; ++c) {
+    const float* pc = partial + (((long long)c * 28 + tap) * cot + co) * 32;
+    acc[0] += two ? pc[ci] + pc[ci + ci_real] : pc[ci];
+  }
+  const float sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  if (i < nw) g[i] += sum;
+  else gb[co] += sum;
 }
 
 // network input, two bf16 parts per channel: with x32 = float((U_c - mean_c) /
@@ -533,11 +548,17 @@ __global__ __launch_bounds__(256) void k_pad16to32(const unsigned short* __restr
 }
 
 __global__ __launch_bounds__(256) void k_dsum(const double* __restrict__ part, int n, double* out) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s;
+  // fixed-order block reduction: strided per-thread sums, then a tree in LDS
+  __shared__ double sd[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += part[i];
+  sd[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sd[threadIdx.x] += sd[threadIdx.x + st];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = sd[0];
 }
 
 // ADAM on the fp32 master parameters, then the bf16 operand layouts:
@@ -657,40 +678,26 @@ hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int b
   const unsigned lb = blocks(cells, 256);
   hipLaunchKernelGGL((k_loss<T>), dim3(lb), dim3(256), 0, s, U, B.y, tgt, gup, n, cells, st,
                      B.dpart, B.dy16, gU);
-  hipLaunchKernelGGL(k_dsum, dim3(1), dim3(64), 0, s, B.dpart, (int)lb, B.loss);
+  hipLaunchKernelGGL(k_dsum, dim3(1), dim3(256), 0, s, B.dpart, (int)lb, B.loss);
   hipLaunchKernelGGL(k_pad16to32, dim3(lb), dim3(256), 0, s, B.dy16, cells, B.dy32);
-  const int chunk = CORR_CHUNK;
-  const int nchunk = (int)((cells + chunk - 1) / chunk);
   const int nblk = (int)(cells / (CTX * CTY * CTZ));
   const int nwg = corr_wgrad_groups(cells);
   // layer 3: dW3, db3; dH2 -> dZ2 = dH2 * GELU'(Z2)
   hipLaunchKernelGGL((k_wgrad<16>), dim3(nwg), dim3(256), 0, s, B.dy16, B.h2, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32, 256)), dim3(256), 0, s, B.wpart, 16,
-                     nwg, 5, 32, 0, B.grad + CORR_OFF_W3);
-  hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dy16, 16, cells, chunk,
-                     B.bpart);
-  hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 16, nchunk, 5,
-                     B.grad + CORR_OFF_B3);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32 + 5, 256)), dim3(256), 0, s, B.wpart,
+                     16, nwg, 5, 32, 0, B.grad + CORR_OFF_W3, B.grad + CORR_OFF_B3);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dy32, B.w3t,
                      (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2);
   // layer 2
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz2, B.h1, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.wpart, 32,
-                     nwg, 32, 32, 0, B.grad + CORR_OFF_W2);
-  hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz2, 32, cells, chunk,
-                     B.bpart);
-  hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
-                     B.grad + CORR_OFF_B2);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32 + 32, 256)), dim3(256), 0, s,
+                     B.wpart, 32, nwg, 32, 32, 0, B.grad + CORR_OFF_W2, B.grad + CORR_OFF_B2);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dz2, B.w2t,
                      (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1);
   // layer 1
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5, 256)), dim3(256), 0, s, B.wpart, 32,
-                     nwg, 32, 5, 1, B.grad + CORR_OFF_W1);
-  hipLaunchKernelGGL(k_colsum_partial, dim3(nchunk), dim3(64), 0, s, B.dz1, 32, cells, chunk,
-                     B.bpart);
-  hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, B.bpart, 32, nchunk, 32,
-                     B.grad + CORR_OFF_B1);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5 + 32, 256)), dim3(256), 0, s,
+                     B.wpart, 32, nwg, 32, 5, 1, B.grad + CORR_OFF_W1, B.grad + CORR_OFF_B1);
   if (gU) {
     hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_blocks), dim3(256), 0, s, B.dz1, B.w1t,
                        (const float*)nullptr, 0, n, (const float*)nullptr, B.gx,

@@ -14,7 +14,6 @@ constexpr int CORR_OFF_B2 = 32000;
 constexpr int CORR_OFF_W3 = 32032;
 constexpr int CORR_OFF_B3 = 36352;
 constexpr int CORR_NPARAM = 36357;
-constexpr int CORR_CHUNK = 4096;  // cells per bias-gradient partial sum
 constexpr int CORR_BLOCK_CELLS = 256;  // cells per convolution tile (16 x 4 x 4)
 constexpr int CORR_WG_MAX = 512;       // persistent weight-gradient workgroups
 
@@ -32,7 +31,7 @@ struct CorrBuffers {
   float *theta, *m, *v, *grad;
   unsigned short *w1, *w2, *w3, *w1t, *w2t, *w3t;
   unsigned short *x0, *h1, *h2, *dy16, *dy32, *dz2, *dz1;
-  float *z1, *z2, *y, *gx, *wpart, *bpart;
+  float *z1, *z2, *y, *gx, *wpart;
   double *dpart, *loss;
   unsigned long long* counters;
 };
