@@ -8,10 +8,13 @@ region holds exactly --steps steps, bracketed by device synchronisation; the
 state is resident in HBM before it starts.  Prints one JSON line.
 
 value            cell-updates/s = cells * steps / seconds of the timed region
-roofline         the dominant kernel (RK stage 2) against the MI355X HBM peak:
-                 algorithmic bytes per launch (60 B per cell in fp32: read U1,
-                 read U^n, write U^{n+1}) over its mean duration from HIP events
-                 recorded around every launch on the library's stream
+roofline         the dominant kernel (RK stage 2), which is bound by the fp32
+                 vector ALU: algorithmic FLOPs per launch (594 per cell) over
+                 its mean duration from HIP events recorded around every launch
+                 on the library's stream, against the fp32 vector peak;
+                 `traffic` = HBM bytes per launch from the committed counter
+                 summary (null when the kernel source changed since); the HBM
+                 fractions of the metric are in `config`
 cpu_baseline     the FP64 oracle on the same physics at 192^3 for 16 steps
 corrector        the solver-in-the-loop study: density L2 error of the plain and
                  the corrected 64^3 runs against the block-averaged 256^3 run,
@@ -29,6 +32,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X fp32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz =
+# 78.6 TFLOP/s with one-lane-per-op instructions, 157.3 with packed FP32
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# algorithmic floating-point operations per cell of one RK stage of the fp32
+# method (primitive recovery, 3 faces of limited slopes + face states + HLLC,
+# conservative update; stage 2 adds the RK combination, OU kick, exact cooling
+# and the CFL signal speed): FMA = 2, every other arithmetic, min/max, compare
+# or select, reciprocal, square root, exp or log = 1
+FLOP_STAGE1 = 486
+FLOP_STAGE2 = 594
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_k_stage_512_fp32.md")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2512_13403_amd", "csrc", f)
                for f in ("hydro_kernels.hip", "mh_device.h")]
@@ -171,6 +184,7 @@ def main():
     ach2 = bytes2 / (st2_ms / 1e3) / 1e9
     ach1 = bytes1 / (st1_ms / 1e3) / 1e9
     traffic = measured_traffic() if args.dtype == "f32" and n == 512 else None
+    flops2 = FLOP_STAGE2 * N / (st2_ms / 1e3) / 1e12
     rec = {
         "metric": "cell-updates/s & %HBM BW at 512^3 fp32; corrected-64^3 L2 err vs plain",
         "value": value,
@@ -195,16 +209,22 @@ def main():
             "stage2_ms": st2_ms,
             "prologue_ms": ms[mh.TIME_PROLOGUE] / max(launches[mh.TIME_PROLOGUE], 1),
             "stage1_GBps": ach1,
+            "stage2_GBps": ach2,
+            "hbm_frac_stage2_algorithmic": ach2 / HBM_PEAK_GBS,
+            "hbm_frac_stage2_measured": (traffic / (st2_ms / 1e3) / 1e9 / HBM_PEAK_GBS
+                                         if traffic else None),
+            "hbm_frac_step_algorithmic": 25 * es * value / 1e9 / HBM_PEAK_GBS,
             "t_end": t_sim,
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "kernel": "k_stage<2> (RK stage 2 + forcing + cooling + CFL max)",
-            "achieved": ach2,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": ach2 / HBM_PEAK_GBS,
+            "achieved": flops2,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": flops2 / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
+            "flop_per_cell": FLOP_STAGE2,
         },
     }
     del s
