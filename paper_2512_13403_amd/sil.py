@@ -127,14 +127,14 @@ class TrainResult:
 
 def train(trajs, nc: int, iters: int = 500, batch: int = 8, lr0: float = 1e-3, lr1: float = 1e-4,
           loss_w=(4.0, 1.0, 1.0, 1.0, 1.0), seed: int = 0, init_scale: float = 1e-2,
-          unroll: int = 1, unroll_from: float = 0.6) -> TrainResult:
-    """Fits the corrector.  The first iterations use single-step pairs (the
-    plain coarse step from T_k against T_{k+1}); with unroll = m > 1 the
-    iterations after the fraction `unroll_from` run m corrected coarse steps
-    from T_k and back-propagate the summed loss against T_{k+1..k+m} through
-    the corrector (mh_corr_backward) and the hydro step (mh_adjoint_step),
-    solver in the loop.  The learning rate decays geometrically over all
-    iterations."""
+          schedule=((1.0, 1),)) -> TrainResult:
+    """Fits the corrector in `iters` ADAM iterations; `schedule` lists
+    (fraction of the iterations, unroll m) phases in order.  m = 1 uses
+    single-step pairs (the plain coarse step from T_k against T_{k+1}); m > 1
+    runs m corrected coarse steps from T_k and back-propagates the summed loss
+    against T_{k+1..k+m} through the corrector (mh_corr_backward) and the
+    hydro step (mh_adjoint_step): the solver in the loop.  The learning rate
+    decays geometrically over all iterations."""
     import torch
 
     from workloads import corrector_init_params
@@ -165,17 +165,20 @@ def train(trajs, nc: int, iters: int = 500, batch: int = 8, lr0: float = 1e-3, l
     losses = []
     nk = [len(tr.dts) for tr in trajs]
     offs = np.cumsum([0] + nk)
-    switch = int(unroll_from * iters) if unroll > 1 else iters
+    phase_m = []
+    for frac, m in schedule:
+        phase_m += [int(m)] * int(round(frac * iters))
+    phase_m = (phase_m + [phase_m[-1]] * iters)[:iters]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(iters):
         lr = lr0 * (lr1 / lr0) ** (it / max(iters - 1, 1))
-        if it < switch:
+        m = phase_m[it]
+        if m == 1:
             idx = torch.as_tensor(rng.integers(0, P.shape[0], batch), device=P.device)
             losses.append(corr.train_step(P[idx], T[idx], lr))
             continue
         # solver in the loop: m corrected steps from T_k of `batch` windows
-        m = unroll
         picks = []
         for _ in range(batch):
             i = int(rng.integers(0, len(trajs)))
@@ -287,13 +290,13 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
 
 
 def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256, r: int = 4,
-              t_spinup: float = 1.0, nsteps: int = 100, iters: int = 500, batch: int = 8,
-              unroll: int = 4, log=print) -> dict:
+              t_spinup: float = 1.0, nsteps: int = 100, iters: int = 500, batch: int = 4,
+              schedule=((0.1, 1), (0.3, 8), (0.6, 32)), log=print) -> dict:
     nc = nf // r
     t0 = time.perf_counter()
     trajs = [record_trajectory(s, nf, r, t_spinup, nsteps) for s in train_seeds]
     log(f"[sil] recorded {len(trajs)} training trajectories in {time.perf_counter() - t0:.1f} s")
-    res = train(trajs, nc, iters, batch, unroll=unroll)
+    res = train(trajs, nc, iters, batch, schedule=schedule)
     log(f"[sil] trained {iters} iterations in {res.seconds:.1f} s: loss {res.losses[0]:.4g} -> "
         f"{np.mean(res.losses[-20:]):.4g}")
     del trajs
@@ -311,7 +314,8 @@ def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256,
         f"{ev['corrected']['seconds']:.3f} s, plain coarse {ev['plain']['seconds']:.3f} s "
         f"(ratio {ev['cost_ratio']:.1f})")
     return dict(
-        fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch, unroll=unroll,
+        fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch,
+        schedule=[list(p) for p in schedule],
         rho_rel_l2_plain=plain, rho_rel_l2_corrected=corrected,
         error_ratio=corrected / plain,
         rho_rel_l2_plain_mean_over_steps=plain_avg,
@@ -335,13 +339,17 @@ if __name__ == "__main__":
     ap.add_argument("--ratio", type=int, default=4)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--iters", type=int, default=500)
-    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--train-seeds", type=int, default=12)
     ap.add_argument("--eval-seeds", type=int, default=4)
     ap.add_argument("--spinup", type=float, default=1.0)
-    ap.add_argument("--unroll", type=int, default=4)
+    ap.add_argument("--unroll", type=int, default=32,
+                    help="longest unroll: 10 %% of the iterations on pairs, 30 %% at "
+                         "unroll/4, 60 %% at unroll")
     a = ap.parse_args()
     out = run_study(range(a.train_seeds), range(a.train_seeds, a.train_seeds + a.eval_seeds),
-                    a.fine, a.ratio, a.spinup, a.steps, a.iters, a.batch, a.unroll,
+                    a.fine, a.ratio, a.spinup, a.steps, a.iters, a.batch,
+                    ((0.1, 1), (0.3, max(a.unroll // 4, 1)), (0.6, a.unroll))
+                    if a.unroll > 1 else ((1.0, 1),),
                     log=lambda m: print(m, flush=True))
     print(json.dumps(out))

@@ -58,6 +58,26 @@ def test_unrolled_training_through_the_adjoint():
     from paper_2512_13403_amd import sil
 
     trajs = [sil.record_trajectory(seed=s, nf=64, r=4, t_spinup=0.05, nsteps=5) for s in (2, 3)]
-    res = sil.train(trajs, 16, iters=12, batch=2, unroll=3, unroll_from=0.5)
+    res = sil.train(trajs, 16, iters=12, batch=2, schedule=((0.5, 1), (0.5, 3)))
     assert len(res.losses) == 12 and np.isfinite(res.losses).all()
     assert np.isfinite(res.theta).all()
+
+
+def test_trained_corrector_beats_the_plain_coarse_run():
+    """What the learned part gains: a corrector trained through the solver
+    (pairs, then unrolls of 4 and 16 steps back-propagated through
+    mh_adjoint_step) lowers the density L2 error of held-out 32^3 runs against
+    the block-averaged 128^3 run, over 50 coarse steps, below the plain 32^3
+    run's.  Everything is seeded and the kernels are deterministic."""
+    from paper_2512_13403_amd import sil
+
+    train = [sil.record_trajectory(s, 128, 4, 1.0, 50) for s in range(6)]
+    held = [sil.record_trajectory(s, 128, 4, 1.0, 50) for s in (100, 101)]
+    res = sil.train(train, 32, iters=300, batch=4, schedule=((0.1, 1), (0.3, 4), (0.6, 16)))
+    ev = sil.evaluate(held, 32, res)
+    plain = np.array(ev["plain"]["rho_rel_l2"])
+    corr = np.array(ev["corrected"]["rho_rel_l2"])
+    print(f"rho rel. L2 after 50 steps: plain {plain[:, -1]}, corrected {corr[:, -1]}")
+    assert ev["corrected"]["fallbacks"] == 0
+    assert corr[:, -1].mean() < 0.95 * plain[:, -1].mean()
+    assert corr.mean() < plain.mean()
