@@ -309,6 +309,12 @@ mh_status mh_get_timing(mh_ctx *ctx, double *ms, int64_t *launches);
 mh_status mh_set_potential(mh_ctx *ctx, const void *phi, int where);
 
 /* Message of the last failed call on ctx (empty string if none). */
+/* Multigrid V-cycles are replayed from HIP graphs captured on first use
+ * (one V-cycle is ~60 small launches); enable = 0 launches them kernel by
+ * kernel instead.  Default on; results are identical either way.
+ * Synchronises. */
+mh_status mh_set_graphs(mh_ctx *ctx, int enable);
+
 const char *mh_last_error(const mh_ctx *ctx);
 
 /* Waits for the context's stream, then frees the host context (not the

@@ -36,7 +36,7 @@ EXPORTED = [
     "mh_corr_query_workspace", "mh_corr_init", "mh_corr_set_params", "mh_corr_get_params",
     "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
     "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
-    "mh_corr_adam_step", "mh_corr_get_grad",
+    "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -125,6 +125,7 @@ def load_library():
             "mh_corr_get_activation": [vp, ctypes.c_int, vp, ctypes.c_int],
             "mh_block_average": [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32, vp],
             "mh_corr_zero_grad": [vp],
+            "mh_set_graphs": [vp, ctypes.c_int],
             "mh_corr_backward": [vp, vp, vp, vp, dp, vp],
             "mh_corr_adam_step": [vp, ctypes.c_float],
             "mh_corr_get_grad": [vp, vp, ctypes.c_int],
@@ -320,6 +321,11 @@ class Solver:
         c = ctypes.c_int32()
         self._check(self.lib.mh_last_mg_cycles(self.ctx, ctypes.byref(c)), "mh_last_mg_cycles")
         return c.value
+
+    def set_graphs(self, enable: bool):
+        """Multigrid V-cycles from captured HIP graphs (default) or launched
+        kernel by kernel."""
+        self._check(self.lib.mh_set_graphs(self.ctx, int(bool(enable))), "mh_set_graphs")
 
     def set_timing(self, enable: bool):
         """Records HIP events around every kernel launch of step()."""

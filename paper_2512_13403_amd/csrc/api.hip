@@ -140,6 +140,8 @@ struct mh_ctx {
   std::string err;
   // kernel timing (mh_set_timing): event pairs and the kind of each pair
   bool timing = false;
+  // V-cycle graphs of the step's solver and of the adjoint's second solve
+  MGGraphCache mg_graphs, adj_graphs;
   std::vector<hipEvent_t> ev;
   std::vector<int> kinds;
   int64_t untimed = 0;
@@ -265,6 +267,7 @@ extern "C" mh_status mh_init(const mh_grid_desc* grid, const mh_physics_desc* ph
   c->ws = (char*)workspace;
   c->ws_bytes = workspace_bytes;
   c->L = L;
+  c->L.mg.graphs = &c->mg_graphs;
   c->nmodes = nm;
   DevClock hc{};
   hc.bad_first = ~0ull;
@@ -681,6 +684,7 @@ extern "C" mh_status mh_adjoint_step(mh_ctx* c, void* adj_workspace, size_t adj_
     return set_err(c, MH_E_INVALID, "mh_adjoint_step: forcing is on but ou_ahat is NULL");
   if (!(dt >= 0.0) || step < 0) return set_err(c, MH_E_INVALID, "mh_adjoint_step: bad dt or step");
   AdjLayout A = make_adj_layout(c->g, c->p);
+  A.mg.graphs = &c->adj_graphs;
   if (!adj_workspace || adj_workspace_bytes < A.total || ((uintptr_t)adj_workspace % ALIGN) != 0)
     return set_err(c, MH_E_WORKSPACE, "mh_adjoint_step: adjoint workspace too small or misaligned");
   char* ws = (char*)adj_workspace;
@@ -731,9 +735,21 @@ extern "C" mh_status mh_set_potential(mh_ctx* c, const void* phi, int where) {
 
 extern "C" const char* mh_last_error(const mh_ctx* c) { return c ? c->err.c_str() : ""; }
 
+extern "C" mh_status mh_set_graphs(mh_ctx* c, int enable) {
+  if (!c) return MH_E_INVALID;
+  MH_HIP(c, hipStreamSynchronize(c->stream));
+  for (MGGraphCache* G : {&c->mg_graphs, &c->adj_graphs}) {
+    G->enabled = enable != 0;
+    if (!G->enabled) G->reset();
+  }
+  return MH_OK;
+}
+
 extern "C" void mh_destroy(mh_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  c->mg_graphs.destroy();
+  c->adj_graphs.destroy();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }

@@ -304,16 +304,18 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
 }
 
 // gtheta[off + (co * ci_real + ci) * 27 + tap] += sum of the nwg partials
-// [nwg][28][cot][32] in a fixed order (eight interleaved running sums, then
-// their sum); with `fold`, input channel ci also collects channel ci + ci_real
-// (the two bf16 parts of the network input share the first layer's weights).
-// The co_real entries after the weights take the bias gradient (slot 27,
-// column 0) into gb.
+// [nwg][28][cot][32]; with `fold`, input channel ci also collects channel
+// ci + ci_real (the two bf16 parts of the network input share the first
+// layer's weights).  The co_real entries after the weights take the bias
+// gradient (slot 27, column 0) into gb.  Each output is summed by 32 lanes of
+// a wave (lane l takes partials l, l + 32, ...), then by a fixed butterfly:
+// the order is fixed, so the result is deterministic.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int cot,
                                                       int nwg, int co_real, int ci_real,
                                                       int fold, float* __restrict__ g,
                                                       float* __restrict__ gb) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int l = threadIdx.x & 31;
   const int nw = 27 * co_real * ci_real;
   if (i >= nw + co_real) return;
   int tap, ci, co;
@@ -327,22 +329,17 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     co = i - nw;
   }
   const bool two = fold && tap < 27;
-  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int c = 0;
-  for (; c + 8 <= nwg; c += 8) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const float* pc = partial + (((long long)(c + u) * 28 + tap) * cot + co) * 32;
-      acc[u] += two ? pc[ci] + pc[ci + ci_real] : pc[ci];
-    }
-  }
-  for (; c < nwg; ++c) {
+  float acc = 0.f;
+  for (int c = l; c < nwg; c += 32) {
     const float* pc = partial + (((long long)c * 28 + tap) * cot + co) * 32;
-    acc[0] += two ? pc[ci] + pc[ci + ci_real] : pc[ci];
+    acc += two ? pc[ci] + pc[ci + ci_real] : pc[ci];
   }
-  const float sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-  if (i < nw) g[i] += sum;
-  else gb[co] += sum;
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+  if (l == 0) {
+    if (i < nw) g[i] += acc;
+    else gb[co] += acc;
+  }
 }
 
 // network input, two bf16 parts per channel: with x32 = float((U_c - mean_c) /
@@ -684,19 +681,19 @@ hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int b
   const int nwg = corr_wgrad_groups(cells);
   // layer 3: dW3, db3; dH2 -> dZ2 = dH2 * GELU'(Z2)
   hipLaunchKernelGGL((k_wgrad<16>), dim3(nwg), dim3(256), 0, s, B.dy16, B.h2, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32 + 5, 256)), dim3(256), 0, s, B.wpart,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32 + 5, 8)), dim3(256), 0, s, B.wpart,
                      16, nwg, 5, 32, 0, B.grad + CORR_OFF_W3, B.grad + CORR_OFF_B3);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dy32, B.w3t,
                      (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2);
   // layer 2
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz2, B.h1, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32 + 32, 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32 + 32, 8)), dim3(256), 0, s,
                      B.wpart, 32, nwg, 32, 32, 0, B.grad + CORR_OFF_W2, B.grad + CORR_OFF_B2);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dz2, B.w2t,
                      (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1);
   // layer 1
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5 + 32, 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5 + 32, 8)), dim3(256), 0, s,
                      B.wpart, 32, nwg, 32, 5, 1, B.grad + CORR_OFF_W1, B.grad + CORR_OFF_B1);
   if (gU) {
     hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_blocks), dim3(256), 0, s, B.dz1, B.w1t,

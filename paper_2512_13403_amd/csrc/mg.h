@@ -22,11 +22,27 @@ struct MGLevel {
   size_t r;       // residual
 };
 
+// V-cycles replayed from captured HIP graphs: one V-cycle is ~60 small
+// launches, so on a mid-size grid it is launch-bound when issued one kernel
+// at a time.  A cache holds one executable graph per parity of the fine-level
+// ping-pong buffer, valid for one workspace base address (the nodes hold raw
+// pointers); it is captured on a private stream and launched on the caller's.
+struct MGGraphCache {
+  bool enabled = true;
+  hipStream_t cs = nullptr;
+  char* ws = nullptr;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int cur_after[2] = {0, 0};
+  void reset();     // drops the executable graphs (keeps the stream)
+  void destroy();   // drops everything
+};
+
 struct MGLayout {
   int nlev = 0;
   MGLevel lev[MG_MAX_LEVELS];
   size_t partial = 0;  // MG_PARTIALS doubles
   int cur0 = 0;        // which fine-level phi buffer holds the solution
+  MGGraphCache* graphs = nullptr;  // not owned; null: launch kernel by kernel
 };
 
 mh_status mg_validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string& err);

@@ -161,10 +161,13 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nc, const T* __restrict
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_solve(int n, T h2, const T* __restrict__ F,
                                                       T* __restrict__ phi, int sweeps) {
-  __shared__ T a[MG_COARSE_MAX_CELLS], b[MG_COARSE_MAX_CELLS];
+  __shared__ T a[MG_COARSE_MAX_CELLS], b[MG_COARSE_MAX_CELLS], f[MG_COARSE_MAX_CELLS];
   __shared__ double sh[256];
   const int N = n * n * n;
-  for (int q = threadIdx.x; q < N; q += 256) a[q] = T(0);
+  for (int q = threadIdx.x; q < N; q += 256) {
+    a[q] = T(0);
+    f[q] = F[q];  // the right-hand side stays in LDS for all sweeps
+  }
   __syncthreads();
   const T w = T(2) / T(3);
   T* src = a;
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int n, T h2, const T* __re
   for (int s = 0; s < sweeps; ++s) {
     for (int q = threadIdx.x; q < N; q += 256) {
       const int i = q % n, j = (q / n) % n, k = q / (n * n);
-      dst[q] = (T(1) - w) * src[q] + (w / T(6)) * (nb6(src, n, i, j, k) - h2 * F[q]);
+      dst[q] = (T(1) - w) * src[q] + (w / T(6)) * (nb6(src, n, i, j, k) - h2 * f[q]);
     }
     __syncthreads();
     T* t = src;
@@ -183,6 +186,145 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int n, T h2, const T* __re
   for (int q = threadIdx.x; q < N; q += 256) s += (double)src[q];
   const double mean = block_sum256(s, sh) / (double)N;
   for (int q = threadIdx.x; q < N; q += 256) phi[q] = src[q] - (T)mean;
+}
+
+// The bottom of the V-cycle in one workgroup.  Every level with at most
+// MG_TAIL_MAX_CELLS cells lives in LDS (the levels below a 16^3 level take
+// 4096 + 512 + 64 + ... cells), so the ~20 small launches those levels would
+// cost (sweeps, residual, restriction, mean removal, coarse solve,
+// prolongation) become one.  On entry F of the tail's first level is its
+// restricted, mean-free right-hand side; on exit phi0 holds its correction
+// after post-smoothing.  The arithmetic of each step is that of the
+// corresponding kernel above; the means are summed with a different fixed
+// tree.
+constexpr int MG_TAIL_MAX_CELLS = 4096;
+constexpr int MG_TAIL_ALLOC = 4688;  // >= 4096 * 8 / 7: all levels of the tail
+constexpr int MG_TAIL_THREADS = 1024;
+
+template <typename T>
+struct TailArgs {
+  int nl;                    // levels in the tail (>= 2)
+  int n[MG_MAX_LEVELS];      // cells per axis
+  T h2[MG_MAX_LEVELS];       // h^2
+  T ih2[MG_MAX_LEVELS];      // 1 / h^2
+  int off[MG_MAX_LEVELS];    // offset of each level in the LDS arrays
+  const T* F0;               // right-hand side of the first level (global)
+  T* phi0;                   // its correction (global, written)
+  int pre, post, csweeps;
+};
+
+__device__ __forceinline__ double block_sum1024(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = MG_TAIL_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__device__ void tail_sweeps(T* pa, T* pb, const T* ff, int o, int n, T h2, int sweeps, int& cur) {
+  const int N = n * n * n;
+  const T w = T(2) / T(3);
+  for (int it = 0; it < sweeps; ++it) {
+    const T* src = (cur ? pb : pa) + o;
+    T* dst = (cur ? pa : pb) + o;
+    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) {
+      const int i = q % n, j = (q / n) % n, k = q / (n * n);
+      dst[q] = (T(1) - w) * src[q] + (w / T(6)) * (nb6(src, n, i, j, k) - h2 * ff[o + q]);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(MG_TAIL_THREADS) void k_vcycle_tail(TailArgs<T> t) {
+  __shared__ T pa[MG_TAIL_ALLOC], pb[MG_TAIL_ALLOC], ff[MG_TAIL_ALLOC];
+  __shared__ double sh[MG_TAIL_THREADS];
+  int cur[MG_MAX_LEVELS];
+  {
+    const int N0 = t.n[0] * t.n[0] * t.n[0];
+    for (int q = threadIdx.x; q < N0; q += MG_TAIL_THREADS) ff[t.off[0] + q] = t.F0[q];
+  }
+  for (int l = 0; l < t.nl - 1; ++l) {
+    const int n = t.n[l], N = n * n * n, o = t.off[l];
+    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) pa[o + q] = T(0);
+    cur[l] = 0;
+    __syncthreads();
+    tail_sweeps(pa, pb, ff, o, n, t.h2[l], t.pre, cur[l]);
+    // restricted residual: F_{l+1} = average over the 8 children of F - A phi
+    const T* phi = (cur[l] ? pb : pa) + o;
+    const int nc = t.n[l + 1], Nc = nc * nc * nc, oc = t.off[l + 1];
+    for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) {
+      const int I = Q % nc, J = (Q / nc) % nc, K = Q / (nc * nc);
+      T sum = T(0);
+      for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+          for (int a = 0; a < 2; ++a) {
+            const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+            const int q = (k * n + j) * n + i;
+            sum += ff[o + q] - (nb6(phi, n, i, j, k) - T(6) * phi[q]) * t.ih2[l];
+          }
+      ff[oc + Q] = T(0.125) * sum;
+    }
+    __syncthreads();
+    double m = 0.0;
+    for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) m += (double)ff[oc + Q];
+    const T mean = (T)(block_sum1024(m, sh) / (double)Nc);
+    for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) ff[oc + Q] = ff[oc + Q] - mean;
+    __syncthreads();
+  }
+  {
+    // coarsest level: phi = 0, sweeps, remove the mean (as k_coarse_solve)
+    const int l = t.nl - 1, n = t.n[l], N = n * n * n, o = t.off[l];
+    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) pa[o + q] = T(0);
+    cur[l] = 0;
+    __syncthreads();
+    tail_sweeps(pa, pb, ff, o, n, t.h2[l], t.csweeps, cur[l]);
+    T* phi = (cur[l] ? pb : pa) + o;
+    double m = 0.0;
+    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) m += (double)phi[q];
+    const double mean = block_sum1024(m, sh) / (double)N;
+    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) phi[q] = phi[q] - (T)mean;
+    __syncthreads();
+  }
+  for (int l = t.nl - 2; l >= 0; --l) {
+    // cell-centred trilinear prolongation of the coarse correction, added
+    const int nc = t.n[l + 1], nf = t.n[l], Nf = nf * nf * nf;
+    const T* ec = (cur[l + 1] ? pb : pa) + t.off[l + 1];
+    T* phif = (cur[l] ? pb : pa) + t.off[l];
+    for (int q = threadIdx.x; q < Nf; q += MG_TAIL_THREADS) {
+      const int i = q % nf, j = (q / nf) % nf, k = q / (nf * nf);
+      const int I = i >> 1, J = j >> 1, K = k >> 1;
+      const int I2 = wrapi(I + ((i & 1) ? 1 : -1), nc);
+      const int J2 = wrapi(J + ((j & 1) ? 1 : -1), nc);
+      const int K2 = wrapi(K + ((k & 1) ? 1 : -1), nc);
+      auto at = [&](int a, int b, int c) { return ec[(c * nc + b) * nc + a]; };
+      const T w0 = T(0.75), w1 = T(0.25);
+      T e = T(0);
+      e += w0 * w0 * w0 * at(I, J, K);
+      e += w1 * w0 * w0 * at(I2, J, K);
+      e += w0 * w1 * w0 * at(I, J2, K);
+      e += w1 * w1 * w0 * at(I2, J2, K);
+      e += w0 * w0 * w1 * at(I, J, K2);
+      e += w1 * w0 * w1 * at(I2, J, K2);
+      e += w0 * w1 * w1 * at(I, J2, K2);
+      e += w1 * w1 * w1 * at(I2, J2, K2);
+      phif[q] += e;
+    }
+    __syncthreads();
+    tail_sweeps(pa, pb, ff, t.off[l], nf, t.h2[l], t.post, cur[l]);
+  }
+  {
+    const int N0 = t.n[0] * t.n[0] * t.n[0];
+    const T* phi = (cur[0] ? pb : pa) + t.off[0];
+    for (int q = threadIdx.x; q < N0; q += MG_TAIL_THREADS) t.phi0[q] = phi[q];
+  }
 }
 
 // gravity kick g = -(phi_{i+1} - phi_{i-1}) / (2h) with m += rho g dt,
@@ -277,7 +419,17 @@ hipError_t vcycle(char* ws, MGLayout& L, const mh_physics_desc& p, double* parti
   const int nl = L.nlev;
   int cur[MG_MAX_LEVELS];
   cur[0] = L.cur0;
-  for (int l = 0; l < nl - 1; ++l) {
+  // first level handled by the single-workgroup tail (fine level excluded:
+  // it starts from the previous solution, the tail from zero)
+  int l0 = nl;
+  for (int l = 1; l < nl - 1; ++l) {
+    const long long Nl = (long long)L.lev[l].n * L.lev[l].n * L.lev[l].n;
+    if (Nl <= MG_TAIL_MAX_CELLS) {
+      l0 = l;
+      break;
+    }
+  }
+  for (int l = 0; l < nl - 1 && l < l0; ++l) {
     MGLevel& lv = L.lev[l];
     const long long N = (long long)lv.n * lv.n * lv.n;
     const T h2 = (T)(lv.h * lv.h);
@@ -299,7 +451,27 @@ hipError_t vcycle(char* ws, MGLayout& L, const mh_physics_desc& p, double* parti
     hipError_t e = remove_mean(P<T>(ws, cv.F), Nc, partial, mean_slot, s);
     if (e != hipSuccess) return e;
   }
-  {
+  if (l0 < nl) {
+    TailArgs<T> t{};
+    t.nl = nl - l0;
+    int off = 0;
+    for (int m = 0; m < t.nl; ++m) {
+      const MGLevel& lv = L.lev[l0 + m];
+      t.n[m] = lv.n;
+      t.h2[m] = (T)(lv.h * lv.h);
+      t.ih2[m] = (T)(1.0 / (lv.h * lv.h));
+      t.off[m] = off;
+      off += lv.n * lv.n * lv.n;
+    }
+    if (off > MG_TAIL_ALLOC) return hipErrorInvalidValue;
+    t.F0 = P<T>(ws, L.lev[l0].F);
+    t.phi0 = P<T>(ws, L.lev[l0].phi[0]);
+    t.pre = p.mg_pre;
+    t.post = p.mg_post;
+    t.csweeps = p.mg_coarse_sweeps;
+    cur[l0] = 0;
+    hipLaunchKernelGGL((k_vcycle_tail<T>), dim3(1), dim3(MG_TAIL_THREADS), 0, s, t);
+  } else {
     MGLevel& cv = L.lev[nl - 1];
     if (nl == 1) {
       // the whole grid is the coarsest grid: plain sweeps from the warm start
@@ -317,7 +489,7 @@ hipError_t vcycle(char* ws, MGLayout& L, const mh_physics_desc& p, double* parti
                          P<T>(ws, cv.F), P<T>(ws, cv.phi[0]), p.mg_coarse_sweeps);
     }
   }
-  for (int l = nl - 2; l >= 0; --l) {
+  for (int l = (l0 < nl ? l0 : nl - 1) - 1; l >= 0; --l) {
     MGLevel& lv = L.lev[l];
     MGLevel& cv = L.lev[l + 1];
     const long long N = (long long)lv.n * lv.n * lv.n;
@@ -442,6 +614,54 @@ hipError_t mg_set_guess(char* ws, MGLayout& L, const T* phi0, hipStream_t s) {
 // V-cycles on A phi = F (F already mean-free on the fine level) from the
 // current guess until ||F - A phi||_2 <= tol ||F||_2 or max_cycles cycles;
 // the mean of phi is removed before the first and after every cycle.
+void MGGraphCache::reset() {
+  for (int k = 0; k < 2; ++k) {
+    if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+    exec[k] = nullptr;
+  }
+  ws = nullptr;
+}
+
+void MGGraphCache::destroy() {
+  reset();
+  if (cs) (void)hipStreamDestroy(cs);
+  cs = nullptr;
+}
+
+// one V-cycle: replayed from the cached graph of the current parity (captured
+// on first use), or launched kernel by kernel when no cache is attached
+template <typename T>
+hipError_t run_vcycle(char* ws, MGLayout& L, const mh_physics_desc& p, double* partial,
+                      double* mean_slot, hipStream_t s) {
+  MGGraphCache* G = L.graphs;
+  if (!G || !G->enabled) return vcycle<T>(ws, L, p, partial, mean_slot, s);
+  if (G->ws != ws) {
+    G->reset();
+    G->ws = ws;
+  }
+  const int k = L.cur0;
+  if (!G->exec[k]) {
+    if (!G->cs) MG_CHECK(hipStreamCreateWithFlags(&G->cs, hipStreamNonBlocking));
+    MG_CHECK(hipStreamBeginCapture(G->cs, hipStreamCaptureModeRelaxed));
+    const hipError_t e = vcycle<T>(ws, L, p, partial, mean_slot, G->cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(G->cs, &graph);
+    G->cur_after[k] = L.cur0;
+    L.cur0 = k;  // nothing ran during the capture
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e;
+    }
+    MG_CHECK(e2);
+    const hipError_t e3 = hipGraphInstantiate(&G->exec[k], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    MG_CHECK(e3);
+  }
+  MG_CHECK(hipGraphLaunch(G->exec[k], s));
+  L.cur0 = G->cur_after[k];
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* clk, int* cycles_out,
                     hipStream_t s) {
@@ -460,7 +680,7 @@ hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* c
     MG_CHECK(hipMemcpyAsync(norms, &clk->mg_fnorm2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     MG_CHECK(hipStreamSynchronize(s));
     if (std::sqrt(norms[1]) <= p.mg_tol * std::sqrt(norms[0]) || cycles >= p.mg_max_cycles) break;
-    MG_CHECK(vcycle<T>(ws, L, p, partial, &clk->mean, s));
+    MG_CHECK(run_vcycle<T>(ws, L, p, partial, &clk->mean, s));
     MG_CHECK(remove_mean(P<T>(ws, f.phi[L.cur0]), N, partial, &clk->mean, s));
     ++cycles;
   }
