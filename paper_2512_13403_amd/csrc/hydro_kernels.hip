@@ -49,12 +49,10 @@ __device__ __forceinline__ T limited_slope(T wm, T w0, T wp) {
   return minmod(wp - w0, w0 - wm);
 }
 
-// c = sqrt(gamma P / rho) from gp = gamma P: in fp32 as gp * rsq(gp rho), one
-// transcendental instead of a reciprocal and a square root
-__device__ __forceinline__ float sound_speed(float gp, float rho) {
-  return gp * __builtin_amdgcn_rsqf(gp * rho);
-}
-__device__ __forceinline__ double sound_speed(double gp, double rho) { return sqrt(gp / rho); }
+// c = sqrt(gamma P / rho) from gp = gamma P, as gp * rsq(gp rho): one
+// reciprocal square root instead of a division and a square root
+__device__ __forceinline__ float sound_speed(float gp, float rho) { return gp * dev_rsq(gp * rho); }
+__device__ __forceinline__ double sound_speed(double gp, double rho) { return gp * dev_rsq(gp * rho); }
 
 // HLLC flux through a face with normal velocity component `n` (0, 1, 2) of
 // the primitive face states wl, wr = (rho, vx, vy, vz, P).  Davis speeds
