@@ -48,8 +48,8 @@ typedef enum mh_status {
 
 enum { MH_BC_PERIODIC = 0, MH_BC_OUTFLOW = 1 };
 enum { MH_F32 = 0, MH_F64 = 1 };
-enum { MH_LIM_MINMOD = 0, MH_LIM_NONE = 1 };
-enum { MH_RS_HLLC = 0 };
+enum { MH_LIM_MINMOD = 0, MH_LIM_NONE = 1, MH_LIM_VANLEER = 2, MH_LIM_MC = 3, MH_LIM_SUPERBEE = 4 };
+enum { MH_RS_HLLC = 0, MH_RS_HLL = 1, MH_RS_RUSANOV = 2 };
 enum { MH_SRC_COOLING = 1u, MH_SRC_FORCING = 2u, MH_SRC_GRAVITY = 4u };
 enum { MH_HOST = 0, MH_DEVICE = 1 };
 
@@ -60,8 +60,15 @@ enum { MH_HOST = 0, MH_DEVICE = 1 };
  * h[3]    cell spacing per axis (> 0).
  * dtype   MH_F32 or MH_F64: storage and arithmetic precision of the state.
  * limiter MH_LIM_MINMOD (App. A.1; a tie |a| = |b| takes the forward
- *         difference) or MH_LIM_NONE (piecewise constant).
- * riemann MH_RS_HLLC (App. A.2).
+ *         difference), MH_LIM_NONE (piecewise constant), MH_LIM_VANLEER
+ *         (2ab/(a+b)), MH_LIM_MC (monotonised central) or MH_LIM_SUPERBEE,
+ *         each 0 when the two differences disagree in sign (App. A.1 lists
+ *         the family).
+ * riemann MH_RS_HLLC (App. A.2), MH_RS_HLL or MH_RS_RUSANOV, all with the
+ *         Davis wave-speed estimates.  minmod or none with HLLC run the
+ *         specialised kernels; the other combinations a kernel that selects
+ *         limiter and solver at run time.  The adjoint step supports minmod
+ *         or none with HLLC.
  * gamma   adiabatic index (> 1).
  * cfl     Courant number C of dt = C min_a dx_a / (|v_a| + c_s) (App. A.4). */
 typedef struct mh_grid_desc {

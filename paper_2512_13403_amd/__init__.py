@@ -23,8 +23,8 @@ STATUS_NAMES = ["MH_OK", "MH_E_INVALID", "MH_E_SHAPE", "MH_E_DTYPE", "MH_E_DEVIC
                 "MH_E_NONFINITE", "MH_E_UNSUPPORTED", "MH_E_WORKSPACE"]
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 F32, F64 = 0, 1
-LIM_MINMOD, LIM_NONE = 0, 1
-RS_HLLC = 0
+LIM_MINMOD, LIM_NONE, LIM_VANLEER, LIM_MC, LIM_SUPERBEE = 0, 1, 2, 3, 4
+RS_HLLC, RS_HLL, RS_RUSANOV = 0, 1, 2
 SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
 HOST, DEVICE = 0, 1
 

@@ -66,9 +66,10 @@ mh_status validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string&
   const long long N = (long long)g->n[0] * g->n[1] * g->n[2];
   if (N > (1ll << 31)) return fail(MH_E_SHAPE, "more than 2^31 cells");
   if (g->dtype != MH_F32 && g->dtype != MH_F64) return fail(MH_E_DTYPE, "dtype must be F32 or F64");
-  if (g->limiter != MH_LIM_MINMOD && g->limiter != MH_LIM_NONE)
-    return fail(MH_E_UNSUPPORTED, "limiter not implemented on the GPU (minmod or none)");
-  if (g->riemann != MH_RS_HLLC) return fail(MH_E_UNSUPPORTED, "only the HLLC Riemann solver");
+  if (g->limiter < MH_LIM_MINMOD || g->limiter > MH_LIM_SUPERBEE)
+    return fail(MH_E_UNSUPPORTED, "unknown limiter");
+  if (g->riemann < MH_RS_HLLC || g->riemann > MH_RS_RUSANOV)
+    return fail(MH_E_UNSUPPORTED, "unknown Riemann solver");
   if (!(g->gamma > 1.0)) return fail(MH_E_INVALID, "gamma must exceed 1");
   if (!(g->cfl > 0.0)) return fail(MH_E_INVALID, "CFL number must be positive");
   const uint32_t known = MH_SRC_COOLING | MH_SRC_FORCING | MH_SRC_GRAVITY;
@@ -343,6 +344,8 @@ static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) 
   a.ihy = (T)(1.0 / g.h[1]);
   a.ihz = (T)(1.0 / g.h[2]);
   a.cool = cool_params<T>(g, p);
+  a.lim = g.limiter;
+  a.rs = g.riemann;
   if (p.flags & MH_SRC_FORCING) {
     a.ou_rows = ou_rows;
     for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
@@ -683,6 +686,9 @@ extern "C" mh_status mh_adjoint_step(mh_ctx* c, void* adj_workspace, size_t adj_
   if ((c->p.flags & MH_SRC_FORCING) && !ou_ahat)
     return set_err(c, MH_E_INVALID, "mh_adjoint_step: forcing is on but ou_ahat is NULL");
   if (!(dt >= 0.0) || step < 0) return set_err(c, MH_E_INVALID, "mh_adjoint_step: bad dt or step");
+  if ((c->g.limiter != MH_LIM_MINMOD && c->g.limiter != MH_LIM_NONE) || c->g.riemann != MH_RS_HLLC)
+    return set_err(c, MH_E_UNSUPPORTED,
+                   "mh_adjoint_step: the adjoint is implemented for minmod or none with HLLC");
   AdjLayout A = make_adj_layout(c->g, c->p);
   A.mg.graphs = &c->adj_graphs;
   if (!adj_workspace || adj_workspace_bytes < A.total || ((uintptr_t)adj_workspace % ALIGN) != 0)

@@ -42,10 +42,32 @@ __device__ __forceinline__ double minmod(double a, double b) {
   return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
-// limited slope of W_i from W_{i-1}, W_i, W_{i+1} (App. A.1)
+// limited slope of W_i from W_{i-1}, W_i, W_{i+1} (App. A.1): limiter(a, b)
+// of the forward and backward differences a = W_{i+1} - W_i, b = W_i - W_{i-1};
+// every limiter is 0 when a and b disagree in sign.  The LIM_GENERIC kernel
+// takes the limiter `rl` at run time.
+template <typename T>
+__device__ __forceinline__ T slope_of(int rl, T a, T b) {
+  if (rl == LIM_MINMOD) return minmod(a, b);
+  if (rl == LIM_NONE) return T(0);
+  const bool same = a * b > T(0);
+  T m;
+  if (rl == LIM_VANLEER) {
+    m = T(2) * a * b * dev_rcp(a + b);  // harmonic mean
+  } else {
+    const T aa = fabs(a), ab = fabs(b);
+    T mag;
+    if (rl == LIM_MC) mag = fmin(fabs(T(0.5) * (a + b)), fmin(T(2) * aa, T(2) * ab));
+    else mag = fmax(fmin(T(2) * aa, ab), fmin(aa, T(2) * ab));  // superbee
+    m = a > T(0) ? mag : -mag;
+  }
+  return same ? m : T(0);
+}
+
 template <typename T, int LIM>
-__device__ __forceinline__ T limited_slope(T wm, T w0, T wp) {
+__device__ __forceinline__ T limited_slope(T wm, T w0, T wp, int rl = 0) {
   if (LIM == LIM_NONE) return T(0);
+  if (LIM == LIM_GENERIC) return slope_of(rl, wp - w0, w0 - wm);
   return minmod(wp - w0, w0 - wm);
 }
 
@@ -100,31 +122,100 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   F[4] = fan ? f4 : FK4;
 }
 
+// conserved state and physical flux of a primitive face state, in the
+// component order of the grid (normal momentum at 1 + N)
+template <typename T, int N>
+__device__ __forceinline__ void state_flux(const T (&w)[5], T gm1inv, T (&U)[5], T (&F)[5]) {
+  constexpr int vn = 1 + N;
+  const T rho = w[0], u = w[vn], p = w[4];
+  const T E = fmad(p, gm1inv, (T(0.5) * rho) * fmad(w[1], w[1], fmad(w[2], w[2], w[3] * w[3])));
+  const T m = rho * u;
+  U[0] = rho;
+  U[1] = rho * w[1];
+  U[2] = rho * w[2];
+  U[3] = rho * w[3];
+  U[4] = E;
+  F[0] = m;
+  F[1] = m * w[1];
+  F[2] = m * w[2];
+  F[3] = m * w[3];
+  F[vn] = fmad(m, u, p);
+  F[4] = u * (E + p);
+}
+
+// HLL (two-wave) flux with the Davis speeds (App. A.2 lists it with Rusanov
+// as alternatives to HLLC): F_L for 0 <= S_L, F_R for S_R <= 0, else
+// (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L)
+template <typename T, int N>
+__device__ __forceinline__ void hll_flux(const T (&wl)[5], const T (&wr)[5], T gamma, T gm1inv,
+                                         T (&F)[5]) {
+  constexpr int vn = 1 + N;
+  const T cl = sound_speed(gamma * wl[4], wl[0]), cr = sound_speed(gamma * wr[4], wr[0]);
+  const T SL = fmin(wl[vn] - cl, wr[vn] - cr), SR = fmax(wl[vn] + cl, wr[vn] + cr);
+  T UL[5], FL[5], UR[5], FR[5];
+  state_flux<T, N>(wl, gm1inv, UL, FL);
+  state_flux<T, N>(wr, gm1inv, UR, FR);
+  const T q = dev_rcp(SR - SL);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const T fm = (fmad(SR, FL[f], -SL * FR[f]) + SL * SR * (UR[f] - UL[f])) * q;
+    F[f] = SL >= T(0) ? FL[f] : (SR <= T(0) ? FR[f] : fm);
+  }
+}
+
+// Rusanov (local Lax-Friedrichs): (F_L + F_R)/2 - s (U_R - U_L)/2 with
+// s = max(|v_L| + c_L, |v_R| + c_R)
+template <typename T, int N>
+__device__ __forceinline__ void rusanov_flux(const T (&wl)[5], const T (&wr)[5], T gamma,
+                                             T gm1inv, T (&F)[5]) {
+  constexpr int vn = 1 + N;
+  const T cl = sound_speed(gamma * wl[4], wl[0]), cr = sound_speed(gamma * wr[4], wr[0]);
+  const T smax = fmax(fabs(wl[vn]) + cl, fabs(wr[vn]) + cr);
+  T UL[5], FL[5], UR[5], FR[5];
+  state_flux<T, N>(wl, gm1inv, UL, FL);
+  state_flux<T, N>(wr, gm1inv, UR, FR);
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+    F[f] = fmad(T(0.5), FL[f] + FR[f], -(T(0.5) * smax) * (UR[f] - UL[f]));
+}
+
+// the face flux of the scheme: HLLC in the specialised kernels, the solver
+// `rs` chosen at run time in the LIM_GENERIC kernel
+template <typename T, int N, int LIM>
+__device__ __forceinline__ void riemann_flux(const T (&wl)[5], const T (&wr)[5], T gamma, T gm1inv,
+                                             int rs, T (&F)[5]) {
+  if (LIM == LIM_GENERIC && rs == RS_HLL) hll_flux<T, N>(wl, wr, gamma, gm1inv, F);
+  else if (LIM == LIM_GENERIC && rs == RS_RUSANOV) rusanov_flux<T, N>(wl, wr, gamma, gm1inv, F);
+  else hllc_flux<T, N>(wl, wr, gamma, gm1inv, F);
+}
+
 // flux through the face between cells i and i+1 from W_{i-1}, W_i, W_{i+1},
 // W_{i+2}: W^L = W_i + dW_i/2, W^R = W_{i+1} - dW_{i+1}/2 (App. A.1)
 template <typename T, int LIM, int N>
 __device__ __forceinline__ void face_flux(const T (&wm)[5], const T (&w0)[5], const T (&w1)[5],
-                                          const T (&w2)[5], T gamma, T gm1inv, T (&F)[5]) {
+                                          const T (&w2)[5], T gamma, T gm1inv, int rl, int rs,
+                                          T (&F)[5]) {
   T wl[5], wr[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
-    wl[f] = fmad(T(0.5), limited_slope<T, LIM>(wm[f], w0[f], w1[f]), w0[f]);
-    wr[f] = fmad(T(-0.5), limited_slope<T, LIM>(w0[f], w1[f], w2[f]), w1[f]);
+    wl[f] = fmad(T(0.5), limited_slope<T, LIM>(wm[f], w0[f], w1[f], rl), w0[f]);
+    wr[f] = fmad(T(-0.5), limited_slope<T, LIM>(w0[f], w1[f], w2[f], rl), w1[f]);
   }
-  hllc_flux<T, N>(wl, wr, gamma, gm1inv, F);
+  riemann_flux<T, N, LIM>(wl, wr, gamma, gm1inv, rs, F);
 }
 
 // the same flux from precomputed limited slopes d0 of W_i and d1 of W_{i+1}
-template <typename T, int N>
+template <typename T, int N, int LIM>
 __device__ __forceinline__ void face_flux_sl(const T (&w0)[5], const T (&d0)[5], const T (&w1)[5],
-                                             const T (&d1)[5], T gamma, T gm1inv, T (&F)[5]) {
+                                             const T (&d1)[5], T gamma, T gm1inv, int rs,
+                                             T (&F)[5]) {
   T wl[5], wr[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     wl[f] = fmad(T(0.5), d0[f], w0[f]);
     wr[f] = fmad(T(-0.5), d1[f], w1[f]);
   }
-  hllc_flux<T, N>(wl, wr, gamma, gm1inv, F);
+  riemann_flux<T, N, LIM>(wl, wr, gamma, gm1inv, rs, F);
 }
 
 // Each row of the tile (fixed ty) is exactly one wave, so the lower-edge
@@ -220,10 +311,10 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
     to_prim(u[1], gm1, w[2]);
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      dz0[f] = limited_slope<T, LIM>(wz[f], w[0][f], w[1][f]);
-      dz1[f] = limited_slope<T, LIM>(w[0][f], w[1][f], w[2][f]);
+      dz0[f] = limited_slope<T, LIM>(wz[f], w[0][f], w[1][f], a.lim);
+      dz1[f] = limited_slope<T, LIM>(w[0][f], w[1][f], w[2][f], a.lim);
     }
-    face_flux_sl<T, 2>(w[0], dz0, w[1], dz1, gamma, gm1inv, fzm);
+    face_flux_sl<T, 2, LIM>(w[0], dz0, w[1], dz1, gamma, gm1inv, a.rs, fzm);
   }
 
   T smax = T(0);
@@ -272,7 +363,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         c2[f] = sW[f][ty + 2][tx + 3];
         c3[f] = sW[f][ty + 2][tx + 4];
       }
-      face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, F);
+      face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sFx[f][ty][tx + 1] = F[f];
       // y face at y + 1/2
@@ -283,7 +374,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         c2[f] = sW[f][ty + 3][tx + 2];
         c3[f] = sW[f][ty + 4][tx + 2];
       }
-      face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, F);
+      face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sFy[f][ty + 1][tx] = F[f];
       // the tile's lower-edge faces: the TX y faces at y0 - 1/2 by the wave
@@ -297,7 +388,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
           c2[f] = sW[f][2][tx + 2];
           c3[f] = sW[f][3][tx + 2];
         }
-        face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, F);
+        face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
 #pragma unroll
         for (int f = 0; f < 5; ++f) sFy[f][0][tx] = F[f];
       } else if (ty == 1 && tx < TY) {
@@ -308,15 +399,15 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
           c2[f] = sW[f][tx + 2][2];
           c3[f] = sW[f][tx + 2][3];
         }
-        face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, F);
+        face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
 #pragma unroll
         for (int f = 0; f < 5; ++f) sFx[f][tx][0] = F[f];
       }
     }
     T fzp[5], dz2[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) dz2[f] = limited_slope<T, LIM>(w[1][f], w[2][f], w[3][f]);
-    face_flux_sl<T, 2>(w[1], dz1, w[2], dz2, gamma, gm1inv, fzp);
+    for (int f = 0; f < 5; ++f) dz2[f] = limited_slope<T, LIM>(w[1][f], w[2][f], w[3][f], a.lim);
+    face_flux_sl<T, 2, LIM>(w[1], dz1, w[2], dz2, gamma, gm1inv, a.rs, fzp);
     __syncthreads();
 
     T un[5];
@@ -555,9 +646,18 @@ hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs
   dim3 grid(8 * a.nb_per_xcd);
 #define MH_LAUNCH(ST, LM, FO, CO) \
   hipLaunchKernelGGL((k_stage<T, ST, LM, FO, CO>), grid, block, 0, s, a)
+  // minmod or none with HLLC: the specialised kernels; any other limiter or
+  // solver: the kernel that reads them at run time
+  if (a.rs != RS_HLLC || (limiter != LIM_MINMOD && limiter != LIM_NONE)) limiter = LIM_GENERIC;
   if (stage == 1) {
     if (limiter == LIM_NONE) MH_LAUNCH(1, LIM_NONE, false, false);
+    else if (limiter == LIM_GENERIC) MH_LAUNCH(1, LIM_GENERIC, false, false);
     else MH_LAUNCH(1, LIM_MINMOD, false, false);
+  } else if (limiter == LIM_GENERIC) {
+    if (force && cool) MH_LAUNCH(2, LIM_GENERIC, true, true);
+    else if (force) MH_LAUNCH(2, LIM_GENERIC, true, false);
+    else if (cool) MH_LAUNCH(2, LIM_GENERIC, false, true);
+    else MH_LAUNCH(2, LIM_GENERIC, false, false);
   } else if (limiter == LIM_NONE) {
     if (force && cool) MH_LAUNCH(2, LIM_NONE, true, true);
     else if (force) MH_LAUNCH(2, LIM_NONE, true, false);

@@ -35,7 +35,10 @@ struct DevClock {
 };
 
 enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1 };
-enum : int { LIM_MINMOD = 0, LIM_NONE = 1 };
+enum : int { LIM_MINMOD = 0, LIM_NONE = 1, LIM_VANLEER = 2, LIM_MC = 3, LIM_SUPERBEE = 4 };
+// template tag of the stage kernel that selects limiter and solver at run time
+enum : int { LIM_GENERIC = 15 };
+enum : int { RS_HLLC = 0, RS_HLL = 1, RS_RUSANOV = 2 };
 
 __device__ __forceinline__ int bc_map(int i, int n, int bc) {
   if ((unsigned)i < (unsigned)n) return i;

@@ -28,6 +28,7 @@ struct StageArgs {
   T gamma, gm1, gm1inv, ihx, ihy, ihz;
   CoolParams<T> cool;
   int zc, nbx, nby, nbz, nb_per_xcd;
+  int lim, rs;  // limiter and Riemann solver (read by the run-time-scheme kernel)
 };
 
 struct OUArgs {

@@ -44,6 +44,60 @@ def test_random_state_ragged_periodic(dtype, nsteps):
     assert rel_err(s.get_state(), sim.U) < TOL[dtype]
 
 
+SCHEMES = [(oracle.LIM_VANLEER, oracle.RS_HLLC), (oracle.LIM_MC, oracle.RS_HLLC),
+           (oracle.LIM_SUPERBEE, oracle.RS_HLLC), (oracle.LIM_MINMOD, oracle.RS_HLL),
+           (oracle.LIM_MINMOD, oracle.RS_RUSANOV), (oracle.LIM_VANLEER, oracle.RS_HLL),
+           (oracle.LIM_NONE, oracle.RS_RUSANOV)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("limiter,riemann", SCHEMES)
+def test_scheme_variants_ragged(dtype, limiter, riemann):
+    """The other limiters and Riemann solvers of App. A.1/A.2 (run-time scheme
+    kernel) against the oracle, 3 steps on a ragged grid with outflow in x."""
+    shape = (9, 11, 70)
+    h = (1 / 70, 1 / 11, 1 / 9)
+    U0 = wl.random_state(shape, seed=8, vmax=0.6)
+    s, sim = run_both(shape, h, U0, dtype, 3, bc=(1, 0, 0), limiter=limiter, riemann=riemann)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_scheme_variant_with_sources(dtype):
+    shape = (12, 14, 66)
+    h = (1 / 66, 1 / 14, 1 / 12)
+    U0 = wl.random_state(shape, seed=9, vmax=0.5)
+    s, sim = run_both(shape, h, U0, dtype, 2, limiter=oracle.LIM_VANLEER, riemann=oracle.RS_HLL,
+                      flags=oracle.SRC_FORCING | oracle.SRC_COOLING, ou_seed=3)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+@pytest.mark.parametrize("limiter,riemann", [(oracle.LIM_VANLEER, oracle.RS_HLLC),
+                                             (oracle.LIM_MC, oracle.RS_HLL)])
+def test_sod_full_run_scheme_variants_fp64(limiter, riemann):
+    grid = wl.sod_grid(128, 16, 16)
+    U0 = wl.sod_state(grid)
+    s, oc = pair(grid.shape, grid.h, grid.bc, "f64", gamma=1.4, limiter=limiter, riemann=riemann)
+    s.set_state(U0)
+    dts = s.run_to(0.2)
+    sim = oracle.Simulation(oc, U0)
+    assert len(dts) == sim.run_to(0.2)
+    U = s.get_state()
+    assert rel_err(U, sim.U) < 1e-12
+    assert np.array_equal(U, np.broadcast_to(U[:, :1, :1, :], U.shape))
+
+
+def test_adjoint_rejects_scheme_variants():
+    import torch
+
+    shape = (8, 8, 8)
+    s, _ = pair(shape, (1 / 8,) * 3, dtype="f64", limiter=oracle.LIM_VANLEER)
+    U = torch.tensor(wl.random_state(shape, seed=1), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(mh.MHError) as e:
+        s.adjoint_step(U, 1e-3, 0, U.clone())
+    assert e.value.status == mh.E_UNSUPPORTED
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("bc", [(1, 1, 1), (1, 0, 0), (0, 1, 0), (0, 0, 1)])
 def test_outflow_boundaries(dtype, bc):

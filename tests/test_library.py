@@ -52,7 +52,8 @@ def test_workspace_size_of_valid_grids():
     (lambda g, p: setattr(g, "gamma", 1.0), mh.E_INVALID),
     (lambda g, p: setattr(g, "cfl", 0.0), mh.E_INVALID),
     (lambda g, p: setattr(g, "limiter", 9), mh.E_UNSUPPORTED),
-    (lambda g, p: setattr(g, "riemann", 2), mh.E_UNSUPPORTED),
+    (lambda g, p: setattr(g, "riemann", 7), mh.E_UNSUPPORTED),
+    (lambda g, p: setattr(g, "limiter", -1), mh.E_UNSUPPORTED),
     (lambda g, p: setattr(p, "flags", 64), mh.E_INVALID),
     (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_tau", 0.0)), mh.E_INVALID),
     (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_kmin", 3.0),
@@ -69,6 +70,13 @@ def test_validation_rejects(mutate, status):
     mutate(g, p)
     st, _ = ws(g, p)
     assert st == status
+
+
+def test_scheme_variants_are_accepted():
+    for lim in (mh.LIM_MINMOD, mh.LIM_NONE, mh.LIM_VANLEER, mh.LIM_MC, mh.LIM_SUPERBEE):
+        for rs in (mh.RS_HLLC, mh.RS_HLL, mh.RS_RUSANOV):
+            g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32", limiter=lim, riemann=rs)
+            assert ws(g, mh.physics_desc())[0] == mh.OK
 
 
 def test_gravity_coarsest_grid_limit():
