@@ -9,7 +9,7 @@ state is resident in HBM before it starts.  Prints one JSON line.
 
 value            cell-updates/s = cells * steps / seconds of the timed region
 roofline         the dominant kernel (RK stage 2), which is bound by the fp32
-                 vector ALU: algorithmic FLOPs per launch (594 per cell) over
+                 vector ALU: algorithmic FLOPs per launch (489 per cell) over
                  its mean duration from HIP events recorded around every launch
                  on the library's stream, against the fp32 vector peak;
                  `traffic` = HBM bytes per launch from the committed counter
@@ -38,10 +38,13 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # algorithmic floating-point operations per cell of one RK stage of the fp32
 # method (primitive recovery, 3 faces of limited slopes + face states + HLLC,
 # conservative update; stage 2 adds the RK combination, OU kick, exact cooling
-# and the CFL signal speed): FMA = 2, every other arithmetic, min/max, compare
-# or select, reciprocal, square root, exp or log = 1
-FLOP_STAGE1 = 486
-FLOP_STAGE2 = 594
+# and the CFL signal speed): add, subtract, multiply, reciprocal, square root,
+# exp and log count 1, an FMA 2; compares, selects, min/max and the
+# median-of-three of minmod count 0 (the convention of the hardware FP32 FLOP
+# counter, which reads 405 and 498 per cell executed, the excess being the
+# tile-edge faces and halo primitives computed twice)
+FLOP_STAGE1 = 396
+FLOP_STAGE2 = 489
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_k_stage_512_fp32.md")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2512_13403_amd", "csrc", f)
                for f in ("hydro_kernels.hip", "mh_device.h")]
