@@ -10,6 +10,7 @@ Each wrapper names the paper passage its C function follows:
 * ``cfl_dt``        -- App. A.4 (CFL condition)
 * ``rhs``           -- App. A.1-A.3 (MUSCL on primitives, HLLC, rhs_unsplit)
 * ``rk2``           -- App. A.3 (RK2 / Heun in Shu-Osher form)
+* ``ssprk3``/``euler``/``integrate`` -- App. A.3 (the other explicit RK options)
 * ``cool``          -- Sec. 4 (operator-split cooling, exact per cell)
 * ``ou_*``/``kick`` -- Sec. 3.1.1 (Ornstein-Uhlenbeck forcing)
 * ``mg_*``/``gravity_accel`` -- Sec. 6, 6.2, App. C (multigrid self-gravity)
@@ -29,6 +30,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 LIM_MINMOD, LIM_NONE, LIM_VANLEER, LIM_MC, LIM_SUPERBEE = 0, 1, 2, 3, 4
 RS_HLLC, RS_HLL, RS_RUSANOV = 0, 1, 2
+RK_SSP2, RK_SSP3, RK_EULER = 0, 1, 2
 SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
 OU_MAXMODES = 64
 
@@ -63,7 +65,7 @@ class Config(ctypes.Structure):
         ("mg_coarsest", ctypes.c_int32),
         ("mg_tol", ctypes.c_double),
         ("mg_coarse_sweeps", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -87,6 +89,8 @@ def lib():
             "or_rhs": (None, [cp, dp, dp]),
             "or_rk2": (None, [cp, dp, ctypes.c_double]),
             "or_euler": (None, [cp, dp, ctypes.c_double]),
+            "or_ssprk3": (None, [cp, dp, ctypes.c_double]),
+            "or_integrate": (None, [cp, dp, ctypes.c_double]),
             "or_cool_temperature": (ctypes.c_double, [ctypes.c_double] * 8),
             "or_cool": (None, [cp, dp, ctypes.c_double]),
             "or_ou_gauss": (None, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, dp]),
@@ -105,6 +109,9 @@ def lib():
             "or_num_threads": (ctypes.c_int, []),
             "or_rhs_vjp": (None, [cp, dp, dp, dp]),
             "or_rk2_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
+            "or_euler_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
+            "or_ssprk3_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
+            "or_integrate_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
             "or_kick_vjp": (None, [cp, dp, dp, ctypes.c_double, dp, dp, dp]),
             "or_cool_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
             "or_gravity_vjp": (ctypes.c_int, [cp, dp, ctypes.c_double, dp, dp, dp]),
@@ -135,7 +142,7 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
                 riemann=RS_HLLC, flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5,
                 ou_arms=1.0, ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0, ou_every=1, grav_G=0.0,
                 mg_pre=2, mg_post=2, mg_max_cycles=20, mg_coarsest=4, mg_tol=1e-10,
-                mg_coarse_sweeps=200) -> Config:
+                mg_coarse_sweeps=200, integrator=RK_SSP2) -> Config:
     """shape = (nz, ny, nx) of the state arrays; h = (hx, hy, hz); bc per (x, y, z)."""
     nz, ny, nx = shape
     c = Config()
@@ -149,6 +156,7 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
     c.grav_G = grav_G
     c.mg_pre, c.mg_post, c.mg_max_cycles, c.mg_coarsest = mg_pre, mg_post, mg_max_cycles, mg_coarsest
     c.mg_tol, c.mg_coarse_sweeps = mg_tol, mg_coarse_sweeps
+    c.integrator = integrator
     return c
 
 
@@ -188,6 +196,19 @@ def rk2(c, U, dt):
 def euler(c, U, dt):
     U = np.array(U, dtype=np.float64, order="C", copy=True)
     lib().or_euler(ctypes.byref(c), _dp(U), dt)
+    return U
+
+
+def ssprk3(c, U, dt):
+    U = np.array(U, dtype=np.float64, order="C", copy=True)
+    lib().or_ssprk3(ctypes.byref(c), _dp(U), dt)
+    return U
+
+
+def integrate(c, U, dt):
+    """One update by the configuration's integrator (c.integrator)."""
+    U = np.array(U, dtype=np.float64, order="C", copy=True)
+    lib().or_integrate(ctypes.byref(c), _dp(U), dt)
     return U
 
 
@@ -305,6 +326,26 @@ def rk2_vjp(c, U, dt, lam):
     out = np.empty_like(U)
     lib().or_rk2_vjp(ctypes.byref(c), _dp(U), dt, _dp(lam), _dp(out))
     return out
+
+
+def _vjp(fn, c, U, dt, lam):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.empty_like(U)
+    fn(ctypes.byref(c), _dp(U), dt, _dp(lam), _dp(out))
+    return out
+
+
+def euler_vjp(c, U, dt, lam):
+    return _vjp(lib().or_euler_vjp, c, U, dt, lam)
+
+
+def ssprk3_vjp(c, U, dt, lam):
+    return _vjp(lib().or_ssprk3_vjp, c, U, dt, lam)
+
+
+def integrate_vjp(c, U, dt, lam):
+    return _vjp(lib().or_integrate_vjp, c, U, dt, lam)
 
 
 def kick_vjp(c, U, acc, dt, lam):

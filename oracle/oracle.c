@@ -13,7 +13,8 @@
  *      (App. A.3, the rhs equation): MUSCL reconstruction on primitive
  *      variables with a slope limiter (App. A.1), HLLC fluxes with Davis wave
  *      speeds (App. A.2), conservative differencing per axis;
- *   3. the two-stage RK2 (Heun / SSP-RK2) update (App. A.3, first item);
+ *   3. the explicit Runge-Kutta update (App. A.3): the two-stage RK2 (Heun /
+ *      SSP-RK2, the default), the three-stage SSPRK3, or forward Euler;
  *   4. operator-split sources on the result, in the order forcing -> gravity
  *      -> cooling: OU forcing (Sec. 3.1.1), multigrid self-gravity (Sec. 6.2,
  *      in oracle_mg.c), optically thin cooling integrated exactly per cell
@@ -360,14 +361,42 @@ void or_rk2(const or_config *c, double *U, double dt) {
   free(U1);
 }
 
-/* one forward-Euler stage, kept for the test that the RK2 update is the
- * average of two Euler stages (App. A.3, "first-order Euler for testing") */
+/* forward Euler, U_new = U + dt L(U) (App. A.3, the first-order option kept
+ * for testing) */
 void or_euler(const or_config *c, double *U, double dt) {
   long N5 = 5 * or_cells(c);
   double *L = (double *)malloc(sizeof(double) * N5);
   or_rhs(c, U, L);
   for (long q = 0; q < N5; ++q) U[q] = U[q] + dt * L[q];
   free(L);
+}
+
+/* SSPRK3 (App. A.3, third item), the three-stage strong-stability-preserving
+ * scheme of Shu & Osher in its convex form:
+ *   U1 = U + dt L(U)
+ *   U2 = 3/4 U + 1/4 (U1 + dt L(U1))
+ *   U_new = 1/3 U + 2/3 (U2 + dt L(U2)) */
+void or_ssprk3(const or_config *c, double *U, double dt) {
+  long N5 = 5 * or_cells(c);
+  double *L = (double *)malloc(sizeof(double) * N5);
+  double *U1 = (double *)malloc(sizeof(double) * N5);
+  double *U2 = (double *)malloc(sizeof(double) * N5);
+  or_rhs(c, U, L);
+  for (long q = 0; q < N5; ++q) U1[q] = U[q] + dt * L[q];
+  or_rhs(c, U1, L);
+  for (long q = 0; q < N5; ++q) U2[q] = 0.75 * U[q] + 0.25 * (U1[q] + dt * L[q]);
+  or_rhs(c, U2, L);
+  for (long q = 0; q < N5; ++q) U[q] = U[q] / 3.0 + 2.0 / 3.0 * (U2[q] + dt * L[q]);
+  free(L);
+  free(U1);
+  free(U2);
+}
+
+/* the integrator the configuration names */
+void or_integrate(const or_config *c, double *U, double dt) {
+  if (c->integrator == OR_RK_SSP3) or_ssprk3(c, U, dt);
+  else if (c->integrator == OR_RK_EULER) or_euler(c, U, dt);
+  else or_rk2(c, U, dt);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -586,7 +615,7 @@ double or_step(const or_config *c, double *U, double dt_fixed, double dt_cap,
                double *phi, int *mg_cycles) {
   double dt = dt_fixed > 0.0 ? dt_fixed : or_cfl_dt(c, U);
   if (dt > dt_cap) dt = dt_cap;
-  or_rk2(c, U, dt);
+  or_integrate(c, U, dt);
   long N = or_cells(c);
   if ((c->flags & OR_SRC_FORCING) && nmodes > 0) {
     int every = c->ou_every > 0 ? c->ou_every : 1;

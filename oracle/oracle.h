@@ -11,6 +11,7 @@ enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1 };
 enum { OR_LIM_MINMOD = 0, OR_LIM_NONE = 1, OR_LIM_VANLEER = 2, OR_LIM_MC = 3,
        OR_LIM_SUPERBEE = 4 };
 enum { OR_RS_HLLC = 0, OR_RS_HLL = 1, OR_RS_RUSANOV = 2 };
+enum { OR_RK_SSP2 = 0, OR_RK_SSP3 = 1, OR_RK_EULER = 2 };
 enum { OR_SRC_COOLING = 1u, OR_SRC_FORCING = 2u, OR_SRC_GRAVITY = 4u };
 #define OR_OU_MAXMODES 64
 
@@ -33,7 +34,7 @@ typedef struct {
   int32_t mg_pre, mg_post, mg_max_cycles, mg_coarsest;
   double mg_tol;
   int32_t mg_coarse_sweeps;
-  int32_t pad_;
+  int32_t integrator; /* OR_RK_* */
 } or_config;
 
 void or_primitives(const or_config *c, const double *U, double *W);
@@ -41,6 +42,8 @@ double or_cfl_dt(const or_config *c, const double *U);
 void or_rhs(const or_config *c, const double *U, double *L);
 void or_rk2(const or_config *c, double *U, double dt);
 void or_euler(const or_config *c, double *U, double dt);
+void or_ssprk3(const or_config *c, double *U, double dt);
+void or_integrate(const or_config *c, double *U, double dt);
 
 double or_cool_temperature(double rho, double T, double dt, double gamma,
                            double L0, double Tc, double Ts, double Tfloor);
@@ -70,6 +73,12 @@ int or_num_threads(void);
 void or_hllc_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],
                  double wlb[5], double wrb[5]);
 void or_rhs_vjp(const or_config *c, const double *U, const double *v, double *out);
+void or_euler_vjp(const or_config *c, const double *U, double dt, const double *lam1,
+                  double *lam);
+void or_ssprk3_vjp(const or_config *c, const double *U, double dt, const double *lam3,
+                   double *lam);
+void or_integrate_vjp(const or_config *c, const double *U, double dt, const double *lamp,
+                      double *lam);
 void or_rk2_vjp(const or_config *c, const double *U, double dt, const double *lam2,
                 double *lam);
 void or_kick_vjp(const or_config *c, const double *U, const double *acc, double dt,

@@ -319,6 +319,52 @@ void or_rk2_vjp(const or_config *c, const double *U, double dt, const double *la
   free(U1); free(L); free(lam1); free(tmp);
 }
 
+/* Reverse of forward Euler: lam = lam1 + dt J(U)^T lam1. */
+void or_euler_vjp(const or_config *c, const double *U, double dt, const double *lam1,
+                  double *lam) {
+  long N5 = 5 * cells(c);
+  double *tmp = (double *)malloc(sizeof(double) * N5);
+  or_rhs_vjp(c, U, lam1, tmp);
+  for (long q = 0; q < N5; ++q) lam[q] = lam1[q] + dt * tmp[q];
+  free(tmp);
+}
+
+/* Reverse of SSPRK3 (or_ssprk3), stage by stage from the last one, with lam3
+ * the adjoint of U_new:
+ *   lam2 = 2/3 (lam3 + dt J(U2)^T lam3)            (adjoint of U2)
+ *   lam1 = 1/4 (lam2 + dt J(U1)^T lam2)            (adjoint of U1)
+ *   lam  = lam3/3 + 3/4 lam2 + lam1 + dt J(U)^T lam1 */
+void or_ssprk3_vjp(const or_config *c, const double *U, double dt, const double *lam3,
+                   double *lam) {
+  long N5 = 5 * cells(c);
+  double *L = (double *)malloc(sizeof(double) * N5);
+  double *U1 = (double *)malloc(sizeof(double) * N5);
+  double *U2 = (double *)malloc(sizeof(double) * N5);
+  double *lam1 = (double *)malloc(sizeof(double) * N5);
+  double *lam2 = (double *)malloc(sizeof(double) * N5);
+  double *tmp = (double *)malloc(sizeof(double) * N5);
+  or_rhs(c, U, L);
+  for (long q = 0; q < N5; ++q) U1[q] = U[q] + dt * L[q];
+  or_rhs(c, U1, L);
+  for (long q = 0; q < N5; ++q) U2[q] = 0.75 * U[q] + 0.25 * (U1[q] + dt * L[q]);
+  or_rhs_vjp(c, U2, lam3, tmp);
+  for (long q = 0; q < N5; ++q) lam2[q] = 2.0 / 3.0 * (lam3[q] + dt * tmp[q]);
+  or_rhs_vjp(c, U1, lam2, tmp);
+  for (long q = 0; q < N5; ++q) lam1[q] = 0.25 * (lam2[q] + dt * tmp[q]);
+  or_rhs_vjp(c, U, lam1, tmp);
+  for (long q = 0; q < N5; ++q)
+    lam[q] = lam3[q] / 3.0 + 0.75 * lam2[q] + lam1[q] + dt * tmp[q];
+  free(L); free(U1); free(U2); free(lam1); free(lam2); free(tmp);
+}
+
+/* reverse of or_integrate */
+void or_integrate_vjp(const or_config *c, const double *U, double dt, const double *lamp,
+                      double *lam) {
+  if (c->integrator == OR_RK_SSP3) or_ssprk3_vjp(c, U, dt, lamp, lam);
+  else if (c->integrator == OR_RK_EULER) or_euler_vjp(c, U, dt, lamp, lam);
+  else or_rk2_vjp(c, U, dt, lamp, lam);
+}
+
 /* ------------------------------------------------------------------------- */
 /* sources                                                                    */
 /* ------------------------------------------------------------------------- */
@@ -472,7 +518,7 @@ void or_step_vjp(const or_config *c, const double *Un, double dt, int64_t step, 
                  const int32_t *nvec, const double *ou_ahat, double *phi,
                  const double *lam_np1, double *lam_n) {
   long N = cells(c), N5 = 5 * N;
-  double *Ua = (double *)malloc(sizeof(double) * N5); /* after RK2 */
+  double *Ua = (double *)malloc(sizeof(double) * N5); /* after the RK update */
   double *Ub = (double *)malloc(sizeof(double) * N5); /* after forcing */
   double *Uc = (double *)malloc(sizeof(double) * N5); /* after gravity */
   double *acc = (double *)malloc(sizeof(double) * 3 * N);
@@ -481,7 +527,7 @@ void or_step_vjp(const or_config *c, const double *Un, double dt, int64_t step, 
   double *ahat = (double *)malloc(sizeof(double) * 6 * (nmodes > 0 ? nmodes : 1));
   double *phi0 = (double *)malloc(sizeof(double) * N);
   memcpy(Ua, Un, sizeof(double) * N5);
-  or_rk2(c, Ua, dt);
+  or_integrate(c, Ua, dt);
   memcpy(Ub, Ua, sizeof(double) * N5);
   int force = (c->flags & OR_SRC_FORCING) && nmodes > 0;
   if (force) {
@@ -506,6 +552,6 @@ void or_step_vjp(const or_config *c, const double *Un, double dt, int64_t step, 
   if (c->flags & OR_SRC_GRAVITY) or_gravity_vjp(c, Ub, dt, phi0, lb, la);
   memcpy(lb, la, sizeof(double) * N5);
   if (force) or_kick_vjp(c, Ua, acc, dt, la, lb, NULL);
-  or_rk2_vjp(c, Un, dt, lb, lam_n);
+  or_integrate_vjp(c, Un, dt, lb, lam_n);
   free(Ua); free(Ub); free(Uc); free(acc); free(la); free(lb); free(ahat); free(phi0);
 }

@@ -144,11 +144,26 @@ def test_gravity_vjp():
     check_dot(fwd, lambda w: oracle.gravity_vjp(c, U, dt, phi0, w), U, seed=17, rtol=1e-6)
 
 
-@pytest.mark.parametrize("flags", [0, oracle.SRC_FORCING | oracle.SRC_COOLING])
-def test_step_vjp_against_full_steps(flags):
+@pytest.mark.parametrize("integrator", [oracle.RK_SSP3, oracle.RK_EULER])
+def test_other_integrators_vjp(integrator):
+    """Reverse of the SSPRK3 and forward-Euler updates (App. A.3)."""
+    grid = wl.Grid((5, 6, 7), (1 / 7, 1 / 6, 1 / 5))
+    U = wl.random_state(grid.shape, seed=6, vmax=0.6)
+    c = oracle.make_config(grid.shape, grid.h, integrator=integrator)
+    dt = 0.5 * oracle.cfl_dt(c, U)
+    f = lambda X: oracle.integrate(c, X, dt)
+    g = lambda w: oracle.integrate_vjp(c, U, dt, w)
+    check_dot(f, g, U, seed=27)
+    check_entries(f, g, U, seed=28)
+
+
+@pytest.mark.parametrize("flags,integrator", [(0, oracle.RK_SSP2),
+                                              (oracle.SRC_FORCING | oracle.SRC_COOLING, oracle.RK_SSP2),
+                                              (oracle.SRC_FORCING | oracle.SRC_COOLING, oracle.RK_SSP3)])
+def test_step_vjp_against_full_steps(flags, integrator):
     grid = wl.cube(8)
     U = wl.random_state(grid.shape, seed=18, vmax=0.5)
-    c = oracle.make_config(grid.shape, grid.h, flags=flags)
+    c = oracle.make_config(grid.shape, grid.h, flags=flags, integrator=integrator)
     dt = 0.6 * oracle.cfl_dt(c, U)
     nvec = oracle.ou_modes(1.0, 2.0) if flags & oracle.SRC_FORCING else np.zeros((0, 3), np.int32)
     ahat = oracle.ou_init(c, nvec) if flags & oracle.SRC_FORCING else np.zeros(6)

@@ -322,3 +322,60 @@ def test_temporal_order_of_rk2():
     d = [np.abs(outs[i] - outs[i + 1]).max() for i in range(3)]
     ratio = d[1] / d[2]
     assert 3.3 < ratio < 4.7, d
+
+
+def test_temporal_order_of_ssprk3():
+    """The SSPRK3 option is a third-order method for the semi-discrete system:
+    halving dt reduces the time error about eightfold."""
+    n = 32
+    grid = wl.Grid((1, 1, n), (1.0 / n, 1.0, 1.0))
+    x = wl.centres(n).reshape(1, 1, n)
+    o = np.ones((1, 1, n))
+    U = wl.conserved(1.0 + 0.01 * np.sin(2 * np.pi * x), 0.01 * np.sin(2 * np.pi * x), 0 * o,
+                     0 * o, 1.0 + 0.014 * np.sin(2 * np.pi * x), 1.4)
+    c = cfg_for(grid, gamma=1.4, limiter=oracle.LIM_NONE, integrator=oracle.RK_SSP3)
+    T = 0.25
+    outs = []
+    for m in (8, 16, 32, 64):
+        outs.append(oracle.Simulation(c, U).advance(m, T / m).U)
+    d = [np.abs(outs[i] - outs[i + 1]).max() for i in range(3)]
+    ratio = d[1] / d[2]
+    assert 6.5 < ratio < 9.5, d
+
+
+STABILITY_POLYNOMIAL = {
+    oracle.RK_EULER: lambda z: 1 + z,
+    oracle.RK_SSP2: lambda z: 1 + z + z * z / 2,
+    oracle.RK_SSP3: lambda z: 1 + z + z * z / 2 + z ** 3 / 6,
+}
+
+
+@pytest.mark.parametrize("integrator", sorted(STABILITY_POLYNOMIAL))
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_integrator_amplifies_a_density_wave_by_its_stability_polynomial(integrator, k):
+    """A density wave at uniform velocity u > 0 and pressure, with piecewise
+    constant faces, is exactly linear upwind advection (HLLC returns the
+    upwind flux at a contact), d rho_i/dt = -(u/h)(rho_i - rho_{i-1}), whose
+    Fourier mode exp(i theta j) has the eigenvalue lambda = -(u/h)(1 - exp(-i
+    theta)).  One step multiplies the mode by the integrator's stability
+    polynomial R(dt lambda): 1 + z (Euler), 1 + z + z^2/2 (two-stage SSP),
+    1 + z + z^2/2 + z^3/6 (SSPRK3), a closed form independent of the stage
+    coefficients; the velocity and pressure stay uniform."""
+    n = 16
+    grid = wl.Grid((1, 1, n), (1.0 / n, 1.0, 1.0))
+    j = np.arange(n)
+    theta = 2.0 * np.pi * k / n
+    amp = 0.1 * np.exp(0.4j)
+    rho = 1.0 + np.real(amp * np.exp(1j * theta * j))
+    u, p, gamma = 0.7, 1.0, 1.4
+    o = np.ones((1, 1, n))
+    U = wl.conserved(rho.reshape(1, 1, n), u * o, 0 * o, 0 * o, p * o, gamma)
+    c = cfg_for(grid, gamma=gamma, limiter=oracle.LIM_NONE, integrator=integrator)
+    dt = 0.02
+    out = oracle.integrate(c, U, dt)
+    lam = -(u * n) * (1.0 - np.exp(-1j * theta))
+    want = 1.0 + np.real(STABILITY_POLYNOMIAL[integrator](dt * lam) * amp * np.exp(1j * theta * j))
+    assert np.abs(out[0, 0, 0] - want).max() < 1e-14
+    assert np.abs(out[1, 0, 0] / out[0, 0, 0] - u).max() < 1e-14
+    W = oracle.primitives(c, out)
+    assert np.abs(W[4] - p).max() < 1e-13
