@@ -50,6 +50,7 @@ enum { MH_BC_PERIODIC = 0, MH_BC_OUTFLOW = 1 };
 enum { MH_F32 = 0, MH_F64 = 1 };
 enum { MH_LIM_MINMOD = 0, MH_LIM_NONE = 1, MH_LIM_VANLEER = 2, MH_LIM_MC = 3, MH_LIM_SUPERBEE = 4 };
 enum { MH_RS_HLLC = 0, MH_RS_HLL = 1, MH_RS_RUSANOV = 2 };
+enum { MH_RK_SSP2 = 0, MH_RK_SSP3 = 1, MH_RK_EULER = 2 };
 enum { MH_SRC_COOLING = 1u, MH_SRC_FORCING = 2u, MH_SRC_GRAVITY = 4u };
 enum { MH_HOST = 0, MH_DEVICE = 1 };
 
@@ -69,6 +70,11 @@ enum { MH_HOST = 0, MH_DEVICE = 1 };
  *         specialised kernels; the other combinations a kernel that selects
  *         limiter and solver at run time.  The adjoint step supports minmod
  *         or none with HLLC.
+ * integrator  the explicit Runge-Kutta update (App. A.3): MH_RK_SSP2 (the
+ *         two-stage Heun / SSP-RK2, the default), MH_RK_SSP3 (three-stage
+ *         SSPRK3; the workspace holds one more state) or MH_RK_EULER
+ *         (first order, for testing; one extra state copy per step).  The
+ *         sources follow the full update in every case.
  * gamma   adiabatic index (> 1).
  * cfl     Courant number C of dt = C min_a dx_a / (|v_a| + c_s) (App. A.4). */
 typedef struct mh_grid_desc {
@@ -78,7 +84,7 @@ typedef struct mh_grid_desc {
   int32_t dtype;
   int32_t limiter;
   int32_t riemann;
-  int32_t reserved0;
+  int32_t integrator;
   double gamma;
   double cfl;
 } mh_grid_desc;

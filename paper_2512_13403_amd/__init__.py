@@ -25,6 +25,7 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 F32, F64 = 0, 1
 LIM_MINMOD, LIM_NONE, LIM_VANLEER, LIM_MC, LIM_SUPERBEE = 0, 1, 2, 3, 4
 RS_HLLC, RS_HLL, RS_RUSANOV = 0, 1, 2
+RK_SSP2, RK_SSP3, RK_EULER = 0, 1, 2
 SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
 HOST, DEVICE = 0, 1
 
@@ -45,7 +46,7 @@ class GridDesc(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32 * 3), ("bc", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3),
         ("dtype", ctypes.c_int32), ("limiter", ctypes.c_int32), ("riemann", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("integrator", ctypes.c_int32), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
     ]
 
 
@@ -145,8 +146,9 @@ def load_library():
 
 
 def grid_desc(shape, h, bc=(BC_PERIODIC,) * 3, dtype="f32", gamma=5.0 / 3.0, cfl=0.4,
-              limiter=LIM_MINMOD, riemann=RS_HLLC) -> GridDesc:
-    """shape = (nz, ny, nx); h and bc per (x, y, z)."""
+              limiter=LIM_MINMOD, riemann=RS_HLLC, integrator=RK_SSP2) -> GridDesc:
+    """shape = (nz, ny, nx); h and bc per (x, y, z); integrator RK_SSP2 (default),
+    RK_SSP3 or RK_EULER."""
     g = GridDesc()
     nz, ny, nx = shape
     g.n[:] = [nx, ny, nz]
@@ -154,6 +156,7 @@ def grid_desc(shape, h, bc=(BC_PERIODIC,) * 3, dtype="f32", gamma=5.0 / 3.0, cfl
     g.h[:] = list(h)
     g.dtype = F64 if dtype in ("f64", "float64", F64) else F32
     g.limiter, g.riemann, g.gamma, g.cfl = limiter, riemann, gamma, cfl
+    g.integrator = integrator
     return g
 
 

@@ -317,12 +317,12 @@ __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
   for (int s = 0; s < 5; ++s) Wacc[perm[s] * N + q] += acc[s];
 }
 
-// out = c0 x0 + c1 x1 + beta (dW/dU)^T Wacc, W = (rho, v, P) of U
+// out = c0 x0 + c1 x1 + c2 x2 + beta (dW/dU)^T Wacc, W = (rho, v, P) of U
 template <typename T>
 __global__ __launch_bounds__(256) void k_jtv_finish(const T* __restrict__ U,
                                                     const T* __restrict__ Wacc, long long N, T gm1,
                                                     T beta, T c0, const T* x0, T c1, const T* x1,
-                                                    T* out) {
+                                                    T c2, const T* x2, T* out) {
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   if (q >= N) return;
   const T rho = U[q];
@@ -341,6 +341,7 @@ __global__ __launch_bounds__(256) void k_jtv_finish(const T* __restrict__ U,
     T o = beta * g[f];
     if (x0) o += c0 * x0[f * N + q];
     if (x1) o += c1 * x1[f * N + q];
+    if (x2) o += c2 * x2[f * N + q];
     out[f * N + q] = o;
   }
 }
@@ -534,7 +535,7 @@ inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 template <typename T>
 hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, T gamma,
                    const double* h, const T* U, const T* v, T beta, T c0, const T* x0, T c1,
-                   const T* x1, T* out, hipStream_t s) {
+                   const T* x1, T c2, const T* x2, T* out, hipStream_t s) {
   const long long N = (long long)geom.nx * geom.ny * geom.nz;
   hipLaunchKernelGGL((k_fill<T>), dim3(nblk(5 * N)), dim3(256), 0, s, B.Wacc, 5 * N, T(0));
   const int nn[3] = {geom.nx, geom.ny, geom.nz};
@@ -561,7 +562,7 @@ hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limite
 #undef MH_FACE
   }
   hipLaunchKernelGGL((k_jtv_finish<T>), dim3(nblk(N)), dim3(256), 0, s, U, B.Wacc, N,
-                     gamma - T(1), beta, c0, x0, c1, x1, out);
+                     gamma - T(1), beta, c0, x0, c1, x1, c2, x2, out);
   return hipGetLastError();
 }
 
@@ -617,7 +618,7 @@ hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws
 #define ADJ_INSTANTIATE(T)                                                                       \
   template hipError_t adj_jtv<T>(const AdjointBuffers<T>&, const StageGeom&, int, T,             \
                                  const double*, const T*, const T*, T, T, const T*, T, const T*, \
-                                 T*, hipStream_t);                                               \
+                                 T, const T*, T*, hipStream_t);                                  \
   template hipError_t adj_force_kick<T>(T*, const T*, const T*, int, const StageGeom&, T,        \
                                         hipStream_t);                                            \
   template hipError_t adj_force_kick_vjp<T>(const T*, const T*, int, const StageGeom&, T,        \

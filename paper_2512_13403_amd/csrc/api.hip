@@ -23,7 +23,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-  size_t U = 0, U1 = 0, clk = 0, dtlog = 0, ou_n = 0, ou_ahat = 0, ou_coef = 0, ou_rows = 0;
+  size_t U = 0, U1 = 0, U2 = 0, clk = 0, dtlog = 0, ou_n = 0, ou_ahat = 0, ou_coef = 0, ou_rows = 0;
   size_t tab[3] = {0, 0, 0};
   MGLayout mg;
   size_t total = 0;
@@ -70,6 +70,8 @@ mh_status validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string&
     return fail(MH_E_UNSUPPORTED, "unknown limiter");
   if (g->riemann < MH_RS_HLLC || g->riemann > MH_RS_RUSANOV)
     return fail(MH_E_UNSUPPORTED, "unknown Riemann solver");
+  if (g->integrator < MH_RK_SSP2 || g->integrator > MH_RK_EULER)
+    return fail(MH_E_UNSUPPORTED, "unknown time integrator");
   if (!(g->gamma > 1.0)) return fail(MH_E_INVALID, "gamma must exceed 1");
   if (!(g->cfl > 0.0)) return fail(MH_E_INVALID, "CFL number must be positive");
   const uint32_t known = MH_SRC_COOLING | MH_SRC_FORCING | MH_SRC_GRAVITY;
@@ -111,6 +113,7 @@ Layout make_layout(const mh_grid_desc* g, const mh_physics_desc* p, int nmodes) 
   };
   L.U = take(5 * N * es);
   L.U1 = take(5 * N * es);
+  if (g->integrator == MH_RK_SSP3) L.U2 = take(5 * N * es);
   L.clk = take(sizeof(DevClock));
   L.dtlog = take(DTLOG_CAP * sizeof(double));
   if (p->flags & MH_SRC_FORCING) {
@@ -346,6 +349,8 @@ static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) 
   a.cool = cool_params<T>(g, p);
   a.lim = g.limiter;
   a.rs = g.riemann;
+  a.ca = T(0.5);
+  a.cb = T(0.5);
   if (p.flags & MH_SRC_FORCING) {
     a.ou_rows = ou_rows;
     for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
@@ -395,27 +400,59 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
                                      a.ou_tab[1], a.ou_tab[2], g.n[1], g.n[2], a.ou_R,
                                      c->at<T>(c->L.ou_rows), c->stream));
     time_end(c, tk);
-    a.uin = U;
-    a.un = nullptr;
-    a.uout = U1;
-    tk = time_begin(c, MH_TIME_STAGE1);
-    MH_HIP(c, launch_stage<T>(1, g.limiter, false, false, a, geom, c->stream));
-    time_end(c, tk);
-    a.uin = U1;
-    a.un = U;
-    a.uout = U;
+    // all stages but the last
+    if (g.integrator != MH_RK_EULER) {
+      a.uin = U;
+      a.un = nullptr;
+      a.uout = U1;
+      tk = time_begin(c, MH_TIME_STAGE1);
+      MH_HIP(c, launch_stage<T>(1, g.limiter, false, false, a, geom, c->stream));
+      time_end(c, tk);
+    }
+    if (g.integrator == MH_RK_SSP3) {
+      T* U2 = c->at<T>(c->L.U2);
+      a.uin = U1;
+      a.un = U;
+      a.uout = U2;
+      a.ca = T(0.75);
+      a.cb = T(0.25);
+      tk = time_begin(c, MH_TIME_OTHER);
+      MH_HIP(c, launch_stage<T>(3, g.limiter, false, false, a, geom, c->stream));
+      time_end(c, tk);
+      a.uin = U2;
+      a.uout = U;
+      a.ca = T(1.0 / 3.0);
+      a.cb = T(2.0 / 3.0);
+    } else if (g.integrator == MH_RK_EULER) {
+      a.uin = U;  // the lone stage reads U with its stencil, so it writes U1
+      a.un = nullptr;
+      a.uout = U1;
+    } else {
+      a.uin = U1;
+      a.un = U;
+      a.uout = U;
+    }
+    // the last stage, with the sources
     if (grav) {
-      // forcing fused into stage 2; gravity needs the new density everywhere
-      // first, then the kick, cooling and CFL run in the sources kernel
+      // forcing fused into the last stage; gravity needs the new density
+      // everywhere first, then the kick, cooling and CFL run in the sources
+      // kernel
       tk = time_begin(c, MH_TIME_STAGE2);
       MH_HIP(c, launch_stage<T>(2, g.limiter, force, false, a, geom, c->stream));
-      time_end(c, tk);
-      tk = time_begin(c, MH_TIME_OTHER);
-      MH_HIP(c, mg_gravity_step<T>(c->ws, c->L.mg, c->g, c->p, a.cool, U, clk, c->stream));
       time_end(c, tk);
     } else {
       tk = time_begin(c, MH_TIME_STAGE2);
       MH_HIP(c, launch_stage<T>(2, g.limiter, force, cool, a, geom, c->stream));
+      time_end(c, tk);
+    }
+    if (g.integrator == MH_RK_EULER)
+      MH_HIP(c, hipMemcpyAsync(U, U1, 5 * (size_t)c->cells() * sizeof(T),
+                               hipMemcpyDeviceToDevice, c->stream));
+    a.ca = T(0.5);
+    a.cb = T(0.5);
+    if (grav) {
+      tk = time_begin(c, MH_TIME_OTHER);
+      MH_HIP(c, mg_gravity_step<T>(c->ws, c->L.mg, c->g, c->p, a.cool, U, clk, c->stream));
       time_end(c, tk);
     }
     c->smax_valid = true;
@@ -525,7 +562,8 @@ extern "C" mh_status mh_get_potential(mh_ctx* c, void* phi, int where) {
 namespace {
 
 struct AdjLayout {
-  size_t clk = 0, dtlog = 0, U1 = 0, Ua = 0, Ub = 0, Uc = 0, lamA = 0, lamB = 0, lam1 = 0;
+  size_t clk = 0, dtlog = 0, U1 = 0, U2 = 0, Ua = 0, Ub = 0, Uc = 0, lamA = 0, lamB = 0;
+  size_t lam1 = 0, lam2 = 0;
   size_t Wacc = 0, wbar = 0, flags = 0, accb = 0, phib = 0, ahat = 0, coef = 0, rows = 0;
   MGLayout mg;
   size_t total = 0;
@@ -556,6 +594,10 @@ AdjLayout make_adj_layout(const mh_grid_desc& g, const mh_physics_desc& p) {
   A.lamA = take(5 * N * es);
   A.lamB = take(5 * N * es);
   A.lam1 = take(5 * N * es);
+  if (g.integrator == MH_RK_SSP3) {
+    A.U2 = take(5 * N * es);
+    A.lam2 = take(5 * N * es);
+  }
   A.Wacc = take(5 * N * es);
   A.wbar = take(10 * faces * es);
   A.flags = take(faces * sizeof(int));
@@ -629,13 +671,29 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
     MH_HIP(c, launch_force_rows<T>(at(A.coef), c->at<int>(c->L.ou_n), c->nmodes, a.ou_tab[1],
                                    a.ou_tab[2], g.n[1], g.n[2], a.ou_R, at(A.rows), c->stream));
 
-  // forward recomputation: U1, Ua (RK2), Ub (forcing), Uc (gravity)
-  a.uin = Un;
-  a.un = nullptr;
-  a.uout = U1;
-  MH_HIP(c, launch_stage<T>(1, g.limiter, false, false, a, geom, c->stream));
-  a.uin = U1;
-  a.un = Un;
+  // forward recomputation: U1 (and U2), Ua (the RK update), Ub (forcing), Uc
+  // (gravity)
+  T* U2 = g.integrator == MH_RK_SSP3 ? at(A.U2) : nullptr;
+  if (g.integrator == MH_RK_EULER) {
+    a.uin = Un;
+    a.un = nullptr;
+  } else {
+    a.uin = Un;
+    a.un = nullptr;
+    a.uout = U1;
+    MH_HIP(c, launch_stage<T>(1, g.limiter, false, false, a, geom, c->stream));
+    a.uin = U1;
+    a.un = Un;
+  }
+  if (U2) {
+    a.uout = U2;
+    a.ca = T(0.75);
+    a.cb = T(0.25);
+    MH_HIP(c, launch_stage<T>(3, g.limiter, false, false, a, geom, c->stream));
+    a.uin = U2;
+    a.ca = T(1.0 / 3.0);
+    a.cb = T(2.0 / 3.0);
+  }
   a.uout = Ua;
   MH_HIP(c, launch_stage<T>(2, g.limiter, false, false, a, geom, c->stream));
   MH_HIP(c, hipMemcpyAsync(Ub, Ua, sbytes, hipMemcpyDeviceToDevice, c->stream));
@@ -651,7 +709,7 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
     phi_sol = reinterpret_cast<const T*>(ws + mg_phi_offset(A.mg));
   }
 
-  // reverse sweep: cooling, gravity, forcing, then RK2
+  // reverse sweep: cooling, gravity, forcing, then the RK update
   const T* cur = lam_np1;
   if (cool) {
     MH_HIP(c, adj_cool_vjp<T>(Uc, N, (T)(g.gamma - 1.0), (T)dt, a.cool, cur, lamA, c->stream));
@@ -668,11 +726,29 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
                                     c->stream));
     cur = dst;
   }
-  // lam1 = cur/2 + (dt/2) J(U1)^T cur;  lam_n = cur/2 + lam1 + dt J(U^n)^T lam1
-  MH_HIP(c, adj_jtv<T>(B, geom, g.limiter, (T)g.gamma, g.h, U1, cur, (T)(0.5 * dt), T(0.5), cur,
-                       T(0), nullptr, lam1, c->stream));
-  MH_HIP(c, adj_jtv<T>(B, geom, g.limiter, (T)g.gamma, g.h, Un, lam1, (T)dt, T(0.5), cur, T(1),
-                       lam1, lam_n, c->stream));
+  const int lim = g.limiter;
+  const T gam = (T)g.gamma;
+  if (g.integrator == MH_RK_EULER) {
+    // lam_n = cur + dt J(U^n)^T cur
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, Un, cur, (T)dt, T(1), cur, T(0), nullptr, T(0),
+                         nullptr, lam_n, c->stream));
+  } else if (g.integrator == MH_RK_SSP3) {
+    // lam2 = 2/3 (cur + dt J(U2)^T cur);  lam1 = 1/4 (lam2 + dt J(U1)^T lam2);
+    // lam_n = cur/3 + 3/4 lam2 + lam1 + dt J(U^n)^T lam1
+    T* lam2 = at(A.lam2);
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, U2, cur, (T)(2.0 / 3.0 * dt), (T)(2.0 / 3.0),
+                         cur, T(0), nullptr, T(0), nullptr, lam2, c->stream));
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, U1, lam2, (T)(0.25 * dt), T(0.25), lam2, T(0),
+                         nullptr, T(0), nullptr, lam1, c->stream));
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, Un, lam1, (T)dt, (T)(1.0 / 3.0), cur, T(0.75),
+                         lam2, T(1), lam1, lam_n, c->stream));
+  } else {
+    // lam1 = cur/2 + (dt/2) J(U1)^T cur;  lam_n = cur/2 + lam1 + dt J(U^n)^T lam1
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, U1, cur, (T)(0.5 * dt), T(0.5), cur, T(0),
+                         nullptr, T(0), nullptr, lam1, c->stream));
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, Un, lam1, (T)dt, T(0.5), cur, T(1), lam1, T(0),
+                         nullptr, lam_n, c->stream));
+  }
   return MH_OK;
 }
 

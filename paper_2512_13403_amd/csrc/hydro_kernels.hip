@@ -2,9 +2,12 @@
 //
 // One launch of k_stage performs one Runge-Kutta stage of the unsplit
 // method-of-lines update of diffhydro (arXiv 2512.13403, App. A.3):
-//   stage 1:  U1     = U^n + dt L(U^n)
-//   stage 2:  U^{n+1} = U^n / 2 + (U1 + dt L(U1)) / 2
-// with L(U) = -sum_a (F_{a,i+1/2} - F_{a,i-1/2}) / dx_a, the face fluxes F
+//   stage 1:  U1 = U^n + dt L(U^n)
+//   stage 3:  U' = ca U^n + cb (Uk + dt L(Uk))            (an inner stage)
+//   stage 2:  U^{n+1} = ca U^n + cb (Uk + dt L(Uk)), then the sources
+// -- (ca, cb) = (1/2, 1/2) after stage 1 for the two-stage SSP-RK2; (3/4, 1/4)
+// for the inner stage and (1/3, 2/3) for the last one in SSPRK3; forward Euler
+// is a lone final stage without U^n -- with L(U) = -sum_a (F_{a,i+1/2} - F_{a,i-1/2}) / dx_a, the face fluxes F
 // from HLLC (App. A.2) on MUSCL face states of the primitive variables with a
 // minmod-limited slope (App. A.1).  Stage 2 also applies, per cell and in
 // registers, the operator-split sources in the order forcing -> cooling
@@ -419,12 +422,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       un[f] = fmad(dt, L, u[0][f]);
     }
     const long long q = (long long)z * plane + col;
-    if (STAGE == 1) {
-      if (inside) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
-      }
-    } else {
+    if (STAGE != 1 && a.un != nullptr) {
       T u0[5];
       if (inside) load_cell(a.un, N, q, u0);
       else {
@@ -432,8 +430,14 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         for (int f = 0; f < 5; ++f) u0[f] = u[0][f];
       }
 #pragma unroll
-      for (int f = 0; f < 5; ++f) un[f] = fmad(T(0.5), u0[f], T(0.5) * un[f]);
-
+      for (int f = 0; f < 5; ++f) un[f] = fmad(a.ca, u0[f], a.cb * un[f]);
+    }
+    if (STAGE != 2) {
+      if (inside) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
+      }
+    } else {
       if (FORCE) {
         // a(x) = scale sum_m 2 Re(ahat_m exp(2 pi i n_m . x / L)) at the cell
         // centre; coef = 2 scale ahat (T), phase tables per axis for n >= 0,
@@ -653,6 +657,10 @@ hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs
     if (limiter == LIM_NONE) MH_LAUNCH(1, LIM_NONE, false, false);
     else if (limiter == LIM_GENERIC) MH_LAUNCH(1, LIM_GENERIC, false, false);
     else MH_LAUNCH(1, LIM_MINMOD, false, false);
+  } else if (stage == 3) {
+    if (limiter == LIM_NONE) MH_LAUNCH(3, LIM_NONE, false, false);
+    else if (limiter == LIM_GENERIC) MH_LAUNCH(3, LIM_GENERIC, false, false);
+    else MH_LAUNCH(3, LIM_MINMOD, false, false);
   } else if (limiter == LIM_GENERIC) {
     if (force && cool) MH_LAUNCH(2, LIM_GENERIC, true, true);
     else if (force) MH_LAUNCH(2, LIM_GENERIC, true, false);

@@ -16,7 +16,8 @@ struct StageGeom {
 template <typename T>
 struct StageArgs {
   const T* __restrict__ uin;  // stage input (read with halo)
-  const T* un;                // U^n at the cell itself (stage 2; may alias uout)
+  const T* un;                // U^n at the cell itself (stages 2 and 3; may alias uout;
+                              // NULL: no combination with U^n)
   T* uout;                    // stage output
   DevClock* clk;
   const T* __restrict__ ou_rows;  // [nz][ny][R+1][3][P, Q] forcing row records
@@ -29,6 +30,7 @@ struct StageArgs {
   CoolParams<T> cool;
   int zc, nbx, nby, nbz, nb_per_xcd;
   int lim, rs;  // limiter and Riemann solver (read by the run-time-scheme kernel)
+  T ca, cb;     // stages 2 and 3: out = ca U^n + cb (uin + dt L(uin))
 };
 
 struct OUArgs {

@@ -71,6 +71,19 @@ def test_adjoint_forcing_cooling(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("integrator", [oracle.RK_SSP3, oracle.RK_EULER])
+def test_adjoint_other_integrators(dtype, integrator):
+    """Reverse of SSPRK3 and forward Euler (App. A.3) with forcing and cooling,
+    outflow in x."""
+    shape = (9, 11, 70)
+    U0 = wl.random_state(shape, seed=34, vmax=0.6)
+    got, ref = gpu_vs_oracle_adjoint(shape, (1 / 70, 1 / 11, 1 / 9), U0, dtype, (1, 0, 0),
+                                     flags=oracle.SRC_FORCING | oracle.SRC_COOLING, ou_seed=6,
+                                     integrator=integrator)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_gravity_cooling(dtype):
     n = 16
     U0 = wl.grf_density_state(n, seed=5)

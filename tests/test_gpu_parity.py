@@ -87,6 +87,57 @@ def test_sod_full_run_scheme_variants_fp64(limiter, riemann):
     assert np.array_equal(U, np.broadcast_to(U[:, :1, :1, :], U.shape))
 
 
+INTEGRATORS = [oracle.RK_SSP3, oracle.RK_EULER]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_other_integrators_ragged(dtype, integrator):
+    """SSPRK3 (stage kernel with an inner stage) and forward Euler (a lone
+    final stage) of App. A.3 against the oracle, 5 steps on a ragged grid."""
+    shape = (19, 21, 77)
+    h = (1 / 77, 1 / 21, 1 / 19)
+    U0 = wl.random_state(shape, seed=2, vmax=0.6)
+    s, sim = run_both(shape, h, U0, dtype, 5, integrator=integrator)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_other_integrators_with_sources_and_variant(dtype, integrator):
+    """The run-time-scheme kernel (van Leer + HLL) with forcing and cooling."""
+    shape = (12, 14, 66)
+    h = (1 / 66, 1 / 14, 1 / 12)
+    U0 = wl.random_state(shape, seed=10, vmax=0.5)
+    s, sim = run_both(shape, h, U0, dtype, 3, limiter=oracle.LIM_VANLEER, riemann=oracle.RS_HLL,
+                      flags=oracle.SRC_FORCING | oracle.SRC_COOLING, ou_seed=5,
+                      integrator=integrator)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ssprk3_gravity_cooling(dtype):
+    n = 32
+    U0 = wl.grf_density_state(n, seed=1)
+    s, sim = run_both((n, n, n), (1 / n,) * 3, U0, dtype, 3,
+                      flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING, grav_G=wl.JEANS_G,
+                      mg_tol=0.0, mg_max_cycles=3, integrator=oracle.RK_SSP3)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+def test_sod_full_run_ssprk3_fp64():
+    grid = wl.sod_grid(128, 16, 16)
+    U0 = wl.sod_state(grid)
+    s, oc = pair(grid.shape, grid.h, grid.bc, "f64", gamma=1.4, integrator=oracle.RK_SSP3)
+    s.set_state(U0)
+    dts = s.run_to(0.2)
+    sim = oracle.Simulation(oc, U0)
+    assert len(dts) == sim.run_to(0.2)
+    U = s.get_state()
+    assert rel_err(U, sim.U) < 1e-12
+    assert np.array_equal(U, np.broadcast_to(U[:, :1, :1, :], U.shape))
+
+
 def test_adjoint_rejects_scheme_variants():
     import torch
 

@@ -54,6 +54,8 @@ def test_workspace_size_of_valid_grids():
     (lambda g, p: setattr(g, "limiter", 9), mh.E_UNSUPPORTED),
     (lambda g, p: setattr(g, "riemann", 7), mh.E_UNSUPPORTED),
     (lambda g, p: setattr(g, "limiter", -1), mh.E_UNSUPPORTED),
+    (lambda g, p: setattr(g, "integrator", 3), mh.E_UNSUPPORTED),
+    (lambda g, p: setattr(g, "integrator", -1), mh.E_UNSUPPORTED),
     (lambda g, p: setattr(p, "flags", 64), mh.E_INVALID),
     (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_tau", 0.0)), mh.E_INVALID),
     (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_kmin", 3.0),
@@ -77,6 +79,16 @@ def test_scheme_variants_are_accepted():
         for rs in (mh.RS_HLLC, mh.RS_HLL, mh.RS_RUSANOV):
             g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32", limiter=lim, riemann=rs)
             assert ws(g, mh.physics_desc())[0] == mh.OK
+
+
+def test_ssprk3_workspace_holds_one_more_state():
+    p = mh.physics_desc()
+    g2 = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32")
+    g3 = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32", integrator=mh.RK_SSP3)
+    ge = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32", integrator=mh.RK_EULER)
+    (s2, n2), (s3, n3), (se, ne) = ws(g2, p), ws(g3, p), ws(ge, p)
+    assert s2 == s3 == se == mh.OK
+    assert n3 >= n2 + 5 * 16 ** 3 * 4 and ne == n2
 
 
 def test_gravity_coarsest_grid_limit():
