@@ -72,6 +72,10 @@ int or_num_threads(void);
 /* reverse-mode derivatives (oracle_adjoint.c) */
 void or_hllc_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],
                  double wlb[5], double wrb[5]);
+void or_hll_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],
+                double wlb[5], double wrb[5]);
+void or_rusanov_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],
+                    double wlb[5], double wrb[5]);
 void or_rhs_vjp(const or_config *c, const double *U, const double *v, double *out);
 void or_euler_vjp(const or_config *c, const double *U, double dt, const double *lam1,
                   double *lam);

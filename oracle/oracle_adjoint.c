@@ -14,7 +14,9 @@
  * the derivative of the argument it returned (0 when it returned 0), min/max
  * of the wave speeds that of the argument selected (the first on ties), the
  * HLLC region that of the region selected, the cooling branch and floor those
- * of the branch taken.
+ * of the branch taken.  The other limiters (van Leer, MC, superbee) and
+ * solvers (HLL, Rusanov) follow the same rule; the branch orders are given
+ * at lim_partials and at the solvers' reverse functions.
  *
  * All vectors are laid out like the state: [5][nz][ny][nx].
  */
@@ -53,6 +55,56 @@ static double minmod_sel(double a, double b, int *sel) {
   }
   *sel = 2;
   return b;
+}
+
+/* A limited slope phi(a, b) of App. A.1 (a = W_{i+1} - W_i, b = W_i -
+ * W_{i-1}), computed like oracle.c, with its partial derivatives pa =
+ * dphi/da, pb = dphi/db on the branch taken.  Every limiter is 0 (pa = pb =
+ * 0) when ab <= 0.  Otherwise:
+ *   minmod   a if |a| <= |b| (1, 0), else b (0, 1);
+ *   van Leer 2ab/(a+b): (2b^2/(a+b)^2, 2a^2/(a+b)^2);
+ *   MC       the smallest of |a+b|/2, 2|a|, 2|b| with the sign of a, ties in
+ *            that order: (a+b)/2 (1/2, 1/2), 2a (2, 0), 2b (0, 2);
+ *   superbee max(min(2|a|, |b|), min(|a|, 2|b|)) with the sign of a: the
+ *            first min on ties, each min its first argument on ties:
+ *            2a (2, 0), b (0, 1), a (1, 0), 2b (0, 2). */
+static double lim_partials(int limiter, double a, double b, double *pa, double *pb) {
+  *pa = 0.0;
+  *pb = 0.0;
+  if (limiter == OR_LIM_NONE || a * b <= 0.0) return 0.0;
+  if (limiter == OR_LIM_MINMOD) {
+    int sel;
+    double m = minmod_sel(a, b, &sel);
+    *pa = sel == 1 ? 1.0 : 0.0;
+    *pb = sel == 2 ? 1.0 : 0.0;
+    return m;
+  }
+  if (limiter == OR_LIM_VANLEER) {
+    double s = a + b;
+    *pa = 2.0 * b * b / (s * s);
+    *pb = 2.0 * a * a / (s * s);
+    return 2.0 * a * b / (a + b);
+  }
+  if (limiter == OR_LIM_MC) {
+    double cen = fabs(0.5 * (a + b)), ta = 2.0 * fabs(a), tb = 2.0 * fabs(b);
+    double m = fmin(cen, fmin(ta, tb));
+    if (cen <= fmin(ta, tb)) { *pa = 0.5; *pb = 0.5; }
+    else if (ta <= tb) *pa = 2.0;
+    else *pb = 2.0;
+    return a > 0.0 ? m : -m;
+  }
+  /* superbee */
+  double s1 = fmin(2.0 * fabs(a), fabs(b));
+  double s2 = fmin(fabs(a), 2.0 * fabs(b));
+  double m = fmax(s1, s2);
+  if (s1 >= s2) {
+    if (2.0 * fabs(a) <= fabs(b)) *pa = 2.0;
+    else *pb = 1.0;
+  } else {
+    if (fabs(a) <= 2.0 * fabs(b)) *pa = 1.0;
+    else *pb = 2.0;
+  }
+  return a > 0.0 ? m : -m;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -198,6 +250,117 @@ void or_hllc_vjp(const double wl[5], const double wr[5], double g, const double 
 }
 
 /* ------------------------------------------------------------------------- */
+/* HLL and Rusanov: reverse sweeps                                            */
+/* ------------------------------------------------------------------------- */
+
+/* conserved state U and flux F of a face-frame primitive state (oracle.c's
+ * flux_of), and the reverse: adds dL/dw given Ub = dL/dU, Fb = dL/dF */
+static void state_flux(const double w[5], double g, double U[5], double F[5]) {
+  double rho = w[0], vn = w[1], t1 = w[2], t2 = w[3], p = w[4];
+  double E = p / (g - 1.0) + 0.5 * rho * (vn * vn + t1 * t1 + t2 * t2);
+  U[0] = rho; U[1] = rho * vn; U[2] = rho * t1; U[3] = rho * t2; U[4] = E;
+  F[0] = rho * vn; F[1] = rho * vn * vn + p; F[2] = rho * vn * t1; F[3] = rho * vn * t2;
+  F[4] = vn * (E + p);
+}
+
+static void state_flux_vjp(const double w[5], double g, const double Ub[5], const double Fb[5],
+                           double wb[5]) {
+  double rho = w[0], vn = w[1], t1 = w[2], t2 = w[3], p = w[4];
+  double E = p / (g - 1.0) + 0.5 * rho * (vn * vn + t1 * t1 + t2 * t2);
+  double Eb = Ub[4] + Fb[4] * vn;
+  wb[0] += Ub[0] + Ub[1] * vn + Ub[2] * t1 + Ub[3] * t2 + Fb[0] * vn + Fb[1] * vn * vn +
+           Fb[2] * vn * t1 + Fb[3] * vn * t2 + Eb * 0.5 * (vn * vn + t1 * t1 + t2 * t2);
+  wb[1] += Ub[1] * rho + Fb[0] * rho + Fb[1] * 2.0 * rho * vn + Fb[2] * rho * t1 +
+           Fb[3] * rho * t2 + Fb[4] * (E + p) + Eb * rho * vn;
+  wb[2] += Ub[2] * rho + Fb[2] * rho * vn + Eb * rho * t1;
+  wb[3] += Ub[3] * rho + Fb[3] * rho * vn + Eb * rho * t2;
+  wb[4] += Fb[1] + Fb[4] * vn + Eb / (g - 1.0);
+}
+
+/* c = sqrt(g P / rho) reversed: adds cb dc/dw to wb */
+static void sound_vjp(const double w[5], double g, double c, double cb, double wb[5]) {
+  wb[4] += cb * g / (2.0 * c * w[0]);
+  wb[0] -= cb * c / (2.0 * w[0]);
+}
+
+/* Reverse of oracle.c's HLL flux.  Regions: F_L when 0 <= S_L, else F_R when
+ * S_R <= 0, else the HLL average
+ *   F = (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L),
+ * whose partials are dF/dS_L = (S_R (U_R - U_L) - F_R + F)/(S_R - S_L),
+ * dF/dS_R = (F_L + S_L (U_R - U_L) - F)/(S_R - S_L).  The Davis min/max
+ * take the left argument on ties, as in or_hllc_vjp. */
+void or_hll_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],
+                double wlb[5], double wrb[5]) {
+  double UL[5], FL[5], UR[5], FR[5];
+  state_flux(wl, g, UL, FL);
+  state_flux(wr, g, UR, FR);
+  double cl = sqrt(g * wl[4] / wl[0]), cr = sqrt(g * wr[4] / wr[0]);
+  int minL = (wl[1] - cl) <= (wr[1] - cr);
+  int maxL = (wl[1] + cl) >= (wr[1] + cr);
+  double SL = minL ? wl[1] - cl : wr[1] - cr;
+  double SR = maxL ? wl[1] + cl : wr[1] + cr;
+  double ULb[5] = {0}, FLb[5] = {0}, URb[5] = {0}, FRb[5] = {0};
+  double SLb = 0.0, SRb = 0.0;
+  if (0.0 <= SL) {
+    for (int f = 0; f < 5; ++f) FLb[f] = Fb[f];
+  } else if (SR <= 0.0) {
+    for (int f = 0; f < 5; ++f) FRb[f] = Fb[f];
+  } else {
+    double D = SR - SL;
+    for (int f = 0; f < 5; ++f) {
+      double F = (SR * FL[f] - SL * FR[f] + SL * SR * (UR[f] - UL[f])) / D;
+      FLb[f] = Fb[f] * SR / D;
+      FRb[f] = -Fb[f] * SL / D;
+      URb[f] = Fb[f] * SL * SR / D;
+      ULb[f] = -URb[f];
+      SLb += Fb[f] * (SR * (UR[f] - UL[f]) - FR[f] + F) / D;
+      SRb += Fb[f] * (FL[f] + SL * (UR[f] - UL[f]) - F) / D;
+    }
+  }
+  double clb = 0.0, crb = 0.0;
+  if (minL) { wlb[1] += SLb; clb -= SLb; } else { wrb[1] += SLb; crb -= SLb; }
+  if (maxL) { wlb[1] += SRb; clb += SRb; } else { wrb[1] += SRb; crb += SRb; }
+  sound_vjp(wl, g, cl, clb, wlb);
+  sound_vjp(wr, g, cr, crb, wrb);
+  state_flux_vjp(wl, g, ULb, FLb, wlb);
+  state_flux_vjp(wr, g, URb, FRb, wrb);
+}
+
+/* Reverse of the Rusanov flux F = (F_L + F_R)/2 - s (U_R - U_L)/2 with
+ * s = max(|v_L| + c_L, |v_R| + c_R): the left argument on ties, and
+ * d|v|/dv = -1 for v < 0, else +1. */
+void or_rusanov_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],
+                    double wlb[5], double wrb[5]) {
+  double UL[5], FL[5], UR[5], FR[5];
+  state_flux(wl, g, UL, FL);
+  state_flux(wr, g, UR, FR);
+  double cl = sqrt(g * wl[4] / wl[0]), cr = sqrt(g * wr[4] / wr[0]);
+  int maxL = (fabs(wl[1]) + cl) >= (fabs(wr[1]) + cr);
+  double s = maxL ? fabs(wl[1]) + cl : fabs(wr[1]) + cr;
+  double ULb[5], FLb[5], URb[5], FRb[5];
+  double sb = 0.0;
+  for (int f = 0; f < 5; ++f) {
+    FLb[f] = 0.5 * Fb[f];
+    FRb[f] = 0.5 * Fb[f];
+    URb[f] = -0.5 * s * Fb[f];
+    ULb[f] = 0.5 * s * Fb[f];
+    sb -= 0.5 * Fb[f] * (UR[f] - UL[f]);
+  }
+  double clb = 0.0, crb = 0.0;
+  if (maxL) {
+    wlb[1] += sb * (wl[1] < 0.0 ? -1.0 : 1.0);
+    clb = sb;
+  } else {
+    wrb[1] += sb * (wr[1] < 0.0 ? -1.0 : 1.0);
+    crb = sb;
+  }
+  sound_vjp(wl, g, cl, clb, wlb);
+  sound_vjp(wr, g, cr, crb, wrb);
+  state_flux_vjp(wl, g, ULb, FLb, wlb);
+  state_flux_vjp(wr, g, URb, FRb, wrb);
+}
+
+/* ------------------------------------------------------------------------- */
 /* J(U)^T v for L = or_rhs                                                    */
 /* ------------------------------------------------------------------------- */
 
@@ -225,7 +388,8 @@ void or_rhs_vjp(const or_config *c, const double *U, const double *v, double *ou
       double (*wg)[5] = malloc(sizeof(double[5]) * (n + 4));
       double (*wgb)[5] = calloc(n + 4, sizeof(double[5]));
       double (*slope)[5] = malloc(sizeof(double[5]) * (n + 2));
-      int (*sel)[5] = malloc(sizeof(int[5]) * (n + 2));
+      double (*pa)[5] = malloc(sizeof(double[5]) * (n + 2));
+      double (*pb)[5] = malloc(sizeof(double[5]) * (n + 2));
       long *q = malloc(sizeof(long) * (n + 4)); /* cell of each position */
       long cq[3];
       for (long i = -2; i < n + 2; ++i) {
@@ -238,12 +402,7 @@ void or_rhs_vjp(const or_config *c, const double *U, const double *v, double *ou
       for (long i = -1; i <= n; ++i)
         for (int s = 0; s < 5; ++s) {
           double av = wg[i + 3][s] - wg[i + 2][s], bv = wg[i + 2][s] - wg[i + 1][s];
-          if (c->limiter == OR_LIM_MINMOD) {
-            slope[i + 1][s] = minmod_sel(av, bv, &sel[i + 1][s]);
-          } else {
-            slope[i + 1][s] = 0.0;
-            sel[i + 1][s] = 0;
-          }
+          slope[i + 1][s] = lim_partials(c->limiter, av, bv, &pa[i + 1][s], &pb[i + 1][s]);
         }
       for (long fidx = 0; fidx <= n; ++fidx) {
         double wl[5], wr[5], Fb[5], wlb[5] = {0}, wrb[5] = {0};
@@ -256,25 +415,29 @@ void or_rhs_vjp(const or_config *c, const double *U, const double *v, double *ou
           double left = (fidx - 1 >= 0) ? v[perm[s] * N + q[fidx + 1]] : 0.0;
           Fb[s] = (right - left) * inv_h;
         }
-        or_hllc_vjp(wl, wr, c->gamma, Fb, wlb, wrb);
+        if (c->riemann == OR_RS_HLL) or_hll_vjp(wl, wr, c->gamma, Fb, wlb, wrb);
+        else if (c->riemann == OR_RS_RUSANOV) or_rusanov_vjp(wl, wr, c->gamma, Fb, wlb, wrb);
+        else or_hllc_vjp(wl, wr, c->gamma, Fb, wlb, wrb);
         /* wl = W_{i} + slope_i/2 (i = fidx-1, position fidx+1), with
-         * slope_i = minmod(W_{i+1} - W_i, W_i - W_{i-1}) */
+         * slope_i = phi(W_{i+1} - W_i, W_i - W_{i-1}) */
         for (int s = 0; s < 5; ++s) {
           wgb[fidx + 1][s] += wlb[s];
           double sb = 0.5 * wlb[s];
-          if (sel[fidx][s] == 1) { wgb[fidx + 2][s] += sb; wgb[fidx + 1][s] -= sb; }
-          if (sel[fidx][s] == 2) { wgb[fidx + 1][s] += sb; wgb[fidx][s] -= sb; }
+          wgb[fidx + 2][s] += sb * pa[fidx][s];
+          wgb[fidx + 1][s] += sb * (pb[fidx][s] - pa[fidx][s]);
+          wgb[fidx][s] -= sb * pb[fidx][s];
           /* wr = W_{i+1} - slope_{i+1}/2 (position fidx+2) */
           wgb[fidx + 2][s] += wrb[s];
           double tb = -0.5 * wrb[s];
-          if (sel[fidx + 1][s] == 1) { wgb[fidx + 3][s] += tb; wgb[fidx + 2][s] -= tb; }
-          if (sel[fidx + 1][s] == 2) { wgb[fidx + 2][s] += tb; wgb[fidx + 1][s] -= tb; }
+          wgb[fidx + 3][s] += tb * pa[fidx + 1][s];
+          wgb[fidx + 2][s] += tb * (pb[fidx + 1][s] - pa[fidx + 1][s]);
+          wgb[fidx + 1][s] -= tb * pb[fidx + 1][s];
         }
       }
       /* fold positions onto cells (the pencil is private to this thread) */
       for (long i = -2; i < n + 2; ++i)
         for (int s = 0; s < 5; ++s) Wb[perm[s] * N + q[i + 2]] += wgb[i + 2][s];
-      free(wg); free(wgb); free(slope); free(sel); free(q);
+      free(wg); free(wgb); free(slope); free(pa); free(pb); free(q);
     }
   }
   /* W = (rho, v, P) from U = (rho, m, E):

@@ -85,6 +85,62 @@ def test_rhs_vjp_supersonic_regions():
     check_dot(lambda X: oracle.rhs(c, X), lambda w: oracle.rhs_vjp(c, U, w), U, seed=5)
 
 
+SCHEMES = [(oracle.LIM_VANLEER, oracle.RS_HLLC), (oracle.LIM_MC, oracle.RS_HLLC),
+           (oracle.LIM_SUPERBEE, oracle.RS_HLLC), (oracle.LIM_MINMOD, oracle.RS_HLL),
+           (oracle.LIM_MINMOD, oracle.RS_RUSANOV), (oracle.LIM_VANLEER, oracle.RS_HLL),
+           (oracle.LIM_NONE, oracle.RS_RUSANOV)]
+
+
+@pytest.mark.parametrize("name,grid", GRIDS)
+@pytest.mark.parametrize("limiter,riemann", SCHEMES)
+def test_rhs_vjp_scheme_variants_dot_product(name, grid, limiter, riemann):
+    """Reverse of the other limiters and Riemann solvers of App. A.1/A.2."""
+    U = wl.random_state(grid.shape, seed=3, vmax=0.7)
+    c = oracle.make_config(grid.shape, grid.h, grid.bc, limiter=limiter, riemann=riemann)
+    check_dot(lambda X: oracle.rhs(c, X), lambda w: oracle.rhs_vjp(c, U, w), U, seed=1)
+
+
+@pytest.mark.parametrize("limiter,riemann", SCHEMES)
+def test_rhs_vjp_scheme_variants_entries_rough_state(limiter, riemann):
+    grid = wl.Grid((4, 5, 6), (1 / 6, 1 / 5, 1 / 4))
+    U = wl.random_state(grid.shape, seed=22, vmax=1.5)
+    c = oracle.make_config(grid.shape, grid.h, limiter=limiter, riemann=riemann)
+    check_entries(lambda X: oracle.rhs(c, X), lambda w: oracle.rhs_vjp(c, U, w), U, seed=2,
+                  count=40, eps=1e-7)
+
+
+@pytest.mark.parametrize("riemann", [oracle.RS_HLL, oracle.RS_RUSANOV])
+def test_rhs_vjp_supersonic_other_solvers(riemann):
+    """Every face one-sided for HLL (S_L >= 0); Rusanov's speed from the
+    positive |v| branch."""
+    grid = wl.Grid((4, 4, 8), (1 / 8, 1 / 4, 1 / 4))
+    U = wl.random_state(grid.shape, seed=4, vmax=0.2)
+    U[4] += 0.5 * ((U[1] + 3.0 * U[0]) ** 2 - U[1] ** 2) / U[0]
+    U[1] += 3.0 * U[0]
+    c = oracle.make_config(grid.shape, grid.h, limiter=oracle.LIM_VANLEER, riemann=riemann)
+    # van Leer's curvature near a + b = 0 needs the smaller difference step
+    check_dot(lambda X: oracle.rhs(c, X), lambda w: oracle.rhs_vjp(c, U, w), U, seed=5, eps=1e-7)
+
+
+def test_limiter_partials_cover_every_branch():
+    """The rough test states visit each branch of MC and superbee (so the
+    entry checks above exercise each partial), judged from the forward
+    differences of the oracle's own primitives."""
+    U = wl.random_state((4, 5, 6), seed=22, vmax=1.5)
+    W = oracle.primitives(oracle.make_config((4, 5, 6), (1 / 6, 1 / 5, 1 / 4)), U)
+    a = (np.roll(W, -1, axis=3) - W).ravel()
+    b = (W - np.roll(W, 1, axis=3)).ravel()
+    same = a * b > 0
+    aa, ab = np.abs(a[same]), np.abs(b[same])
+    cen = 0.5 * (aa + ab)
+    mc = [np.sum(cen <= np.minimum(2 * aa, 2 * ab)), np.sum((cen > np.minimum(2 * aa, 2 * ab)) & (aa <= ab)),
+          np.sum((cen > np.minimum(2 * aa, 2 * ab)) & (aa > ab))]
+    s1, s2 = np.minimum(2 * aa, ab), np.minimum(aa, 2 * ab)
+    sb = [np.sum((s1 >= s2) & (2 * aa <= ab)), np.sum((s1 >= s2) & (2 * aa > ab)),
+          np.sum((s1 < s2) & (aa <= 2 * ab)), np.sum((s1 < s2) & (aa > 2 * ab))]
+    assert min(mc) > 5 and min(sb) > 5, (mc, sb)
+
+
 def test_rk2_vjp():
     grid = wl.Grid((5, 6, 7), (1 / 7, 1 / 6, 1 / 5))
     U = wl.random_state(grid.shape, seed=6, vmax=0.6)
@@ -175,6 +231,27 @@ def test_step_vjp_against_full_steps(flags, integrator):
         return sim.advance(1, dt).U
 
     check_dot(fwd, lambda w: oracle.step_vjp(c, U, dt, 4, nvec, ahat, phi, w), U, seed=19)
+
+
+def test_step_vjp_fiducial_scheme():
+    """The paper's fiducial scheme (van Leer + HLLC, RK2) with forcing and
+    cooling, through full steps."""
+    grid = wl.cube(8)
+    U = wl.random_state(grid.shape, seed=23, vmax=0.5)
+    flags = oracle.SRC_FORCING | oracle.SRC_COOLING
+    c = oracle.make_config(grid.shape, grid.h, flags=flags, limiter=oracle.LIM_VANLEER)
+    dt = 0.6 * oracle.cfl_dt(c, U)
+    nvec = oracle.ou_modes(1.0, 2.0)
+    ahat = oracle.ou_init(c, nvec)
+    phi = np.zeros(grid.shape)
+
+    def fwd(X):
+        sim = oracle.Simulation(c, X, nvec=nvec, ahat=ahat.copy(), phi=phi.copy())
+        sim.step_index = 2
+        return sim.advance(1, dt).U
+
+    check_dot(fwd, lambda w: oracle.step_vjp(c, U, dt, 2, nvec, ahat, phi, w), U, seed=24,
+              eps=1e-7)
 
 
 def test_step_vjp_gravity():
