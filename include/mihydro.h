@@ -68,8 +68,7 @@ enum { MH_HOST = 0, MH_DEVICE = 1 };
  * riemann MH_RS_HLLC (App. A.2), MH_RS_HLL or MH_RS_RUSANOV, all with the
  *         Davis wave-speed estimates.  minmod or none with HLLC run the
  *         specialised kernels; the other combinations a kernel that selects
- *         limiter and solver at run time.  The adjoint step supports minmod
- *         or none with HLLC.
+ *         limiter and solver at run time (also in the adjoint step).
  * integrator  the explicit Runge-Kutta update (App. A.3): MH_RK_SSP2 (the
  *         two-stage Heun / SSP-RK2, the default), MH_RK_SSP3 (three-stage
  *         SSPRK3; the workspace holds one more state) or MH_RK_EULER
@@ -188,7 +187,12 @@ mh_status mh_get_potential(mh_ctx *ctx, void *phi, int where);
  * derivative of the branch the forward took is used: minmod the argument it
  * returned (0 when it returned 0), the wave-speed min/max the selected
  * argument (the first on ties), HLLC the side and fan the face fell in, the
- * cooling branch and floor those taken.
+ * cooling branch and floor those taken.  Van Leer's slope 2ab/(a+b) is
+ * differentiated where ab > 0; MC takes the smallest of |a+b|/2, 2|a|, 2|b|
+ * (ties in that order), superbee the larger of min(2|a|, |b|) and min(|a|,
+ * 2|b|) (the first on ties, each min its first argument on ties); HLL the
+ * region selected; Rusanov the larger signal speed (the left one on ties)
+ * with d|v|/dv = -1 for v < 0, else +1.
  * U_n, lam_np1, lam_n: device arrays [5][nz][ny][nx] of the context dtype;
  *   lam_n may alias lam_np1.
  * ou_ahat: host array of the OU amplitudes before the step (6 doubles per mode,

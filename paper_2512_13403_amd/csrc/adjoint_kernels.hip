@@ -16,7 +16,12 @@
 // and k_jtv_finish applies (dW/dU)^T per cell.  At every kink the derivative
 // of the branch the forward took is used (minmod: the returned argument, or 0;
 // wave-speed min/max: the selected argument, the first on ties; HLLC: the
-// side and fan the face fell in).
+// side and fan the face fell in).  The other limiters and solvers run in
+// k_face_vjp_rt, which takes them at run time and writes each face's four
+// stencil contributions instead of the minmod selections: the slope partials
+// dphi/da, dphi/db of van Leer (2b^2/(a+b)^2, 2a^2/(a+b)^2), MC ((1/2, 1/2),
+// (2, 0) or (0, 2), ties in that order) and superbee ((2, 0), (0, 1), (1, 0)
+// or (0, 2)), and the HLL / Rusanov reverse sweeps.
 #include "mg.h"
 #include "mh_adjoint.h"
 #include "mh_device.h"
@@ -169,6 +174,160 @@ __device__ void hllc_reverse(const T (&wl)[5], const T (&wr)[5], T g, const T (&
   wrb[0] = rrb; wrb[1] = urb; wrb[2] = arb; wrb[3] = brb; wrb[4] = prb;
 }
 
+// limited slope phi(a, b) of a run-time limiter with its partials on the
+// branch taken (0 when ab <= 0)
+template <typename T>
+__device__ __forceinline__ T slope_partials(int lim, T a, T b, T& pa, T& pb) {
+  pa = T(0);
+  pb = T(0);
+  if (lim == LIM_NONE || !(a * b > T(0))) return T(0);
+  const T aa = fabs(a), ab = fabs(b);
+  T m;
+  if (lim == LIM_MINMOD) {
+    if (aa <= ab) { pa = T(1); return a; }
+    pb = T(1);
+    return b;
+  }
+  if (lim == LIM_VANLEER) {
+    const T s = a + b;
+    const T is2 = T(1) / (s * s);
+    pa = T(2) * b * b * is2;
+    pb = T(2) * a * a * is2;
+    return T(2) * a * b / s;
+  }
+  if (lim == LIM_MC) {
+    const T cen = fabs(T(0.5) * (a + b)), t2 = fmin(T(2) * aa, T(2) * ab);
+    if (cen <= t2) { pa = T(0.5); pb = T(0.5); m = cen; }
+    else if (aa <= ab) { pa = T(2); m = T(2) * aa; }
+    else { pb = T(2); m = T(2) * ab; }
+  } else {  // superbee
+    const T s1 = fmin(T(2) * aa, ab), s2 = fmin(aa, T(2) * ab);
+    if (s1 >= s2) {
+      if (T(2) * aa <= ab) pa = T(2); else pb = T(1);
+      m = s1;
+    } else {
+      if (aa <= T(2) * ab) pa = T(1); else pb = T(2);
+      m = s2;
+    }
+  }
+  return a > T(0) ? m : -m;
+}
+
+// conserved state and flux of a face-frame primitive state (rho, v_n, v_t1,
+// v_t2, P), and the reverse: wb += (dU/dw)^T Ub + (dF/dw)^T Fb
+template <typename T>
+__device__ __forceinline__ void frame_state_flux(const T (&w)[5], T gm1, T (&U)[5], T (&F)[5]) {
+  const T r = w[0], u = w[1], a = w[2], b = w[3], p = w[4];
+  const T E = p / gm1 + T(0.5) * r * (u * u + a * a + b * b);
+  U[0] = r; U[1] = r * u; U[2] = r * a; U[3] = r * b; U[4] = E;
+  F[0] = r * u; F[1] = r * u * u + p; F[2] = r * u * a; F[3] = r * u * b; F[4] = u * (E + p);
+}
+template <typename T>
+__device__ __forceinline__ void frame_state_flux_reverse(const T (&w)[5], T gm1, const T (&Ub)[5],
+                                                         const T (&Fb)[5], T (&wb)[5]) {
+  const T r = w[0], u = w[1], a = w[2], b = w[3], p = w[4];
+  const T q2 = u * u + a * a + b * b;
+  const T E = p / gm1 + T(0.5) * r * q2;
+  const T Eb = Ub[4] + Fb[4] * u;  // E enters U[4] and F[4]
+  wb[0] += Ub[0] + Ub[1] * u + Ub[2] * a + Ub[3] * b +
+           u * (Fb[0] + Fb[1] * u + Fb[2] * a + Fb[3] * b) + Eb * T(0.5) * q2;
+  wb[1] += r * (Ub[1] + Fb[0] + T(2) * Fb[1] * u + Fb[2] * a + Fb[3] * b + Eb * u) +
+           Fb[4] * (E + p);
+  wb[2] += r * (Ub[2] + Fb[2] * u + Eb * a);
+  wb[3] += r * (Ub[3] + Fb[3] * u + Eb * b);
+  wb[4] += Fb[1] + Fb[4] * u + Eb / gm1;
+}
+// c = sqrt(g P / rho): wb += cb dc/dw
+template <typename T>
+__device__ __forceinline__ void sound_reverse(const T (&w)[5], T g, T c, T cb, T (&wb)[5]) {
+  wb[4] += cb * g / (T(2) * c * w[0]);
+  wb[0] -= cb * c / (T(2) * w[0]);
+}
+
+// Reverse of the HLL flux (F_L for 0 <= S_L, F_R for S_R <= 0, else the HLL
+// average); Davis min/max take the left argument on ties.  Writes wlb, wrb.
+template <typename T>
+__device__ void hll_reverse(const T (&wl)[5], const T (&wr)[5], T g, const T (&Fb)[5],
+                            T (&wlb)[5], T (&wrb)[5]) {
+  const T gm1 = g - T(1);
+  T UL[5], FL[5], UR[5], FR[5];
+  frame_state_flux(wl, gm1, UL, FL);
+  frame_state_flux(wr, gm1, UR, FR);
+  const T cl = sqrt(g * wl[4] / wl[0]), cr = sqrt(g * wr[4] / wr[0]);
+  const bool minL = (wl[1] - cl) <= (wr[1] - cr);
+  const bool maxL = (wl[1] + cl) >= (wr[1] + cr);
+  const T SL = minL ? wl[1] - cl : wr[1] - cr;
+  const T SR = maxL ? wl[1] + cl : wr[1] + cr;
+  T ULb[5], FLb[5], URb[5], FRb[5];
+  T SLb = T(0), SRb = T(0);
+  const bool lo = T(0) <= SL, hi = !lo && SR <= T(0);
+  const T iD = T(1) / (SR - SL);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    wlb[f] = T(0);
+    wrb[f] = T(0);
+    if (lo || hi) {
+      FLb[f] = lo ? Fb[f] : T(0);
+      FRb[f] = hi ? Fb[f] : T(0);
+      ULb[f] = URb[f] = T(0);
+    } else {
+      const T dU = UR[f] - UL[f];
+      const T Fm = (SR * FL[f] - SL * FR[f] + SL * SR * dU) * iD;
+      FLb[f] = Fb[f] * SR * iD;
+      FRb[f] = -Fb[f] * SL * iD;
+      URb[f] = Fb[f] * SL * SR * iD;
+      ULb[f] = -URb[f];
+      SLb += Fb[f] * (SR * dU - FR[f] + Fm) * iD;
+      SRb += Fb[f] * (FL[f] + SL * dU - Fm) * iD;
+    }
+  }
+  T clb = T(0), crb = T(0);
+  if (minL) { wlb[1] += SLb; clb -= SLb; } else { wrb[1] += SLb; crb -= SLb; }
+  if (maxL) { wlb[1] += SRb; clb += SRb; } else { wrb[1] += SRb; crb += SRb; }
+  sound_reverse(wl, g, cl, clb, wlb);
+  sound_reverse(wr, g, cr, crb, wrb);
+  frame_state_flux_reverse(wl, gm1, ULb, FLb, wlb);
+  frame_state_flux_reverse(wr, gm1, URb, FRb, wrb);
+}
+
+// Reverse of the Rusanov flux (F_L + F_R)/2 - s (U_R - U_L)/2, s = max(|v_L|
+// + c_L, |v_R| + c_R): the left argument on ties, d|v|/dv = -1 for v < 0,
+// else +1.  Writes wlb, wrb.
+template <typename T>
+__device__ void rusanov_reverse(const T (&wl)[5], const T (&wr)[5], T g, const T (&Fb)[5],
+                                T (&wlb)[5], T (&wrb)[5]) {
+  const T gm1 = g - T(1);
+  T UL[5], FL[5], UR[5], FR[5];
+  frame_state_flux(wl, gm1, UL, FL);
+  frame_state_flux(wr, gm1, UR, FR);
+  const T cl = sqrt(g * wl[4] / wl[0]), cr = sqrt(g * wr[4] / wr[0]);
+  const bool maxL = (fabs(wl[1]) + cl) >= (fabs(wr[1]) + cr);
+  const T s = maxL ? fabs(wl[1]) + cl : fabs(wr[1]) + cr;
+  T ULb[5], FLb[5], URb[5], FRb[5];
+  T sb = T(0);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    wlb[f] = T(0);
+    wrb[f] = T(0);
+    FLb[f] = FRb[f] = T(0.5) * Fb[f];
+    URb[f] = -T(0.5) * s * Fb[f];
+    ULb[f] = -URb[f];
+    sb -= T(0.5) * Fb[f] * (UR[f] - UL[f]);
+  }
+  T clb = T(0), crb = T(0);
+  if (maxL) {
+    wlb[1] += wl[1] < T(0) ? -sb : sb;
+    clb = sb;
+  } else {
+    wrb[1] += wr[1] < T(0) ? -sb : sb;
+    crb = sb;
+  }
+  sound_reverse(wl, g, cl, clb, wlb);
+  sound_reverse(wr, g, cr, crb, wrb);
+  frame_state_flux_reverse(wl, gm1, ULb, FLb, wlb);
+  frame_state_flux_reverse(wr, gm1, URb, FRb, wrb);
+}
+
 struct AxisGeom {
   int n[3];   // cells along x, y, z
   int bc;     // boundary kind of the axis
@@ -257,6 +416,75 @@ __global__ __launch_bounds__(256) void k_face_vjp(const T* __restrict__ U, const
   flags[rec] = fl;
 }
 
+// The same for a run-time limiter `lim` and solver `rs`: writes the face's
+// contributions to the W adjoint of its four stencil cells i-1+k (k = 0..3),
+// per face-frame field s, to slots[(5 k + s) NF + rec]:
+//   k = 0: -pb0 WLb/2
+//   k = 1: WLb (1 + (pb0 - pa0)/2) + pb1 WRb/2
+//   k = 2: pa0 WLb/2 + WRb (1 - (pb1 - pa1)/2)
+//   k = 3: -pa1 WRb/2
+// from W^L = W_i + phi(a0, b0)/2, W^R = W_{i+1} - phi(a1, b1)/2.
+template <typename T, int AX>
+__global__ __launch_bounds__(256) void k_face_vjp_rt(const T* __restrict__ U,
+                                                     const T* __restrict__ v, AxisGeom g, T gamma,
+                                                     T ih, int lim, int rs,
+                                                     T* __restrict__ slots, long long nfaces) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nfaces) return;
+  int d1, d2;
+  other_dims<AX>(g, d1, d2);
+  const int f = (int)(t % g.nf);
+  const long long rest = t / g.nf;
+  const int o1 = (int)(rest % d1), o2 = (int)(rest / d1);
+  const int n = g.n[AX];
+  const int i = g.bc == BC_PERIODIC ? f : f - 1;
+  const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+  const T gm1 = gamma - T(1);
+  constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
+  const int perm[5] = {0, vn, t1, t2, 4};
+  T w[4][5];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T wc[5];
+    prim_at(U, N, cell_of<AX>(g, bc_map(i - 1 + k, n, g.bc), o1, o2), gm1, wc);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) w[k][s] = wc[perm[s]];
+  }
+  T wl[5], wr[5], pa0[5], pb0[5], pa1[5], pb1[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const T d0 = slope_partials(lim, w[2][s] - w[1][s], w[1][s] - w[0][s], pa0[s], pb0[s]);
+    const T d1 = slope_partials(lim, w[3][s] - w[2][s], w[2][s] - w[1][s], pa1[s], pb1[s]);
+    wl[s] = w[1][s] + T(0.5) * d0;
+    wr[s] = w[2][s] - T(0.5) * d1;
+  }
+  const bool has_right = g.bc == BC_PERIODIC || i + 1 <= n - 1;
+  const bool has_left = g.bc == BC_PERIODIC || i >= 0;
+  const long long qr = cell_of<AX>(g, bc_map(i + 1, n, g.bc), o1, o2);
+  const long long ql = cell_of<AX>(g, bc_map(i, n, g.bc), o1, o2);
+  T Fb[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const T vr = has_right ? v[perm[s] * N + qr] : T(0);
+    const T vl = has_left ? v[perm[s] * N + ql] : T(0);
+    Fb[s] = (vr - vl) * ih;
+  }
+  T wlb[5], wrb[5];
+  if (rs == RS_HLL) hll_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+  else if (rs == RS_RUSANOV) rusanov_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+  else hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+  const long long rec = face_of<AX>(g, f, o1, o2);
+  const long long NF = (long long)g.nf * d1 * d2;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const T L = wlb[s], R = wrb[s];
+    slots[(0 + s) * NF + rec] = -T(0.5) * pb0[s] * L;
+    slots[(5 + s) * NF + rec] = L + T(0.5) * (pb0[s] - pa0[s]) * L + T(0.5) * pb1[s] * R;
+    slots[(10 + s) * NF + rec] = T(0.5) * pa0[s] * L + R - T(0.5) * (pb1[s] - pa1[s]) * R;
+    slots[(15 + s) * NF + rec] = -T(0.5) * pa1[s] * R;
+  }
+}
+
 // contribution of the face with left cell position i to the stencil slot k
 // (position i - 1 + k), field s (face frame), from the reverse of
 // W^L = W_i + minmod_i/2 and W^R = W_{i+1} - minmod_{i+1}/2
@@ -273,7 +501,9 @@ __device__ __forceinline__ T slot_contrib(int k, int fl, int s, T WLb, T WRb) {
   }
 }
 
-template <typename T, int AX>
+// SLOTS: the face records are the four stencil contributions written by
+// k_face_vjp_rt; otherwise (W^L_b, W^R_b) and the minmod selections
+template <typename T, int AX, bool SLOTS>
 __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
                                                      const int* __restrict__ flags, AxisGeom g,
                                                      T* __restrict__ Wacc) {
@@ -292,12 +522,13 @@ __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
   T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
   auto add_face = [&](int f, int i) {  // record f, left cell position i
     const long long rec = face_of<AX>(g, f, o1, o2);
-    const int fl = flags[rec];
+    const int fl = SLOTS ? 0 : flags[rec];
     for (int k = 0; k < 4; ++k) {
       if (bc_map(i - 1 + k, n, g.bc) != c) continue;
 #pragma unroll
       for (int s = 0; s < 5; ++s)
-        acc[s] += slot_contrib<T>(k, fl, s, wbar[s * NF + rec], wbar[(5 + s) * NF + rec]);
+        acc[s] += SLOTS ? wbar[(5 * k + s) * NF + rec]
+                        : slot_contrib<T>(k, fl, s, wbar[s * NF + rec], wbar[(5 + s) * NF + rec]);
     }
   };
   if (g.bc == BC_PERIODIC) {
@@ -533,28 +764,37 @@ inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 
 // J(U)^T v into out = c0 x0 + c1 x1 + beta J^T v (x0, x1 may be NULL)
 template <typename T>
-hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, T gamma,
+hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, int riemann,
+                   T gamma,
                    const double* h, const T* U, const T* v, T beta, T c0, const T* x0, T c1,
                    const T* x1, T c2, const T* x2, T* out, hipStream_t s) {
   const long long N = (long long)geom.nx * geom.ny * geom.nz;
   hipLaunchKernelGGL((k_fill<T>), dim3(nblk(5 * N)), dim3(256), 0, s, B.Wacc, 5 * N, T(0));
   const int nn[3] = {geom.nx, geom.ny, geom.nz};
+  const bool rt = adj_runtime_scheme(limiter, riemann);
   for (int ax = 0; ax < 3; ++ax) {
     AxisGeom ag{{geom.nx, geom.ny, geom.nz}, geom.bc[ax], 0};
     ag.nf = geom.bc[ax] == BC_PERIODIC ? nn[ax] : nn[ax] + 1;
     if (geom.bc[ax] == BC_PERIODIC && nn[ax] == 1) continue;  // the axis' fluxes cancel exactly
     const long long nfaces = (long long)ag.nf * (N / nn[ax]);
     const T ih = (T)(1.0 / h[ax]);
-#define MH_FACE(AX)                                                                          \
-  do {                                                                                       \
-    if (limiter == LIM_NONE)                                                                 \
-      hipLaunchKernelGGL((k_face_vjp<T, LIM_NONE, AX>), dim3(nblk(nfaces)), dim3(256), 0, s, \
-                         U, v, ag, gamma, ih, B.wbar, B.flags, nfaces);                      \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_face_vjp<T, LIM_MINMOD, AX>), dim3(nblk(nfaces)), dim3(256), 0,  \
-                         s, U, v, ag, gamma, ih, B.wbar, B.flags, nfaces);                   \
-    hipLaunchKernelGGL((k_cell_gather<T, AX>), dim3(nblk(N)), dim3(256), 0, s, B.wbar,       \
-                       B.flags, ag, B.Wacc);                                                 \
+#define MH_FACE(AX)                                                                           \
+  do {                                                                                        \
+    if (rt) {                                                                                 \
+      hipLaunchKernelGGL((k_face_vjp_rt<T, AX>), dim3(nblk(nfaces)), dim3(256), 0, s, U, v,   \
+                         ag, gamma, ih, limiter, riemann, B.wbar, nfaces);                    \
+      hipLaunchKernelGGL((k_cell_gather<T, AX, true>), dim3(nblk(N)), dim3(256), 0, s,        \
+                         B.wbar, B.flags, ag, B.Wacc);                                        \
+    } else {                                                                                  \
+      if (limiter == LIM_NONE)                                                                \
+        hipLaunchKernelGGL((k_face_vjp<T, LIM_NONE, AX>), dim3(nblk(nfaces)), dim3(256), 0,   \
+                           s, U, v, ag, gamma, ih, B.wbar, B.flags, nfaces);                  \
+      else                                                                                    \
+        hipLaunchKernelGGL((k_face_vjp<T, LIM_MINMOD, AX>), dim3(nblk(nfaces)), dim3(256), 0, \
+                           s, U, v, ag, gamma, ih, B.wbar, B.flags, nfaces);                  \
+      hipLaunchKernelGGL((k_cell_gather<T, AX, false>), dim3(nblk(N)), dim3(256), 0, s,       \
+                         B.wbar, B.flags, ag, B.Wacc);                                        \
+    }                                                                                         \
   } while (0)
     if (ax == 0) MH_FACE(0);
     else if (ax == 1) MH_FACE(1);
@@ -616,7 +856,7 @@ hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws
 }
 
 #define ADJ_INSTANTIATE(T)                                                                       \
-  template hipError_t adj_jtv<T>(const AdjointBuffers<T>&, const StageGeom&, int, T,             \
+  template hipError_t adj_jtv<T>(const AdjointBuffers<T>&, const StageGeom&, int, int, T,        \
                                  const double*, const T*, const T*, T, T, const T*, T, const T*, \
                                  T, const T*, T*, hipStream_t);                                  \
   template hipError_t adj_force_kick<T>(T*, const T*, const T*, int, const StageGeom&, T,        \

@@ -599,7 +599,7 @@ AdjLayout make_adj_layout(const mh_grid_desc& g, const mh_physics_desc& p) {
     A.lam2 = take(5 * N * es);
   }
   A.Wacc = take(5 * N * es);
-  A.wbar = take(10 * faces * es);
+  A.wbar = take((adj_runtime_scheme(g.limiter, g.riemann) ? 20 : 10) * faces * es);
   A.flags = take(faces * sizeof(int));
   if (p.flags & MH_SRC_FORCING) {
     const int R = (int)std::floor(p.ou_kmax);
@@ -730,23 +730,23 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   const T gam = (T)g.gamma;
   if (g.integrator == MH_RK_EULER) {
     // lam_n = cur + dt J(U^n)^T cur
-    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, Un, cur, (T)dt, T(1), cur, T(0), nullptr, T(0),
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, Un, cur, (T)dt, T(1), cur, T(0), nullptr, T(0),
                          nullptr, lam_n, c->stream));
   } else if (g.integrator == MH_RK_SSP3) {
     // lam2 = 2/3 (cur + dt J(U2)^T cur);  lam1 = 1/4 (lam2 + dt J(U1)^T lam2);
     // lam_n = cur/3 + 3/4 lam2 + lam1 + dt J(U^n)^T lam1
     T* lam2 = at(A.lam2);
-    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, U2, cur, (T)(2.0 / 3.0 * dt), (T)(2.0 / 3.0),
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, U2, cur, (T)(2.0 / 3.0 * dt), (T)(2.0 / 3.0),
                          cur, T(0), nullptr, T(0), nullptr, lam2, c->stream));
-    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, U1, lam2, (T)(0.25 * dt), T(0.25), lam2, T(0),
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, U1, lam2, (T)(0.25 * dt), T(0.25), lam2, T(0),
                          nullptr, T(0), nullptr, lam1, c->stream));
-    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, Un, lam1, (T)dt, (T)(1.0 / 3.0), cur, T(0.75),
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, Un, lam1, (T)dt, (T)(1.0 / 3.0), cur, T(0.75),
                          lam2, T(1), lam1, lam_n, c->stream));
   } else {
     // lam1 = cur/2 + (dt/2) J(U1)^T cur;  lam_n = cur/2 + lam1 + dt J(U^n)^T lam1
-    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, U1, cur, (T)(0.5 * dt), T(0.5), cur, T(0),
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, U1, cur, (T)(0.5 * dt), T(0.5), cur, T(0),
                          nullptr, T(0), nullptr, lam1, c->stream));
-    MH_HIP(c, adj_jtv<T>(B, geom, lim, gam, g.h, Un, lam1, (T)dt, T(0.5), cur, T(1), lam1, T(0),
+    MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, Un, lam1, (T)dt, T(0.5), cur, T(1), lam1, T(0),
                          nullptr, lam_n, c->stream));
   }
   return MH_OK;
@@ -762,9 +762,6 @@ extern "C" mh_status mh_adjoint_step(mh_ctx* c, void* adj_workspace, size_t adj_
   if ((c->p.flags & MH_SRC_FORCING) && !ou_ahat)
     return set_err(c, MH_E_INVALID, "mh_adjoint_step: forcing is on but ou_ahat is NULL");
   if (!(dt >= 0.0) || step < 0) return set_err(c, MH_E_INVALID, "mh_adjoint_step: bad dt or step");
-  if ((c->g.limiter != MH_LIM_MINMOD && c->g.limiter != MH_LIM_NONE) || c->g.riemann != MH_RS_HLLC)
-    return set_err(c, MH_E_UNSUPPORTED,
-                   "mh_adjoint_step: the adjoint is implemented for minmod or none with HLLC");
   AdjLayout A = make_adj_layout(c->g, c->p);
   A.mg.graphs = &c->adj_graphs;
   if (!adj_workspace || adj_workspace_bytes < A.total || ((uintptr_t)adj_workspace % ALIGN) != 0)

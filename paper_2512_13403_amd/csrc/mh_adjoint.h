@@ -13,14 +13,23 @@ namespace mh {
 template <typename T>
 struct AdjointBuffers {
   T* Wacc;     // [5][N] primitive-variable adjoint accumulator
-  T* wbar;     // [10][faces] face-state adjoints W^L_b, W^R_b of one axis
+  T* wbar;     // [10][faces] face-state adjoints W^L_b, W^R_b of one axis, or
+               // [20][faces] stencil contributions (run-time scheme)
   int* flags;  // [faces] minmod selections of the two slopes of each face
   T* accb;     // [3][N] adjoint of the gravitational acceleration
   T* phib;     // [N] adjoint of the potential
 };
 
+// limiters other than minmod / none, or a solver other than HLLC, take the
+// run-time-scheme face kernel, whose face records are 20 values (wbar holds
+// 20 x faces then, 10 x faces otherwise)
+inline bool adj_runtime_scheme(int limiter, int riemann) {
+  return riemann != RS_HLLC || (limiter != LIM_MINMOD && limiter != LIM_NONE);
+}
+
 template <typename T>
-hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, T gamma,
+hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, int riemann,
+                   T gamma,
                    const double* h, const T* U, const T* v, T beta, T c0, const T* x0, T c1,
                    const T* x1, T c2, const T* x2, T* out, hipStream_t s);
 template <typename T>

@@ -83,6 +83,37 @@ def test_adjoint_other_integrators(dtype, integrator):
     assert rel_err(got, ref) < TOL[dtype]
 
 
+SCHEMES = [(oracle.LIM_VANLEER, oracle.RS_HLLC), (oracle.LIM_MC, oracle.RS_HLLC),
+           (oracle.LIM_SUPERBEE, oracle.RS_HLLC), (oracle.LIM_MINMOD, oracle.RS_HLL),
+           (oracle.LIM_MINMOD, oracle.RS_RUSANOV), (oracle.LIM_VANLEER, oracle.RS_HLL),
+           (oracle.LIM_NONE, oracle.RS_RUSANOV)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("limiter,riemann", SCHEMES)
+def test_adjoint_scheme_variants(dtype, limiter, riemann):
+    """Reverse of the other limiters and Riemann solvers (run-time-scheme face
+    kernel) against the oracle's adjoint, outflow in x."""
+    shape = (9, 11, 70)
+    U0 = wl.random_state(shape, seed=35, vmax=0.7)
+    got, ref = gpu_vs_oracle_adjoint(shape, (1 / 70, 1 / 11, 1 / 9), U0, dtype, (1, 0, 0),
+                                     limiter=limiter, riemann=riemann)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_fiducial_scheme_with_sources(dtype):
+    """The paper's fiducial scheme (van Leer + HLLC) with forcing and cooling,
+    and with SSPRK3."""
+    shape = (12, 14, 66)
+    U0 = wl.random_state(shape, seed=36, vmax=0.5)
+    for integrator in (oracle.RK_SSP2, oracle.RK_SSP3):
+        got, ref = gpu_vs_oracle_adjoint(shape, (1 / 66, 1 / 14, 1 / 12), U0, dtype,
+                                         flags=oracle.SRC_FORCING | oracle.SRC_COOLING, ou_seed=8,
+                                         limiter=oracle.LIM_VANLEER, integrator=integrator)
+        assert rel_err(got, ref) < TOL[dtype], integrator
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_gravity_cooling(dtype):
     n = 16

@@ -138,17 +138,6 @@ def test_sod_full_run_ssprk3_fp64():
     assert np.array_equal(U, np.broadcast_to(U[:, :1, :1, :], U.shape))
 
 
-def test_adjoint_rejects_scheme_variants():
-    import torch
-
-    shape = (8, 8, 8)
-    s, _ = pair(shape, (1 / 8,) * 3, dtype="f64", limiter=oracle.LIM_VANLEER)
-    U = torch.tensor(wl.random_state(shape, seed=1), dtype=torch.float64, device="cuda:0")
-    with pytest.raises(mh.MHError) as e:
-        s.adjoint_step(U, 1e-3, 0, U.clone())
-    assert e.value.status == mh.E_UNSUPPORTED
-
-
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("bc", [(1, 1, 1), (1, 0, 0), (0, 1, 0), (0, 0, 1)])
 def test_outflow_boundaries(dtype, bc):
