@@ -31,6 +31,9 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 LIM_MINMOD, LIM_NONE, LIM_VANLEER, LIM_MC, LIM_SUPERBEE = 0, 1, 2, 3, 4
 RS_HLLC, RS_HLL, RS_RUSANOV = 0, 1, 2
 RK_SSP2, RK_SSP3, RK_EULER = 0, 1, 2
+MG_V, MG_W = 0, 1
+SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
+GRAV_MG, GRAV_FFT = 0, 1
 SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
 OU_MAXMODES = 64
 
@@ -66,6 +69,10 @@ class Config(ctypes.Structure):
         ("mg_tol", ctypes.c_double),
         ("mg_coarse_sweeps", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
+        ("mg_cycle", ctypes.c_int32),
+        ("mg_smoother", ctypes.c_int32),
+        ("grav_solver", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -105,6 +112,10 @@ def lib():
             "or_laplacian": (None, [ctypes.c_int, ctypes.c_double, dp, dp]),
             "or_mg_vcycle": (None, [cp, ctypes.c_int, ctypes.c_double, dp, dp]),
             "or_mg_solve": (ctypes.c_int, [cp, ctypes.c_int, ctypes.c_double, dp, dp]),
+            "or_mg_smooth": (None, [cp, ctypes.c_int, ctypes.c_double, dp, dp]),
+            "or_dft3": (None, [ctypes.c_int, ctypes.c_int, dp, dp]),
+            "or_fft_gravity": (None, [cp, dp, dp, dp]),
+            "or_fft_gravity_vjp": (None, [cp, dp, dp]),
             "or_gravity_accel": (ctypes.c_int, [cp, dp, dp, dp]),
             "or_num_threads": (ctypes.c_int, []),
             "or_rhs_vjp": (None, [cp, dp, dp, dp]),
@@ -142,7 +153,8 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
                 riemann=RS_HLLC, flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5,
                 ou_arms=1.0, ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0, ou_every=1, grav_G=0.0,
                 mg_pre=2, mg_post=2, mg_max_cycles=20, mg_coarsest=4, mg_tol=1e-10,
-                mg_coarse_sweeps=200, integrator=RK_SSP2) -> Config:
+                mg_coarse_sweeps=200, integrator=RK_SSP2, mg_cycle=MG_V, mg_smoother=SMOOTH_JACOBI,
+                grav_solver=GRAV_MG) -> Config:
     """shape = (nz, ny, nx) of the state arrays; h = (hx, hy, hz); bc per (x, y, z)."""
     nz, ny, nx = shape
     c = Config()
@@ -157,6 +169,7 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
     c.mg_pre, c.mg_post, c.mg_max_cycles, c.mg_coarsest = mg_pre, mg_post, mg_max_cycles, mg_coarsest
     c.mg_tol, c.mg_coarse_sweeps = mg_tol, mg_coarse_sweeps
     c.integrator = integrator
+    c.mg_cycle, c.mg_smoother, c.grav_solver = mg_cycle, mg_smoother, grav_solver
     return c
 
 
@@ -298,6 +311,39 @@ def mg_solve(c, n, h, phi, F):
     F = np.ascontiguousarray(F, dtype=np.float64)
     cyc = lib().or_mg_solve(ctypes.byref(c), n, h, _dp(phi), _dp(F))
     return phi, cyc
+
+
+def mg_smooth(c, n, h, phi, F):
+    """One sweep of the configured smoother (c.mg_smoother)."""
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    lib().or_mg_smooth(ctypes.byref(c), n, h, _dp(phi), _dp(F))
+    return phi
+
+
+def dft3(x, inverse=False):
+    """3D DFT of an n^3 complex array by its definition (oracle_fft.c)."""
+    x = np.asarray(x, dtype=np.complex128)
+    re = np.ascontiguousarray(x.real)
+    im = np.ascontiguousarray(x.imag)
+    lib().or_dft3(x.shape[0], int(inverse), _dp(re), _dp(im))
+    return re + 1j * im
+
+
+def fft_gravity(c, rho):
+    """Spectral potential and acceleration of a density field (Sec. 6.1)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    phi = np.empty_like(rho)
+    acc = np.empty((3,) + rho.shape)
+    lib().or_fft_gravity(ctypes.byref(c), _dp(rho), _dp(phi), _dp(acc))
+    return phi, acc
+
+
+def fft_gravity_vjp(c, accb):
+    accb = np.ascontiguousarray(accb, dtype=np.float64)
+    rhob = np.empty(accb.shape[1:])
+    lib().or_fft_gravity_vjp(ctypes.byref(c), _dp(accb), _dp(rhob))
+    return rhob
 
 
 def gravity_accel(c, U, phi):

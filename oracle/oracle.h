@@ -12,6 +12,9 @@ enum { OR_LIM_MINMOD = 0, OR_LIM_NONE = 1, OR_LIM_VANLEER = 2, OR_LIM_MC = 3,
        OR_LIM_SUPERBEE = 4 };
 enum { OR_RS_HLLC = 0, OR_RS_HLL = 1, OR_RS_RUSANOV = 2 };
 enum { OR_RK_SSP2 = 0, OR_RK_SSP3 = 1, OR_RK_EULER = 2 };
+enum { OR_MG_V = 0, OR_MG_W = 1 };
+enum { OR_SMOOTH_JACOBI = 0, OR_SMOOTH_RBGS = 1 };
+enum { OR_GRAV_MG = 0, OR_GRAV_FFT = 1 };
 enum { OR_SRC_COOLING = 1u, OR_SRC_FORCING = 2u, OR_SRC_GRAVITY = 4u };
 #define OR_OU_MAXMODES 64
 
@@ -35,6 +38,10 @@ typedef struct {
   double mg_tol;
   int32_t mg_coarse_sweeps;
   int32_t integrator; /* OR_RK_* */
+  int32_t mg_cycle;    /* OR_MG_V or OR_MG_W */
+  int32_t mg_smoother; /* OR_SMOOTH_* */
+  int32_t grav_solver; /* OR_GRAV_MG or OR_GRAV_FFT */
+  int32_t pad_;
 } or_config;
 
 void or_primitives(const or_config *c, const double *U, double *W);
@@ -66,6 +73,12 @@ void or_laplacian(int n, double h, const double *phi, double *out);
 void or_mg_vcycle(const or_config *c, int n, double h, double *phi, const double *F);
 int or_mg_solve(const or_config *c, int n, double h, double *phi, const double *F);
 int or_gravity_accel(const or_config *c, const double *U, double *phi, double *acc);
+void or_mg_smooth(const or_config *c, int n, double h, double *phi, const double *F);
+
+/* spectral self-gravity (oracle_fft.c) */
+void or_dft3(int n, int inverse, double *re, double *im);
+void or_fft_gravity(const or_config *c, const double *rho, double *phi, double *acc);
+void or_fft_gravity_vjp(const or_config *c, const double *accb, double *rhob);
 
 int or_num_threads(void);
 

@@ -640,6 +640,13 @@ int or_gravity_vjp(const or_config *c, const double *U, double dt, double *phi,
   double *accb = (double *)malloc(sizeof(double) * 3 * N);
   int cyc = or_gravity_accel(c, U, phi, acc);
   or_kick_vjp(c, U, acc, dt, lamp, lam, accb);
+  if (c->grav_solver == OR_GRAV_FFT) {
+    double *rhob = (double *)malloc(sizeof(double) * N);
+    or_fft_gravity_vjp(c, accb, rhob);
+    for (long q = 0; q < N; ++q) lam[q] += rhob[q];
+    free(rhob); free(acc); free(accb);
+    return cyc;
+  }
   /* g_a,i = -(phi_{i+1} - phi_{i-1}) / (2h)  =>  phib_j = sum_a (gb_{a,j+1} - gb_{a,j-1}) / (2h) */
   double *phib = (double *)malloc(sizeof(double) * N);
   double i2h = 1.0 / (2.0 * h);

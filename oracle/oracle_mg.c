@@ -10,7 +10,12 @@
  * One V-cycle (App. C): nu1 weighted-Jacobi sweeps, residual, restriction by
  * the average of the 8 children, recursive coarse solve of the error equation
  * from a zero guess, trilinear prolongation and correction, nu2 sweeps.  The
- * coarsest grid is solved to round-off by many Jacobi sweeps.  The mean is
+ * coarsest grid is solved to round-off by many Jacobi sweeps.  The W-cycle
+ * (App. C, the paper's default) makes two recursive cycles of the error
+ * equation on each coarser level instead of one (the level just above the
+ * coarsest solves it once), the second starting from the first one's result.
+ * The smoother is weighted Jacobi or red-black Gauss-Seidel (Sec. 6.2.1).
+ * The mean is
  * projected out of every right-hand side and of every solution, so the
  * singular periodic problem is solved on its mean-zero subspace (gauge
  * <phi> = 0, Sec. 6.1).
@@ -100,6 +105,41 @@ static void jacobi(long n, double h, double *phi, const double *F, double *tmp) 
   memcpy(phi, tmp, sizeof(double) * n * n * n);
 }
 
+/* one red-black Gauss-Seidel sweep (Sec. 6.2.1 names it as the alternative
+ * smoother): first every red cell (i + j + k even), then every black cell,
+ * each set to the value that zeroes its own residual given its neighbours,
+ * phi = (sum of the six neighbours - h^2 F) / 6, in place.  The grids it
+ * smooths have an even n, so the colouring is consistent across the periodic
+ * wrap and the cells of one colour only read the other colour. */
+static void rbgs(long n, double h, double *phi, const double *F) {
+  double h2 = h * h;
+  for (long colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k)
+      for (long j = 0; j < n; ++j)
+        for (long i = 0; i < n; ++i) {
+          if ((i + j + k) % 2 != colour) continue;
+          double nb = phi[id3(n, i - 1, j, k)] + phi[id3(n, i + 1, j, k)] +
+                      phi[id3(n, i, j - 1, k)] + phi[id3(n, i, j + 1, k)] +
+                      phi[id3(n, i, j, k - 1)] + phi[id3(n, i, j, k + 1)];
+          phi[id3(n, i, j, k)] = (nb - h2 * F[id3(n, i, j, k)]) / 6.0;
+        }
+  }
+}
+
+/* one sweep of the configured smoother */
+static void smooth(const or_config *c, long n, double h, double *phi, const double *F,
+                   double *tmp) {
+  if (c->mg_smoother == OR_SMOOTH_RBGS) rbgs(n, h, phi, F);
+  else jacobi(n, h, phi, F, tmp);
+}
+
+void or_mg_smooth(const or_config *c, int n, double h, double *phi, const double *F) {
+  double *tmp = (double *)malloc(sizeof(double) * (long)n * n * n);
+  smooth(c, n, h, phi, F, tmp);
+  free(tmp);
+}
+
 static void residual(long n, double h, const double *phi, const double *F,
                      double *r) {
   or_laplacian((int)n, h, phi, r);
@@ -159,7 +199,7 @@ void or_mg_vcycle(const or_config *c, int n_, double h, double *phi,
     free(tmp);
     return;
   }
-  for (int s = 0; s < c->mg_pre; ++s) jacobi(n, h, phi, F, tmp);
+  for (int s = 0; s < c->mg_pre; ++s) smooth(c, n, h, phi, F, tmp);
   double *r = (double *)malloc(sizeof(double) * N);
   residual(n, h, phi, F, r);
   long nc = n / 2, Nc = nc * nc * nc;
@@ -167,16 +207,18 @@ void or_mg_vcycle(const or_config *c, int n_, double h, double *phi,
   double *ec = (double *)calloc(Nc, sizeof(double));
   restrict8(nc, r, rc);
   remove_mean(nc, rc);
-  or_mg_vcycle(c, (int)nc, 2.0 * h, ec, rc);
+  /* V: one cycle of the error equation; W: two (one on the coarsest) */
+  int mu = (c->mg_cycle == OR_MG_W && !is_coarsest(c, nc)) ? 2 : 1;
+  for (int m = 0; m < mu; ++m) or_mg_vcycle(c, (int)nc, 2.0 * h, ec, rc);
   prolong_add(nc, ec, phi);
-  for (int s = 0; s < c->mg_post; ++s) jacobi(n, h, phi, F, tmp);
+  for (int s = 0; s < c->mg_post; ++s) smooth(c, n, h, phi, F, tmp);
   free(r);
   free(rc);
   free(ec);
   free(tmp);
 }
 
-/* V-cycles from the warm start in phi until ||F - A phi||_2 <= tol ||F||_2 or
+/* Cycles (V or W) from the warm start in phi until ||F - A phi||_2 <= tol ||F||_2 or
  * mg_max_cycles cycles; the mean of phi is removed after every cycle.
  * Returns the number of cycles run. */
 int or_mg_solve(const or_config *c, int n_, double h, double *phi,
@@ -204,6 +246,11 @@ int or_mg_solve(const or_config *c, int n_, double h, double *phi,
 int or_gravity_accel(const or_config *c, const double *U, double *phi,
                      double *acc) {
   long n = c->n[0], N = n * n * n;
+  if (c->grav_solver == OR_GRAV_FFT) {
+    /* the spectral solve and gradient of Sec. 6.1 (oracle_fft.c) */
+    or_fft_gravity(c, U, phi, acc);
+    return 0;
+  }
   double h = c->h[0];
   double *F = (double *)malloc(sizeof(double) * N);
   double mean = fixed_sum(n, U) / (double)N;

@@ -185,11 +185,14 @@ def test_kick_vjp():
     assert float((w * jv).sum()) == pytest.approx(float((accb * da).sum()), rel=1e-8)
 
 
-def test_gravity_vjp():
+@pytest.mark.parametrize("solver,cycle", [(oracle.GRAV_MG, oracle.MG_V),
+                                          (oracle.GRAV_MG, oracle.MG_W),
+                                          (oracle.GRAV_FFT, oracle.MG_V)])
+def test_gravity_vjp(solver, cycle):
     n = 16
     U = wl.grf_density_state(n, seed=2)
     c = oracle.make_config((n, n, n), (1 / n,) * 3, flags=oracle.SRC_GRAVITY, grav_G=wl.JEANS_G,
-                           mg_tol=1e-13, mg_max_cycles=80)
+                           mg_tol=1e-13, mg_max_cycles=80, grav_solver=solver, mg_cycle=cycle)
     dt = 1e-3
     phi0 = np.zeros((n, n, n))
 
@@ -254,12 +257,13 @@ def test_step_vjp_fiducial_scheme():
               eps=1e-7)
 
 
-def test_step_vjp_gravity():
+@pytest.mark.parametrize("solver", [oracle.GRAV_MG, oracle.GRAV_FFT])
+def test_step_vjp_gravity(solver):
     n = 8
     U = wl.grf_density_state(n, seed=3)
     c = oracle.make_config((n, n, n), (1 / n,) * 3,
                            flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING, grav_G=wl.JEANS_G,
-                           mg_tol=1e-13, mg_max_cycles=80)
+                           mg_tol=1e-13, mg_max_cycles=80, grav_solver=solver)
     dt = 0.5 * oracle.cfl_dt(c, U)
     phi = np.zeros((n, n, n))
 

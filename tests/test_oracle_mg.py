@@ -124,3 +124,131 @@ def test_warm_start_and_cycle_cap():
     c0 = mgcfg(n, mg_tol=0.0, mg_max_cycles=3)
     _, cyc3 = oracle.mg_solve(c0, n, h, np.zeros_like(F), F)
     assert cyc3 == 3
+
+
+# ---------------------------------------------------------------- W-cycle, RBGS
+
+@pytest.mark.parametrize("cycle,smoother", [(oracle.MG_W, oracle.SMOOTH_JACOBI),
+                                            (oracle.MG_V, oracle.SMOOTH_RBGS),
+                                            (oracle.MG_W, oracle.SMOOTH_RBGS)])
+def test_cycle_and_smoother_variants_match_fft_solve(cycle, smoother):
+    n = 32
+    rng = np.random.default_rng(7)
+    h = 1.0 / n
+    F = rng.standard_normal((n, n, n))
+    F -= F.mean()
+    c = mgcfg(n, mg_tol=1e-13, mg_max_cycles=60, mg_cycle=cycle, mg_smoother=smoother)
+    phi, cyc = oracle.mg_solve(c, n, h, np.zeros_like(F), F)
+    ref = fft_solve(F, h)
+    assert np.abs(phi - ref).max() < 1e-10 * np.abs(ref).max()
+    assert cyc < 60
+
+
+def _factors(n, **kw):
+    rng = np.random.default_rng(1)
+    h = 1.0 / n
+    F = rng.standard_normal((n, n, n))
+    F -= F.mean()
+    c = mgcfg(n, **kw)
+    phi = np.zeros_like(F)
+    res = []
+    for _ in range(6):
+        r = F - oracle.laplacian(n, h, phi)
+        res.append(math.sqrt((r * r).sum()))
+        phi = oracle.mg_vcycle(c, n, h, phi, F)
+        phi -= phi.mean()
+    return [res[i + 1] / res[i] for i in range(len(res) - 1)]
+
+
+@pytest.mark.parametrize("smoother", [oracle.SMOOTH_JACOBI, oracle.SMOOTH_RBGS])
+def test_wcycle_converges_faster_than_vcycle(smoother):
+    """App. C: the W-cycle's stronger coarse-grid correction reduces the
+    residual more per cycle than the V-cycle, cycle by cycle (with 8-cell
+    averaging, trilinear prolongation and weighted Jacobi the smoother limits
+    both to about 0.3 per cycle; red-black Gauss-Seidel gets the W-cycle to
+    below 0.1, the order of magnitude App. C reports)."""
+    fv = _factors(64, mg_smoother=smoother)
+    fw = _factors(64, mg_cycle=oracle.MG_W, mg_smoother=smoother)
+    assert all(w < v for w, v in zip(fw, fv)), (fw, fv)
+    if smoother == oracle.SMOOTH_RBGS:
+        assert max(fw[1:]) < 0.1, fw
+
+
+def test_rbgs_sweep_zeroes_the_residual_on_black_cells():
+    """A red-black Gauss-Seidel sweep updates the black cells last, each to
+    the value that satisfies its own equation given its (red) neighbours, so
+    afterwards the residual vanishes on every black cell and not on the red
+    ones (a swapped colour order, a Jacobi-style update or a wrong stencil
+    breaks this)."""
+    n = 16
+    h = 1.0 / n
+    rng = np.random.default_rng(3)
+    F = rng.standard_normal((n, n, n)); F -= F.mean()
+    phi0 = rng.standard_normal((n, n, n))
+    c = mgcfg(n, mg_smoother=oracle.SMOOTH_RBGS)
+    phi = oracle.mg_smooth(c, n, h, phi0, F)
+    Aphi = oracle.laplacian(n, h, phi)
+    r = F - Aphi
+    k, j, i = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    black = (i + j + k) % 2 == 1
+    tiny = 1e-12 * np.abs(Aphi).max()
+    assert np.abs(r[black]).max() < tiny
+    assert np.abs(r[~black]).max() > 1e6 * tiny
+
+
+# ---------------------------------------------------------------- spectral gravity
+
+def test_dft3_matches_numpy_fft():
+    rng = np.random.default_rng(4)
+    for n in (5, 8):
+        x = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+        assert np.abs(oracle.dft3(x) - np.fft.fftn(x)).max() < 1e-12 * n ** 3
+        assert np.abs(oracle.dft3(x, inverse=True) - np.fft.ifftn(x)).max() < 1e-13 * n ** 3
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_spectral_gravity_of_single_mode(n):
+    """Sec. 6.1 on rho = 1 + A cos(kappa . x + p): Phi = -4 pi G A cos(.) /
+    |kappa|^2 and a = -grad Phi = -4 pi G A kappa sin(.) / |kappa|^2 exactly."""
+    L = 2.0
+    h = L / n
+    G, A, p = 1.7, 0.05, 0.4
+    m = (1, -2, 3)
+    c = oracle.make_config((n, n, n), (h,) * 3, grav_G=G, grav_solver=oracle.GRAV_FFT)
+    z, y, x = np.meshgrid(*((np.arange(n) + 0.5) * h,) * 3, indexing="ij")
+    kap = [2 * np.pi * mi / L for mi in m]
+    th = kap[0] * x + kap[1] * y + kap[2] * z + p
+    phi, acc = oracle.fft_gravity(c, 1.0 + A * np.cos(th))
+    k2 = sum(k * k for k in kap)
+    assert np.abs(phi + 4 * np.pi * G * A * np.cos(th) / k2).max() < 1e-13
+    for a in range(3):
+        want = -4 * np.pi * G * A * kap[a] * np.sin(th) / k2
+        assert np.abs(acc[a] - want).max() < 1e-13, a
+
+
+def test_spectral_gravity_nyquist_mode_has_no_gradient():
+    """Reading: the derivative of the Nyquist mode is dropped (its i kappa
+    factor has no real counterpart), while it still enters the potential."""
+    n = 8
+    h = 1.0 / n
+    G, A = 1.0, 0.1
+    c = oracle.make_config((n, n, n), (h,) * 3, grav_G=G, grav_solver=oracle.GRAV_FFT)
+    i = np.arange(n).reshape(1, 1, n) * np.ones((n, n, 1))
+    phi, acc = oracle.fft_gravity(c, 1.0 + A * (-1.0) ** i)
+    kN = np.pi * n
+    assert np.abs(phi + 4 * np.pi * G * A * (-1.0) ** i / kN ** 2).max() < 1e-14
+    assert np.abs(acc).max() < 1e-14
+
+
+def test_spectral_gravity_adjoint_identity():
+    """rho -> acc is linear: <g, J v> = <J^T g, v> to round-off."""
+    n = 8
+    h = 1.0 / n
+    c = oracle.make_config((n, n, n), (h,) * 3, grav_G=2.0, grav_solver=oracle.GRAV_FFT)
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal((n, n, n))
+    g = rng.standard_normal((3, n, n, n))
+    _, Jv = oracle.fft_gravity(c, v)
+    lhs = (g * Jv).sum()
+    rhs = (oracle.fft_gravity_vjp(c, g) * v).sum()
+    assert lhs == pytest.approx(rhs, rel=1e-12)
