@@ -51,6 +51,9 @@ enum { MH_F32 = 0, MH_F64 = 1 };
 enum { MH_LIM_MINMOD = 0, MH_LIM_NONE = 1, MH_LIM_VANLEER = 2, MH_LIM_MC = 3, MH_LIM_SUPERBEE = 4 };
 enum { MH_RS_HLLC = 0, MH_RS_HLL = 1, MH_RS_RUSANOV = 2 };
 enum { MH_RK_SSP2 = 0, MH_RK_SSP3 = 1, MH_RK_EULER = 2 };
+enum { MH_MG_V = 0, MH_MG_W = 1 };
+enum { MH_SMOOTH_JACOBI = 0, MH_SMOOTH_RBGS = 1 };
+enum { MH_GRAV_MG = 0, MH_GRAV_FFT = 1 };
 enum { MH_SRC_COOLING = 1u, MH_SRC_FORCING = 2u, MH_SRC_GRAVITY = 4u };
 enum { MH_HOST = 0, MH_DEVICE = 1 };
 
@@ -88,8 +91,8 @@ typedef struct mh_grid_desc {
   double cfl;
 } mh_grid_desc;
 
-/* Source terms, applied after each RK2 step in the order forcing -> gravity
- * -> cooling, each on the state left by the previous one.
+/* Source terms, applied after each Runge-Kutta update in the order forcing ->
+ * gravity -> cooling, each on the state left by the previous one.
  * flags           OR of MH_SRC_*.
  * cool_*          cooling curve in code units with T = P/rho:
  *                 Lambda = lambda0 (T/tc)^(1/2) for T >= tc,
@@ -102,10 +105,17 @@ typedef struct mh_grid_desc {
  *                 (integer mode numbers), and update period every (the mode
  *                 amplitudes advance once every `every` steps by every*dt).
  * grav_G          gravitational constant of lap(phi) = 4 pi G (rho - <rho>).
- * mg_*            multigrid V-cycle (Sec. 6.2, App. C): pre/post weighted
- *                 Jacobi sweeps, maximum cycles per step, coarsest grid size,
- *                 relative residual tolerance (0 runs exactly max_cycles
- *                 cycles), and Jacobi sweeps used to solve the coarsest grid. */
+ * mg_*            multigrid (Sec. 6.2, App. C): pre/post smoothing sweeps,
+ *                 maximum cycles per step, coarsest grid size, relative
+ *                 residual tolerance (0 runs exactly max_cycles cycles),
+ *                 Jacobi sweeps used to solve the coarsest grid, the cycle
+ *                 (MH_MG_V, or MH_MG_W: two coarse cycles per level, the
+ *                 paper's default) and the smoother (MH_SMOOTH_JACOBI,
+ *                 weighted with omega = 2/3, or MH_SMOOTH_RBGS, red-black
+ *                 Gauss-Seidel).
+ * grav_solver     MH_GRAV_MG (the multigrid solve, central-difference
+ *                 gradient) or MH_GRAV_FFT (the spectral solve and gradient
+ *                 of Sec. 6.1; power-of-two n). */
 typedef struct mh_physics_desc {
   uint32_t flags;
   int32_t ou_every;
@@ -116,7 +126,9 @@ typedef struct mh_physics_desc {
   int32_t mg_pre, mg_post, mg_max_cycles, mg_coarsest;
   double mg_tol;
   int32_t mg_coarse_sweeps;
-  int32_t reserved0;
+  int32_t mg_cycle;
+  int32_t mg_smoother;
+  int32_t grav_solver;
 } mh_physics_desc;
 
 typedef struct mh_ctx mh_ctx;

@@ -26,6 +26,9 @@ F32, F64 = 0, 1
 LIM_MINMOD, LIM_NONE, LIM_VANLEER, LIM_MC, LIM_SUPERBEE = 0, 1, 2, 3, 4
 RS_HLLC, RS_HLL, RS_RUSANOV = 0, 1, 2
 RK_SSP2, RK_SSP3, RK_EULER = 0, 1, 2
+MG_V, MG_W = 0, 1
+SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
+GRAV_MG, GRAV_FFT = 0, 1
 SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
 HOST, DEVICE = 0, 1
 
@@ -60,7 +63,8 @@ class PhysicsDesc(ctypes.Structure):
         ("grav_G", ctypes.c_double), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
         ("mg_max_cycles", ctypes.c_int32), ("mg_coarsest", ctypes.c_int32),
         ("mg_tol", ctypes.c_double), ("mg_coarse_sweeps", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("mg_cycle", ctypes.c_int32), ("mg_smoother", ctypes.c_int32),
+        ("grav_solver", ctypes.c_int32),
     ]
 
 
@@ -163,7 +167,8 @@ def grid_desc(shape, h, bc=(BC_PERIODIC,) * 3, dtype="f32", gamma=5.0 / 3.0, cfl
 def physics_desc(flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, ou_arms=1.0,
                  ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0, ou_every=1, grav_G=0.0, mg_pre=2,
                  mg_post=2, mg_max_cycles=20, mg_coarsest=4, mg_tol=1e-10,
-                 mg_coarse_sweeps=200) -> PhysicsDesc:
+                 mg_coarse_sweeps=200, mg_cycle=MG_V, mg_smoother=SMOOTH_JACOBI,
+                 grav_solver=GRAV_MG) -> PhysicsDesc:
     p = PhysicsDesc()
     p.flags = flags
     p.cool_lambda0, p.cool_tc, p.cool_ts, p.cool_tfloor = cool
@@ -172,6 +177,7 @@ def physics_desc(flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, o
     p.grav_G = grav_G
     p.mg_pre, p.mg_post, p.mg_max_cycles, p.mg_coarsest = mg_pre, mg_post, mg_max_cycles, mg_coarsest
     p.mg_tol, p.mg_coarse_sweeps = mg_tol, mg_coarse_sweeps
+    p.mg_cycle, p.mg_smoother, p.grav_solver = mg_cycle, mg_smoother, grav_solver
     return p
 
 

@@ -3,11 +3,14 @@
 //
 // The discrete problem is A phi = F on the periodic n^3 cube, A the
 // seven-point Laplacian, F = 4 pi G (rho - <rho>).  One V-cycle: nu1 weighted
-// Jacobi sweeps (omega = 2/3), residual, restriction by the mean of the 8
-// children, the coarse error equation solved recursively from zero,
-// cell-centred trilinear prolongation (per axis 3/4 parent + 1/4 neighbour on
-// the child's side) and correction, nu2 sweeps; the coarsest grid is solved
-// by many Jacobi sweeps inside one workgroup.  Means are removed from every
+// Jacobi sweeps (omega = 2/3) or red-black Gauss-Seidel sweeps, residual,
+// restriction by the mean of the 8 children, the coarse error equation solved
+// recursively from zero, cell-centred trilinear prolongation (per axis 3/4
+// parent + 1/4 neighbour on the child's side) and correction, nu2 sweeps; the
+// coarsest grid is solved by many Jacobi sweeps inside one workgroup.  The
+// W-cycle (the paper's default, App. C) solves each coarse error equation
+// with two recursive cycles, the second from the first one's result (one
+// solve where the next level is the coarsest).  Means are removed from every
 // restricted right-hand side and from phi after every cycle (gauge <phi> = 0).
 // All reductions are two-stage with fixed block counts, so results do not
 // depend on scheduling.  Every kernel here is memory-bound (about 2 field
@@ -103,6 +106,21 @@ __global__ __launch_bounds__(256) void k_jacobi(int n, T h2, const T* __restrict
   out[q] = (T(1) - w) * phi[q] + (w / T(6)) * (nb6(phi, n, i, j, k) - h2 * F[q]);
 }
 
+// one half of a red-black Gauss-Seidel sweep, in place: every cell of the
+// colour (i + j + k) mod 2 = `colour` is set to (sum of neighbours - h^2 F)/6;
+// the smoothed levels have an even n, so those cells read only the other
+// colour
+template <typename T>
+__global__ __launch_bounds__(256) void k_rbgs(int n, T h2, T* phi, const T* __restrict__ F,
+                                              int colour) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
+  if (((i + j + k) & 1) != colour) return;
+  phi[q] = (nb6(phi, n, i, j, k) - h2 * F[q]) / T(6);
+}
+
 // r = F - A phi
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual(int n, T ih2, const T* __restrict__ phi,
@@ -188,15 +206,17 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int n, T h2, const T* __re
   for (int q = threadIdx.x; q < N; q += 256) phi[q] = src[q] - (T)mean;
 }
 
-// The bottom of the V-cycle in one workgroup.  Every level with at most
+// The bottom of the cycle in one workgroup.  Every level with at most
 // MG_TAIL_MAX_CELLS cells lives in LDS (the levels below a 16^3 level take
-// 4096 + 512 + 64 + ... cells), so the ~20 small launches those levels would
+// 4096 + 512 + 64 + ... cells), so the many small launches those levels would
 // cost (sweeps, residual, restriction, mean removal, coarse solve,
 // prolongation) become one.  On entry F of the tail's first level is its
-// restricted, mean-free right-hand side; on exit phi0 holds its correction
-// after post-smoothing.  The arithmetic of each step is that of the
-// corresponding kernel above; the means are summed with a different fixed
-// tree.
+// restricted, mean-free right-hand side and its phi starts from zero, or from
+// phi0 (`warm`: the second cycle of a W-cycle); on exit phi0 holds the result.
+// Inside, the V- or W-cycle over the tail's levels runs as a loop over an
+// explicit per-level count of the coarse cycles still to do.  The arithmetic
+// of each step is that of the corresponding kernel above; the means are
+// summed with a different fixed tree.
 constexpr int MG_TAIL_MAX_CELLS = 4096;
 constexpr int MG_TAIL_ALLOC = 4688;  // >= 4096 * 8 / 7: all levels of the tail
 constexpr int MG_TAIL_THREADS = 1024;
@@ -209,8 +229,11 @@ struct TailArgs {
   T ih2[MG_MAX_LEVELS];      // 1 / h^2
   int off[MG_MAX_LEVELS];    // offset of each level in the LDS arrays
   const T* F0;               // right-hand side of the first level (global)
-  T* phi0;                   // its correction (global, written)
+  T* phi0;                   // its phi (global: read when warm, written)
   int pre, post, csweeps;
+  int wcycle;                // 1: two coarse cycles per level (W), 0: one (V)
+  int rbgs;                  // smoother: 1 red-black Gauss-Seidel, 0 Jacobi
+  int warm;                  // start the first level from phi0
 };
 
 __device__ __forceinline__ double block_sum1024(double v, double* sh) {
@@ -243,82 +266,122 @@ __device__ void tail_sweeps(T* pa, T* pb, const T* ff, int o, int n, T h2, int s
 }
 
 template <typename T>
-__global__ __launch_bounds__(MG_TAIL_THREADS) void k_vcycle_tail(TailArgs<T> t) {
+__device__ void tail_rbgs(T* pa, T* pb, const T* ff, int o, int n, T h2, int sweeps, int cur) {
+  const int N = n * n * n;
+  T* phi = (cur ? pb : pa) + o;
+  for (int it = 0; it < sweeps; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) {
+        const int i = q % n, j = (q / n) % n, k = q / (n * n);
+        if (((i + j + k) & 1) == colour) phi[q] = (nb6(phi, n, i, j, k) - h2 * ff[o + q]) / T(6);
+      }
+      __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(MG_TAIL_THREADS) void k_mgcycle_tail(TailArgs<T> t) {
   __shared__ T pa[MG_TAIL_ALLOC], pb[MG_TAIL_ALLOC], ff[MG_TAIL_ALLOC];
   __shared__ double sh[MG_TAIL_THREADS];
   int cur[MG_MAX_LEVELS];
+  int todo[MG_MAX_LEVELS];  // coarse cycles of level m + 1 still to run for level m
   {
     const int N0 = t.n[0] * t.n[0] * t.n[0];
-    for (int q = threadIdx.x; q < N0; q += MG_TAIL_THREADS) ff[t.off[0] + q] = t.F0[q];
-  }
-  for (int l = 0; l < t.nl - 1; ++l) {
-    const int n = t.n[l], N = n * n * n, o = t.off[l];
-    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) pa[o + q] = T(0);
-    cur[l] = 0;
-    __syncthreads();
-    tail_sweeps(pa, pb, ff, o, n, t.h2[l], t.pre, cur[l]);
-    // restricted residual: F_{l+1} = average over the 8 children of F - A phi
-    const T* phi = (cur[l] ? pb : pa) + o;
-    const int nc = t.n[l + 1], Nc = nc * nc * nc, oc = t.off[l + 1];
-    for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) {
-      const int I = Q % nc, J = (Q / nc) % nc, K = Q / (nc * nc);
-      T sum = T(0);
-      for (int c = 0; c < 2; ++c)
-        for (int b = 0; b < 2; ++b)
-          for (int a = 0; a < 2; ++a) {
-            const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
-            const int q = (k * n + j) * n + i;
-            sum += ff[o + q] - (nb6(phi, n, i, j, k) - T(6) * phi[q]) * t.ih2[l];
-          }
-      ff[oc + Q] = T(0.125) * sum;
+    for (int q = threadIdx.x; q < N0; q += MG_TAIL_THREADS) {
+      ff[t.off[0] + q] = t.F0[q];
+      pa[t.off[0] + q] = t.warm ? t.phi0[q] : T(0);
     }
-    __syncthreads();
-    double m = 0.0;
-    for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) m += (double)ff[oc + Q];
-    const T mean = (T)(block_sum1024(m, sh) / (double)Nc);
-    for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) ff[oc + Q] = ff[oc + Q] - mean;
+    cur[0] = 0;
     __syncthreads();
   }
-  {
-    // coarsest level: phi = 0, sweeps, remove the mean (as k_coarse_solve)
-    const int l = t.nl - 1, n = t.n[l], N = n * n * n, o = t.off[l];
-    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) pa[o + q] = T(0);
-    cur[l] = 0;
-    __syncthreads();
-    tail_sweeps(pa, pb, ff, o, n, t.h2[l], t.csweeps, cur[l]);
-    T* phi = (cur[l] ? pb : pa) + o;
-    double m = 0.0;
-    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) m += (double)phi[q];
-    const double mean = block_sum1024(m, sh) / (double)N;
-    for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) phi[q] = phi[q] - (T)mean;
-    __syncthreads();
-  }
-  for (int l = t.nl - 2; l >= 0; --l) {
-    // cell-centred trilinear prolongation of the coarse correction, added
-    const int nc = t.n[l + 1], nf = t.n[l], Nf = nf * nf * nf;
-    const T* ec = (cur[l + 1] ? pb : pa) + t.off[l + 1];
-    T* phif = (cur[l] ? pb : pa) + t.off[l];
-    for (int q = threadIdx.x; q < Nf; q += MG_TAIL_THREADS) {
-      const int i = q % nf, j = (q / nf) % nf, k = q / (nf * nf);
-      const int I = i >> 1, J = j >> 1, K = k >> 1;
-      const int I2 = wrapi(I + ((i & 1) ? 1 : -1), nc);
-      const int J2 = wrapi(J + ((j & 1) ? 1 : -1), nc);
-      const int K2 = wrapi(K + ((k & 1) ? 1 : -1), nc);
-      auto at = [&](int a, int b, int c) { return ec[(c * nc + b) * nc + a]; };
-      const T w0 = T(0.75), w1 = T(0.25);
-      T e = T(0);
-      e += w0 * w0 * w0 * at(I, J, K);
-      e += w1 * w0 * w0 * at(I2, J, K);
-      e += w0 * w1 * w0 * at(I, J2, K);
-      e += w1 * w1 * w0 * at(I2, J2, K);
-      e += w0 * w0 * w1 * at(I, J, K2);
-      e += w1 * w0 * w1 * at(I2, J, K2);
-      e += w0 * w1 * w1 * at(I, J2, K2);
-      e += w1 * w1 * w1 * at(I2, J2, K2);
-      phif[q] += e;
+  auto smooth = [&](int m, int sweeps) {
+    if (t.rbgs) tail_rbgs(pa, pb, ff, t.off[m], t.n[m], t.h2[m], sweeps, cur[m]);
+    else tail_sweeps(pa, pb, ff, t.off[m], t.n[m], t.h2[m], sweeps, cur[m]);
+  };
+  int m = 0;
+  bool down = true;
+  for (;;) {
+    if (down) {
+      if (m == t.nl - 1) {
+        // coarsest level: phi = 0, Jacobi sweeps, remove the mean (as
+        // k_coarse_solve)
+        const int n = t.n[m], N = n * n * n, o = t.off[m];
+        for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) pa[o + q] = T(0);
+        cur[m] = 0;
+        __syncthreads();
+        tail_sweeps(pa, pb, ff, o, n, t.h2[m], t.csweeps, cur[m]);
+        T* phi = (cur[m] ? pb : pa) + o;
+        double s = 0.0;
+        for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) s += (double)phi[q];
+        const double mean = block_sum1024(s, sh) / (double)N;
+        for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) phi[q] = phi[q] - (T)mean;
+        __syncthreads();
+        down = false;
+        continue;
+      }
+      const int n = t.n[m], o = t.off[m];
+      smooth(m, t.pre);
+      // restricted residual: F_{m+1} = average over the 8 children of F - A phi
+      const T* phi = (cur[m] ? pb : pa) + o;
+      const int nc = t.n[m + 1], Nc = nc * nc * nc, oc = t.off[m + 1];
+      for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) {
+        const int I = Q % nc, J = (Q / nc) % nc, K = Q / (nc * nc);
+        T sum = T(0);
+        for (int c = 0; c < 2; ++c)
+          for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+              const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+              const int q = (k * n + j) * n + i;
+              sum += ff[o + q] - (nb6(phi, n, i, j, k) - T(6) * phi[q]) * t.ih2[m];
+            }
+        ff[oc + Q] = T(0.125) * sum;
+      }
+      __syncthreads();
+      double s = 0.0;
+      for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) s += (double)ff[oc + Q];
+      const T mean = (T)(block_sum1024(s, sh) / (double)Nc);
+      for (int Q = threadIdx.x; Q < Nc; Q += MG_TAIL_THREADS) {
+        ff[oc + Q] = ff[oc + Q] - mean;
+        pa[oc + Q] = T(0);  // the coarse error starts from zero
+      }
+      cur[m + 1] = 0;
+      __syncthreads();
+      todo[m] = (t.wcycle && m + 1 < t.nl - 1) ? 2 : 1;
+      ++m;
+    } else {
+      if (m == 0) break;
+      const int p = m - 1;
+      if (--todo[p] > 0) {
+        down = true;  // the next coarse cycle starts from the current result
+        continue;
+      }
+      // cell-centred trilinear prolongation of the coarse correction, added
+      const int nc = t.n[m], nf = t.n[p], Nf = nf * nf * nf;
+      const T* ec = (cur[m] ? pb : pa) + t.off[m];
+      T* phif = (cur[p] ? pb : pa) + t.off[p];
+      for (int q = threadIdx.x; q < Nf; q += MG_TAIL_THREADS) {
+        const int i = q % nf, j = (q / nf) % nf, k = q / (nf * nf);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int I2 = wrapi(I + ((i & 1) ? 1 : -1), nc);
+        const int J2 = wrapi(J + ((j & 1) ? 1 : -1), nc);
+        const int K2 = wrapi(K + ((k & 1) ? 1 : -1), nc);
+        auto at = [&](int a, int b, int c) { return ec[(c * nc + b) * nc + a]; };
+        const T w0 = T(0.75), w1 = T(0.25);
+        T e = T(0);
+        e += w0 * w0 * w0 * at(I, J, K);
+        e += w1 * w0 * w0 * at(I2, J, K);
+        e += w0 * w1 * w0 * at(I, J2, K);
+        e += w1 * w1 * w0 * at(I2, J2, K);
+        e += w0 * w0 * w1 * at(I, J, K2);
+        e += w1 * w0 * w1 * at(I2, J, K2);
+        e += w0 * w1 * w1 * at(I, J2, K2);
+        e += w1 * w1 * w1 * at(I2, J2, K2);
+        phif[q] += e;
+      }
+      __syncthreads();
+      m = p;
+      smooth(m, t.post);
     }
-    __syncthreads();
-    tail_sweeps(pa, pb, ff, t.off[l], nf, t.h2[l], t.post, cur[l]);
   }
   {
     const int N0 = t.n[0] * t.n[0] * t.n[0];
@@ -412,95 +475,122 @@ T* P(char* ws, size_t off) {
   return reinterpret_cast<T*>(ws + off);
 }
 
-// one V-cycle on level 0; phi of level 0 is lev[0].phi[cur]
+// smoothing sweeps on host-launched level l: weighted Jacobi (ping-pong,
+// flips cur) or red-black Gauss-Seidel (in place)
+template <typename T>
+void smooth_level(char* ws, MGLevel& lv, int sweeps, int rbgs, int& cur, hipStream_t s) {
+  const long long N = (long long)lv.n * lv.n * lv.n;
+  const T h2 = (T)(lv.h * lv.h);
+  for (int it = 0; it < sweeps; ++it) {
+    if (rbgs) {
+      for (int colour = 0; colour < 2; ++colour)
+        hipLaunchKernelGGL((k_rbgs<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
+                           P<T>(ws, lv.phi[cur]), P<T>(ws, lv.F), colour);
+    } else {
+      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
+                         P<T>(ws, lv.phi[cur]), P<T>(ws, lv.F), P<T>(ws, lv.phi[1 - cur]));
+      cur = 1 - cur;
+    }
+  }
+}
+
+// first level handled by the single-workgroup tail: the first one after the
+// fine level with at most MG_TAIL_MAX_CELLS cells that is not the coarsest
+// (nlev when there is none)
+inline int tail_level(const MGLayout& L) {
+  for (int l = 1; l < L.nlev - 1; ++l) {
+    const long long Nl = (long long)L.lev[l].n * L.lev[l].n * L.lev[l].n;
+    if (Nl <= MG_TAIL_MAX_CELLS) return l;
+  }
+  return L.nlev;
+}
+
+// one cycle on level l < l0 from its current phi (lev[l].phi[cur[l]]): pre
+// smoothing, restriction of the residual, the coarse error equation solved by
+// one (V) or two (W) cycles of level l + 1 from zero -- one solve when level
+// l + 1 is the coarsest -- prolongation and correction, post smoothing
+template <typename T>
+hipError_t level_cycle(char* ws, MGLayout& L, const mh_physics_desc& p, int l, int l0,
+                       int* cur, double* partial, double* mean_slot, hipStream_t s) {
+  const int nl = L.nlev;
+  const int rbgs = p.mg_smoother == MH_SMOOTH_RBGS;
+  MGLevel& lv = L.lev[l];
+  const long long N = (long long)lv.n * lv.n * lv.n;
+  smooth_level<T>(ws, lv, p.mg_pre, rbgs, cur[l], s);
+  hipLaunchKernelGGL((k_residual<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, (T)(1.0 / (lv.h * lv.h)),
+                     P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.r));
+  MGLevel& cv = L.lev[l + 1];
+  const long long Nc = (long long)cv.n * cv.n * cv.n;
+  hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(Nc)), dim3(256), 0, s, cv.n, P<T>(ws, lv.r),
+                     P<T>(ws, cv.F));
+  hipError_t e = remove_mean(P<T>(ws, cv.F), Nc, partial, mean_slot, s);
+  if (e != hipSuccess) return e;
+  const int mu = (p.mg_cycle == MH_MG_W && l + 1 < nl - 1) ? 2 : 1;
+  if (l + 1 == l0) {
+    TailArgs<T> t{};
+    t.nl = nl - l0;
+    int off = 0;
+    for (int m = 0; m < t.nl; ++m) {
+      const MGLevel& tv = L.lev[l0 + m];
+      t.n[m] = tv.n;
+      t.h2[m] = (T)(tv.h * tv.h);
+      t.ih2[m] = (T)(1.0 / (tv.h * tv.h));
+      t.off[m] = off;
+      off += tv.n * tv.n * tv.n;
+    }
+    if (off > MG_TAIL_ALLOC) return hipErrorInvalidValue;
+    t.F0 = P<T>(ws, cv.F);
+    t.phi0 = P<T>(ws, cv.phi[0]);
+    t.pre = p.mg_pre;
+    t.post = p.mg_post;
+    t.csweeps = p.mg_coarse_sweeps;
+    t.wcycle = p.mg_cycle == MH_MG_W;
+    t.rbgs = rbgs;
+    cur[l + 1] = 0;
+    for (int k = 0; k < mu; ++k) {
+      t.warm = k > 0;
+      hipLaunchKernelGGL((k_mgcycle_tail<T>), dim3(1), dim3(MG_TAIL_THREADS), 0, s, t);
+    }
+  } else if (l + 1 == nl - 1) {
+    cur[l + 1] = 0;
+    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(256), 0, s, cv.n, (T)(cv.h * cv.h),
+                       P<T>(ws, cv.F), P<T>(ws, cv.phi[0]), p.mg_coarse_sweeps);
+  } else {
+    cur[l + 1] = 0;
+    hipLaunchKernelGGL((k_zero<T>), dim3(nblk(Nc)), dim3(256), 0, s, P<T>(ws, cv.phi[0]), Nc);
+    for (int k = 0; k < mu; ++k) {
+      e = level_cycle<T>(ws, L, p, l + 1, l0, cur, partial, mean_slot, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL((k_prolong_add<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n,
+                     P<T>(ws, cv.phi[cur[l + 1]]), P<T>(ws, lv.phi[cur[l]]));
+  smooth_level<T>(ws, lv, p.mg_post, rbgs, cur[l], s);
+  return hipGetLastError();
+}
+
+// one cycle (V or W) on level 0; phi of level 0 is lev[0].phi[L.cur0]
 template <typename T>
 hipError_t vcycle(char* ws, MGLayout& L, const mh_physics_desc& p, double* partial,
                   double* mean_slot, hipStream_t s) {
   const int nl = L.nlev;
   int cur[MG_MAX_LEVELS];
   cur[0] = L.cur0;
-  // first level handled by the single-workgroup tail (fine level excluded:
-  // it starts from the previous solution, the tail from zero)
-  int l0 = nl;
-  for (int l = 1; l < nl - 1; ++l) {
-    const long long Nl = (long long)L.lev[l].n * L.lev[l].n * L.lev[l].n;
-    if (Nl <= MG_TAIL_MAX_CELLS) {
-      l0 = l;
-      break;
+  if (nl == 1) {
+    // the whole grid is the coarsest grid: plain Jacobi sweeps from the warm
+    // start
+    MGLevel& cv = L.lev[0];
+    const long long N = (long long)cv.n * cv.n * cv.n;
+    for (int it = 0; it < p.mg_coarse_sweeps; ++it) {
+      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n, (T)(cv.h * cv.h),
+                         P<T>(ws, cv.phi[cur[0]]), P<T>(ws, cv.F), P<T>(ws, cv.phi[1 - cur[0]]));
+      cur[0] = 1 - cur[0];
     }
-  }
-  for (int l = 0; l < nl - 1 && l < l0; ++l) {
-    MGLevel& lv = L.lev[l];
-    const long long N = (long long)lv.n * lv.n * lv.n;
-    const T h2 = (T)(lv.h * lv.h);
-    if (l > 0) {
-      cur[l] = 0;
-      hipLaunchKernelGGL((k_zero<T>), dim3(nblk(N)), dim3(256), 0, s, P<T>(ws, lv.phi[0]), N);
-    }
-    for (int it = 0; it < p.mg_pre; ++it) {
-      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
-                         P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.phi[1 - cur[l]]));
-      cur[l] = 1 - cur[l];
-    }
-    hipLaunchKernelGGL((k_residual<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, (T)(1.0 / (lv.h * lv.h)),
-                       P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.r));
-    MGLevel& cv = L.lev[l + 1];
-    const long long Nc = (long long)cv.n * cv.n * cv.n;
-    hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(Nc)), dim3(256), 0, s, cv.n, P<T>(ws, lv.r),
-                       P<T>(ws, cv.F));
-    hipError_t e = remove_mean(P<T>(ws, cv.F), Nc, partial, mean_slot, s);
+    hipError_t e = remove_mean(P<T>(ws, cv.phi[cur[0]]), N, partial, mean_slot, s);
     if (e != hipSuccess) return e;
-  }
-  if (l0 < nl) {
-    TailArgs<T> t{};
-    t.nl = nl - l0;
-    int off = 0;
-    for (int m = 0; m < t.nl; ++m) {
-      const MGLevel& lv = L.lev[l0 + m];
-      t.n[m] = lv.n;
-      t.h2[m] = (T)(lv.h * lv.h);
-      t.ih2[m] = (T)(1.0 / (lv.h * lv.h));
-      t.off[m] = off;
-      off += lv.n * lv.n * lv.n;
-    }
-    if (off > MG_TAIL_ALLOC) return hipErrorInvalidValue;
-    t.F0 = P<T>(ws, L.lev[l0].F);
-    t.phi0 = P<T>(ws, L.lev[l0].phi[0]);
-    t.pre = p.mg_pre;
-    t.post = p.mg_post;
-    t.csweeps = p.mg_coarse_sweeps;
-    cur[l0] = 0;
-    hipLaunchKernelGGL((k_vcycle_tail<T>), dim3(1), dim3(MG_TAIL_THREADS), 0, s, t);
   } else {
-    MGLevel& cv = L.lev[nl - 1];
-    if (nl == 1) {
-      // the whole grid is the coarsest grid: plain sweeps from the warm start
-      const long long N = (long long)cv.n * cv.n * cv.n;
-      for (int it = 0; it < p.mg_coarse_sweeps; ++it) {
-        hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n, (T)(cv.h * cv.h),
-                           P<T>(ws, cv.phi[cur[0]]), P<T>(ws, cv.F), P<T>(ws, cv.phi[1 - cur[0]]));
-        cur[0] = 1 - cur[0];
-      }
-      hipError_t e = remove_mean(P<T>(ws, cv.phi[cur[0]]), N, partial, mean_slot, s);
-      if (e != hipSuccess) return e;
-    } else {
-      cur[nl - 1] = 0;
-      hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(256), 0, s, cv.n, (T)(cv.h * cv.h),
-                         P<T>(ws, cv.F), P<T>(ws, cv.phi[0]), p.mg_coarse_sweeps);
-    }
-  }
-  for (int l = (l0 < nl ? l0 : nl - 1) - 1; l >= 0; --l) {
-    MGLevel& lv = L.lev[l];
-    MGLevel& cv = L.lev[l + 1];
-    const long long N = (long long)lv.n * lv.n * lv.n;
-    const T h2 = (T)(lv.h * lv.h);
-    hipLaunchKernelGGL((k_prolong_add<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n,
-                       P<T>(ws, cv.phi[cur[l + 1]]), P<T>(ws, lv.phi[cur[l]]));
-    for (int it = 0; it < p.mg_post; ++it) {
-      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
-                         P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.phi[1 - cur[l]]));
-      cur[l] = 1 - cur[l];
-    }
+    hipError_t e = level_cycle<T>(ws, L, p, 0, tail_level(L), cur, partial, mean_slot, s);
+    if (e != hipSuccess) return e;
   }
   L.cur0 = cur[0];
   return hipGetLastError();
@@ -522,6 +612,18 @@ mh_status mg_validate(const mh_grid_desc* g, const mh_physics_desc* p, std::stri
       p->mg_coarsest < 1 || !(p->mg_tol >= 0.0) || p->mg_coarse_sweeps < 0) {
     err = "bad multigrid parameters";
     return MH_E_INVALID;
+  }
+  if (p->mg_cycle != MH_MG_V && p->mg_cycle != MH_MG_W) {
+    err = "unknown multigrid cycle";
+    return MH_E_UNSUPPORTED;
+  }
+  if (p->mg_smoother != MH_SMOOTH_JACOBI && p->mg_smoother != MH_SMOOTH_RBGS) {
+    err = "unknown multigrid smoother";
+    return MH_E_UNSUPPORTED;
+  }
+  if (p->grav_solver != MH_GRAV_MG) {
+    err = "unknown gravity solver";
+    return MH_E_UNSUPPORTED;
   }
   int n = g->n[0], levels = 1;
   while (!(n <= p->mg_coarsest || (n % 2) != 0)) {

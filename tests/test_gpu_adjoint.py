@@ -115,6 +115,21 @@ def test_adjoint_fiducial_scheme_with_sources(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_gravity_wcycle_rbgs(dtype):
+    # the input of test_adjoint_gravity_cooling, whose branch decisions keep
+    # margins above fp32 rounding (with seeds 6/7 a relative change of 1e-7
+    # in the input moves the oracle's own adjoint by 2e-2: a kink)
+    n = 16
+    U0 = wl.grf_density_state(n, seed=5)
+    U0[1:4] += 0.05 * np.random.default_rng(6).standard_normal((3, n, n, n)) * U0[0]
+    got, ref = gpu_vs_oracle_adjoint((n, n, n), (1 / n,) * 3, U0, dtype,
+                                     flags=oracle.SRC_GRAVITY, grav_G=wl.JEANS_G, mg_tol=0.0,
+                                     mg_max_cycles=10, mg_cycle=oracle.MG_W,
+                                     mg_smoother=oracle.SMOOTH_RBGS)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_gravity_cooling(dtype):
     n = 16
     U0 = wl.grf_density_state(n, seed=5)

@@ -18,22 +18,25 @@ def _name(request):
     yield
 
 
-def make(n, dtype, graphs):
+def make(n, dtype, graphs, cycle=mh.MG_V, smoother=mh.SMOOTH_JACOBI):
     g = mh.grid_desc((n, n, n), (1.0 / n,) * 3, dtype=dtype)
     p = mh.physics_desc(flags=mh.SRC_GRAVITY | mh.SRC_COOLING, grav_G=wl.JEANS_G,
-                        mg_tol=1e-9 if dtype == "f64" else 1e-5, mg_max_cycles=12)
+                        mg_tol=1e-9 if dtype == "f64" else 1e-5, mg_max_cycles=12,
+                        mg_cycle=cycle, mg_smoother=smoother)
     s = mh.Solver(g, p)
     s.set_graphs(graphs)
     return s
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_graph_replays_match_eager_launches(dtype):
+@pytest.mark.parametrize("dtype,cycle,smoother", [("f64", mh.MG_V, mh.SMOOTH_JACOBI),
+                                                  ("f32", mh.MG_V, mh.SMOOTH_JACOBI),
+                                                  ("f64", mh.MG_W, mh.SMOOTH_RBGS)])
+def test_graph_replays_match_eager_launches(dtype, cycle, smoother):
     import torch
 
-    n = 32
+    n = 32 if cycle == mh.MG_V else 64
     U0 = as_input(wl.grf_density_state(n, seed=7), dtype)
-    sg, se = make(n, dtype, True), make(n, dtype, False)
+    sg, se = make(n, dtype, True, cycle, smoother), make(n, dtype, False, cycle, smoother)
     for s in (sg, se):
         s.set_state(U0)
     for k in range(6):

@@ -347,6 +347,39 @@ def test_gravity_fixed_cycles(dtype, cool):
     assert np.abs(phi - sim.phi).max() < 10 * TOL[dtype] * np.abs(sim.phi).max()
 
 
+MG_VARIANTS = [(oracle.MG_W, oracle.SMOOTH_JACOBI), (oracle.MG_V, oracle.SMOOTH_RBGS),
+               (oracle.MG_W, oracle.SMOOTH_RBGS)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("cycle,smoother", MG_VARIANTS)
+def test_gravity_cycle_and_smoother_variants(dtype, cycle, smoother):
+    """W-cycle and red-black Gauss-Seidel (App. C, Sec. 6.2.1) at 32^3: the
+    single-workgroup tail runs the W recursion and is launched twice."""
+    n = 32
+    U0 = wl.grf_density_state(n, seed=2)
+    s, sim = run_both((n, n, n), (1 / n,) * 3, U0, dtype, 3,
+                      flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING, grav_G=wl.JEANS_G,
+                      mg_tol=0.0, mg_max_cycles=3, mg_cycle=cycle, mg_smoother=smoother)
+    assert s.mg_cycles() == 3
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+    phi = s.potential().astype(np.float64)
+    assert np.abs(phi - sim.phi).max() < 10 * TOL[dtype] * np.abs(sim.phi).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gravity_wcycle_host_levels_64(dtype):
+    """64^3: two host-launched levels recurse (W) above the tail."""
+    n = 64
+    U0 = wl.grf_density_state(n, seed=3)
+    s, sim = run_both((n, n, n), (1 / n,) * 3, U0, dtype, 2, flags=oracle.SRC_GRAVITY,
+                      grav_G=wl.JEANS_G, mg_tol=0.0, mg_max_cycles=2, mg_cycle=oracle.MG_W,
+                      mg_smoother=oracle.SMOOTH_RBGS)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+    phi = s.potential().astype(np.float64)
+    assert np.abs(phi - sim.phi).max() < 10 * TOL[dtype] * np.abs(sim.phi).max()
+
+
 def test_gravity_tolerance_cycle_counts():
     n = 32
     U0 = wl.grf_density_state(n, seed=1)

@@ -65,6 +65,11 @@ def test_workspace_size_of_valid_grids():
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.bc.__setitem__(0, 1)), mh.E_SHAPE),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.n.__setitem__(0, 32)), mh.E_SHAPE),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "mg_coarsest", 0)), mh.E_INVALID),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "mg_cycle", 2)), mh.E_UNSUPPORTED),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "mg_smoother", 5)),
+     mh.E_UNSUPPORTED),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "grav_solver", 4)),
+     mh.E_UNSUPPORTED),
 ])
 def test_validation_rejects(mutate, status):
     g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f64")
