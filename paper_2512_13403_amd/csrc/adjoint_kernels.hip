@@ -839,6 +839,7 @@ hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws
                            const mh_physics_desc& p, const T* Ub, const T* phi, int n, double h,
                            T dt, const T* lin, T* lout, DevClock* clk, hipStream_t s) {
   const long long N = (long long)n * n * n;
+  if (mgL.fft) return fft_gravity_vjp<T>(mgws, mgL, h, p.grav_G, Ub, dt, lin, lout, B.accb, s);
   const T i2h = (T)(1.0 / (2.0 * h));
   hipLaunchKernelGGL((k_grav_kick_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, Ub, phi, n, i2h, dt,
                      lin, lout, B.accb);

@@ -1,0 +1,427 @@
+// fft_kernels.hip -- spectral self-gravity on the device (arXiv 2512.13403,
+// Sec. 6.1): the Poisson equation lap(Phi) = 4 pi G (rho - <rho>) solved in
+// Fourier space, Phi_hat = -F_hat / |kappa|^2 (zero mode 0), the acceleration
+// a = -grad Phi by multiplying with -i kappa, and the adjoint of rho -> a for
+// the reverse pass (the potential adjoint sum_a i kappa_a g_hat_a scaled by
+// -4 pi G / kappa^2).
+//
+// Transforms are complex-to-complex over the whole n^3 cube (n a power of
+// two), one axis at a time.  A workgroup loads `lpb` whole lines along the
+// axis into 64 KB of LDS -- for the y and z axes lines of consecutive x, so every load
+// and store touches lpb consecutive elements -- in bit-reversed order, runs
+// the log2(n) radix-2 butterfly stages in place in LDS, and writes the lines
+// back in natural order.  Twiddles exp(-2 pi i t / n), t < n/2, come from
+// fp64 sincospi.  The inverse transform is unscaled; the 1/n^3 is folded into
+// the spectral multipliers.
+//
+// Wavenumbers on a box of length L = n h: kappa = 2 pi m / L with m = q for
+// index q <= n/2, q - n above.  The derivative uses kappa with the Nyquist
+// index q = n/2 set to 0 (its i kappa factor has no real counterpart), while
+// |kappa|^2 keeps it.
+#include <cmath>
+
+#include "mg.h"
+#include "mh_device.h"
+#include "mh_launch.h"
+
+namespace mh {
+
+namespace {
+
+template <typename T>
+struct CplxOf;
+template <>
+struct CplxOf<float> {
+  using type = float2;
+};
+template <>
+struct CplxOf<double> {
+  using type = double2;
+};
+
+constexpr int FFT_THREADS = 512;
+constexpr int FFT_LDS_BYTES = 65536;  // lines per workgroup: as many as fit
+
+inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+T* P(char* ws, size_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_twiddles(typename CplxOf<T>::type* tw, int n) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n / 2) return;
+  double s, c;
+  sincospi(-2.0 * (double)t / (double)n, &s, &c);
+  tw[t].x = (T)c;
+  tw[t].y = (T)s;
+}
+
+__device__ __forceinline__ int bitrev(int j, int logn) {
+  return (int)(__builtin_bitreverse32((unsigned)j) >> (32 - logn));
+}
+
+// first element and stride of line `line` along AXIS of the n^3 cube; lines
+// are numbered with x fastest among the two other coordinates
+template <int AXIS>
+__device__ __forceinline__ void line_geom(int n, long long line, long long& base,
+                                          long long& stride) {
+  const long long nn = n;
+  if (AXIS == 0) {
+    base = line * nn;
+    stride = 1;
+  } else if (AXIS == 1) {
+    const long long x = line % nn, z = line / nn;
+    base = z * nn * nn + x;
+    stride = nn;
+  } else {
+    base = line;  // line = y n + x
+    stride = nn * nn;
+  }
+}
+
+// in-place FFT of lpb lines per workgroup; inverse: conjugate twiddles,
+// unscaled
+template <typename T, int AXIS>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::type* data,
+                                                           const typename CplxOf<T>::type* tw,
+                                                           int n, int logn, int lpb,
+                                                           int inverse) {
+  using C = typename CplxOf<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const long long line0 = (long long)blockIdx.x * lpb;
+  const int E = lpb * n;
+  for (int e = threadIdx.x; e < E; e += FFT_THREADS) {
+    // x axis: consecutive threads walk along a line; y, z: across lines
+    const int li = AXIS == 0 ? e / n : e % lpb;
+    const int j = AXIS == 0 ? e % n : e / lpb;
+    long long base, stride;
+    line_geom<AXIS>(n, line0 + li, base, stride);
+    buf[li * n + bitrev(j, logn)] = data[base + (long long)j * stride];
+  }
+  __syncthreads();
+  const int half = n / 2;
+  for (int s = 0; s < logn; ++s) {
+    const int m = 1 << s;
+    for (int b = threadIdx.x; b < lpb * half; b += FFT_THREADS) {
+      const int li = b / half, t = b % half;
+      const int g = t >> s, j = t & (m - 1);
+      const int i = li * n + g * 2 * m + j;
+      C w = tw[j << (logn - 1 - s)];
+      if (inverse) w.y = -w.y;
+      const C u = buf[i], x = buf[i + m];
+      const C v = {x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x};
+      buf[i] = C{u.x + v.x, u.y + v.y};
+      buf[i + m] = C{u.x - v.x, u.y - v.y};
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < E; e += FFT_THREADS) {
+    const int li = AXIS == 0 ? e / n : e % lpb;
+    const int j = AXIS == 0 ? e % n : e / lpb;
+    long long base, stride;
+    line_geom<AXIS>(n, line0 + li, base, stride);
+    data[base + (long long)j * stride] = buf[li * n + j];
+  }
+}
+
+__device__ __forceinline__ int wavenum(int q, int n) { return q <= n / 2 ? q : q - n; }
+
+// c = (x, 0)
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_pack(typename CplxOf<T>::type* c,
+                                                  const T* __restrict__ x, long long N) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  c[q].x = x[q];
+  c[q].y = T(0);
+}
+
+// Phi_hat / N = -F_hat / (|kappa|^2 N), 0 at kappa = 0
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_phi(typename CplxOf<T>::type* c, int n, double tk) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int kx = wavenum((int)(q % n), n), ky = wavenum((int)((q / n) % n), n),
+            kz = wavenum((int)(q / ((long long)n * n)), n);
+  const double k2 = tk * tk * (double)(kx * kx + ky * ky + kz * kz);
+  const T f = k2 > 0.0 ? (T)(-1.0 / (k2 * (double)N)) : T(0);
+  c[q].x *= f;
+  c[q].y *= f;
+}
+
+// derivative wavenumber of index q along an axis (Nyquist -> 0)
+__device__ __forceinline__ double dkappa(int q, int n, double tk) {
+  return q == n / 2 ? 0.0 : tk * (double)wavenum(q, n);
+}
+
+template <int AXIS>
+__device__ __forceinline__ int axis_index(long long q, int n) {
+  return AXIS == 0 ? (int)(q % n) : (AXIS == 1 ? (int)((q / n) % n) : (int)(q / ((long long)n * n)));
+}
+
+// a_hat = -i kappa~_a Phi_hat: (re, im) -> (kappa~ im, -kappa~ re)
+template <typename T, int AXIS>
+__global__ __launch_bounds__(256) void k_fft_grad(const typename CplxOf<T>::type* __restrict__ c0,
+                                                  typename CplxOf<T>::type* c1, int n, double tk) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const T ka = (T)dkappa(axis_index<AXIS>(q, n), n, tk);
+  c1[q].x = ka * c0[q].y;
+  c1[q].y = -ka * c0[q].x;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_real(const typename CplxOf<T>::type* __restrict__ c,
+                                                  T* out, long long N) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < N) out[q] = c[q].x;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_real_add(const typename CplxOf<T>::type* __restrict__ c,
+                                                      T* out, long long N) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q < N) out[q] += c[q].x;
+}
+
+// adjoint accumulation: acc (+)= conj(m_a) g_hat / N with m_a = 4 pi G i
+// kappa~_a / |kappa|^2, i.e. conj(m_a) g = -4 pi G kappa~_a / k2 (-g.y, g.x)
+template <typename T, int AXIS>
+__global__ __launch_bounds__(256) void k_fft_adj_accum(const typename CplxOf<T>::type* __restrict__ g,
+                                                       typename CplxOf<T>::type* acc, int n,
+                                                       double tk, double fourpiG, int first) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int kx = wavenum((int)(q % n), n), ky = wavenum((int)((q / n) % n), n),
+            kz = wavenum((int)(q / ((long long)n * n)), n);
+  const double k2 = tk * tk * (double)(kx * kx + ky * ky + kz * kz);
+  const T f = k2 > 0.0 ? (T)(-fourpiG * dkappa(axis_index<AXIS>(q, n), n, tk) / (k2 * (double)N))
+                       : T(0);
+  const T re = -f * g[q].y, im = f * g[q].x;
+  if (first) {
+    acc[q].x = re;
+    acc[q].y = im;
+  } else {
+    acc[q].x += re;
+    acc[q].y += im;
+  }
+}
+
+// gravity kick with a given acceleration field, m += rho a dt, E += (m_old .
+// a) dt; then cooling; then the CFL max and the health check (the same
+// epilogue as the multigrid path's sources kernel)
+template <typename T, bool COOL>
+__global__ __launch_bounds__(256) void k_accel_sources(T* U, const T* __restrict__ acc,
+                                                       long long N, T gamma, T ihx,
+                                                       CoolParams<T> cool, DevClock* clk) {
+  __shared__ T sRed[4];
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  const T dt = (T)clk->dt;
+  const T gm1 = gamma - T(1);
+  T s = T(0);
+  unsigned long long bad = 0;
+  if (q < N) {
+    const T gx = acc[q], gy = acc[N + q], gz = acc[2 * N + q];
+    T u[5];
+    load_cell(U, N, q, u);
+    const T dE = u[1] * gx + u[2] * gy + u[3] * gz;
+    u[1] += u[0] * gx * dt;
+    u[2] += u[0] * gy * dt;
+    u[3] += u[0] * gz * dt;
+    u[4] += dE * dt;
+    if (COOL) {
+      const T ek = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+      const T Tin = gm1 * (u[4] - ek) / u[0];
+      const T Tn = cool_T(u[0], Tin, dt, cool);
+      u[4] = ek + u[0] * Tn / gm1;
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) U[f * N + q] = u[f];
+    T w[5];
+    to_prim(u, gm1, w);
+    const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
+    s = (fmax(fmax(fabs(w[1]), fabs(w[2])), fabs(w[3])) + cs) * ihx;
+    const bool ok = (w[0] > T(0)) && (w[4] > T(0)) && isfinite(u[1]) && isfinite(u[2]) &&
+                    isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
+    if (!ok) bad = 1;
+  }
+  const T m = wave_max(s);
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(&clk->smax, pos_bits(fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]))));
+  if (bad) {
+    atomicAdd(&clk->bad_count, 1ull);
+    atomicMin(&clk->bad_first, (unsigned long long)q);
+  }
+}
+
+// reverse of the kick at fixed acceleration: lout from lin, and the
+// acceleration adjoint accb
+template <typename T>
+__global__ __launch_bounds__(256) void k_accel_kick_vjp(const T* __restrict__ U,
+                                                        const T* __restrict__ acc, long long N,
+                                                        T dt, const T* __restrict__ lin, T* lout,
+                                                        T* __restrict__ accb) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const T rho = U[q], Eb = lin[4 * N + q];
+  T rb = lin[q];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T a = acc[c * N + q];
+    const T mb = lin[(1 + c) * N + q];
+    rb += mb * a * dt;
+    lout[(1 + c) * N + q] = mb + Eb * a * dt;
+    accb[c * N + q] = mb * rho * dt + Eb * U[(1 + c) * N + q] * dt;
+  }
+  lout[q] = rb;
+  lout[4 * N + q] = Eb;
+}
+
+template <typename T>
+hipError_t fft3(char* ws, const MGLayout& L, typename CplxOf<T>::type* c, int inverse,
+                hipStream_t s) {
+  using C = typename CplxOf<T>::type;
+  const int n = L.lev[0].n;
+  int logn = 0;
+  while ((1 << logn) < n) ++logn;
+  const long long lines = (long long)n * n;
+  int lpb = (int)(FFT_LDS_BYTES / ((size_t)n * sizeof(C)));
+  if (lpb < 1) lpb = 1;
+  if (lpb > lines) lpb = (int)lines;
+  const unsigned grid = (unsigned)(lines / lpb);
+  const size_t lds = (size_t)lpb * n * sizeof(C);
+  const C* tw = P<C>(ws, L.fft_tw);
+  hipLaunchKernelGGL((k_fft_lines<T, 0>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
+                     lpb, inverse);
+  hipLaunchKernelGGL((k_fft_lines<T, 1>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
+                     lpb, inverse);
+  hipLaunchKernelGGL((k_fft_lines<T, 2>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
+                     lpb, inverse);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fft_size_ok(int n) { return n >= 2 && n <= 1024 && (n & (n - 1)) == 0; }
+
+size_t fft_layout(int n, size_t off, size_t es, MGLayout& L) {
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t N = (size_t)n * n * n;
+  L.fft = 1;
+  L.fft_c0 = take(2 * N * es);
+  L.fft_c1 = take(2 * N * es);
+  L.fft_tw = take((size_t)(n / 2 > 0 ? n / 2 : 1) * 2 * es);
+  L.fft_acc = take(3 * N * es);
+  return off;
+}
+
+// From F = 4 pi G (rho - <rho>) on level 0: the potential into
+// lev[0].phi[cur0] and the acceleration into fft_acc
+template <typename T>
+hipError_t fft_poisson(char* ws, MGLayout& L, double h, hipStream_t s) {
+  using C = typename CplxOf<T>::type;
+  const MGLevel& f = L.lev[0];
+  const int n = f.n;
+  const long long N = (long long)n * n * n;
+  const double tk = 2.0 * M_PI / ((double)n * h);
+  C* c0 = P<C>(ws, L.fft_c0);
+  C* c1 = P<C>(ws, L.fft_c1);
+  T* acc = P<T>(ws, L.fft_acc);
+  hipLaunchKernelGGL((k_fft_twiddles<T>), dim3(nblk(n / 2 > 0 ? n / 2 : 1)), dim3(256), 0, s,
+                     P<C>(ws, L.fft_tw), n);
+  hipLaunchKernelGGL((k_fft_pack<T>), dim3(nblk(N)), dim3(256), 0, s, c0, P<T>(ws, f.F), N);
+  hipError_t e = fft3<T>(ws, L, c0, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_phi<T>), dim3(nblk(N)), dim3(256), 0, s, c0, n, tk);
+  for (int a = 0; a < 3; ++a) {
+    if (a == 0) hipLaunchKernelGGL((k_fft_grad<T, 0>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
+    if (a == 1) hipLaunchKernelGGL((k_fft_grad<T, 1>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
+    if (a == 2) hipLaunchKernelGGL((k_fft_grad<T, 2>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
+    e = fft3<T>(ws, L, c1, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fft_real<T>), dim3(nblk(N)), dim3(256), 0, s, c1, acc + a * N, N);
+  }
+  e = fft3<T>(ws, L, c0, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_real<T>), dim3(nblk(N)), dim3(256), 0, s, c0,
+                     P<T>(ws, f.phi[L.cur0]), N);
+  return hipGetLastError();
+}
+
+// kick (+ cooling if `cool`), CFL and health check with the acceleration of
+// the last fft_poisson
+template <typename T>
+hipError_t fft_sources(char* ws, const MGLayout& L, const mh_grid_desc& g, bool cool,
+                       const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s) {
+  const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+  const T* acc = P<T>(ws, L.fft_acc);
+  if (cool)
+    hipLaunchKernelGGL((k_accel_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U, acc, N,
+                       (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk);
+  else
+    hipLaunchKernelGGL((k_accel_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U, acc, N,
+                       (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk);
+  return hipGetLastError();
+}
+
+// reverse of the spectral gravity kick at the state Ub the kick acted on
+// (whose acceleration the last fft_poisson left in fft_acc): lout from lin,
+// then lout_rho += (d a / d rho)^T accb
+template <typename T>
+hipError_t fft_gravity_vjp(char* ws, MGLayout& L, double h, double G, const T* Ub, T dt,
+                           const T* lin, T* lout, T* accb, hipStream_t s) {
+  using C = typename CplxOf<T>::type;
+  const int n = L.lev[0].n;
+  const long long N = (long long)n * n * n;
+  const double tk = 2.0 * M_PI / ((double)n * h);
+  const double fourpiG = 4.0 * M_PI * G;
+  C* c0 = P<C>(ws, L.fft_c0);
+  C* c1 = P<C>(ws, L.fft_c1);
+  hipLaunchKernelGGL((k_accel_kick_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, Ub,
+                     P<T>(ws, L.fft_acc), N, dt, lin, lout, accb);
+  hipLaunchKernelGGL((k_fft_twiddles<T>), dim3(nblk(n / 2 > 0 ? n / 2 : 1)), dim3(256), 0, s,
+                     P<C>(ws, L.fft_tw), n);
+  for (int a = 0; a < 3; ++a) {
+    hipLaunchKernelGGL((k_fft_pack<T>), dim3(nblk(N)), dim3(256), 0, s, c1, accb + a * N, N);
+    hipError_t e = fft3<T>(ws, L, c1, 0, s);
+    if (e != hipSuccess) return e;
+    if (a == 0)
+      hipLaunchKernelGGL((k_fft_adj_accum<T, 0>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
+                         fourpiG, 1);
+    if (a == 1)
+      hipLaunchKernelGGL((k_fft_adj_accum<T, 1>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
+                         fourpiG, 0);
+    if (a == 2)
+      hipLaunchKernelGGL((k_fft_adj_accum<T, 2>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
+                         fourpiG, 0);
+  }
+  hipError_t e = fft3<T>(ws, L, c0, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_real_add<T>), dim3(nblk(N)), dim3(256), 0, s, c0, lout, N);
+  return hipGetLastError();
+}
+
+#define FFT_INSTANTIATE(T)                                                                     \
+  template hipError_t fft_poisson<T>(char*, MGLayout&, double, hipStream_t);                  \
+  template hipError_t fft_sources<T>(char*, const MGLayout&, const mh_grid_desc&, bool,       \
+                                     const CoolParams<T>&, T*, DevClock*, hipStream_t);       \
+  template hipError_t fft_gravity_vjp<T>(char*, MGLayout&, double, double, const T*, T,       \
+                                         const T*, T*, T*, hipStream_t);
+FFT_INSTANTIATE(float)
+FFT_INSTANTIATE(double)
+#undef FFT_INSTANTIATE
+
+}  // namespace mh

@@ -43,6 +43,10 @@ struct MGLayout {
   size_t partial = 0;  // MG_PARTIALS doubles
   int cur0 = 0;        // which fine-level phi buffer holds the solution
   MGGraphCache* graphs = nullptr;  // not owned; null: launch kernel by kernel
+  // spectral solver (grav_solver = MH_GRAV_FFT): level 0 only, plus two
+  // complex n^3 work arrays, the twiddles and the acceleration [3][n^3]
+  int fft = 0;
+  size_t fft_c0 = 0, fft_c1 = 0, fft_tw = 0, fft_acc = 0;
 };
 
 mh_status mg_validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string& err);
@@ -50,6 +54,18 @@ size_t mg_layout(const mh_grid_desc* g, const mh_physics_desc* p, size_t off, si
                  MGLayout& L);
 hipError_t mg_init(char* ws, const MGLayout& L, const mh_grid_desc* g, hipStream_t s);
 size_t mg_phi_offset(const MGLayout& L);
+
+// spectral gravity (fft_kernels.hip)
+bool fft_size_ok(int n);
+size_t fft_layout(int n, size_t off, size_t es, MGLayout& L);
+template <typename T>
+hipError_t fft_poisson(char* ws, MGLayout& L, double h, hipStream_t s);
+template <typename T>
+hipError_t fft_sources(char* ws, const MGLayout& L, const mh_grid_desc& g, bool cool,
+                       const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s);
+template <typename T>
+hipError_t fft_gravity_vjp(char* ws, MGLayout& L, double h, double G, const T* Ub, T dt,
+                           const T* lin, T* lout, T* accb, hipStream_t s);
 
 // Solves lap(phi) = 4 pi G (rho - <rho>) for the density of U (warm start from
 // the previous solution), then applies the gravity kick, cooling (if on), the

@@ -621,6 +621,13 @@ mh_status mg_validate(const mh_grid_desc* g, const mh_physics_desc* p, std::stri
     err = "unknown multigrid smoother";
     return MH_E_UNSUPPORTED;
   }
+  if (p->grav_solver == MH_GRAV_FFT) {
+    if (!fft_size_ok(g->n[0])) {
+      err = "the spectral gravity solver needs a power-of-two n <= 1024";
+      return MH_E_SHAPE;
+    }
+    return MH_OK;
+  }
   if (p->grav_solver != MH_GRAV_MG) {
     err = "unknown gravity solver";
     return MH_E_UNSUPPORTED;
@@ -653,6 +660,17 @@ size_t mg_layout(const mh_grid_desc* g, const mh_physics_desc* p, size_t off, si
   L.partial = take(MG_PARTIALS * sizeof(double));
   int n = g->n[0];
   double h = g->h[0];
+  if (p->grav_solver == MH_GRAV_FFT) {
+    MGLevel& lv = L.lev[L.nlev++];
+    const size_t bytes = (size_t)n * n * n * es;
+    lv.n = n;
+    lv.h = h;
+    lv.phi[0] = take(bytes);
+    lv.phi[1] = take(bytes);
+    lv.F = take(bytes);
+    lv.r = take(bytes);
+    return fft_layout(n, off, es, L);
+  }
   for (;;) {
     MGLevel& lv = L.lev[L.nlev++];
     const size_t bytes = (size_t)n * n * n * es;
@@ -771,6 +789,13 @@ hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* c
   const int n = f.n;
   const long long N = (long long)n * n * n;
   double* partial = P<double>(ws, L.partial);
+  if (L.fft) {
+    // the spectral solve: exact for the spectral operator, no cycles
+    MG_CHECK(fft_poisson<T>(ws, L, f.h, s));
+    hipLaunchKernelGGL(k_set_cycles, dim3(1), dim3(64), 0, s, clk, 0);
+    if (cycles_out) *cycles_out = 0;
+    return hipGetLastError();
+  }
   MG_CHECK(sum_to(P<T>(ws, f.F), N, true, partial, 1.0, &clk->mg_fnorm2, s));
   MG_CHECK(remove_mean(P<T>(ws, f.phi[L.cur0]), N, partial, &clk->mean, s));
   int cycles = 0;
@@ -800,6 +825,7 @@ hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const m
   // F = 4 pi G (rho - <rho>), solve from the previous potential
   MG_CHECK(mg_set_rhs<T>(ws, L, U, 4.0 * M_PI * p.grav_G, clk, s));
   MG_CHECK(mg_solve<T>(ws, L, p, clk, nullptr, s));
+  if (L.fft) return fft_sources<T>(ws, L, g, (p.flags & MH_SRC_COOLING) != 0, cp, U, clk, s);
   const T i2h = (T)(1.0 / (2.0 * f.h));
   if (p.flags & MH_SRC_COOLING)
     hipLaunchKernelGGL((k_grav_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U,
@@ -818,6 +844,7 @@ hipError_t mg_kick(char* ws, MGLayout& L, const mh_grid_desc& g, T* U, DevClock*
   MGLevel& f = L.lev[0];
   const long long N = (long long)f.n * f.n * f.n;
   CoolParams<T> none{};
+  if (L.fft) return fft_sources<T>(ws, L, g, false, none, U, clk, s);
   hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
                      P<T>(ws, f.phi[L.cur0]), f.n, (T)(1.0 / (2.0 * f.h)), (T)g.gamma,
                      (T)(1.0 / f.h), none, clk);

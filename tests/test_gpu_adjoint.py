@@ -130,6 +130,18 @@ def test_adjoint_gravity_wcycle_rbgs(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_gravity_spectral(dtype):
+    """Reverse of the spectral gravity kick (Sec. 6.1's adjoint) with cooling."""
+    n = 16
+    U0 = wl.grf_density_state(n, seed=5)
+    U0[1:4] += 0.05 * np.random.default_rng(6).standard_normal((3, n, n, n)) * U0[0]
+    got, ref = gpu_vs_oracle_adjoint((n, n, n), (1 / n,) * 3, U0, dtype,
+                                     flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING,
+                                     grav_G=wl.JEANS_G, grav_solver=oracle.GRAV_FFT)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_gravity_cooling(dtype):
     n = 16
     U0 = wl.grf_density_state(n, seed=5)

@@ -70,6 +70,9 @@ def test_workspace_size_of_valid_grids():
      mh.E_UNSUPPORTED),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "grav_solver", 4)),
      mh.E_UNSUPPORTED),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "grav_solver", mh.GRAV_FFT),
+                   g.n.__setitem__(0, 12), g.n.__setitem__(1, 12), g.n.__setitem__(2, 12)),
+     mh.E_SHAPE),
 ])
 def test_validation_rejects(mutate, status):
     g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f64")
