@@ -351,6 +351,7 @@ static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) 
   a.rs = g.riemann;
   a.ca = T(0.5);
   a.cb = T(0.5);
+  a.epilogue = (p.flags & MH_SRC_GRAVITY) ? 0 : 1;
   if (p.flags & MH_SRC_FORCING) {
     a.ou_rows = ou_rows;
     for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);

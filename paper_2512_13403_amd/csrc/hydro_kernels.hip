@@ -471,6 +471,8 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       if (inside) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
+      }
+      if (inside && a.epilogue) {
         // CFL signal speed of the new state and the health check
         T wn[5] = {un[0], vx, vy, vz, pn};
         const T cs = sound_speed(gamma * pn, un[0]);
@@ -500,7 +502,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
     }
   }
 
-  if (STAGE == 2) {
+  if (STAGE == 2 && a.epilogue) {
     T m = wave_max(smax);
     if ((tid & 63) == 0) sRed[tid >> 6] = m;
     __syncthreads();

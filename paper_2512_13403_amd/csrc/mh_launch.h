@@ -31,6 +31,8 @@ struct StageArgs {
   int zc, nbx, nby, nbz, nb_per_xcd;
   int lim, rs;  // limiter and Riemann solver (read by the run-time-scheme kernel)
   T ca, cb;     // stages 2 and 3: out = ca U^n + cb (uin + dt L(uin))
+  int epilogue; // stage 2: reduce the CFL speed and check health (0 when a
+                // sources kernel follows and does both on the final state)
 };
 
 struct OUArgs {
