@@ -34,6 +34,9 @@ RK_SSP2, RK_SSP3, RK_EULER = 0, 1, 2
 MG_V, MG_W = 0, 1
 SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
 GRAV_MG, GRAV_FFT = 0, 1
+COOL_EXACT2, COOL_TABLE = 0, 1
+COOLINT_TRAPEZOID, COOLINT_SUBCYCLE, COOLINT_AUTO = 0, 1, 2
+COOL_TABMAX = 64
 SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
 OU_MAXMODES = 64
 
@@ -72,7 +75,20 @@ class Config(ctypes.Structure):
         ("mg_cycle", ctypes.c_int32),
         ("mg_smoother", ctypes.c_int32),
         ("grav_solver", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("cool_model", ctypes.c_int32),
+        ("cool_integrator", ctypes.c_int32),
+        ("cool_nsub_max", ctypes.c_int32),
+        ("cool_ntab", ctypes.c_int32),
+        ("pad2_", ctypes.c_int32),
+        ("cool_frac", ctypes.c_double),
+        ("cool_ccool", ctypes.c_double),
+        ("cool_L1", ctypes.c_double),
+        ("cool_a1", ctypes.c_double),
+        ("cool_L2", ctypes.c_double),
+        ("cool_a2", ctypes.c_double),
+        ("cool_heat", ctypes.c_double),
+        ("cool_logT", ctypes.c_double * 64),
+        ("cool_logL", ctypes.c_double * 64),
     ]
 
 
@@ -97,6 +113,11 @@ def lib():
             "or_rk2": (None, [cp, dp, ctypes.c_double]),
             "or_euler": (None, [cp, dp, ctypes.c_double]),
             "or_ssprk3": (None, [cp, dp, ctypes.c_double]),
+            "or_cool_lambda": (ctypes.c_double, [cp, ctypes.c_double]),
+            "or_cool_edot": (ctypes.c_double, [cp, ctypes.c_double, ctypes.c_double]),
+            "or_cool_eth_step": (ctypes.c_double, [cp, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_double]),
+            "or_cool_dt_limit": (ctypes.c_double, [cp, dp]),
             "or_integrate": (None, [cp, dp, ctypes.c_double]),
             "or_cool_temperature": (ctypes.c_double, [ctypes.c_double] * 8),
             "or_cool": (None, [cp, dp, ctypes.c_double]),
@@ -154,7 +175,9 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
                 ou_arms=1.0, ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0, ou_every=1, grav_G=0.0,
                 mg_pre=2, mg_post=2, mg_max_cycles=20, mg_coarsest=4, mg_tol=1e-10,
                 mg_coarse_sweeps=200, integrator=RK_SSP2, mg_cycle=MG_V, mg_smoother=SMOOTH_JACOBI,
-                grav_solver=GRAV_MG) -> Config:
+                grav_solver=GRAV_MG, cool_model=COOL_EXACT2, cool_integrator=COOLINT_TRAPEZOID,
+                cool_nsub_max=1000, cool_frac=0.1, cool_ccool=0.0, cool_ki=(0.0, 0.0, 0.0, 0.0),
+                cool_heat=0.0, cool_table=None) -> Config:
     """shape = (nz, ny, nx) of the state arrays; h = (hx, hy, hz); bc per (x, y, z)."""
     nz, ny, nx = shape
     c = Config()
@@ -170,6 +193,15 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
     c.mg_tol, c.mg_coarse_sweeps = mg_tol, mg_coarse_sweeps
     c.integrator = integrator
     c.mg_cycle, c.mg_smoother, c.grav_solver = mg_cycle, mg_smoother, grav_solver
+    c.cool_model, c.cool_integrator, c.cool_nsub_max = cool_model, cool_integrator, cool_nsub_max
+    c.cool_frac, c.cool_ccool, c.cool_heat = cool_frac, cool_ccool, cool_heat
+    c.cool_L1, c.cool_a1, c.cool_L2, c.cool_a2 = cool_ki
+    if cool_table is not None:
+        logT, logL = (np.asarray(a, dtype=np.float64) for a in cool_table)
+        assert logT.shape == logL.shape and 2 <= len(logT) <= COOL_TABMAX
+        c.cool_ntab = len(logT)
+        c.cool_logT[:len(logT)] = list(logT)
+        c.cool_logL[:len(logL)] = list(logL)
     return c
 
 
@@ -223,6 +255,24 @@ def integrate(c, U, dt):
     U = np.array(U, dtype=np.float64, order="C", copy=True)
     lib().or_integrate(ctypes.byref(c), _dp(U), dt)
     return U
+
+
+def cool_lambda(c, T):
+    return lib().or_cool_lambda(ctypes.byref(c), T)
+
+
+def cool_edot(c, rho, Eth):
+    return lib().or_cool_edot(ctypes.byref(c), rho, Eth)
+
+
+def cool_eth_step(c, rho, Eth, dt):
+    """One step of the tabulated model's integrator (oracle_cool.c)."""
+    return lib().or_cool_eth_step(ctypes.byref(c), rho, Eth, dt)
+
+
+def cool_dt_limit(c, U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return lib().or_cool_dt_limit(ctypes.byref(c), _dp(U))
 
 
 def cool_temperature(rho, T, dt, gamma, L0, Tc, Ts, Tfloor):

@@ -7,7 +7,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle.c", "oracle_mg.c", "oracle_adjoint.c", "oracle_fft.c"]
+SOURCES = ["oracle.c", "oracle_mg.c", "oracle_adjoint.c", "oracle_fft.c", "oracle_cool.c"]
 
 
 def build(verbose: bool = False) -> str:

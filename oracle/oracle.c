@@ -106,7 +106,13 @@ double or_cfl_dt(const or_config *c, const double *U) {
       if (s > smax) smax = s;
     }
   }
-  return c->cfl / smax;
+  double dt = c->cfl / smax;
+  /* the cooling-time limit of Sec. 4.3 (oracle_cool.c), when c_cool > 0 */
+  if ((c->flags & OR_SRC_COOLING) && c->cool_ccool > 0.0) {
+    double dc = or_cool_dt_limit(c, U);
+    if (dc < dt) dt = dc;
+  }
+  return dt;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -441,6 +447,11 @@ void or_cool(const or_config *c, double *U, double dt) {
     double rho = U[q];
     double ek = 0.5 * (U[N + q] * U[N + q] + U[2 * N + q] * U[2 * N + q] +
                        U[3 * N + q] * U[3 * N + q]) / rho;
+    if (c->cool_model == OR_COOL_TABLE) {
+      /* the paper's tabulated model and integrators (oracle_cool.c) */
+      U[4 * N + q] = ek + or_cool_eth_step(c, rho, U[4 * N + q] - ek, dt);
+      continue;
+    }
     double T = (g - 1.0) * (U[4 * N + q] - ek) / rho;
     double Tn = or_cool_temperature(rho, T, dt, g, c->cool_lambda0, c->cool_tc,
                                     c->cool_ts, c->cool_tfloor);

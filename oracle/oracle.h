@@ -15,6 +15,9 @@ enum { OR_RK_SSP2 = 0, OR_RK_SSP3 = 1, OR_RK_EULER = 2 };
 enum { OR_MG_V = 0, OR_MG_W = 1 };
 enum { OR_SMOOTH_JACOBI = 0, OR_SMOOTH_RBGS = 1 };
 enum { OR_GRAV_MG = 0, OR_GRAV_FFT = 1 };
+enum { OR_COOL_EXACT2 = 0, OR_COOL_TABLE = 1 };
+enum { OR_COOLINT_TRAPEZOID = 0, OR_COOLINT_SUBCYCLE = 1, OR_COOLINT_AUTO = 2 };
+#define OR_COOL_TABMAX 64
 enum { OR_SRC_COOLING = 1u, OR_SRC_FORCING = 2u, OR_SRC_GRAVITY = 4u };
 #define OR_OU_MAXMODES 64
 
@@ -41,7 +44,16 @@ typedef struct {
   int32_t mg_cycle;    /* OR_MG_V or OR_MG_W */
   int32_t mg_smoother; /* OR_SMOOTH_* */
   int32_t grav_solver; /* OR_GRAV_MG or OR_GRAV_FFT */
-  int32_t pad_;
+  int32_t cool_model;  /* OR_COOL_EXACT2 or OR_COOL_TABLE */
+  int32_t cool_integrator; /* OR_COOLINT_* (tabulated model) */
+  int32_t cool_nsub_max;   /* most substeps of the subcycled update */
+  int32_t cool_ntab;       /* points of the CIE table */
+  int32_t pad2_;
+  double cool_frac;  /* largest fractional change of E_th per substep */
+  double cool_ccool; /* c_cool of the cooling-time step limit (0: off) */
+  double cool_L1, cool_a1, cool_L2, cool_a2; /* low-T branch L1 T^a1 + L2 T^a2 */
+  double cool_heat;  /* heating rate Gamma_0 below cool_tc */
+  double cool_logT[OR_COOL_TABMAX], cool_logL[OR_COOL_TABMAX]; /* log10 T, log10 Lambda */
 } or_config;
 
 void or_primitives(const or_config *c, const double *U, double *W);
@@ -55,6 +67,12 @@ void or_integrate(const or_config *c, double *U, double dt);
 double or_cool_temperature(double rho, double T, double dt, double gamma,
                            double L0, double Tc, double Ts, double Tfloor);
 void or_cool(const or_config *c, double *U, double dt);
+
+/* the tabulated heating/cooling model (oracle_cool.c) */
+double or_cool_lambda(const or_config *c, double T);
+double or_cool_edot(const or_config *c, double rho, double Eth);
+double or_cool_eth_step(const or_config *c, double rho, double Eth, double dt);
+double or_cool_dt_limit(const or_config *c, const double *U);
 
 void or_ou_gauss(uint64_t seed, int64_t group, int mode, int comp, double out[2]);
 int or_ou_modes(double kmin, double kmax, int32_t *nvec);

@@ -193,3 +193,112 @@ def test_step_source_order_forcing_then_cooling():
     V = oracle.cool(c, V, dt)
     assert np.array_equal(sim.U, V)
     assert np.array_equal(sim.ahat, a1)
+
+
+# ---------------------------------------------------------------- tabulated model (Sec. 4)
+
+def table_cfg(**kw):
+    base = dict(cool_model=oracle.COOL_TABLE, cool_table=wl.synthetic_cie_table(),
+                **wl.COOLING_TABLE_MODEL)
+    base.update(kw)
+    return oracle.make_config((2, 2, 2), (0.5,) * 3, flags=oracle.SRC_COOLING, **base)
+
+
+def test_table_interpolation_is_exact_for_a_power_law():
+    """log-log linear interpolation reproduces a pure power law between any
+    nodes, and is flat beyond the table's ends."""
+    A, b = 0.7, -0.6
+    logT = np.array([-2.0, -1.3, -0.2, 0.4, 1.5])
+    c = table_cfg(cool_table=(logT, np.log10(A) + b * logT))
+    for T in (0.01, 0.02, 0.31, 1.0, 2.5, 30.0):
+        assert oracle.cool_lambda(c, T) == pytest.approx(A * T ** b, rel=1e-13)
+    assert oracle.cool_lambda(c, 1e3) == pytest.approx(A * 10 ** (1.5 * b), rel=1e-13)
+
+
+def _run(c, rho, E0, t, nsteps):
+    E = E0
+    for _ in range(nsteps):
+        E = oracle.cool_eth_step(c, rho, E, t / nsteps)
+    return E
+
+
+def test_trapezoid_is_second_order_and_subcycling_first_order():
+    """Against the closed form for a linear curve Lambda = A T (no heating,
+    above tc), T(t) = T0 exp(-(gamma-1) rho A t): halving dt quarters the
+    trapezoid's error; doubling the substeps halves the subcycled update's
+    error (the fractional change per substep is constant, below the limiter's
+    bound)."""
+    A, rho, g = 0.5, 1.3, 5.0 / 3.0
+    logT = np.array([-2.0, 2.0])
+    kw = dict(cool_table=(logT, np.log10(A) + logT), cool_heat=0.0)
+    T0, t = 1.0, 0.4
+    k = (g - 1) * rho * A
+    E0 = rho * T0 / (g - 1)
+    Tex = T0 * math.exp(-k * t)
+    ct = table_cfg(cool_integrator=oracle.COOLINT_TRAPEZOID, **kw)
+    et = [abs(_run(ct, rho, E0, t, m) * (g - 1) / rho - Tex) for m in (8, 16, 32)]
+    assert 3.6 < et[0] / et[1] < 4.4 and 3.6 < et[1] / et[2] < 4.4, et
+    es = []
+    for nsub in (64, 128, 256):
+        # N = ceil(k t / f) = nsub
+        cs = table_cfg(cool_integrator=oracle.COOLINT_SUBCYCLE, cool_frac=k * t / (nsub - 0.5),
+                       cool_nsub_max=100000, **kw)
+        E = oracle.cool_eth_step(cs, rho, E0, t)
+        assert E == pytest.approx(E0 * (1 - k * t / nsub) ** nsub, rel=1e-12)
+        es.append(abs(E * (g - 1) / rho - Tex))
+    assert 1.8 < es[0] / es[1] < 2.2 and 1.8 < es[1] / es[2] < 2.2, es
+
+
+def test_heating_equilibrium_is_a_fixed_point():
+    """Below tc, where Gamma_0 = rho Lambda(T_eq), both integrators keep T_eq."""
+    from scipy.optimize import brentq
+
+    rho, g = 1.0, 5.0 / 3.0
+    c = table_cfg()
+    f = lambda T: oracle.cool_edot(c, rho, rho * T / (g - 1))
+    Teq = brentq(f, 1e-3, 9e-3, xtol=1e-15)
+    for integ in (oracle.COOLINT_TRAPEZOID, oracle.COOLINT_SUBCYCLE, oracle.COOLINT_AUTO):
+        ci = table_cfg(cool_integrator=integ)
+        E = rho * Teq / (g - 1)
+        assert oracle.cool_eth_step(ci, rho, E, 10.0) == pytest.approx(E, rel=1e-9)
+    # and it attracts: a perturbed cell relaxes towards it (relaxation rate
+    # about 12 here, so dt = 0.025 keeps the explicit update stable)
+    E1 = _run(table_cfg(), rho, 1.5 * rho * Teq / (g - 1), 50.0, 2000)
+    assert abs(E1 * (g - 1) / rho - Teq) < 1e-3 * Teq
+
+
+def test_floor_and_fractional_limiter():
+    rho, g = 50.0, 5.0 / 3.0
+    c = table_cfg(cool_integrator=oracle.COOLINT_SUBCYCLE, cool_nsub_max=4, cool_frac=0.1)
+    E0 = rho * 0.1 / (g - 1)
+    E1 = oracle.cool_eth_step(c, rho, E0, 1.0)
+    # four substeps, each at most a 10 % change
+    assert E1 >= E0 * 0.9 ** 4 * (1 - 1e-14)
+    cf = table_cfg(cool_integrator=oracle.COOLINT_TRAPEZOID, cool=(0.3, 1e-2, 1e-3, 0.05))
+    assert oracle.cool_eth_step(cf, rho, E0, 10.0) == pytest.approx(rho * 0.05 / (g - 1), rel=1e-14)
+
+
+def test_auto_integrator_picks_by_the_first_step_change():
+    rho, g = 1.0, 5.0 / 3.0
+    ca, ct, cs = (table_cfg(cool_integrator=m) for m in (oracle.COOLINT_AUTO,
+                                                          oracle.COOLINT_TRAPEZOID,
+                                                          oracle.COOLINT_SUBCYCLE))
+    E = rho * 0.15 / (g - 1)
+    small, large = 1e-4, 1.0  # |Edot| dt / E is about 0.002 and 20
+    assert oracle.cool_eth_step(ca, rho, E, small) == oracle.cool_eth_step(ct, rho, E, small)
+    assert oracle.cool_eth_step(ca, rho, E, large) == oracle.cool_eth_step(cs, rho, E, large)
+
+
+def test_cooling_time_step_limit():
+    """Sec. 4.3: dt <= c_cool min t_cool with t_cool = E_th / |rho Gamma -
+    rho^2 Lambda|; for a uniform state the closed form."""
+    n, rho, p, g = 4, 2.0, 0.3, 5.0 / 3.0
+    U = wl.rest_state((n, n, n), rho=rho, p=p, gamma=g)
+    c = oracle.make_config((n, n, n), (1 / n,) * 3, flags=oracle.SRC_COOLING, cool_ccool=0.2,
+                           cool_model=oracle.COOL_TABLE, cool_table=wl.synthetic_cie_table(),
+                           **wl.COOLING_TABLE_MODEL)
+    Eth = p / (g - 1)
+    tcool = Eth / abs(oracle.cool_edot(c, rho, Eth))
+    cs = math.sqrt(g * p / rho)
+    assert oracle.cfl_dt(c, U) == pytest.approx(min(0.4 / (n * cs), 0.2 * tcool), rel=1e-14)
+    assert 0.2 * tcool < 0.4 / (n * cs)

@@ -197,6 +197,23 @@ COOLING_CURVE = dict(lambda0=0.3, tc=1e-2, ts=1e-3, tfloor=1e-4)
 code units with T = P/rho (T = 1e-2 corresponds to 1e4 K at T[K] = 1e6 P/rho):
 Lambda = L0 (T/Tc)^(1/2) above Tc and L0 exp((T-Tc)/Ts) below; floor Tfloor."""
 
+def synthetic_cie_table():
+    """Synthetic stand-in for the tabulated CIE cooling curve of the paper's
+    model (its SD93 table is not available), in code units T = P/rho (T = 1e-2
+    is 1e4 K): 17 points log10 T = -2 .. 2, a peak of log10 Lambda near
+    log10 T = -0.8 (about 1.6e5 K), a decline above it and a T^(1/2) rise
+    above log10 T = 0.5.  Returns (log10 T, log10 Lambda)."""
+    x = np.linspace(-2.0, 2.0, 17)
+    y = (math.log10(0.3) + 1.0 * np.exp(-((x + 0.8) / 0.45) ** 2) - 0.3 * np.maximum(0.0, x + 0.8)
+         + 0.8 * np.maximum(0.0, x - 0.5))
+    return x, y
+
+
+COOLING_TABLE_MODEL = dict(cool_ki=(3000.0, 2.0, 0.003, 0.5), cool_heat=0.0272)
+"""Low-temperature branch L1 T^a1 + L2 T^a2 of the tabulated model and its
+heating rate Gamma_0 (code units): at rho = 1 heating balances cooling near
+T = 3e-3 (3000 K), so denser gas cools further (the two-phase medium)."""
+
 OU_DRIVE = dict(seed=0, tau=0.5, arms=1.0, zeta=1.0, kmin=1.0, kmax=2.0)
 """Solenoidal OU forcing on 1 <= |n| <= 2 with correlation time 0.5."""
 
