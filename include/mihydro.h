@@ -54,6 +54,9 @@ enum { MH_RK_SSP2 = 0, MH_RK_SSP3 = 1, MH_RK_EULER = 2 };
 enum { MH_MG_V = 0, MH_MG_W = 1 };
 enum { MH_SMOOTH_JACOBI = 0, MH_SMOOTH_RBGS = 1 };
 enum { MH_GRAV_MG = 0, MH_GRAV_FFT = 1 };
+enum { MH_COOL_EXACT2 = 0, MH_COOL_TABLE = 1 };
+enum { MH_COOLINT_TRAPEZOID = 0, MH_COOLINT_SUBCYCLE = 1, MH_COOLINT_AUTO = 2 };
+#define MH_COOL_TABMAX 64
 enum { MH_SRC_COOLING = 1u, MH_SRC_FORCING = 2u, MH_SRC_GRAVITY = 4u };
 enum { MH_HOST = 0, MH_DEVICE = 1 };
 
@@ -94,11 +97,23 @@ typedef struct mh_grid_desc {
 /* Source terms, applied after each Runge-Kutta update in the order forcing ->
  * gravity -> cooling, each on the state left by the previous one.
  * flags           OR of MH_SRC_*.
- * cool_*          cooling curve in code units with T = P/rho:
+ * cool_*          cooling in code units with T = P/rho.  cool_model
+ *                 MH_COOL_EXACT2 (the default): the synthetic two-branch curve
  *                 Lambda = lambda0 (T/tc)^(1/2) for T >= tc,
  *                 Lambda = lambda0 exp((T - tc)/ts) for T < tc;
  *                 dT/dt = -(gamma-1) rho Lambda(T) is integrated exactly over
  *                 dt, then T is floored at tfloor (Sec. 4 and 4.3).
+ *                 MH_COOL_TABLE: the paper's model (Sec. 4.1-4.3) with
+ *                 dE_th/dt = rho Gamma - rho^2 Lambda, Lambda = L1 T^a1 +
+ *                 L2 T^a2 and Gamma = heat below tc, Lambda from log-log
+ *                 interpolation of the cool_ntab (2..64) points (log10 T,
+ *                 log10 Lambda) at and above tc (flat beyond the ends), no
+ *                 heating; integrated by cool_integrator (trapezoid, subcycled
+ *                 with N = ceil(dt |Edot| / (frac E_th)) <= nsub_max
+ *                 substeps each changing E_th by at most frac, or auto:
+ *                 trapezoid when dt |Edot| <= frac E_th), E_th floored at
+ *                 rho tfloor/(gamma-1).  cool_ccool > 0 (tabulated model
+ *                 only) limits CFL steps to ccool min E_th/|Edot|.
  * ou_*            OU forcing (Sec. 3.1.1): seed of the counter-based noise,
  *                 correlation time tau, target rms acceleration arms,
  *                 solenoidal fraction zeta, forced band kmin <= |n| <= kmax
@@ -129,6 +144,13 @@ typedef struct mh_physics_desc {
   int32_t mg_cycle;
   int32_t mg_smoother;
   int32_t grav_solver;
+  int32_t cool_model;
+  int32_t cool_integrator;
+  int32_t cool_nsub_max;
+  int32_t cool_ntab;
+  double cool_frac, cool_ccool;
+  double cool_L1, cool_a1, cool_L2, cool_a2, cool_heat;
+  double cool_logT[MH_COOL_TABMAX], cool_logL[MH_COOL_TABMAX];
 } mh_physics_desc;
 
 typedef struct mh_ctx mh_ctx;
@@ -216,9 +238,10 @@ mh_status mh_get_potential(mh_ctx *ctx, void *phi, int where);
  *   intermediates and the scratch of the reverse sweep.  The context's own
  *   state, clock, OU amplitudes and potential are not touched.
  * Enqueued on the context stream; with gravity it synchronises once per
- * multigrid cycle.  Every grid, limiter and source the context accepts is
- * supported.  Errors: MH_E_INVALID (null pointer, or ou_ahat missing with
- * forcing on), MH_E_WORKSPACE, MH_E_DEVICE. */
+ * multigrid cycle.  Every grid, scheme, integrator and source the context
+ * accepts is supported except the tabulated cooling model (MH_E_UNSUPPORTED).
+ * Errors: MH_E_INVALID (null pointer, or ou_ahat missing with forcing on),
+ * MH_E_UNSUPPORTED, MH_E_WORKSPACE, MH_E_DEVICE. */
 mh_status mh_query_adjoint_workspace(mh_ctx *ctx, size_t *bytes);
 mh_status mh_adjoint_step(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace_bytes,
                           const void *U_n, double dt, int64_t step, const double *ou_ahat,

@@ -29,6 +29,9 @@ RK_SSP2, RK_SSP3, RK_EULER = 0, 1, 2
 MG_V, MG_W = 0, 1
 SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
 GRAV_MG, GRAV_FFT = 0, 1
+COOL_EXACT2, COOL_TABLE = 0, 1
+COOLINT_TRAPEZOID, COOLINT_SUBCYCLE, COOLINT_AUTO = 0, 1, 2
+COOL_TABMAX = 64
 SRC_COOLING, SRC_FORCING, SRC_GRAVITY = 1, 2, 4
 HOST, DEVICE = 0, 1
 
@@ -64,7 +67,13 @@ class PhysicsDesc(ctypes.Structure):
         ("mg_max_cycles", ctypes.c_int32), ("mg_coarsest", ctypes.c_int32),
         ("mg_tol", ctypes.c_double), ("mg_coarse_sweeps", ctypes.c_int32),
         ("mg_cycle", ctypes.c_int32), ("mg_smoother", ctypes.c_int32),
-        ("grav_solver", ctypes.c_int32),
+        ("grav_solver", ctypes.c_int32), ("cool_model", ctypes.c_int32),
+        ("cool_integrator", ctypes.c_int32), ("cool_nsub_max", ctypes.c_int32),
+        ("cool_ntab", ctypes.c_int32), ("cool_frac", ctypes.c_double),
+        ("cool_ccool", ctypes.c_double), ("cool_L1", ctypes.c_double),
+        ("cool_a1", ctypes.c_double), ("cool_L2", ctypes.c_double), ("cool_a2", ctypes.c_double),
+        ("cool_heat", ctypes.c_double), ("cool_logT", ctypes.c_double * 64),
+        ("cool_logL", ctypes.c_double * 64),
     ]
 
 
@@ -168,7 +177,10 @@ def physics_desc(flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, o
                  ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0, ou_every=1, grav_G=0.0, mg_pre=2,
                  mg_post=2, mg_max_cycles=20, mg_coarsest=4, mg_tol=1e-10,
                  mg_coarse_sweeps=200, mg_cycle=MG_V, mg_smoother=SMOOTH_JACOBI,
-                 grav_solver=GRAV_MG) -> PhysicsDesc:
+                 grav_solver=GRAV_MG, cool_model=COOL_EXACT2, cool_integrator=COOLINT_TRAPEZOID,
+                 cool_nsub_max=1000, cool_frac=0.1, cool_ccool=0.0,
+                 cool_ki=(0.0, 0.0, 0.0, 0.0), cool_heat=0.0, cool_table=None) -> PhysicsDesc:
+    """cool_table: (log10 T, log10 Lambda) arrays of the tabulated model."""
     p = PhysicsDesc()
     p.flags = flags
     p.cool_lambda0, p.cool_tc, p.cool_ts, p.cool_tfloor = cool
@@ -178,6 +190,16 @@ def physics_desc(flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, o
     p.mg_pre, p.mg_post, p.mg_max_cycles, p.mg_coarsest = mg_pre, mg_post, mg_max_cycles, mg_coarsest
     p.mg_tol, p.mg_coarse_sweeps = mg_tol, mg_coarse_sweeps
     p.mg_cycle, p.mg_smoother, p.grav_solver = mg_cycle, mg_smoother, grav_solver
+    p.cool_model, p.cool_integrator, p.cool_nsub_max = cool_model, cool_integrator, cool_nsub_max
+    p.cool_frac, p.cool_ccool, p.cool_heat = cool_frac, cool_ccool, cool_heat
+    p.cool_L1, p.cool_a1, p.cool_L2, p.cool_a2 = cool_ki
+    if cool_table is not None:
+        logT, logL = cool_table
+        if len(logT) != len(logL) or not 2 <= len(logT) <= COOL_TABMAX:
+            raise ValueError("cool_table needs 2..64 matching (log10 T, log10 Lambda) points")
+        p.cool_ntab = len(logT)
+        p.cool_logT[:len(logT)] = [float(v) for v in logT]
+        p.cool_logL[:len(logL)] = [float(v) for v in logL]
     return p
 
 

@@ -9,7 +9,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmihydro.so")
 SOURCES = ["api.hip", "hydro_kernels.hip", "step_kernels.hip", "mg_kernels.hip",
-           "fft_kernels.hip", "adjoint_kernels.hip", "corrector_kernels.hip", "corrector_api.hip"]
+           "fft_kernels.hip", "cool_kernels.hip", "adjoint_kernels.hip", "corrector_kernels.hip",
+           "corrector_api.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed FP32 instructions anywhere (v_pk_*_f32)

@@ -23,7 +23,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-  size_t U = 0, U1 = 0, U2 = 0, clk = 0, dtlog = 0, ou_n = 0, ou_ahat = 0, ou_coef = 0, ou_rows = 0;
+  size_t U = 0, U1 = 0, U2 = 0, cool_tab = 0, clk = 0, dtlog = 0, ou_n = 0, ou_ahat = 0, ou_coef = 0, ou_rows = 0;
   size_t tab[3] = {0, 0, 0};
   MGLayout mg;
   size_t total = 0;
@@ -80,6 +80,28 @@ mh_status validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string&
     if (!(p->cool_lambda0 >= 0.0) || !(p->cool_tc > 0.0) || !(p->cool_ts > 0.0) ||
         !(p->cool_tfloor >= 0.0))
       return fail(MH_E_INVALID, "cooling constants must be positive");
+    if (p->cool_model != MH_COOL_EXACT2 && p->cool_model != MH_COOL_TABLE)
+      return fail(MH_E_UNSUPPORTED, "unknown cooling model");
+    if (!(p->cool_ccool >= 0.0)) return fail(MH_E_INVALID, "cool_ccool must be >= 0");
+    if (p->cool_model == MH_COOL_EXACT2 && p->cool_ccool > 0.0)
+      return fail(MH_E_UNSUPPORTED, "the cooling-time step limit needs the tabulated model");
+    if (p->cool_model == MH_COOL_TABLE) {
+      if (p->cool_integrator < MH_COOLINT_TRAPEZOID || p->cool_integrator > MH_COOLINT_AUTO)
+        return fail(MH_E_UNSUPPORTED, "unknown cooling integrator");
+      if (p->cool_ntab < 2 || p->cool_ntab > MH_COOL_TABMAX)
+        return fail(MH_E_INVALID, "the cooling table needs 2..64 points");
+      for (int i = 0; i < p->cool_ntab; ++i)
+        if (!std::isfinite(p->cool_logT[i]) || !std::isfinite(p->cool_logL[i]) ||
+            (i > 0 && !(p->cool_logT[i] > p->cool_logT[i - 1])))
+          return fail(MH_E_INVALID, "cooling table: finite values, increasing log10 T");
+      if (!(p->cool_tfloor > 0.0) || !(p->cool_frac > 0.0 && p->cool_frac <= 1.0) ||
+          p->cool_nsub_max < 1 || p->cool_nsub_max > 1000000 || !(p->cool_heat >= 0.0) ||
+          !std::isfinite(p->cool_L1) || !std::isfinite(p->cool_a1) ||
+          !std::isfinite(p->cool_L2) || !std::isfinite(p->cool_a2))
+        return fail(MH_E_INVALID,
+                    "tabulated cooling: tfloor > 0, 0 < frac <= 1, 1 <= nsub_max <= 1e6, "
+                    "heat >= 0, finite L1, a1, L2, a2");
+    }
   }
   int nm = 0;
   if (p->flags & MH_SRC_FORCING) {
@@ -114,6 +136,8 @@ Layout make_layout(const mh_grid_desc* g, const mh_physics_desc* p, int nmodes) 
   L.U = take(5 * N * es);
   L.U1 = take(5 * N * es);
   if (g->integrator == MH_RK_SSP3) L.U2 = take(5 * N * es);
+  if ((p->flags & MH_SRC_COOLING) && p->cool_model == MH_COOL_TABLE)
+    L.cool_tab = take(2 * MH_COOL_TABMAX * es);
   L.clk = take(sizeof(DevClock));
   L.dtlog = take(DTLOG_CAP * sizeof(double));
   if (p->flags & MH_SRC_FORCING) {
@@ -157,6 +181,29 @@ struct mh_ctx {
   long long cells() const { return (long long)g.n[0] * g.n[1] * g.n[2]; }
   size_t esize() const { return g.dtype == MH_F64 ? 8 : 4; }
   DevClock* clk() const { return at<DevClock>(L.clk); }
+  // the tabulated cooling model runs as its own kernel at the end of a step
+  bool cool_table() const {
+    return (p.flags & MH_SRC_COOLING) && p.cool_model == MH_COOL_TABLE;
+  }
+  template <typename T>
+  CoolTable<T> cool_table_args() const {
+    CoolTable<T> t{};
+    t.logT = at<T>(L.cool_tab);
+    t.logL = at<T>(L.cool_tab) + MH_COOL_TABMAX;
+    t.ntab = p.cool_ntab;
+    t.integ = p.cool_integrator;
+    t.nsub_max = p.cool_nsub_max;
+    t.rate = p.cool_ccool > 0.0;
+    t.tc = (T)p.cool_tc;
+    t.tfloor = (T)p.cool_tfloor;
+    t.L1 = (T)p.cool_L1;
+    t.a1 = (T)p.cool_a1;
+    t.L2 = (T)p.cool_L2;
+    t.a2 = (T)p.cool_a2;
+    t.heat = (T)p.cool_heat;
+    t.frac = (T)p.cool_frac;
+    return t;
+  }
 };
 
 static constexpr size_t MAX_TIMED = 65536;
@@ -214,6 +261,16 @@ extern "C" mh_status mh_query_workspace(const mh_grid_desc* grid, const mh_physi
 template <typename T>
 static mh_status upload_tables(mh_ctx* c) {
   const mh_physics_desc& p = c->p;
+  if (c->cool_table()) {
+    std::vector<T> tab(2 * MH_COOL_TABMAX, T(0));
+    for (int i = 0; i < p.cool_ntab; ++i) {
+      tab[i] = (T)p.cool_logT[i];
+      tab[MH_COOL_TABMAX + i] = (T)p.cool_logL[i];
+    }
+    MH_HIP(c, hipMemcpyAsync(c->ws + c->L.cool_tab, tab.data(), tab.size() * sizeof(T),
+                             hipMemcpyHostToDevice, c->stream));
+    MH_HIP(c, hipStreamSynchronize(c->stream));
+  }
   if (!(p.flags & MH_SRC_FORCING)) return MH_OK;
   std::vector<int> nv;
   ou_enumerate(p.ou_kmin, p.ou_kmax, nv);
@@ -351,7 +408,7 @@ static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) 
   a.rs = g.riemann;
   a.ca = T(0.5);
   a.cb = T(0.5);
-  a.epilogue = (p.flags & MH_SRC_GRAVITY) ? 0 : 1;
+  a.epilogue = ((p.flags & MH_SRC_GRAVITY) || c->cool_table()) ? 0 : 1;
   if (p.flags & MH_SRC_FORCING) {
     a.ou_rows = ou_rows;
     for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
@@ -369,9 +426,12 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
   const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
   const bool force = (p.flags & MH_SRC_FORCING) != 0;
   const bool grav = (p.flags & MH_SRC_GRAVITY) != 0;
-  const bool cool = (p.flags & MH_SRC_COOLING) != 0;
+  const bool table = c->cool_table();
+  // the exact two-branch cooling is fused into the last stage kernel
+  const bool cool = (p.flags & MH_SRC_COOLING) != 0 && !table;
   T* U = c->at<T>(c->L.U);
   T* U1 = c->at<T>(c->L.U1);
+  const CoolTable<T> ctab = table ? c->cool_table_args<T>() : CoolTable<T>{};
   DevClock* clk = c->clk();
   StageArgs<T> a = base_stage_args<T>(c, clk, c->at<T>(c->L.ou_rows));
 
@@ -381,6 +441,7 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
   pa.f64 = g.dtype == MH_F64;
   pa.dt_fixed = dt;
   pa.cfl = g.cfl;
+  pa.ccool = table ? p.cool_ccool : 0.0;
   pa.t_stop = t_stop;
   pa.forcing = force;
   if (force) pa.ou = ou_args(c);
@@ -390,6 +451,8 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
     if (!c->smax_valid && !(dt > 0.0)) {
       const long tk = time_begin(c, MH_TIME_OTHER);
       MH_HIP(c, launch_smax<T>(U, geom, (T)g.gamma, ih, clk, c->stream));
+      if (table && ctab.rate)
+        MH_HIP(c, launch_cool_rate<T>(U, geom, (T)g.gamma, ctab, clk, c->stream));
       time_end(c, tk);
       c->smax_valid = true;
     }
@@ -453,7 +516,13 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
     a.cb = T(0.5);
     if (grav) {
       tk = time_begin(c, MH_TIME_OTHER);
-      MH_HIP(c, mg_gravity_step<T>(c->ws, c->L.mg, c->g, c->p, a.cool, U, clk, c->stream));
+      MH_HIP(c, mg_gravity_step<T>(c->ws, c->L.mg, c->g, c->p, a.cool, U, clk, !table,
+                                   c->stream));
+      time_end(c, tk);
+    }
+    if (table) {
+      tk = time_begin(c, MH_TIME_OTHER);
+      MH_HIP(c, launch_cool_table<T>(U, geom, (T)g.gamma, ih, ctab, clk, c->stream));
       time_end(c, tk);
     }
     c->smax_valid = true;
@@ -763,6 +832,10 @@ extern "C" mh_status mh_adjoint_step(mh_ctx* c, void* adj_workspace, size_t adj_
   if ((c->p.flags & MH_SRC_FORCING) && !ou_ahat)
     return set_err(c, MH_E_INVALID, "mh_adjoint_step: forcing is on but ou_ahat is NULL");
   if (!(dt >= 0.0) || step < 0) return set_err(c, MH_E_INVALID, "mh_adjoint_step: bad dt or step");
+  if (c->cool_table())
+    return set_err(c, MH_E_UNSUPPORTED,
+                   "mh_adjoint_step: the tabulated cooling model has no adjoint; use the exact "
+                   "two-branch model");
   AdjLayout A = make_adj_layout(c->g, c->p);
   A.mg.graphs = &c->adj_graphs;
   if (!adj_workspace || adj_workspace_bytes < A.total || ((uintptr_t)adj_workspace % ALIGN) != 0)

@@ -1,0 +1,172 @@
+// cool_kernels.hip -- the paper's tabulated heating/cooling model on the
+// device (arXiv 2512.13403, Sec. 4.1-4.3), the optional replacement of the
+// exact two-branch cooling fused into the last stage kernel.
+//
+// In code units (n = rho, T = P/rho) the thermal energy density E_th =
+// rho T/(gamma-1) of a cell changes at fixed rho and momentum as
+//   dE_th/dt = rho Gamma(T) - rho^2 Lambda(T),
+//   Lambda = L1 T^a1 + L2 T^a2, Gamma = heat          for T <  tc,
+//   Lambda = 10^(log-log interpolation of the table), Gamma = 0   for T >= tc
+// (the table used flat beyond its ends).  One operator-split step dt:
+// trapezoid (E* = E + dt Edot(E), E' = E + dt/2 (Edot(E) + Edot(E*))),
+// subcycled (N = ceil(dt |Edot| / (f E)) <= N_max substeps, each changing E
+// by at most f E), or auto (trapezoid when dt |Edot| <= f E); E_th is floored
+// at rho T_floor/(gamma-1) on entry and after every update.
+//
+// k_cool_table runs after the last stage (and after gravity, when on) as the
+// final per-cell kernel of the step: cooling, then the CFL signal speed, the
+// health check and, for the cooling-time step limit, max |Edot| / E_th of the
+// new state, all reduced into the device clock for the next step.
+#include "mh_device.h"
+#include "mh_launch.h"
+
+namespace mh {
+
+namespace {
+
+inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+__device__ __forceinline__ float dpow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double dpow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float dlog10(float x) { return log10f(x); }
+__device__ __forceinline__ double dlog10(double x) { return log10(x); }
+__device__ __forceinline__ float dexp10(float x) { return exp10f(x); }
+__device__ __forceinline__ double dexp10(double x) { return exp10(x); }
+
+template <typename T>
+__device__ T cool_lambda(const CoolTable<T>& c, T temp) {
+  if (temp < c.tc) return c.L1 * dpow(temp, c.a1) + c.L2 * dpow(temp, c.a2);
+  const T x = dlog10(temp);
+  const int n = c.ntab;
+  if (x <= c.logT[0]) return dexp10(c.logL[0]);
+  if (x >= c.logT[n - 1]) return dexp10(c.logL[n - 1]);
+  int i = 0;
+  while (!(x < c.logT[i + 1])) ++i;  // logT[i] <= x < logT[i+1]; n <= 64
+  const T w = (x - c.logT[i]) / (c.logT[i + 1] - c.logT[i]);
+  return dexp10(c.logL[i] + w * (c.logL[i + 1] - c.logL[i]));
+}
+
+template <typename T>
+__device__ __forceinline__ T cool_edot(const CoolTable<T>& c, T rho, T E, T gm1) {
+  const T temp = gm1 * E / rho;
+  const T heat = temp < c.tc ? c.heat : T(0);
+  return rho * heat - rho * rho * cool_lambda(c, temp);
+}
+
+template <typename T>
+__device__ T cool_eth_step(const CoolTable<T>& c, T rho, T E, T dt, T gm1) {
+  const T Ef = rho * c.tfloor / gm1;
+  E = fmax(E, Ef);
+  const T d0 = cool_edot(c, rho, E, gm1);
+  int m = c.integ;
+  if (m == COOLINT_AUTO) m = dt * fabs(d0) <= c.frac * E ? COOLINT_TRAPEZOID : COOLINT_SUBCYCLE;
+  if (m == COOLINT_TRAPEZOID) {
+    const T Ep = fmax(E + dt * d0, Ef);
+    const T d1 = cool_edot(c, rho, Ep, gm1);
+    return fmax(E + T(0.5) * dt * (d0 + d1), Ef);
+  }
+  const double nd = ceil((double)(dt * fabs(d0)) / (double)(c.frac * E));
+  const int N = nd < 1.0 ? 1 : (nd > (double)c.nsub_max ? c.nsub_max : (int)nd);
+  const T h = dt / (T)N;
+  for (int k = 0; k < N; ++k) {
+    T dE = (k == 0 ? d0 : cool_edot(c, rho, E, gm1)) * h;
+    const T lim = c.frac * E;
+    dE = fmin(fmax(dE, -lim), lim);
+    E = fmax(E + dE, Ef);
+  }
+  return E;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cool_table(T* U, long long N, T gamma, T ihx, T ihy,
+                                                    T ihz, CoolTable<T> c, DevClock* clk) {
+  __shared__ T sRed[4], sRate[4];
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  const T dt = (T)clk->dt;
+  const T gm1 = gamma - T(1);
+  T s = T(0), r = T(0);
+  unsigned long long bad = 0;
+  if (q < N) {
+    T u[5];
+    load_cell(U, N, q, u);
+    const T ek = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+    const T E = cool_eth_step(c, u[0], u[4] - ek, dt, gm1);
+    u[4] = ek + E;
+    U[4 * N + q] = u[4];
+    if (c.rate) r = fabs(cool_edot(c, u[0], E, gm1)) / E;
+    T w[5];
+    to_prim(u, gm1, w);
+    const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
+    s = fmax(fmax((fabs(w[1]) + cs) * ihx, (fabs(w[2]) + cs) * ihy), (fabs(w[3]) + cs) * ihz);
+    const bool ok = (w[0] > T(0)) && (w[4] > T(0)) && isfinite(u[1]) && isfinite(u[2]) &&
+                    isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
+    if (!ok) bad = 1;
+  }
+  const T m = wave_max(s);
+  const T mr = wave_max(r);
+  if ((threadIdx.x & 63) == 0) {
+    sRed[threadIdx.x >> 6] = m;
+    sRate[threadIdx.x >> 6] = mr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(&clk->smax, pos_bits(fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]))));
+    if (c.rate)
+      atomicMax(&clk->crate, pos_bits(fmax(fmax(sRate[0], sRate[1]), fmax(sRate[2], sRate[3]))));
+  }
+  if (bad) {
+    atomicAdd(&clk->bad_count, 1ull);
+    atomicMin(&clk->bad_first, (unsigned long long)q);
+  }
+}
+
+// max |Edot| / E_th of a state (the first step's cooling-time limit)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cool_rate(const T* __restrict__ U, long long N, T gamma,
+                                                   CoolTable<T> c, DevClock* clk) {
+  __shared__ T sRate[4];
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  const T gm1 = gamma - T(1);
+  T r = T(0);
+  if (q < N) {
+    T u[5];
+    load_cell(U, N, q, u);
+    const T E = u[4] - T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+    r = fabs(cool_edot(c, u[0], E, gm1)) / E;
+  }
+  const T mr = wave_max(r);
+  if ((threadIdx.x & 63) == 0) sRate[threadIdx.x >> 6] = mr;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(&clk->crate, pos_bits(fmax(fmax(sRate[0], sRate[1]), fmax(sRate[2], sRate[3]))));
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_cool_table(T* U, const StageGeom& g, T gamma, const double* ih,
+                             const CoolTable<T>& c, DevClock* clk, hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL((k_cool_table<T>), dim3(nblk(N)), dim3(256), 0, s, U, N, gamma, (T)ih[0],
+                     (T)ih[1], (T)ih[2], c, clk);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cool_rate(const T* U, const StageGeom& g, T gamma, const CoolTable<T>& c,
+                            DevClock* clk, hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL((k_cool_rate<T>), dim3(nblk(N)), dim3(256), 0, s, U, N, gamma, c, clk);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cool_table<float>(float*, const StageGeom&, float, const double*,
+                                             const CoolTable<float>&, DevClock*, hipStream_t);
+template hipError_t launch_cool_table<double>(double*, const StageGeom&, double, const double*,
+                                              const CoolTable<double>&, DevClock*, hipStream_t);
+template hipError_t launch_cool_rate<float>(const float*, const StageGeom&, float,
+                                            const CoolTable<float>&, DevClock*, hipStream_t);
+template hipError_t launch_cool_rate<double>(const double*, const StageGeom&, double,
+                                             const CoolTable<double>&, DevClock*, hipStream_t);
+
+}  // namespace mh

@@ -220,7 +220,8 @@ __global__ __launch_bounds__(256) void k_fft_adj_accum(const typename CplxOf<T>:
 template <typename T, bool COOL>
 __global__ __launch_bounds__(256) void k_accel_sources(T* U, const T* __restrict__ acc,
                                                        long long N, T gamma, T ihx,
-                                                       CoolParams<T> cool, DevClock* clk) {
+                                                       CoolParams<T> cool, DevClock* clk,
+                                                       int cfl) {
   __shared__ T sRed[4];
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   const T dt = (T)clk->dt;
@@ -244,6 +245,7 @@ __global__ __launch_bounds__(256) void k_accel_sources(T* U, const T* __restrict
     }
 #pragma unroll
     for (int f = 0; f < 5; ++f) U[f * N + q] = u[f];
+    if (!cfl) return;  // a later kernel reduces the CFL speed of the final state
     T w[5];
     to_prim(u, gm1, w);
     const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
@@ -252,6 +254,7 @@ __global__ __launch_bounds__(256) void k_accel_sources(T* U, const T* __restrict
                     isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
     if (!ok) bad = 1;
   }
+  if (!cfl) return;  // uniform: the whole block returns
   const T m = wave_max(s);
   if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -364,16 +367,16 @@ hipError_t fft_poisson(char* ws, MGLayout& L, double h, hipStream_t s) {
 // kick (+ cooling if `cool`), CFL and health check with the acceleration of
 // the last fft_poisson
 template <typename T>
-hipError_t fft_sources(char* ws, const MGLayout& L, const mh_grid_desc& g, bool cool,
+hipError_t fft_sources(char* ws, const MGLayout& L, const mh_grid_desc& g, bool cool, bool cfl,
                        const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s) {
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   const T* acc = P<T>(ws, L.fft_acc);
   if (cool)
     hipLaunchKernelGGL((k_accel_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U, acc, N,
-                       (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk);
+                       (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk, (int)cfl);
   else
     hipLaunchKernelGGL((k_accel_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U, acc, N,
-                       (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk);
+                       (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk, (int)cfl);
   return hipGetLastError();
 }
 
@@ -416,7 +419,7 @@ hipError_t fft_gravity_vjp(char* ws, MGLayout& L, double h, double G, const T* U
 
 #define FFT_INSTANTIATE(T)                                                                     \
   template hipError_t fft_poisson<T>(char*, MGLayout&, double, hipStream_t);                  \
-  template hipError_t fft_sources<T>(char*, const MGLayout&, const mh_grid_desc&, bool,       \
+  template hipError_t fft_sources<T>(char*, const MGLayout&, const mh_grid_desc&, bool, bool, \
                                      const CoolParams<T>&, T*, DevClock*, hipStream_t);       \
   template hipError_t fft_gravity_vjp<T>(char*, MGLayout&, double, double, const T*, T,       \
                                          const T*, T*, T*, hipStream_t);

@@ -603,7 +603,10 @@ __global__ __launch_bounds__(256) void k_smax(const T* __restrict__ U, long long
 }
 
 __global__ void k_clock_reset_smax(DevClock* clk) {
-  if (threadIdx.x == 0) clk->smax = 0ull;
+  if (threadIdx.x == 0) {
+    clk->smax = 0ull;
+    clk->crate = 0ull;
+  }
 }
 
 __global__ void k_clock_reset_health(DevClock* clk) {

@@ -61,19 +61,21 @@ size_t fft_layout(int n, size_t off, size_t es, MGLayout& L);
 template <typename T>
 hipError_t fft_poisson(char* ws, MGLayout& L, double h, hipStream_t s);
 template <typename T>
-hipError_t fft_sources(char* ws, const MGLayout& L, const mh_grid_desc& g, bool cool,
+hipError_t fft_sources(char* ws, const MGLayout& L, const mh_grid_desc& g, bool cool, bool cfl,
                        const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s);
 template <typename T>
 hipError_t fft_gravity_vjp(char* ws, MGLayout& L, double h, double G, const T* Ub, T dt,
                            const T* lin, T* lout, T* accb, hipStream_t s);
 
 // Solves lap(phi) = 4 pi G (rho - <rho>) for the density of U (warm start from
-// the previous solution), then applies the gravity kick, cooling (if on), the
-// CFL reduction and the health check to U.  Synchronises once per V-cycle to
-// test convergence.
+// the previous solution), then applies the gravity kick and, when `last` (no
+// later kernel in the step), the exact two-branch cooling (if on), the CFL
+// reduction and the health check to U.  Synchronises once per V-cycle to test
+// convergence.
 template <typename T>
 hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
-                           const CoolParams<T>& cool, T* U, DevClock* clk, hipStream_t s);
+                           const CoolParams<T>& cool, T* U, DevClock* clk, bool last,
+                           hipStream_t s);
 
 // Pieces of the solve for the adjoint step: F = scale (x - <x>) on the fine
 // level; the initial guess (a copy of phi0, or zero when phi0 is NULL); the

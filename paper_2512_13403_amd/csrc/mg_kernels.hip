@@ -394,7 +394,8 @@ __global__ __launch_bounds__(MG_TAIL_THREADS) void k_mgcycle_tail(TailArgs<T> t)
 // E += (m_old . g) dt; then cooling; then the CFL max and the health check
 template <typename T, bool COOL>
 __global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict__ phi, int n, T i2h,
-                                                      T gamma, T ihx, CoolParams<T> cool, DevClock* clk) {
+                                                      T gamma, T ihx, CoolParams<T> cool, DevClock* clk,
+                                                      int cfl) {
   __shared__ T sRed[4];
   const long long N = (long long)n * n * n;
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -426,6 +427,7 @@ __global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict_
     }
 #pragma unroll
     for (int f = 0; f < 5; ++f) U[f * N + q] = u[f];
+    if (!cfl) return;  // a later kernel reduces the CFL speed of the final state
     T w[5];
     to_prim(u, gm1, w);
     const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
@@ -434,6 +436,7 @@ __global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict_
                     isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
     if (!ok) bad = 1;
   }
+  if (!cfl) return;  // uniform: the whole block returns
   const T m = wave_max(s);
   if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -818,21 +821,25 @@ hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* c
 
 template <typename T>
 hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const mh_physics_desc& p,
-                           const CoolParams<T>& cp, T* U, DevClock* clk, hipStream_t s) {
+                           const CoolParams<T>& cp, T* U, DevClock* clk, bool last, hipStream_t s) {
   MGLevel& f = L.lev[0];
   const int n = f.n;
   const long long N = (long long)n * n * n;
   // F = 4 pi G (rho - <rho>), solve from the previous potential
   MG_CHECK(mg_set_rhs<T>(ws, L, U, 4.0 * M_PI * p.grav_G, clk, s));
   MG_CHECK(mg_solve<T>(ws, L, p, clk, nullptr, s));
-  if (L.fft) return fft_sources<T>(ws, L, g, (p.flags & MH_SRC_COOLING) != 0, cp, U, clk, s);
+  // the exact two-branch cooling is fused here when this kernel ends the step
+  const bool cool = last && (p.flags & MH_SRC_COOLING) && p.cool_model == MH_COOL_EXACT2;
+  if (L.fft) return fft_sources<T>(ws, L, g, cool, last, cp, U, clk, s);
   const T i2h = (T)(1.0 / (2.0 * f.h));
-  if (p.flags & MH_SRC_COOLING)
+  if (cool)
     hipLaunchKernelGGL((k_grav_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U,
-                       P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk);
+                       P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk,
+                       (int)last);
   else
     hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
-                       P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk);
+                       P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk,
+                       (int)last);
   return hipGetLastError();
 }
 
@@ -844,10 +851,10 @@ hipError_t mg_kick(char* ws, MGLayout& L, const mh_grid_desc& g, T* U, DevClock*
   MGLevel& f = L.lev[0];
   const long long N = (long long)f.n * f.n * f.n;
   CoolParams<T> none{};
-  if (L.fft) return fft_sources<T>(ws, L, g, false, none, U, clk, s);
+  if (L.fft) return fft_sources<T>(ws, L, g, false, true, none, U, clk, s);
   hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
                      P<T>(ws, f.phi[L.cur0]), f.n, (T)(1.0 / (2.0 * f.h)), (T)g.gamma,
-                     (T)(1.0 / f.h), none, clk);
+                     (T)(1.0 / f.h), none, clk, 1);
   return hipGetLastError();
 }
 
@@ -856,7 +863,7 @@ hipError_t mg_kick(char* ws, MGLayout& L, const mh_grid_desc& g, T* U, DevClock*
 #define MG_INSTANTIATE(T)                                                                      \
   template hipError_t mg_gravity_step<T>(char*, MGLayout&, const mh_grid_desc&,                \
                                          const mh_physics_desc&, const CoolParams<T>&, T*,     \
-                                         DevClock*, hipStream_t);                               \
+                                         DevClock*, bool, hipStream_t);                         \
   template hipError_t mg_set_rhs<T>(char*, MGLayout&, const T*, double, DevClock*, hipStream_t); \
   template hipError_t mg_set_guess<T>(char*, MGLayout&, const T*, hipStream_t);                 \
   template hipError_t mg_solve<T>(char*, MGLayout&, const mh_physics_desc&, DevClock*, int*,    \

@@ -32,10 +32,12 @@ struct DevClock {
   double mg_fnorm2;         // ||F||^2 of the current gravity solve
   double mg_rnorm2;         // ||r||^2 of the last residual
   double mean;              // scratch: mean of a field
+  unsigned long long crate; // bit pattern of max |Edot| / E_th (tabulated cooling)
 };
 
 enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1 };
 enum : int { LIM_MINMOD = 0, LIM_NONE = 1, LIM_VANLEER = 2, LIM_MC = 3, LIM_SUPERBEE = 4 };
+enum : int { COOLINT_TRAPEZOID = 0, COOLINT_SUBCYCLE = 1, COOLINT_AUTO = 2 };
 // template tag of the stage kernel that selects limiter and solver at run time
 enum : int { LIM_GENERIC = 15 };
 enum : int { RS_HLLC = 0, RS_HLL = 1, RS_RUSANOV = 2 };
@@ -120,6 +122,15 @@ __device__ __forceinline__ double wave_max(double v) {
 template <typename T>
 struct CoolParams {
   T tc, ts, its, tfloor, sqrt_tc, k1r, k2r;  // its = 1 / ts
+};
+
+// the tabulated heating/cooling model (cool_kernels.hip)
+template <typename T>
+struct CoolTable {
+  const T* logT;  // [ntab] log10 T
+  const T* logL;  // [ntab] log10 Lambda
+  int ntab, integ, nsub_max, rate;  // rate: reduce max |Edot|/E_th
+  T tc, tfloor, L1, a1, L2, a2, heat, frac;
 };
 
 // a * b + c in one rounding (v_fma_f32 / v_fma_f64), written out where a

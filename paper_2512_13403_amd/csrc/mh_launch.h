@@ -54,6 +54,7 @@ struct PrologueArgs {
   int f64;
   double dt_fixed;  // > 0: fixed dt
   double cfl;
+  double ccool;     // > 0: CFL steps also <= ccool / max |Edot|/E_th
   double t_stop;
   int forcing;
   OUArgs ou;
@@ -68,6 +69,12 @@ hipError_t launch_force_rows(const T* coef, const int* nvec, int nmodes, const T
 template <typename T>
 hipError_t launch_smax(const T* U, const StageGeom& g, T gamma, const double* ih, DevClock* clk,
                        hipStream_t s);
+template <typename T>
+hipError_t launch_cool_table(T* U, const StageGeom& g, T gamma, const double* ih,
+                             const CoolTable<T>& c, DevClock* clk, hipStream_t s);
+template <typename T>
+hipError_t launch_cool_rate(const T* U, const StageGeom& g, T gamma, const CoolTable<T>& c,
+                            DevClock* clk, hipStream_t s);
 hipError_t launch_clock_reset_health(DevClock* clk, hipStream_t s);
 hipError_t launch_clock_set(DevClock* clk, double t, long long step, hipStream_t s);
 hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s);

@@ -79,6 +79,11 @@ __global__ void k_prologue(const PrologueArgs a) {
     } else {
       const double smax = a.f64 ? bits_to_double_f64(clk->smax) : bits_to_double_f32(clk->smax);
       dt = a.cfl / smax;
+      if (a.ccool > 0.0) {
+        // cooling-time limit of the tabulated cooling model
+        const double r = a.f64 ? bits_to_double_f64(clk->crate) : bits_to_double_f32(clk->crate);
+        if (r > 0.0 && a.ccool / r < dt) dt = a.ccool / r;
+      }
     }
     const double cap = a.t_stop - clk->t;
     if (dt > cap) dt = cap;
@@ -122,6 +127,7 @@ __global__ void k_prologue(const PrologueArgs a) {
     clk->t += s_dt;
     clk->step += 1;
     clk->smax = 0ull;
+    clk->crate = 0ull;
   }
 }
 

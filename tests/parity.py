@@ -12,7 +12,9 @@ import paper_2512_13403_amd as mh
 
 PHYS_KEYS = ("cool", "ou_seed", "ou_tau", "ou_arms", "ou_zeta", "ou_kmin", "ou_kmax", "ou_every",
              "grav_G", "mg_pre", "mg_post", "mg_max_cycles", "mg_coarsest", "mg_tol",
-             "mg_coarse_sweeps", "mg_cycle", "mg_smoother", "grav_solver")
+             "mg_coarse_sweeps", "mg_cycle", "mg_smoother", "grav_solver", "cool_model",
+             "cool_integrator", "cool_nsub_max", "cool_frac", "cool_ccool", "cool_ki", "cool_heat",
+             "cool_table")
 
 
 def pair(shape, h, bc=(0, 0, 0), dtype="f64", gamma=5.0 / 3.0, cfl=0.4, limiter=0, flags=0,

@@ -444,6 +444,62 @@ def test_gravity_cfl_steps_match_oracle(solver):
     assert rel_err(s.get_state(), sim.U) < 1e-11
 
 
+TABLE_MODEL = dict(cool_model=oracle.COOL_TABLE, cool_table=wl.synthetic_cie_table(),
+                   **wl.COOLING_TABLE_MODEL)
+
+
+def _multiphase_state(shape, seed):
+    """Random state whose temperatures T = P/rho span 1e-3 .. 1, across the
+    heating branch, tc = 1e-2 and the table."""
+    U = wl.random_state(shape, seed=seed, vmax=0.4, rho=(0.5, 2.0), p=(0.002, 1.0))
+    return U
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("integ", [oracle.COOLINT_TRAPEZOID, oracle.COOLINT_SUBCYCLE,
+                                   oracle.COOLINT_AUTO])
+def test_tabulated_cooling(dtype, integ):
+    """The paper's cooling model (Sec. 4.1-4.3) as the step's last kernel,
+    with forcing, against the oracle."""
+    shape = (12, 14, 66)
+    h = (1 / 66, 1 / 14, 1 / 12)
+    U0 = _multiphase_state(shape, 21)
+    s, sim = run_both(shape, h, U0, dtype, 3, flags=oracle.SRC_FORCING | oracle.SRC_COOLING,
+                      ou_seed=2, cool_integrator=integ, cool_frac=0.05, cool_nsub_max=200,
+                      **TABLE_MODEL)
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+
+
+@pytest.mark.parametrize("solver", [oracle.GRAV_MG, oracle.GRAV_FFT])
+def test_tabulated_cooling_with_gravity_and_cfl_limit(solver):
+    """CFL steps limited by c_cool min t_cool, with gravity: the dt sequence
+    and the state follow the oracle (fp64)."""
+    n = 16
+    U0 = _multiphase_state((n, n, n), 22)
+    s, oc = pair((n, n, n), (1 / n,) * 3, dtype="f64",
+                 flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING, grav_G=wl.JEANS_G, mg_tol=1e-12,
+                 mg_max_cycles=60, grav_solver=solver, cool_ccool=0.3,
+                 cool_integrator=oracle.COOLINT_AUTO, **TABLE_MODEL)
+    s.set_state(U0)
+    dts = s.step(4, 0.0, record=True)
+    sim = oracle.Simulation(oc, U0).advance(4)
+    assert np.allclose(dts, sim.dts, rtol=1e-12, atol=0.0), (dts, sim.dts)
+    # the cooling limit is the binding one here
+    assert dts[0] < 0.99 * oracle.cfl_dt(oracle.make_config((n, n, n), (1 / n,) * 3), U0)
+    assert rel_err(s.get_state(), sim.U) < 1e-11
+
+
+def test_adjoint_rejects_tabulated_cooling():
+    import torch
+
+    shape = (8, 8, 8)
+    s, _ = pair(shape, (1 / 8,) * 3, dtype="f64", flags=oracle.SRC_COOLING, **TABLE_MODEL)
+    U = torch.tensor(_multiphase_state(shape, 1), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(mh.MHError) as e:
+        s.adjoint_step(U, 1e-3, 0, U.clone())
+    assert e.value.status == mh.E_UNSUPPORTED
+
+
 def test_gravity_tolerance_cycle_counts():
     n = 32
     U0 = wl.grf_density_state(n, seed=1)

@@ -9,6 +9,7 @@ import re
 import pytest
 
 import paper_2512_13403_amd as mh
+import workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -62,6 +63,13 @@ def test_workspace_size_of_valid_grids():
                    setattr(p, "ou_kmax", 2.0)), mh.E_INVALID),
     (lambda g, p: (setattr(p, "flags", mh.SRC_FORCING), setattr(p, "ou_kmax", 3.5)), mh.E_UNSUPPORTED),
     (lambda g, p: (setattr(p, "flags", mh.SRC_COOLING), setattr(p, "cool_ts", 0.0)), mh.E_INVALID),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_COOLING), setattr(p, "cool_model", 3)),
+     mh.E_UNSUPPORTED),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_COOLING), setattr(p, "cool_ccool", 0.3)),
+     mh.E_UNSUPPORTED),
+    (lambda g, p: (setattr(p, "flags", mh.SRC_COOLING), setattr(p, "cool_model", 1)),
+     mh.E_INVALID),  # no table points
+
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.bc.__setitem__(0, 1)), mh.E_SHAPE),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.n.__setitem__(0, 32)), mh.E_SHAPE),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "mg_coarsest", 0)), mh.E_INVALID),
@@ -87,6 +95,18 @@ def test_scheme_variants_are_accepted():
         for rs in (mh.RS_HLLC, mh.RS_HLL, mh.RS_RUSANOV):
             g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32", limiter=lim, riemann=rs)
             assert ws(g, mh.physics_desc())[0] == mh.OK
+
+
+def test_tabulated_cooling_is_accepted_and_checked():
+    g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32")
+    kw = dict(flags=mh.SRC_COOLING, cool_model=mh.COOL_TABLE, cool_table=wl.synthetic_cie_table(),
+              **wl.COOLING_TABLE_MODEL)
+    assert ws(g, mh.physics_desc(**kw))[0] == mh.OK
+    assert ws(g, mh.physics_desc(cool_ccool=0.2, cool_integrator=mh.COOLINT_AUTO, **kw))[0] == mh.OK
+    bad = mh.physics_desc(**kw)
+    bad.cool_logT[3] = bad.cool_logT[2]
+    assert ws(g, bad)[0] == mh.E_INVALID
+    assert ws(g, mh.physics_desc(cool_frac=0.0, **kw))[0] == mh.E_INVALID
 
 
 def test_ssprk3_workspace_holds_one_more_state():
