@@ -489,8 +489,10 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
       a.cb = T(2.0 / 3.0);
     } else if (g.integrator == MH_RK_EULER) {
       a.uin = U;  // the lone stage reads U with its stencil, so it writes U1
-      a.un = nullptr;
+      a.un = U;
       a.uout = U1;
+      a.ca = T(0);
+      a.cb = T(1);
     } else {
       a.uin = U1;
       a.un = U;
@@ -746,7 +748,9 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   T* U2 = g.integrator == MH_RK_SSP3 ? at(A.U2) : nullptr;
   if (g.integrator == MH_RK_EULER) {
     a.uin = Un;
-    a.un = nullptr;
+    a.un = Un;
+    a.ca = T(0);
+    a.cb = T(1);
   } else {
     a.uin = Un;
     a.un = nullptr;

@@ -6,8 +6,8 @@
 //   stage 3:  U' = ca U^n + cb (Uk + dt L(Uk))            (an inner stage)
 //   stage 2:  U^{n+1} = ca U^n + cb (Uk + dt L(Uk)), then the sources
 // -- (ca, cb) = (1/2, 1/2) after stage 1 for the two-stage SSP-RK2; (3/4, 1/4)
-// for the inner stage and (1/3, 2/3) for the last one in SSPRK3; forward Euler
-// is a lone final stage without U^n -- with L(U) = -sum_a (F_{a,i+1/2} - F_{a,i-1/2}) / dx_a, the face fluxes F
+// for the inner stage and (1/3, 2/3) for the last one in SSPRK3; (0, 1) for
+// forward Euler, a lone final stage -- with L(U) = -sum_a (F_{a,i+1/2} - F_{a,i-1/2}) / dx_a, the face fluxes F
 // from HLLC (App. A.2) on MUSCL face states of the primitive variables with a
 // minmod-limited slope (App. A.1).  Stage 2 also applies, per cell and in
 // registers, the operator-split sources in the order forcing -> cooling
@@ -109,20 +109,18 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   const bool fan = left ? (SL < T(0)) : (SR > T(0));
   const T mK = rK * uK;
   const T FK0 = mK, FK1 = fmad(mK, uK, pK), FK2 = mK * aK, FK3 = mK * bK, FK4 = uK * (EK + pK);
-  const T q = dev_rcp(SK - sstar);
+  // outside the fan the star terms are multiplied by 0 instead of being
+  // selected away: q = 0 keeps them finite, and F = F_K + 0 * (...)
+  const T q = fan ? dev_rcp(SK - sstar) : T(0);
+  const T Sf = fan ? SK : T(0);
   const T qd = q * dK;
   const T s0 = qd, s1 = qd * sstar, s2 = qd * aK, s3 = qd * bK;
   const T s4 = q * fmad(SK - uK, EK, (sstar - uK) * fmad(dK, sstar, pK));
-  const T f0 = fmad(SK, s0 - rK, FK0);
-  const T f1 = fmad(SK, s1 - mK, FK1);
-  const T f2 = fmad(SK, fmad(-rK, aK, s2), FK2);
-  const T f3 = fmad(SK, fmad(-rK, bK, s3), FK3);
-  const T f4 = fmad(SK, s4 - EK, FK4);
-  F[0] = fan ? f0 : FK0;
-  F[vn] = fan ? f1 : FK1;
-  F[t1] = fan ? f2 : FK2;
-  F[t2] = fan ? f3 : FK3;
-  F[4] = fan ? f4 : FK4;
+  F[0] = fmad(Sf, s0 - rK, FK0);
+  F[vn] = fmad(Sf, s1 - mK, FK1);
+  F[t1] = fmad(Sf, fmad(-rK, aK, s2), FK2);
+  F[t2] = fmad(Sf, fmad(-rK, bK, s3), FK3);
+  F[4] = fmad(Sf, s4 - EK, FK4);
 }
 
 // conserved state and physical flux of a primitive face state, in the
@@ -422,7 +420,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       un[f] = fmad(dt, L, u[0][f]);
     }
     const long long q = (long long)z * plane + col;
-    if (STAGE != 1 && a.un != nullptr) {
+    if (STAGE != 1) {
       T u0[5];
       if (inside) load_cell(a.un, N, q, u0);
       else {
@@ -471,19 +469,19 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       if (inside) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
-      }
-      if (inside && a.epilogue) {
-        // CFL signal speed of the new state and the health check
-        T wn[5] = {un[0], vx, vy, vz, pn};
-        const T cs = sound_speed(gamma * pn, un[0]);
-        const T s = fmax(fmax((fabs(wn[1]) + cs) * a.ihx, (fabs(wn[2]) + cs) * a.ihy),
-                         (fabs(wn[3]) + cs) * a.ihz);
-        smax = fmax(smax, s);
-        const bool ok = (wn[0] > T(0)) && (wn[4] > T(0)) && isfinite(un[1]) &&
-                        isfinite(un[2]) && isfinite(un[3]) && isfinite(un[4]) && isfinite(s);
-        if (!ok) {
-          ++nbad;
-          if ((unsigned long long)q < first_bad) first_bad = (unsigned long long)q;
+        if (a.epilogue) {
+          // CFL signal speed of the new state and the health check
+          T wn[5] = {un[0], vx, vy, vz, pn};
+          const T cs = sound_speed(gamma * pn, un[0]);
+          const T s = fmax(fmax((fabs(wn[1]) + cs) * a.ihx, (fabs(wn[2]) + cs) * a.ihy),
+                           (fabs(wn[3]) + cs) * a.ihz);
+          smax = fmax(smax, s);
+          const bool ok = (wn[0] > T(0)) && (wn[4] > T(0)) && isfinite(un[1]) &&
+                          isfinite(un[2]) && isfinite(un[3]) && isfinite(un[4]) && isfinite(s);
+          if (!ok) {
+            ++nbad;
+            if ((unsigned long long)q < first_bad) first_bad = (unsigned long long)q;
+          }
         }
       }
     }

@@ -16,8 +16,7 @@ struct StageGeom {
 template <typename T>
 struct StageArgs {
   const T* __restrict__ uin;  // stage input (read with halo)
-  const T* un;                // U^n at the cell itself (stages 2 and 3; may alias uout;
-                              // NULL: no combination with U^n)
+  const T* un;                // U^n at the cell itself (stages 2 and 3; may alias uout)
   T* uout;                    // stage output
   DevClock* clk;
   const T* __restrict__ ou_rows;  // [nz][ny][R+1][3][P, Q] forcing row records
