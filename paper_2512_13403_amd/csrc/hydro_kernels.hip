@@ -109,18 +109,20 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   const bool fan = left ? (SL < T(0)) : (SR > T(0));
   const T mK = rK * uK;
   const T FK0 = mK, FK1 = fmad(mK, uK, pK), FK2 = mK * aK, FK3 = mK * bK, FK4 = uK * (EK + pK);
-  // outside the fan the star terms are multiplied by 0 instead of being
-  // selected away: q = 0 keeps them finite, and F = F_K + 0 * (...)
-  const T q = fan ? dev_rcp(SK - sstar) : T(0);
-  const T Sf = fan ? SK : T(0);
+  const T q = dev_rcp(SK - sstar);
   const T qd = q * dK;
   const T s0 = qd, s1 = qd * sstar, s2 = qd * aK, s3 = qd * bK;
   const T s4 = q * fmad(SK - uK, EK, (sstar - uK) * fmad(dK, sstar, pK));
-  F[0] = fmad(Sf, s0 - rK, FK0);
-  F[vn] = fmad(Sf, s1 - mK, FK1);
-  F[t1] = fmad(Sf, fmad(-rK, aK, s2), FK2);
-  F[t2] = fmad(Sf, fmad(-rK, bK, s3), FK3);
-  F[4] = fmad(Sf, s4 - EK, FK4);
+  const T f0 = fmad(SK, s0 - rK, FK0);
+  const T f1 = fmad(SK, s1 - mK, FK1);
+  const T f2 = fmad(SK, fmad(-rK, aK, s2), FK2);
+  const T f3 = fmad(SK, fmad(-rK, bK, s3), FK3);
+  const T f4 = fmad(SK, s4 - EK, FK4);
+  F[0] = fan ? f0 : FK0;
+  F[vn] = fan ? f1 : FK1;
+  F[t1] = fan ? f2 : FK2;
+  F[t2] = fan ? f3 : FK3;
+  F[4] = fan ? f4 : FK4;
 }
 
 // conserved state and physical flux of a primitive face state, in the
