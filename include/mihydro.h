@@ -340,6 +340,19 @@ void mh_corr_destroy(mh_corr *c);
 mh_status mh_block_average(const void *fine, int32_t nf, int32_t r, void *coarse, int32_t dtype,
                            void *stream);
 
+/* In-place 3D discrete Fourier transform of an n^3 complex array on the
+ * device (the transform of the spectral gravity solver, Sec. 6.1, offered on
+ * its own for spectral initial conditions): data holds interleaved (re, im)
+ * values of dtype, x fastest; forward X_k = sum_j x_j exp(-2 pi i j.k/n),
+ * inverse unnormalised (sum with exp(+...)).  n is a power of two, 2..1024.
+ * workspace: device memory of at least mh_fft3_query_workspace bytes (the
+ * twiddle table, rewritten by every call).  Enqueued on `stream`.  Errors:
+ * MH_E_INVALID (null pointer, inverse not 0/1), MH_E_SHAPE (n), MH_E_DTYPE,
+ * MH_E_WORKSPACE, MH_E_DEVICE. */
+mh_status mh_fft3_query_workspace(int32_t n, int32_t dtype, size_t *bytes);
+mh_status mh_fft3(void *data, int32_t n, int32_t dtype, int32_t inverse, void *workspace,
+                  size_t workspace_bytes, void *stream);
+
 /* Kernel timing with HIP events.  While enabled, mh_step records an event pair
  * on the context stream around every kernel launch it makes, by kind:
  *   MH_TIME_STAGE1, MH_TIME_STAGE2 (the fused stage kernels),
@@ -360,13 +373,13 @@ mh_status mh_get_timing(mh_ctx *ctx, double *ms, int64_t *launches);
  * where = MH_HOST (synchronises) or MH_DEVICE.  MH_E_INVALID without gravity. */
 mh_status mh_set_potential(mh_ctx *ctx, const void *phi, int where);
 
-/* Message of the last failed call on ctx (empty string if none). */
 /* Multigrid V-cycles are replayed from HIP graphs captured on first use
  * (one V-cycle is ~60 small launches); enable = 0 launches them kernel by
  * kernel instead.  Default on; results are identical either way.
  * Synchronises. */
 mh_status mh_set_graphs(mh_ctx *ctx, int enable);
 
+/* Message of the last failed call on ctx (empty string if none). */
 const char *mh_last_error(const mh_ctx *ctx);
 
 /* Waits for the context's stream, then frees the host context (not the

@@ -43,7 +43,8 @@ EXPORTED = [
     "mh_corr_query_workspace", "mh_corr_init", "mh_corr_set_params", "mh_corr_get_params",
     "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
     "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
-    "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs",
+    "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs", "mh_fft3_query_workspace",
+    "mh_fft3",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -143,6 +144,10 @@ def load_library():
             "mh_corr_backward": [vp, vp, vp, vp, dp, vp],
             "mh_corr_adam_step": [vp, ctypes.c_float],
             "mh_corr_get_grad": [vp, vp, ctypes.c_int],
+            "mh_fft3_query_workspace": [ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_size_t)],
+            "mh_fft3": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t,
+                        vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -593,6 +598,30 @@ class Corrector:
         if raw.dtype == np.uint16:
             return (raw.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
         return raw.astype(np.float64)
+
+
+def fft3(x, inverse: bool = False):
+    """In-place 3D DFT (mh_fft3) of a CUDA tensor [n][n][n][2] of interleaved
+    (re, im) float32/float64 values, x fastest; forward exp(-i), inverse
+    unnormalised.  Returns x."""
+    import torch
+
+    lib = load_library()
+    n = x.shape[0]
+    if x.shape != (n, n, n, 2) or not x.is_contiguous() or x.device.type != "cuda":
+        raise ValueError("fft3 needs a contiguous CUDA tensor [n][n][n][2]")
+    dt = F64 if x.dtype == torch.float64 else F32
+    need = ctypes.c_size_t(0)
+    st = lib.mh_fft3_query_workspace(n, dt, ctypes.byref(need))
+    if st != OK:
+        raise MHError(st, "mh_fft3_query_workspace")
+    ws = torch.empty(need.value, dtype=torch.uint8, device=x.device)
+    st = lib.mh_fft3(ctypes.c_void_p(x.data_ptr()), n, dt, int(bool(inverse)),
+                     ctypes.c_void_p(ws.data_ptr()), need.value,
+                     ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+    if st != OK:
+        raise MHError(st, "mh_fft3")
+    return x
 
 
 def block_average(fine, r: int):

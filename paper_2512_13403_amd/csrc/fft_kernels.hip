@@ -289,11 +289,11 @@ __global__ __launch_bounds__(256) void k_accel_kick_vjp(const T* __restrict__ U,
   lout[4 * N + q] = Eb;
 }
 
+// the three one-axis passes over the n^3 cube c, with the twiddles tw
 template <typename T>
-hipError_t fft3(char* ws, const MGLayout& L, typename CplxOf<T>::type* c, int inverse,
-                hipStream_t s) {
+hipError_t fft3_raw(typename CplxOf<T>::type* c, const typename CplxOf<T>::type* tw, int n,
+                    int inverse, hipStream_t s) {
   using C = typename CplxOf<T>::type;
-  const int n = L.lev[0].n;
   int logn = 0;
   while ((1 << logn) < n) ++logn;
   const long long lines = (long long)n * n;
@@ -302,7 +302,6 @@ hipError_t fft3(char* ws, const MGLayout& L, typename CplxOf<T>::type* c, int in
   if (lpb > lines) lpb = (int)lines;
   const unsigned grid = (unsigned)(lines / lpb);
   const size_t lds = (size_t)lpb * n * sizeof(C);
-  const C* tw = P<C>(ws, L.fft_tw);
   hipLaunchKernelGGL((k_fft_lines<T, 0>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
                      lpb, inverse);
   hipLaunchKernelGGL((k_fft_lines<T, 1>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
@@ -310,6 +309,21 @@ hipError_t fft3(char* ws, const MGLayout& L, typename CplxOf<T>::type* c, int in
   hipLaunchKernelGGL((k_fft_lines<T, 2>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
                      lpb, inverse);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fft3(char* ws, const MGLayout& L, typename CplxOf<T>::type* c, int inverse,
+                hipStream_t s) {
+  using C = typename CplxOf<T>::type;
+  return fft3_raw<T>(c, P<C>(ws, L.fft_tw), L.lev[0].n, inverse, s);
+}
+
+template <typename T>
+hipError_t fft3_standalone(void* data, int n, int inverse, void* tw, hipStream_t s) {
+  using C = typename CplxOf<T>::type;
+  hipLaunchKernelGGL((k_fft_twiddles<T>), dim3(nblk(n / 2 > 0 ? n / 2 : 1)), dim3(256), 0, s,
+                     (C*)tw, n);
+  return fft3_raw<T>((C*)data, (const C*)tw, n, inverse, s);
 }
 
 }  // namespace
@@ -428,3 +442,26 @@ FFT_INSTANTIATE(double)
 #undef FFT_INSTANTIATE
 
 }  // namespace mh
+
+extern "C" mh_status mh_fft3_query_workspace(int32_t n, int32_t dtype, size_t* bytes) {
+  if (!bytes) return MH_E_INVALID;
+  if (!mh::fft_size_ok(n)) return MH_E_SHAPE;
+  if (dtype != MH_F32 && dtype != MH_F64) return MH_E_DTYPE;
+  const size_t es = dtype == MH_F64 ? 8 : 4;
+  *bytes = (size_t)(n / 2 > 0 ? n / 2 : 1) * 2 * es;
+  return MH_OK;
+}
+
+extern "C" mh_status mh_fft3(void* data, int32_t n, int32_t dtype, int32_t inverse,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  size_t need = 0;
+  const mh_status st = mh_fft3_query_workspace(n, dtype, &need);
+  if (st != MH_OK) return st;
+  if (!data || !workspace || (inverse != 0 && inverse != 1)) return MH_E_INVALID;
+  if (workspace_bytes < need) return MH_E_WORKSPACE;
+  const hipError_t e =
+      dtype == MH_F64
+          ? mh::fft3_standalone<double>(data, n, inverse, workspace, (hipStream_t)stream)
+          : mh::fft3_standalone<float>(data, n, inverse, workspace, (hipStream_t)stream);
+  return e == hipSuccess ? MH_OK : MH_E_DEVICE;
+}

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_entry_points():
     text = open(os.path.join(ROOT, "include", "mihydro.h")).read()
-    return sorted(set(re.findall(r"\b(mh_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mh_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -95,6 +95,15 @@ def test_scheme_variants_are_accepted():
         for rs in (mh.RS_HLLC, mh.RS_HLL, mh.RS_RUSANOV):
             g = mh.grid_desc((16, 16, 16), (1 / 16,) * 3, dtype="f32", limiter=lim, riemann=rs)
             assert ws(g, mh.physics_desc())[0] == mh.OK
+
+
+def test_fft3_workspace_query_checks_its_arguments():
+    L = mh.load_library()
+    n = ctypes.c_size_t(0)
+    assert L.mh_fft3_query_workspace(64, mh.F64, ctypes.byref(n)) == mh.OK and n.value == 32 * 16
+    assert L.mh_fft3_query_workspace(48, mh.F64, ctypes.byref(n)) == mh.E_SHAPE
+    assert L.mh_fft3_query_workspace(2048, mh.F32, ctypes.byref(n)) == mh.E_SHAPE
+    assert L.mh_fft3_query_workspace(64, 9, ctypes.byref(n)) == mh.E_DTYPE
 
 
 def test_tabulated_cooling_is_accepted_and_checked():
