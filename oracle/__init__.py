@@ -89,6 +89,7 @@ class Config(ctypes.Structure):
         ("cool_heat", ctypes.c_double),
         ("cool_logT", ctypes.c_double * 64),
         ("cool_logL", ctypes.c_double * 64),
+        ("flux_corr", ctypes.c_void_p),
     ]
 
 
@@ -149,6 +150,9 @@ def lib():
             "or_gravity_vjp": (ctypes.c_int, [cp, dp, ctypes.c_double, dp, dp, dp]),
             "or_step_vjp": (None, [cp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int, ip, dp, dp,
                                    dp, dp]),
+            "or_step_vjp_flux": (None, [cp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int, ip, dp,
+                                        dp, dp, dp, dp]),
+            "or_flux_corr_vjp": (None, [cp, dp, ctypes.c_double, dp]),
             "or_step": (ctypes.c_double, [cp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                           ctypes.c_int, ip, dp, dp, ip]),
         }
@@ -177,7 +181,7 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
                 mg_coarse_sweeps=200, integrator=RK_SSP2, mg_cycle=MG_V, mg_smoother=SMOOTH_JACOBI,
                 grav_solver=GRAV_MG, cool_model=COOL_EXACT2, cool_integrator=COOLINT_TRAPEZOID,
                 cool_nsub_max=1000, cool_frac=0.1, cool_ccool=0.0, cool_ki=(0.0, 0.0, 0.0, 0.0),
-                cool_heat=0.0, cool_table=None) -> Config:
+                cool_heat=0.0, cool_table=None, flux_corr=None) -> Config:
     """shape = (nz, ny, nx) of the state arrays; h = (hx, hy, hz); bc per (x, y, z)."""
     nz, ny, nx = shape
     c = Config()
@@ -202,6 +206,21 @@ def make_config(shape, h, bc=(BC_PERIODIC,) * 3, gamma=5.0 / 3.0, cfl=0.4, limit
         c.cool_ntab = len(logT)
         c.cool_logT[:len(logT)] = list(logT)
         c.cool_logL[:len(logL)] = list(logL)
+    set_flux_corr(c, flux_corr)
+    return c
+
+
+def set_flux_corr(c, field):
+    """Attach a flux-correction field [5][nz][ny][nx] (or None) to c; c keeps
+    a reference to the array it points at."""
+    if field is None:
+        c.flux_corr = None
+        c._flux_ref = None
+        return c
+    a = np.ascontiguousarray(field, dtype=np.float64)
+    assert a.shape == (5,) + _shape(c)
+    c._flux_ref = a
+    c.flux_corr = a.ctypes.data
     return c
 
 
@@ -486,6 +505,31 @@ def step_vjp(c, Un, dt, step, nvec, ahat, phi, lam):
     lib().or_step_vjp(ctypes.byref(c), _dp(Un), dt, step, len(nvec), _ip(nv), _dp(a), _dp(ph),
                       _dp(lam), _dp(out))
     return out
+
+
+def step_vjp_flux(c, Un, dt, step, nvec, ahat, phi, lam):
+    """step_vjp that also returns the adjoint of the flux-correction field
+    attached to c: (lam_n, gflux)."""
+    Un = np.ascontiguousarray(Un, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    nv = np.ascontiguousarray(nvec, dtype=np.int32).reshape(-1)
+    if nv.size == 0:
+        nv = np.zeros(3, dtype=np.int32)
+    a = np.array(ahat, dtype=np.float64, copy=True)
+    ph = np.array(phi, dtype=np.float64, copy=True)
+    out = np.empty_like(Un)
+    g = np.zeros_like(Un)
+    lib().or_step_vjp_flux(ctypes.byref(c), _dp(Un), dt, step, len(nvec), _ip(nv), _dp(a),
+                           _dp(ph), _dp(lam), _dp(out), _dp(g))
+    return out, g
+
+
+def flux_corr_vjp(c, v, weight=1.0):
+    """weight (dL/dflux_corr)^T v for L = rhs."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    g = np.zeros_like(v)
+    lib().or_flux_corr_vjp(ctypes.byref(c), _dp(v), weight, _dp(g))
+    return g
 
 
 @dataclass

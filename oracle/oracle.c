@@ -333,6 +333,15 @@ void or_rhs(const or_config *c, const double *U, double *L) {
         flux[fidx][vt1] = fr[2];
         flux[fidx][vt2] = fr[3];
         flux[fidx][4] = fr[4];
+        if (c->flux_corr) {
+          /* the face between cells fidx-1 and fidx is the +a face of cell
+           * fidx-1 (boundary-mapped for the face below the first cell) */
+          cellq[a] = or_bc(fidx - 1, n, c->bc[a]);
+          cellq[b1] = j1;
+          cellq[b2] = j2;
+          long qc = or_idx(c, cellq[0], cellq[1], cellq[2]);
+          for (int f = 0; f < 5; ++f) flux[fidx][f] += c->flux_corr[f * N + qc];
+        }
       }
       for (long i = 0; i < n; ++i) {
         cellq[a] = i;

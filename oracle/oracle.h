@@ -54,6 +54,10 @@ typedef struct {
   double cool_L1, cool_a1, cool_L2, cool_a2; /* low-T branch L1 T^a1 + L2 T^a2 */
   double cool_heat;  /* heating rate Gamma_0 below cool_tc */
   double cool_logT[OR_COOL_TABMAX], cool_logL[OR_COOL_TABMAX]; /* log10 T, log10 Lambda */
+  /* learned flux correction (Sec. 8, the solver-in-the-loop flux term): a
+   * per-cell field [5][N] added to the flux of the cell's +x, +y and +z
+   * faces in every stage, or NULL */
+  const double *flux_corr;
 } or_config;
 
 void or_primitives(const or_config *c, const double *U, double *W);
@@ -114,6 +118,12 @@ void or_ssprk3_vjp(const or_config *c, const double *U, double dt, const double 
                    double *lam);
 void or_integrate_vjp(const or_config *c, const double *U, double dt, const double *lamp,
                       double *lam);
+void or_flux_corr_vjp(const or_config *c, const double *v, double weight, double *g);
+void or_integrate_vjp_flux(const or_config *c, const double *U, double dt, const double *lamp,
+                           double *lam, double *gflux);
+void or_step_vjp_flux(const or_config *c, const double *Un, double dt, int64_t step, int nmodes,
+                      const int32_t *nvec, const double *ou_ahat, double *phi,
+                      const double *lam_np1, double *lam_n, double *gflux);
 void or_rk2_vjp(const or_config *c, const double *U, double dt, const double *lam2,
                 double *lam);
 void or_kick_vjp(const or_config *c, const double *U, const double *acc, double dt,

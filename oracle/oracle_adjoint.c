@@ -466,8 +466,10 @@ void or_rhs_vjp(const or_config *c, const double *U, const double *v, double *ou
 /* Reverse of U1 = U + dt L(U), U2 = U/2 + (U1 + dt L(U1))/2:
  *   lam1 = lam2/2 + (dt/2) J(U1)^T lam2,
  *   lam  = lam2/2 + lam1 + dt J(U)^T lam1. */
-void or_rk2_vjp(const or_config *c, const double *U, double dt, const double *lam2,
-                double *lam) {
+/* gflux (or NULL): += the adjoint of the flux-correction field, which enters
+ * every stage's L with the stage's dt weight (or_flux_corr_vjp) */
+static void rk2_vjp(const or_config *c, const double *U, double dt, const double *lam2,
+                    double *lam, double *gflux) {
   long N5 = 5 * cells(c);
   double *U1 = (double *)malloc(sizeof(double) * N5);
   double *L = (double *)malloc(sizeof(double) * N5);
@@ -479,17 +481,32 @@ void or_rk2_vjp(const or_config *c, const double *U, double dt, const double *la
   for (long q = 0; q < N5; ++q) lam1[q] = 0.5 * lam2[q] + 0.5 * dt * tmp[q];
   or_rhs_vjp(c, U, lam1, tmp);
   for (long q = 0; q < N5; ++q) lam[q] = 0.5 * lam2[q] + lam1[q] + dt * tmp[q];
+  if (gflux) {
+    or_flux_corr_vjp(c, lam2, 0.5 * dt, gflux); /* U_new = U/2 + (U1 + dt L(U1))/2 */
+    or_flux_corr_vjp(c, lam1, dt, gflux);       /* U1 = U + dt L(U) */
+  }
   free(U1); free(L); free(lam1); free(tmp);
 }
 
+void or_rk2_vjp(const or_config *c, const double *U, double dt, const double *lam2,
+                double *lam) {
+  rk2_vjp(c, U, dt, lam2, lam, NULL);
+}
+
 /* Reverse of forward Euler: lam = lam1 + dt J(U)^T lam1. */
-void or_euler_vjp(const or_config *c, const double *U, double dt, const double *lam1,
-                  double *lam) {
+static void euler_vjp(const or_config *c, const double *U, double dt, const double *lam1,
+                      double *lam, double *gflux) {
   long N5 = 5 * cells(c);
   double *tmp = (double *)malloc(sizeof(double) * N5);
   or_rhs_vjp(c, U, lam1, tmp);
   for (long q = 0; q < N5; ++q) lam[q] = lam1[q] + dt * tmp[q];
+  if (gflux) or_flux_corr_vjp(c, lam1, dt, gflux);
   free(tmp);
+}
+
+void or_euler_vjp(const or_config *c, const double *U, double dt, const double *lam1,
+                  double *lam) {
+  euler_vjp(c, U, dt, lam1, lam, NULL);
 }
 
 /* Reverse of SSPRK3 (or_ssprk3), stage by stage from the last one, with lam3
@@ -497,8 +514,8 @@ void or_euler_vjp(const or_config *c, const double *U, double dt, const double *
  *   lam2 = 2/3 (lam3 + dt J(U2)^T lam3)            (adjoint of U2)
  *   lam1 = 1/4 (lam2 + dt J(U1)^T lam2)            (adjoint of U1)
  *   lam  = lam3/3 + 3/4 lam2 + lam1 + dt J(U)^T lam1 */
-void or_ssprk3_vjp(const or_config *c, const double *U, double dt, const double *lam3,
-                   double *lam) {
+static void ssprk3_vjp(const or_config *c, const double *U, double dt, const double *lam3,
+                       double *lam, double *gflux) {
   long N5 = 5 * cells(c);
   double *L = (double *)malloc(sizeof(double) * N5);
   double *U1 = (double *)malloc(sizeof(double) * N5);
@@ -517,15 +534,68 @@ void or_ssprk3_vjp(const or_config *c, const double *U, double dt, const double 
   or_rhs_vjp(c, U, lam1, tmp);
   for (long q = 0; q < N5; ++q)
     lam[q] = lam3[q] / 3.0 + 0.75 * lam2[q] + lam1[q] + dt * tmp[q];
+  if (gflux) {
+    or_flux_corr_vjp(c, lam3, 2.0 / 3.0 * dt, gflux); /* the last stage's L(U2) */
+    or_flux_corr_vjp(c, lam2, 0.25 * dt, gflux);       /* U2's L(U1) */
+    or_flux_corr_vjp(c, lam1, dt, gflux);              /* U1's L(U) */
+  }
   free(L); free(U1); free(U2); free(lam1); free(lam2); free(tmp);
 }
 
-/* reverse of or_integrate */
+void or_ssprk3_vjp(const or_config *c, const double *U, double dt, const double *lam3,
+                   double *lam) {
+  ssprk3_vjp(c, U, dt, lam3, lam, NULL);
+}
+
+/* reverse of or_integrate; gflux (or NULL) += the adjoint of the flux
+ * correction */
+void or_integrate_vjp_flux(const or_config *c, const double *U, double dt, const double *lamp,
+                           double *lam, double *gflux) {
+  if (c->integrator == OR_RK_SSP3) ssprk3_vjp(c, U, dt, lamp, lam, gflux);
+  else if (c->integrator == OR_RK_EULER) euler_vjp(c, U, dt, lamp, lam, gflux);
+  else rk2_vjp(c, U, dt, lamp, lam, gflux);
+}
+
 void or_integrate_vjp(const or_config *c, const double *U, double dt, const double *lamp,
                       double *lam) {
-  if (c->integrator == OR_RK_SSP3) or_ssprk3_vjp(c, U, dt, lamp, lam);
-  else if (c->integrator == OR_RK_EULER) or_euler_vjp(c, U, dt, lamp, lam);
-  else or_rk2_vjp(c, U, dt, lamp, lam);
+  or_integrate_vjp_flux(c, U, dt, lamp, lam, NULL);
+}
+
+/* g += weight (dL/dflux_corr)^T v for L = or_rhs: the correction at cell i
+ * is the flux of its +a face on every axis a; a face's flux enters L of the
+ * cell on its left with -1/h_a and of the cell on its right with +1/h_a
+ * (cells that exist: with outflow the lowest face, mapped to cell 0, has
+ * only its right cell and the highest face only its left one). */
+void or_flux_corr_vjp(const or_config *c, const double *v, double weight, double *g) {
+  long N = cells(c);
+  for (int a = 0; a < 3; ++a) {
+    long n = c->n[a];
+    int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    long npencil = (long)c->n[b1] * c->n[b2];
+    double w = weight / c->h[a];
+    for (long p = 0; p < npencil; ++p) {
+      long j1 = p % c->n[b1], j2 = p / c->n[b1];
+      long cq[3];
+      cq[b1] = j1;
+      cq[b2] = j2;
+      for (long fidx = 0; fidx <= n; ++fidx) {
+        cq[a] = bcmap(fidx - 1, n, c->bc[a]);
+        long qc = idx(c, cq[0], cq[1], cq[2]);
+        for (int f = 0; f < 5; ++f) {
+          double d = 0.0;
+          if (fidx <= n - 1) {
+            cq[a] = fidx;
+            d += v[f * N + idx(c, cq[0], cq[1], cq[2])];
+          }
+          if (fidx >= 1) {
+            cq[a] = fidx - 1;
+            d -= v[f * N + idx(c, cq[0], cq[1], cq[2])];
+          }
+          g[f * N + qc] += w * d;
+        }
+      }
+    }
+  }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -687,6 +757,14 @@ int or_gravity_vjp(const or_config *c, const double *U, double dt, double *phi,
 void or_step_vjp(const or_config *c, const double *Un, double dt, int64_t step, int nmodes,
                  const int32_t *nvec, const double *ou_ahat, double *phi,
                  const double *lam_np1, double *lam_n) {
+  or_step_vjp_flux(c, Un, dt, step, nmodes, nvec, ou_ahat, phi, lam_np1, lam_n, NULL);
+}
+
+/* or_step_vjp that also accumulates the flux-correction adjoint into gflux
+ * (when not NULL) */
+void or_step_vjp_flux(const or_config *c, const double *Un, double dt, int64_t step, int nmodes,
+                      const int32_t *nvec, const double *ou_ahat, double *phi,
+                      const double *lam_np1, double *lam_n, double *gflux) {
   long N = cells(c), N5 = 5 * N;
   double *Ua = (double *)malloc(sizeof(double) * N5); /* after the RK update */
   double *Ub = (double *)malloc(sizeof(double) * N5); /* after forcing */
@@ -722,6 +800,6 @@ void or_step_vjp(const or_config *c, const double *Un, double dt, int64_t step, 
   if (c->flags & OR_SRC_GRAVITY) or_gravity_vjp(c, Ub, dt, phi0, lb, la);
   memcpy(lb, la, sizeof(double) * N5);
   if (force) or_kick_vjp(c, Ua, acc, dt, la, lb, NULL);
-  or_integrate_vjp(c, Un, dt, lb, lam_n);
+  or_integrate_vjp_flux(c, Un, dt, lb, lam_n, gflux);
   free(Ua); free(Ub); free(Uc); free(acc); free(la); free(lb); free(ahat); free(phi0);
 }

@@ -276,3 +276,65 @@ def test_step_vjp_gravity(solver):
     # perturbations leave them there in both difference runs
     check_dot(fwd, lambda w: oracle.step_vjp(c, U, dt, 0, nv, np.zeros(6), phi, w), U, seed=20,
               rtol=1e-6, fields=[0])
+
+
+# ---------------------------------------------------------------- flux correction (Sec. 8)
+
+@pytest.mark.parametrize("name,grid", GRIDS)
+def test_flux_correction_enters_as_a_face_flux(name, grid):
+    """L(U) with a correction field B equals L(U) plus the difference of B
+    over each cell's faces: -sum_a (B_i - B_{i-e_a}) / h_a with the face
+    below the first cell taking B of its mapped cell (periodic wrap, or the
+    cell itself with outflow); a uniform B changes nothing with periodic
+    boundaries."""
+    rng = np.random.default_rng(40)
+    U = wl.random_state(grid.shape, seed=41, vmax=0.5)
+    B = rng.standard_normal((5,) + grid.shape)
+    c0 = oracle.make_config(grid.shape, grid.h, grid.bc)
+    c1 = oracle.make_config(grid.shape, grid.h, grid.bc, flux_corr=B)
+    d = oracle.rhs(c1, U) - oracle.rhs(c0, U)
+    want = np.zeros_like(B)
+    for a, axis in enumerate((3, 2, 1)):  # x, y, z axes of the [5][z][y][x] arrays
+        lower = np.roll(B, 1, axis=axis)
+        if grid.bc[a] == 1:  # outflow: the face below cell 0 carries B of cell 0
+            sl = [slice(None)] * 4
+            sl[axis] = 0
+            lower[tuple(sl)] = B[tuple(sl)]
+        want -= (B - lower) / grid.h[a]
+    assert np.abs(d - want).max() < 1e-12 * np.abs(want).max()
+    if all(b == 0 for b in grid.bc):
+        cu = oracle.make_config(grid.shape, grid.h, grid.bc,
+                                flux_corr=np.ones((5,) + grid.shape) * rng.standard_normal((5, 1, 1, 1)))
+        assert np.abs(oracle.rhs(cu, U) - oracle.rhs(c0, U)).max() < 1e-12
+
+
+@pytest.mark.parametrize("integrator", [oracle.RK_SSP2, oracle.RK_SSP3, oracle.RK_EULER])
+def test_flux_correction_adjoint(integrator):
+    """The adjoint of the flux-correction field through a full step (with
+    forcing and cooling) against central differences of the step in B."""
+    grid = wl.Grid((5, 6, 7), (1 / 7, 1 / 6, 1 / 5), (1, 0, 0))
+    U = wl.random_state(grid.shape, seed=42, vmax=0.5)
+    rng = np.random.default_rng(43)
+    B = 0.05 * rng.standard_normal((5,) + grid.shape)
+    flags = oracle.SRC_FORCING | oracle.SRC_COOLING
+    c = oracle.make_config(grid.shape, grid.h, grid.bc, flags=flags, integrator=integrator,
+                           flux_corr=B)
+    dt = 0.4 * oracle.cfl_dt(c, U)
+    nvec = oracle.ou_modes(1.0, 2.0)
+    ahat = oracle.ou_init(c, nvec)
+    phi = np.zeros(grid.shape)
+    w = rng.standard_normal(U.shape)
+    _, g = oracle.step_vjp_flux(c, U, dt, 1, nvec, ahat, phi, w)
+
+    def fwd(Bx):
+        cx = oracle.make_config(grid.shape, grid.h, grid.bc, flags=flags, integrator=integrator,
+                                flux_corr=Bx)
+        sim = oracle.Simulation(cx, U, nvec=nvec, ahat=ahat.copy(), phi=phi.copy())
+        sim.step_index = 1
+        return sim.advance(1, dt).U
+
+    for trial in range(3):
+        v = rng.standard_normal(B.shape) * 0.05
+        eps = 1e-6
+        jv = (fwd(B + eps * v) - fwd(B - eps * v)) / (2 * eps)
+        assert float((w * jv).sum()) == pytest.approx(float((g * v).sum()), rel=2e-7)
