@@ -373,6 +373,19 @@ mh_status mh_get_timing(mh_ctx *ctx, double *ms, int64_t *launches);
  * where = MH_HOST (synchronises) or MH_DEVICE.  MH_E_INVALID without gravity. */
 mh_status mh_set_potential(mh_ctx *ctx, const void *phi, int where);
 
+/* Learned flux correction (Sec. 8: the solver-in-the-loop flux term added to
+ * the base convective fluxes).  field: device array [5][nz][ny][nx] of the
+ * context dtype, in the conserved-field order, or NULL to switch it off; its
+ * value at a cell is added to the flux through the cell's upper face on each
+ * axis (x+1/2, y+1/2, z+1/2; with outflow the lowest face of an axis takes
+ * the value of the first cell), in every RK stage of every later mh_step,
+ * until changed.  Steps with a field run the kernel that takes the scheme at
+ * run time.  grad: device array of the same shape, or NULL; when given, every
+ * later mh_adjoint_step adds (dU^{n+1}/d field)^T lam^{n+1} to it (the
+ * caller zeroes it).  Both stay owned by the caller and must stay valid while
+ * attached.  Enqueues nothing. */
+mh_status mh_set_flux_correction(mh_ctx *ctx, const void *field, void *grad);
+
 /* Multigrid V-cycles are replayed from HIP graphs captured on first use
  * (one V-cycle is ~60 small launches); enable = 0 launches them kernel by
  * kernel instead.  Default on; results are identical either way.

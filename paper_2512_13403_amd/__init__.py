@@ -44,7 +44,7 @@ EXPORTED = [
     "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
     "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
     "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs", "mh_fft3_query_workspace",
-    "mh_fft3",
+    "mh_fft3", "mh_set_flux_correction",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -148,6 +148,7 @@ def load_library():
                                         ctypes.POINTER(ctypes.c_size_t)],
             "mh_fft3": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t,
                         vp],
+            "mh_set_flux_correction": [vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -357,6 +358,22 @@ class Solver:
         c = ctypes.c_int32()
         self._check(self.lib.mh_last_mg_cycles(self.ctx, ctypes.byref(c)), "mh_last_mg_cycles")
         return c.value
+
+    def set_flux_correction(self, field=None, grad=None):
+        """Attaches a learned flux-correction field (CUDA tensor [5][nz][ny][nx]
+        of the state dtype) added to each cell's upper-face fluxes in every
+        later step, and optionally a gradient tensor of the same shape that
+        later adjoint steps accumulate into; None detaches.  The solver keeps
+        references to both."""
+        for t in (field, grad):
+            if t is not None and (tuple(t.shape) != (5,) + self.shape or not t.is_contiguous()
+                                  or t.dtype != self.torch_dtype):
+                raise ValueError("flux correction tensors must be contiguous [5][nz][ny][nx] "
+                                 "of the state dtype")
+        self._dflux, self._dflux_grad = field, grad
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        self._check(self.lib.mh_set_flux_correction(self.ctx, ptr(field), ptr(grad)),
+                    "mh_set_flux_correction")
 
     def set_graphs(self, enable: bool):
         """Multigrid V-cycles from captured HIP graphs (default) or launched

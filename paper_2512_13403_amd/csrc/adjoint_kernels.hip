@@ -577,6 +577,41 @@ __global__ __launch_bounds__(256) void k_jtv_finish(const T* __restrict__ U,
   }
 }
 
+// g += weight (dL/dB)^T v for the flux-correction field B (B at a cell is
+// added to the flux through its upper face on each axis a; a face's flux
+// leaves the cell below with -1/h_a and enters the cell above with +1/h_a):
+// per axis, d = v(i+1) - v(i), with v beyond the last cell 0 for outflow
+// (periodic: wrapped), plus v(0) at the first cell with outflow, whose B
+// also sits on the face below it
+template <typename T>
+__global__ __launch_bounds__(256) void k_flux_corr_vjp(const T* __restrict__ v, int nx, int ny,
+                                                       int nz, int bcx, int bcy, int bcz, T wx,
+                                                       T wy, T wz, T* g) {
+  const long long N = (long long)nx * ny * nz;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int i = (int)(q % nx), j = (int)((q / nx) % ny), k = (int)(q / ((long long)nx * ny));
+  const long long sx = 1, sy = nx, sz = (long long)nx * ny;
+  const int n[3] = {nx, ny, nz}, c[3] = {i, j, k}, bc[3] = {bcx, bcy, bcz};
+  const long long st[3] = {sx, sy, sz};
+  const T w[3] = {wx, wy, wz};
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const T* vf = v + f * N;
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T up;
+      if (c[a] + 1 < n[a]) up = vf[q + st[a]];
+      else up = bc[a] == BC_PERIODIC ? vf[q - (long long)(n[a] - 1) * st[a]] : T(0);
+      T d = up - vf[q];
+      if (bc[a] != BC_PERIODIC && c[a] == 0) d += vf[q];
+      acc += w[a] * d;
+    }
+    g[f * N + q] += acc;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T* y, long long n, T v) {
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -807,6 +842,16 @@ hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limite
 }
 
 template <typename T>
+hipError_t adj_flux_corr_vjp(const T* v, const StageGeom& g, const double* h, double weight,
+                             T* grad, hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL((k_flux_corr_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, v, g.nx, g.ny, g.nz,
+                     g.bc[0], g.bc[1], g.bc[2], (T)(weight / h[0]), (T)(weight / h[1]),
+                     (T)(weight / h[2]), grad);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t adj_force_kick(T* U, const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
                           hipStream_t s) {
   const long long N = (long long)g.nx * g.ny * g.nz;
@@ -860,6 +905,8 @@ hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws
   template hipError_t adj_jtv<T>(const AdjointBuffers<T>&, const StageGeom&, int, int, T,        \
                                  const double*, const T*, const T*, T, T, const T*, T, const T*, \
                                  T, const T*, T*, hipStream_t);                                  \
+  template hipError_t adj_flux_corr_vjp<T>(const T*, const StageGeom&, const double*, double,   \
+                                           T*, hipStream_t);                                   \
   template hipError_t adj_force_kick<T>(T*, const T*, const T*, int, const StageGeom&, T,        \
                                         hipStream_t);                                            \
   template hipError_t adj_force_kick_vjp<T>(const T*, const T*, int, const StageGeom&, T,        \

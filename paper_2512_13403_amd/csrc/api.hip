@@ -170,6 +170,9 @@ struct mh_ctx {
   bool timing = false;
   // V-cycle graphs of the step's solver and of the adjoint's second solve
   MGGraphCache mg_graphs, adj_graphs;
+  // learned flux correction and the buffer its adjoint accumulates into
+  const void* dflux = nullptr;
+  void* dflux_grad = nullptr;
   std::vector<hipEvent_t> ev;
   std::vector<int> kinds;
   int64_t untimed = 0;
@@ -409,6 +412,7 @@ static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) 
   a.ca = T(0.5);
   a.cb = T(0.5);
   a.epilogue = ((p.flags & MH_SRC_GRAVITY) || c->cool_table()) ? 0 : 1;
+  a.dflux = static_cast<const T*>(c->dflux);
   if (p.flags & MH_SRC_FORCING) {
     a.ou_rows = ou_rows;
     for (int k = 0; k < 3; ++k) a.ou_tab[k] = c->at<T>(c->L.tab[k]);
@@ -802,8 +806,10 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   }
   const int lim = g.limiter;
   const T gam = (T)g.gamma;
+  T* gflux = static_cast<T*>(c->dflux_grad);
   if (g.integrator == MH_RK_EULER) {
     // lam_n = cur + dt J(U^n)^T cur
+    if (gflux) MH_HIP(c, adj_flux_corr_vjp<T>(cur, geom, g.h, dt, gflux, c->stream));
     MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, Un, cur, (T)dt, T(1), cur, T(0), nullptr, T(0),
                          nullptr, lam_n, c->stream));
   } else if (g.integrator == MH_RK_SSP3) {
@@ -814,12 +820,21 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
                          cur, T(0), nullptr, T(0), nullptr, lam2, c->stream));
     MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, U1, lam2, (T)(0.25 * dt), T(0.25), lam2, T(0),
                          nullptr, T(0), nullptr, lam1, c->stream));
+    if (gflux) {
+      MH_HIP(c, adj_flux_corr_vjp<T>(cur, geom, g.h, 2.0 / 3.0 * dt, gflux, c->stream));
+      MH_HIP(c, adj_flux_corr_vjp<T>(lam2, geom, g.h, 0.25 * dt, gflux, c->stream));
+      MH_HIP(c, adj_flux_corr_vjp<T>(lam1, geom, g.h, dt, gflux, c->stream));
+    }
     MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, Un, lam1, (T)dt, (T)(1.0 / 3.0), cur, T(0.75),
                          lam2, T(1), lam1, lam_n, c->stream));
   } else {
     // lam1 = cur/2 + (dt/2) J(U1)^T cur;  lam_n = cur/2 + lam1 + dt J(U^n)^T lam1
     MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, U1, cur, (T)(0.5 * dt), T(0.5), cur, T(0),
                          nullptr, T(0), nullptr, lam1, c->stream));
+    if (gflux) {
+      MH_HIP(c, adj_flux_corr_vjp<T>(cur, geom, g.h, 0.5 * dt, gflux, c->stream));
+      MH_HIP(c, adj_flux_corr_vjp<T>(lam1, geom, g.h, dt, gflux, c->stream));
+    }
     MH_HIP(c, adj_jtv<T>(B, geom, lim, g.riemann, gam, g.h, Un, lam1, (T)dt, T(0.5), cur, T(1), lam1, T(0),
                          nullptr, lam_n, c->stream));
   }
@@ -891,6 +906,15 @@ extern "C" mh_status mh_set_potential(mh_ctx* c, const void* phi, int where) {
 }
 
 extern "C" const char* mh_last_error(const mh_ctx* c) { return c ? c->err.c_str() : ""; }
+
+extern "C" mh_status mh_set_flux_correction(mh_ctx* c, const void* field, void* grad) {
+  if (!c) return MH_E_INVALID;
+  if (!field && grad)
+    return set_err(c, MH_E_INVALID, "mh_set_flux_correction: a gradient buffer needs a field");
+  c->dflux = field;
+  c->dflux_grad = grad;
+  return MH_OK;
+}
 
 extern "C" mh_status mh_set_graphs(mh_ctx* c, int enable) {
   if (!c) return MH_E_INVALID;

@@ -221,6 +221,15 @@ __device__ __forceinline__ void face_flux_sl(const T (&w0)[5], const T (&d0)[5],
   riemann_flux<T, N, LIM>(wl, wr, gamma, gm1inv, rs, F);
 }
 
+// learned flux correction (the solver-in-the-loop flux term): the field's
+// value at a cell is added to the flux through each of its upper faces
+template <typename T>
+__device__ __forceinline__ void add_dflux(const T* __restrict__ d, long long N, long long q,
+                                          T (&F)[5]) {
+#pragma unroll
+  for (int f = 0; f < 5; ++f) F[f] += d[f * N + q];
+}
+
 // Each row of the tile (fixed ty) is exactly one wave, so the lower-edge
 // faces below can be given to whole waves.
 static_assert(TX == 64 && TY <= TX, "one wave per tile row");
@@ -318,6 +327,8 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       dz1[f] = limited_slope<T, LIM>(w[0][f], w[1][f], w[2][f], a.lim);
     }
     face_flux_sl<T, 2, LIM>(w[0], dz0, w[1], dz1, gamma, gm1inv, a.rs, fzm);
+    if (LIM == LIM_GENERIC && a.dflux)
+      add_dflux(a.dflux, N, (long long)bc_map(z0 - 1, a.nz, a.bcz) * plane + col, fzm);
   }
 
   T smax = T(0);
@@ -367,6 +378,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         c3[f] = sW[f][ty + 2][tx + 4];
       }
       face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
+      if (LIM == LIM_GENERIC && a.dflux) add_dflux(a.dflux, N, (long long)z * plane + col, F);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sFx[f][ty][tx + 1] = F[f];
       // y face at y + 1/2
@@ -378,6 +390,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         c3[f] = sW[f][ty + 4][tx + 2];
       }
       face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
+      if (LIM == LIM_GENERIC && a.dflux) add_dflux(a.dflux, N, (long long)z * plane + col, F);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sFy[f][ty + 1][tx] = F[f];
       // the tile's lower-edge faces: the TX y faces at y0 - 1/2 by the wave
@@ -392,6 +405,11 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
           c3[f] = sW[f][3][tx + 2];
         }
         face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
+        if (LIM == LIM_GENERIC && a.dflux)
+          add_dflux(a.dflux, N,
+                    (long long)z * plane + (long long)bc_map(y0 - 1, a.ny, a.bcy) * a.nx +
+                        bc_map(gx, a.nx, a.bcx),
+                    F);
 #pragma unroll
         for (int f = 0; f < 5; ++f) sFy[f][0][tx] = F[f];
       } else if (ty == 1 && tx < TY) {
@@ -403,6 +421,11 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
           c3[f] = sW[f][tx + 2][3];
         }
         face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
+        if (LIM == LIM_GENERIC && a.dflux)
+          add_dflux(a.dflux, N,
+                    (long long)z * plane + (long long)bc_map(y0 + tx, a.ny, a.bcy) * a.nx +
+                        bc_map(x0 - 1, a.nx, a.bcx),
+                    F);
 #pragma unroll
         for (int f = 0; f < 5; ++f) sFx[f][tx][0] = F[f];
       }
@@ -411,6 +434,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
 #pragma unroll
     for (int f = 0; f < 5; ++f) dz2[f] = limited_slope<T, LIM>(w[1][f], w[2][f], w[3][f], a.lim);
     face_flux_sl<T, 2, LIM>(w[1], dz1, w[2], dz2, gamma, gm1inv, a.rs, fzp);
+    if (LIM == LIM_GENERIC && a.dflux) add_dflux(a.dflux, N, (long long)z * plane + col, fzp);
     __syncthreads();
 
     T un[5];
@@ -657,7 +681,8 @@ hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs
   hipLaunchKernelGGL((k_stage<T, ST, LM, FO, CO>), grid, block, 0, s, a)
   // minmod or none with HLLC: the specialised kernels; any other limiter or
   // solver: the kernel that reads them at run time
-  if (a.rs != RS_HLLC || (limiter != LIM_MINMOD && limiter != LIM_NONE)) limiter = LIM_GENERIC;
+  if (a.rs != RS_HLLC || (limiter != LIM_MINMOD && limiter != LIM_NONE) || a.dflux)
+    limiter = LIM_GENERIC;
   if (stage == 1) {
     if (limiter == LIM_NONE) MH_LAUNCH(1, LIM_NONE, false, false);
     else if (limiter == LIM_GENERIC) MH_LAUNCH(1, LIM_GENERIC, false, false);

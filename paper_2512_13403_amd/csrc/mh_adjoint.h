@@ -33,6 +33,9 @@ hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limite
                    const double* h, const T* U, const T* v, T beta, T c0, const T* x0, T c1,
                    const T* x1, T c2, const T* x2, T* out, hipStream_t s);
 template <typename T>
+hipError_t adj_flux_corr_vjp(const T* v, const StageGeom& g, const double* h, double weight,
+                             T* grad, hipStream_t s);
+template <typename T>
 hipError_t adj_force_kick(T* U, const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
                           hipStream_t s);
 template <typename T>

@@ -32,6 +32,8 @@ struct StageArgs {
   T ca, cb;     // stages 2 and 3: out = ca U^n + cb (uin + dt L(uin))
   int epilogue; // stage 2: reduce the CFL speed and check health (0 when a
                 // sources kernel follows and does both on the final state)
+  const T* dflux;  // learned flux correction [5][N] (the +x, +y, +z faces of
+                   // each cell), or null; run-time-scheme kernel only
 };
 
 struct OUArgs {

@@ -77,3 +77,46 @@ def invert_initial_density(solver, U_init, target, dts, iters=50, lr=1e-2, K=10,
             callback(it, losses[-1])
     with torch.no_grad():
         return assemble_state(rho, v, p, gamma).detach(), losses
+
+
+def learn_flux_correction(solver, U0, target, dts, iters=30, lr=1e-3, K=10, kind="l2",
+                          field_init=None, callback=None):
+    """Solver-in-the-loop training of a learned flux term (Sec. 8): a
+    correction field B [5][...] added to each cell's upper-face fluxes
+    (``Solver.set_flux_correction``) is fitted with ADAM so that len(dts)
+    steps from U0 with the fixed time steps dts end with a density close to
+    ``target``; the gradient of the misfit with respect to B is accumulated
+    by the adjoint steps of the checkpointed rollout.  Here B is a free field
+    (the parameters themselves); a network producing B from the state would
+    chain its own reverse pass onto the same gradient.  Returns (B, misfit
+    before each iteration)."""
+    import torch
+
+    from .rollout import rollout_backward, rollout_forward
+
+    B = (torch.zeros_like(U0) if field_init is None else field_init.detach().clone())
+    B.requires_grad_(True)
+    gB = torch.zeros_like(U0)
+    opt = torch.optim.Adam([B], lr=lr)
+    dts = np.asarray(dts, dtype=np.float64)
+    losses = []
+    for it in range(iters):
+        opt.zero_grad()
+        field = B.detach().contiguous()
+        gB.zero_()
+        solver.set_flux_correction(field, gB)
+        Uf, used, cks = rollout_forward(solver, U0, len(dts), K, dts)
+        rho = Uf[0].detach().requires_grad_(True)
+        loss = misfit(rho, target, kind)
+        loss.backward()
+        lam = torch.zeros_like(Uf)
+        lam[0] = rho.grad
+        rollout_backward(solver, cks, used, K, lam)
+        torch.cuda.synchronize()
+        B.grad = gB.clone()
+        losses.append(float(loss.detach()))
+        opt.step()
+        if callback is not None:
+            callback(it, losses[-1])
+    solver.set_flux_correction(None, None)
+    return B.detach(), losses
