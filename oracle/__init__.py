@@ -119,6 +119,8 @@ def lib():
             "or_cool_eth_step": (ctypes.c_double, [cp, ctypes.c_double, ctypes.c_double,
                                                    ctypes.c_double]),
             "or_cool_dt_limit": (ctypes.c_double, [cp, dp]),
+            "or_cool_eth_step_d": (ctypes.c_double, [cp, ctypes.c_double, ctypes.c_double,
+                                                     ctypes.c_double, dp, dp]),
             "or_integrate": (None, [cp, dp, ctypes.c_double]),
             "or_cool_temperature": (ctypes.c_double, [ctypes.c_double] * 8),
             "or_cool": (None, [cp, dp, ctypes.c_double]),
@@ -287,6 +289,14 @@ def cool_edot(c, rho, Eth):
 def cool_eth_step(c, rho, Eth, dt):
     """One step of the tabulated model's integrator (oracle_cool.c)."""
     return lib().or_cool_eth_step(ctypes.byref(c), rho, Eth, dt)
+
+
+def cool_eth_step_d(c, rho, Eth, dt):
+    """(E', dE'/dEth, dE'/drho) of the tabulated model's step."""
+    dE = ctypes.c_double(0.0)
+    dr = ctypes.c_double(0.0)
+    v = lib().or_cool_eth_step_d(ctypes.byref(c), rho, Eth, dt, ctypes.byref(dE), ctypes.byref(dr))
+    return v, dE.value, dr.value
 
 
 def cool_dt_limit(c, U):

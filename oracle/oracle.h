@@ -77,6 +77,8 @@ double or_cool_lambda(const or_config *c, double T);
 double or_cool_edot(const or_config *c, double rho, double Eth);
 double or_cool_eth_step(const or_config *c, double rho, double Eth, double dt);
 double or_cool_dt_limit(const or_config *c, const double *U);
+double or_cool_eth_step_d(const or_config *c, double rho, double Eth, double dt, double *dE,
+                          double *dr);
 
 void or_ou_gauss(uint64_t seed, int64_t group, int mode, int comp, double out[2]);
 int or_ou_modes(double kmin, double kmax, int32_t *nvec);

@@ -666,6 +666,25 @@ void or_cool_vjp(const or_config *c, const double *U, double dt, const double *l
                  double *lam) {
   long N = cells(c);
   double g = c->gamma, gm1 = g - 1.0;
+  if (c->cool_model == OR_COOL_TABLE) {
+    /* E' = ek + C(rho, E - ek), ek = |m|^2/(2 rho), with C the tabulated
+     * model's step and its partials C_E, C_rho (oracle_cool.c) */
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < N; ++q) {
+      double rho = U[q], mx = U[N + q], my = U[2 * N + q], mz = U[3 * N + q], E = U[4 * N + q];
+      double ek = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+      double CE, Cr;
+      or_cool_eth_step_d(c, rho, E - ek, dt, &CE, &Cr);
+      double Eb = lamp[4 * N + q];
+      double ekb = Eb * (1.0 - CE); /* dE'/dek */
+      lam[q] = lamp[q] + Eb * Cr - ekb * ek / rho;
+      lam[N + q] = lamp[N + q] + ekb * mx / rho;
+      lam[2 * N + q] = lamp[2 * N + q] + ekb * my / rho;
+      lam[3 * N + q] = lamp[3 * N + q] + ekb * mz / rho;
+      lam[4 * N + q] = Eb * CE;
+    }
+    return;
+  }
 #pragma omp parallel for schedule(static)
   for (long q = 0; q < N; ++q) {
     double rho = U[q], mx = U[N + q], my = U[2 * N + q], mz = U[3 * N + q], E = U[4 * N + q];

@@ -111,3 +111,92 @@ double or_cool_dt_limit(const or_config *c, const double *U) {
   }
   return rmax > 0.0 ? c->cool_ccool / rmax : INFINITY;
 }
+
+/* ------------------------------------------------------------------------- */
+/* derivatives of the tabulated model's step (for the adjoint)               */
+/* ------------------------------------------------------------------------- */
+
+/* dLambda/dT on the branch taken: below tc the two power laws; in the table
+ * s Lambda / T with s the segment's slope d log10 Lambda / d log10 T; flat
+ * beyond the table's ends (0) */
+static double lambda_dT(const or_config *c, double T) {
+  if (T < c->cool_tc)
+    return c->cool_L1 * c->cool_a1 * pow(T, c->cool_a1 - 1.0) +
+           c->cool_L2 * c->cool_a2 * pow(T, c->cool_a2 - 1.0);
+  int n = c->cool_ntab;
+  double x = log10(T);
+  if (x <= c->cool_logT[0] || x >= c->cool_logT[n - 1]) return 0.0;
+  int i = 0;
+  while (!(x < c->cool_logT[i + 1])) ++i;
+  double s = (c->cool_logL[i + 1] - c->cool_logL[i]) / (c->cool_logT[i + 1] - c->cool_logT[i]);
+  return s * or_cool_lambda(c, T) / T;
+}
+
+/* a value with its derivatives with respect to the step's inputs E_th and rho */
+typedef struct {
+  double v, dE, dr;
+} dual2;
+
+/* Edot(rho, E) with dEdot/dE = -(g-1) rho Lambda'(T) and dEdot/drho =
+ * Gamma - 2 rho Lambda + rho T Lambda'(T) (Gamma constant on each branch) */
+static dual2 edot_d(const or_config *c, double rho, dual2 E) {
+  double g1 = c->gamma - 1.0;
+  double T = g1 * E.v / rho;
+  double heat = T < c->cool_tc ? c->cool_heat : 0.0;
+  double L = or_cool_lambda(c, T), Lp = lambda_dT(c, T);
+  double pE = -g1 * rho * Lp;
+  double pr = heat - 2.0 * rho * L + rho * T * Lp;
+  dual2 r = {rho * heat - rho * rho * L, pE * E.dE, pE * E.dr + pr};
+  return r;
+}
+
+static dual2 floor_d(const or_config *c, double rho, dual2 E) {
+  double Ef = rho * c->cool_tfloor / (c->gamma - 1.0); /* as floor_eth */
+  if (E.v > Ef) return E;
+  dual2 f = {Ef, 0.0, c->cool_tfloor / (c->gamma - 1.0)};
+  return f;
+}
+
+/* or_cool_eth_step with dE'/dEth in *dE and dE'/drho in *dr, the branches
+ * (floor, limiter, integrator choice, substep count) as the forward takes
+ * them */
+double or_cool_eth_step_d(const or_config *c, double rho, double Eth, double dt, double *dE,
+                          double *dr) {
+  dual2 E = {Eth, 1.0, 0.0};
+  E = floor_d(c, rho, E);
+  double f = c->cool_frac;
+  dual2 d0 = edot_d(c, rho, E);
+  int m = c->cool_integrator;
+  if (m == OR_COOLINT_AUTO)
+    m = dt * fabs(d0.v) <= f * E.v ? OR_COOLINT_TRAPEZOID : OR_COOLINT_SUBCYCLE;
+  if (m == OR_COOLINT_TRAPEZOID) {
+    dual2 Ep = {E.v + dt * d0.v, E.dE + dt * d0.dE, E.dr + dt * d0.dr};
+    Ep = floor_d(c, rho, Ep);
+    dual2 d1 = edot_d(c, rho, Ep);
+    dual2 r = {E.v + 0.5 * dt * (d0.v + d1.v), E.dE + 0.5 * dt * (d0.dE + d1.dE),
+               E.dr + 0.5 * dt * (d0.dr + d1.dr)};
+    r = floor_d(c, rho, r);
+    *dE = r.dE;
+    *dr = r.dr;
+    return r.v;
+  }
+  double nd = ceil(dt * fabs(d0.v) / (f * E.v));
+  long N = nd < 1.0 ? 1 : (nd > (double)c->cool_nsub_max ? c->cool_nsub_max : (long)nd);
+  double h = dt / (double)N;
+  for (long k = 0; k < N; ++k) {
+    dual2 d = edot_d(c, rho, E);
+    dual2 dEk = {d.v * h, d.dE * h, d.dr * h};
+    dual2 lim = {f * E.v, f * E.dE, f * E.dr};
+    if (dEk.v > lim.v) dEk = lim;
+    if (dEk.v < -lim.v) {
+      dEk.v = -lim.v;
+      dEk.dE = -lim.dE;
+      dEk.dr = -lim.dr;
+    }
+    dual2 s = {E.v + dEk.v, E.dE + dEk.dE, E.dr + dEk.dr};
+    E = floor_d(c, rho, s);
+  }
+  *dE = E.dE;
+  *dr = E.dr;
+  return E.v;
+}

@@ -338,3 +338,26 @@ def test_flux_correction_adjoint(integrator):
         eps = 1e-6
         jv = (fwd(B + eps * v) - fwd(B - eps * v)) / (2 * eps)
         assert float((w * jv).sum()) == pytest.approx(float((g * v).sum()), rel=2e-7)
+
+
+@pytest.mark.parametrize("integ", [oracle.COOLINT_TRAPEZOID, oracle.COOLINT_SUBCYCLE])
+def test_tabulated_cooling_step_vjp(integ):
+    """Full steps with forcing and the tabulated cooling model (Sec. 4)."""
+    grid = wl.cube(8)
+    U = wl.random_state(grid.shape, seed=44, vmax=0.4, rho=(0.5, 2.0), p=(0.002, 1.0))
+    c = oracle.make_config(grid.shape, grid.h, flags=oracle.SRC_FORCING | oracle.SRC_COOLING,
+                           cool_model=oracle.COOL_TABLE, cool_table=wl.synthetic_cie_table(),
+                           cool_integrator=integ, cool_frac=0.05, cool_nsub_max=50,
+                           **wl.COOLING_TABLE_MODEL)
+    dt = 0.5 * oracle.cfl_dt(c, U)
+    nvec = oracle.ou_modes(1.0, 2.0)
+    ahat = oracle.ou_init(c, nvec)
+    phi = np.zeros(grid.shape)
+
+    def fwd(X):
+        sim = oracle.Simulation(c, X, nvec=nvec, ahat=ahat.copy(), phi=phi.copy())
+        sim.step_index = 3
+        return sim.advance(1, dt).U
+
+    check_dot(fwd, lambda w: oracle.step_vjp(c, U, dt, 3, nvec, ahat, phi, w), U, seed=45,
+              eps=1e-7, rtol=1e-6)

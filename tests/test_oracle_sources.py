@@ -302,3 +302,25 @@ def test_cooling_time_step_limit():
     cs = math.sqrt(g * p / rho)
     assert oracle.cfl_dt(c, U) == pytest.approx(min(0.4 / (n * cs), 0.2 * tcool), rel=1e-14)
     assert 0.2 * tcool < 0.4 / (n * cs)
+
+
+@pytest.mark.parametrize("integ", [oracle.COOLINT_TRAPEZOID, oracle.COOLINT_SUBCYCLE,
+                                   oracle.COOLINT_AUTO])
+def test_tabulated_step_derivatives_match_finite_differences(integ):
+    """dE'/dE_th and dE'/drho of the tabulated model's step (forward-mode
+    derivatives through the branches taken) against central differences,
+    across the heating branch, tc and the table."""
+    g = 5.0 / 3.0
+    c = table_cfg(cool_integrator=integ, cool_frac=0.05, cool_nsub_max=50)
+    for rho, T, dt in ((0.7, 0.002, 0.3), (1.6, 0.008, 0.01), (1.2, 0.05, 0.003),
+                       (0.9, 0.4, 0.02), (2.0, 3.0, 0.05)):
+        E = rho * T / (g - 1)
+        v, dE, dr = oracle.cool_eth_step_d(c, rho, E, dt)
+        assert v == oracle.cool_eth_step(c, rho, E, dt)
+        h = 1e-7
+        fE = (oracle.cool_eth_step(c, rho, E * (1 + h), dt) -
+              oracle.cool_eth_step(c, rho, E * (1 - h), dt)) / (2 * h * E)
+        fr = (oracle.cool_eth_step(c, rho * (1 + h), E, dt) -
+              oracle.cool_eth_step(c, rho * (1 - h), E, dt)) / (2 * h * rho)
+        assert dE == pytest.approx(fE, rel=1e-5, abs=1e-9), (rho, T)
+        assert dr == pytest.approx(fr, rel=1e-5, abs=1e-9 * abs(v / rho)), (rho, T)
