@@ -239,9 +239,10 @@ mh_status mh_get_potential(mh_ctx *ctx, void *phi, int where);
  *   state, clock, OU amplitudes and potential are not touched.
  * Enqueued on the context stream; with gravity it synchronises once per
  * multigrid cycle.  Every grid, scheme, integrator and source the context
- * accepts is supported except the tabulated cooling model (MH_E_UNSUPPORTED).
- * Errors: MH_E_INVALID (null pointer, or ou_ahat missing with forcing on),
- * MH_E_UNSUPPORTED, MH_E_WORKSPACE, MH_E_DEVICE. */
+ * accepts is supported; the tabulated cooling model is differentiated through
+ * its integrator's branches (floor, limiter, substep count and integrator
+ * choice held as taken).  Errors: MH_E_INVALID (null pointer, or ou_ahat
+ * missing with forcing on), MH_E_WORKSPACE, MH_E_DEVICE. */
 mh_status mh_query_adjoint_workspace(mh_ctx *ctx, size_t *bytes);
 mh_status mh_adjoint_step(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace_bytes,
                           const void *U_n, double dt, int64_t step, const double *ou_ahat,

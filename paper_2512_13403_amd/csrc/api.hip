@@ -790,7 +790,11 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   // reverse sweep: cooling, gravity, forcing, then the RK update
   const T* cur = lam_np1;
   if (cool) {
-    MH_HIP(c, adj_cool_vjp<T>(Uc, N, (T)(g.gamma - 1.0), (T)dt, a.cool, cur, lamA, c->stream));
+    if (c->cool_table())
+      MH_HIP(c, launch_cool_table_vjp<T>(Uc, N, (T)g.gamma, (T)dt, c->cool_table_args<T>(), cur,
+                                         lamA, c->stream));
+    else
+      MH_HIP(c, adj_cool_vjp<T>(Uc, N, (T)(g.gamma - 1.0), (T)dt, a.cool, cur, lamA, c->stream));
     cur = lamA;
   }
   if (grav) {
@@ -851,10 +855,6 @@ extern "C" mh_status mh_adjoint_step(mh_ctx* c, void* adj_workspace, size_t adj_
   if ((c->p.flags & MH_SRC_FORCING) && !ou_ahat)
     return set_err(c, MH_E_INVALID, "mh_adjoint_step: forcing is on but ou_ahat is NULL");
   if (!(dt >= 0.0) || step < 0) return set_err(c, MH_E_INVALID, "mh_adjoint_step: bad dt or step");
-  if (c->cool_table())
-    return set_err(c, MH_E_UNSUPPORTED,
-                   "mh_adjoint_step: the tabulated cooling model has no adjoint; use the exact "
-                   "two-branch model");
   AdjLayout A = make_adj_layout(c->g, c->p);
   A.mg.graphs = &c->adj_graphs;
   if (!adj_workspace || adj_workspace_bytes < A.total || ((uintptr_t)adj_workspace % ALIGN) != 0)

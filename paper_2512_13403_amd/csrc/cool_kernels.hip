@@ -120,6 +120,98 @@ __global__ __launch_bounds__(256) void k_cool_table(T* U, long long N, T gamma, 
   }
 }
 
+// ---- reverse pass: the step's partial derivatives in forward mode ----------
+// dLambda/dT on the branch taken (0 beyond the table's ends)
+template <typename T>
+__device__ T cool_lambda_dT(const CoolTable<T>& c, T temp) {
+  if (temp < c.tc)
+    return c.L1 * c.a1 * dpow(temp, c.a1 - T(1)) + c.L2 * c.a2 * dpow(temp, c.a2 - T(1));
+  const T x = dlog10(temp);
+  const int n = c.ntab;
+  if (x <= c.logT[0] || x >= c.logT[n - 1]) return T(0);
+  int i = 0;
+  while (!(x < c.logT[i + 1])) ++i;
+  const T s = (c.logL[i + 1] - c.logL[i]) / (c.logT[i + 1] - c.logT[i]);
+  return s * cool_lambda(c, temp) / temp;
+}
+
+// a value with its derivatives with respect to the step's inputs E_th, rho
+template <typename T>
+struct Dual2 {
+  T v, dE, dr;
+};
+
+template <typename T>
+__device__ Dual2<T> cool_edot_d(const CoolTable<T>& c, T rho, Dual2<T> E, T gm1) {
+  const T temp = gm1 * E.v / rho;
+  const T heat = temp < c.tc ? c.heat : T(0);
+  const T L = cool_lambda(c, temp), Lp = cool_lambda_dT(c, temp);
+  const T pE = -gm1 * rho * Lp;
+  const T pr = heat - T(2) * rho * L + rho * temp * Lp;
+  return Dual2<T>{rho * heat - rho * rho * L, pE * E.dE, pE * E.dr + pr};
+}
+
+template <typename T>
+__device__ __forceinline__ Dual2<T> cool_floor_d(const CoolTable<T>& c, T rho, Dual2<T> E,
+                                                 T gm1) {
+  const T Ef = rho * c.tfloor / gm1;
+  if (E.v > Ef) return E;
+  return Dual2<T>{Ef, T(0), c.tfloor / gm1};
+}
+
+// the step's result with dE'/dE_th and dE'/drho, branches as the forward
+template <typename T>
+__device__ Dual2<T> cool_eth_step_d(const CoolTable<T>& c, T rho, T Eth, T dt, T gm1) {
+  Dual2<T> E = cool_floor_d(c, rho, Dual2<T>{Eth, T(1), T(0)}, gm1);
+  const Dual2<T> d0 = cool_edot_d(c, rho, E, gm1);
+  int m = c.integ;
+  if (m == COOLINT_AUTO)
+    m = dt * fabs(d0.v) <= c.frac * E.v ? COOLINT_TRAPEZOID : COOLINT_SUBCYCLE;
+  if (m == COOLINT_TRAPEZOID) {
+    const Dual2<T> Ep = cool_floor_d(
+        c, rho, Dual2<T>{E.v + dt * d0.v, E.dE + dt * d0.dE, E.dr + dt * d0.dr}, gm1);
+    const Dual2<T> d1 = cool_edot_d(c, rho, Ep, gm1);
+    return cool_floor_d(c, rho,
+                        Dual2<T>{E.v + T(0.5) * dt * (d0.v + d1.v),
+                                 E.dE + T(0.5) * dt * (d0.dE + d1.dE),
+                                 E.dr + T(0.5) * dt * (d0.dr + d1.dr)},
+                        gm1);
+  }
+  const double nd = ceil((double)(dt * fabs(d0.v)) / (double)(c.frac * E.v));
+  const int N = nd < 1.0 ? 1 : (nd > (double)c.nsub_max ? c.nsub_max : (int)nd);
+  const T h = dt / (T)N;
+  for (int k = 0; k < N; ++k) {
+    const Dual2<T> d = k == 0 ? d0 : cool_edot_d(c, rho, E, gm1);
+    Dual2<T> dE{d.v * h, d.dE * h, d.dr * h};
+    const Dual2<T> lim{c.frac * E.v, c.frac * E.dE, c.frac * E.dr};
+    if (dE.v > lim.v) dE = lim;
+    if (dE.v < -lim.v) dE = Dual2<T>{-lim.v, -lim.dE, -lim.dr};
+    E = cool_floor_d(c, rho, Dual2<T>{E.v + dE.v, E.dE + dE.dE, E.dr + dE.dr}, gm1);
+  }
+  return E;
+}
+
+// reverse of the cooling of one cell at the state U it acted on:
+// E' = ek + C(rho, E - ek), ek = |m|^2/(2 rho)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cool_table_vjp(const T* __restrict__ U, long long N,
+                                                        T gamma, T dt, CoolTable<T> c,
+                                                        const T* __restrict__ lin, T* lout) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const T gm1 = gamma - T(1);
+  const T rho = U[q], mx = U[N + q], my = U[2 * N + q], mz = U[3 * N + q];
+  const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / rho;
+  const Dual2<T> r = cool_eth_step_d(c, rho, U[4 * N + q] - ek, dt, gm1);
+  const T Eb = lin[4 * N + q];
+  const T ekb = Eb * (T(1) - r.dE);
+  lout[q] = lin[q] + Eb * r.dr - ekb * ek / rho;
+  lout[N + q] = lin[N + q] + ekb * mx / rho;
+  lout[2 * N + q] = lin[2 * N + q] + ekb * my / rho;
+  lout[3 * N + q] = lin[3 * N + q] + ekb * mz / rho;
+  lout[4 * N + q] = Eb * r.dE;
+}
+
 // max |Edot| / E_th of a state (the first step's cooling-time limit)
 template <typename T>
 __global__ __launch_bounds__(256) void k_cool_rate(const T* __restrict__ U, long long N, T gamma,
@@ -160,6 +252,20 @@ hipError_t launch_cool_rate(const T* U, const StageGeom& g, T gamma, const CoolT
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_cool_table_vjp(const T* U, long long N, T gamma, T dt, const CoolTable<T>& c,
+                                 const T* lin, T* lout, hipStream_t s) {
+  hipLaunchKernelGGL((k_cool_table_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, U, N, gamma, dt, c,
+                     lin, lout);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cool_table_vjp<float>(const float*, long long, float, float,
+                                                 const CoolTable<float>&, const float*, float*,
+                                                 hipStream_t);
+template hipError_t launch_cool_table_vjp<double>(const double*, long long, double, double,
+                                                  const CoolTable<double>&, const double*,
+                                                  double*, hipStream_t);
 template hipError_t launch_cool_table<float>(float*, const StageGeom&, float, const double*,
                                              const CoolTable<float>&, DevClock*, hipStream_t);
 template hipError_t launch_cool_table<double>(double*, const StageGeom&, double, const double*,

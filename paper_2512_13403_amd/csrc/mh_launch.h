@@ -74,6 +74,9 @@ template <typename T>
 hipError_t launch_cool_table(T* U, const StageGeom& g, T gamma, const double* ih,
                              const CoolTable<T>& c, DevClock* clk, hipStream_t s);
 template <typename T>
+hipError_t launch_cool_table_vjp(const T* U, long long N, T gamma, T dt, const CoolTable<T>& c,
+                                 const T* lin, T* lout, hipStream_t s);
+template <typename T>
 hipError_t launch_cool_rate(const T* U, const StageGeom& g, T gamma, const CoolTable<T>& c,
                             DevClock* clk, hipStream_t s);
 hipError_t launch_clock_reset_health(DevClock* clk, hipStream_t s);

@@ -142,6 +142,21 @@ def test_adjoint_gravity_spectral(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("integ", [oracle.COOLINT_TRAPEZOID, oracle.COOLINT_SUBCYCLE,
+                                   oracle.COOLINT_AUTO])
+def test_adjoint_tabulated_cooling(dtype, integ):
+    """Reverse of the paper's tabulated cooling model with forcing."""
+    shape = (12, 14, 66)
+    U0 = wl.random_state(shape, seed=37, vmax=0.4, rho=(0.5, 2.0), p=(0.002, 1.0))
+    got, ref = gpu_vs_oracle_adjoint(shape, (1 / 66, 1 / 14, 1 / 12), U0, dtype,
+                                     flags=oracle.SRC_FORCING | oracle.SRC_COOLING, ou_seed=9,
+                                     cool_model=oracle.COOL_TABLE,
+                                     cool_table=wl.synthetic_cie_table(), cool_integrator=integ,
+                                     cool_frac=0.05, cool_nsub_max=50, **wl.COOLING_TABLE_MODEL)
+    assert rel_err(got, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_gravity_cooling(dtype):
     n = 16
     U0 = wl.grf_density_state(n, seed=5)

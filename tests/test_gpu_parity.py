@@ -489,17 +489,6 @@ def test_tabulated_cooling_with_gravity_and_cfl_limit(solver):
     assert rel_err(s.get_state(), sim.U) < 1e-11
 
 
-def test_adjoint_rejects_tabulated_cooling():
-    import torch
-
-    shape = (8, 8, 8)
-    s, _ = pair(shape, (1 / 8,) * 3, dtype="f64", flags=oracle.SRC_COOLING, **TABLE_MODEL)
-    U = torch.tensor(_multiphase_state(shape, 1), dtype=torch.float64, device="cuda:0")
-    with pytest.raises(mh.MHError) as e:
-        s.adjoint_step(U, 1e-3, 0, U.clone())
-    assert e.value.status == mh.E_UNSUPPORTED
-
-
 def test_gravity_tolerance_cycle_counts():
     n = 32
     U0 = wl.grf_density_state(n, seed=1)
