@@ -266,11 +266,16 @@ mh_status mh_adjoint_step(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace
  * t = 9(dz+1) + 3(dy+1) + (dx+1) reads the input at (x+dx, y+dy, z+dz).
  * States are device arrays [batch][5][n][n][n] of dtype MH_F32 or MH_F64.
  * n must be a multiple of 16. */
+enum { MH_CORR_STATE = 0, MH_CORR_FLUX = 1 };
+
 typedef struct mh_corr_desc {
   int32_t n;          /* cells per axis of each (cubic, periodic) state */
   int32_t batch;      /* states per call */
   int32_t dtype;      /* MH_F32 or MH_F64 */
-  int32_t reserved0;
+  int32_t mode;       /* MH_CORR_STATE: the corrected state U + scale Net(U);
+                         MH_CORR_FLUX: the correction scale Net(U) alone, a
+                         learned flux field for mh_set_flux_correction
+                         (Sec. 8), without floor or fallback */
   double gamma;       /* adiabatic index (for the positivity floor) */
   double mean[5];     /* per-channel standardisation of the network input */
   double std[5];
@@ -292,7 +297,7 @@ mh_status mh_corr_init(const mh_corr_desc *desc, void *workspace, size_t bytes, 
  * the ADAM moments and iteration count. */
 mh_status mh_corr_set_params(mh_corr *c, const float *theta, int where);
 mh_status mh_corr_get_params(mh_corr *c, float *theta, int where);
-/* U_out = floor(U + scale * Net(U)); when any value is non-finite or more
+/* State mode: U_out = floor(U + scale * Net(U)); when any value is non-finite or more
  * than fallback_frac of the cells needed the floor, U_out = U instead
  * (the plain coarse state; the choice is made on the device).  U_out must
  * not alias U.  floored / fell_back are optional host outputs: when either
@@ -301,9 +306,12 @@ mh_status mh_corr_get_params(mh_corr *c, float *theta, int where);
  * pass's values). */
 mh_status mh_corr_apply(mh_corr *c, const void *U, void *U_out, int64_t *floored,
                         int32_t *fell_back);
+/* (Flux mode: U_out = scale * Net(U); floored and fell_back report 0.) */
 /* Loss against the target batch and its gradient in the parameters (to host
  * or device memory): zero_grad + backward(U, target) + get_grad;
- * synchronises. */
+ * synchronises.  State mode only (MH_E_INVALID in flux mode, whose output
+ * is trained through the solver with mh_corr_backward and an upstream
+ * gradient). */
 mh_status mh_corr_loss_grad(mh_corr *c, const void *U, const void *target, double *loss,
                             float *grad, int where);
 /* One ADAM iteration (learning rate lr) on the loss against target; returns
@@ -320,8 +328,9 @@ mh_status mh_corr_zero_grad(mh_corr *c);
  * When gU is non-NULL it receives dL/dU (device array like U, aliasing
  * neither U nor gUc): the upstream gradient (residual path) plus the network
  * path; the positivity floor and the two-part input split pass the gradient
- * through unchanged.  Used to unroll training through several solver steps
- * together with mh_adjoint_step. */
+ * through unchanged.  In flux mode target must be NULL and gU receives the
+ * network path alone (the output has no residual term).  Used to unroll
+ * training through several solver steps together with mh_adjoint_step. */
 mh_status mh_corr_backward(mh_corr *c, const void *U, const void *target, const void *gUc,
                            double *loss, void *gU);
 /* One ADAM iteration with the accumulated gradient (learning rate lr). */

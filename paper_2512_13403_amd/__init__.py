@@ -29,6 +29,7 @@ RK_SSP2, RK_SSP3, RK_EULER = 0, 1, 2
 MG_V, MG_W = 0, 1
 SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
 GRAV_MG, GRAV_FFT = 0, 1
+CORR_STATE, CORR_FLUX = 0, 1
 COOL_EXACT2, COOL_TABLE = 0, 1
 COOLINT_TRAPEZOID, COOLINT_SUBCYCLE, COOLINT_AUTO = 0, 1, 2
 COOL_TABMAX = 64
@@ -81,7 +82,7 @@ class PhysicsDesc(ctypes.Structure):
 class CorrDesc(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32), ("batch", ctypes.c_int32), ("dtype", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32), ("gamma", ctypes.c_double),
+        ("mode", ctypes.c_int32), ("gamma", ctypes.c_double),
         ("mean", ctypes.c_double * 5), ("std", ctypes.c_double * 5),
         ("scale", ctypes.c_double * 5), ("loss_w", ctypes.c_double * 5),
         ("floor_rel", ctypes.c_double), ("fallback_frac", ctypes.c_double),
@@ -459,8 +460,10 @@ NPARAM_CORRECTOR = 36357
 
 def corr_desc(n: int, batch: int, dtype="f32", gamma=5.0 / 3.0, mean=(0.0,) * 5, std=(1.0,) * 5,
               scale=(1.0,) * 5, loss_w=(1.0,) * 5, floor_rel=1e-6,
-              fallback_frac=1e-3) -> CorrDesc:
+              fallback_frac=1e-3, mode=0) -> CorrDesc:
+    """mode: CORR_STATE (corrected state) or CORR_FLUX (the learned flux field)."""
     d = CorrDesc()
+    d.mode = mode
     d.n, d.batch = n, batch
     d.dtype = F64 if dtype in ("f64", "float64", F64) else F32
     d.gamma = gamma

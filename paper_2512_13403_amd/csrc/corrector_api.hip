@@ -70,6 +70,7 @@ mh_status corr_validate(const mh_corr_desc* d) {
     if (!(d->std[c] > 0.0) || !std::isfinite(d->mean[c]) || !std::isfinite(d->scale[c]))
       return MH_E_INVALID;
   if (!(d->floor_rel >= 0.0) || !(d->fallback_frac >= 0.0)) return MH_E_INVALID;
+  if (d->mode != MH_CORR_STATE && d->mode != MH_CORR_FLUX) return MH_E_UNSUPPORTED;
   return MH_OK;
 }
 
@@ -170,7 +171,13 @@ extern "C" mh_status mh_corr_get_params(mh_corr* c, float* theta, int where) {
 
 template <typename T>
 static mh_status apply_impl(mh_corr* c, const T* U, T* out, int64_t* floored, int32_t* fell) {
-  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, out, false, c->stream));
+  if (c->d.mode == MH_CORR_FLUX) {
+    MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, out, false, false, c->stream));
+    if (floored) *floored = 0;
+    if (fell) *fell = 0;
+    return MH_OK;
+  }
+  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, out, false, true, c->stream));
   MH_CHK(corr_floor<T>(c->B, U, out, c->d.n, c->d.batch, c->d.gamma, c->d.floor_rel,
                        c->d.fallback_frac, c->stream));
   if (floored || fell) {
@@ -195,8 +202,9 @@ extern "C" mh_status mh_corr_apply(mh_corr* c, const void* U, void* U_out, int64
 template <typename T>
 static mh_status backward_impl(mh_corr* c, const T* U, const T* tgt, const T* gup, double* loss,
                                T* gU) {
-  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, (T*)nullptr, true, c->stream));
-  MH_CHK(corr_backward<T>(c->B, c->st, c->d.n, c->d.batch, U, tgt, gup, gU, c->stream));
+  MH_CHK(corr_forward<T>(c->B, c->st, c->d.n, c->d.batch, U, (T*)nullptr, true, true, c->stream));
+  MH_CHK(corr_backward<T>(c->B, c->st, c->d.n, c->d.batch, U, tgt, gup, gU,
+                          c->d.mode == MH_CORR_STATE, c->stream));
   if (loss && tgt) {
     double l;
     MH_CHK(hipMemcpyAsync(&l, c->B.loss, sizeof l, hipMemcpyDeviceToHost, c->stream));
@@ -224,6 +232,7 @@ extern "C" mh_status mh_corr_zero_grad(mh_corr* c) {
 extern "C" mh_status mh_corr_backward(mh_corr* c, const void* U, const void* target,
                                       const void* gUc, double* loss, void* gU) {
   if (!c || !U || (!target && !gUc) || (gU && (gU == U || gU == gUc))) return MH_E_INVALID;
+  if (c->d.mode == MH_CORR_FLUX && target) return MH_E_INVALID;
   return backward_any(c, U, target, gUc, loss, gU);
 }
 
@@ -246,6 +255,7 @@ extern "C" mh_status mh_corr_get_grad(mh_corr* c, float* grad, int where) {
 extern "C" mh_status mh_corr_loss_grad(mh_corr* c, const void* U, const void* target, double* loss,
                                        float* grad, int where) {
   if (!c || !U || !target || (grad && where != MH_HOST && where != MH_DEVICE)) return MH_E_INVALID;
+  if (c->d.mode == MH_CORR_FLUX) return MH_E_INVALID;
   MH_CHK(corr_zero_grad(c->B, c->stream));
   mh_status s = backward_any(c, U, target, nullptr, loss, nullptr);
   if (s != MH_OK) return s;

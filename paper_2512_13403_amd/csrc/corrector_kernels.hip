@@ -394,14 +394,16 @@ __global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ U, in
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ U, const float* __restrict__ y,
                                                   int n, long long cells, CorrStats st,
-                                                  T* __restrict__ out) {
+                                                  T* __restrict__ out, int add_u) {
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
   if (cell >= cells) return;
   const long long n3 = (long long)n * n * n;
   const long long b = cell / n3, q = cell % n3;
 #pragma unroll
-  for (int c = 0; c < 5; ++c)
-    out[(b * 5 + c) * n3 + q] = U[(b * 5 + c) * n3 + q] + (T)(st.scale[c] * (double)y[cell * 16 + c]);
+  for (int c = 0; c < 5; ++c) {
+    const T d = (T)(st.scale[c] * (double)y[cell * 16 + c]);
+    out[(b * 5 + c) * n3 + q] = add_u ? U[(b * 5 + c) * n3 + q] + d : d;
+  }
 }
 
 // per-sample sums of rho and P of the uncorrected state (two-stage, fixed order)
@@ -502,7 +504,7 @@ __global__ __launch_bounds__(256) void k_loss(const T* __restrict__ U, const flo
                                               const T* __restrict__ gup, int n, long long cells,
                                               CorrStats st, double* __restrict__ part,
                                               unsigned short* __restrict__ dy,
-                                              T* __restrict__ gfull) {
+                                              T* __restrict__ gfull, int ident) {
   __shared__ double sl[256];
   const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
   double l = 0.0;
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(256) void k_loss(const T* __restrict__ U, const flo
         g = 2.0 * st.lw[c] * d / s2 / (double)cells;
       }
       if (gup) g += (double)gup[(b * 5 + c) * n3 + q];
-      if (gfull) gfull[(b * 5 + c) * n3 + q] = (T)g;
+      if (gfull) gfull[(b * 5 + c) * n3 + q] = ident ? (T)g : T(0);
       v[c] = f2bf((float)(st.scale[c] * g));
     }
     __builtin_memcpy(dy + cell * 16, v, 16);
@@ -657,7 +659,7 @@ hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s) {
 
 template <typename T>
 hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
-                        T* out, bool store_z, hipStream_t s) {
+                        T* out, bool store_z, bool add_u, hipStream_t s) {
   const long long cells = (long long)batch * n * n * n;
   const unsigned conv_blocks = conv_grid(n, batch);
   hipLaunchKernelGGL((k_standardize<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, n, cells, st,
@@ -673,7 +675,7 @@ hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int ba
                      (unsigned short*)nullptr);
   if (out)
     hipLaunchKernelGGL((k_residual<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, B.y, n, cells,
-                       st, out);
+                       st, out, (int)add_u);
   return hipGetLastError();
 }
 
@@ -694,12 +696,12 @@ hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch
 
 template <typename T>
 hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
-                         const T* tgt, const T* gup, T* gU, hipStream_t s) {
+                         const T* tgt, const T* gup, T* gU, bool ident, hipStream_t s) {
   const long long cells = (long long)batch * n * n * n;
   const unsigned conv_blocks = conv_grid(n, batch);
   const unsigned lb = blocks(cells, 256);
   hipLaunchKernelGGL((k_loss<T>), dim3(lb), dim3(256), 0, s, U, B.y, tgt, gup, n, cells, st,
-                     B.dpart, B.dy16, gU);
+                     B.dpart, B.dy16, gU, (int)ident);
   hipLaunchKernelGGL(k_dsum, dim3(1), dim3(256), 0, s, B.dpart, (int)lb, B.loss);
   hipLaunchKernelGGL(k_pad16to32, dim3(lb), dim3(256), 0, s, B.dy16, cells, B.dy32);
   const int nblk = (int)(cells / (CTX * CTY * CTZ));
@@ -752,11 +754,11 @@ hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStre
 
 #define CORR_INSTANTIATE(T)                                                                       \
   template hipError_t corr_forward<T>(const CorrBuffers&, const CorrStats&, int, int, const T*, T*, \
-                                      bool, hipStream_t);                                         \
+                                      bool, bool, hipStream_t);                                   \
   template hipError_t corr_floor<T>(const CorrBuffers&, const T*, T*, int, int, double, double,    \
                                     double, hipStream_t);                                         \
   template hipError_t corr_backward<T>(const CorrBuffers&, const CorrStats&, int, int, const T*,  \
-                                       const T*, const T*, T*, hipStream_t);                      \
+                                       const T*, const T*, T*, bool, hipStream_t);                \
   template hipError_t launch_block_average<T>(const T*, int, int, T*, hipStream_t);
 CORR_INSTANTIATE(float)
 CORR_INSTANTIATE(double)

@@ -39,13 +39,13 @@ struct CorrBuffers {
 hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s);
 template <typename T>
 hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
-                        T* out, bool store_z, hipStream_t s);
+                        T* out, bool store_z, bool add_u, hipStream_t s);
 template <typename T>
 hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch, double gamma,
                       double frel, double fallback_frac, hipStream_t s);
 template <typename T>
 hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
-                         const T* tgt, const T* gup, T* gU, hipStream_t s);
+                         const T* tgt, const T* gup, T* gU, bool ident, hipStream_t s);
 hipError_t corr_zero_grad(const CorrBuffers& B, hipStream_t s);
 hipError_t corr_adam(const CorrBuffers& B, int it, float lr, hipStream_t s);
 template <typename T>

@@ -275,3 +275,52 @@ def test_block_average(dtype, r):
     # conservation: the coarse totals times r^3 are the fine totals
     assert np.allclose(got.astype(np.float64).sum(axis=(1, 2, 3)) * r ** 3, F.sum(axis=(1, 2, 3)),
                        rtol=1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_flux_mode_output_and_gradients(dtype):
+    """Flux mode: the output is scale * Net(U) alone, and the reverse pass has
+    no residual term in dL/dU."""
+    n, batch = 16, 2
+    U = batch_state(n, batch, 130, dtype)
+    gup = as_input(1e-3 * np.random.default_rng(131).standard_normal(U.shape), dtype)
+    mean, std = stats(U)
+    scale = np.array([2e-2, 1e-2, 1e-2, 1e-2, 3e-2])
+    d = mh.corr_desc(n, batch, dtype, GAMMA, mean, std, scale, (1.0,) * 5, 1e-6, 1e-3,
+                     mode=mh.CORR_FLUX)
+    c = mh.Corrector(d)
+    th = params(seed=3)
+    c.set_params(th)
+    Ud, Gd = torch_dev(U, dtype), torch_dev(gup, dtype)
+    out, nfl, fb = c.apply(Ud)
+    assert nfl == 0 and not fb
+    y = c.activation(5)[:, :5]
+    ref = np.moveaxis(to_oracle(y, batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
+    assert np.array_equal(out.cpu().numpy(), as_input(ref, dtype))
+    # the same network in state mode gives U + the same correction
+    ds = mh.corr_desc(n, batch, dtype, GAMMA, mean, std, scale, (1.0,) * 5, 1e-6, 1e-3)
+    cs = mh.Corrector(ds)
+    cs.set_params(th)
+    outs, _, _ = cs.apply(Ud)
+    assert np.array_equal(cs.activation(5), c.activation(5))
+    tol = 1e-15 if dtype == "f64" else 2e-7
+    assert rel_inf(outs.cpu().numpy(), U + out.cpu().numpy()) < tol
+    # reverse pass with an upstream gradient against the oracle's
+    c.zero_grad()
+    _, gU = c.backward(Ud, gUc=Gd, input_grad=True)
+    p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
+    x0 = c.activation(0)
+    cache = dict(x=to_oracle(x0[:, :5] + x0[:, 5:10], batch, n),
+                 z1=to_oracle(c.activation(1), batch, n), h1=to_oracle(c.activation(2), batch, n),
+                 z2=to_oracle(c.activation(3), batch, n), h2=to_oracle(c.activation(4), batch, n),
+                 y=to_oracle(c.activation(5)[:, :5], batch, n), p=p, rd=oc.bf16_round)
+    gref = oc.backward(gup, cache, scale)
+    assert np.linalg.norm(c.grad() - gref) / np.linalg.norm(gref) < 2e-3
+    gUref = oc.input_grad(gup, cache, std) - gup
+    gU = gU.cpu().numpy()
+    assert np.linalg.norm(gU - gUref) / np.linalg.norm(gUref) < 2e-3
+    # training against a target is a state-mode operation
+    with pytest.raises(mh.MHError):
+        c.backward(Ud, Ud)
+    with pytest.raises(mh.MHError):
+        c.loss_grad(Ud, Ud)

@@ -173,7 +173,9 @@ def test_corrector_workspace_and_validation():
         (lambda d: setattr(d, "gamma", 0.5), mh.E_INVALID),
         (lambda d: d.std.__setitem__(2, 0.0), mh.E_INVALID),
         (lambda d: setattr(d, "floor_rel", -1.0), mh.E_INVALID),
+        (lambda d: setattr(d, "mode", 2), mh.E_UNSUPPORTED),
     ]
+    assert corr_ws(mh.corr_desc(32, 1, "f64", mode=mh.CORR_FLUX))[0] == mh.OK
     for mutate, status in bad:
         d = mh.corr_desc(32, 1, "f64")
         mutate(d)
