@@ -18,7 +18,7 @@ inline size_t calign(size_t x) { return (x + CALIGN - 1) & ~(CALIGN - 1); }
 struct CorrLayout {
   size_t theta, m, v, grad, w1, w2, w3, w1t, w2t, w3t, x0, z1, h1, z2, h2, y, gx, dy16, dy32, dz2,
       dz1;
-  size_t wpart, dpart, loss, counters, total;
+  size_t wpart, dpart, loss, counters, cpart, total;
 };
 
 CorrLayout corr_layout(const mh_corr_desc* d) {
@@ -53,10 +53,14 @@ CorrLayout corr_layout(const mh_corr_desc* d) {
   L.dz2 = take(cells * 32 * 2);
   L.dz1 = take(cells * 32 * 2);
   L.wpart = take((size_t)28 * corr_wgrad_groups((long long)cells) * 32 * 32 * 4);
-  const size_t nd = std::max((cells + 255) / 256, (size_t)d->batch * 64 * 2);
+  // per-block partial sums, or the floor partials (64 blocks per sample) and
+  // the two floor values of each sample after them
+  const size_t nd = std::max((cells + 255) / 256, (size_t)d->batch * (64 * 2 + 2));
   L.dpart = take(nd * sizeof(double));
   L.loss = take(sizeof(double));
   L.counters = take(2 * sizeof(unsigned long long));
+  // per-block floored / non-finite counts of the positivity floor
+  L.cpart = take(2 * ((cells + 255) / 256) * sizeof(unsigned long long));
   L.total = off;
   return L;
 }
@@ -125,7 +129,8 @@ extern "C" mh_status mh_corr_init(const mh_corr_desc* d, void* workspace, size_t
                      H(L.w2t), H(L.w3t), H(L.x0), H(L.h1), H(L.h2), H(L.dy16), H(L.dy32),
                      H(L.dz2), H(L.dz1), F(L.z1), F(L.z2), F(L.y), F(L.gx), F(L.wpart),
                      reinterpret_cast<double*>(w + L.dpart), reinterpret_cast<double*>(w + L.loss),
-                     reinterpret_cast<unsigned long long*>(w + L.counters)};
+                     reinterpret_cast<unsigned long long*>(w + L.counters),
+                     reinterpret_cast<unsigned long long*>(w + L.cpart)};
   for (int k = 0; k < 5; ++k) {
     c->st.mean[k] = d->mean[k];
     c->st.std[k] = d->std[k];

@@ -32,6 +32,7 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned short)))) unsigned short u16x4;
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
   // round to nearest even
@@ -105,97 +106,154 @@ __device__ __forceinline__ int cslot(int h, int hx, int c) { return h * 4 + (c ^
 // the LDS tile and multiply them by the tap's 32 x COT weight block (bf16
 // [27][COT][32]), loaded once per tap and prefetched CPD taps ahead.
 template <int COT, int EPI>
-__global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__ in,
+__global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restrict__ in,
                                               const unsigned short* __restrict__ w,
                                               const float* __restrict__ bias, int nbias, int n,
                                               const float* __restrict__ zin,
                                               float* __restrict__ fout,
-                                              unsigned short* __restrict__ hout) {
+                                              unsigned short* __restrict__ hout, int ntiles) {
   __shared__ u32x4 tile[CNH * 4];
+  constexpr int NLD = (CNH * 4 + 255) / 256;  // 16-byte halo chunks per thread
   const int ntx = n / CTX, nty = n / CTY, ntz = n / CTZ;
-  int t = blockIdx.x;
-  const int bx = t % ntx;
-  t /= ntx;
-  const int by = t % nty;
-  t /= nty;
-  const int bz = t % ntz;
-  const long long b = t / ntz;
-  const int x0 = bx * CTX, y0 = by * CTY, z0 = bz * CTZ;
-  const long long base = b * n * n * (long long)n;
-  for (int i = threadIdx.x; i < CNH * 4; i += 256) {
-    const int h = i >> 2, c = i & 3;
-    const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
-    const long long src = base + ((long long)wrap(z0 - 1 + hz, n) * n + wrap(y0 - 1 + hy, n)) * n +
-                          wrap(x0 - 1 + hx, n);
-    u32x4 v;
-    __builtin_memcpy(&v, in + src * 32 + c * 8, 16);
-    tile[cslot(h, hx, c)] = v;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = lane & 15, grp = lane >> 4;
-  f32x4 acc[CROWS][COT / 16];
+  // tile t: origin (x0, y0, z0) in sample b, whose first cell is `base`
+  auto origin = [&](int t, int& x0, int& y0, int& z0, long long& base) {
+    const int bx = t % ntx;
+    t /= ntx;
+    const int by = t % nty;
+    t /= nty;
+    const int bz = t % ntz;
+    base = (long long)(t / ntz) * n * n * (long long)n;
+    x0 = bx * CTX;
+    y0 = by * CTY;
+    z0 = bz * CTZ;
+  };
+  // a persistent workgroup walks the tiles t = blockIdx.x, + gridDim.x, ...;
+  // the halo of its next tile is loaded into registers while the current
+  // tile's outputs are formed and stored, then written to LDS
+  // (the thread index is made opaque where the chunk coordinates are
+  // derived, so that they are recomputed per tile rather than hoisted out of
+  // the tile loop and held in registers)
+  u32x4 pre[NLD];
+  auto fetch = [&](int t) {
+    int x0, y0, z0;
+    long long base;
+    origin(t, x0, y0, z0, base);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
 #pragma unroll
-  for (int r = 0; r < CROWS; ++r)
-#pragma unroll
-    for (int nt = 0; nt < COT / 16; ++nt) acc[r][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // weights: CPD taps in flight (a register ring), so the load of a tap's
-  // block is issued CPD taps before its MFMAs
-  const unsigned short* wl = w + row * 32 + 8 * grp;
-  bf16x8 bq[CPD][COT / 16];
-#pragma unroll
-  for (int p = 0; p < CPD; ++p)
-#pragma unroll
-    for (int nt = 0; nt < COT / 16; ++nt) bq[p][nt] = load8(wl + (p * COT + nt * 16) * 32);
-#pragma unroll
-  for (int tap = 0; tap < 27; ++tap) {
-    bf16x8 bw[COT / 16];
-#pragma unroll
-    for (int nt = 0; nt < COT / 16; ++nt) bw[nt] = bq[tap % CPD][nt];
-    if (tap + CPD < 27) {
-#pragma unroll
-      for (int nt = 0; nt < COT / 16; ++nt)
-        bq[tap % CPD][nt] = load8(wl + ((tap + CPD) * COT + nt * 16) * 32);
+    for (int k = 0; k < NLD; ++k) {
+      // lanes past the last chunk load the last chunk again (unused): every
+      // load is unconditional
+      const int i = min(tid + 256 * k, CNH * 4 - 1);
+      const int h = i >> 2, c = i & 3;
+      const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
+      const long long src = base +
+                            ((long long)wrap(z0 - 1 + hz, n) * n + wrap(y0 - 1 + hy, n)) * n +
+                            wrap(x0 - 1 + hx, n);
+      __builtin_memcpy(&pre[k], in + src * 32 + c * 8, 16);
     }
-    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-    const int hx = row + 1 + dx;
+  };
+  fetch(blockIdx.x);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = tid + 256 * k;
+      if (i < CNH * 4) {
+        const int h = i >> 2;
+        tile[cslot(h, h % CHX, i & 3)] = pre[k];
+      }
+    }
+    __syncthreads();
+    int x0, y0, z0;
+    long long base;
+    origin(t, x0, y0, z0, base);
+    const int lane = tid & 63, wave = tid >> 6;  // (tid: opaque, see above)
+    const int row = lane & 15, grp = lane >> 4;
+    f32x4 acc[CROWS][COT / 16];
+#pragma unroll
+    for (int r = 0; r < CROWS; ++r)
+#pragma unroll
+      for (int nt = 0; nt < COT / 16; ++nt) acc[r][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // weights: CPD taps in flight (a register ring), so the load of a tap's
+    // block is issued CPD taps before its MFMAs
+    // (opaque per tile: the weight loads stay inside the tile loop instead of
+    // being hoisted out of it and held, all 27 taps, in registers)
+    const unsigned short* wl = w + row * 32 + 8 * grp;
+    asm volatile("" : "+v"(wl));
+    bf16x8 bq[CPD][COT / 16];
+#pragma unroll
+    for (int p = 0; p < CPD; ++p)
+#pragma unroll
+      for (int nt = 0; nt < COT / 16; ++nt) bq[p][nt] = load8(wl + (p * COT + nt * 16) * 32);
+#pragma unroll
+    for (int tap = 0; tap < 27; ++tap) {
+      bf16x8 bw[COT / 16];
+#pragma unroll
+      for (int nt = 0; nt < COT / 16; ++nt) bw[nt] = bq[tap % CPD][nt];
+      if (tap + CPD < 27) {
+#pragma unroll
+        for (int nt = 0; nt < COT / 16; ++nt)
+          bq[tap % CPD][nt] = load8(wl + ((tap + CPD) * COT + nt * 16) * 32);
+      }
+      const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+      const int hx = row + 1 + dx;
+#pragma unroll
+      for (int r = 0; r < CROWS; ++r) {
+        const int j = wave * CROWS + r;
+        const int hy = j % CTY + 1 + dy, hz = j / CTY + 1 + dz;
+        const u32x4 raw = tile[cslot((hz * CHY + hy) * CHX + hx, hx, grp)];
+        bf16x8 a;
+        __builtin_memcpy(&a, &raw, 16);
+#pragma unroll
+        for (int nt = 0; nt < COT / 16; ++nt)
+          acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[nt], a, acc[r][nt], 0, 0, 0);
+      }
+    }
+    // the next tile's loads are in flight during the epilogue
+    if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);
+    // the weights are the A operand (rows: output channels) and the shifted
+    // inputs B (columns: the row's 16 cells), so lane (row, grp) holds output
+    // channels nt * 16 + 4 grp .. + 3 of cell x0 + row: four consecutive
+    // channels, written with one vector store per (row, tile)
 #pragma unroll
     for (int r = 0; r < CROWS; ++r) {
       const int j = wave * CROWS + r;
-      const int hy = j % CTY + 1 + dy, hz = j / CTY + 1 + dz;
-      const u32x4 raw = tile[cslot((hz * CHY + hy) * CHX + hx, hx, grp)];
-      bf16x8 a;
-      __builtin_memcpy(&a, &raw, 16);
+      const long long cell =
+          base + ((long long)(z0 + j / CTY) * n + (y0 + j % CTY)) * n + x0 + row;
 #pragma unroll
-      for (int nt = 0; nt < COT / 16; ++nt)
-        acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[nt], acc[r][nt], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < CROWS; ++r) {
-    const int j = wave * CROWS + r;
-    const long long rowcell = base + ((long long)(z0 + j / CTY) * n + (y0 + j % CTY)) * n + x0;
-#pragma unroll
-    for (int nt = 0; nt < COT / 16; ++nt) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const long long cell = rowcell + 4 * grp + q;
-        const int co = nt * 16 + row;
-        const float v = acc[r][nt][q];
+      for (int nt = 0; nt < COT / 16; ++nt) {
+        const int co = nt * 16 + 4 * grp;
         const long long o = cell * COT + co;
+        const f32x4 v = acc[r][nt];
         if (EPI == EPI_GELU) {
-          const float zz = v + bias[co];
-          if (fout) fout[o] = zz;
-          hout[o] = f2bf(gelu(zz));
+          f32x4 zz;
+          unsigned short hv[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            zz[q] = v[q] + bias[co + q];
+            hv[q] = f2bf(gelu(zz[q]));
+          }
+          if (fout) *(f32x4*)(fout + o) = zz;
+          *(u16x4*)(hout + o) = u16x4{hv[0], hv[1], hv[2], hv[3]};
         } else if (EPI == EPI_LINEAR) {
-          fout[o] = v + (co < nbias ? bias[co] : 0.f);
+          f32x4 y;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) y[q] = v[q] + (co + q < nbias ? bias[co + q] : 0.f);
+          *(f32x4*)(fout + o) = y;
         } else if (EPI == EPI_GELU_BWD) {
-          hout[o] = f2bf(v * gelu_grad(zin[o]));
+          const f32x4 zi = *(const f32x4*)(zin + o);
+          unsigned short hv[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) hv[q] = f2bf(v[q] * gelu_grad(zi[q]));
+          *(u16x4*)(hout + o) = u16x4{hv[0], hv[1], hv[2], hv[3]};
         } else {
-          fout[o] = v;
+          *(f32x4*)(fout + o) = v;
         }
       }
     }
+    __syncthreads();  // the tile is read by every wave before the next is stored
   }
 }
 
@@ -438,40 +496,87 @@ __global__ __launch_bounds__(256) void k_rho_p_partial(const T* __restrict__ U, 
 
 // positivity floor: rho >= f <rho>, then P >= f <P> by raising E at fixed m;
 // counts floored and non-finite cells
-template <typename T>
-__global__ __launch_bounds__(256) void k_floor(T* __restrict__ U, long long n3, long long cells, double gm1,
-                                               double frel, const double* __restrict__ part,
-                                               int blocks_per_sample,
-                                               unsigned long long* __restrict__ counters) {
-  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (cell >= cells) return;
-  const long long b = cell / n3, q = cell % n3;
+// the floor values of each sample, frel times the mean density and pressure,
+// from the k_rho_p_partial sums (one thread per sample, partials added in
+// block order): ref[2 b] = rho floor, ref[2 b + 1] = pressure floor
+__global__ __launch_bounds__(64) void k_floor_ref(const double* __restrict__ part,
+                                                  int blocks_per_sample, int batch, long long n3,
+                                                  double frel, double* __restrict__ ref) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= batch) return;
   double sr = 0.0, sp = 0.0;
   for (int k = 0; k < blocks_per_sample; ++k) {
     sr += part[2 * (b * blocks_per_sample + k)];
     sp += part[2 * (b * blocks_per_sample + k) + 1];
   }
-  const double rf = frel * sr / (double)n3, pf = frel * sp / (double)n3;
-  T* u = U + b * 5 * n3 + q;
-  bool fl = false;
-  double rho = (double)u[0];
-  if (rho < rf) {
-    rho = rf;
-    u[0] = (T)rf;
-    fl = true;
-  }
-  const double mx = (double)u[n3], my = (double)u[2 * n3], mz = (double)u[3 * n3];
-  const double ek = 0.5 * (mx * mx + my * my + mz * mz) / rho;
-  const double p = gm1 * ((double)u[4 * n3] - ek);
-  if (p < pf) {
-    u[4 * n3] = (T)(ek + pf / gm1);
-    fl = true;
-  }
-  const bool bad = !(isfinite(rho) && isfinite(mx) && isfinite(my) && isfinite(mz) &&
-                     isfinite((double)u[4 * n3]));
-  if (fl) atomicAdd(&counters[0], 1ull);
-  if (bad) atomicAdd(&counters[1], 1ull);
+  ref[2 * b] = frel * sr / (double)n3;
+  ref[2 * b + 1] = frel * sp / (double)n3;
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_floor(T* __restrict__ U, long long n3, long long cells, double gm1,
+                                               const double* __restrict__ ref,
+                                               unsigned long long* __restrict__ cpart) {
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  bool fl = false, bad = false;
+  if (cell < cells) {
+    const long long b = cell / n3, q = cell % n3;
+    const double rf = ref[2 * b], pf = ref[2 * b + 1];
+    T* u = U + b * 5 * n3 + q;
+    double rho = (double)u[0];
+    if (rho < rf) {
+      rho = rf;
+      u[0] = (T)rf;
+      fl = true;
+    }
+    const double mx = (double)u[n3], my = (double)u[2 * n3], mz = (double)u[3 * n3];
+    const double ek = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+    const double p = gm1 * ((double)u[4 * n3] - ek);
+    if (p < pf) {
+      u[4 * n3] = (T)(ek + pf / gm1);
+      fl = true;
+    }
+    bad = !(isfinite(rho) && isfinite(mx) && isfinite(my) && isfinite(mz) &&
+            isfinite((double)u[4 * n3]));
+  }
+  // the block's counts, without atomics (a mostly floored state would
+  // serialise them on two addresses); k_count_sum adds the blocks
+  __shared__ unsigned long long sc[2][4];
+  const unsigned long long nf = __popcll(__ballot(fl)), nb = __popcll(__ballot(bad));
+  if ((threadIdx.x & 63) == 0) {
+    sc[0][threadIdx.x >> 6] = nf;
+    sc[1][threadIdx.x >> 6] = nb;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2)
+    cpart[2 * blockIdx.x + threadIdx.x] =
+        sc[threadIdx.x][0] + sc[threadIdx.x][1] + sc[threadIdx.x][2] + sc[threadIdx.x][3];
+}
+
+// counters[k] = sum over blocks of cpart[2 b + k] (fixed order)
+__global__ __launch_bounds__(256) void k_count_sum(const unsigned long long* __restrict__ cpart,
+                                                   int nblocks,
+                                                   unsigned long long* __restrict__ counters) {
+  __shared__ unsigned long long s[2][256];
+  unsigned long long a = 0, b = 0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) {
+    a += cpart[2 * i];
+    b += cpart[2 * i + 1];
+  }
+  s[0][threadIdx.x] = a;
+  s[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + st];
+      s[1][threadIdx.x] += s[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) counters[threadIdx.x] = s[threadIdx.x][0];
+}
+
+
 
 // fallback on the device: when any value was non-finite or more than `limit`
 // cells were floored, out = U (the plain state); counters as k_floor left them
@@ -487,10 +592,6 @@ __global__ __launch_bounds__(256) void k_fallback(const T* __restrict__ U, T* __
 __global__ __launch_bounds__(256) void k_fill_f32(float* p, int count, float v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < count) p[i] = v;
-}
-
-__global__ __launch_bounds__(64) void k_zero_counters(unsigned long long* c) {
-  if (threadIdx.x < 2) c[threadIdx.x] = 0;
 }
 
 // upstream gradient of the network output: with a target T, the loss
@@ -643,6 +744,10 @@ inline unsigned conv_grid(int n, int batch) {
   return (unsigned)((long long)(n / CTX) * (n / CTY) * (n / CTZ) * batch);
 }
 
+// persistent convolution workgroups: three per CU of a 256-CU MI355X (the
+// LDS tile allows three), never more than there are tiles
+inline unsigned conv_wgs(unsigned ntiles) { return ntiles < 768u ? ntiles : 768u; }
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -664,15 +769,15 @@ hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int ba
   const unsigned conv_blocks = conv_grid(n, batch);
   hipLaunchKernelGGL((k_standardize<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, n, cells, st,
                      B.x0);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_blocks), dim3(256), 0, s, B.x0, B.w1,
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.x0, B.w1,
                      B.theta + CORR_OFF_B1, 32, n, (const float*)nullptr,
-                     store_z ? B.z1 : (float*)nullptr, B.h1);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_blocks), dim3(256), 0, s, B.h1, B.w2,
+                     store_z ? B.z1 : (float*)nullptr, B.h1, (int)conv_blocks);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.h1, B.w2,
                      B.theta + CORR_OFF_B2, 32, n, (const float*)nullptr,
-                     store_z ? B.z2 : (float*)nullptr, B.h2);
-  hipLaunchKernelGGL((k_conv<16, EPI_LINEAR>), dim3(conv_blocks), dim3(256), 0, s, B.h2, B.w3,
+                     store_z ? B.z2 : (float*)nullptr, B.h2, (int)conv_blocks);
+  hipLaunchKernelGGL((k_conv<16, EPI_LINEAR>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.h2, B.w3,
                      B.theta + CORR_OFF_B3, 5, n, (const float*)nullptr, B.y,
-                     (unsigned short*)nullptr);
+                     (unsigned short*)nullptr, (int)conv_blocks);
   if (out)
     hipLaunchKernelGGL((k_residual<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, B.y, n, cells,
                        st, out, (int)add_u);
@@ -684,11 +789,14 @@ hipError_t corr_floor(const CorrBuffers& B, const T* U, T* out, int n, int batch
                       double frel, double fallback_frac, hipStream_t s) {
   const long long n3 = (long long)n * n * n, cells = batch * n3;
   const int bps = 64;
-  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, B.counters);
   hipLaunchKernelGGL((k_rho_p_partial<T>), dim3(batch * bps), dim3(256), 0, s, U, n3, gamma - 1.0,
                      bps, B.dpart);
+  double* ref = B.dpart + 2 * batch * bps;
+  hipLaunchKernelGGL(k_floor_ref, dim3(blocks(batch, 64)), dim3(64), 0, s, B.dpart, bps, batch, n3, frel, ref);
   hipLaunchKernelGGL((k_floor<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, out, n3, cells,
-                     gamma - 1.0, frel, B.dpart, bps, B.counters);
+                     gamma - 1.0, ref, B.cpart);
+  hipLaunchKernelGGL(k_count_sum, dim3(1), dim3(256), 0, s, B.cpart, (int)blocks(cells, 256),
+                     B.counters);
   hipLaunchKernelGGL((k_fallback<T>), dim3(blocks(5 * cells, 256)), dim3(256), 0, s, U, out,
                      5 * cells, fallback_frac * (double)cells, B.counters);
   return hipGetLastError();
@@ -710,22 +818,22 @@ hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int b
   hipLaunchKernelGGL((k_wgrad<16>), dim3(nwg), dim3(256), 0, s, B.dy16, B.h2, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32 + 5, 8)), dim3(256), 0, s, B.wpart,
                      16, nwg, 5, 32, 0, B.grad + CORR_OFF_W3, B.grad + CORR_OFF_B3);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dy32, B.w3t,
-                     (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dy32, B.w3t,
+                     (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2, (int)conv_blocks);
   // layer 2
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz2, B.h1, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32 + 32, 8)), dim3(256), 0, s,
                      B.wpart, 32, nwg, 32, 32, 0, B.grad + CORR_OFF_W2, B.grad + CORR_OFF_B2);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_blocks), dim3(256), 0, s, B.dz2, B.w2t,
-                     (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1);
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz2, B.w2t,
+                     (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1, (int)conv_blocks);
   // layer 1
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5 + 32, 8)), dim3(256), 0, s,
                      B.wpart, 32, nwg, 32, 5, 1, B.grad + CORR_OFF_W1, B.grad + CORR_OFF_B1);
   if (gU) {
-    hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_blocks), dim3(256), 0, s, B.dz1, B.w1t,
+    hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz1, B.w1t,
                        (const float*)nullptr, 0, n, (const float*)nullptr, B.gx,
-                       (unsigned short*)nullptr);
+                       (unsigned short*)nullptr, (int)conv_blocks);
     hipLaunchKernelGGL((k_input_grad<T>), dim3(lb), dim3(256), 0, s, B.gx, n, cells, st, gU);
   }
   return hipGetLastError();

@@ -33,7 +33,8 @@ struct CorrBuffers {
   unsigned short *x0, *h1, *h2, *dy16, *dy32, *dz2, *dz1;
   float *z1, *z2, *y, *gx, *wpart;
   double *dpart, *loss;
-  unsigned long long* counters;
+  unsigned long long* counters;  // [floored cells, non-finite cells] of the last floor
+  unsigned long long* cpart;     // their per-block parts
 };
 
 hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s);
