@@ -261,17 +261,20 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
 // dz[cell][co] x[cell + off_tap][ci], on the same 16 x 4 x 4 halo tiles as
 // k_conv.  A persistent workgroup takes every gridDim.x-th block of cells; per
 // block it stages the layer input with its halo and the block's output
-// gradients in LDS, and wave w accumulates taps w, w + 4, ... in registers
-// over all its blocks: per MFMA the reduction runs over 32 cells (16 along x
-// in two rows), dz^T is the A operand (rows: output channels) and the shifted
-// input the B operand (columns: input channels).  Wave 3, which has one tap
-// fewer, also forms the bias gradient (slot 27).  Each workgroup writes its
-// partial [28][COT][32]; k_wgrad_reduce adds them in a fixed order
+// gradients in LDS.  Per MFMA the reduction runs over 32 cells (16 along x in
+// two rows), dz^T is the A operand (rows: output channels) and the shifted
+// input the B operand (columns: input channels).  The taps are grouped by
+// their (dy, dz) row: wave w takes the rows g = w, w + 4, w + 8 (< 9), each
+// with its three x shifts, so a lane reads the 10 input values of its 8-cell
+// strip once per row and channel tile and forms the three shifted operands
+// from them (the LDS reads, 16-bit, bound the kernel).  Wave 3, which has the
+// fewest rows, also forms the bias gradient (slot 27).  Each workgroup writes
+// its partial [28][COT][32]; k_wgrad_reduce adds them in a fixed order
 // (deterministic, no atomics).
-constexpr int WTAPS = 7;  // taps per wave: ceil(27 / 4)
+constexpr int WROWS = 3;  // (dy, dz) rows per wave: ceil(9 / 4)
 
 template <int COT>
-__global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict__ dz,
+__global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restrict__ dz,
                                                const unsigned short* __restrict__ x, int n,
                                                int nblocks, float* __restrict__ partial) {
   constexpr int CB = CTX * CTY * CTZ;  // cells per block
@@ -282,12 +285,16 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, grp = lane >> 4;
   const int ntx = n / CTX, nty = n / CTY, ntz = n / CTZ;
-  f32x4 acc[WTAPS][COT / 16][2];
+  // acc[row group][dx + 1][co tile][ci tile] (wave 3 keeps the bias gradient
+  // in acc[2][0], its third row group being empty)
+  f32x4 acc[WROWS][3][COT / 16][2];
 #pragma unroll
-  for (int tt = 0; tt < WTAPS; ++tt)
+  for (int gg = 0; gg < WROWS; ++gg)
 #pragma unroll
-    for (int mt = 0; mt < COT / 16; ++mt)
-      acc[tt][mt][0] = acc[tt][mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int mt = 0; mt < COT / 16; ++mt)
+        acc[gg][d][mt][0] = acc[gg][d][mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     int t = blk;
     const int bx = t % ntx;
@@ -332,56 +339,65 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
         __builtin_memcpy(&a[mt], v, 16);
       }
 #pragma unroll
-      for (int tt = 0; tt < WTAPS; ++tt) {
-        const int tap = wave + 4 * tt;
-        if (tap == 27) {
-          // the bias gradient, sum over cells of dz, as one more product with a
-          // B operand of ones (column 0 of the result is kept)
+      for (int gg = 0; gg < WROWS; ++gg) {
+        const int g = wave + 4 * gg;  // (dy, dz) row: dy = g % 3 - 1, dz = g / 3 - 1
+        if (g < 9) {
+          const int hrow = ((tz + 1 + g / 3 - 1) * CHY + (ty + 1 + g % 3 - 1)) * CHX;
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const int ci = ct * 16 + row;
+            // input channel ci at hx = xs .. xs + 9: the strip for dx = -1, 0, 1
+            unsigned short v[10];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) {
+              const int hx = xs + m;
+              v[m] = tile16[cslot(hrow + hx, hx, ci >> 3) * 8 + (ci & 7)];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              bf16x8 bv;
+              __builtin_memcpy(&bv, v + d, 16);
+#pragma unroll
+              for (int mt = 0; mt < COT / 16; ++mt)
+                acc[gg][d][mt][ct] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc[gg][d][mt][ct], 0, 0, 0);
+            }
+          }
+        } else if (g == 11) {
+          // wave 3's empty third row: the bias gradient, sum over cells of dz,
+          // as one more product with a B operand of ones (column 0 is kept)
           bf16x8 ones;
           const unsigned short one[8] = {0x3F80, 0x3F80, 0x3F80, 0x3F80,
                                          0x3F80, 0x3F80, 0x3F80, 0x3F80};
           __builtin_memcpy(&ones, one, 16);
 #pragma unroll
           for (int mt = 0; mt < COT / 16; ++mt)
-            acc[tt][mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], ones, acc[tt][mt][0],
-                                                                     0, 0, 0);
-        } else if (tap < 27) {
-          const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dzz = tap / 9 - 1;
-          const int hrow = ((tz + 1 + dzz) * CHY + (ty + 1 + dy)) * CHX;
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            const int ci = ct * 16 + row;
-            unsigned short v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const int hx = xs + j + 1 + dx;
-              v[j] = tile16[cslot(hrow + hx, hx, ci >> 3) * 8 + (ci & 7)];
-            }
-            bf16x8 bv;
-            __builtin_memcpy(&bv, v, 16);
-#pragma unroll
-            for (int mt = 0; mt < COT / 16; ++mt)
-              acc[tt][mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc[tt][mt][ct],
-                                                                        0, 0, 0);
-          }
+            acc[gg][0][mt][0] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], ones, acc[gg][0][mt][0], 0, 0, 0);
         }
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int tt = 0; tt < WTAPS; ++tt) {
-    const int tap = wave + 4 * tt;
-    if (tap < 28) {
+  for (int gg = 0; gg < WROWS; ++gg) {
+    const int g = wave + 4 * gg;
+    if (g < 9 || g == 11) {
 #pragma unroll
-      for (int mt = 0; mt < COT / 16; ++mt)
+      for (int d = 0; d < 3; ++d) {
+        const int tap = g < 9 ? 3 * g + d : 27;
+        if (g == 11 && d > 0) continue;
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int mt = 0; mt < COT / 16; ++mt)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int co = mt * 16 + 4 * grp + q, ci = ct * 16 + row;
-            partial[(((long long)blockIdx.x * 28 + tap) * COT + co) * 32 + ci] = acc[tt][mt][ct][q];
-          }
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int co = mt * 16 + 4 * grp + q, ci = ct * 16 + row;
+              partial[(((long long)blockIdx.x * 28 + tap) * COT + co) * 32 + ci] =
+                  acc[gg][d][mt][ct][q];
+            }
+      }
     }
   }
 }
@@ -390,38 +406,36 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short* __restrict_
 // [nwg][28][cot][32]; with `fold`, input channel ci also collects channel
 // ci + ci_real (the two bf16 parts of the network input share the first
 // layer's weights).  The co_real entries after the weights take the bias
-// gradient (slot 27, column 0) into gb.  Each output is summed by 32 lanes of
-// a wave (lane l takes partials l, l + 32, ...), then by a fixed butterfly:
-// the order is fixed, so the result is deterministic.
+// gradient (slot 27, column 0) into gb.  A block takes 64 consecutive
+// elements of a partial (one per lane, ci fastest, so each load of a wave is
+// 256 contiguous bytes); wave v adds the partials v, v + 4, ... in order, and
+// the four sums are added in a fixed order: the result is deterministic.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int cot,
                                                       int nwg, int co_real, int ci_real,
                                                       int fold, float* __restrict__ g,
                                                       float* __restrict__ gb) {
-  const int i = blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int l = threadIdx.x & 31;
-  const int nw = 27 * co_real * ci_real;
-  if (i >= nw + co_real) return;
-  int tap, ci, co;
-  if (i < nw) {
-    tap = i % 27;
-    ci = (i / 27) % ci_real;
-    co = i / (27 * ci_real);
-  } else {
-    tap = 27;
-    ci = 0;
-    co = i - nw;
-  }
+  __shared__ float sp[4][64];
+  const int per = 28 * cot * 32;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int ci = e % 32, co = (e / 32) % cot, tap = e / (32 * cot);
+  const bool need =
+      e < per && co < co_real && (tap == 27 ? ci == 0 : ci < ci_real);
   const bool two = fold && tap < 27;
   float acc = 0.f;
-  for (int c = l; c < nwg; c += 32) {
-    const float* pc = partial + (((long long)c * 28 + tap) * cot + co) * 32;
-    acc += two ? pc[ci] + pc[ci + ci_real] : pc[ci];
+  if (need) {
+#pragma unroll 8
+    for (int w = wv; w < nwg; w += 4) {
+      const float* pw = partial + (long long)w * per;
+      acc += two ? pw[e] + pw[e + ci_real] : pw[e];
+    }
   }
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-  if (l == 0) {
-    if (i < nw) g[i] += acc;
-    else gb[co] += acc;
+  sp[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0 && need) {
+    const float tot = ((sp[0][lane] + sp[1][lane]) + sp[2][lane]) + sp[3][lane];
+    if (tap < 27) g[(co * ci_real + ci) * 27 + tap] += tot;
+    else gb[co] += tot;
   }
 }
 
@@ -816,19 +830,19 @@ hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int b
   const int nwg = corr_wgrad_groups(cells);
   // layer 3: dW3, db3; dH2 -> dZ2 = dH2 * GELU'(Z2)
   hipLaunchKernelGGL((k_wgrad<16>), dim3(nwg), dim3(256), 0, s, B.dy16, B.h2, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 5 * 32 + 5, 8)), dim3(256), 0, s, B.wpart,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 16 * 32, 64)), dim3(256), 0, s, B.wpart,
                      16, nwg, 5, 32, 0, B.grad + CORR_OFF_W3, B.grad + CORR_OFF_B3);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dy32, B.w3t,
                      (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2, (int)conv_blocks);
   // layer 2
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz2, B.h1, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 32 + 32, 8)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 32 * 32, 64)), dim3(256), 0, s,
                      B.wpart, 32, nwg, 32, 32, 0, B.grad + CORR_OFF_W2, B.grad + CORR_OFF_B2);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz2, B.w2t,
                      (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1, (int)conv_blocks);
   // layer 1
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk, B.wpart);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(27 * 32 * 5 + 32, 8)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 32 * 32, 64)), dim3(256), 0, s,
                      B.wpart, 32, nwg, 32, 5, 1, B.grad + CORR_OFF_W1, B.grad + CORR_OFF_B1);
   if (gU) {
     hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz1, B.w1t,

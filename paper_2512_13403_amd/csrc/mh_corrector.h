@@ -15,7 +15,7 @@ constexpr int CORR_OFF_W3 = 32032;
 constexpr int CORR_OFF_B3 = 36352;
 constexpr int CORR_NPARAM = 36357;
 constexpr int CORR_BLOCK_CELLS = 256;  // cells per convolution tile (16 x 4 x 4)
-constexpr int CORR_WG_MAX = 256;       // persistent weight-gradient workgroups (one per CU)
+constexpr int CORR_WG_MAX = 512;       // persistent weight-gradient workgroups (two per CU)
 
 // workgroups of the weight-gradient kernel (each writes a [27][32][32] partial)
 inline int corr_wgrad_groups(long long cells) {
