@@ -106,7 +106,8 @@ __device__ __forceinline__ void hllc_flux(const T (&wl)[5], const T (&wr)[5], T 
   const T SK = left ? SL : SR, dK = left ? dl : dr;
   // total energy of the selected side only (the other side's is never used)
   const T EK = fmad(pK, gm1inv, (T(0.5) * rK) * fmad(uK, uK, fmad(aK, aK, bK * bK)));
-  const bool fan = left ? (SL < T(0)) : (SR > T(0));
+  // inside the star fan: S_L < 0 on the left side, S_R > 0 on the right
+  const bool fan = (left ? -SL : SR) > T(0);
   const T mK = rK * uK;
   const T FK0 = mK, FK1 = fmad(mK, uK, pK), FK2 = mK * aK, FK3 = mK * bK, FK4 = uK * (EK + pK);
   const T q = dev_rcp(SK - sstar);
