@@ -61,7 +61,8 @@ enum { MH_SRC_COOLING = 1u, MH_SRC_FORCING = 2u, MH_SRC_GRAVITY = 4u };
 enum { MH_HOST = 0, MH_DEVICE = 1 };
 
 /* Grid and scheme.
- * n[3]    cells along x, y, z (each >= 1).
+ * n[3]    cells along x, y, z (each >= 1; at most 2^31 cells in all, and one
+ *         x-y plane of a field below 4 GiB, else MH_E_SHAPE).
  * bc[3]   MH_BC_PERIODIC (wrap) or MH_BC_OUTFLOW (zero-gradient copy of the
  *         edge cell) per axis.
  * h[3]    cell spacing per axis (> 0).

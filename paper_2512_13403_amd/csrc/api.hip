@@ -66,6 +66,8 @@ mh_status validate(const mh_grid_desc* g, const mh_physics_desc* p, std::string&
   const long long N = (long long)g->n[0] * g->n[1] * g->n[2];
   if (N > (1ll << 31)) return fail(MH_E_SHAPE, "more than 2^31 cells");
   if (g->dtype != MH_F32 && g->dtype != MH_F64) return fail(MH_E_DTYPE, "dtype must be F32 or F64");
+  if ((long long)g->n[0] * g->n[1] * (g->dtype == MH_F64 ? 8 : 4) > 0xffffffffll)
+    return fail(MH_E_SHAPE, "one x-y plane of a field must stay below 4 GiB");
   if (g->limiter < MH_LIM_MINMOD || g->limiter > MH_LIM_SUPERBEE)
     return fail(MH_E_UNSUPPORTED, "unknown limiter");
   if (g->riemann < MH_RS_HLLC || g->riemann > MH_RS_RUSANOV)

@@ -231,6 +231,44 @@ __device__ __forceinline__ void add_dflux(const T* __restrict__ d, long long N, 
   for (int f = 0; f < 5; ++f) F[f] += d[f * N + q];
 }
 
+// the 5 fields of one lane's cell in a z-plane: `base` is field 0 of the
+// plane (the same for the whole wave) and `off` the lane's byte offset
+// within the plane.  The empty asm statements make the offset and each
+// field's plane base opaque at the access, the base in scalar registers, so
+// the compiler neither folds the offset into per-lane 64-bit pointers nor
+// shares one base among the fields: every access is one scalar base + one
+// 32-bit vector offset, without 64-bit vector address arithmetic.
+__device__ __forceinline__ uint32_t lane_off(uint32_t off) {
+  asm volatile("" : "+v"(off));
+  return off;
+}
+template <typename T>
+__device__ __forceinline__ void load_lane(const T* __restrict__ base, long long N, uint32_t off,
+                                          T (&u)[5]) {
+  typedef __attribute__((address_space(1))) const char gchar;
+  typedef __attribute__((address_space(1))) const T gT;
+  const uint32_t o = lane_off(off);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    gchar* b = (gchar*)(base + f * N);
+    asm volatile("" : "+s"(b));
+    u[f] = *(gT*)(b + o);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store_lane(T* __restrict__ base, long long N, uint32_t off,
+                                           const T (&u)[5]) {
+  typedef __attribute__((address_space(1))) char gchar;
+  typedef __attribute__((address_space(1))) T gT;
+  const uint32_t o = lane_off(off);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    gchar* b = (gchar*)(base + f * N);
+    asm volatile("" : "+s"(b));
+    *(gT*)(b + o) = u[f];
+  }
+}
+
 // Each row of the tile (fixed ty) is exactly one wave, so the lower-edge
 // faces below can be given to whole waves.
 static_assert(TX == 64 && TY <= TX, "one wave per tile row");
@@ -266,6 +304,9 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
   const long long col = (long long)bc_map(gy, a.ny, a.bcy) * a.nx + bc_map(gx, a.nx, a.bcx);
   const T gamma = a.gamma, gm1 = a.gm1, gm1inv = a.gm1inv;
   const T dt = (T)a.clk->dt;
+  // byte offsets of this lane's column within a z-plane (all in-loop loads
+  // and stores address a plane base plus such an offset)
+  const uint32_t col_b = (uint32_t)col * (uint32_t)sizeof(T);
 
   // halo cells of the current plane this thread loads into LDS (if any):
   // 4 columns x TY rows left/right of the tile, TX columns x 4 rows below/above
@@ -283,6 +324,8 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
     h_lx = hx + 2;
     h_col = (long long)bc_map(y0 - 2 + h_ly, a.ny, a.bcy) * a.nx + bc_map(x0 + hx, a.nx, a.bcx);
   }
+
+  const uint32_t h_b = (uint32_t)h_col * (uint32_t)sizeof(T);
 
   // forcing rows: thread tid < TY * 6(R+1) owns element `pq_e` of its row's
   // record; the record of plane z+1 is loaded during plane z-1 and stored to
@@ -349,8 +392,8 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
       hu[f] = h_ahead[f];
     }
     if (z + 1 < zend) {
-      load_cell(a.uin, N, (long long)bc_map(z + 3, a.nz, a.bcz) * plane + col, u_ahead);
-      if (h_lx >= 0) load_cell(a.uin, N, (long long)(z + 1) * plane + h_col, h_ahead);
+      load_lane(a.uin + (long long)bc_map(z + 3, a.nz, a.bcz) * plane, N, col_b, u_ahead);
+      if (h_lx >= 0) load_lane(a.uin + (long long)(z + 1) * plane, N, h_b, h_ahead);
     }
     to_prim(u[2], gm1, w[3]);
 #pragma unroll
@@ -449,7 +492,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
     const long long q = (long long)z * plane + col;
     if (STAGE != 1) {
       T u0[5];
-      if (inside) load_cell(a.un, N, q, u0);
+      if (inside) load_lane(a.un + (long long)z * plane, N, col_b, u0);
       else {
 #pragma unroll
         for (int f = 0; f < 5; ++f) u0[f] = u[0][f];
@@ -459,8 +502,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
     }
     if (STAGE != 2) {
       if (inside) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
+        store_lane(a.uout + (long long)z * plane, N, col_b, un);
       }
     } else {
       if (FORCE) {
@@ -494,8 +536,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
         pn = gm1 * (un[4] - ek);
       }
       if (inside) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
+        store_lane(a.uout + (long long)z * plane, N, col_b, un);
         if (a.epilogue) {
           // CFL signal speed of the new state and the health check
           T wn[5] = {un[0], vx, vy, vz, pn};
@@ -675,6 +716,9 @@ static void fill_geom(StageArgs<T>& a, const StageGeom& g) {
 template <typename T>
 hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs<T> a,
                         const StageGeom& g, hipStream_t s) {
+  // a lane's offset within a z-plane is a 32-bit byte offset
+  if ((unsigned long long)g.nx * (unsigned long long)g.ny * sizeof(T) > 0xffffffffull)
+    return hipErrorInvalidValue;
   fill_geom(a, g);
   dim3 block(TX, TY);
   dim3 grid(8 * a.nb_per_xcd);

@@ -70,6 +70,9 @@ def test_workspace_size_of_valid_grids():
     (lambda g, p: (setattr(p, "flags", mh.SRC_COOLING), setattr(p, "cool_model", 1)),
      mh.E_INVALID),  # no table points
 
+    # an x-y plane of 4 GiB (fp64): lane offsets inside a plane are 32-bit
+    (lambda g, p: (g.n.__setitem__(0, 65536), g.n.__setitem__(1, 8192), g.n.__setitem__(2, 1)),
+     mh.E_SHAPE),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.bc.__setitem__(0, 1)), mh.E_SHAPE),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), g.n.__setitem__(0, 32)), mh.E_SHAPE),
     (lambda g, p: (setattr(p, "flags", mh.SRC_GRAVITY), setattr(p, "mg_coarsest", 0)), mh.E_INVALID),
