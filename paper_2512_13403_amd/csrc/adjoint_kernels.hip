@@ -348,6 +348,48 @@ __device__ __forceinline__ long long face_of(const AxisGeom& g, int f, int o1, i
   if (AX == 1) return ((long long)o2 * g.nf + f) * g.n[0] + o1;
   return ((long long)f * g.n[1] + o2) * g.n[0] + o1;
 }
+// the inverses: thread t takes face record t and cell t, so that consecutive
+// lanes touch consecutive addresses (x fastest) along every axis
+template <int AX>
+__device__ __forceinline__ void face_coords(const AxisGeom& g, long long t, int& f, int& o1,
+                                            int& o2) {
+  if (AX == 0) {
+    f = (int)(t % g.nf);
+    const long long r = t / g.nf;
+    o1 = (int)(r % g.n[1]);
+    o2 = (int)(r / g.n[1]);
+  } else if (AX == 1) {
+    o1 = (int)(t % g.n[0]);
+    const long long r = t / g.n[0];
+    f = (int)(r % g.nf);
+    o2 = (int)(r / g.nf);
+  } else {
+    o1 = (int)(t % g.n[0]);
+    const long long r = t / g.n[0];
+    o2 = (int)(r % g.n[1]);
+    f = (int)(r / g.n[1]);
+  }
+}
+template <int AX>
+__device__ __forceinline__ void cell_coords(const AxisGeom& g, long long t, int& c, int& o1,
+                                            int& o2) {
+  if (AX == 0) {
+    c = (int)(t % g.n[0]);
+    const long long r = t / g.n[0];
+    o1 = (int)(r % g.n[1]);
+    o2 = (int)(r / g.n[1]);
+  } else if (AX == 1) {
+    o1 = (int)(t % g.n[0]);
+    const long long r = t / g.n[0];
+    c = (int)(r % g.n[1]);
+    o2 = (int)(r / g.n[1]);
+  } else {
+    o1 = (int)(t % g.n[0]);
+    const long long r = t / g.n[0];
+    o2 = (int)(r % g.n[1]);
+    c = (int)(r / g.n[1]);
+  }
+}
 // the two other coordinates of axis AX: AX=0 -> (y, z), AX=1 -> (x, z), AX=2 -> (x, y)
 template <int AX>
 __device__ __forceinline__ void other_dims(const AxisGeom& g, int& d1, int& d2) {
@@ -363,9 +405,8 @@ __global__ __launch_bounds__(256) void k_face_vjp(const T* __restrict__ U, const
   if (t >= nfaces) return;
   int d1, d2;
   other_dims<AX>(g, d1, d2);
-  const int f = (int)(t % g.nf);
-  const long long rest = t / g.nf;
-  const int o1 = (int)(rest % d1), o2 = (int)(rest / d1);
+  int f, o1, o2;
+  face_coords<AX>(g, t, f, o1, o2);
   const int n = g.n[AX];
   const int i = g.bc == BC_PERIODIC ? f : f - 1;  // left cell position of the face
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
@@ -433,9 +474,8 @@ __global__ __launch_bounds__(256) void k_face_vjp_rt(const T* __restrict__ U,
   if (t >= nfaces) return;
   int d1, d2;
   other_dims<AX>(g, d1, d2);
-  const int f = (int)(t % g.nf);
-  const long long rest = t / g.nf;
-  const int o1 = (int)(rest % d1), o2 = (int)(rest / d1);
+  int f, o1, o2;
+  face_coords<AX>(g, t, f, o1, o2);
   const int n = g.n[AX];
   const int i = g.bc == BC_PERIODIC ? f : f - 1;
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
@@ -513,9 +553,8 @@ __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
   int d1, d2;
   other_dims<AX>(g, d1, d2);
   const int n = g.n[AX];
-  const int c = (int)(t % n);
-  const long long rest = t / n;
-  const int o1 = (int)(rest % d1), o2 = (int)(rest / d1);
+  int c, o1, o2;
+  cell_coords<AX>(g, t, c, o1, o2);
   const long long NF = (long long)g.nf * d1 * d2;
   constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
   const int perm[5] = {0, vn, t1, t2, 4};
