@@ -7,12 +7,15 @@
 //
 // Transforms are complex-to-complex over the whole n^3 cube (n a power of
 // two), one axis at a time.  A workgroup loads `lpb` whole lines along the
-// axis into 64 KB of LDS -- for the y and z axes lines of consecutive x, so every load
-// and store touches lpb consecutive elements -- in bit-reversed order, runs
-// the log2(n) radix-2 butterfly stages in place in LDS, and writes the lines
-// back in natural order.  Twiddles exp(-2 pi i t / n), t < n/2, come from
-// fp64 sincospi.  The inverse transform is unscaled; the 1/n^3 is folded into
-// the spectral multipliers.
+// axis into 64 KB of LDS -- for the y and z axes lines of consecutive x, so
+// every load and store touches lpb consecutive elements -- and transforms
+// them with the self-sorting (Stockham) formulation: radix-8 passes and one
+// radix-2 or radix-4 pass for the rest of log2(n), each an in-register DFT
+// of the values a thread reads, so a 512-point line takes three passes
+// through LDS and no bit-reversal.  Twiddles exp(-2 pi i t / n), t < n/2,
+// come from fp64 sincospi (a table read through the caches).  The inverse
+// transform is conj(FFT(conj x)), unscaled; the 1/n^3 is folded into the
+// spectral multipliers.
 //
 // Wavenumbers on a box of length L = n h: kappa = 2 pi m / L with m = q for
 // index q <= n/2, q - n above.  The derivative uses kappa with the Nyquist
@@ -59,10 +62,6 @@ __global__ __launch_bounds__(256) void k_fft_twiddles(typename CplxOf<T>::type* 
   tw[t].y = (T)s;
 }
 
-__device__ __forceinline__ int bitrev(int j, int logn) {
-  return (int)(__builtin_bitreverse32((unsigned)j) >> (32 - logn));
-}
-
 // first element and stride of line `line` along AXIS of the n^3 cube; lines
 // are numbered with x fastest among the two other coordinates
 template <int AXIS>
@@ -82,14 +81,102 @@ __device__ __forceinline__ void line_geom(int n, long long line, long long& base
   }
 }
 
-// in-place FFT of lpb lines per workgroup; inverse: conjugate twiddles,
-// unscaled
+// v exp(-2 pi i j / ln) for the roots of an in-register DFT (ln <= 8)
+template <typename C>
+__device__ __forceinline__ C mul_root(C v, int j, int ln) {
+  using T = decltype(v.x);
+  const T s = T(0.70710678118654752440);
+  if (j == 0) return v;
+  if (4 * j == ln) return C{v.y, -v.x};
+  if (8 * j == ln) return C{(v.x + v.y) * s, (v.y - v.x) * s};
+  return C{(v.y - v.x) * s, -(v.x + v.y) * s};  // 8 j == 3 ln
+}
+
+// R-point DFT (R = 2, 4, 8) of u in registers: radix-2 decimation in time on
+// the bit-reversed values
+template <typename C, int R>
+__device__ __forceinline__ void dft_regs(C (&u)[R]) {
+  constexpr int LB = R == 2 ? 1 : (R == 4 ? 2 : 3);
+  C v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    int b = 0;
+#pragma unroll
+    for (int q = 0; q < LB; ++q) b |= ((i >> q) & 1) << (LB - 1 - q);
+    v[b] = u[i];
+  }
+#pragma unroll
+  for (int ln = 2; ln <= R; ln <<= 1)
+#pragma unroll
+    for (int i = 0; i < R; i += ln)
+#pragma unroll
+      for (int j = 0; j < ln / 2; ++j) {
+        const C t = mul_root(v[i + j + ln / 2], j, ln);
+        const C a = v[i + j];
+        v[i + j] = C{a.x + t.x, a.y + t.y};
+        v[i + j + ln / 2] = C{a.x - t.x, a.y - t.y};
+      }
+#pragma unroll
+  for (int i = 0; i < R; ++i) u[i] = v[i];
+}
+
+// One radix-R pass of the self-sorting (Stockham) FFT over the E = lpb n
+// values of the workgroup's lines in LDS, after passes whose radices multiply
+// to p: group i (< n / R) of a line reads x[i + r n / R], multiplies by
+// exp(-2 pi i r k / (R p)) with k = i mod p, transforms them, and writes
+// x'[(i - k) R + k + r p].  All groups are read before any is written (one
+// barrier), so the pass works in place; ELEMS = E / 512 at most, so every
+// thread holds its values in registers.
+template <typename C, int R, int ELEMS>
+__device__ __forceinline__ void stockham_pass(C* buf, const C* __restrict__ stw, int n, int E,
+                                              int p) {
+  constexpr int GMAX = ELEMS / R;
+  const int m = n / R, groups = E / R;
+  C u[GMAX][R];
+#pragma unroll
+  for (int gi = 0; gi < GMAX; ++gi) {
+    const int g = threadIdx.x + gi * FFT_THREADS;
+    if (g < groups) {
+      const int li = g / m, i = g % m, k = i & (p - 1);
+      const C* x = buf + li * n;
+      const int step = n / (R * p);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C v = x[i + r * m];
+        if (r > 0) {
+          const int t = r * k * step;  // < n: table of the first half, negated above it
+          C w = stw[t < n / 2 ? t : t - n / 2];
+          if (t >= n / 2) w = C{-w.x, -w.y};
+          v = C{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+        }
+        u[gi][r] = v;
+      }
+      dft_regs<C, R>(u[gi]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int gi = 0; gi < GMAX; ++gi) {
+    const int g = threadIdx.x + gi * FFT_THREADS;
+    if (g < groups) {
+      const int li = g / m, i = g % m, k = i & (p - 1);
+      C* x = buf + li * n;
+      const int j = (i - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[j + r * p] = u[gi][r];
+    }
+  }
+  __syncthreads();
+}
+
+// FFT of lpb lines per workgroup (unscaled); the inverse is conj(FFT(conj))
 template <typename T, int AXIS>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::type* data,
                                                            const typename CplxOf<T>::type* tw,
                                                            int n, int logn, int lpb,
                                                            int inverse) {
   using C = typename CplxOf<T>::type;
+  constexpr int ELEMS = FFT_LDS_BYTES / (int)sizeof(C) / FFT_THREADS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const long long line0 = (long long)blockIdx.x * lpb;
@@ -100,31 +187,26 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::t
     const int j = AXIS == 0 ? e % n : e / lpb;
     long long base, stride;
     line_geom<AXIS>(n, line0 + li, base, stride);
-    buf[li * n + bitrev(j, logn)] = data[base + (long long)j * stride];
+    C v = data[base + (long long)j * stride];
+    if (inverse) v.y = -v.y;
+    buf[li * n + j] = v;
   }
   __syncthreads();
-  const int half = n / 2;
-  for (int s = 0; s < logn; ++s) {
-    const int m = 1 << s;
-    for (int b = threadIdx.x; b < lpb * half; b += FFT_THREADS) {
-      const int li = b / half, t = b % half;
-      const int g = t >> s, j = t & (m - 1);
-      const int i = li * n + g * 2 * m + j;
-      C w = tw[j << (logn - 1 - s)];
-      if (inverse) w.y = -w.y;
-      const C u = buf[i], x = buf[i + m];
-      const C v = {x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x};
-      buf[i] = C{u.x + v.x, u.y + v.y};
-      buf[i + m] = C{u.x - v.x, u.y - v.y};
-    }
-    __syncthreads();
+  int p = 1;
+  for (int q = 0; q < logn / 3; ++q) {
+    stockham_pass<C, 8, ELEMS>(buf, tw, n, E, p);
+    p *= 8;
   }
+  if (logn % 3 == 1) stockham_pass<C, 2, ELEMS>(buf, tw, n, E, p);
+  else if (logn % 3 == 2) stockham_pass<C, 4, ELEMS>(buf, tw, n, E, p);
   for (int e = threadIdx.x; e < E; e += FFT_THREADS) {
     const int li = AXIS == 0 ? e / n : e % lpb;
     const int j = AXIS == 0 ? e % n : e / lpb;
     long long base, stride;
     line_geom<AXIS>(n, line0 + li, base, stride);
-    data[base + (long long)j * stride] = buf[li * n + j];
+    C v = buf[li * n + j];
+    if (inverse) v.y = -v.y;
+    data[base + (long long)j * stride] = v;
   }
 }
 
