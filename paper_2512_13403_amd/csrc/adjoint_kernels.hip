@@ -541,12 +541,50 @@ __device__ __forceinline__ T slot_contrib(int k, int fl, int s, T WLb, T WRb) {
   }
 }
 
+// out = c0 x0 + c1 x1 + c2 x2 + beta (dW/dU)^T w at cell q, W = (rho, v, P)
+// of U (the last step of J(U)^T v)
+template <typename T>
+struct FinishArgs {
+  T gm1, beta, c0, c1, c2;
+  const T *x0, *x1, *x2;
+  T* out;
+};
+template <typename T>
+__device__ __forceinline__ void finish_cell(const T* __restrict__ U, const T (&w)[5], long long q,
+                                            long long N, const FinishArgs<T>& fa) {
+  const T rho = U[q];
+  const T ir = T(1) / rho;
+  const T vx = U[N + q] * ir, vy = U[2 * N + q] * ir, vz = U[3 * N + q] * ir;
+  const T wr = w[0], wx = w[1], wy = w[2], wz = w[3], wp = w[4];
+  const T gm1 = fa.gm1;
+  T g[5];
+  g[0] = wr - (wx * vx + wy * vy + wz * vz) * ir + wp * gm1 * T(0.5) * (vx * vx + vy * vy + vz * vz);
+  g[1] = wx * ir - wp * gm1 * vx;
+  g[2] = wy * ir - wp * gm1 * vy;
+  g[3] = wz * ir - wp * gm1 * vz;
+  g[4] = wp * gm1;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    T o = fa.beta * g[f];
+    if (fa.x0) o += fa.c0 * fa.x0[f * N + q];
+    if (fa.x1) o += fa.c1 * fa.x1[f * N + q];
+    if (fa.x2) o += fa.c2 * fa.x2[f * N + q];
+    fa.out[f * N + q] = o;
+  }
+}
+
+// what a gather does with its sum: add it to Wacc, store it to Wacc (the
+// first axis), or add Wacc and finish the cell (the last axis; FIRST_LAST when
+// it is the only one)
+enum : int { GATHER_ADD = 0, GATHER_FIRST = 1, GATHER_LAST = 2, GATHER_FIRST_LAST = 3 };
+
 // SLOTS: the face records are the four stencil contributions written by
 // k_face_vjp_rt; otherwise (W^L_b, W^R_b) and the minmod selections
-template <typename T, int AX, bool SLOTS>
+template <typename T, int AX, bool SLOTS, int MODE>
 __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
                                                      const int* __restrict__ flags, AxisGeom g,
-                                                     T* __restrict__ Wacc) {
+                                                     T* __restrict__ Wacc,
+                                                     const T* __restrict__ U, FinishArgs<T> fa) {
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
   if (t >= N) return;
@@ -583,37 +621,32 @@ __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
     for (int i = max(-1, c - 2); i <= min(n - 1, c + 1); ++i) add_face(i + 1, i);
   }
   const long long q = cell_of<AX>(g, c, o1, o2);
+  if (MODE == GATHER_ADD) {
 #pragma unroll
-  for (int s = 0; s < 5; ++s) Wacc[perm[s] * N + q] += acc[s];
+    for (int s = 0; s < 5; ++s) Wacc[perm[s] * N + q] += acc[s];
+  } else if (MODE == GATHER_FIRST) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s) Wacc[perm[s] * N + q] = acc[s];
+  } else {
+    T w[5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+      w[perm[s]] = MODE == GATHER_LAST ? Wacc[perm[s] * N + q] + acc[s] : acc[s];
+    finish_cell(U, w, q, N, fa);
+  }
 }
 
 // out = c0 x0 + c1 x1 + c2 x2 + beta (dW/dU)^T Wacc, W = (rho, v, P) of U
 template <typename T>
 __global__ __launch_bounds__(256) void k_jtv_finish(const T* __restrict__ U,
-                                                    const T* __restrict__ Wacc, long long N, T gm1,
-                                                    T beta, T c0, const T* x0, T c1, const T* x1,
-                                                    T c2, const T* x2, T* out) {
+                                                    const T* __restrict__ Wacc, long long N,
+                                                    FinishArgs<T> fa) {
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   if (q >= N) return;
-  const T rho = U[q];
-  const T ir = T(1) / rho;
-  const T vx = U[N + q] * ir, vy = U[2 * N + q] * ir, vz = U[3 * N + q] * ir;
-  const T wr = Wacc[q], wx = Wacc[N + q], wy = Wacc[2 * N + q], wz = Wacc[3 * N + q],
-          wp = Wacc[4 * N + q];
-  T g[5];
-  g[0] = wr - (wx * vx + wy * vy + wz * vz) * ir + wp * gm1 * T(0.5) * (vx * vx + vy * vy + vz * vz);
-  g[1] = wx * ir - wp * gm1 * vx;
-  g[2] = wy * ir - wp * gm1 * vy;
-  g[3] = wz * ir - wp * gm1 * vz;
-  g[4] = wp * gm1;
+  T w[5];
 #pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    T o = beta * g[f];
-    if (x0) o += c0 * x0[f * N + q];
-    if (x1) o += c1 * x1[f * N + q];
-    if (x2) o += c2 * x2[f * N + q];
-    out[f * N + q] = o;
-  }
+  for (int f = 0; f < 5; ++f) w[f] = Wacc[f * N + q];
+  finish_cell(U, w, q, N, fa);
 }
 
 // g += weight (dL/dB)^T v for the flux-correction field B (B at a cell is
@@ -843,22 +876,49 @@ hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limite
                    const double* h, const T* U, const T* v, T beta, T c0, const T* x0, T c1,
                    const T* x1, T c2, const T* x2, T* out, hipStream_t s) {
   const long long N = (long long)geom.nx * geom.ny * geom.nz;
-  hipLaunchKernelGGL((k_fill<T>), dim3(nblk(5 * N)), dim3(256), 0, s, B.Wacc, 5 * N, T(0));
   const int nn[3] = {geom.nx, geom.ny, geom.nz};
   const bool rt = adj_runtime_scheme(limiter, riemann);
-  for (int ax = 0; ax < 3; ++ax) {
+  const FinishArgs<T> fa{gamma - T(1), beta, c0, c1, c2, x0, x1, x2, out};
+  // the axes with fluxes (a periodic axis of one cell has none: its fluxes
+  // cancel exactly); the first one's gather stores the W adjoint, the last
+  // one's adds the others and finishes the cell
+  int active[3], na = 0;
+  for (int ax = 0; ax < 3; ++ax)
+    if (!(geom.bc[ax] == BC_PERIODIC && nn[ax] == 1)) active[na++] = ax;
+  if (na == 0) {
+    hipLaunchKernelGGL((k_fill<T>), dim3(nblk(5 * N)), dim3(256), 0, s, B.Wacc, 5 * N, T(0));
+    hipLaunchKernelGGL((k_jtv_finish<T>), dim3(nblk(N)), dim3(256), 0, s, U, B.Wacc, N, fa);
+    return hipGetLastError();
+  }
+  for (int ia = 0; ia < na; ++ia) {
+    const int ax = active[ia];
+    const int mode = na == 1 ? GATHER_FIRST_LAST
+                             : (ia == 0 ? GATHER_FIRST : (ia == na - 1 ? GATHER_LAST : GATHER_ADD));
     AxisGeom ag{{geom.nx, geom.ny, geom.nz}, geom.bc[ax], 0};
     ag.nf = geom.bc[ax] == BC_PERIODIC ? nn[ax] : nn[ax] + 1;
-    if (geom.bc[ax] == BC_PERIODIC && nn[ax] == 1) continue;  // the axis' fluxes cancel exactly
     const long long nfaces = (long long)ag.nf * (N / nn[ax]);
     const T ih = (T)(1.0 / h[ax]);
+#define MH_GATHER(AX, SL)                                                                     \
+  do {                                                                                        \
+    if (mode == GATHER_ADD)                                                                   \
+      hipLaunchKernelGGL((k_cell_gather<T, AX, SL, GATHER_ADD>), dim3(nblk(N)), dim3(256), 0, \
+                         s, B.wbar, B.flags, ag, B.Wacc, U, fa);                              \
+    else if (mode == GATHER_FIRST)                                                            \
+      hipLaunchKernelGGL((k_cell_gather<T, AX, SL, GATHER_FIRST>), dim3(nblk(N)), dim3(256),  \
+                         0, s, B.wbar, B.flags, ag, B.Wacc, U, fa);                           \
+    else if (mode == GATHER_LAST)                                                             \
+      hipLaunchKernelGGL((k_cell_gather<T, AX, SL, GATHER_LAST>), dim3(nblk(N)), dim3(256),   \
+                         0, s, B.wbar, B.flags, ag, B.Wacc, U, fa);                           \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_cell_gather<T, AX, SL, GATHER_FIRST_LAST>), dim3(nblk(N)),        \
+                         dim3(256), 0, s, B.wbar, B.flags, ag, B.Wacc, U, fa);                \
+  } while (0)
 #define MH_FACE(AX)                                                                           \
   do {                                                                                        \
     if (rt) {                                                                                 \
       hipLaunchKernelGGL((k_face_vjp_rt<T, AX>), dim3(nblk(nfaces)), dim3(256), 0, s, U, v,   \
                          ag, gamma, ih, limiter, riemann, B.wbar, nfaces);                    \
-      hipLaunchKernelGGL((k_cell_gather<T, AX, true>), dim3(nblk(N)), dim3(256), 0, s,        \
-                         B.wbar, B.flags, ag, B.Wacc);                                        \
+      MH_GATHER(AX, true);                                                                    \
     } else {                                                                                  \
       if (limiter == LIM_NONE)                                                                \
         hipLaunchKernelGGL((k_face_vjp<T, LIM_NONE, AX>), dim3(nblk(nfaces)), dim3(256), 0,   \
@@ -866,17 +926,15 @@ hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limite
       else                                                                                    \
         hipLaunchKernelGGL((k_face_vjp<T, LIM_MINMOD, AX>), dim3(nblk(nfaces)), dim3(256), 0, \
                            s, U, v, ag, gamma, ih, B.wbar, B.flags, nfaces);                  \
-      hipLaunchKernelGGL((k_cell_gather<T, AX, false>), dim3(nblk(N)), dim3(256), 0, s,       \
-                         B.wbar, B.flags, ag, B.Wacc);                                        \
+      MH_GATHER(AX, false);                                                                   \
     }                                                                                         \
   } while (0)
     if (ax == 0) MH_FACE(0);
     else if (ax == 1) MH_FACE(1);
     else MH_FACE(2);
 #undef MH_FACE
+#undef MH_GATHER
   }
-  hipLaunchKernelGGL((k_jtv_finish<T>), dim3(nblk(N)), dim3(256), 0, s, U, B.Wacc, N,
-                     gamma - T(1), beta, c0, x0, c1, x1, c2, x2, out);
   return hipGetLastError();
 }
 
