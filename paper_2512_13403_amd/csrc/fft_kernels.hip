@@ -46,6 +46,8 @@ constexpr int FFT_THREADS = 512;
 constexpr int FFT_LDS_BYTES = 65536;  // lines per workgroup: as many as fit
 
 inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+// grid of a grid-stride kernel that ends in one clock atomic per block
+inline unsigned nblk_capped(long long n) { return nblk(n) < 4096u ? nblk(n) : 4096u; }
 
 template <typename T>
 T* P(char* ws, size_t off) {
@@ -305,12 +307,13 @@ __global__ __launch_bounds__(256) void k_accel_sources(T* U, const T* __restrict
                                                        CoolParams<T> cool, DevClock* clk,
                                                        int cfl) {
   __shared__ T sRed[4];
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   const T dt = (T)clk->dt;
   const T gm1 = gamma - T(1);
   T s = T(0);
-  unsigned long long bad = 0;
-  if (q < N) {
+  unsigned long long bad = 0, first_bad = ~0ull;
+  // grid-stride over the cells, so that a capped grid issues few clock atomics
+  for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < N;
+       q += (long long)gridDim.x * 256) {
     const T gx = acc[q], gy = acc[N + q], gz = acc[2 * N + q];
     T u[5];
     load_cell(U, N, q, u);
@@ -327,14 +330,18 @@ __global__ __launch_bounds__(256) void k_accel_sources(T* U, const T* __restrict
     }
 #pragma unroll
     for (int f = 0; f < 5; ++f) U[f * N + q] = u[f];
-    if (!cfl) return;  // a later kernel reduces the CFL speed of the final state
+    if (!cfl) continue;  // a later kernel reduces the CFL speed of the final state
     T w[5];
     to_prim(u, gm1, w);
     const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
-    s = (fmax(fmax(fabs(w[1]), fabs(w[2])), fabs(w[3])) + cs) * ihx;
+    const T sq = (fmax(fmax(fabs(w[1]), fabs(w[2])), fabs(w[3])) + cs) * ihx;
+    s = fmax(s, sq);
     const bool ok = (w[0] > T(0)) && (w[4] > T(0)) && isfinite(u[1]) && isfinite(u[2]) &&
-                    isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
-    if (!ok) bad = 1;
+                    isfinite(u[3]) && isfinite(u[4]) && isfinite(sq);
+    if (!ok) {
+      ++bad;
+      if ((unsigned long long)q < first_bad) first_bad = (unsigned long long)q;
+    }
   }
   if (!cfl) return;  // uniform: the whole block returns
   const T m = wave_max(s);
@@ -343,8 +350,8 @@ __global__ __launch_bounds__(256) void k_accel_sources(T* U, const T* __restrict
   if (threadIdx.x == 0)
     atomicMax(&clk->smax, pos_bits(fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]))));
   if (bad) {
-    atomicAdd(&clk->bad_count, 1ull);
-    atomicMin(&clk->bad_first, (unsigned long long)q);
+    atomicAdd(&clk->bad_count, bad);
+    atomicMin(&clk->bad_first, first_bad);
   }
 }
 
@@ -468,10 +475,10 @@ hipError_t fft_sources(char* ws, const MGLayout& L, const mh_grid_desc& g, bool 
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   const T* acc = P<T>(ws, L.fft_acc);
   if (cool)
-    hipLaunchKernelGGL((k_accel_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U, acc, N,
+    hipLaunchKernelGGL((k_accel_sources<T, true>), dim3(nblk_capped(N)), dim3(256), 0, s, U, acc, N,
                        (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk, (int)cfl);
   else
-    hipLaunchKernelGGL((k_accel_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U, acc, N,
+    hipLaunchKernelGGL((k_accel_sources<T, false>), dim3(nblk_capped(N)), dim3(256), 0, s, U, acc, N,
                        (T)g.gamma, (T)(1.0 / g.h[0]), cp, clk, (int)cfl);
   return hipGetLastError();
 }

@@ -398,12 +398,13 @@ __global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict_
                                                       int cfl) {
   __shared__ T sRed[4];
   const long long N = (long long)n * n * n;
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   const T dt = (T)clk->dt;
   const T gm1 = gamma - T(1);
   T s = T(0);
-  unsigned long long bad = 0;
-  if (q < N) {
+  unsigned long long bad = 0, first_bad = ~0ull;
+  // grid-stride over the cells, so that a capped grid issues few clock atomics
+  for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < N;
+       q += (long long)gridDim.x * 256) {
     const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
     const long long n2 = (long long)n * n;
     const long long row = (long long)k * n2 + (long long)j * n;
@@ -427,14 +428,18 @@ __global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict_
     }
 #pragma unroll
     for (int f = 0; f < 5; ++f) U[f * N + q] = u[f];
-    if (!cfl) return;  // a later kernel reduces the CFL speed of the final state
+    if (!cfl) continue;  // a later kernel reduces the CFL speed of the final state
     T w[5];
     to_prim(u, gm1, w);
     const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
-    s = (fmax(fmax(fabs(w[1]), fabs(w[2])), fabs(w[3])) + cs) * ihx;
+    const T sq = (fmax(fmax(fabs(w[1]), fabs(w[2])), fabs(w[3])) + cs) * ihx;
+    s = fmax(s, sq);
     const bool ok = (w[0] > T(0)) && (w[4] > T(0)) && isfinite(u[1]) && isfinite(u[2]) &&
-                    isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
-    if (!ok) bad = 1;
+                    isfinite(u[3]) && isfinite(u[4]) && isfinite(sq);
+    if (!ok) {
+      ++bad;
+      if ((unsigned long long)q < first_bad) first_bad = (unsigned long long)q;
+    }
   }
   if (!cfl) return;  // uniform: the whole block returns
   const T m = wave_max(s);
@@ -443,8 +448,8 @@ __global__ __launch_bounds__(256) void k_grav_sources(T* U, const T* __restrict_
   if (threadIdx.x == 0)
     atomicMax(&clk->smax, pos_bits(fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]))));
   if (bad) {
-    atomicAdd(&clk->bad_count, 1ull);
-    atomicMin(&clk->bad_first, (unsigned long long)q);
+    atomicAdd(&clk->bad_count, bad);
+    atomicMin(&clk->bad_first, first_bad);
   }
 }
 
@@ -453,6 +458,8 @@ __global__ void k_set_cycles(DevClock* clk, int cycles) {
 }
 
 inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+// grid of a grid-stride kernel that ends in one clock atomic per block
+inline unsigned nblk_capped(long long n) { return nblk(n) < 4096u ? nblk(n) : 4096u; }
 
 template <typename T>
 hipError_t sum_to(const T* x, long long n, bool square, double* partial, double scale, double* out,
@@ -833,11 +840,11 @@ hipError_t mg_gravity_step(char* ws, MGLayout& L, const mh_grid_desc& g, const m
   if (L.fft) return fft_sources<T>(ws, L, g, cool, last, cp, U, clk, s);
   const T i2h = (T)(1.0 / (2.0 * f.h));
   if (cool)
-    hipLaunchKernelGGL((k_grav_sources<T, true>), dim3(nblk(N)), dim3(256), 0, s, U,
+    hipLaunchKernelGGL((k_grav_sources<T, true>), dim3(nblk_capped(N)), dim3(256), 0, s, U,
                        P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk,
                        (int)last);
   else
-    hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
+    hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk_capped(N)), dim3(256), 0, s, U,
                        P<T>(ws, f.phi[L.cur0]), n, i2h, (T)g.gamma, (T)(1.0 / f.h), cp, clk,
                        (int)last);
   return hipGetLastError();
@@ -852,7 +859,7 @@ hipError_t mg_kick(char* ws, MGLayout& L, const mh_grid_desc& g, T* U, DevClock*
   const long long N = (long long)f.n * f.n * f.n;
   CoolParams<T> none{};
   if (L.fft) return fft_sources<T>(ws, L, g, false, true, none, U, clk, s);
-  hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk(N)), dim3(256), 0, s, U,
+  hipLaunchKernelGGL((k_grav_sources<T, false>), dim3(nblk_capped(N)), dim3(256), 0, s, U,
                      P<T>(ws, f.phi[L.cur0]), f.n, (T)(1.0 / (2.0 * f.h)), (T)g.gamma,
                      (T)(1.0 / f.h), none, clk, 1);
   return hipGetLastError();
