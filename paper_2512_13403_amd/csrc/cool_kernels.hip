@@ -25,6 +25,8 @@ namespace mh {
 namespace {
 
 inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+// grid of a grid-stride kernel that ends in one clock atomic per block
+inline unsigned nblk_capped(long long n) { return nblk(n) < 4096u ? nblk(n) : 4096u; }
 
 __device__ __forceinline__ float dpow(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double dpow(double x, double y) { return pow(x, y); }
@@ -81,26 +83,32 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cool_table(T* U, long long N, T gamma, T ihx, T ihy,
                                                     T ihz, CoolTable<T> c, DevClock* clk) {
   __shared__ T sRed[4], sRate[4];
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   const T dt = (T)clk->dt;
   const T gm1 = gamma - T(1);
   T s = T(0), r = T(0);
-  unsigned long long bad = 0;
-  if (q < N) {
+  unsigned long long bad = 0, first_bad = ~0ull;
+  // grid-stride over the cells, so that a capped grid issues few clock atomics
+  for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < N;
+       q += (long long)gridDim.x * 256) {
     T u[5];
     load_cell(U, N, q, u);
     const T ek = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
     const T E = cool_eth_step(c, u[0], u[4] - ek, dt, gm1);
     u[4] = ek + E;
     U[4 * N + q] = u[4];
-    if (c.rate) r = fabs(cool_edot(c, u[0], E, gm1)) / E;
+    if (c.rate) r = fmax(r, fabs(cool_edot(c, u[0], E, gm1)) / E);
     T w[5];
     to_prim(u, gm1, w);
     const T cs = dev_sqrt(gamma * w[4] * dev_rcp(w[0]));
-    s = fmax(fmax((fabs(w[1]) + cs) * ihx, (fabs(w[2]) + cs) * ihy), (fabs(w[3]) + cs) * ihz);
+    const T sq =
+        fmax(fmax((fabs(w[1]) + cs) * ihx, (fabs(w[2]) + cs) * ihy), (fabs(w[3]) + cs) * ihz);
+    s = fmax(s, sq);
     const bool ok = (w[0] > T(0)) && (w[4] > T(0)) && isfinite(u[1]) && isfinite(u[2]) &&
-                    isfinite(u[3]) && isfinite(u[4]) && isfinite(s);
-    if (!ok) bad = 1;
+                    isfinite(u[3]) && isfinite(u[4]) && isfinite(sq);
+    if (!ok) {
+      ++bad;
+      if ((unsigned long long)q < first_bad) first_bad = (unsigned long long)q;
+    }
   }
   const T m = wave_max(s);
   const T mr = wave_max(r);
@@ -115,8 +123,8 @@ __global__ __launch_bounds__(256) void k_cool_table(T* U, long long N, T gamma, 
       atomicMax(&clk->crate, pos_bits(fmax(fmax(sRate[0], sRate[1]), fmax(sRate[2], sRate[3]))));
   }
   if (bad) {
-    atomicAdd(&clk->bad_count, 1ull);
-    atomicMin(&clk->bad_first, (unsigned long long)q);
+    atomicAdd(&clk->bad_count, bad);
+    atomicMin(&clk->bad_first, first_bad);
   }
 }
 
@@ -217,14 +225,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cool_rate(const T* __restrict__ U, long long N, T gamma,
                                                    CoolTable<T> c, DevClock* clk) {
   __shared__ T sRate[4];
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   const T gm1 = gamma - T(1);
   T r = T(0);
-  if (q < N) {
+  for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < N;
+       q += (long long)gridDim.x * 256) {
     T u[5];
     load_cell(U, N, q, u);
     const T E = u[4] - T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
-    r = fabs(cool_edot(c, u[0], E, gm1)) / E;
+    r = fmax(r, fabs(cool_edot(c, u[0], E, gm1)) / E);
   }
   const T mr = wave_max(r);
   if ((threadIdx.x & 63) == 0) sRate[threadIdx.x >> 6] = mr;
@@ -239,7 +247,7 @@ template <typename T>
 hipError_t launch_cool_table(T* U, const StageGeom& g, T gamma, const double* ih,
                              const CoolTable<T>& c, DevClock* clk, hipStream_t s) {
   const long long N = (long long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL((k_cool_table<T>), dim3(nblk(N)), dim3(256), 0, s, U, N, gamma, (T)ih[0],
+  hipLaunchKernelGGL((k_cool_table<T>), dim3(nblk_capped(N)), dim3(256), 0, s, U, N, gamma, (T)ih[0],
                      (T)ih[1], (T)ih[2], c, clk);
   return hipGetLastError();
 }
@@ -248,7 +256,7 @@ template <typename T>
 hipError_t launch_cool_rate(const T* U, const StageGeom& g, T gamma, const CoolTable<T>& c,
                             DevClock* clk, hipStream_t s) {
   const long long N = (long long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL((k_cool_rate<T>), dim3(nblk(N)), dim3(256), 0, s, U, N, gamma, c, clk);
+  hipLaunchKernelGGL((k_cool_rate<T>), dim3(nblk_capped(N)), dim3(256), 0, s, U, N, gamma, c, clk);
   return hipGetLastError();
 }
 
