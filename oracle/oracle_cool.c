@@ -37,7 +37,9 @@ double or_cool_lambda(const or_config *c, double T) {
   if (x <= c->cool_logT[0]) return pow(10.0, c->cool_logL[0]);
   if (x >= c->cool_logT[n - 1]) return pow(10.0, c->cool_logL[n - 1]);
   int i = 0;
-  while (!(x < c->cool_logT[i + 1])) ++i; /* logT[i] <= x < logT[i+1] */
+  /* logT[i] <= x < logT[i+1]; the bound (never reached by a finite x inside
+     the table) keeps a NaN temperature from reading past the table */
+  while (i < n - 2 && !(x < c->cool_logT[i + 1])) ++i;
   double w = (x - c->cool_logT[i]) / (c->cool_logT[i + 1] - c->cool_logT[i]);
   return pow(10.0, c->cool_logL[i] + w * (c->cool_logL[i + 1] - c->cool_logL[i]));
 }
@@ -65,7 +67,7 @@ static double subcycled(const or_config *c, double rho, double E, double dt) {
   double f = c->cool_frac;
   double d0 = or_cool_edot(c, rho, E);
   double nd = ceil(dt * fabs(d0) / (f * E));
-  long N = nd < 1.0 ? 1 : (nd > (double)c->cool_nsub_max ? c->cool_nsub_max : (long)nd);
+  long N = !(nd >= 1.0) ? 1 : (nd > (double)c->cool_nsub_max ? c->cool_nsub_max : (long)nd);
   double h = dt / (double)N;
   for (long k = 0; k < N; ++k) {
     double dE = or_cool_edot(c, rho, E) * h;
@@ -127,7 +129,7 @@ static double lambda_dT(const or_config *c, double T) {
   double x = log10(T);
   if (x <= c->cool_logT[0] || x >= c->cool_logT[n - 1]) return 0.0;
   int i = 0;
-  while (!(x < c->cool_logT[i + 1])) ++i;
+  while (i < n - 2 && !(x < c->cool_logT[i + 1])) ++i;
   double s = (c->cool_logL[i + 1] - c->cool_logL[i]) / (c->cool_logT[i + 1] - c->cool_logT[i]);
   return s * or_cool_lambda(c, T) / T;
 }
@@ -181,7 +183,7 @@ double or_cool_eth_step_d(const or_config *c, double rho, double Eth, double dt,
     return r.v;
   }
   double nd = ceil(dt * fabs(d0.v) / (f * E.v));
-  long N = nd < 1.0 ? 1 : (nd > (double)c->cool_nsub_max ? c->cool_nsub_max : (long)nd);
+  long N = !(nd >= 1.0) ? 1 : (nd > (double)c->cool_nsub_max ? c->cool_nsub_max : (long)nd);
   double h = dt / (double)N;
   for (long k = 0; k < N; ++k) {
     dual2 d = edot_d(c, rho, E);

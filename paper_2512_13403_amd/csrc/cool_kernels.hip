@@ -42,8 +42,10 @@ __device__ T cool_lambda(const CoolTable<T>& c, T temp) {
   const int n = c.ntab;
   if (x <= c.logT[0]) return dexp10(c.logL[0]);
   if (x >= c.logT[n - 1]) return dexp10(c.logL[n - 1]);
+  // logT[i] <= x < logT[i+1]; the bound (which a finite x inside the table
+  // never reaches) keeps a NaN temperature from reading past the table
   int i = 0;
-  while (!(x < c.logT[i + 1])) ++i;  // logT[i] <= x < logT[i+1]; n <= 64
+  while (i < n - 2 && !(x < c.logT[i + 1])) ++i;
   const T w = (x - c.logT[i]) / (c.logT[i + 1] - c.logT[i]);
   return dexp10(c.logL[i] + w * (c.logL[i + 1] - c.logL[i]));
 }
@@ -68,7 +70,8 @@ __device__ T cool_eth_step(const CoolTable<T>& c, T rho, T E, T dt, T gm1) {
     return fmax(E + T(0.5) * dt * (d0 + d1), Ef);
   }
   const double nd = ceil((double)(dt * fabs(d0)) / (double)(c.frac * E));
-  const int N = nd < 1.0 ? 1 : (nd > (double)c.nsub_max ? c.nsub_max : (int)nd);
+  // (a NaN count, from a non-finite cell, takes one substep)
+  const int N = !(nd >= 1.0) ? 1 : (nd > (double)c.nsub_max ? c.nsub_max : (int)nd);
   const T h = dt / (T)N;
   for (int k = 0; k < N; ++k) {
     T dE = (k == 0 ? d0 : cool_edot(c, rho, E, gm1)) * h;
@@ -138,7 +141,7 @@ __device__ T cool_lambda_dT(const CoolTable<T>& c, T temp) {
   const int n = c.ntab;
   if (x <= c.logT[0] || x >= c.logT[n - 1]) return T(0);
   int i = 0;
-  while (!(x < c.logT[i + 1])) ++i;
+  while (i < n - 2 && !(x < c.logT[i + 1])) ++i;  // bounded as in cool_lambda
   const T s = (c.logL[i + 1] - c.logL[i]) / (c.logT[i + 1] - c.logT[i]);
   return s * cool_lambda(c, temp) / temp;
 }
@@ -186,7 +189,8 @@ __device__ Dual2<T> cool_eth_step_d(const CoolTable<T>& c, T rho, T Eth, T dt, T
                         gm1);
   }
   const double nd = ceil((double)(dt * fabs(d0.v)) / (double)(c.frac * E.v));
-  const int N = nd < 1.0 ? 1 : (nd > (double)c.nsub_max ? c.nsub_max : (int)nd);
+  // (a NaN count, from a non-finite cell, takes one substep)
+  const int N = !(nd >= 1.0) ? 1 : (nd > (double)c.nsub_max ? c.nsub_max : (int)nd);
   const T h = dt / (T)N;
   for (int k = 0; k < N; ++k) {
     const Dual2<T> d = k == 0 ? d0 : cool_edot_d(c, rho, E, gm1);

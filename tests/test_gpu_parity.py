@@ -547,3 +547,56 @@ def test_driven_turbulence_512_sampled_fp32():
     ref = oracle_step_sampled(oc, U0, cells, dt, ahat=ahat, nvec=nvec)
     got = np.array([[U[f, k, j, i] for (i, j, k) in cells] for f in range(5)], dtype=np.float64)
     assert rel_err(got, ref) < TOL["f32"]
+
+
+def _cfl_speed(U, gamma, h):
+    """max over cells of max_a (|v_a| + c_s) / h_a, from the state in float64"""
+    rho = U[0].astype(np.float64)
+    v = U[1:4].astype(np.float64) / rho
+    p = (gamma - 1.0) * (U[4].astype(np.float64) - 0.5 * rho * (v * v).sum(axis=0))
+    cs = np.sqrt(gamma * p / rho)
+    return max(((np.abs(v[a]) + cs) / h).max() for a in range(3))
+
+
+@pytest.mark.parametrize("kind", ["fft", "mg", "table"])
+def test_clock_reductions_over_many_cells(kind):
+    """The sources kernels that end a step reduce the CFL speed and the health
+    counts over a capped, grid-stride grid (several cells per thread above 2^20
+    cells): at 128^3 the next step's dt is the CFL dt of the returned state,
+    and planted non-finite cells are counted exactly, with the smallest flat
+    index."""
+    n, gamma, cfl = 128, 5.0 / 3.0, 0.4
+    if kind == "table":
+        U0 = as_input(_multiphase_state((n, n, n), 31), "f32")
+        phys = mh.physics_desc(flags=mh.SRC_COOLING, cool_model=mh.COOL_TABLE,
+                               cool_integrator=mh.COOLINT_TRAPEZOID,
+                               cool_table=wl.synthetic_cie_table(), **wl.COOLING_TABLE_MODEL)
+    else:
+        U0 = as_input(wl.grf_density_state(n, seed=12), "f32")
+        U0[1:4] += 0.2 * np.random.default_rng(13).standard_normal((3, n, n, n)) * U0[0]
+        U0 = as_input(U0, "f32")
+        phys = mh.physics_desc(flags=mh.SRC_GRAVITY | mh.SRC_COOLING, grav_G=wl.JEANS_G,
+                               mg_tol=1e-5,
+                               grav_solver=mh.GRAV_FFT if kind == "fft" else mh.GRAV_MG)
+    s = mh.Solver(mh.grid_desc((n, n, n), (1.0 / n,) * 3, dtype="f32", gamma=gamma, cfl=cfl),
+                  phys)
+    s.set_state(U0)
+    s.step(1, 0.0)
+    U1 = s.get_state()
+    dt2 = s.step(1, 0.0, record=True)[0]
+    assert dt2 == pytest.approx(cfl / _cfl_speed(U1, gamma, 1.0 / n), rel=1e-5)
+    # non-finite cells late in the flat order: the kernel's count and first
+    # index against the returned state
+    Ub = U0.copy()
+    N = n ** 3
+    for q in (N - 70000, N - 3 * n * n - 5, N - 9):
+        Ub.reshape(5, -1)[0, q] = np.nan
+    s.set_state(Ub)
+    s.step(1, 0.5 * dt2)
+    bad, first = s.check()
+    U = s.get_state().astype(np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        p = (gamma - 1.0) * (U[4] - 0.5 * (U[1:4] ** 2).sum(axis=0) / U[0])
+        ok = (U[0] > 0) & (p > 0) & np.isfinite(U).all(axis=0)
+    want = np.flatnonzero(~ok.reshape(-1))
+    assert want.size > 0 and bad == want.size and first == want[0], (bad, first, want.size, want[:3])

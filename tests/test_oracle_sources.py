@@ -215,6 +215,22 @@ def test_table_interpolation_is_exact_for_a_power_law():
     assert oracle.cool_lambda(c, 1e3) == pytest.approx(A * 10 ** (1.5 * b), rel=1e-13)
 
 
+def test_table_search_stops_for_a_non_finite_temperature():
+    """A NaN temperature (a non-finite cell) does not walk the interval search
+    past the table: the table model returns NaN for it, and every integrator
+    returns without reading beyond the nodes (the same bound as the device's
+    search).  Finite temperatures are unaffected (the interpolation pin
+    above)."""
+    nan = float("nan")
+    for integ in (oracle.COOLINT_TRAPEZOID, oracle.COOLINT_SUBCYCLE, oracle.COOLINT_AUTO):
+        c = table_cfg(cool_integrator=integ, cool_nsub_max=50, cool_frac=0.1)
+        assert math.isnan(oracle.cool_lambda(c, nan))
+        assert math.isnan(oracle.cool_edot(c, 1.0, nan))
+        oracle.cool_eth_step(c, 1.0, nan, 0.1)
+        oracle.cool_eth_step(c, nan, 1.0, 0.1)
+        oracle.cool_eth_step_d(c, 1.0, nan, 0.1)
+
+
 def _run(c, rho, E0, t, nsteps):
     E = E0
     for _ in range(nsteps):
