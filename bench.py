@@ -106,6 +106,72 @@ def corrector_study():
     return out
 
 
+def adjoint_probe(n=256, reps=10):
+    """Adjoint steps of the hydro step with forcing and cooling (no gravity)
+    from a smooth random state, against forward steps of the same solver."""
+    import torch
+
+    import paper_2512_13403_amd as mh
+    import workloads as wl
+
+    s = mh.Solver(mh.grid_desc((n,) * 3, (1.0 / n,) * 3, dtype="f32"),
+                  mh.physics_desc(flags=mh.SRC_FORCING | mh.SRC_COOLING))
+    s.set_state(torch.tensor(wl.smooth_random_state((n,) * 3, seed=3, kmax=4),
+                             dtype=torch.float32, device="cuda"))
+    _, k0 = s.clock()
+    ahat = s.ou_state()
+    Un = s.get_state_device().clone()
+    dt = float(s.step(1, 0.0, record=True)[0])
+    lam = torch.randn(Un.shape, generator=torch.Generator(device="cuda").manual_seed(1),
+                      device="cuda")
+    for _ in range(2):
+        s.adjoint_step(Un, dt, k0, lam, ou_ahat=ahat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.adjoint_step(Un, dt, k0, lam, ou_ahat=ahat)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.set_state(Un)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.step(reps, dt)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    print(f"adjoint probe {n}^3 f32: adjoint step {1e3 * (t1 - t0) / reps:.3f} ms, "
+          f"forward step {1e3 * (t3 - t2) / reps:.3f} ms", flush=True)
+
+
+def fft_gravity_probe(n=512):
+    """Three checkpointed steps with spectral gravity and cooling on a
+    Gaussian-random-field density, then ten standalone 3D transforms."""
+    import torch
+
+    import paper_2512_13403_amd as mh
+    import workloads as wl
+    from paper_2512_13403_amd import rollout as ro
+
+    s = mh.Solver(mh.grid_desc((n,) * 3, (1.0 / n,) * 3, dtype="f32"),
+                  mh.physics_desc(flags=mh.SRC_GRAVITY | mh.SRC_COOLING, grav_G=wl.JEANS_G,
+                                  grav_solver=mh.GRAV_FFT))
+    U0 = torch.tensor(wl.grf_density_state(n, seed=0), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ro.rollout_forward(s, U0, 3, 20)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    del U0
+    x = torch.randn((n, n, n, 2), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(10):
+        mh.fft3(x)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    print(f"fft gravity probe {n}^3 f32: {1e3 * (t1 - t0) / 3:.3f} ms per step (first steps), "
+          f"{1e3 * (t3 - t2) / 10:.3f} ms per 3D transform", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +185,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (torch copy_ of 2^28 fp32), "
                          "the reference for scaling HBM counters")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="instead: time adjoint steps at 256^3 fp32 (forcing + cooling) for "
+                         "the kernel profiles, one text line")
+    ap.add_argument("--fft-gravity-probe", action="store_true",
+                    help="instead: 3 steps with spectral gravity at 512^3 fp32 and 10 "
+                         "standalone 3D transforms, for the kernel profiles, one text line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -128,6 +200,11 @@ def main():
     import torch
 
     import paper_2512_13403_amd as mh
+
+    if args.adjoint_probe:
+        return adjoint_probe()
+    if args.fft_gravity_probe:
+        return fft_gravity_probe()
 
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
