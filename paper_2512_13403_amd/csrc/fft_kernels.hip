@@ -7,7 +7,7 @@
 //
 // Transforms are complex-to-complex over the whole n^3 cube (n a power of
 // two), one axis at a time.  A workgroup loads `lpb` whole lines along the
-// axis into 64 KB of LDS -- for the y and z axes lines of consecutive x, so
+// axis into LDS -- for the y and z axes lines of consecutive x, so
 // every load and store touches lpb consecutive elements -- and transforms
 // them with the self-sorting (Stockham) formulation: radix-8 passes and one
 // radix-2 or radix-4 pass for the rest of log2(n), each an in-register DFT
@@ -42,8 +42,14 @@ struct CplxOf<double> {
   using type = double2;
 };
 
-constexpr int FFT_THREADS = 512;
-constexpr int FFT_LDS_BYTES = 65536;  // lines per workgroup: as many as fit
+constexpr int FFT_THREADS = 256;
+// values per thread: 128 bytes (16 in fp32, 8 in fp64), so a workgroup holds
+// 32 KB of whole lines in LDS
+template <typename C>
+constexpr int fft_elems() {
+  return 128 / (int)sizeof(C);
+}
+static_assert(fft_elems<double2>() >= 8, "a radix-8 pass needs 8 values per thread");
 
 inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 // grid of a grid-stride kernel that ends in one clock atomic per block
@@ -64,23 +70,15 @@ __global__ __launch_bounds__(256) void k_fft_twiddles(typename CplxOf<T>::type* 
   tw[t].y = (T)s;
 }
 
-// first element and stride of line `line` along AXIS of the n^3 cube; lines
-// are numbered with x fastest among the two other coordinates
+// element index of point j of line `line` along AXIS of the n^3 cube (n =
+// 2^logn <= 1024, so every index fits 32 bits); lines are numbered with x
+// fastest among the two other coordinates
 template <int AXIS>
-__device__ __forceinline__ void line_geom(int n, long long line, long long& base,
-                                          long long& stride) {
-  const long long nn = n;
-  if (AXIS == 0) {
-    base = line * nn;
-    stride = 1;
-  } else if (AXIS == 1) {
-    const long long x = line % nn, z = line / nn;
-    base = z * nn * nn + x;
-    stride = nn;
-  } else {
-    base = line;  // line = y n + x
-    stride = nn * nn;
-  }
+__device__ __forceinline__ unsigned line_elem(int logn, unsigned line, unsigned j) {
+  if (AXIS == 0) return (line << logn) + j;
+  if (AXIS == 1)
+    return ((line >> logn) << (2 * logn)) + (j << logn) + (line & ((1u << logn) - 1u));
+  return (j << (2 * logn)) + line;  // line = y n + x
 }
 
 // v exp(-2 pi i j / ln) for the roots of an in-register DFT (ln <= 8)
@@ -127,20 +125,21 @@ __device__ __forceinline__ void dft_regs(C (&u)[R]) {
 // to p: group i (< n / R) of a line reads x[i + r n / R], multiplies by
 // exp(-2 pi i r k / (R p)) with k = i mod p, transforms them, and writes
 // x'[(i - k) R + k + r p].  All groups are read before any is written (one
-// barrier), so the pass works in place; ELEMS = E / 512 at most, so every
+// barrier), so the pass works in place; E / FFT_THREADS <= ELEMS, so every
 // thread holds its values in registers.
 template <typename C, int R, int ELEMS>
-__device__ __forceinline__ void stockham_pass(C* buf, const C* __restrict__ stw, int n, int E,
+__device__ __forceinline__ void stockham_pass(C* buf, const C* __restrict__ stw, int logn, int E,
                                               int p) {
   constexpr int GMAX = ELEMS / R;
-  const int m = n / R, groups = E / R;
+  constexpr int LR = R == 2 ? 1 : (R == 4 ? 2 : 3);
+  const int n = 1 << logn, logm = logn - LR, m = n >> LR, groups = E >> LR;
   C u[GMAX][R];
 #pragma unroll
   for (int gi = 0; gi < GMAX; ++gi) {
     const int g = threadIdx.x + gi * FFT_THREADS;
     if (g < groups) {
-      const int li = g / m, i = g % m, k = i & (p - 1);
-      const C* x = buf + li * n;
+      const int li = g >> logm, i = g & (m - 1), k = i & (p - 1);
+      const C* x = buf + (li << logn);
       const int step = n / (R * p);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -161,8 +160,8 @@ __device__ __forceinline__ void stockham_pass(C* buf, const C* __restrict__ stw,
   for (int gi = 0; gi < GMAX; ++gi) {
     const int g = threadIdx.x + gi * FFT_THREADS;
     if (g < groups) {
-      const int li = g / m, i = g % m, k = i & (p - 1);
-      C* x = buf + li * n;
+      const int li = g >> logm, i = g & (m - 1), k = i & (p - 1);
+      C* x = buf + (li << logn);
       const int j = (i - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) x[j + r * p] = u[gi][r];
@@ -171,44 +170,64 @@ __device__ __forceinline__ void stockham_pass(C* buf, const C* __restrict__ stw,
   __syncthreads();
 }
 
-// FFT of lpb lines per workgroup (unscaled); the inverse is conj(FFT(conj))
+// FFT of 2^loglpb lines per workgroup (unscaled); the inverse is
+// conj(FFT(conj)).  Every thread first issues all of its (at most ELEMS)
+// loads, then writes them to LDS, so that each wave has its whole share of
+// the lines in flight at once; the store to the cube is batched the same way.
 template <typename T, int AXIS>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::type* data,
                                                            const typename CplxOf<T>::type* tw,
-                                                           int n, int logn, int lpb,
-                                                           int inverse) {
+                                                           int logn, int loglpb, int inverse) {
   using C = typename CplxOf<T>::type;
-  constexpr int ELEMS = FFT_LDS_BYTES / (int)sizeof(C) / FFT_THREADS;
+  constexpr int ELEMS = fft_elems<C>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const long long line0 = (long long)blockIdx.x * lpb;
-  const int E = lpb * n;
-  for (int e = threadIdx.x; e < E; e += FFT_THREADS) {
-    // x axis: consecutive threads walk along a line; y, z: across lines
-    const int li = AXIS == 0 ? e / n : e % lpb;
-    const int j = AXIS == 0 ? e % n : e / lpb;
-    long long base, stride;
-    line_geom<AXIS>(n, line0 + li, base, stride);
-    C v = data[base + (long long)j * stride];
-    if (inverse) v.y = -v.y;
-    buf[li * n + j] = v;
+  // workgroups are dealt round-robin over the 8 XCDs: give each XCD a
+  // contiguous range of line blocks, so that the y and z passes' neighbouring
+  // blocks (the next lpb values of x) share that XCD's L2 lines
+  unsigned b = blockIdx.x;
+  if ((gridDim.x & 7u) == 0) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
+  const unsigned line0 = b << loglpb;
+  const int E = 1 << (logn + loglpb);  // <= ELEMS * FFT_THREADS (the launch sizes lpb so)
+  // x axis: consecutive threads walk along a line; y, z: across lines
+  auto line_of = [&](int e) { return AXIS == 0 ? e >> logn : e & ((1 << loglpb) - 1); };
+  auto point_of = [&](int e) { return AXIS == 0 ? e & ((1 << logn) - 1) : e >> loglpb; };
+  C v[ELEMS];
+#pragma unroll
+  for (int q = 0; q < ELEMS; ++q) {
+    const int e = threadIdx.x + q * FFT_THREADS;
+    if (e < E) v[q] = data[line_elem<AXIS>(logn, line0 + line_of(e), point_of(e))];
+  }
+#pragma unroll
+  for (int q = 0; q < ELEMS; ++q) {
+    const int e = threadIdx.x + q * FFT_THREADS;
+    if (e < E) {
+      C x = v[q];
+      if (inverse) x.y = -x.y;
+      buf[(line_of(e) << logn) + point_of(e)] = x;
+    }
   }
   __syncthreads();
   int p = 1;
   for (int q = 0; q < logn / 3; ++q) {
-    stockham_pass<C, 8, ELEMS>(buf, tw, n, E, p);
+    stockham_pass<C, 8, ELEMS>(buf, tw, logn, E, p);
     p *= 8;
   }
-  if (logn % 3 == 1) stockham_pass<C, 2, ELEMS>(buf, tw, n, E, p);
-  else if (logn % 3 == 2) stockham_pass<C, 4, ELEMS>(buf, tw, n, E, p);
-  for (int e = threadIdx.x; e < E; e += FFT_THREADS) {
-    const int li = AXIS == 0 ? e / n : e % lpb;
-    const int j = AXIS == 0 ? e % n : e / lpb;
-    long long base, stride;
-    line_geom<AXIS>(n, line0 + li, base, stride);
-    C v = buf[li * n + j];
-    if (inverse) v.y = -v.y;
-    data[base + (long long)j * stride] = v;
+  if (logn % 3 == 1) stockham_pass<C, 2, ELEMS>(buf, tw, logn, E, p);
+  else if (logn % 3 == 2) stockham_pass<C, 4, ELEMS>(buf, tw, logn, E, p);
+#pragma unroll
+  for (int q = 0; q < ELEMS; ++q) {
+    const int e = threadIdx.x + q * FFT_THREADS;
+    if (e < E) v[q] = buf[(line_of(e) << logn) + point_of(e)];
+  }
+#pragma unroll
+  for (int q = 0; q < ELEMS; ++q) {
+    const int e = threadIdx.x + q * FFT_THREADS;
+    if (e < E) {
+      C x = v[q];
+      if (inverse) x.y = -x.y;
+      data[line_elem<AXIS>(logn, line0 + line_of(e), point_of(e))] = x;
+    }
   }
 }
 
@@ -386,17 +405,19 @@ hipError_t fft3_raw(typename CplxOf<T>::type* c, const typename CplxOf<T>::type*
   int logn = 0;
   while ((1 << logn) < n) ++logn;
   const long long lines = (long long)n * n;
-  int lpb = (int)(FFT_LDS_BYTES / ((size_t)n * sizeof(C)));
-  if (lpb < 1) lpb = 1;
-  if (lpb > lines) lpb = (int)lines;
-  const unsigned grid = (unsigned)(lines / lpb);
-  const size_t lds = (size_t)lpb * n * sizeof(C);
-  hipLaunchKernelGGL((k_fft_lines<T, 0>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
-                     lpb, inverse);
-  hipLaunchKernelGGL((k_fft_lines<T, 1>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
-                     lpb, inverse);
-  hipLaunchKernelGGL((k_fft_lines<T, 2>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, n, logn,
-                     lpb, inverse);
+  // lines per workgroup: a power of two, as many as fit in the LDS budget
+  int loglpb = 0;
+  while (((long long)n << (loglpb + 1)) <= (long long)FFT_THREADS * fft_elems<C>() &&
+         (1ll << (loglpb + 1)) <= lines)
+    ++loglpb;
+  const unsigned grid = (unsigned)(lines >> loglpb);
+  const size_t lds = (size_t)n * sizeof(C) << loglpb;
+  hipLaunchKernelGGL((k_fft_lines<T, 0>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, logn,
+                     loglpb, inverse);
+  hipLaunchKernelGGL((k_fft_lines<T, 1>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, logn,
+                     loglpb, inverse);
+  hipLaunchKernelGGL((k_fft_lines<T, 2>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, logn,
+                     loglpb, inverse);
   return hipGetLastError();
 }
 
