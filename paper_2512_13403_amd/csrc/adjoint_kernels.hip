@@ -608,15 +608,39 @@ __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
                         : slot_contrib<T>(k, fl, s, wbar[s * NF + rec], wbar[(5 + s) * NF + rec]);
     }
   };
-  if (g.bc == BC_PERIODIC) {
-    if (n < 4) {
-      for (int f = 0; f < n; ++f) add_face(f, f);
-    } else {
-      for (int i = c - 2; i <= c + 1; ++i) {
-        const int f = i < 0 ? i + n : (i >= n ? i - n : i);
-        add_face(f, f + (i - f));  // positions relative to c keep the slot unique
+  if (g.bc == BC_PERIODIC && n >= 4) {
+    // face c - 2 + m (wrapped) holds this cell in stencil slot k = 3 - m, so
+    // every record is loaded before any sum (the slot known at compile time);
+    // slot 3 reads only W^R_b, slot 0 only W^L_b; sums in face order
+    long long rec[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = c - 2 + m;
+      rec[m] = face_of<AX>(g, i < 0 ? i + n : (i >= n ? i - n : i), o1, o2);
+    }
+    int fl[4];
+    T wl[4][5], wr[4][5];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      fl[m] = SLOTS ? 0 : flags[rec[m]];
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        if (SLOTS) {
+          wl[m][s] = wbar[(5 * (3 - m) + s) * NF + rec[m]];
+          wr[m][s] = T(0);
+        } else {
+          wl[m][s] = m >= 1 ? wbar[s * NF + rec[m]] : T(0);
+          wr[m][s] = m <= 2 ? wbar[(5 + s) * NF + rec[m]] : T(0);
+        }
       }
     }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int s = 0; s < 5; ++s)
+        acc[s] += SLOTS ? wl[m][s] : slot_contrib<T>(3 - m, fl[m], s, wl[m][s], wr[m][s]);
+  } else if (g.bc == BC_PERIODIC) {
+    for (int f = 0; f < n; ++f) add_face(f, f);
   } else {
     for (int i = max(-1, c - 2); i <= min(n - 1, c + 1); ++i) add_face(i + 1, i);
   }
