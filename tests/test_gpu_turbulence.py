@@ -27,8 +27,10 @@ def dev(a, dtype="f64"):
                         device="cuda:0")
 
 
+# n = 2 .. 128: one to three line blocks per workgroup regime, radix-2/4
+# remainders, one and two radix-8 passes, XCD-ordered grids of 8 to 1024 blocks
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("n", [2, 8, 32])
+@pytest.mark.parametrize("n", [2, 8, 16, 32, 64, 128])
 def test_fft3_matches_numpy(dtype, n):
     rng = np.random.default_rng(n)
     z = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
@@ -40,6 +42,38 @@ def test_fft3_matches_numpy(dtype, n):
     inv = mh.fft3(x.clone(), inverse=True).cpu().numpy()
     ref = np.fft.ifftn(z) * n ** 3
     assert np.abs(inv[..., 0] + 1j * inv[..., 1] - ref).max() < tol * np.abs(ref).max()
+
+
+def test_fft3_512_sampled_outputs_and_round_trip():
+    """512^3 fp32 (three radix-8 passes, z lines striding 2 MB planes): the
+    inverse of the forward transform returns n^3 x, and sampled outputs match
+    the DFT sum written out in fp64."""
+    import torch
+
+    n = 512
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    x = torch.randn((n, n, n, 2), dtype=torch.float32, device="cuda:0", generator=g)
+    X = mh.fft3(x.clone())
+    y = mh.fft3(X.clone(), inverse=True)
+    assert float((y / n ** 3 - x).abs().max()) < 1e-5 * float(x.abs().max())
+    del y
+    Xs = {}
+    samples = [(0, 0, 1), (3, 500, 1), (256, 17, 257), (511, 256, 257)]  # (kz, ky, kx)
+    for kz, ky, kx in samples:
+        Xs[(kz, ky, kx)] = complex(X[kz, ky, kx, 0].item(), X[kz, ky, kx, 1].item())
+    del X
+    xc = x.double().cpu().numpy()
+    z = xc[..., 0] + 1j * xc[..., 1]
+    del xc, x
+    l2 = float(np.sqrt((np.abs(z) ** 2).sum()))
+    j = np.arange(n)
+    for kx in sorted({s[2] for s in samples}):
+        S = z @ np.exp(-2j * np.pi * kx * j / n)  # [z][y]: the sum over x
+        for kz, ky, kx2 in samples:
+            if kx2 != kx:
+                continue
+            ref = np.exp(-2j * np.pi * kz * j / n) @ S @ np.exp(-2j * np.pi * ky * j / n)
+            assert abs(Xs[(kz, ky, kx)] - ref) < 2e-5 * l2, (kz, ky, kx)
 
 
 def numpy_field(phases, n, kmin, kmax, power, zeta, mach, rho0, p0, gamma):
