@@ -640,7 +640,7 @@ extern "C" mh_status mh_get_potential(mh_ctx* c, void* phi, int where) {
 namespace {
 
 struct AdjLayout {
-  size_t clk = 0, dtlog = 0, U1 = 0, U2 = 0, Ua = 0, Ub = 0, Uc = 0, lamA = 0, lamB = 0;
+  size_t clk = 0, dtlog = 0, U1 = 0, U2 = 0, Ua = 0, Uc = 0, lamA = 0, lamB = 0;
   size_t lam1 = 0, lam2 = 0;
   size_t Wacc = 0, wbar = 0, flags = 0, accb = 0, phib = 0, ahat = 0, coef = 0, rows = 0;
   MGLayout mg;
@@ -667,8 +667,7 @@ AdjLayout make_adj_layout(const mh_grid_desc& g, const mh_physics_desc& p) {
   A.dtlog = take(sizeof(double));
   A.U1 = take(5 * N * es);
   A.Ua = take(5 * N * es);
-  A.Ub = take(5 * N * es);
-  A.Uc = take(5 * N * es);
+  if (p.flags & MH_SRC_GRAVITY) A.Uc = take(5 * N * es);  // the state after the gravity kick
   A.lamA = take(5 * N * es);
   A.lamB = take(5 * N * es);
   A.lam1 = take(5 * N * es);
@@ -716,7 +715,7 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
   auto at = [&](size_t off) { return reinterpret_cast<T*>(ws + off); };
   DevClock* aclk = reinterpret_cast<DevClock*>(ws + A.clk);
-  T *U1 = at(A.U1), *Ua = at(A.Ua), *Ub = at(A.Ub), *Uc = at(A.Uc);
+  T *U1 = at(A.U1), *Ua = at(A.Ua), *Ub = nullptr, *Uc = nullptr;
   T *lamA = at(A.lamA), *lamB = at(A.lamB), *lam1 = at(A.lam1);
   AdjointBuffers<T> B{at(A.Wacc), at(A.wbar), reinterpret_cast<int*>(ws + A.flags),
                       grav ? at(A.accb) : nullptr, grav ? at(A.phib) : nullptr};
@@ -749,8 +748,8 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
     MH_HIP(c, launch_force_rows<T>(at(A.coef), c->at<int>(c->L.ou_n), c->nmodes, a.ou_tab[1],
                                    a.ou_tab[2], g.n[1], g.n[2], a.ou_R, at(A.rows), c->stream));
 
-  // forward recomputation: U1 (and U2), Ua (the RK update), Ub (forcing), Uc
-  // (gravity)
+  // forward recomputation: U1 (and U2), Ua (the RK update), Ub (after the
+  // forcing kick), Uc (after the gravity kick)
   T* U2 = g.integrator == MH_RK_SSP3 ? at(A.U2) : nullptr;
   if (g.integrator == MH_RK_EULER) {
     a.uin = Un;
@@ -776,10 +775,16 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   }
   a.uout = Ua;
   MH_HIP(c, launch_stage<T>(2, g.limiter, false, false, a, geom, c->stream));
-  MH_HIP(c, hipMemcpyAsync(Ub, Ua, sbytes, hipMemcpyDeviceToDevice, c->stream));
+  // the forcing kick acts on Ua in place (the RK update itself is not read
+  // again); only gravity needs the states before (Ub) and after (Uc) a kick
+  Ub = Ua;
   if (force)
     MH_HIP(c, adj_force_kick<T>(Ub, at(A.rows), a.ou_tab[0], a.ou_R, geom, (T)dt, c->stream));
-  MH_HIP(c, hipMemcpyAsync(Uc, Ub, sbytes, hipMemcpyDeviceToDevice, c->stream));
+  Uc = Ub;
+  if (grav) {
+    Uc = at(A.Uc);
+    MH_HIP(c, hipMemcpyAsync(Uc, Ub, sbytes, hipMemcpyDeviceToDevice, c->stream));
+  }
   const T* phi_sol = nullptr;
   if (grav) {
     MH_HIP(c, mg_set_guess<T>(ws, A.mg, phi_n, c->stream));
