@@ -174,8 +174,14 @@ __device__ __forceinline__ void stockham_pass(C* buf, const C* __restrict__ stw,
 // conj(FFT(conj)).  Every thread first issues all of its (at most ELEMS)
 // loads, then writes them to LDS, so that each wave has its whole share of
 // the lines in flight at once; the store to the cube is batched the same way.
-template <typename T, int AXIS>
+// IO selects the ends of a 3D transform: 0 in place on `data`; FFT_REAL_IN
+// reads the real field `rin` (imaginary part 0) and writes `data`;
+// FFT_REAL_OUT reads `data` and writes only the real part, to `rout`.
+enum : int { FFT_COMPLEX = 0, FFT_REAL_IN = 1, FFT_REAL_OUT = 2 };
+template <typename T, int AXIS, int IO>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::type* data,
+                                                           const T* __restrict__ rin,
+                                                           T* __restrict__ rout,
                                                            const typename CplxOf<T>::type* tw,
                                                            int logn, int loglpb, int inverse) {
   using C = typename CplxOf<T>::type;
@@ -196,7 +202,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::t
 #pragma unroll
   for (int q = 0; q < ELEMS; ++q) {
     const int e = threadIdx.x + q * FFT_THREADS;
-    if (e < E) v[q] = data[line_elem<AXIS>(logn, line0 + line_of(e), point_of(e))];
+    if (e < E) {
+      const unsigned idx = line_elem<AXIS>(logn, line0 + line_of(e), point_of(e));
+      if (IO == FFT_REAL_IN) v[q] = C{rin[idx], T(0)};
+      else v[q] = data[idx];
+    }
   }
 #pragma unroll
   for (int q = 0; q < ELEMS; ++q) {
@@ -226,22 +236,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::t
     if (e < E) {
       C x = v[q];
       if (inverse) x.y = -x.y;
-      data[line_elem<AXIS>(logn, line0 + line_of(e), point_of(e))] = x;
+      const unsigned idx = line_elem<AXIS>(logn, line0 + line_of(e), point_of(e));
+      if (IO == FFT_REAL_OUT) rout[idx] = x.x;
+      else data[idx] = x;
     }
   }
 }
 
 __device__ __forceinline__ int wavenum(int q, int n) { return q <= n / 2 ? q : q - n; }
-
-// c = (x, 0)
-template <typename T>
-__global__ __launch_bounds__(256) void k_fft_pack(typename CplxOf<T>::type* c,
-                                                  const T* __restrict__ x, long long N) {
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= N) return;
-  c[q].x = x[q];
-  c[q].y = T(0);
-}
 
 // Phi_hat / N = -F_hat / (|kappa|^2 N), 0 at kappa = 0
 template <typename T>
@@ -277,13 +279,6 @@ __global__ __launch_bounds__(256) void k_fft_grad(const typename CplxOf<T>::type
   const T ka = (T)dkappa(axis_index<AXIS>(q, n), n, tk);
   c1[q].x = ka * c0[q].y;
   c1[q].y = -ka * c0[q].x;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_fft_real(const typename CplxOf<T>::type* __restrict__ c,
-                                                  T* out, long long N) {
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q < N) out[q] = c[q].x;
 }
 
 template <typename T>
@@ -397,10 +392,12 @@ __global__ __launch_bounds__(256) void k_accel_kick_vjp(const T* __restrict__ U,
   lout[4 * N + q] = Eb;
 }
 
-// the three one-axis passes over the n^3 cube c, with the twiddles tw
+// the three one-axis passes over the n^3 cube c, with the twiddles tw; with
+// rin the x pass reads the real field rin instead of c, with rout the z pass
+// writes only the real part of the result, to rout (c then holds no result)
 template <typename T>
 hipError_t fft3_raw(typename CplxOf<T>::type* c, const typename CplxOf<T>::type* tw, int n,
-                    int inverse, hipStream_t s) {
+                    int inverse, hipStream_t s, const T* rin = nullptr, T* rout = nullptr) {
   using C = typename CplxOf<T>::type;
   int logn = 0;
   while ((1 << logn) < n) ++logn;
@@ -412,20 +409,28 @@ hipError_t fft3_raw(typename CplxOf<T>::type* c, const typename CplxOf<T>::type*
     ++loglpb;
   const unsigned grid = (unsigned)(lines >> loglpb);
   const size_t lds = (size_t)n * sizeof(C) << loglpb;
-  hipLaunchKernelGGL((k_fft_lines<T, 0>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, logn,
-                     loglpb, inverse);
-  hipLaunchKernelGGL((k_fft_lines<T, 1>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, logn,
-                     loglpb, inverse);
-  hipLaunchKernelGGL((k_fft_lines<T, 2>), dim3(grid), dim3(FFT_THREADS), lds, s, c, tw, logn,
-                     loglpb, inverse);
+  if (rin)
+    hipLaunchKernelGGL((k_fft_lines<T, 0, FFT_REAL_IN>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
+                       rin, (T*)nullptr, tw, logn, loglpb, inverse);
+  else
+    hipLaunchKernelGGL((k_fft_lines<T, 0, FFT_COMPLEX>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
+                       (const T*)nullptr, (T*)nullptr, tw, logn, loglpb, inverse);
+  hipLaunchKernelGGL((k_fft_lines<T, 1, FFT_COMPLEX>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
+                     (const T*)nullptr, (T*)nullptr, tw, logn, loglpb, inverse);
+  if (rout)
+    hipLaunchKernelGGL((k_fft_lines<T, 2, FFT_REAL_OUT>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
+                       (const T*)nullptr, rout, tw, logn, loglpb, inverse);
+  else
+    hipLaunchKernelGGL((k_fft_lines<T, 2, FFT_COMPLEX>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
+                       (const T*)nullptr, (T*)nullptr, tw, logn, loglpb, inverse);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t fft3(char* ws, const MGLayout& L, typename CplxOf<T>::type* c, int inverse,
-                hipStream_t s) {
+                hipStream_t s, const T* rin = nullptr, T* rout = nullptr) {
   using C = typename CplxOf<T>::type;
-  return fft3_raw<T>(c, P<C>(ws, L.fft_tw), L.lev[0].n, inverse, s);
+  return fft3_raw<T>(c, P<C>(ws, L.fft_tw), L.lev[0].n, inverse, s, rin, rout);
 }
 
 template <typename T>
@@ -469,22 +474,18 @@ hipError_t fft_poisson(char* ws, MGLayout& L, double h, hipStream_t s) {
   T* acc = P<T>(ws, L.fft_acc);
   hipLaunchKernelGGL((k_fft_twiddles<T>), dim3(nblk(n / 2 > 0 ? n / 2 : 1)), dim3(256), 0, s,
                      P<C>(ws, L.fft_tw), n);
-  hipLaunchKernelGGL((k_fft_pack<T>), dim3(nblk(N)), dim3(256), 0, s, c0, P<T>(ws, f.F), N);
-  hipError_t e = fft3<T>(ws, L, c0, 0, s);
+  hipError_t e = fft3<T>(ws, L, c0, 0, s, P<T>(ws, f.F));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fft_phi<T>), dim3(nblk(N)), dim3(256), 0, s, c0, n, tk);
   for (int a = 0; a < 3; ++a) {
     if (a == 0) hipLaunchKernelGGL((k_fft_grad<T, 0>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
     if (a == 1) hipLaunchKernelGGL((k_fft_grad<T, 1>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
     if (a == 2) hipLaunchKernelGGL((k_fft_grad<T, 2>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
-    e = fft3<T>(ws, L, c1, 1, s);
+    e = fft3<T>(ws, L, c1, 1, s, nullptr, acc + a * N);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fft_real<T>), dim3(nblk(N)), dim3(256), 0, s, c1, acc + a * N, N);
   }
-  e = fft3<T>(ws, L, c0, 1, s);
+  e = fft3<T>(ws, L, c0, 1, s, nullptr, P<T>(ws, f.phi[L.cur0]));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_fft_real<T>), dim3(nblk(N)), dim3(256), 0, s, c0,
-                     P<T>(ws, f.phi[L.cur0]), N);
   return hipGetLastError();
 }
 
@@ -522,8 +523,7 @@ hipError_t fft_gravity_vjp(char* ws, MGLayout& L, double h, double G, const T* U
   hipLaunchKernelGGL((k_fft_twiddles<T>), dim3(nblk(n / 2 > 0 ? n / 2 : 1)), dim3(256), 0, s,
                      P<C>(ws, L.fft_tw), n);
   for (int a = 0; a < 3; ++a) {
-    hipLaunchKernelGGL((k_fft_pack<T>), dim3(nblk(N)), dim3(256), 0, s, c1, accb + a * N, N);
-    hipError_t e = fft3<T>(ws, L, c1, 0, s);
+    hipError_t e = fft3<T>(ws, L, c1, 0, s, accb + a * N);
     if (e != hipSuccess) return e;
     if (a == 0)
       hipLaunchKernelGGL((k_fft_adj_accum<T, 0>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
