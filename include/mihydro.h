@@ -364,6 +364,22 @@ mh_status mh_fft3_query_workspace(int32_t n, int32_t dtype, size_t *bytes);
 mh_status mh_fft3(void *data, int32_t n, int32_t dtype, int32_t inverse, void *workspace,
                   size_t workspace_bytes, void *stream);
 
+/* mh_fft3 without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The twiddle table
+ * lives in a library-owned device array of 8 KiB per GPU (enough for every n
+ * and dtype mh_fft3 accepts), whose device address is looked up once per GPU
+ * on the first call with that GPU current; `data` and `stream` must belong to
+ * the current device.  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  Every call on a GPU rewrites that GPU's table,
+ * so calls that overlap on one GPU (two streams, or two host threads) race:
+ * serialise them.  Arguments, layout and result are those of mh_fft3.
+ * Errors: MH_E_INVALID (null data, inverse not 0/1), MH_E_SHAPE (n not a
+ * power of two in 2..1024), MH_E_DTYPE, MH_E_WORKSPACE (a table larger than
+ * the array; not reachable with the sizes above), MH_E_DEVICE (HIP error, or
+ * a device index of 64 or more). */
+mh_status mh_fft3_noalloc(void *data, int32_t n, int32_t dtype, int32_t inverse, void *stream);
+
 /* Kernel timing with HIP events.  While enabled, mh_step records an event pair
  * on the context stream around every kernel launch it makes, by kind:
  *   MH_TIME_STAGE1, MH_TIME_STAGE2 (the fused stage kernels),

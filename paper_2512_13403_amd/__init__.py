@@ -45,7 +45,7 @@ EXPORTED = [
     "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
     "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
     "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs", "mh_fft3_query_workspace",
-    "mh_fft3", "mh_set_flux_correction",
+    "mh_fft3", "mh_set_flux_correction", "mh_fft3_noalloc",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -150,6 +150,7 @@ def load_library():
             "mh_fft3": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t,
                         vp],
             "mh_set_flux_correction": [vp, vp, vp],
+            "mh_fft3_noalloc": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -641,6 +642,25 @@ def fft3(x, inverse: bool = False):
                      ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
     if st != OK:
         raise MHError(st, "mh_fft3")
+    return x
+
+
+def fft3_noalloc(x, inverse: bool = False):
+    """fft3 through mh_fft3_noalloc: the twiddle table in the library's own
+    device array, no workspace and no allocation (calls on one GPU must not
+    overlap).  Returns x."""
+    import torch
+
+    lib = load_library()
+    n = x.shape[0]
+    if x.shape != (n, n, n, 2) or not x.is_contiguous() or x.device.type != "cuda":
+        raise ValueError("fft3_noalloc needs a contiguous CUDA tensor [n][n][n][2]")
+    dt = F64 if x.dtype == torch.float64 else F32
+    with torch.cuda.device(x.device):
+        st = lib.mh_fft3_noalloc(ctypes.c_void_p(x.data_ptr()), n, dt, int(bool(inverse)),
+                                 ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+    if st != OK:
+        raise MHError(st, "mh_fft3_noalloc")
     return x
 
 

@@ -22,6 +22,7 @@
 // index q = n/2 set to 0 (its i kappa factor has no real counterpart), while
 // |kappa|^2 keeps it.
 #include <cmath>
+#include <mutex>
 
 #include "mg.h"
 #include "mh_device.h"
@@ -573,5 +574,52 @@ extern "C" mh_status mh_fft3(void* data, int32_t n, int32_t dtype, int32_t inver
       dtype == MH_F64
           ? mh::fft3_standalone<double>(data, n, inverse, workspace, (hipStream_t)stream)
           : mh::fft3_standalone<float>(data, n, inverse, workspace, (hipStream_t)stream);
+  return e == hipSuccess ? MH_OK : MH_E_DEVICE;
+}
+
+// ------------------------------------------- the transform without allocation
+
+// Twiddle table of mh_fft3_noalloc: n/2 complex values of the largest dtype at
+// the largest n (512 x 16 B).  Each GPU the library runs on holds its own copy
+// until the process ends; every call on that GPU rewrites it.
+constexpr size_t FFT_SCRATCH_BYTES = 8192;
+static __device__ __align__(256) char scratch[FFT_SCRATCH_BYTES];
+
+namespace {
+constexpr int FFT_SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[FFT_SCRATCH_MAX_DEVICES] = {};
+
+// device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the host-side symbol is not a device address)
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= FFT_SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" mh_status mh_fft3_noalloc(void* data, int32_t n, int32_t dtype, int32_t inverse,
+                                     void* stream) {
+  size_t need = 0;
+  const mh_status st = mh_fft3_query_workspace(n, dtype, &need);
+  if (st != MH_OK) return st;
+  if (!data || (inverse != 0 && inverse != 1)) return MH_E_INVALID;
+  if (need > FFT_SCRATCH_BYTES) return MH_E_WORKSPACE;
+  void* tw = nullptr;
+  if (scratch_address(&tw) != hipSuccess) return MH_E_DEVICE;
+  const hipError_t e =
+      dtype == MH_F64 ? mh::fft3_standalone<double>(data, n, inverse, tw, (hipStream_t)stream)
+                      : mh::fft3_standalone<float>(data, n, inverse, tw, (hipStream_t)stream);
   return e == hipSuccess ? MH_OK : MH_E_DEVICE;
 }
