@@ -4,18 +4,27 @@ thin cooling, CFL 0.4, from rest with rho = 1, p = 1, gamma = 5/3).
 
 A step is one full pass of the method: per-step dt/OU kernel, RK stage 1,
 RK stage 2 with forcing, cooling and the CFL reduction fused.  The timed
-region holds exactly --steps steps, bracketed by device synchronisation; the
-state is resident in HBM before it starts.  Prints one JSON line.
+region holds exactly --steps steps, bracketed by device synchronisation, with
+no per-launch events in it; the state is resident in HBM before it starts.
+A second pass of the same number of steps records HIP events around every
+launch on the library's stream, for the per-kernel durations.  Prints one
+JSON line.
 
 value            cell-updates/s = cells * steps / seconds of the timed region
-roofline         the dominant kernel (RK stage 2), which is bound by the fp32
-                 vector ALU: algorithmic FLOPs per launch (489 per cell) over
-                 its mean duration from HIP events recorded around every launch
-                 on the library's stream, against the fp32 vector peak;
-                 `traffic` = HBM bytes per launch from the committed counter
-                 summary (null when the kernel source changed since); the HBM
-                 fractions of the metric are in `config`
-cpu_baseline     the FP64 oracle on the same physics at 192^3 for 16 steps
+roofline         the dominant kernel (RK stage 2 with the sources and the CFL
+                 reduction): algorithmic HBM bytes per launch (60 per cell:
+                 read U1 and U^n, write U^{n+1}) over its mean launch duration,
+                 against the 8 TB/s HBM peak; `traffic` = HBM bytes per launch
+                 from the committed counter summary (null when the kernel
+                 source changed since); `alu` = the same launch's algorithmic
+                 FLOPs (489 per cell) against the 78.6 TFLOP/s fp32 vector
+                 peak without packed instructions
+extra            the same step on a second input (band-limited turbulent
+                 velocity field, Mach 1) and the paper's fiducial van Leer +
+                 HLLC scheme on the headline input
+cpu_baseline     the FP64 oracle on the same physics at 256^3 for 2 steps on
+                 all of the job's threads, with the CPU model and the rate of
+                 one thread (128^3, 2 steps)
 corrector        the solver-in-the-loop study: density L2 error of the plain and
                  the corrected 64^3 runs against the block-averaged 256^3 run,
                  and the cost ratio (fine run time / corrected coarse run time)
@@ -32,9 +41,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HBM_TARGET_FRAC = 0.6
 # MI355X fp32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz =
-# 78.6 TFLOP/s with one-lane-per-op instructions, 157.3 with packed FP32
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# 78.6 TFLOP/s with one-lane-per-op instructions (157.3 with packed FP32
+# instructions, which this build does not emit)
+FP32_VECTOR_PEAK_TFLOPS = 78.6
 # algorithmic floating-point operations per cell of one RK stage of the fp32
 # method (primitive recovery, 3 faces of limited slopes + face states + HLLC,
 # conservative update; stage 2 adds the RK combination, OU kick, exact cooling
@@ -74,9 +85,19 @@ def measured_traffic():
     return float(rec["stage2_bytes"])
 
 
-def cpu_baseline(n=192, steps=16):
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
 
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(n, steps):
     import oracle
     import workloads as wl
 
@@ -87,11 +108,28 @@ def cpu_baseline(n=192, steps=16):
     t0 = time.perf_counter()
     sim.advance(steps)
     dt = time.perf_counter() - t0
+    return n ** 3 * steps / dt, dt
+
+
+def cpu_baseline(n=256, steps=2, n1=128, steps1=2):
+    """The FP64 oracle on the headline physics (forcing + cooling from rest):
+    n^3 for `steps` steps on all of the job's OpenMP threads, and n1^3 for
+    `steps1` steps on one thread."""
+    import oracle
+
     threads = oracle.num_threads()
-    return {"value": n ** 3 * steps / dt, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
+    rate, secs = _oracle_rate(n, steps)
+    oracle.set_num_threads(1)
+    try:
+        rate1, secs1 = _oracle_rate(n1, steps1)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": rate, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"same physics (forcing + cooling, from rest) at {n}^3 for {steps} steps, "
-                      f"fp64, OpenMP over {threads} threads, {dt:.1f} s"}
+                      f"fp64, OpenMP over {threads} threads, {secs:.1f} s",
+            "cpu_model": cpu_model(),
+            "one_core_value": rate1,
+            "one_core_sample": f"{n1}^3 for {steps1} steps on 1 thread, {secs1:.1f} s"}
 
 
 def corrector_study():
@@ -172,6 +210,131 @@ def fft_gravity_probe(n=512):
           f"{1e3 * (t3 - t2) / 10:.3f} ms per 3D transform", flush=True)
 
 
+GAMMA = 5.0 / 3.0
+
+
+def make_solver(n, dtype, limiter=None):
+    """The headline configuration: forcing + cooling, CFL 0.4, gamma 5/3."""
+    import paper_2512_13403_amd as mh
+
+    lim = mh.LIM_MINMOD if limiter is None else limiter
+    grid = mh.grid_desc((n,) * 3, (1.0 / n,) * 3, dtype=dtype, gamma=GAMMA, cfl=0.4,
+                        limiter=lim, riemann=mh.RS_HLLC)
+    phys = mh.physics_desc(flags=mh.SRC_FORCING | mh.SRC_COOLING, cool=(0.3, 1e-2, 1e-3, 1e-4),
+                           ou_seed=0, ou_tau=0.5, ou_arms=1.0, ou_zeta=1.0, ou_kmin=1.0,
+                           ou_kmax=2.0)
+    return mh.Solver(grid, phys)
+
+
+def rest_state_device(n, dtype):
+    import torch
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    U0 = torch.zeros((5, n, n, n), dtype=tdt, device="cuda:0")
+    U0[0] = 1.0
+    U0[4] = 1.0 / (GAMMA - 1.0)  # rest, rho = 1, p = 1
+    return U0
+
+
+def turbulent_state_device(n, dtype, seed=0, kmin=2.0, kmax=20.0, power=-5.0 / 3.0, mach=1.0):
+    """Band-limited solenoidal velocity field of the Sec. 3.1 construction at
+    uniform rho = 1, p = 1: coefficients A(k) P(k) exp(i phi(k)) with
+    A = |k|^(power/2) on kmin <= |k| <= kmax, P the solenoidal projector and
+    seeded uniform phases, the real part of the library's inverse transform,
+    rescaled to rms Mach `mach` (a synthetic input built on the device)."""
+    import torch
+
+    import paper_2512_13403_amd as mh
+
+    dev = "cuda:0"
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    k1 = torch.arange(n, device=dev, dtype=tdt)
+    k1 = torch.where(k1 > n // 2, k1 - n, k1)
+    kx, ky, kz = k1.view(1, 1, n), k1.view(1, n, 1), k1.view(n, 1, 1)
+    k2 = kx * kx + ky * ky + kz * kz
+    k = torch.sqrt(k2)
+    A = torch.where((k >= kmin) & (k <= kmax), k.clamp(min=1.0) ** (power / 2.0),
+                    torch.zeros_like(k))
+    k2s = torch.where(k2 > 0, k2, torch.ones_like(k2))
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    ph = torch.rand((3, n, n, n), generator=gen, device=dev, dtype=tdt) * (2.0 * math.pi)
+    er, ei = torch.cos(ph), torch.sin(ph)
+    del ph
+    dr = (kx * er[0] + ky * er[1] + kz * er[2]) / k2s
+    di = (kx * ei[0] + ky * ei[1] + kz * ei[2]) / k2s
+    u = []
+    for i, ki in enumerate((kx, ky, kz)):
+        X = torch.empty((n, n, n, 2), dtype=tdt, device=dev)
+        X[..., 0] = A * (er[i] - ki * dr)
+        X[..., 1] = A * (ei[i] - ki * di)
+        mh.fft3(X, inverse=True)
+        u.append(X[..., 0].clone())
+        del X
+    del er, ei, dr, di
+    v = torch.stack(u)
+    del u
+    cs = math.sqrt(GAMMA)
+    v *= mach * cs / torch.sqrt((v * v).sum(dim=0).mean())
+    U = torch.empty((5, n, n, n), dtype=tdt, device=dev)
+    U[0] = 1.0
+    U[1:4] = v
+    U[4] = 1.0 / (GAMMA - 1.0) + 0.5 * (v * v).sum(dim=0)
+    del v
+    torch.cuda.empty_cache()
+    return U
+
+
+def timed_steps(s, steps):
+    """(GPU ms from events on the solver's stream, wall seconds) of `steps`
+    CFL steps, bracketed by device synchronisation."""
+    import torch
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(s.stream)
+    s.step(steps, 0.0)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1), time.perf_counter() - w0
+
+
+def extra_inputs(n, dtype, steps, warmup):
+    """The step on C3's second input (the turbulent velocity field) and the
+    paper's fiducial van Leer + HLLC scheme on the headline input, each timed
+    like the headline (warm-up, then `steps` steps without per-launch events)."""
+    import torch
+
+    import paper_2512_13403_amd as mh
+
+    es = 4 if dtype == "f32" else 8
+    out = {}
+    cases = (("turbulent_ic", "minmod + HLLC, band-limited solenoidal velocity 2<=|k|<=20, "
+                              "E(k) ~ k^-5/3, Mach 1, seed 0, forcing + cooling", None),
+             ("vanleer_hllc", "van Leer + HLLC (the paper's fiducial scheme), from rest, "
+                              "forcing + cooling", mh.LIM_VANLEER))
+    for name, what, lim in cases:
+        print(f"# extra input: {name}", file=sys.stderr, flush=True)
+        s = make_solver(n, dtype, limiter=lim)
+        U0 = turbulent_state_device(n, dtype) if name == "turbulent_ic" else rest_state_device(n, dtype)
+        s.set_state(U0)
+        torch.cuda.synchronize()
+        del U0
+        s.step(warmup, 0.0)
+        ms, _ = timed_steps(s, steps)
+        bad, _ = s.check()
+        t_sim, _ = s.clock()
+        rate = n ** 3 * steps / (ms / 1e3)
+        out[name] = {"workload": f"{n}^3 {dtype}: {what}", "steps": steps,
+                     "ms_per_step": ms / steps, "value": rate, "unit": "cell-updates/s",
+                     "hbm_frac_step_algorithmic": 25 * es * rate / 1e9 / HBM_PEAK_GBS,
+                     "t_end": t_sim, "bad_cells": bad}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +343,8 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the second input and the van Leer scheme")
     ap.add_argument("--no-corrector-study", action="store_true",
                     help="skip the solver-in-the-loop study (fine 256^3 vs corrected 64^3)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -217,46 +382,31 @@ def main():
     n = args.n
     shape = (n, n, n)
     N = n ** 3
-    gamma = 5.0 / 3.0
-    grid = mh.grid_desc(shape, (1.0 / n,) * 3, dtype=args.dtype, gamma=gamma, cfl=0.4)
-    phys = mh.physics_desc(flags=mh.SRC_FORCING | mh.SRC_COOLING, cool=(0.3, 1e-2, 1e-3, 1e-4),
-                           ou_seed=0, ou_tau=0.5, ou_arms=1.0, ou_zeta=1.0, ou_kmin=1.0,
-                           ou_kmax=2.0)
-    s = mh.Solver(grid, phys)
-    tdt = torch.float32 if args.dtype == "f32" else torch.float64
-    U0 = torch.zeros((5,) + shape, dtype=tdt, device="cuda:0")
-    U0[0] = 1.0
-    U0[4] = 1.0 / (gamma - 1.0)  # rest, rho = 1, p = 1
-    s.set_state(U0)
+    es = 4 if args.dtype == "f32" else 8
+    s = make_solver(n, args.dtype)
+    s.set_state(rest_state_device(n, args.dtype))
     torch.cuda.synchronize()
-    del U0
     print(f"# warmup {args.warmup} steps at {n}^3 {args.dtype}", file=sys.stderr, flush=True)
     s.step(args.warmup, 0.0)
     torch.cuda.synchronize()
 
-    s.set_timing(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(s.stream)
-    s.step(args.steps, 0.0)
-    ev1.record(s.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms, launches = s.timing()
-    s.set_timing(False)
+    # the timed region: exactly --steps steps, no per-launch events
+    gpu_ms, wall = timed_steps(s, args.steps)
     bad, first = s.check()
     t_sim, nstep = s.clock()
     print(f"# timed {args.steps} steps: {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms), t = {t_sim:.4f}, "
           f"bad cells {bad}", file=sys.stderr, flush=True)
     if bad:
         raise SystemExit(f"unphysical cells after the run (first at {first})")
+    # per-kernel durations: the same number of steps again with HIP events
+    # recorded around every launch on the library's stream
+    s.set_timing(True)
+    pass_ms, _ = timed_steps(s, args.steps)
+    ms, launches = s.timing()
+    s.set_timing(False)
 
     seconds = gpu_ms / 1e3
     value = N * args.steps / seconds
-    es = 4 if args.dtype == "f32" else 8
     st2_ms = ms[mh.TIME_STAGE2] / max(launches[mh.TIME_STAGE2], 1)
     st1_ms = ms[mh.TIME_STAGE1] / max(launches[mh.TIME_STAGE1], 1)
     bytes2 = 15 * es * N  # read U1, read U^n, write U^{n+1}: 3 x 5 fields
@@ -265,6 +415,7 @@ def main():
     ach1 = bytes1 / (st1_ms / 1e3) / 1e9
     traffic = measured_traffic() if args.dtype == "f32" and n == 512 else None
     flops2 = FLOP_STAGE2 * N / (st2_ms / 1e3) / 1e12
+    step_frac = 25 * es * value / 1e9 / HBM_PEAK_GBS
     rec = {
         "metric": "cell-updates/s & %HBM BW at 512^3 fp32; corrected-64^3 L2 err vs plain",
         "value": value,
@@ -285,30 +436,38 @@ def main():
             "cells": N,
             "bytes_per_cell_update": 25 * es,
             "effective_GBps": 25 * es * value / 1e9,
+            "hbm_frac_step_algorithmic": step_frac,
+            "hbm_target_frac": HBM_TARGET_FRAC,
+            "hbm_target_met": step_frac >= HBM_TARGET_FRAC,
             "stage1_ms": st1_ms,
             "stage2_ms": st2_ms,
             "prologue_ms": ms[mh.TIME_PROLOGUE] / max(launches[mh.TIME_PROLOGUE], 1),
+            "timing_pass_ms_per_step": pass_ms / args.steps,
             "stage1_GBps": ach1,
             "stage2_GBps": ach2,
-            "hbm_frac_stage2_algorithmic": ach2 / HBM_PEAK_GBS,
+            "hbm_frac_stage1_algorithmic": ach1 / HBM_PEAK_GBS,
             "hbm_frac_stage2_measured": (traffic / (st2_ms / 1e3) / 1e9 / HBM_PEAK_GBS
                                          if traffic else None),
-            "hbm_frac_step_algorithmic": 25 * es * value / 1e9 / HBM_PEAK_GBS,
             "t_end": t_sim,
         },
         "roofline": {
-            "bound": "alu",
+            "bound": "hbm",
             "kernel": "k_stage<2> (RK stage 2 + forcing + cooling + CFL max)",
-            "achieved": flops2,
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": flops2 / FP32_VECTOR_PEAK_TFLOPS,
+            "achieved": ach2,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach2 / HBM_PEAK_GBS,
             "traffic": traffic,
-            "flop_per_cell": FLOP_STAGE2,
+            "bytes_per_cell": 15 * es,
+            "cells_per_launch": N,
+            "alu": {"achieved": flops2, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": flops2 / FP32_VECTOR_PEAK_TFLOPS, "flop_per_cell": FLOP_STAGE2},
         },
     }
     del s
     torch.cuda.empty_cache()
+    if not args.no_extra:
+        rec["extra"] = extra_inputs(n, args.dtype, args.steps, args.warmup)
     if not args.no_corrector_study:
         print("# solver-in-the-loop study: fine 256^3, coarse 64^3", file=sys.stderr, flush=True)
         rec["corrector"] = corrector_study()

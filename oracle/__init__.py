@@ -142,6 +142,7 @@ def lib():
             "or_fft_gravity_vjp": (None, [cp, dp, dp]),
             "or_gravity_accel": (ctypes.c_int, [cp, dp, dp, dp]),
             "or_num_threads": (ctypes.c_int, []),
+            "or_set_num_threads": (None, [ctypes.c_int]),
             "or_rhs_vjp": (None, [cp, dp, dp, dp]),
             "or_rk2_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
             "or_euler_vjp": (None, [cp, dp, ctypes.c_double, dp, dp]),
@@ -232,6 +233,11 @@ def _shape(c: Config):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls in this process."""
+    lib().or_set_num_threads(int(n))
 
 
 def primitives(c, U):

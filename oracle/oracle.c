@@ -660,3 +660,4 @@ double or_step(const or_config *c, double *U, double dt_fixed, double dt_cap,
 /* threads the OpenMP loops above run on (reported with CPU timings) */
 #include <omp.h>
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

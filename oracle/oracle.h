@@ -105,6 +105,7 @@ void or_fft_gravity(const or_config *c, const double *rho, double *phi, double *
 void or_fft_gravity_vjp(const or_config *c, const double *accb, double *rhob);
 
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 /* reverse-mode derivatives (oracle_adjoint.c) */
 void or_hllc_vjp(const double wl[5], const double wr[5], double g, const double Fb[5],

@@ -71,6 +71,7 @@ template <typename T, int LIM>
 __device__ __forceinline__ T limited_slope(T wm, T w0, T wp, int rl = 0) {
   if (LIM == LIM_NONE) return T(0);
   if (LIM == LIM_GENERIC) return slope_of(rl, wp - w0, w0 - wm);
+  if (LIM == LIM_VANLEER) return slope_of(LIM_VANLEER, wp - w0, w0 - wm);
   return minmod(wp - w0, w0 - wm);
 }
 
@@ -713,6 +714,19 @@ static void fill_geom(StageArgs<T>& a, const StageGeom& g) {
   a.nb_per_xcd = (nb + 7) / 8;
 }
 
+template <typename T, int LM>
+static void launch_stage_lim(int stage, bool force, bool cool, const StageArgs<T>& a, dim3 grid,
+                             dim3 block, hipStream_t s) {
+#define MH_LAUNCH(ST, FO, CO) hipLaunchKernelGGL((k_stage<T, ST, LM, FO, CO>), grid, block, 0, s, a)
+  if (stage == 1) MH_LAUNCH(1, false, false);
+  else if (stage == 3) MH_LAUNCH(3, false, false);
+  else if (force && cool) MH_LAUNCH(2, true, true);
+  else if (force) MH_LAUNCH(2, true, false);
+  else if (cool) MH_LAUNCH(2, false, true);
+  else MH_LAUNCH(2, false, false);
+#undef MH_LAUNCH
+}
+
 template <typename T>
 hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs<T> a,
                         const StageGeom& g, hipStream_t s) {
@@ -722,37 +736,18 @@ hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs
   fill_geom(a, g);
   dim3 block(TX, TY);
   dim3 grid(8 * a.nb_per_xcd);
-#define MH_LAUNCH(ST, LM, FO, CO) \
-  hipLaunchKernelGGL((k_stage<T, ST, LM, FO, CO>), grid, block, 0, s, a)
-  // minmod or none with HLLC: the specialised kernels; any other limiter or
-  // solver: the kernel that reads them at run time
-  if (a.rs != RS_HLLC || (limiter != LIM_MINMOD && limiter != LIM_NONE) || a.dflux)
+  // minmod, van Leer (the paper's fiducial limiter) or none with HLLC: the
+  // specialised kernels; any other limiter or solver, or a flux-correction
+  // field: the kernel that reads them at run time
+  if (a.rs != RS_HLLC || a.dflux ||
+      (limiter != LIM_MINMOD && limiter != LIM_NONE && limiter != LIM_VANLEER))
     limiter = LIM_GENERIC;
-  if (stage == 1) {
-    if (limiter == LIM_NONE) MH_LAUNCH(1, LIM_NONE, false, false);
-    else if (limiter == LIM_GENERIC) MH_LAUNCH(1, LIM_GENERIC, false, false);
-    else MH_LAUNCH(1, LIM_MINMOD, false, false);
-  } else if (stage == 3) {
-    if (limiter == LIM_NONE) MH_LAUNCH(3, LIM_NONE, false, false);
-    else if (limiter == LIM_GENERIC) MH_LAUNCH(3, LIM_GENERIC, false, false);
-    else MH_LAUNCH(3, LIM_MINMOD, false, false);
-  } else if (limiter == LIM_GENERIC) {
-    if (force && cool) MH_LAUNCH(2, LIM_GENERIC, true, true);
-    else if (force) MH_LAUNCH(2, LIM_GENERIC, true, false);
-    else if (cool) MH_LAUNCH(2, LIM_GENERIC, false, true);
-    else MH_LAUNCH(2, LIM_GENERIC, false, false);
-  } else if (limiter == LIM_NONE) {
-    if (force && cool) MH_LAUNCH(2, LIM_NONE, true, true);
-    else if (force) MH_LAUNCH(2, LIM_NONE, true, false);
-    else if (cool) MH_LAUNCH(2, LIM_NONE, false, true);
-    else MH_LAUNCH(2, LIM_NONE, false, false);
-  } else {
-    if (force && cool) MH_LAUNCH(2, LIM_MINMOD, true, true);
-    else if (force) MH_LAUNCH(2, LIM_MINMOD, true, false);
-    else if (cool) MH_LAUNCH(2, LIM_MINMOD, false, true);
-    else MH_LAUNCH(2, LIM_MINMOD, false, false);
-  }
-#undef MH_LAUNCH
+  if (limiter == LIM_NONE) launch_stage_lim<T, LIM_NONE>(stage, force, cool, a, grid, block, s);
+  else if (limiter == LIM_VANLEER)
+    launch_stage_lim<T, LIM_VANLEER>(stage, force, cool, a, grid, block, s);
+  else if (limiter == LIM_GENERIC)
+    launch_stage_lim<T, LIM_GENERIC>(stage, force, cool, a, grid, block, s);
+  else launch_stage_lim<T, LIM_MINMOD>(stage, force, cool, a, grid, block, s);
   return hipGetLastError();
 }
 
