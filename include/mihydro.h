@@ -341,9 +341,48 @@ mh_status mh_corr_get_grad(mh_corr *c, float *grad, int where);
 /* Copies an activation of the last forward pass: 0 x (bf16, [cells][32]:
  * channel c < 5 holds hi = bf16(x_c), channel 5 + c holds bf16(x_c - hi)),
  * 1 z1 (fp32, [cells][32]), 2 h1 (bf16), 3 z2 (fp32), 4 h2 (bf16),
- * 5 y (fp32, [cells][16]); cells = batch n^3.  MH_HOST synchronises. */
+ * 5 y (fp32, [cells][16]); or a gradient of the last reverse pass
+ * (mh_corr_backward, mh_corr_loss_grad): 6 dY = bf16(scale dL/dU')
+ * (bf16, [cells][16], channels >= 5 zero), 7 dZ2 (bf16, [cells][32]),
+ * 8 dZ1 (bf16, [cells][32]), 9 the first layer's transposed convolution of
+ * dZ1 (fp32, [cells][16]; channel c < 5 the gradient of input part hi,
+ * 5 + c of part lo; written only when dL/dU was requested); cells =
+ * batch n^3.  MH_HOST synchronises.  Errors: MH_E_INVALID (null handle or
+ * destination, which outside 0..9, bad where). */
 mh_status mh_corr_get_activation(mh_corr *c, int which, void *dst, int where);
 void mh_corr_destroy(mh_corr *c);
+
+/* The corrector inside the step (Sec. 8, the solver-in-the-loop update
+ * U^{n+1} = U* + s Net(U*), U* = H(U^n) the plain coarse step): advances B
+ * contexts together by nsteps corrected steps.  Each step enqueues every
+ * context's plain step, gathers the B states into stage[0 .. B 5 n^3),
+ * applies the corrector to the batch into stage[B 5 n^3 .. 2 B 5 n^3) with
+ * mh_corr_apply's semantics (residual update, positivity floor, fallback to
+ * the plain states when a value is non-finite or too many cells needed the
+ * floor) and scatters the result back into the contexts.  No step waits for
+ * the host.
+ *   ctxs      B distinct contexts with the same cubic grid n^3 and dtype,
+ *             created on one stream; corr: a state-mode corrector of batch B,
+ *             cube n and that dtype, on the same stream.
+ *   stage     caller device buffer of 2 B 5 n^3 values of the dtype.
+ *   dts       device array of nsteps * B doubles: step s of context b takes
+ *             dts[s B + b]; NULL = CFL steps (each context's dt from its own
+ *             corrected state).  The clock, OU forcing and the other sources
+ *             advance as in mh_step.
+ *   use_graph 1: one corrected step is captured into a HIP graph and
+ *             replayed nsteps times (synchronises at the end); contexts with
+ *             gravity are rejected in this mode (MH_E_UNSUPPORTED: the
+ *             multigrid convergence test reads the host).  0: launched
+ *             kernel by kernel.  Both give bitwise the same states.
+ *   fallbacks optional host pointer: the number of steps whose correction
+ *             fell back to the plain states (synchronises).
+ * Errors (message in mh_last_error(ctxs[0])): MH_E_INVALID (null pointers,
+ * repeated contexts, nsteps < 0, different streams), MH_E_SHAPE (non-cubic
+ * grid, grids or dtypes that differ, a corrector that does not match),
+ * MH_E_UNSUPPORTED, MH_E_DEVICE. */
+mh_status mh_step_corrected(mh_ctx *const *ctxs, int32_t B, mh_corr *corr, void *stage,
+                            int32_t nsteps, const double *dts, int32_t use_graph,
+                            int64_t *fallbacks);
 
 /* Conservative r^3 block average of a fine state [5][nf^3] onto
  * [5][(nf/r)^3] (targets of the corrector from a fine run); device arrays of

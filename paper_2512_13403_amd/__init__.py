@@ -45,7 +45,7 @@ EXPORTED = [
     "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
     "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
     "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs", "mh_fft3_query_workspace",
-    "mh_fft3", "mh_set_flux_correction", "mh_fft3_noalloc",
+    "mh_fft3", "mh_set_flux_correction", "mh_fft3_noalloc", "mh_step_corrected",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -151,6 +151,8 @@ def load_library():
                         vp],
             "mh_set_flux_correction": [vp, vp, vp],
             "mh_fft3_noalloc": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp],
+            "mh_step_corrected": [ctypes.POINTER(vp), ctypes.c_int32, vp, vp, ctypes.c_int32,
+                                  vp, ctypes.c_int32, i64p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -606,10 +608,11 @@ class Corrector:
         return out
 
     def activation(self, which: int) -> np.ndarray:
-        """0 x, 1 z1, 2 h1, 3 z2, 4 h2, 5 y of the last forward pass, as float64
-        arrays [cells][channels] (bf16 ones widened exactly)."""
-        ch = 16 if which == 5 else 32
-        if which in (0, 2, 4):
+        """0 x, 1 z1, 2 h1, 3 z2, 4 h2, 5 y of the last forward pass, or 6 dY,
+        7 dZ2, 8 dZ1, 9 the first layer's input gradient of the last reverse
+        pass, as float64 arrays [cells][channels] (bf16 ones widened exactly)."""
+        ch = 16 if which in (5, 6, 9) else 32
+        if which in (0, 2, 4, 6, 7, 8):
             raw = np.empty((self.cells, ch), dtype=np.uint16)
         else:
             raw = np.empty((self.cells, ch), dtype=np.float32)
@@ -643,6 +646,39 @@ def fft3(x, inverse: bool = False):
     if st != OK:
         raise MHError(st, "mh_fft3")
     return x
+
+
+def step_corrected(solvers, corrector, nsteps: int, dts=None, use_graph: bool = True,
+                   stage=None, count_fallbacks: bool = False):
+    """mh_step_corrected: advances the solvers (one per batch member of the
+    state-mode corrector, all on one stream) by nsteps corrected steps.  dts:
+    CUDA float64 tensor [nsteps][B] of step sizes, or None for CFL steps.
+    stage: optional CUDA buffer of 2 B 5 n^3 values of the dtype (allocated
+    here when None).  Returns the number of fallbacks when count_fallbacks
+    (synchronises), else None."""
+    import torch
+
+    lib = load_library()
+    B = len(solvers)
+    s0 = solvers[0]
+    need = 2 * B * 5 * int(np.prod(s0.shape))
+    if stage is None:
+        stage = torch.empty(need, dtype=s0.torch_dtype, device=s0.device)
+    elif stage.numel() < need or stage.dtype != s0.torch_dtype or not stage.is_contiguous():
+        raise ValueError("stage must be a contiguous tensor of 2 B 5 n^3 values of the dtype")
+    if dts is not None:
+        if (tuple(dts.shape) != (nsteps, B) or dts.dtype != torch.float64 or not dts.is_cuda
+                or not dts.is_contiguous()):
+            raise ValueError("dts must be a contiguous CUDA float64 tensor [nsteps][B]")
+    arr = (ctypes.c_void_p * B)(*[s.ctx.value for s in solvers])
+    fb = ctypes.c_int64(0)
+    corrector._keep_step = (stage, dts)
+    st = lib.mh_step_corrected(arr, B, corrector.h, ctypes.c_void_p(stage.data_ptr()), nsteps,
+                               ctypes.c_void_p(dts.data_ptr()) if dts is not None else None,
+                               int(bool(use_graph)), ctypes.byref(fb) if count_fallbacks else None)
+    if st != OK:
+        raise MHError(st, f"mh_step_corrected: {lib.mh_last_error(solvers[0].ctx).decode()}")
+    return fb.value if count_fallbacks else None
 
 
 def fft3_noalloc(x, inverse: bool = False):

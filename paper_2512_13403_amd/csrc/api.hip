@@ -11,6 +11,7 @@
 
 #include "../../include/mihydro.h"
 #include "mg.h"
+#include "mh_corrector.h"
 #include "mh_adjoint.h"
 #include "mh_device.h"
 #include "mh_launch.h"
@@ -424,8 +425,11 @@ static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) 
   return a;
 }
 
+// dt_sched (device, or null): the steps take their dt from this schedule,
+// entry clk->sched_pos * sched_stride, instead of `dt`
 template <typename T>
-static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, double* dt_out) {
+static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, double* dt_out,
+                           const double* dt_sched = nullptr, long long sched_stride = 0) {
   const mh_grid_desc& g = c->g;
   const mh_physics_desc& p = c->p;
   StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
@@ -451,10 +455,13 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
   pa.t_stop = t_stop;
   pa.forcing = force;
   if (force) pa.ou = ou_args(c);
+  pa.dt_sched = dt_sched;
+  pa.sched_stride = sched_stride;
+  const bool cfl = !(dt > 0.0) && !dt_sched;
 
   MH_HIP(c, launch_clock_reset_health(clk, c->stream));
   for (int s = 0; s < nsteps; ++s) {
-    if (!c->smax_valid && !(dt > 0.0)) {
+    if (!c->smax_valid && cfl) {
       const long tk = time_begin(c, MH_TIME_OTHER);
       MH_HIP(c, launch_smax<T>(U, geom, (T)g.gamma, ih, clk, c->stream));
       if (table && ctab.rate)
@@ -558,6 +565,144 @@ extern "C" mh_status mh_step(mh_ctx* c, int32_t nsteps, double dt, double t_stop
     MH_HIP(c, hipStreamSynchronize(c->stream));
     *t_out = hc.t;
   }
+  return MH_OK;
+}
+
+// ------------------------------------------------- batched corrected steps
+
+// One corrected step of the B contexts, enqueued on their common stream:
+// each context's plain step, the gather of the B states into `in`, the
+// corrector's batched pass into `out`, the scatter back, and (CFL steps) the
+// signal speed of the corrected states for the next step's dt.
+template <typename T>
+static mh_status corrected_step(mh_ctx* const* ctxs, int B, mh_corr* corr, T* in, T* out,
+                                const double* dts) {
+  const size_t bytes = 5 * (size_t)ctxs[0]->cells() * sizeof(T);
+  for (int b = 0; b < B; ++b) {
+    mh_status st = step_impl<T>(ctxs[b], 1, 0.0, INFINITY, nullptr, dts ? dts + b : nullptr, B);
+    if (st != MH_OK) return st;
+  }
+  for (int b = 0; b < B; ++b)
+    MH_HIP(ctxs[0], launch_copy(ctxs[b]->ws + ctxs[b]->L.U, in + (size_t)b * bytes / sizeof(T),
+                                bytes, ctxs[0]->stream));
+  MH_HIP(ctxs[0], corr_apply_enqueue(corr, in, out, ctxs[0]->stream));
+  for (int b = 0; b < B; ++b)
+    MH_HIP(ctxs[0], launch_copy(out + (size_t)b * bytes / sizeof(T), ctxs[b]->ws + ctxs[b]->L.U,
+                                bytes, ctxs[0]->stream));
+  if (!dts) {
+    for (int b = 0; b < B; ++b) {
+      mh_ctx* c = ctxs[b];
+      const mh_grid_desc& g = c->g;
+      StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
+      const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
+      MH_HIP(c, launch_smax<T>(c->at<T>(c->L.U), geom, (T)g.gamma, ih, c->clk(), c->stream));
+    }
+  }
+  return MH_OK;
+}
+
+template <typename T>
+static mh_status step_corrected_impl(mh_ctx* const* ctxs, int B, mh_corr* corr, void* stage,
+                                     int nsteps, const double* dts, bool graph) {
+  mh_ctx* c0 = ctxs[0];
+  const size_t per = 5 * (size_t)c0->cells() * (size_t)B;
+  T* in = (T*)stage;
+  T* out = in + per;
+  MH_HIP(c0, corr_fallbacks_reset(corr));
+  for (int b = 0; b < B; ++b) {
+    MH_HIP(c0, launch_sched_reset(ctxs[b]->clk(), c0->stream));
+    if (!dts && !ctxs[b]->smax_valid) {
+      // CFL speed of a state that no step has produced yet
+      mh_ctx* c = ctxs[b];
+      const mh_grid_desc& g = c->g;
+      StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
+      const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
+      MH_HIP(c, launch_smax<T>(c->at<T>(c->L.U), geom, (T)g.gamma, ih, c->clk(), c->stream));
+      c->smax_valid = true;
+    }
+  }
+  if (!graph || nsteps == 0) {
+    for (int s = 0; s < nsteps; ++s) {
+      mh_status st = corrected_step<T>(ctxs, B, corr, in, out, dts);
+      if (st != MH_OK) return st;
+    }
+    return MH_OK;
+  }
+  // One corrected step captured into a graph (kernel nodes only) and replayed
+  // on the contexts' stream.  The capture records on a stream of its own (the
+  // contexts' stream may be the null stream, which cannot capture); nothing
+  // runs during the capture.
+  hipStream_t cs = nullptr;
+  MH_HIP(c0, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const hipStream_t user = c0->stream;
+  std::vector<int> timing(B);
+  for (int b = 0; b < B; ++b) {
+    timing[b] = ctxs[b]->timing;
+    ctxs[b]->timing = false;
+    ctxs[b]->stream = cs;
+  }
+  hipGraph_t gr = nullptr;
+  hipGraphExec_t ex = nullptr;
+  hipError_t ec = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  mh_status st = MH_OK;
+  if (ec == hipSuccess) {
+    st = corrected_step<T>(ctxs, B, corr, in, out, dts);
+    ec = hipStreamEndCapture(cs, &gr);
+  }
+  for (int b = 0; b < B; ++b) {
+    ctxs[b]->timing = timing[b];
+    ctxs[b]->stream = user;
+  }
+  (void)hipStreamDestroy(cs);
+  if (st != MH_OK) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return st;
+  }
+  MH_HIP(c0, ec);
+  hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  for (int s = 0; e == hipSuccess && s < nsteps; ++s) e = hipGraphLaunch(ex, c0->stream);
+  // the executable graph is released once its launches have run
+  const hipError_t es = hipStreamSynchronize(c0->stream);
+  if (ex) (void)hipGraphExecDestroy(ex);
+  (void)hipGraphDestroy(gr);
+  MH_HIP(c0, e);
+  MH_HIP(c0, es);
+  return MH_OK;
+}
+
+extern "C" mh_status mh_step_corrected(mh_ctx* const* ctxs, int32_t B, mh_corr* corr,
+                                       void* stage, int32_t nsteps, const double* dts,
+                                       int32_t use_graph, int64_t* fallbacks) {
+  if (!ctxs || B < 1 || !ctxs[0]) return MH_E_INVALID;
+  mh_ctx* c0 = ctxs[0];
+  if (!corr || !stage || nsteps < 0 || (use_graph != 0 && use_graph != 1))
+    return set_err(c0, MH_E_INVALID, "mh_step_corrected: null corrector or stage, nsteps < 0 "
+                                     "or use_graph not 0/1");
+  const mh_grid_desc& g = c0->g;
+  if (g.n[0] != g.n[1] || g.n[0] != g.n[2])
+    return set_err(c0, MH_E_SHAPE, "mh_step_corrected: the grid must be a cube");
+  for (int b = 0; b < B; ++b) {
+    mh_ctx* c = ctxs[b];
+    if (!c) return set_err(c0, MH_E_INVALID, "mh_step_corrected: context %d is null", b);
+    for (int q = 0; q < b; ++q)
+      if (ctxs[q] == c) return set_err(c0, MH_E_INVALID, "mh_step_corrected: context %d repeats", b);
+    if (c->g.dtype != g.dtype || c->g.n[0] != g.n[0] || c->g.n[1] != g.n[1] || c->g.n[2] != g.n[2])
+      return set_err(c0, MH_E_SHAPE, "mh_step_corrected: context %d differs in grid or dtype", b);
+    if (c->stream != c0->stream || corr_stream(corr) != c0->stream)
+      return set_err(c0, MH_E_INVALID, "mh_step_corrected: contexts and corrector must share "
+                                       "one stream");
+    if (use_graph && (c->p.flags & MH_SRC_GRAVITY))
+      return set_err(c0, MH_E_UNSUPPORTED, "mh_step_corrected: a captured step cannot hold the "
+                                           "gravity solve (its convergence test reads the host)");
+  }
+  if (!corr_matches(corr, g.n[0], B, g.dtype))
+    return set_err(c0, MH_E_SHAPE, "mh_step_corrected: the corrector is not a state corrector "
+                                   "of this cube, batch %d and dtype", B);
+  mh_status st = g.dtype == MH_F64
+                     ? step_corrected_impl<double>(ctxs, B, corr, stage, nsteps, dts, use_graph)
+                     : step_corrected_impl<float>(ctxs, B, corr, stage, nsteps, dts, use_graph);
+  if (st != MH_OK) return st;
+  if (fallbacks) MH_HIP(c0, corr_fallbacks_read(corr, fallbacks));
   return MH_OK;
 }
 

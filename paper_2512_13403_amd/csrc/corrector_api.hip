@@ -58,7 +58,9 @@ CorrLayout corr_layout(const mh_corr_desc* d) {
   const size_t nd = std::max((cells + 255) / 256, (size_t)d->batch * (64 * 2 + 2));
   L.dpart = take(nd * sizeof(double));
   L.loss = take(sizeof(double));
-  L.counters = take(2 * sizeof(unsigned long long));
+  // [floored cells, non-finite cells] of the last floor, then the number of
+  // fallbacks counted by the batched corrected step
+  L.counters = take(3 * sizeof(unsigned long long));
   // per-block floored / non-finite counts of the positivity floor
   L.cpart = take(2 * ((cells + 255) / 256) * sizeof(unsigned long long));
   L.total = off;
@@ -196,6 +198,61 @@ static mh_status apply_impl(mh_corr* c, const T* U, T* out, int64_t* floored, in
   return MH_OK;
 }
 
+namespace {
+// counters[2] += 1 when the floor just run made the batch fall back
+__global__ void k_fallback_count(unsigned long long* counters, double limit) {
+  if (threadIdx.x == 0 && (counters[1] > 0 || (double)counters[0] > limit)) counters[2] += 1;
+}
+
+__global__ void k_fallback_reset(unsigned long long* counters) {
+  if (threadIdx.x == 0) counters[2] = 0;
+}
+}  // namespace
+
+namespace mh {
+
+hipStream_t corr_stream(const mh_corr* c) { return c->stream; }
+
+bool corr_matches(const mh_corr* c, int n, int batch, int dtype) {
+  return c->d.mode == MH_CORR_STATE && c->d.n == n && c->d.batch == batch && c->d.dtype == dtype;
+}
+
+hipError_t corr_apply_enqueue(mh_corr* c, const void* U, void* out, hipStream_t s) {
+  hipError_t e;
+  if (c->d.dtype == MH_F64) {
+    e = corr_forward<double>(c->B, c->st, c->d.n, c->d.batch, (const double*)U, (double*)out,
+                             false, true, s);
+    if (e == hipSuccess)
+      e = corr_floor<double>(c->B, (const double*)U, (double*)out, c->d.n, c->d.batch,
+                             c->d.gamma, c->d.floor_rel, c->d.fallback_frac, s);
+  } else {
+    e = corr_forward<float>(c->B, c->st, c->d.n, c->d.batch, (const float*)U, (float*)out,
+                            false, true, s);
+    if (e == hipSuccess)
+      e = corr_floor<float>(c->B, (const float*)U, (float*)out, c->d.n, c->d.batch, c->d.gamma,
+                            c->d.floor_rel, c->d.fallback_frac, s);
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fallback_count, dim3(1), dim3(64), 0, s, c->B.counters,
+                     c->d.fallback_frac * (double)c->cells());
+  return hipGetLastError();
+}
+
+hipError_t corr_fallbacks_reset(mh_corr* c) {
+  hipLaunchKernelGGL(k_fallback_reset, dim3(1), dim3(64), 0, c->stream, c->B.counters);
+  return hipGetLastError();
+}
+
+hipError_t corr_fallbacks_read(mh_corr* c, int64_t* count) {
+  unsigned long long v = 0;
+  hipError_t e = hipMemcpyAsync(&v, c->B.counters + 2, sizeof v, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  *count = (int64_t)v;
+  return e;
+}
+
+}  // namespace mh
+
 extern "C" mh_status mh_corr_apply(mh_corr* c, const void* U, void* U_out, int64_t* floored,
                                    int32_t* fell_back) {
   if (!c || !U || !U_out || U == U_out) return MH_E_INVALID;
@@ -277,7 +334,7 @@ extern "C" mh_status mh_corr_train_step(mh_corr* c, const void* U, const void* t
 }
 
 extern "C" mh_status mh_corr_get_activation(mh_corr* c, int which, void* dst, int where) {
-  if (!c || !dst || which < 0 || which > 5 || (where != MH_HOST && where != MH_DEVICE))
+  if (!c || !dst || which < 0 || which > 9 || (where != MH_HOST && where != MH_DEVICE))
     return MH_E_INVALID;
   const size_t cells = (size_t)c->cells();
   const void* src = nullptr;
@@ -288,7 +345,11 @@ extern "C" mh_status mh_corr_get_activation(mh_corr* c, int which, void* dst, in
     case 2: src = c->B.h1; bytes = cells * 32 * 2; break;
     case 3: src = c->B.z2; bytes = cells * 32 * 4; break;
     case 4: src = c->B.h2; bytes = cells * 32 * 2; break;
-    default: src = c->B.y; bytes = cells * 16 * 4; break;
+    case 5: src = c->B.y; bytes = cells * 16 * 4; break;
+    case 6: src = c->B.dy16; bytes = cells * 16 * 2; break;
+    case 7: src = c->B.dz2; bytes = cells * 32 * 2; break;
+    case 8: src = c->B.dz1; bytes = cells * 32 * 2; break;
+    default: src = c->B.gx; bytes = cells * 16 * 4; break;
   }
   MH_CHK(hipMemcpyAsync(dst, src, bytes,
                         where == MH_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,

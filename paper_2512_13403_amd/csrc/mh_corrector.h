@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace mh {
 
@@ -51,5 +52,19 @@ hipError_t corr_zero_grad(const CorrBuffers& B, hipStream_t s);
 hipError_t corr_adam(const CorrBuffers& B, int it, float lr, hipStream_t s);
 template <typename T>
 hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStream_t s);
+
+}  // namespace mh
+
+// the batched corrected step of api.hip drives a corrector through these
+typedef struct mh_corr mh_corr;
+namespace mh {
+hipStream_t corr_stream(const mh_corr* c);
+// a state-mode corrector of this cube size, batch and dtype
+bool corr_matches(const mh_corr* c, int n, int batch, int dtype);
+// mh_corr_apply's correction of the batch U into out (forward, residual,
+// floor, fallback), enqueued on stream s only; counts a fallback on the device
+hipError_t corr_apply_enqueue(mh_corr* c, const void* U, void* out, hipStream_t s);
+hipError_t corr_fallbacks_reset(mh_corr* c);
+hipError_t corr_fallbacks_read(mh_corr* c, int64_t* count);
 
 }  // namespace mh

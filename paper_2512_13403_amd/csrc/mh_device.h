@@ -33,6 +33,7 @@ struct DevClock {
   double mg_rnorm2;         // ||r||^2 of the last residual
   double mean;              // scratch: mean of a field
   unsigned long long crate; // bit pattern of max |Edot| / E_th (tabulated cooling)
+  long long sched_pos;      // next entry of a device dt schedule (batched corrected steps)
 };
 
 enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1 };

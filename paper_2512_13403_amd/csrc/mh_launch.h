@@ -59,6 +59,8 @@ struct PrologueArgs {
   double t_stop;
   int forcing;
   OUArgs ou;
+  const double* dt_sched;  // device dt schedule, entry clk->sched_pos * sched_stride (or null)
+  long long sched_stride;
 };
 
 template <typename T>
@@ -82,6 +84,8 @@ hipError_t launch_cool_rate(const T* U, const StageGeom& g, T gamma, const CoolT
 hipError_t launch_clock_reset_health(DevClock* clk, hipStream_t s);
 hipError_t launch_clock_set(DevClock* clk, double t, long long step, hipStream_t s);
 hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s);
+hipError_t launch_sched_reset(DevClock* clk, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_ou_init(const OUArgs& a, hipStream_t s);
 
 }  // namespace mh

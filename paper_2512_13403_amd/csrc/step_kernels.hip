@@ -74,7 +74,10 @@ __global__ void k_prologue(const PrologueArgs a) {
   DevClock* clk = a.clk;
   if (t == 0) {
     double dt;
-    if (a.dt_fixed > 0.0) {
+    if (a.dt_sched) {
+      dt = a.dt_sched[clk->sched_pos * a.sched_stride];
+      clk->sched_pos += 1;
+    } else if (a.dt_fixed > 0.0) {
       dt = a.dt_fixed;
     } else {
       const double smax = a.f64 ? bits_to_double_f64(clk->smax) : bits_to_double_f32(clk->smax);
@@ -133,6 +136,41 @@ __global__ void k_prologue(const PrologueArgs a) {
 
 hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_prologue, dim3(1), dim3(MAX_MODES), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_sched_reset(DevClock* clk) {
+  if (threadIdx.x == 0) clk->sched_pos = 0;
+}
+
+hipError_t launch_sched_reset(DevClock* clk, hipStream_t s) {
+  hipLaunchKernelGGL(k_sched_reset, dim3(1), dim3(64), 0, s, clk);
+  return hipGetLastError();
+}
+
+// plain device copy in 16-byte words (the corrected step's gathers and
+// scatters, as kernels so that a captured step holds no copy nodes)
+__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
+                                                uint4* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+__global__ void k_copy1(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+                        size_t n) {
+  for (size_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  if (n16) {
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)src,
+                       (uint4*)dst, n16);
+  }
+  if (bytes % 16)
+    hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, s, (const unsigned char*)src + 16 * n16,
+                       (unsigned char*)dst + 16 * n16, bytes % 16);
   return hipGetLastError();
 }
 

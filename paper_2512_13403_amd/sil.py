@@ -228,10 +228,14 @@ def rel_l2(a, b) -> float:
 def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dict:
     """Plain and corrected coarse rollouts from T_0 of each held-out trajectory
     against its fine run.  The trajectories advance together, one coarse solver
-    each, and the corrector takes all of them in one batched launch per step.
-    Cost = wall clock of the batched rollout; the fine cost is the summed wall
-    clock of the same trajectories' fine groups."""
+    each; the corrected rollout is one call of the library's corrected step
+    (mh_step_corrected: the plain steps and one batched corrector pass per
+    step, replayed from a captured HIP graph, the step sizes from a device
+    schedule).  Cost = wall clock of the batched rollout; the fine cost is the
+    summed wall clock of the same trajectories' fine groups."""
     import torch
+
+    from . import step_corrected
 
     B = len(trajs)
     n = min(len(t.dts) for t in trajs) if nsteps is None else nsteps
@@ -240,8 +244,10 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
                                st["loss_w"], 1e-6, 1e-3))
     corr.set_params(res.theta)
     solvers = [make_solver(nc, t.seed, 1) for t in trajs]
-    buf = torch.empty((B, 5, nc, nc, nc), dtype=solvers[0].torch_dtype, device=solvers[0].device)
-    cor = torch.empty_like(buf)
+    stage = torch.empty(2 * B * 5 * nc ** 3, dtype=solvers[0].torch_dtype,
+                        device=solvers[0].device)
+    dts = torch.tensor(np.stack([t.dts[:n] for t in trajs], axis=1), dtype=torch.float64,
+                       device=solvers[0].device).contiguous()
 
     def reset():
         for c, t in zip(solvers, trajs):
@@ -250,15 +256,12 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
             c.set_clock(float(t.t[0]), int(t.step[0]))
 
     def advance(k, corrected, stats):
-        for c, t in zip(solvers, trajs):
-            c.step(1, float(t.dts[k]))
         if not corrected:
+            for c, t in zip(solvers, trajs):
+                c.step(1, float(t.dts[k]))
             return 0
-        for i, c in enumerate(solvers):
-            c.get_state_into(buf[i])
-        _, _, fb = corr.apply(buf, cor, stats=stats)
-        for i, c in enumerate(solvers):
-            c.set_state(cor[i])
+        fb = step_corrected(solvers, corr, 1, dts[k:k + 1].contiguous(), use_graph=False,
+                            stage=stage, count_fallbacks=stats)
         return int(fb) if stats else 0
 
     out = {}
@@ -267,11 +270,16 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
         reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(n):
-            advance(k, corrected, False)
+        if corrected:
+            step_corrected(solvers, corr, n, dts, use_graph=True, stage=stage)
+        else:
+            for k in range(n):
+                advance(k, False, False)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
-        # errors and fallback counts from a replay (kept out of the timed loop)
+        final = [c.get_state_device() for c in solvers]
+        # errors and fallback counts from a step-by-step replay (kept out of
+        # the timed loop); it ends in the same states as the timed rollout
         reset()
         errs = [[] for _ in trajs]
         fallbacks = 0
@@ -279,6 +287,9 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
             fallbacks += advance(k, corrected, True)
             for i, (c, t) in enumerate(zip(solvers, trajs)):
                 errs[i].append(rel_l2(c.get_state_device()[0], t.T[k + 1][0]))
+        for c, u in zip(solvers, final):
+            if not torch.equal(c.get_state_device(), u):
+                raise RuntimeError("the replayed rollout differs from the timed one")
         out[mode] = dict(rho_rel_l2=errs, seconds=secs, fallbacks=fallbacks)
     for c in solvers:
         c.close()
@@ -313,9 +324,20 @@ def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256,
     log(f"[sil] cost: fine {ev['fine_seconds']:.3f} s, corrected coarse "
         f"{ev['corrected']['seconds']:.3f} s, plain coarse {ev['plain']['seconds']:.3f} s "
         f"(ratio {ev['cost_ratio']:.1f})")
+    # per curriculum phase: the loss of its first iteration and the mean of
+    # its last min(20, length) iterations, each the mean per unrolled step of
+    # that phase's objective (so first and last of a phase are comparable)
+    phases, it0 = [], 0
+    for frac, m in schedule:
+        k = int(round(frac * iters))
+        seg = res.losses[it0:it0 + k]
+        if seg:
+            phases.append(dict(unroll=int(m), iters=len(seg), loss_first=float(seg[0]),
+                               loss_last=float(np.mean(seg[-min(20, len(seg)):]))))
+        it0 += k
     return dict(
         fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch,
-        schedule=[list(p) for p in schedule],
+        schedule=[list(p) for p in schedule], train_phases=phases,
         rho_rel_l2_plain=plain, rho_rel_l2_corrected=corrected,
         error_ratio=corrected / plain,
         rho_rel_l2_plain_mean_over_steps=plain_avg,

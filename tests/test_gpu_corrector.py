@@ -7,8 +7,15 @@ own input activations, so every comparison sees one layer's arithmetic only:
 fp32-accumulated products within 1e-5 of the fp64 sum (relative to the
 layer's largest value), and bf16-rounded activations equal except for
 elements that sit on a rounding boundary, which may differ by one bf16 ulp
-(at most 0.1 % of them).  The end-to-end correction and the gradients, where
-such flips propagate, are compared in norm."""
+(at most 0.1 % of them).  The reverse pass is checked the same way, element
+by element on the GPU's own activations and gradient activations: dY, dZ2
+and dZ1 as bf16 activations, each weight and bias gradient and the first
+layer's input gradient within 1e-5 of the sum of the magnitudes of its
+products (the worst-case error of fp32 accumulation over the ~130 sequential
+MFMA accumulations of one chunk of cells is about 130 * 2^-24 = 8e-6 of that
+sum), and dL/dU within two fp32 roundings.  Only the end-to-end correction
+and gradients against the oracle's own forward pass, where one-ulp flips
+propagate, are compared in norm."""
 import numpy as np
 import pytest
 
@@ -75,6 +82,36 @@ def check_bf16_activation(got, ref):
     assert diff.mean() <= 1e-3, diff.mean()
     if diff.any():
         assert np.all(np.abs(got[diff] - ref[diff]) <= 2.0 ** -7 * np.abs(ref[diff]) + 1e-30)
+
+
+def check_bf16_recomputed(got, ref, err):
+    """A bf16 activation that the oracle recomputes from the GPU's inputs to
+    it (an fp32-accumulated convolution times GELU', then bf16): equal to the
+    rounded oracle value except on at most 0.1 % of the elements, which may
+    differ by one bf16 ulp plus the bound `err` of the GPU's own arithmetic
+    before the rounding."""
+    r = oc.bf16_round(ref)
+    diff = got != r
+    assert diff.mean() <= 1e-3, diff.mean()
+    if diff.any():
+        bound = 2.0 ** -7 * np.abs(r) + err
+        assert np.all(np.abs(got - r)[diff] <= bound[diff] + 1e-300)
+
+
+def dz_error_bound(S, z):
+    """Error bound of dZ = (conv of the upstream bf16 gradient) * GELU'(z) on
+    the GPU before its bf16 rounding, with S the sum of the magnitudes of the
+    convolution's products: fp32 accumulation (1e-5 of S, as for the other
+    products) times |GELU'|, plus S times the absolute error of the GPU's
+    GELU' = Phi + z phi.  That derivative comes from the Numerical Recipes
+    erfc fit (relative error 1.2e-7) and fp32 exp, a relative error well
+    below 1e-6 in each of Phi and z phi; near its root (z = -0.75) the two
+    cancel and only this absolute bound holds."""
+    from scipy.special import erfc
+
+    Phi = 0.5 * erfc(-z / np.sqrt(2.0))
+    phi = np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)
+    return S * (1e-5 * np.abs(oc.gelu_grad(z)) + 1e-6 * (Phi + np.abs(z) * phi))
 
 
 def to_oracle(a, batch, n):
@@ -155,6 +192,85 @@ BLOCKS = [("W1", 0, 4320), ("b1", 4320, 4352), ("W2", 4352, 32000), ("b2", 32000
           ("W3", 32032, 36352), ("b3", 36352, 36357)]
 
 
+def check_sum_bound(got, ref, absref, what, tol=1e-5):
+    """|got - ref| <= tol * (sum of the magnitudes of the products) per element."""
+    err = np.abs(np.asarray(got, dtype=np.float64) - ref)
+    bound = tol * absref + 1e-300
+    worst = float((err / bound).max())
+    assert worst <= 1.0, (what, worst)
+    return worst
+
+
+def check_reverse_pass(c, th, gUc, scale, batch, n, grad=None, input_grad=False):
+    """Element-wise checks of one GPU reverse pass, each step from the GPU's
+    own inputs to it: dY from the upstream gradient gUc (dL/dU' of the oracle
+    on the GPU's y), the layer-3 gradients from dY and h2, dZ2 from dY, W3
+    and z2, the layer-2 gradients from dZ2 and h1, dZ1 from dZ2, W2 and z1,
+    the layer-1 gradients from dZ1 and both input parts, and (input_grad) the
+    transposed first layer from dZ1.  grad: the GPU's parameter gradient of
+    this pass alone."""
+    p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
+    B = lambda a: to_oracle(a, batch, n)
+    x0 = c.activation(0)
+    xhi, xlo = B(x0[:, :5]), B(x0[:, 5:10])
+    z1, h1, z2, h2 = (B(c.activation(k)) for k in (1, 2, 3, 4))
+    dy = c.activation(6)
+    assert not dy[:, 5:].any()
+    dy = B(dy[:, :5])
+    check_bf16_activation(dy.reshape(-1, 5),
+                          oc.bf16_round(np.moveaxis(gUc, 1, -1) * scale).reshape(-1, 5))
+    dz2 = B(c.activation(7))
+    check_bf16_recomputed(dz2, oc.conv3_input_grad(dy, p["W3"]) * oc.gelu_grad(z2),
+                          dz_error_bound(oc.conv3_input_grad(np.abs(dy), np.abs(p["W3"])), z2))
+    dz1 = B(c.activation(8))
+    check_bf16_recomputed(dz1, oc.conv3_input_grad(dz2, p["W2"]) * oc.gelu_grad(z1),
+                          dz_error_bound(oc.conv3_input_grad(np.abs(dz2), np.abs(p["W2"])), z1))
+    if grad is not None:
+        g = oc.unpack(grad.astype(np.float64))
+        wg = oc.conv3_weight_grad
+        check_sum_bound(g["W3"], wg(dy, h2), wg(np.abs(dy), np.abs(h2)), "W3")
+        check_sum_bound(g["b3"], dy.sum(axis=(0, 1, 2, 3)), np.abs(dy).sum(axis=(0, 1, 2, 3)), "b3")
+        check_sum_bound(g["W2"], wg(dz2, h1), wg(np.abs(dz2), np.abs(h1)), "W2")
+        check_sum_bound(g["b2"], dz2.sum(axis=(0, 1, 2, 3)), np.abs(dz2).sum(axis=(0, 1, 2, 3)),
+                        "b2")
+        check_sum_bound(g["W1"], wg(dz1, xhi) + wg(dz1, xlo),
+                        wg(np.abs(dz1), np.abs(xhi)) + wg(np.abs(dz1), np.abs(xlo)), "W1")
+        check_sum_bound(g["b1"], dz1.sum(axis=(0, 1, 2, 3)), np.abs(dz1).sum(axis=(0, 1, 2, 3)),
+                        "b1")
+    gx = None
+    if input_grad:
+        gx = c.activation(9)
+        ref = oc.conv3_input_grad(dz1, p["W1"])
+        aref = oc.conv3_input_grad(np.abs(dz1), np.abs(p["W1"]))
+        check_sum_bound(gx[:, :5], ref.reshape(-1, 5), aref.reshape(-1, 5), "dX hi")
+        check_sum_bound(gx[:, 5:10], ref.reshape(-1, 5), aref.reshape(-1, 5), "dX lo")
+        gx = B(gx[:, :5])
+    return gx
+
+
+def check_input_grad(gU, gres, gx, std, dtype, gres_err=0.0):
+    """dL/dU = residual path + dX / std, from the GPU's dX: within two
+    roundings of the state dtype of the magnitudes involved, plus gres_err,
+    the bound of the residual path's own rounding differences."""
+    ref = gres + np.moveaxis(gx, -1, 1) / std.reshape(1, 5, 1, 1, 1)
+    mag = np.abs(gres) + np.abs(np.moveaxis(gx, -1, 1) / std.reshape(1, 5, 1, 1, 1))
+    u = 2.0 ** -52 if dtype == "f64" else 2.0 ** -23
+    err = np.abs(gU - ref)
+    assert np.all(err <= 2 * u * mag + gres_err + 1e-300), float(err.max())
+
+
+def loss_grad_rounding(U, y, scale, loss_w, std, batch, n):
+    """Bound of the rounding differences of the loss gradient
+    2 w (U + scale y - T) / (std^2 cells) between two fp64 evaluations: the
+    corrected state U + scale y may be formed with or without a fused
+    multiply-add (one rounding of its magnitude each), and the rest of the
+    expression is evaluated in the same order on both sides."""
+    sy = np.moveaxis(to_oracle(y, batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
+    w = np.asarray(loss_w).reshape(1, 5, 1, 1, 1)
+    s2 = (np.asarray(std) ** 2).reshape(1, 5, 1, 1, 1)
+    return 4.0 * w * 2.0 ** -52 * (np.abs(U) + np.abs(sy)) / s2 / (batch * n ** 3)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_loss_and_gradient(dtype):
     n, batch = 16, 2
@@ -168,6 +284,12 @@ def test_loss_and_gradient(dtype):
     assert L == L2 and np.array_equal(g, g2)  # deterministic reductions
     Lref, gref = oracle_grad_from_gpu(c, U, T, th, std, scale, loss_w, batch, n)
     assert L == pytest.approx(Lref, rel=1e-9)
+    # element by element, each step of the reverse pass on the GPU's inputs
+    y = c.activation(5)[:, :5]
+    Uc = U + np.moveaxis(to_oracle(y, batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
+    _, gUc = oc.loss_and_grad_y(Uc, T, loss_w, std)
+    check_reverse_pass(c, th, gUc, scale, batch, n, grad=g)
+    # and in norm against the oracle's chained reverse pass
     for name, a, b in BLOCKS:
         tol = 1e-4 if name in ("W3", "b3") else 2e-3
         err = np.linalg.norm(g[a:b] - gref[a:b]) / np.linalg.norm(gref[a:b])
@@ -205,8 +327,11 @@ def test_input_gradient_and_accumulation(dtype):
     gref = oc.backward(gl + gup, cache, scale)
     gUref = oc.input_grad(gl + gup, cache, std)
     assert L == pytest.approx(Lref, rel=1e-9)
-    assert np.linalg.norm(g1 - gref) / np.linalg.norm(gref) < 2e-3
+    gx = check_reverse_pass(c, th, gl + gup, scale, batch, n, grad=g1, input_grad=True)
     gU = gU.cpu().numpy()
+    check_input_grad(gU, gl + gup, gx, std, dtype,
+                     loss_grad_rounding(U, y, scale, loss_w, std, batch, n))
+    assert np.linalg.norm(g1 - gref) / np.linalg.norm(gref) < 2e-3
     assert np.linalg.norm(gU - gUref) / np.linalg.norm(gUref) < 2e-3
     # the network path is a visible part of dL/dU
     assert np.linalg.norm(gUref - (gl + gup)) > 1e-2 * np.linalg.norm(gUref)
@@ -315,9 +440,11 @@ def test_flux_mode_output_and_gradients(dtype):
                  z2=to_oracle(c.activation(3), batch, n), h2=to_oracle(c.activation(4), batch, n),
                  y=to_oracle(c.activation(5)[:, :5], batch, n), p=p, rd=oc.bf16_round)
     gref = oc.backward(gup, cache, scale)
+    gx = check_reverse_pass(c, th, gup, scale, batch, n, grad=c.grad(), input_grad=True)
+    gU = gU.cpu().numpy()
+    check_input_grad(gU, np.zeros_like(gup), gx, std, dtype)
     assert np.linalg.norm(c.grad() - gref) / np.linalg.norm(gref) < 2e-3
     gUref = oc.input_grad(gup, cache, std) - gup
-    gU = gU.cpu().numpy()
     assert np.linalg.norm(gU - gUref) / np.linalg.norm(gUref) < 2e-3
     # training against a target is a state-mode operation
     with pytest.raises(mh.MHError):
