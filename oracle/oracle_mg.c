@@ -227,11 +227,16 @@ int or_mg_solve(const or_config *c, int n_, double h, double *phi,
   double *r = (double *)malloc(sizeof(double) * N);
   double fn = sqrt(fixed_sumsq(n, F));
   int cyc = 0;
+  double prev = INFINITY;
   remove_mean(n, phi);
   for (;;) {
     residual(n, h, phi, F, r);
     double rn = sqrt(fixed_sumsq(n, r));
     if (rn <= c->mg_tol * fn || cyc >= c->mg_max_cycles) break;
+    /* with a tolerance, stop once a cycle cuts the residual by less than 10 %:
+       the residual has reached the round-off floor of the arithmetic */
+    if (c->mg_tol > 0.0 && rn > 0.9 * prev) break;
+    prev = rn;
     or_mg_vcycle(c, n_, h, phi, F);
     remove_mean(n, phi);
     ++cyc;

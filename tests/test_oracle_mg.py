@@ -252,3 +252,21 @@ def test_spectral_gravity_adjoint_identity():
     lhs = (g * Jv).sum()
     rhs = (oracle.fft_gravity_vjp(c, g) * v).sum()
     assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_solve_stops_at_the_round_off_floor():
+    """With a tolerance below what the arithmetic can reach, the solve stops
+    once a cycle no longer cuts the residual by 10 % (the round-off floor),
+    well before the cycle cap, with the residual at the floor; with a
+    tolerance of 0 it runs exactly the cap."""
+    n = 32
+    c = mgcfg(n, mg_tol=1e-30, mg_max_cycles=200)
+    rng = np.random.default_rng(3)
+    F = rng.standard_normal((n, n, n))
+    F -= F.mean()
+    phi, cycles = oracle.mg_solve(c, n, 1.0 / n, np.zeros((n, n, n)), F)
+    assert 10 < cycles < 60, cycles
+    r = F - oracle.laplacian(n, 1.0 / n, phi)
+    assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(F)
+    c0 = mgcfg(n, mg_tol=0.0, mg_max_cycles=7)
+    assert oracle.mg_solve(c0, n, 1.0 / n, np.zeros((n, n, n)), F)[1] == 7
