@@ -180,6 +180,121 @@ def adjoint_probe(n=256, reps=10):
           f"forward step {1e3 * (t3 - t2) / reps:.3f} ms", flush=True)
 
 
+def stage_probe(n=512, steps=3):
+    """Short runs of the 512^3 fp32 step in configurations that differ by one
+    phase of the method (slopes off, each source on or off, the van Leer
+    limiter), for per-kernel instruction counters: one text line each."""
+    import torch
+
+    import paper_2512_13403_amd as mh
+
+    base = dict(cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, ou_arms=1.0, ou_zeta=1.0,
+                ou_kmin=1.0, ou_kmax=2.0)
+    F, C = mh.SRC_FORCING, mh.SRC_COOLING
+    cases = (("minmod, forcing + cooling", mh.LIM_MINMOD, F | C),
+             ("first order, forcing + cooling", mh.LIM_NONE, F | C),
+             ("minmod, no sources", mh.LIM_MINMOD, 0),
+             ("minmod, forcing", mh.LIM_MINMOD, F),
+             ("minmod, cooling", mh.LIM_MINMOD, C),
+             ("van Leer, forcing + cooling", mh.LIM_VANLEER, F | C))
+    for name, lim, flags in cases:
+        s = mh.Solver(mh.grid_desc((n,) * 3, (1.0 / n,) * 3, dtype="f32", gamma=GAMMA, cfl=0.4,
+                                   limiter=lim), mh.physics_desc(flags=flags, **base))
+        s.set_state(rest_state_device(n, "f32"))
+        s.step(1, 0.0)
+        s.set_timing(True)
+        ms, _ = timed_steps(s, steps)
+        t, launches = s.timing()
+        print(f"stage probe {n}^3 f32 [{name}]: {ms / steps:.3f} ms/step, stage 1 "
+              f"{t[mh.TIME_STAGE1] / launches[mh.TIME_STAGE1]:.3f} ms, stage 2 "
+              f"{t[mh.TIME_STAGE2] / launches[mh.TIME_STAGE2]:.3f} ms", flush=True)
+        del s
+        torch.cuda.empty_cache()
+
+
+def corrector_probe(n=64, batch=4, reps=10):
+    """The corrector's kernels at the solver-in-the-loop size (batch 4 x 64^3,
+    fp32 states): forward passes, then training steps (forward, loss,
+    reverse pass with the input gradient, ADAM); one text line."""
+    import numpy as np
+    import torch
+
+    import paper_2512_13403_amd as mh
+    import workloads as wl
+
+    U = torch.tensor(np.stack([wl.smooth_random_state((n,) * 3, seed=s, kmax=4)
+                               for s in range(batch)]), dtype=torch.float32, device="cuda")
+    T = U + 0.01 * torch.randn(U.shape, generator=torch.Generator(device="cuda").manual_seed(0),
+                               device="cuda")
+    Ud = U.double().cpu().numpy()
+    mean, std = Ud.mean(axis=(0, 2, 3, 4)), Ud.std(axis=(0, 2, 3, 4)) + 1e-3
+    c = mh.Corrector(mh.corr_desc(n, batch, "f32", GAMMA, mean, std, (1e-2,) * 5, (1.0,) * 5))
+    c.set_params(wl.corrector_init_params(seed=0, out_scale=1.0).astype(np.float32))
+    out = torch.empty_like(U)
+    for _ in range(2):
+        c.apply(U, out, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c.apply(U, out, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        c.zero_grad()
+        c.backward(U, T, None, input_grad=True)
+        c.adam_step(1e-4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"corrector probe {batch} x {n}^3 f32: apply {1e3 * (t1 - t0) / reps:.3f} ms, "
+          f"training step {1e3 * (t2 - t1) / reps:.3f} ms", flush=True)
+
+
+def c4_probe(n=128, nsteps=20, K=20):
+    """The self-gravitating cooling box at 128^3 (GRF density, multigrid
+    gravity with the default V-cycle and red-black Gauss-Seidel smoother):
+    per dtype, the forward CFL steps of a checkpointed rollout, the mean
+    multigrid cycles per step, and the adjoint rollout over them; one text
+    line per dtype."""
+    import numpy as np
+    import torch
+
+    import paper_2512_13403_amd as mh
+    import workloads as wl
+    from paper_2512_13403_amd import rollout as ro
+
+    for dtype, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        s = mh.Solver(mh.grid_desc((n,) * 3, (1.0 / n,) * 3, dtype=dtype),
+                      mh.physics_desc(flags=mh.SRC_GRAVITY | mh.SRC_COOLING, grav_G=wl.JEANS_G,
+                                      mg_tol=tol))
+        U0 = torch.tensor(wl.grf_density_state(n, seed=0), dtype=s.torch_dtype, device="cuda")
+        ro.rollout_forward(s, U0, 2, K)  # graphs captured, caches warm
+        s.set_clock(0.0, 0)
+        s.set_potential(np.zeros((n,) * 3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cycles = 0
+        s.set_state(U0)
+        cks = []
+        dts = []
+        for k in range(nsteps):
+            if k % K == 0:
+                cks.append(ro._snapshot(s))
+            dts.append(float(s.step(1, 0.0, record=True)[0]))
+            cycles += s.mg_cycles()
+        Uf = s.get_state_device()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lam = torch.zeros_like(Uf)
+        lam[0] = Uf[0] - 1.0
+        ro.rollout_backward(s, cks, np.array(dts), K, lam)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        print(f"c4 probe {n}^3 {dtype}: forward {1e3 * (t1 - t0) / nsteps:.3f} ms/step "
+              f"({cycles / nsteps:.1f} cycles/step), adjoint rollout "
+              f"{1e3 * (t2 - t1) / nsteps:.3f} ms/step", flush=True)
+        del s
+
+
 def fft_gravity_probe(n=512):
     """Three checkpointed steps with spectral gravity and cooling on a
     Gaussian-random-field density, then ten standalone 3D transforms."""
@@ -353,6 +468,15 @@ def main():
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="instead: time adjoint steps at 256^3 fp32 (forcing + cooling) for "
                          "the kernel profiles, one text line")
+    ap.add_argument("--stage-probe", action="store_true",
+                    help="instead: 3 steps of the 512^3 fp32 step in six configurations that "
+                         "differ by one phase (for instruction counters), one text line each")
+    ap.add_argument("--corrector-probe", action="store_true",
+                    help="instead: corrector forward passes and training steps at 4 x 64^3, "
+                         "one text line")
+    ap.add_argument("--c4-probe", action="store_true",
+                    help="instead: forward and adjoint steps of the 128^3 self-gravitating "
+                         "cooling box in fp64 and fp32, one text line each")
     ap.add_argument("--fft-gravity-probe", action="store_true",
                     help="instead: 3 steps with spectral gravity at 512^3 fp32 and 10 "
                          "standalone 3D transforms, for the kernel profiles, one text line")
@@ -366,11 +490,6 @@ def main():
 
     import paper_2512_13403_amd as mh
 
-    if args.adjoint_probe:
-        return adjoint_probe()
-    if args.fft_gravity_probe:
-        return fft_gravity_probe()
-
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
@@ -378,6 +497,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.adjoint_probe:
+        return adjoint_probe()
+    if args.fft_gravity_probe:
+        return fft_gravity_probe()
+    if args.c4_probe:
+        return c4_probe()
+    if args.stage_probe:
+        return stage_probe()
+    if args.corrector_probe:
+        return corrector_probe()
 
     n = args.n
     shape = (n, n, n)

@@ -123,7 +123,10 @@ typedef struct mh_grid_desc {
  * grav_G          gravitational constant of lap(phi) = 4 pi G (rho - <rho>).
  * mg_*            multigrid (Sec. 6.2, App. C): pre/post smoothing sweeps,
  *                 maximum cycles per step, coarsest grid size, relative
- *                 residual tolerance (0 runs exactly max_cycles cycles),
+ *                 residual tolerance (0 runs exactly max_cycles cycles; with
+ *                 a tolerance the solve also stops when a cycle cuts the
+ *                 residual by less than 10 %, its round-off floor, which in
+ *                 fp32 lies near 1e-4 of ||F|| at 128^3),
  *                 Jacobi sweeps used to solve the coarsest grid, the cycle
  *                 (MH_MG_V, or MH_MG_W: two coarse cycles per level, the
  *                 paper's default) and the smoother (MH_SMOOTH_JACOBI,

@@ -186,7 +186,7 @@ def grid_desc(shape, h, bc=(BC_PERIODIC,) * 3, dtype="f32", gamma=5.0 / 3.0, cfl
 def physics_desc(flags=0, cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, ou_arms=1.0,
                  ou_zeta=1.0, ou_kmin=1.0, ou_kmax=2.0, ou_every=1, grav_G=0.0, mg_pre=2,
                  mg_post=2, mg_max_cycles=20, mg_coarsest=4, mg_tol=1e-10,
-                 mg_coarse_sweeps=200, mg_cycle=MG_V, mg_smoother=SMOOTH_JACOBI,
+                 mg_coarse_sweeps=200, mg_cycle=MG_V, mg_smoother=SMOOTH_RBGS,
                  grav_solver=GRAV_MG, cool_model=COOL_EXACT2, cool_integrator=COOLINT_TRAPEZOID,
                  cool_nsub_max=1000, cool_frac=0.1, cool_ccool=0.0,
                  cool_ki=(0.0, 0.0, 0.0, 0.0), cool_heat=0.0, cool_table=None) -> PhysicsDesc:

@@ -337,10 +337,24 @@ extern "C" mh_status mh_corr_get_activation(mh_corr* c, int which, void* dst, in
   if (!c || !dst || which < 0 || which > 9 || (where != MH_HOST && where != MH_DEVICE))
     return MH_E_INVALID;
   const size_t cells = (size_t)c->cells();
+  if (which == 0) {
+    // the stored input holds the three x neighbours of each cell: extract the
+    // cell's own two parts
+    if (where == MH_DEVICE) {
+      MH_CHK(corr_unpack_input(c->B, (long long)cells, (unsigned short*)dst, c->stream));
+      return MH_OK;
+    }
+    std::vector<unsigned short> xp(cells * 32);
+    MH_CHK(hipMemcpyAsync(xp.data(), c->B.x0, cells * 32 * 2, hipMemcpyDeviceToHost, c->stream));
+    MH_CHK(hipStreamSynchronize(c->stream));
+    unsigned short* out = (unsigned short*)dst;
+    for (size_t q = 0; q < cells; ++q)
+      for (int k = 0; k < 32; ++k) out[q * 32 + k] = k < 10 ? xp[q * 32 + 10 + k] : 0;
+    return MH_OK;
+  }
   const void* src = nullptr;
   size_t bytes = 0;
   switch (which) {
-    case 0: src = c->B.x0; bytes = cells * 32 * 2; break;
     case 1: src = c->B.z1; bytes = cells * 32 * 4; break;
     case 2: src = c->B.h1; bytes = cells * 32 * 2; break;
     case 3: src = c->B.z2; bytes = cells * 32 * 4; break;

@@ -104,8 +104,10 @@ __device__ __forceinline__ int cslot(int h, int hx, int c) { return h * 4 + (c ^
 // out[cell][co] for COT output channels (16 or 32) from in[cell][32] (bf16):
 // per tap, the wave's CROWS rows of 16 cells read their shifted inputs from
 // the LDS tile and multiply them by the tap's 32 x COT weight block (bf16
-// [27][COT][32]), loaded once per tap and prefetched CPD taps ahead.
-template <int COT, int EPI>
+// [NT][COT][32]), loaded once per tap and prefetched CPD taps ahead.  NT = 9
+// for an input whose 32 channels already hold the three x neighbours (the
+// first layer: 3 x 10 input parts): the taps then run over (dy, dz) only.
+template <int COT, int EPI, int NT = 27>
 __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restrict__ in,
                                               const unsigned short* __restrict__ w,
                                               const float* __restrict__ bias, int nbias, int n,
@@ -188,16 +190,20 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
 #pragma unroll
       for (int nt = 0; nt < COT / 16; ++nt) bq[p][nt] = load8(wl + (p * COT + nt * 16) * 32);
 #pragma unroll
-    for (int tap = 0; tap < 27; ++tap) {
+    for (int tap = 0; tap < NT; ++tap) {
       bf16x8 bw[COT / 16];
 #pragma unroll
       for (int nt = 0; nt < COT / 16; ++nt) bw[nt] = bq[tap % CPD][nt];
-      if (tap + CPD < 27) {
+      if (tap + CPD < NT) {
 #pragma unroll
         for (int nt = 0; nt < COT / 16; ++nt)
           bq[tap % CPD][nt] = load8(wl + ((tap + CPD) * COT + nt * 16) * 32);
       }
-      const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+      // 27 taps (dx, dy, dz); 9 taps (dy, dz) when the x shifts are packed
+      // into the input channels (the first layer)
+      const int dx = NT == 27 ? tap % 3 - 1 : 0;
+      const int dy = NT == 27 ? (tap / 3) % 3 - 1 : tap % 3 - 1;
+      const int dz = NT == 27 ? tap / 9 - 1 : tap / 3 - 1;
       const int hx = row + 1 + dx;
 #pragma unroll
       for (int r = 0; r < CROWS; ++r) {
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
 // (deterministic, no atomics).
 constexpr int WROWS = 3;  // (dy, dz) rows per wave: ceil(9 / 4)
 
-template <int COT>
+template <int COT, bool XPACK = false>
 __global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restrict__ dz,
                                                const unsigned short* __restrict__ x, int n,
                                                int nblocks, float* __restrict__ partial) {
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restri
               v[m] = tile16[cslot(hrow + hx, hx, ci >> 3) * 8 + (ci & 7)];
             }
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
+            for (int d = XPACK ? 1 : 0; d < (XPACK ? 2 : 3); ++d) {
               bf16x8 bv;
               __builtin_memcpy(&bv, v + d, 16);
 #pragma unroll
@@ -387,6 +393,7 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restri
       for (int d = 0; d < 3; ++d) {
         const int tap = g < 9 ? 3 * g + d : 27;
         if (g == 11 && d > 0) continue;
+        if (XPACK && g < 9 && d != 1) continue;  // packed input: only the x shift 0
 #pragma unroll
         for (int mt = 0; mt < COT / 16; ++mt)
 #pragma unroll
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restri
 // the four sums are added in a fixed order: the result is deterministic.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int cot,
                                                       int nwg, int co_real, int ci_real,
-                                                      int fold, float* __restrict__ g,
+                                                      int fold, int xpack, float* __restrict__ g,
                                                       float* __restrict__ gb) {
   __shared__ float sp[4][64];
   const int per = 28 * cot * 32;
@@ -422,12 +429,17 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
   const bool need =
       e < per && co < co_real && (tap == 27 ? ci == 0 : ci < ci_real);
   const bool two = fold && tap < 27;
+  // xpack: the partial of (dy, dz) row g = tap / 3 sits at slot 3 g + 1, its
+  // x shift dx = tap % 3 - 1 in input-channel block 2 ci_real (dx + 1)
+  const int src = (xpack && tap < 27)
+                      ? ((3 * (tap / 3) + 1) * cot + co) * 32 + 2 * ci_real * (tap % 3) + ci
+                      : e;
   float acc = 0.f;
   if (need) {
 #pragma unroll 8
     for (int w = wv; w < nwg; w += 4) {
       const float* pw = partial + (long long)w * per;
-      acc += two ? pw[e] + pw[e + ci_real] : pw[e];
+      acc += two ? pw[src] + pw[src + ci_real] : pw[src];
     }
   }
   sp[wv][lane] = acc;
@@ -440,8 +452,11 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
 }
 
 // network input, two bf16 parts per channel: with x32 = float((U_c - mean_c) /
-// std_c), x[cell][c] = hi = bf16(x32) and x[cell][5 + c] = bf16(x32 - hi)
-// (the difference is exact in fp32); channels 10..31 are 0
+// std_c), hi = bf16(x32) and lo = bf16(x32 - hi) (the difference is exact in
+// fp32), stored for the three x neighbours of the cell: x[cell][10 (dx + 1) +
+// c] = hi and x[cell][10 (dx + 1) + 5 + c] = lo of cell x + dx (periodic),
+// channels 30, 31 zero, so the first layer's three x taps meet one 32-wide
+// operand (its K dimension) instead of three mostly zero ones
 template <typename T>
 __global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ U, int n, long long cells,
                                                      CorrStats st, unsigned short* __restrict__ x) {
@@ -449,14 +464,20 @@ __global__ __launch_bounds__(256) void k_standardize(const T* __restrict__ U, in
   if (cell >= cells) return;
   const long long n3 = (long long)n * n * n;
   const long long b = cell / n3, q = cell % n3;
+  const int ix = (int)(q % n);
+  const long long row = q - ix;
   unsigned short v[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) v[c] = 0;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    const float s = (float)(((double)U[(b * 5 + c) * n3 + q] - st.mean[c]) / st.std[c]);
-    v[c] = f2bf(s);
-    v[5 + c] = f2bf(s - bf2f(v[c]));
+  for (int d = 0; d < 3; ++d) {
+    const int xs = ix + d - 1 < 0 ? n - 1 : (ix + d - 1 >= n ? 0 : ix + d - 1);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const float s = (float)(((double)U[(b * 5 + c) * n3 + row + xs] - st.mean[c]) / st.std[c]);
+      v[10 * d + c] = f2bf(s);
+      v[10 * d + 5 + c] = f2bf(s - bf2f(v[10 * d + c]));
+    }
   }
 #pragma unroll
   for (int c = 0; c < 32; c += 8) __builtin_memcpy(x + cell * 32 + c, v + c, 16);
@@ -655,6 +676,20 @@ __global__ __launch_bounds__(256) void k_loss(const T* __restrict__ U, const flo
   if (threadIdx.x == 0) part[blockIdx.x] = sl[0];
 }
 
+// the cell's own two parts (channels 10..19 of the x-packed input) in the
+// unpacked layout [cell][32]: hi at c, lo at 5 + c, zeros after
+__global__ __launch_bounds__(256) void k_unpack_input(const unsigned short* __restrict__ xp,
+                                                      long long cells,
+                                                      unsigned short* __restrict__ x0) {
+  const long long cell = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= cells) return;
+  unsigned short v[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) v[c] = c < 10 ? xp[cell * 32 + 10 + c] : 0;
+#pragma unroll
+  for (int c = 0; c < 32; c += 8) __builtin_memcpy(x0 + cell * 32 + c, v + c, 16);
+}
+
 // dL/dU += gx_c / std_c (gU holds the upstream gradient of U', the residual
 // path; gx: [cell][16] fp32, the first layer's transposed convolution of dZ1;
 // the two-part input split and the positivity floor pass the gradient
@@ -715,6 +750,19 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ th, float* __r
   th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// first layer with the x taps packed into K: w1p[g][co][k], g = 3 (dz + 1) +
+// (dy + 1), k = 10 (dx + 1) + j: W1[co][j mod 5][tap(dx, dy, dz)] for j < 10
+// (both input parts share the weights), zero for k >= 30
+__global__ __launch_bounds__(256) void k_pack_w1(const float* __restrict__ th, int off,
+                                                 unsigned short* __restrict__ wf) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= 9 * 32 * 32) return;
+  const int g = i / 1024, co = (i / 32) % 32, k = i % 32;
+  float val = 0.f;
+  if (k < 30) val = th[off + (co * 5 + (k % 10) % 5) * 27 + 3 * g + k / 10];
+  wf[i] = f2bf(val);
+}
+
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ th, int off, int co_real,
                                               int ci_real, int dup, int cot,
                                               unsigned short* __restrict__ wf, int cit_t,
@@ -729,7 +777,7 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ th, int 
   float val = 0.f;
   if (co < co_real && cs < ci_real) val = th[off + (co * ci_real + cs) * 27 + tap];
   const unsigned short h = f2bf(val);
-  wf[i] = h;
+  if (wf) wf[i] = h;
   if (wt && ci < cit_t) wt[((long long)(26 - tap) * cit_t + ci) * 32 + co] = h;
 }
 
@@ -768,7 +816,9 @@ inline unsigned conv_wgs(unsigned ntiles) { return ntiles < 768u ? ntiles : 768u
 
 hipError_t corr_pack_weights(const CorrBuffers& B, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
-                     CORR_OFF_W1, 32, 5, 1, 32, B.w1, 16, B.w1t);
+                     CORR_OFF_W1, 32, 5, 1, 32, (unsigned short*)nullptr, 16, B.w1t);
+  hipLaunchKernelGGL(k_pack_w1, dim3(blocks(9 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
+                     CORR_OFF_W1, B.w1);
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 32 * 32, 256)), dim3(256), 0, s, B.theta,
                      CORR_OFF_W2, 32, 32, 0, 32, B.w2, 32, B.w2t);
   hipLaunchKernelGGL(k_pack, dim3(blocks(27 * 16 * 32, 256)), dim3(256), 0, s, B.theta,
@@ -783,7 +833,7 @@ hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int ba
   const unsigned conv_blocks = conv_grid(n, batch);
   hipLaunchKernelGGL((k_standardize<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, n, cells, st,
                      B.x0);
-  hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.x0, B.w1,
+  hipLaunchKernelGGL((k_conv<32, EPI_GELU, 9>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.x0, B.w1,
                      B.theta + CORR_OFF_B1, 32, n, (const float*)nullptr,
                      store_z ? B.z1 : (float*)nullptr, B.h1, (int)conv_blocks);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.h1, B.w2,
@@ -831,25 +881,32 @@ hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int b
   // layer 3: dW3, db3; dH2 -> dZ2 = dH2 * GELU'(Z2)
   hipLaunchKernelGGL((k_wgrad<16>), dim3(nwg), dim3(256), 0, s, B.dy16, B.h2, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 16 * 32, 64)), dim3(256), 0, s, B.wpart,
-                     16, nwg, 5, 32, 0, B.grad + CORR_OFF_W3, B.grad + CORR_OFF_B3);
+                     16, nwg, 5, 32, 0, 0, B.grad + CORR_OFF_W3, B.grad + CORR_OFF_B3);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dy32, B.w3t,
                      (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2, (int)conv_blocks);
   // layer 2
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz2, B.h1, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 32 * 32, 64)), dim3(256), 0, s,
-                     B.wpart, 32, nwg, 32, 32, 0, B.grad + CORR_OFF_W2, B.grad + CORR_OFF_B2);
+                     B.wpart, 32, nwg, 32, 32, 0, 0, B.grad + CORR_OFF_W2, B.grad + CORR_OFF_B2);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz2, B.w2t,
                      (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1, (int)conv_blocks);
   // layer 1
-  hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk, B.wpart);
+  hipLaunchKernelGGL((k_wgrad<32, true>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk,
+                     B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 32 * 32, 64)), dim3(256), 0, s,
-                     B.wpart, 32, nwg, 32, 5, 1, B.grad + CORR_OFF_W1, B.grad + CORR_OFF_B1);
+                     B.wpart, 32, nwg, 32, 5, 1, 1, B.grad + CORR_OFF_W1, B.grad + CORR_OFF_B1);
   if (gU) {
     hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz1, B.w1t,
                        (const float*)nullptr, 0, n, (const float*)nullptr, B.gx,
                        (unsigned short*)nullptr, (int)conv_blocks);
     hipLaunchKernelGGL((k_input_grad<T>), dim3(lb), dim3(256), 0, s, B.gx, n, cells, st, gU);
   }
+  return hipGetLastError();
+}
+
+hipError_t corr_unpack_input(const CorrBuffers& B, long long cells, unsigned short* x0,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_input, dim3(blocks(cells, 256)), dim3(256), 0, s, B.x0, cells, x0);
   return hipGetLastError();
 }
 

@@ -13,6 +13,9 @@ namespace mh {
 constexpr int MG_MAX_LEVELS = 16;
 constexpr int MG_PARTIALS = 1024;       // blocks of the two-stage reductions
 constexpr int MG_COARSE_MAX_CELLS = 2048;
+// a cycle that leaves more than this fraction of the residual has stalled at
+// the round-off floor (the V- and W-cycles cut it by 0.07-0.3 otherwise)
+constexpr double MG_STALL = 0.9;
 
 struct MGLevel {
   int n;

@@ -809,6 +809,7 @@ hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* c
   MG_CHECK(sum_to(P<T>(ws, f.F), N, true, partial, 1.0, &clk->mg_fnorm2, s));
   MG_CHECK(remove_mean(P<T>(ws, f.phi[L.cur0]), N, partial, &clk->mean, s));
   int cycles = 0;
+  double prev = INFINITY;
   for (;;) {
     hipLaunchKernelGGL((k_residual<T>), dim3(nblk(N)), dim3(256), 0, s, n, (T)(1.0 / (f.h * f.h)),
                        P<T>(ws, f.phi[L.cur0]), P<T>(ws, f.F), P<T>(ws, f.r));
@@ -816,7 +817,13 @@ hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* c
     double norms[2];
     MG_CHECK(hipMemcpyAsync(norms, &clk->mg_fnorm2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     MG_CHECK(hipStreamSynchronize(s));
-    if (std::sqrt(norms[1]) <= p.mg_tol * std::sqrt(norms[0]) || cycles >= p.mg_max_cycles) break;
+    const double rn = std::sqrt(norms[1]);
+    if (rn <= p.mg_tol * std::sqrt(norms[0]) || cycles >= p.mg_max_cycles) break;
+    // with a tolerance, a cycle that no longer cuts the residual by MG_STALL
+    // has reached the round-off floor of the precision (in fp32 it lies above
+    // the usual tolerances): stop there rather than run to the cycle cap
+    if (p.mg_tol > 0.0 && rn > MG_STALL * prev) break;
+    prev = rn;
     MG_CHECK(run_vcycle<T>(ws, L, p, partial, &clk->mean, s));
     MG_CHECK(remove_mean(P<T>(ws, f.phi[L.cur0]), N, partial, &clk->mean, s));
     ++cycles;

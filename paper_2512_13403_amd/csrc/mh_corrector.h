@@ -49,6 +49,10 @@ template <typename T>
 hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int batch, const T* U,
                          const T* tgt, const T* gup, T* gU, bool ident, hipStream_t s);
 hipError_t corr_zero_grad(const CorrBuffers& B, hipStream_t s);
+// the network input in the unpacked layout [cells][32] (hi parts at 0..4, lo
+// parts at 5..9) from the x-packed one the first layer reads
+hipError_t corr_unpack_input(const CorrBuffers& B, long long cells, unsigned short* x0,
+                             hipStream_t s);
 hipError_t corr_adam(const CorrBuffers& B, int it, float lr, hipStream_t s);
 template <typename T>
 hipError_t launch_block_average(const T* fine, int nf, int r, T* coarse, hipStream_t s);

@@ -19,7 +19,9 @@ PHYS_KEYS = ("cool", "ou_seed", "ou_tau", "ou_arms", "ou_zeta", "ou_kmin", "ou_k
 
 def pair(shape, h, bc=(0, 0, 0), dtype="f64", gamma=5.0 / 3.0, cfl=0.4, limiter=0, flags=0,
          riemann=0, integrator=0, **phys):
-    """(Solver, oracle Config) for the same grid, scheme and physics."""
+    """(Solver, oracle Config) for the same grid, scheme and physics (the
+    binding's default smoother, red-black Gauss-Seidel, on both sides)."""
+    phys.setdefault("mg_smoother", mh.SMOOTH_RBGS)
     g = mh.grid_desc(shape, h, bc, dtype, gamma, cfl, limiter, riemann, integrator)
     p = mh.physics_desc(flags=flags, **phys)
     oc = oracle.make_config(shape, h, bc, gamma=gamma, cfl=cfl, limiter=limiter, riemann=riemann,

@@ -347,7 +347,7 @@ def test_gravity_fixed_cycles(dtype, cool):
     assert np.abs(phi - sim.phi).max() < 10 * TOL[dtype] * np.abs(sim.phi).max()
 
 
-MG_VARIANTS = [(oracle.MG_W, oracle.SMOOTH_JACOBI), (oracle.MG_V, oracle.SMOOTH_RBGS),
+MG_VARIANTS = [(oracle.MG_W, oracle.SMOOTH_JACOBI), (oracle.MG_V, oracle.SMOOTH_JACOBI),
                (oracle.MG_W, oracle.SMOOTH_RBGS)]
 
 
