@@ -660,6 +660,201 @@ __global__ __launch_bounds__(256) void k_cell_gather(const T* __restrict__ wbar,
   }
 }
 
+// J(U)^T v along axis AX = 1 or 2 for periodic boundaries (n >= 4) and the
+// minmod (or first-order) HLLC scheme, face reverse and gather fused: one
+// thread per (x, other) column and segment of `seg` cells along the axis
+// marches the faces c0 - 2 .. c1 in order, reverses each with the arithmetic
+// of k_face_vjp and adds its four stencil contributions (slot_contrib) to a
+// ring of four cell accumulators.  Once face f is done, cell f - 1 has all of
+// its faces (f - 3 .. f, the order in which k_cell_gather sums them, so the
+// result is bitwise the same) and leaves the ring: stored, added to or
+// finished as in k_cell_gather's MODE.  Lanes take consecutive x, so every
+// load and store of a wave is contiguous, and the face records never leave
+// registers (the two-kernel path writes and reads 44 B per face).
+template <typename T, int LIM, int AX, int MODE>
+__global__ __launch_bounds__(256) void k_axis_jtv(const T* __restrict__ U, const T* __restrict__ v,
+                                                  AxisGeom g, T gamma, T ih, int seg,
+                                                  T* __restrict__ Wacc, FinishArgs<T> fa) {
+  static_assert(AX == 1 || AX == 2, "columns along y or z");
+  int d1, d2;
+  other_dims<AX>(g, d1, d2);
+  const int n = g.n[AX];
+  const int nseg = (n + seg - 1) / seg;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)d1 * d2 * nseg) return;
+  const int o1 = (int)(t % d1);
+  const long long r = t / d1;
+  const int o2 = (int)(r % d2), sg = (int)(r / d2);
+  const int c0 = sg * seg, c1 = min(c0 + seg, n);
+  const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+  const T gm1 = gamma - T(1);
+  constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
+  const int perm[5] = {0, vn, t1, t2, 4};
+  auto wrapc = [&](int c) { return c < 0 ? c + n : (c >= n ? c - n : c); };
+  auto load_w = [&](int c, T (&out)[5]) {
+    T wc[5];
+    prim_at(U, N, cell_of<AX>(g, wrapc(c), o1, o2), gm1, wc);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) out[s] = wc[perm[s]];
+  };
+  auto load_v = [&](int c, T (&out)[5]) {
+    const long long q = cell_of<AX>(g, wrapc(c), o1, o2);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) out[s] = v[perm[s] * N + q];
+  };
+  // stencil of face f: cells f - 1 .. f + 2; v of its left and right cells
+  T w[4][5], vl[5], vr[5];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) load_w(c0 - 3 + k, w[k]);
+  load_v(c0 - 2, vl);
+  load_v(c0 - 1, vr);
+  // accumulators of cells f - 1 .. f + 2
+  T acc[4][5];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int s = 0; s < 5; ++s) acc[k][s] = T(0);
+  for (int f = c0 - 2; f <= c1; ++f) {
+    T wl[5], wr[5];
+    int fl = 0;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      const T a0 = w[2][s] - w[1][s], b0 = w[1][s] - w[0][s];
+      const T a1 = w[3][s] - w[2][s], b1 = w[2][s] - w[1][s];
+      const int s0 = LIM == LIM_NONE ? 0 : minmod_sel(a0, b0);
+      const int s1 = LIM == LIM_NONE ? 0 : minmod_sel(a1, b1);
+      wl[s] = w[1][s] + T(0.5) * sel_value(s0, a0, b0);
+      wr[s] = w[2][s] - T(0.5) * sel_value(s1, a1, b1);
+      fl |= (s0 << (2 * s)) | (s1 << (10 + 2 * s));
+    }
+    T Fb[5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) Fb[s] = (vr[s] - vl[s]) * ih;
+    T wlb[5], wrb[5];
+    hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int s = 0; s < 5; ++s) acc[k][s] += slot_contrib<T>(k, fl, s, wlb[s], wrb[s]);
+    // cell f - 1 is complete
+    if (f - 1 >= c0) {
+      const long long q = cell_of<AX>(g, f - 1, o1, o2);
+      if (MODE == GATHER_ADD) {
+#pragma unroll
+        for (int s = 0; s < 5; ++s) Wacc[perm[s] * N + q] += acc[0][s];
+      } else if (MODE == GATHER_FIRST) {
+#pragma unroll
+        for (int s = 0; s < 5; ++s) Wacc[perm[s] * N + q] = acc[0][s];
+      } else {
+        T wc[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s)
+          wc[perm[s]] = MODE == GATHER_LAST ? Wacc[perm[s] * N + q] + acc[0][s] : acc[0][s];
+        finish_cell(U, wc, q, N, fa);
+      }
+    }
+    if (f == c1) break;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      acc[0][s] = acc[1][s];
+      acc[1][s] = acc[2][s];
+      acc[2][s] = acc[3][s];
+      acc[3][s] = T(0);
+      w[0][s] = w[1][s];
+      w[1][s] = w[2][s];
+      w[2][s] = w[3][s];
+      vl[s] = vr[s];
+    }
+    load_w(f + 3, w[3]);
+    load_v(f + 2, vr);
+  }
+}
+
+// J(U)^T v along x for periodic boundaries (nx >= 4) and the minmod (or
+// first-order) HLLC scheme, face reverse and gather fused: each wave takes a
+// segment of XSEG = 61 cells of one x row; lane L reverses the face between
+// cells x0 - 2 + L and x0 - 1 + L (the arithmetic of k_face_vjp) and puts its
+// four stencil contributions (slot_contrib) in LDS, and lane L = 2 .. 62
+// sums, for cell x0 + L - 2, the contributions of the faces on lanes L - 2 ..
+// L + 1 in that order (the order of k_cell_gather: bitwise the same result)
+// and stores, adds or finishes it as in k_cell_gather's MODE.  Three faces in
+// 64 are computed twice (by two segments); the face records stay in LDS.
+constexpr int XSEG = 61;
+
+template <typename T, int LIM, int MODE>
+__global__ __launch_bounds__(256) void k_x_jtv(const T* __restrict__ U, const T* __restrict__ v,
+                                               AxisGeom g, T gamma, T ih, T* __restrict__ Wacc,
+                                               FinishArgs<T> fa) {
+  __shared__ T sc[4][20][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = g.n[0];
+  const int nseg = (n + XSEG - 1) / XSEG;
+  const long long wave = (long long)blockIdx.x * 4 + wv;
+  const long long nrows = (long long)g.n[1] * g.n[2];
+  const bool active = wave < nrows * nseg;
+  const int sg = (int)(wave % nseg);
+  const long long row = active ? wave / nseg : 0;
+  const int o1 = (int)(row % g.n[1]), o2 = (int)(row / g.n[1]);
+  const int x0 = sg * XSEG;
+  const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+  const T gm1 = gamma - T(1);
+  auto wrapc = [&](int c) {
+    c %= n;
+    return c < 0 ? c + n : c;
+  };
+  if (active) {
+    const int f = x0 - 2 + lane;  // the face between cells f and f + 1
+    T w[4][5];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      prim_at(U, N, cell_of<0>(g, wrapc(f - 1 + k), o1, o2), gm1, w[k]);
+    T wl[5], wr[5];
+    int fl = 0;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      const T a0 = w[2][s] - w[1][s], b0 = w[1][s] - w[0][s];
+      const T a1 = w[3][s] - w[2][s], b1 = w[2][s] - w[1][s];
+      const int s0 = LIM == LIM_NONE ? 0 : minmod_sel(a0, b0);
+      const int s1 = LIM == LIM_NONE ? 0 : minmod_sel(a1, b1);
+      wl[s] = w[1][s] + T(0.5) * sel_value(s0, a0, b0);
+      wr[s] = w[2][s] - T(0.5) * sel_value(s1, a1, b1);
+      fl |= (s0 << (2 * s)) | (s1 << (10 + 2 * s));
+    }
+    const long long ql = cell_of<0>(g, wrapc(f), o1, o2);
+    const long long qr = cell_of<0>(g, wrapc(f + 1), o1, o2);
+    T Fb[5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) Fb[s] = (v[s * N + qr] - v[s * N + ql]) * ih;
+    T wlb[5], wrb[5];
+    hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int s = 0; s < 5; ++s) sc[wv][5 * k + s][lane] = slot_contrib<T>(k, fl, s, wlb[s], wrb[s]);
+  }
+  __syncthreads();
+  const int c = x0 + lane - 2;
+  if (!active || lane < 2 || lane > 62 || c >= n) return;
+  T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int s = 0; s < 5; ++s) acc[s] += sc[wv][5 * (3 - m) + s][lane - 2 + m];
+  const long long q = cell_of<0>(g, c, o1, o2);
+  if (MODE == GATHER_ADD) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s) Wacc[s * N + q] += acc[s];
+  } else if (MODE == GATHER_FIRST) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s) Wacc[s * N + q] = acc[s];
+  } else {
+    T wc[5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) wc[s] = MODE == GATHER_LAST ? Wacc[s * N + q] + acc[s] : acc[s];
+    finish_cell(U, wc, q, N, fa);
+  }
+}
+
 // out = c0 x0 + c1 x1 + c2 x2 + beta (dW/dU)^T Wacc, W = (rho, v, P) of U
 template <typename T>
 __global__ __launch_bounds__(256) void k_jtv_finish(const T* __restrict__ U,
@@ -894,6 +1089,9 @@ inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 // J(U)^T v into out = c0 x0 + c1 x1 + beta J^T v (x0, x1 may be NULL)
+// cells per column segment of the fused march (k_axis_jtv)
+constexpr int ADJ_SEG = 64;
+
 template <typename T>
 hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limiter, int riemann,
                    T gamma,
@@ -953,7 +1151,57 @@ hipError_t adj_jtv(const AdjointBuffers<T>& B, const StageGeom& geom, int limite
       MH_GATHER(AX, false);                                                                   \
     }                                                                                         \
   } while (0)
-    if (ax == 0) MH_FACE(0);
+    // y and z, periodic with at least four cells, minmod or first order:
+    // the fused column march
+    const bool march = !rt && geom.bc[ax] == BC_PERIODIC && nn[ax] >= 4;
+    if (march && ax == 0) {
+      const long long waves = (N / nn[0]) * ((nn[0] + XSEG - 1) / XSEG);
+      const unsigned blocks = (unsigned)((waves + 3) / 4);
+#define MH_XJTV(LM)                                                                           \
+  do {                                                                                        \
+    if (mode == GATHER_ADD)                                                                   \
+      hipLaunchKernelGGL((k_x_jtv<T, LM, GATHER_ADD>), dim3(blocks), dim3(256), 0, s, U, v,  \
+                         ag, gamma, ih, B.Wacc, fa);                                          \
+    else if (mode == GATHER_FIRST)                                                            \
+      hipLaunchKernelGGL((k_x_jtv<T, LM, GATHER_FIRST>), dim3(blocks), dim3(256), 0, s, U, v, \
+                         ag, gamma, ih, B.Wacc, fa);                                          \
+    else if (mode == GATHER_LAST)                                                             \
+      hipLaunchKernelGGL((k_x_jtv<T, LM, GATHER_LAST>), dim3(blocks), dim3(256), 0, s, U, v,  \
+                         ag, gamma, ih, B.Wacc, fa);                                          \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_x_jtv<T, LM, GATHER_FIRST_LAST>), dim3(blocks), dim3(256), 0, s,  \
+                         U, v, ag, gamma, ih, B.Wacc, fa);                                    \
+  } while (0)
+      if (limiter == LIM_NONE) MH_XJTV(LIM_NONE);
+      else MH_XJTV(LIM_MINMOD);
+#undef MH_XJTV
+    } else if (march) {
+      const int seg = nn[ax] < ADJ_SEG ? nn[ax] : ADJ_SEG;
+      const long long threads = (N / nn[ax]) * ((nn[ax] + seg - 1) / seg);
+#define MH_MARCH(AX, LM)                                                                      \
+  do {                                                                                        \
+    if (mode == GATHER_ADD)                                                                   \
+      hipLaunchKernelGGL((k_axis_jtv<T, LM, AX, GATHER_ADD>), dim3(nblk(threads)), dim3(256), \
+                         0, s, U, v, ag, gamma, ih, seg, B.Wacc, fa);                         \
+    else if (mode == GATHER_FIRST)                                                            \
+      hipLaunchKernelGGL((k_axis_jtv<T, LM, AX, GATHER_FIRST>), dim3(nblk(threads)),          \
+                         dim3(256), 0, s, U, v, ag, gamma, ih, seg, B.Wacc, fa);              \
+    else if (mode == GATHER_LAST)                                                             \
+      hipLaunchKernelGGL((k_axis_jtv<T, LM, AX, GATHER_LAST>), dim3(nblk(threads)),           \
+                         dim3(256), 0, s, U, v, ag, gamma, ih, seg, B.Wacc, fa);              \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_axis_jtv<T, LM, AX, GATHER_FIRST_LAST>), dim3(nblk(threads)),     \
+                         dim3(256), 0, s, U, v, ag, gamma, ih, seg, B.Wacc, fa);              \
+  } while (0)
+      if (ax == 1) {
+        if (limiter == LIM_NONE) MH_MARCH(1, LIM_NONE);
+        else MH_MARCH(1, LIM_MINMOD);
+      } else {
+        if (limiter == LIM_NONE) MH_MARCH(2, LIM_NONE);
+        else MH_MARCH(2, LIM_MINMOD);
+      }
+#undef MH_MARCH
+    } else if (ax == 0) MH_FACE(0);
     else if (ax == 1) MH_FACE(1);
     else MH_FACE(2);
 #undef MH_FACE

@@ -570,32 +570,41 @@ extern "C" mh_status mh_step(mh_ctx* c, int32_t nsteps, double dt, double t_stop
 
 // ------------------------------------------------- batched corrected steps
 
-// One corrected step of the B contexts, enqueued on their common stream:
-// each context's plain step, the gather of the B states into `in`, the
-// corrector's batched pass into `out`, the scatter back, and (CFL steps) the
-// signal speed of the corrected states for the next step's dt.
+// One corrected step of the B contexts: each context's plain step, the
+// gather of the B states into `in`, the corrector's batched pass into `out`,
+// the scatter back, and (CFL steps) the signal speed of the corrected states
+// for the next step's dt.  The corrector part runs on `main`; with `fork`
+// events (a captured step) the plain steps run on the contexts' own streams
+// as parallel branches (fork[0] ends the previous work on `main`, fork[1 + b]
+// ends context b's step), otherwise on `main` in turn.
 template <typename T>
 static mh_status corrected_step(mh_ctx* const* ctxs, int B, mh_corr* corr, T* in, T* out,
-                                const double* dts) {
+                                const double* dts, hipStream_t main, const hipEvent_t* fork) {
   const size_t bytes = 5 * (size_t)ctxs[0]->cells() * sizeof(T);
+  if (fork) MH_HIP(ctxs[0], hipEventRecord(fork[0], main));
   for (int b = 0; b < B; ++b) {
+    if (fork) MH_HIP(ctxs[b], hipStreamWaitEvent(ctxs[b]->stream, fork[0], 0));
     mh_status st = step_impl<T>(ctxs[b], 1, 0.0, INFINITY, nullptr, dts ? dts + b : nullptr, B);
     if (st != MH_OK) return st;
+    if (fork) {
+      MH_HIP(ctxs[b], hipEventRecord(fork[1 + b], ctxs[b]->stream));
+      MH_HIP(ctxs[0], hipStreamWaitEvent(main, fork[1 + b], 0));
+    }
   }
   for (int b = 0; b < B; ++b)
     MH_HIP(ctxs[0], launch_copy(ctxs[b]->ws + ctxs[b]->L.U, in + (size_t)b * bytes / sizeof(T),
-                                bytes, ctxs[0]->stream));
-  MH_HIP(ctxs[0], corr_apply_enqueue(corr, in, out, ctxs[0]->stream));
+                                bytes, main));
+  MH_HIP(ctxs[0], corr_apply_enqueue(corr, in, out, main));
   for (int b = 0; b < B; ++b)
     MH_HIP(ctxs[0], launch_copy(out + (size_t)b * bytes / sizeof(T), ctxs[b]->ws + ctxs[b]->L.U,
-                                bytes, ctxs[0]->stream));
+                                bytes, main));
   if (!dts) {
     for (int b = 0; b < B; ++b) {
       mh_ctx* c = ctxs[b];
       const mh_grid_desc& g = c->g;
       StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
       const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
-      MH_HIP(c, launch_smax<T>(c->at<T>(c->L.U), geom, (T)g.gamma, ih, c->clk(), c->stream));
+      MH_HIP(c, launch_smax<T>(c->at<T>(c->L.U), geom, (T)g.gamma, ih, c->clk(), main));
     }
   }
   return MH_OK;
@@ -623,37 +632,47 @@ static mh_status step_corrected_impl(mh_ctx* const* ctxs, int B, mh_corr* corr, 
   }
   if (!graph || nsteps == 0) {
     for (int s = 0; s < nsteps; ++s) {
-      mh_status st = corrected_step<T>(ctxs, B, corr, in, out, dts);
+      mh_status st = corrected_step<T>(ctxs, B, corr, in, out, dts, c0->stream, nullptr);
       if (st != MH_OK) return st;
     }
     return MH_OK;
   }
   // One corrected step captured into a graph (kernel nodes only) and replayed
-  // on the contexts' stream.  The capture records on a stream of its own (the
-  // contexts' stream may be the null stream, which cannot capture); nothing
-  // runs during the capture.
-  hipStream_t cs = nullptr;
-  MH_HIP(c0, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  // on the contexts' stream.  The capture records on streams of its own (the
+  // contexts' stream may be the null stream, which cannot capture): the B
+  // plain steps on B branch streams, joined before the corrector, so that the
+  // graph runs them concurrently (one 64^3 step fills a small part of the
+  // GPU).  Nothing runs during the capture.
   const hipStream_t user = c0->stream;
+  std::vector<hipStream_t> bs(B + 1, nullptr);
+  std::vector<hipEvent_t> ev(B + 1, nullptr);
+  hipError_t ec = hipSuccess;
+  for (int b = 0; b <= B && ec == hipSuccess; ++b) {
+    ec = hipStreamCreateWithFlags(&bs[b], hipStreamNonBlocking);
+    if (ec == hipSuccess) ec = hipEventCreateWithFlags(&ev[b], hipEventDisableTiming);
+  }
   std::vector<int> timing(B);
   for (int b = 0; b < B; ++b) {
     timing[b] = ctxs[b]->timing;
     ctxs[b]->timing = false;
-    ctxs[b]->stream = cs;
+    ctxs[b]->stream = bs[1 + b];
   }
   hipGraph_t gr = nullptr;
   hipGraphExec_t ex = nullptr;
-  hipError_t ec = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   mh_status st = MH_OK;
+  if (ec == hipSuccess) ec = hipStreamBeginCapture(bs[0], hipStreamCaptureModeThreadLocal);
   if (ec == hipSuccess) {
-    st = corrected_step<T>(ctxs, B, corr, in, out, dts);
-    ec = hipStreamEndCapture(cs, &gr);
+    st = corrected_step<T>(ctxs, B, corr, in, out, dts, bs[0], ev.data());
+    ec = hipStreamEndCapture(bs[0], &gr);
   }
   for (int b = 0; b < B; ++b) {
     ctxs[b]->timing = timing[b];
     ctxs[b]->stream = user;
   }
-  (void)hipStreamDestroy(cs);
+  for (int b = 0; b <= B; ++b) {
+    if (ev[b]) (void)hipEventDestroy(ev[b]);
+    if (bs[b]) (void)hipStreamDestroy(bs[b]);
+  }
   if (st != MH_OK) {
     if (gr) (void)hipGraphDestroy(gr);
     return st;
