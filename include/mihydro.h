@@ -387,6 +387,17 @@ mh_status mh_step_corrected(mh_ctx *const *ctxs, int32_t B, mh_corr *corr, void 
                             int32_t nsteps, const double *dts, int32_t use_graph,
                             int64_t *fallbacks);
 
+/* One ADAM update (Kingma & Ba 2015; the optimiser of the paper's
+ * reconstructions, Sec. 7) of `count` parameters in place, on device arrays
+ * of dtype: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * theta -= lr (m / (1 - b1^it)) / (sqrt(v / (1 - b2^it)) + eps), with it >= 1
+ * the iteration number.  The caller owns theta, m, v (zero before the first
+ * iteration) and grad.  Enqueued on `stream`.  Errors: MH_E_INVALID (null
+ * pointer, count < 0, it < 1, lr < 0, betas outside [0, 1), eps <= 0),
+ * MH_E_DTYPE, MH_E_DEVICE. */
+mh_status mh_adam(void *theta, void *m, void *v, const void *grad, int64_t count, int32_t dtype,
+                  int64_t it, double lr, double beta1, double beta2, double eps, void *stream);
+
 /* Conservative r^3 block average of a fine state [5][nf^3] onto
  * [5][(nf/r)^3] (targets of the corrector from a fine run); device arrays of
  * dtype, enqueued on `stream`. */

@@ -45,7 +45,7 @@ EXPORTED = [
     "mh_corr_apply", "mh_corr_loss_grad", "mh_corr_train_step", "mh_corr_get_activation",
     "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
     "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs", "mh_fft3_query_workspace",
-    "mh_fft3", "mh_set_flux_correction", "mh_fft3_noalloc", "mh_step_corrected",
+    "mh_fft3", "mh_set_flux_correction", "mh_fft3_noalloc", "mh_step_corrected", "mh_adam",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -153,6 +153,8 @@ def load_library():
             "mh_fft3_noalloc": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp],
             "mh_step_corrected": [ctypes.POINTER(vp), ctypes.c_int32, vp, vp, ctypes.c_int32,
                                   vp, ctypes.c_int32, i64p],
+            "mh_adam": [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -679,6 +681,41 @@ def step_corrected(solvers, corrector, nsteps: int, dts=None, use_graph: bool = 
     if st != OK:
         raise MHError(st, f"mh_step_corrected: {lib.mh_last_error(solvers[0].ctx).decode()}")
     return fb.value if count_fallbacks else None
+
+
+class Adam:
+    """ADAM on one CUDA tensor (float32 or float64) through mh_adam: the
+    moments live in tensors of the same shape, the update runs in the
+    library.  step(grad) applies one iteration to the parameter in place."""
+
+    def __init__(self, param, lr: float, betas=(0.9, 0.999), eps: float = 1e-8):
+        import torch
+
+        if not (param.is_cuda and param.is_contiguous()
+                and param.dtype in (torch.float32, torch.float64)):
+            raise ValueError("Adam needs a contiguous CUDA float32/float64 tensor")
+        self.param, self.lr, self.betas, self.eps = param, lr, betas, eps
+        self.m = torch.zeros_like(param)
+        self.v = torch.zeros_like(param)
+        self.it = 0
+        self.lib = load_library()
+
+    def step(self, grad):
+        import torch
+
+        g = grad.detach().to(self.param.dtype).contiguous()
+        self.it += 1
+        self._keep = g
+        dt = F64 if self.param.dtype == torch.float64 else F32
+        st = self.lib.mh_adam(ctypes.c_void_p(self.param.data_ptr()),
+                              ctypes.c_void_p(self.m.data_ptr()),
+                              ctypes.c_void_p(self.v.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                              self.param.numel(), dt, self.it, self.lr, self.betas[0],
+                              self.betas[1], self.eps,
+                              ctypes.c_void_p(torch.cuda.current_stream(self.param.device)
+                                              .cuda_stream))
+        if st != OK:
+            raise MHError(st, "mh_adam")
 
 
 def fft3_noalloc(x, inverse: bool = False):

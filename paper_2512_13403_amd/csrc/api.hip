@@ -725,6 +725,25 @@ extern "C" mh_status mh_step_corrected(mh_ctx* const* ctxs, int32_t B, mh_corr* 
   return MH_OK;
 }
 
+extern "C" mh_status mh_adam(void* theta, void* m, void* v, const void* grad, int64_t count,
+                             int32_t dtype, int64_t it, double lr, double beta1, double beta2,
+                             double eps, void* stream) {
+  if (!theta || !m || !v || !grad || count < 0 || it < 1 || !(lr >= 0.0) ||
+      !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+    return MH_E_INVALID;
+  if (count == 0) return MH_OK;
+  hipError_t e;
+  if (dtype == MH_F64)
+    e = launch_adam<double>((double*)theta, (double*)m, (double*)v, (const double*)grad, count,
+                            lr, beta1, beta2, eps, it, (hipStream_t)stream);
+  else if (dtype == MH_F32)
+    e = launch_adam<float>((float*)theta, (float*)m, (float*)v, (const float*)grad, count, lr,
+                           beta1, beta2, eps, it, (hipStream_t)stream);
+  else
+    return MH_E_DTYPE;
+  return e == hipSuccess ? MH_OK : MH_E_DEVICE;
+}
+
 extern "C" mh_status mh_get_clock(mh_ctx* c, double* t, int64_t* step) {
   if (!c) return MH_E_INVALID;
   DevClock hc;

@@ -177,12 +177,19 @@ __device__ __forceinline__ void stockham_pass(C* buf, const C* __restrict__ stw,
 // the lines in flight at once; the store to the cube is batched the same way.
 // IO selects the ends of a 3D transform: 0 in place on `data`; FFT_REAL_IN
 // reads the real field `rin` (imaginary part 0) and writes `data`;
-// FFT_REAL_OUT reads `data` and writes only the real part, to `rout`.
-enum : int { FFT_COMPLEX = 0, FFT_REAL_IN = 1, FFT_REAL_OUT = 2 };
+// FFT_REAL_OUT reads `data` and writes only the real part, to `rout`;
+// FFT_SPLIT_OUT writes the real part to `rout` and the imaginary part to
+// `rout2` (the inverse transform of two Hermitian spectra packed as A + i B
+// gives the two real fields a + i b); FFT_PAIR_IN reads `rin` + i `rin2` (the
+// transform of two real fields at once, separated by Hermitian symmetry).
+enum : int { FFT_COMPLEX = 0, FFT_REAL_IN = 1, FFT_REAL_OUT = 2, FFT_SPLIT_OUT = 3,
+             FFT_PAIR_IN = 4 };
 template <typename T, int AXIS, int IO>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::type* data,
                                                            const T* __restrict__ rin,
+                                                           const T* __restrict__ rin2,
                                                            T* __restrict__ rout,
+                                                           T* __restrict__ rout2,
                                                            const typename CplxOf<T>::type* tw,
                                                            int logn, int loglpb, int inverse) {
   using C = typename CplxOf<T>::type;
@@ -206,6 +213,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::t
     if (e < E) {
       const unsigned idx = line_elem<AXIS>(logn, line0 + line_of(e), point_of(e));
       if (IO == FFT_REAL_IN) v[q] = C{rin[idx], T(0)};
+      else if (IO == FFT_PAIR_IN) v[q] = C{rin[idx], rin2[idx]};
       else v[q] = data[idx];
     }
   }
@@ -238,8 +246,14 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(typename CplxOf<T>::t
       C x = v[q];
       if (inverse) x.y = -x.y;
       const unsigned idx = line_elem<AXIS>(logn, line0 + line_of(e), point_of(e));
-      if (IO == FFT_REAL_OUT) rout[idx] = x.x;
-      else data[idx] = x;
+      if (IO == FFT_REAL_OUT) {
+        rout[idx] = x.x;
+      } else if (IO == FFT_SPLIT_OUT) {
+        rout[idx] = x.x;
+        rout2[idx] = x.y;
+      } else {
+        data[idx] = x;
+      }
     }
   }
 }
@@ -270,16 +284,26 @@ __device__ __forceinline__ int axis_index(long long q, int n) {
   return AXIS == 0 ? (int)(q % n) : (AXIS == 1 ? (int)((q / n) % n) : (int)(q / ((long long)n * n)));
 }
 
-// a_hat = -i kappa~_a Phi_hat: (re, im) -> (kappa~ im, -kappa~ re)
-template <typename T, int AXIS>
-__global__ __launch_bounds__(256) void k_fft_grad(const typename CplxOf<T>::type* __restrict__ c0,
-                                                  typename CplxOf<T>::type* c1, int n, double tk) {
+// the four real fields of the solve packed two per complex spectrum: with
+// Phi_hat in c (already divided by N) and a_hat_a = -i kappa~_a Phi_hat,
+// c1 = a_hat_x + i a_hat_y and c (in place) = a_hat_z + i Phi_hat; each of
+// the four spectra is Hermitian (the Nyquist index has kappa~ = 0), so the
+// inverse transforms give a_x + i a_y and a_z + i Phi
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_grad_pairs(typename CplxOf<T>::type* c,
+                                                        typename CplxOf<T>::type* c1, int n,
+                                                        double tk) {
   const long long N = (long long)n * n * n;
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   if (q >= N) return;
-  const T ka = (T)dkappa(axis_index<AXIS>(q, n), n, tk);
-  c1[q].x = ka * c0[q].y;
-  c1[q].y = -ka * c0[q].x;
+  const T kx = (T)dkappa(axis_index<0>(q, n), n, tk), ky = (T)dkappa(axis_index<1>(q, n), n, tk),
+          kz = (T)dkappa(axis_index<2>(q, n), n, tk);
+  const T re = c[q].x, im = c[q].y;
+  // -i k (re + i im) = (k im, -k re); i (u + i w) = (-w, u)
+  c1[q].x = kx * im + ky * re;
+  c1[q].y = -kx * re + ky * im;
+  c[q].x = kz * im - im;
+  c[q].y = -kz * re + re;
 }
 
 template <typename T>
@@ -311,6 +335,29 @@ __global__ __launch_bounds__(256) void k_fft_adj_accum(const typename CplxOf<T>:
     acc[q].x += re;
     acc[q].y += im;
   }
+}
+
+// the same for the x and y components from Z = FFT(g_x + i g_y): G_x(k) =
+// (Z(k) + conj Z(-k)) / 2 and G_y(k) = (Z(k) - conj Z(-k)) / 2i (the two
+// spectra of real fields), acc = conj(m_x) G_x + conj(m_y) G_y
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_adj_accum_pair(
+    const typename CplxOf<T>::type* __restrict__ z, typename CplxOf<T>::type* acc, int n,
+    double tk, double fourpiG) {
+  const long long N = (long long)n * n * n;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int ix = (int)(q % n), iy = (int)((q / n) % n), iz = (int)(q / ((long long)n * n));
+  const long long r = ((long long)((n - iz) % n) * n + (n - iy) % n) * n + (n - ix) % n;
+  const T zr = z[q].x, zi = z[q].y, wr = z[r].x, wi = z[r].y;
+  const T gxr = T(0.5) * (zr + wr), gxi = T(0.5) * (zi - wi);  // (Z + conj W) / 2
+  const T gyr = T(0.5) * (zi + wi), gyi = T(-0.5) * (zr - wr);  // (Z - conj W) / 2i
+  const int kx = wavenum(ix, n), ky = wavenum(iy, n), kz = wavenum(iz, n);
+  const double k2 = tk * tk * (double)(kx * kx + ky * ky + kz * kz);
+  const double s = k2 > 0.0 ? -fourpiG / (k2 * (double)N) : 0.0;
+  const T fx = (T)(s * dkappa(ix, n, tk)), fy = (T)(s * dkappa(iy, n, tk));
+  acc[q].x = -fx * gxi - fy * gyi;
+  acc[q].y = fx * gxr + fy * gyr;
 }
 
 // gravity kick with a given acceleration field, m += rho a dt, E += (m_old .
@@ -396,9 +443,15 @@ __global__ __launch_bounds__(256) void k_accel_kick_vjp(const T* __restrict__ U,
 // the three one-axis passes over the n^3 cube c, with the twiddles tw; with
 // rin the x pass reads the real field rin instead of c, with rout the z pass
 // writes only the real part of the result, to rout (c then holds no result)
+// the three one-axis passes over the n^3 cube c, with the twiddles tw; with
+// rin the x pass reads the real field rin (with rin2 too: rin + i rin2)
+// instead of c, with rout the z pass writes only the real part of the result
+// to rout (with rout2 too: the imaginary part to rout2; c then holds no
+// result)
 template <typename T>
 hipError_t fft3_raw(typename CplxOf<T>::type* c, const typename CplxOf<T>::type* tw, int n,
-                    int inverse, hipStream_t s, const T* rin = nullptr, T* rout = nullptr) {
+                    int inverse, hipStream_t s, const T* rin = nullptr, T* rout = nullptr,
+                    T* rout2 = nullptr, const T* rin2 = nullptr) {
   using C = typename CplxOf<T>::type;
   int logn = 0;
   while ((1 << logn) < n) ++logn;
@@ -410,28 +463,28 @@ hipError_t fft3_raw(typename CplxOf<T>::type* c, const typename CplxOf<T>::type*
     ++loglpb;
   const unsigned grid = (unsigned)(lines >> loglpb);
   const size_t lds = (size_t)n * sizeof(C) << loglpb;
-  if (rin)
-    hipLaunchKernelGGL((k_fft_lines<T, 0, FFT_REAL_IN>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
-                       rin, (T*)nullptr, tw, logn, loglpb, inverse);
-  else
-    hipLaunchKernelGGL((k_fft_lines<T, 0, FFT_COMPLEX>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
-                       (const T*)nullptr, (T*)nullptr, tw, logn, loglpb, inverse);
-  hipLaunchKernelGGL((k_fft_lines<T, 1, FFT_COMPLEX>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
-                     (const T*)nullptr, (T*)nullptr, tw, logn, loglpb, inverse);
-  if (rout)
-    hipLaunchKernelGGL((k_fft_lines<T, 2, FFT_REAL_OUT>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
-                       (const T*)nullptr, rout, tw, logn, loglpb, inverse);
-  else
-    hipLaunchKernelGGL((k_fft_lines<T, 2, FFT_COMPLEX>), dim3(grid), dim3(FFT_THREADS), lds, s, c,
-                       (const T*)nullptr, (T*)nullptr, tw, logn, loglpb, inverse);
+  T* const nul = nullptr;
+  const T* const cnul = nullptr;
+#define MH_LINES(AX, IO, RI, RI2, RO, RO2)                                                   \
+  hipLaunchKernelGGL((k_fft_lines<T, AX, IO>), dim3(grid), dim3(FFT_THREADS), lds, s, c, RI, \
+                     RI2, RO, RO2, tw, logn, loglpb, inverse)
+  if (rin && rin2) MH_LINES(0, FFT_PAIR_IN, rin, rin2, nul, nul);
+  else if (rin) MH_LINES(0, FFT_REAL_IN, rin, cnul, nul, nul);
+  else MH_LINES(0, FFT_COMPLEX, cnul, cnul, nul, nul);
+  MH_LINES(1, FFT_COMPLEX, cnul, cnul, nul, nul);
+  if (rout && rout2) MH_LINES(2, FFT_SPLIT_OUT, cnul, cnul, rout, rout2);
+  else if (rout) MH_LINES(2, FFT_REAL_OUT, cnul, cnul, rout, nul);
+  else MH_LINES(2, FFT_COMPLEX, cnul, cnul, nul, nul);
+#undef MH_LINES
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t fft3(char* ws, const MGLayout& L, typename CplxOf<T>::type* c, int inverse,
-                hipStream_t s, const T* rin = nullptr, T* rout = nullptr) {
+                hipStream_t s, const T* rin = nullptr, T* rout = nullptr, T* rout2 = nullptr,
+                const T* rin2 = nullptr) {
   using C = typename CplxOf<T>::type;
-  return fft3_raw<T>(c, P<C>(ws, L.fft_tw), L.lev[0].n, inverse, s, rin, rout);
+  return fft3_raw<T>(c, P<C>(ws, L.fft_tw), L.lev[0].n, inverse, s, rin, rout, rout2, rin2);
 }
 
 template <typename T>
@@ -478,14 +531,11 @@ hipError_t fft_poisson(char* ws, MGLayout& L, double h, hipStream_t s) {
   hipError_t e = fft3<T>(ws, L, c0, 0, s, P<T>(ws, f.F));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fft_phi<T>), dim3(nblk(N)), dim3(256), 0, s, c0, n, tk);
-  for (int a = 0; a < 3; ++a) {
-    if (a == 0) hipLaunchKernelGGL((k_fft_grad<T, 0>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
-    if (a == 1) hipLaunchKernelGGL((k_fft_grad<T, 1>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
-    if (a == 2) hipLaunchKernelGGL((k_fft_grad<T, 2>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
-    e = fft3<T>(ws, L, c1, 1, s, nullptr, acc + a * N);
-    if (e != hipSuccess) return e;
-  }
-  e = fft3<T>(ws, L, c0, 1, s, nullptr, P<T>(ws, f.phi[L.cur0]));
+  // two inverse transforms for the four real outputs (a_x, a_y | a_z, Phi)
+  hipLaunchKernelGGL((k_fft_grad_pairs<T>), dim3(nblk(N)), dim3(256), 0, s, c0, c1, n, tk);
+  e = fft3<T>(ws, L, c1, 1, s, nullptr, acc, acc + N);
+  if (e != hipSuccess) return e;
+  e = fft3<T>(ws, L, c0, 1, s, nullptr, acc + 2 * N, P<T>(ws, f.phi[L.cur0]));
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -523,20 +573,16 @@ hipError_t fft_gravity_vjp(char* ws, MGLayout& L, double h, double G, const T* U
                      P<T>(ws, L.fft_acc), N, dt, lin, lout, accb);
   hipLaunchKernelGGL((k_fft_twiddles<T>), dim3(nblk(n / 2 > 0 ? n / 2 : 1)), dim3(256), 0, s,
                      P<C>(ws, L.fft_tw), n);
-  for (int a = 0; a < 3; ++a) {
-    hipError_t e = fft3<T>(ws, L, c1, 0, s, accb + a * N);
-    if (e != hipSuccess) return e;
-    if (a == 0)
-      hipLaunchKernelGGL((k_fft_adj_accum<T, 0>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
-                         fourpiG, 1);
-    if (a == 1)
-      hipLaunchKernelGGL((k_fft_adj_accum<T, 1>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
-                         fourpiG, 0);
-    if (a == 2)
-      hipLaunchKernelGGL((k_fft_adj_accum<T, 2>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
-                         fourpiG, 0);
-  }
-  hipError_t e = fft3<T>(ws, L, c0, 1, s);
+  // x and y in one transform (two real fields as re + i im), then z
+  hipError_t e = fft3<T>(ws, L, c1, 0, s, accb, nullptr, nullptr, accb + N);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_adj_accum_pair<T>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
+                     fourpiG);
+  e = fft3<T>(ws, L, c1, 0, s, accb + 2 * N);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_adj_accum<T, 2>), dim3(nblk(N)), dim3(256), 0, s, c1, c0, n, tk,
+                     fourpiG, 0);
+  e = fft3<T>(ws, L, c0, 1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fft_real_add<T>), dim3(nblk(N)), dim3(256), 0, s, c0, lout, N);
   return hipGetLastError();

@@ -86,6 +86,9 @@ hipError_t launch_clock_set(DevClock* clk, double t, long long step, hipStream_t
 hipError_t launch_prologue(const PrologueArgs& a, hipStream_t s);
 hipError_t launch_sched_reset(DevClock* clk, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+template <typename T>
+hipError_t launch_adam(T* th, T* m, T* v, const T* g, long long count, double lr, double b1,
+                       double b2, double eps, long long it, hipStream_t s);
 hipError_t launch_ou_init(const OUArgs& a, hipStream_t s);
 
 }  // namespace mh

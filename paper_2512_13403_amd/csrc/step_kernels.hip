@@ -174,6 +174,41 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
   return hipGetLastError();
 }
 
+// One ADAM update of `count` parameters in place (Kingma & Ba 2015):
+// m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// theta -= lr (m / c1) / (sqrt(v / c2) + eps), c1 = 1 - b1^it, c2 = 1 - b2^it.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adam_any(T* __restrict__ th, T* __restrict__ m,
+                                                  T* __restrict__ v, const T* __restrict__ g,
+                                                  long long count, T lr, T b1, T b2, T eps, T c1,
+                                                  T c2) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (long long)gridDim.x * 256) {
+    const T gi = g[i];
+    const T mi = b1 * m[i] + (T(1) - b1) * gi;
+    const T vi = b2 * v[i] + (T(1) - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrt(vi / c2) + eps);
+  }
+}
+
+template <typename T>
+hipError_t launch_adam(T* th, T* m, T* v, const T* g, long long count, double lr, double b1,
+                       double b2, double eps, long long it, hipStream_t s) {
+  const double c1 = 1.0 - pow(b1, (double)it), c2 = 1.0 - pow(b2, (double)it);
+  long long blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((k_adam_any<T>), dim3((unsigned)blocks), dim3(256), 0, s, th, m, v, g, count,
+                     (T)lr, (T)b1, (T)b2, (T)eps, (T)c1, (T)c2);
+  return hipGetLastError();
+}
+template hipError_t launch_adam<float>(float*, float*, float*, const float*, long long, double,
+                                       double, double, double, long long, hipStream_t);
+template hipError_t launch_adam<double>(double*, double*, double*, const double*, long long,
+                                        double, double, double, double, long long, hipStream_t);
+
 hipError_t launch_ou_init(const OUArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_ou_init, dim3(1), dim3(MAX_MODES), 0, s, a);
   return hipGetLastError();

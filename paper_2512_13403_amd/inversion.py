@@ -7,6 +7,7 @@ library's hand-written adjoint step).
 The control is the initial density; the initial velocity and pressure stay
 fixed, and the conserved state is assembled from them as in the paper's
 initial-condition equation (Sec. 3.1: m = rho v, E = P/(gamma-1) + rho|v|^2/2).
+The ADAM update of the control runs in the library (``mh_adam``).
 Two misfits are offered:
 
 * ``"l2"``:        1/2 sum (rho_final - rho_target)^2 over the cube;
@@ -23,6 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import Adam
 from .rollout import make_rollout_function
 
 
@@ -58,19 +60,19 @@ def invert_initial_density(solver, U_init, target, dts, iters=50, lr=1e-2, K=10,
     rho0 = U_init[0]
     v = (U_init[1:4] / rho0).detach()
     p = ((gamma - 1.0) * (U_init[4] - 0.5 * (U_init[1:4] ** 2).sum(dim=0) / rho0)).detach()
-    rho = rho0.detach().clone().requires_grad_(True)
-    opt = torch.optim.Adam([rho], lr=lr)
+    rho = rho0.detach().clone().contiguous().requires_grad_(True)
+    opt = Adam(rho.data, lr=lr)
     F = make_rollout_function()
     dts = np.asarray(dts, dtype=np.float64)
     losses = []
     for it in range(iters):
-        opt.zero_grad()
+        rho.grad = None
         U0 = assemble_state(rho, v, p, gamma)
         Uf = F.apply(U0, solver, len(dts), K, dts)
         loss = misfit(Uf[0], target, kind)
         loss.backward()
         losses.append(float(loss.detach()))
-        opt.step()
+        opt.step(rho.grad)
         with torch.no_grad():
             rho.clamp_(min=rho_floor)
         if callback is not None:
@@ -94,14 +96,12 @@ def learn_flux_correction(solver, U0, target, dts, iters=30, lr=1e-3, K=10, kind
 
     from .rollout import rollout_backward, rollout_forward
 
-    B = (torch.zeros_like(U0) if field_init is None else field_init.detach().clone())
-    B.requires_grad_(True)
+    B = (torch.zeros_like(U0) if field_init is None else field_init.detach().clone()).contiguous()
     gB = torch.zeros_like(U0)
-    opt = torch.optim.Adam([B], lr=lr)
+    opt = Adam(B, lr=lr)
     dts = np.asarray(dts, dtype=np.float64)
     losses = []
     for it in range(iters):
-        opt.zero_grad()
         field = B.detach().contiguous()
         gB.zero_()
         solver.set_flux_correction(field, gB)
@@ -112,10 +112,8 @@ def learn_flux_correction(solver, U0, target, dts, iters=30, lr=1e-3, K=10, kind
         lam = torch.zeros_like(Uf)
         lam[0] = rho.grad
         rollout_backward(solver, cks, used, K, lam)
-        torch.cuda.synchronize()
-        B.grad = gB.clone()
         losses.append(float(loss.detach()))
-        opt.step()
+        opt.step(gB)
         if callback is not None:
             callback(it, losses[-1])
     solver.set_flux_correction(None, None)

@@ -24,7 +24,7 @@ import math
 
 import numpy as np
 
-from . import fft3
+from . import Adam, fft3
 from .inversion import misfit
 from .rollout import make_rollout_function
 
@@ -133,19 +133,19 @@ def invert_turbulent_phases(solver, phases_init, target, dts, basis, iters=30, l
     import torch
 
     gamma = solver.grid.gamma
-    phases = phases_init.detach().clone().requires_grad_(True)
-    opt = torch.optim.Adam([phases], lr=lr)
+    phases = phases_init.detach().clone().contiguous().requires_grad_(True)
+    opt = Adam(phases.data, lr=lr)
     F = make_rollout_function()
     dts = np.asarray(dts, dtype=np.float64)
     losses = []
     for it in range(iters):
-        opt.zero_grad()
+        phases.grad = None
         U0 = initial_state(phases, basis, mach, rho0, p0, gamma)
         Uf = F.apply(U0, solver, len(dts), K, dts)
         loss = misfit(Uf[0], target, kind)
         loss.backward()
         losses.append(float(loss.detach()))
-        opt.step()
+        opt.step(phases.grad)
         if callback is not None:
             callback(it, losses[-1])
     return phases.detach(), losses

@@ -57,3 +57,30 @@ def test_projected_density_inversion_reduces_misfit():
                                            kind="projected")
     print("projected misfit", losses[0], "->", losses[-1], flush=True)
     assert losses[-1] < 0.3 * losses[0]
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_library_adam_follows_the_update_rule(dtype):
+    """mh_adam (the optimiser of the reconstructions) against the ADAM update
+    written out in float64 over five iterations with varying gradients."""
+    import torch
+
+    td = getattr(torch, dtype)
+    rng = np.random.default_rng(4)
+    theta = rng.standard_normal(1000)
+    grads = [rng.standard_normal(1000) * 10.0 ** (k - 2) for k in range(5)]
+    p = torch.tensor(theta, dtype=td, device="cuda:0")
+    opt = mh.Adam(p, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    ref = theta.astype(np.float32 if dtype == "float32" else np.float64).astype(np.float64)
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    for it, g in enumerate(grads, start=1):
+        gq = torch.tensor(g, dtype=td, device="cuda:0")
+        opt.step(gq)
+        gd = gq.double().cpu().numpy()
+        m = 0.9 * m + 0.1 * gd
+        v = 0.999 * v + 0.001 * gd * gd
+        ref = ref - 1e-2 * (m / (1 - 0.9 ** it)) / (np.sqrt(v / (1 - 0.999 ** it)) + 1e-8)
+    got = p.double().cpu().numpy()
+    tol = 1e-12 if dtype == "float64" else 2e-6
+    assert np.abs(got - ref).max() < tol * np.abs(ref).max()
