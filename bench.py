@@ -180,7 +180,7 @@ def adjoint_probe(n=256, reps=10):
           f"forward step {1e3 * (t3 - t2) / reps:.3f} ms", flush=True)
 
 
-def stage_probe(n=512, steps=3):
+def stage_probe(n=512, steps=20):
     """Short runs of the 512^3 fp32 step in configurations that differ by one
     phase of the method (slopes off, each source on or off, the van Leer
     limiter), for per-kernel instruction counters: one text line each."""
@@ -469,8 +469,11 @@ def main():
                     help="instead: time adjoint steps at 256^3 fp32 (forcing + cooling) for "
                          "the kernel profiles, one text line")
     ap.add_argument("--stage-probe", action="store_true",
-                    help="instead: 3 steps of the 512^3 fp32 step in six configurations that "
-                         "differ by one phase (for instruction counters), one text line each")
+                    help="instead: the 512^3 fp32 step in six configurations that differ by "
+                         "one phase (timed side by side, and for instruction counters), one "
+                         "text line each")
+    ap.add_argument("--probe-steps", type=int, default=20,
+                    help="timed steps per configuration of --stage-probe")
     ap.add_argument("--corrector-probe", action="store_true",
                     help="instead: corrector forward passes and training steps at 4 x 64^3, "
                          "one text line")
@@ -505,7 +508,7 @@ def main():
     if args.c4_probe:
         return c4_probe()
     if args.stage_probe:
-        return stage_probe()
+        return stage_probe(steps=args.probe_steps)
     if args.corrector_probe:
         return corrector_probe()
 

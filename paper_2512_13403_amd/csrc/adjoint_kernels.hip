@@ -41,95 +41,100 @@ __device__ __forceinline__ T sel_value(int s, T a, T b) {
   return s == 1 ? a : (s == 2 ? b : T(0));
 }
 
+// primitive variables of cell q, with the arithmetic of the stage kernels
+// (so every limiter and wave-speed branch is taken as in the forward step)
 template <typename T>
 __device__ __forceinline__ void prim_at(const T* __restrict__ U, long long N, long long q, T gm1,
                                         T (&w)[5]) {
   T u[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) u[f] = U[f * N + q];
-  const T ir = T(1) / u[0];
-  w[0] = u[0];
-  w[1] = u[1] * ir;
-  w[2] = u[2] * ir;
-  w[3] = u[3] * ir;
-  w[4] = gm1 * (u[4] - T(0.5) * u[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]));
+  to_prim(u, gm1, w);
 }
 
 // Reverse of the one-sided HLLC assembly of the stage kernel, for face states
 // wl, wr = (rho, v_n, v_t1, v_t2, P) in the face frame.  Fb = dL/dF; writes
-// dL/dwl and dL/dwr.
+// dL/dwl and dL/dwr.  The forward quantities are recomputed with the stage
+// kernel's own arithmetic (c = gP rsq(gP rho), S* through one reciprocal of
+// rho_L(S_L - u_L) - rho_R(S_R - u_R)), so the side, fan and wave-speed
+// branches are the ones the step took; the derivatives use the same
+// reciprocals (dc/dP = g rsq(gP rho) / 2, dc/drho = -c / (2 rho) with
+// 1/rho = gP rsq^2) instead of divisions.
 template <typename T>
-__device__ void hllc_reverse(const T (&wl)[5], const T (&wr)[5], T g, const T (&Fb)[5],
+__device__ void hllc_reverse(const T (&wl)[5], const T (&wr)[5], T g, T gm1inv, const T (&Fb)[5],
                              T (&wlb)[5], T (&wrb)[5]) {
-  const T gm1 = g - T(1);
   const T rl = wl[0], ul = wl[1], al = wl[2], bl = wl[3], pl = wl[4];
   const T rr = wr[0], ur = wr[1], ar = wr[2], br = wr[3], pr = wr[4];
-  const T cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+  const T gpl = g * pl, gpr = g * pr;
+  const T rsl = dev_rsq(gpl * rl), rsr = dev_rsq(gpr * rr);
+  const T cl = gpl * rsl, cr = gpr * rsr;
   const bool minL = (ul - cl) <= (ur - cr);
   const bool maxL = (ul + cl) >= (ur + cr);
   const T SL = minL ? ul - cl : ur - cr;
   const T SR = maxL ? ul + cl : ur + cr;
-  const T El = pl / gm1 + T(0.5) * rl * (ul * ul + al * al + bl * bl);
-  const T Er = pr / gm1 + T(0.5) * rr * (ur * ur + ar * ar + br * br);
+  const T kl = fmad(ul, ul, fmad(al, al, bl * bl)), kr = fmad(ur, ur, fmad(ar, ar, br * br));
+  const T El = fmad(pl, gm1inv, (T(0.5) * rl) * kl);
+  const T Er = fmad(pr, gm1inv, (T(0.5) * rr) * kr);
   const T dl = rl * (SL - ul), dr = rr * (SR - ur);
-  const T num = pr - pl + ul * dl - ur * dr, den = dl - dr;
-  const T ss = num / den;
+  const T num = fmad(-ur, dr, fmad(ul, dl, pr - pl));
+  const T iden = dev_rcp(dl - dr);
+  const T ss = num * iden;
   const bool left = (SL >= T(0)) || (ss >= T(0));
-  const bool fan = left ? (SL < T(0)) : (SR > T(0));
+  const bool fan = (left ? -SL : SR) > T(0);
   const T rK = left ? rl : rr, uK = left ? ul : ur, aK = left ? al : ar, bK = left ? bl : br;
   const T pK = left ? pl : pr, EK = left ? El : Er, SK = left ? SL : SR, dK = left ? dl : dr;
   const T mK = rK * uK;
 
   T rKb = 0, uKb = 0, aKb = 0, bKb = 0, pKb = 0, EKb = 0, SKb = 0, dKb = 0, mKb = 0, ssb = 0;
   if (fan) {
-    const T q = T(1) / (SK - ss);
+    const T q = dev_rcp(SK - ss);
     const T qd = q * dK;
-    const T H = dK * ss + pK;
-    const T G4 = (SK - uK) * EK + (ss - uK) * H;
+    const T H = fmad(dK, ss, pK);
+    const T G4 = fmad(SK - uK, EK, (ss - uK) * H);
     const T s[5] = {qd, qd * ss, qd * aK, qd * bK, q * G4};
     const T UK[5] = {rK, mK, rK * aK, rK * bK, EK};
     T sb[5], UKb[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      SKb += Fb[f] * (s[f] - UK[f]);
+      SKb = fmad(Fb[f], s[f] - UK[f], SKb);
       sb[f] = SK * Fb[f];
       UKb[f] = -SK * Fb[f];
     }
     T qb = sb[4] * G4;
     const T G4b = sb[4] * q;
-    SKb += G4b * EK;
-    uKb -= G4b * EK;
-    EKb += G4b * (SK - uK);
-    ssb += G4b * H;
-    uKb -= G4b * H;
+    SKb = fmad(G4b, EK, SKb);
+    uKb = fmad(-G4b, EK, uKb);
+    EKb = fmad(G4b, SK - uK, EKb);
+    ssb = fmad(G4b, H, ssb);
+    uKb = fmad(-G4b, H, uKb);
     const T Hb = G4b * (ss - uK);
-    dKb += Hb * ss;
-    ssb += Hb * dK;
+    dKb = fmad(Hb, ss, dKb);
+    ssb = fmad(Hb, dK, ssb);
     pKb += Hb;
-    const T qdb = sb[0] + sb[1] * ss + sb[2] * aK + sb[3] * bK;
-    ssb += sb[1] * qd;
-    aKb += sb[2] * qd;
-    bKb += sb[3] * qd;
-    qb += qdb * dK;
-    dKb += qdb * q;
-    const T Zb = -qb * q * q;  // q = 1/Z, Z = SK - ss
+    const T qdb = fmad(sb[3], bK, fmad(sb[2], aK, fmad(sb[1], ss, sb[0])));
+    ssb = fmad(sb[1], qd, ssb);
+    aKb = fmad(sb[2], qd, aKb);
+    bKb = fmad(sb[3], qd, bKb);
+    qb = fmad(qdb, dK, qb);
+    dKb = fmad(qdb, q, dKb);
+    const T Zb = -(qb * q) * q;  // q = 1/Z, Z = SK - ss
     SKb += Zb;
     ssb -= Zb;
-    rKb += UKb[0] + UKb[2] * aK + UKb[3] * bK;
+    rKb += fmad(UKb[3], bK, fmad(UKb[2], aK, UKb[0]));
     mKb += UKb[1];
-    aKb += UKb[2] * rK;
-    bKb += UKb[3] * rK;
+    aKb = fmad(UKb[2], rK, aKb);
+    bKb = fmad(UKb[3], rK, bKb);
     EKb += UKb[4];
   }
   // F_K = (mK, mK uK + pK, mK aK, mK bK, uK (EK + pK))
-  mKb += Fb[0] + Fb[1] * uK + Fb[2] * aK + Fb[3] * bK;
-  uKb += Fb[1] * mK + Fb[4] * (EK + pK);
-  pKb += Fb[1] + Fb[4] * uK;
-  aKb += Fb[2] * mK;
-  bKb += Fb[3] * mK;
-  EKb += Fb[4] * uK;
-  rKb += mKb * uK;
-  uKb += mKb * rK;
+  mKb += fmad(Fb[3], bK, fmad(Fb[2], aK, fmad(Fb[1], uK, Fb[0])));
+  uKb += fmad(Fb[4], EK + pK, Fb[1] * mK);
+  pKb += fmad(Fb[4], uK, Fb[1]);
+  aKb = fmad(Fb[2], mK, aKb);
+  bKb = fmad(Fb[3], mK, bKb);
+  EKb = fmad(Fb[4], uK, EKb);
+  rKb = fmad(mKb, uK, rKb);
+  uKb = fmad(mKb, rK, uKb);
 
   T rlb = 0, ulb = 0, alb = 0, blb = 0, plb = 0, Elb = 0, SLb = 0, dlb = 0;
   T rrb = 0, urb = 0, arb = 0, brb = 0, prb = 0, Erb = 0, SRb = 0, drb = 0;
@@ -138,38 +143,42 @@ __device__ void hllc_reverse(const T (&wl)[5], const T (&wr)[5], T g, const T (&
   } else {
     rrb = rKb; urb = uKb; arb = aKb; brb = bKb; prb = pKb; Erb = EKb; SRb = SKb; drb = dKb;
   }
-  const T numb = ssb / den, denb = -ssb * ss / den;
+  // ss = num / den
+  const T numb = ssb * iden, denb = -(ssb * ss) * iden;
   prb += numb;
   plb -= numb;
-  ulb += numb * dl;
-  dlb += numb * ul;
-  urb -= numb * dr;
-  drb -= numb * ur;
+  ulb = fmad(numb, dl, ulb);
+  dlb = fmad(numb, ul, dlb);
+  urb = fmad(-numb, dr, urb);
+  drb = fmad(-numb, ur, drb);
   dlb += denb;
   drb -= denb;
-  rlb += dlb * (SL - ul);
-  SLb += dlb * rl;
-  ulb -= dlb * rl;
-  rrb += drb * (SR - ur);
-  SRb += drb * rr;
-  urb -= drb * rr;
-  plb += Elb / gm1;
-  rlb += Elb * T(0.5) * (ul * ul + al * al + bl * bl);
-  ulb += Elb * rl * ul;
-  alb += Elb * rl * al;
-  blb += Elb * rl * bl;
-  prb += Erb / gm1;
-  rrb += Erb * T(0.5) * (ur * ur + ar * ar + br * br);
-  urb += Erb * rr * ur;
-  arb += Erb * rr * ar;
-  brb += Erb * rr * br;
+  rlb = fmad(dlb, SL - ul, rlb);
+  SLb = fmad(dlb, rl, SLb);
+  ulb = fmad(-dlb, rl, ulb);
+  rrb = fmad(drb, SR - ur, rrb);
+  SRb = fmad(drb, rr, SRb);
+  urb = fmad(-drb, rr, urb);
+  plb = fmad(Elb, gm1inv, plb);
+  rlb = fmad(Elb * T(0.5), kl, rlb);
+  const T Elr = Elb * rl;
+  ulb = fmad(Elr, ul, ulb);
+  alb = fmad(Elr, al, alb);
+  blb = fmad(Elr, bl, blb);
+  prb = fmad(Erb, gm1inv, prb);
+  rrb = fmad(Erb * T(0.5), kr, rrb);
+  const T Err = Erb * rr;
+  urb = fmad(Err, ur, urb);
+  arb = fmad(Err, ar, arb);
+  brb = fmad(Err, br, brb);
   T clb = 0, crb = 0;
   if (minL) { ulb += SLb; clb -= SLb; } else { urb += SLb; crb -= SLb; }
   if (maxL) { ulb += SRb; clb += SRb; } else { urb += SRb; crb += SRb; }
-  plb += clb * g / (T(2) * cl * rl);
-  rlb -= clb * cl / (T(2) * rl);
-  prb += crb * g / (T(2) * cr * rr);
-  rrb -= crb * cr / (T(2) * rr);
+  // c = sqrt(gP / rho): dc/dP = g rsq / 2, dc/drho = -c / (2 rho), 1/rho = gP rsq^2
+  plb = fmad(clb, T(0.5) * g * rsl, plb);
+  rlb = fmad(-clb, (T(0.5) * cl) * (gpl * rsl * rsl), rlb);
+  prb = fmad(crb, T(0.5) * g * rsr, prb);
+  rrb = fmad(-crb, (T(0.5) * cr) * (gpr * rsr * rsr), rrb);
   wlb[0] = rlb; wlb[1] = ulb; wlb[2] = alb; wlb[3] = blb; wlb[4] = plb;
   wrb[0] = rrb; wrb[1] = urb; wrb[2] = arb; wrb[3] = brb; wrb[4] = prb;
 }
@@ -411,6 +420,7 @@ __global__ __launch_bounds__(256) void k_face_vjp(const T* __restrict__ U, const
   const int i = g.bc == BC_PERIODIC ? f : f - 1;  // left cell position of the face
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   const T gm1 = gamma - T(1);
+  const T gm1inv = T(1) / gm1;
   constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
   const int perm[5] = {0, vn, t1, t2, 4};
   T w[4][5];
@@ -446,7 +456,7 @@ __global__ __launch_bounds__(256) void k_face_vjp(const T* __restrict__ U, const
     Fb[s] = (vr - vl) * ih;
   }
   T wlb[5], wrb[5];
-  hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+  hllc_reverse<T>(wl, wr, gamma, gm1inv, Fb, wlb, wrb);
   const long long rec = face_of<AX>(g, f, o1, o2);
   const long long NF = (long long)g.nf * d1 * d2;
 #pragma unroll
@@ -480,6 +490,7 @@ __global__ __launch_bounds__(256) void k_face_vjp_rt(const T* __restrict__ U,
   const int i = g.bc == BC_PERIODIC ? f : f - 1;
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   const T gm1 = gamma - T(1);
+  const T gm1inv = T(1) / gm1;
   constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
   const int perm[5] = {0, vn, t1, t2, 4};
   T w[4][5];
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(256) void k_face_vjp_rt(const T* __restrict__ U,
   T wlb[5], wrb[5];
   if (rs == RS_HLL) hll_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
   else if (rs == RS_RUSANOV) rusanov_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
-  else hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+  else hllc_reverse<T>(wl, wr, gamma, gm1inv, Fb, wlb, wrb);
   const long long rec = face_of<AX>(g, f, o1, o2);
   const long long NF = (long long)g.nf * d1 * d2;
 #pragma unroll
@@ -553,7 +564,7 @@ template <typename T>
 __device__ __forceinline__ void finish_cell(const T* __restrict__ U, const T (&w)[5], long long q,
                                             long long N, const FinishArgs<T>& fa) {
   const T rho = U[q];
-  const T ir = T(1) / rho;
+  const T ir = dev_rcp(rho);
   const T vx = U[N + q] * ir, vy = U[2 * N + q] * ir, vz = U[3 * N + q] * ir;
   const T wr = w[0], wx = w[1], wy = w[2], wz = w[3], wp = w[4];
   const T gm1 = fa.gm1;
@@ -688,6 +699,7 @@ __global__ __launch_bounds__(256) void k_axis_jtv(const T* __restrict__ U, const
   const int c0 = sg * seg, c1 = min(c0 + seg, n);
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   const T gm1 = gamma - T(1);
+  const T gm1inv = T(1) / gm1;
   constexpr int vn = 1 + AX, t1 = 1 + (AX + 1) % 3, t2 = 1 + (AX + 2) % 3;
   const int perm[5] = {0, vn, t1, t2, 4};
   auto wrapc = [&](int c) { return c < 0 ? c + n : (c >= n ? c - n : c); };
@@ -731,7 +743,7 @@ __global__ __launch_bounds__(256) void k_axis_jtv(const T* __restrict__ U, const
 #pragma unroll
     for (int s = 0; s < 5; ++s) Fb[s] = (vr[s] - vl[s]) * ih;
     T wlb[5], wrb[5];
-    hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+    hllc_reverse<T>(wl, wr, gamma, gm1inv, Fb, wlb, wrb);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -798,6 +810,7 @@ __global__ __launch_bounds__(256) void k_x_jtv(const T* __restrict__ U, const T*
   const int x0 = sg * XSEG;
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   const T gm1 = gamma - T(1);
+  const T gm1inv = T(1) / gm1;
   auto wrapc = [&](int c) {
     c %= n;
     return c < 0 ? c + n : c;
@@ -826,7 +839,7 @@ __global__ __launch_bounds__(256) void k_x_jtv(const T* __restrict__ U, const T*
 #pragma unroll
     for (int s = 0; s < 5; ++s) Fb[s] = (v[s * N + qr] - v[s * N + ql]) * ih;
     T wlb[5], wrb[5];
-    hllc_reverse<T>(wl, wr, gamma, Fb, wlb, wrb);
+    hllc_reverse<T>(wl, wr, gamma, gm1inv, Fb, wlb, wrb);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
