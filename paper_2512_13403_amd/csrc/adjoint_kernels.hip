@@ -939,25 +939,24 @@ __device__ __forceinline__ void ou_accel(const T* __restrict__ rows, const T* __
   }
 }
 
-// forward kick m += rho a dt, E += (m_old . a) dt with the OU acceleration
+// reverse of the kick m += rho a dt, E += (m_old . a) dt (the acceleration
+// does not depend on the state): lam_rho += sum_c lam_m_c a_c dt,
+// lam_m_c += lam_E a_c dt
 template <typename T>
-__global__ __launch_bounds__(256) void k_force_kick(T* U, const T* __restrict__ rows,
-                                                    const T* __restrict__ tabx, int R, int nx,
-                                                    int ny, int nz, T dt) {
-  const long long N = (long long)nx * ny * nz;
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= N) return;
-  const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((long long)nx * ny));
-  T a[3];
-  ou_accel(rows, tabx, R, nx, ny, x, y, z, a);
-  const T rho = U[q];
-  const T dE = U[N + q] * a[0] + U[2 * N + q] * a[1] + U[3 * N + q] * a[2];
+__device__ __forceinline__ void kick_vjp_cell(const T (&a)[3], T dt, const T (&li)[5],
+                                              T (&lo)[5]) {
+  const T Eb = li[4];
+  T rb = li[0];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) U[(1 + c) * N + q] += rho * a[c] * dt;
-  U[4 * N + q] += dE * dt;
+  for (int c = 0; c < 3; ++c) {
+    const T mb = li[1 + c];
+    rb += mb * a[c] * dt;
+    lo[1 + c] = mb + Eb * a[c] * dt;
+  }
+  lo[0] = rb;
+  lo[4] = Eb;
 }
 
-// reverse of the kick: lam_rho += sum_c lam_m_c a_c dt, lam_m_c += lam_E a_c dt
 template <typename T>
 __global__ __launch_bounds__(256) void k_force_kick_vjp(const T* __restrict__ rows,
                                                         const T* __restrict__ tabx, int R, int nx,
@@ -969,16 +968,12 @@ __global__ __launch_bounds__(256) void k_force_kick_vjp(const T* __restrict__ ro
   const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((long long)nx * ny));
   T a[3];
   ou_accel(rows, tabx, R, nx, ny, x, y, z, a);
-  const T Eb = lin[4 * N + q];
-  T rb = lin[q];
+  T li[5], lo[5];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const T mb = lin[(1 + c) * N + q];
-    rb += mb * a[c] * dt;
-    lout[(1 + c) * N + q] = mb + Eb * a[c] * dt;
-  }
-  lout[q] = rb;
-  lout[4 * N + q] = Eb;
+  for (int f = 0; f < 5; ++f) li[f] = lin[f * N + q];
+  kick_vjp_cell(a, dt, li, lo);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) lout[f * N + q] = lo[f];
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -1042,11 +1037,9 @@ __global__ __launch_bounds__(256) void k_axpy(T* y, const T* __restrict__ x, lon
 // reverse of exact cooling E' = ek + rho Tn(rho, T)/(g-1), T = (g-1)(E - ek)/rho,
 // ek = |m|^2/(2 rho), using the partial derivatives of the branch taken
 template <typename T>
-__global__ __launch_bounds__(256) void k_cool_vjp(const T* __restrict__ U, long long N, T gm1, T dt,
-                                                  CoolParams<T> c, const T* __restrict__ lin,
-                                                  T* lout) {
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= N) return;
+__device__ __forceinline__ void cool_vjp_cell(const T* __restrict__ U, long long N, long long q,
+                                              T gm1, T dt, const CoolParams<T>& c,
+                                              const T (&li)[5], T (&lo)[5]) {
   const T rho = U[q], mx = U[N + q], my = U[2 * N + q], mz = U[3 * N + q], E = U[4 * N + q];
   const T ek = T(0.5) * (mx * mx + my * my + mz * mz) / rho;
   const T Tin = gm1 * (E - ek) / rho;
@@ -1080,9 +1073,9 @@ __global__ __launch_bounds__(256) void k_cool_vjp(const T* __restrict__ U, long 
     dT = T(0);
     dr = T(0);
   }
-  const T Eb = lin[4 * N + q];
+  const T Eb = li[4];
   T ekb = Eb;
-  T rhob = lin[q] + Eb * Tn / gm1;
+  T rhob = li[0] + Eb * Tn / gm1;
   const T Tnb = Eb * rho / gm1;
   const T Tb = Tnb * dT;
   rhob += Tnb * dr;
@@ -1090,11 +1083,50 @@ __global__ __launch_bounds__(256) void k_cool_vjp(const T* __restrict__ U, long 
   ekb -= Tb * gm1 / rho;
   rhob -= Tb * Tin / rho;
   rhob -= ekb * ek / rho;
-  lout[q] = rhob;
-  lout[N + q] = lin[N + q] + ekb * mx / rho;
-  lout[2 * N + q] = lin[2 * N + q] + ekb * my / rho;
-  lout[3 * N + q] = lin[3 * N + q] + ekb * mz / rho;
-  lout[4 * N + q] = Einb;
+  lo[0] = rhob;
+  lo[1] = li[1] + ekb * mx / rho;
+  lo[2] = li[2] + ekb * my / rho;
+  lo[3] = li[3] + ekb * mz / rho;
+  lo[4] = Einb;
+}
+
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cool_vjp(const T* __restrict__ U, long long N, T gm1, T dt,
+                                                  CoolParams<T> c, const T* __restrict__ lin,
+                                                  T* lout) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  T li[5], lo[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) li[f] = lin[f * N + q];
+  cool_vjp_cell(U, N, q, gm1, dt, c, li, lo);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) lout[f * N + q] = lo[f];
+}
+
+// cooling reverse then forcing-kick reverse in one pass (the order of the
+// reverse sweep without gravity): the intermediate adjoint stays in registers
+template <typename T>
+__global__ __launch_bounds__(256) void k_cool_force_vjp(const T* __restrict__ U, T gm1, T dt,
+                                                        CoolParams<T> c,
+                                                        const T* __restrict__ rows,
+                                                        const T* __restrict__ tabx, int R, int nx,
+                                                        int ny, int nz, const T* __restrict__ lin,
+                                                        T* lout) {
+  const long long N = (long long)nx * ny * nz;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int x = (int)(q % nx), y = (int)((q / nx) % ny), z = (int)(q / ((long long)nx * ny));
+  T li[5], lm[5], lo[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) li[f] = lin[f * N + q];
+  cool_vjp_cell(U, N, q, gm1, dt, c, li, lm);
+  T a[3];
+  ou_accel(rows, tabx, R, nx, ny, x, y, z, a);
+  kick_vjp_cell(a, dt, lm, lo);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) lout[f * N + q] = lo[f];
 }
 
 inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
@@ -1234,15 +1266,6 @@ hipError_t adj_flux_corr_vjp(const T* v, const StageGeom& g, const double* h, do
 }
 
 template <typename T>
-hipError_t adj_force_kick(T* U, const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
-                          hipStream_t s) {
-  const long long N = (long long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL((k_force_kick<T>), dim3(nblk(N)), dim3(256), 0, s, U, rows, tabx, R, g.nx,
-                     g.ny, g.nz, dt);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t adj_force_kick_vjp(const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
                               const T* lin, T* lout, hipStream_t s) {
   const long long N = (long long)g.nx * g.ny * g.nz;
@@ -1255,6 +1278,16 @@ template <typename T>
 hipError_t adj_cool_vjp(const T* U, long long N, T gm1, T dt, const CoolParams<T>& c, const T* lin,
                         T* lout, hipStream_t s) {
   hipLaunchKernelGGL((k_cool_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, U, N, gm1, dt, c, lin, lout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t adj_cool_force_vjp(const T* U, T gm1, T dt, const CoolParams<T>& c, const T* rows,
+                              const T* tabx, int R, const StageGeom& g, const T* lin, T* lout,
+                              hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL((k_cool_force_vjp<T>), dim3(nblk(N)), dim3(256), 0, s, U, gm1, dt, c, rows,
+                     tabx, R, g.nx, g.ny, g.nz, lin, lout);
   return hipGetLastError();
 }
 
@@ -1289,12 +1322,13 @@ hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws
                                  T, const T*, T*, hipStream_t);                                  \
   template hipError_t adj_flux_corr_vjp<T>(const T*, const StageGeom&, const double*, double,   \
                                            T*, hipStream_t);                                   \
-  template hipError_t adj_force_kick<T>(T*, const T*, const T*, int, const StageGeom&, T,        \
-                                        hipStream_t);                                            \
   template hipError_t adj_force_kick_vjp<T>(const T*, const T*, int, const StageGeom&, T,        \
                                             const T*, T*, hipStream_t);                          \
   template hipError_t adj_cool_vjp<T>(const T*, long long, T, T, const CoolParams<T>&, const T*, \
                                       T*, hipStream_t);                                          \
+  template hipError_t adj_cool_force_vjp<T>(const T*, T, T, const CoolParams<T>&, const T*,     \
+                                            const T*, int, const StageGeom&, const T*, T*,     \
+                                            hipStream_t);                                      \
   template hipError_t adj_gravity_vjp<T>(const AdjointBuffers<T>&, MGLayout&, char*,             \
                                          const mh_physics_desc&, const T*, const T*, int, double, \
                                          T, const T*, T*, DevClock*, hipStream_t);

@@ -957,12 +957,11 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
     a.cb = T(2.0 / 3.0);
   }
   a.uout = Ua;
-  MH_HIP(c, launch_stage<T>(2, g.limiter, false, false, a, geom, c->stream));
-  // the forcing kick acts on Ua in place (the RK update itself is not read
-  // again); only gravity needs the states before (Ub) and after (Uc) a kick
+  // the last stage applies the forcing kick as the forward step does (the RK
+  // update itself is not read again), so Ua is the state after forcing,
+  // bitwise; only gravity needs the states before (Ub) and after (Uc) a kick
+  MH_HIP(c, launch_stage<T>(2, g.limiter, force, false, a, geom, c->stream));
   Ub = Ua;
-  if (force)
-    MH_HIP(c, adj_force_kick<T>(Ub, at(A.rows), a.ou_tab[0], a.ou_R, geom, (T)dt, c->stream));
   Uc = Ub;
   if (grav) {
     Uc = at(A.Uc);
@@ -979,7 +978,13 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
 
   // reverse sweep: cooling, gravity, forcing, then the RK update
   const T* cur = lam_np1;
-  if (cool) {
+  // without gravity, exact cooling and forcing reverse in one pass
+  const bool cool_force = cool && force && !grav && !c->cool_table();
+  if (cool_force) {
+    MH_HIP(c, adj_cool_force_vjp<T>(Uc, (T)(g.gamma - 1.0), (T)dt, a.cool, at(A.rows),
+                                    a.ou_tab[0], a.ou_R, geom, cur, lamA, c->stream));
+    cur = lamA;
+  } else if (cool) {
     if (c->cool_table())
       MH_HIP(c, launch_cool_table_vjp<T>(Uc, N, (T)g.gamma, (T)dt, c->cool_table_args<T>(), cur,
                                          lamA, c->stream));
@@ -992,7 +997,7 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
                                  aclk, c->stream));
     cur = lamB;
   }
-  if (force) {
+  if (force && !cool_force) {
     T* dst = cur == lamA ? lamB : lamA;
     MH_HIP(c, adj_force_kick_vjp<T>(at(A.rows), a.ou_tab[0], a.ou_R, geom, (T)dt, cur, dst,
                                     c->stream));

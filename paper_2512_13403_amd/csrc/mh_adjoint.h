@@ -36,14 +36,16 @@ template <typename T>
 hipError_t adj_flux_corr_vjp(const T* v, const StageGeom& g, const double* h, double weight,
                              T* grad, hipStream_t s);
 template <typename T>
-hipError_t adj_force_kick(T* U, const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
-                          hipStream_t s);
-template <typename T>
 hipError_t adj_force_kick_vjp(const T* rows, const T* tabx, int R, const StageGeom& g, T dt,
                               const T* lin, T* lout, hipStream_t s);
 template <typename T>
 hipError_t adj_cool_vjp(const T* U, long long N, T gm1, T dt, const CoolParams<T>& c, const T* lin,
                         T* lout, hipStream_t s);
+// exact-cooling reverse followed by the forcing-kick reverse, one pass
+template <typename T>
+hipError_t adj_cool_force_vjp(const T* U, T gm1, T dt, const CoolParams<T>& c, const T* rows,
+                              const T* tabx, int R, const StageGeom& g, const T* lin, T* lout,
+                              hipStream_t s);
 template <typename T>
 hipError_t adj_gravity_vjp(const AdjointBuffers<T>& B, MGLayout& mgL, char* mgws,
                            const mh_physics_desc& p, const T* Ub, const T* phi, int n, double h,
