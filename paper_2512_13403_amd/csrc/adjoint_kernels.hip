@@ -541,14 +541,16 @@ __global__ __launch_bounds__(256) void k_face_vjp_rt(const T* __restrict__ U,
 // W^L = W_i + minmod_i/2 and W^R = W_{i+1} - minmod_{i+1}/2
 template <typename T>
 __device__ __forceinline__ T slot_contrib(int k, int fl, int s, T WLb, T WRb) {
+  // selection codes of the two slopes (1: forward difference, 2: backward,
+  // 0: none); every term is a signed half of WLb or WRb or zero, so selects
+  // give the same sums as multiplying by the 0/1 indicators
   const int s0 = (fl >> (2 * s)) & 3, s1 = (fl >> (10 + 2 * s)) & 3;
-  const T a0 = s0 == 1 ? T(1) : T(0), b0 = s0 == 2 ? T(1) : T(0);
-  const T a1 = s1 == 1 ? T(1) : T(0), b1 = s1 == 2 ? T(1) : T(0);
+  const T hl = T(0.5) * WLb, hr = T(0.5) * WRb;
   switch (k) {
-    case 0: return -T(0.5) * b0 * WLb;
-    case 1: return WLb + T(0.5) * (b0 - a0) * WLb + T(0.5) * b1 * WRb;
-    case 2: return T(0.5) * a0 * WLb + WRb - T(0.5) * (b1 - a1) * WRb;
-    default: return -T(0.5) * a1 * WRb;
+    case 0: return s0 == 2 ? -hl : T(0);
+    case 1: return (WLb + (s0 == 2 ? hl : (s0 == 1 ? -hl : T(0)))) + (s1 == 2 ? hr : T(0));
+    case 2: return ((s0 == 1 ? hl : T(0)) + WRb) + (s1 == 2 ? -hr : (s1 == 1 ? hr : T(0)));
+    default: return s1 == 1 ? -hr : T(0);
   }
 }
 

@@ -267,41 +267,57 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
 // dz[cell][co] x[cell + off_tap][ci], on the same 16 x 4 x 4 halo tiles as
 // k_conv.  A persistent workgroup takes every gridDim.x-th block of cells; per
 // block it stages the layer input with its halo and the block's output
-// gradients in LDS.  Per MFMA the reduction runs over 32 cells (16 along x in
-// two rows), dz^T is the A operand (rows: output channels) and the shifted
-// input the B operand (columns: input channels).  The taps are grouped by
-// their (dy, dz) row: wave w takes the rows g = w, w + 4, w + 8 (< 9), each
-// with its three x shifts, so a lane reads the 10 input values of its 8-cell
-// strip once per row and channel tile and forms the three shifted operands
-// from them (the LDS reads, 16-bit, bound the kernel).  Wave 3, which has the
-// fewest rows, also forms the bias gradient (slot 27).  Each workgroup writes
-// its partial [28][COT][32]; k_wgrad_reduce adds them in a fixed order
-// (deterministic, no atomics).
-constexpr int WROWS = 3;  // (dy, dz) rows per wave: ceil(9 / 4)
+// gradients in LDS, both channel-major (each channel's x rows contiguous), so
+// that every MFMA operand of a lane -- 8 consecutive cells of one channel --
+// is one 16-byte LDS read; the next block's data is loaded into registers
+// while the current one is reduced.  Per MFMA the reduction runs over 32
+// cells (16 along x in two rows), dz^T is the A operand (rows: output
+// channels) and the shifted input the B operand (columns: input channels).
+// The taps are grouped by their (dy, dz) row: wave w takes the rows w and
+// w + 4 with their three x shifts, and waves 0-2 one x shift each of row 8
+// (seven taps per wave); a lane reads cells xs .. xs + 9 of its channel (one
+// 16-byte and one 4-byte read) and forms the shifted operands in registers
+// (the shift by one cell is a byte alignment of neighbouring words, the
+// shift by two a choice of words).  Wave 3 forms the bias gradient (slot 27).
+// Each workgroup writes its partial [28][COT][32]; k_wgrad_reduce adds them
+// in a fixed order (deterministic, no atomics).
+constexpr int WXS = 24;                      // x stride of a staged row (18 used), 16-byte aligned
+constexpr int WCS = CHY * CHZ * WXS + 8;     // channel stride of the input tile: 109 x 16 B
+constexpr int WDS = CTX * CTY * CTZ + 8;     // channel stride of the gradients: 33 x 16 B
 
 template <int COT, bool XPACK = false>
 __global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restrict__ dz,
                                                const unsigned short* __restrict__ x, int n,
                                                int nblocks, float* __restrict__ partial) {
   constexpr int CB = CTX * CTY * CTZ;  // cells per block
-  __shared__ u32x4 tile[CNH * 4];
-  __shared__ u32x4 dzt[CB * COT / 8];
-  const unsigned short* tile16 = reinterpret_cast<const unsigned short*>(tile);
-  const unsigned short* dzt16 = reinterpret_cast<const unsigned short*>(dzt);
+  static_assert(CHX % 2 == 0 && CTX % 2 == 0, "cell pairs stay within an x row");
+  __shared__ u32x4 tin[32 * WCS / 8];
+  __shared__ u32x4 dzs[COT * WDS / 8];
+  unsigned short* tin16 = reinterpret_cast<unsigned short*>(tin);
+  unsigned short* dz16 = reinterpret_cast<unsigned short*>(dzs);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, grp = lane >> 4;
   const int ntx = n / CTX, nty = n / CTY, ntz = n / CTZ;
-  // acc[row group][dx + 1][co tile][ci tile] (wave 3 keeps the bias gradient
-  // in acc[2][0], its third row group being empty)
-  f32x4 acc[WROWS][3][COT / 16][2];
+  // acc[row][dx + 1][co tile][ci tile] for the wave's rows g = wave and
+  // wave + 4; acc8: waves 0-2 the tap (dy, dz) row 8, dx = wave - 1 (the
+  // taps split evenly, seven per wave), wave 3 the bias gradient
+  f32x4 acc[2][3][COT / 16][2], acc8[COT / 16][2];
 #pragma unroll
-  for (int gg = 0; gg < WROWS; ++gg)
+  for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int mt = 0; mt < COT / 16; ++mt)
         acc[gg][d][mt][0] = acc[gg][d][mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+#pragma unroll
+  for (int mt = 0; mt < COT / 16; ++mt) acc8[mt][0] = acc8[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // The next block's tile and gradients are loaded into registers while the
+  // current block is reduced (the loads of a block are issued before the
+  // MFMA loop of the previous one), then transposed into LDS.
+  constexpr int NIN = ((CNH / 2) * 4 + 255) / 256;       // input items per thread
+  constexpr int NDZ = ((CB / 2) * (COT / 8) + 255) / 256;  // gradient items per thread
+  u32x4 rin[NIN][2], rdz[NDZ][2];
+  auto load_block = [&](int blk) {
     int t = blk;
     const int bx = t % ntx;
     t /= ntx;
@@ -311,26 +327,68 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restri
     const long long b = t / ntz;
     const int x0 = bx * CTX, y0 = by * CTY, z0 = bz * CTZ;
     const long long base = b * n * n * (long long)n;
-    for (int i = threadIdx.x; i < CNH * 4; i += 256) {
-      const int h = i >> 2, c = i & 3;
-      const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
-      const long long src = base +
-                            ((long long)wrap(z0 - 1 + hz, n) * n + wrap(y0 - 1 + hy, n)) * n +
-                            wrap(x0 - 1 + hx, n);
-      u32x4 v;
-      __builtin_memcpy(&v, x + src * 32 + c * 8, 16);
-      tile[cslot(h, hx, c)] = v;
+    // the halo tile: two cells of one x row and 8 channels per item
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < (CNH / 2) * 4) {
+        const int hp = i % (CNH / 2), c = i / (CNH / 2);
+        const int h = 2 * hp;
+        const int hx = h % CHX, hr = h / CHX;  // hr = hz * CHY + hy
+        const int hy = hr % CHY, hz = hr / CHY;
+        const long long rowc =
+            base + ((long long)wrap(z0 - 1 + hz, n) * n + wrap(y0 - 1 + hy, n)) * n;
+        __builtin_memcpy(&rin[k][0], x + (rowc + wrap(x0 - 1 + hx, n)) * 32 + c * 8, 16);
+        __builtin_memcpy(&rin[k][1], x + (rowc + wrap(x0 + hx, n)) * 32 + c * 8, 16);
+      }
     }
-    for (int i = threadIdx.x; i < CB * COT / 8; i += 256) {
-      const int cl = i / (COT / 8), c = i % (COT / 8);
-      const int r = cl / CTX;
-      const long long cell =
-          base + ((long long)(z0 + r / CTY) * n + (y0 + r % CTY)) * n + x0 + cl % CTX;
-      u32x4 v;
-      __builtin_memcpy(&v, dz + cell * COT + c * 8, 16);
-      dzt[i] = v;
+    // the block's output gradients: two cells and 8 channels per item
+#pragma unroll
+    for (int k = 0; k < NDZ; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < (CB / 2) * (COT / 8)) {
+        const int pr = i % (CB / 2), c = i / (CB / 2);
+        const int cl = 2 * pr, r = cl / CTX;
+        const long long cell =
+            base + ((long long)(z0 + r / CTY) * n + (y0 + r % CTY)) * n + x0 + cl % CTX;
+        __builtin_memcpy(&rdz[k][0], dz + cell * COT + c * 8, 16);
+        __builtin_memcpy(&rdz[k][1], dz + (cell + 1) * COT + c * 8, 16);
+      }
+    }
+  };
+  // two cells' 8 channels as 8 32-bit words (cell pair per channel) at dst,
+  // one word per `stride` 16-bit elements
+  auto put_pair = [](unsigned int* dst, int stride, const u32x4& v0, const u32x4& v1) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const unsigned int lo = j & 1 ? v0[j >> 1] >> 16 : v0[j >> 1] & 0xffffu;
+      const unsigned int hi = j & 1 ? v1[j >> 1] >> 16 : v1[j >> 1] & 0xffffu;
+      dst[j * (stride / 2)] = lo | (hi << 16);
+    }
+  };
+  if (blockIdx.x < nblocks) load_block(blockIdx.x);
+  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < (CNH / 2) * 4) {
+        const int hp = i % (CNH / 2), c = i / (CNH / 2);
+        const int h = 2 * hp;
+        put_pair(reinterpret_cast<unsigned int*>(tin16 + (c * 8) * WCS + (h / CHX) * WXS + h % CHX),
+                 WCS, rin[k][0], rin[k][1]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NDZ; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < (CB / 2) * (COT / 8)) {
+        const int pr = i % (CB / 2), c = i / (CB / 2);
+        put_pair(reinterpret_cast<unsigned int*>(dz16 + (c * 8) * WDS + 2 * pr), WDS, rdz[k][0],
+                 rdz[k][1]);
+      }
     }
     __syncthreads();
+    if (blk + (int)gridDim.x < nblocks) load_block(blk + gridDim.x);
 #pragma unroll 1
     for (int ks = 0; ks < CB / 32; ++ks) {
       // this lane's 8 cells of the 32-cell step: x = xs .. xs + 7 of row r
@@ -338,75 +396,98 @@ __global__ __launch_bounds__(256, 2) void k_wgrad(const unsigned short* __restri
       const int ty = r % CTY, tz = r / CTY;
       bf16x8 a[COT / 16];
 #pragma unroll
-      for (int mt = 0; mt < COT / 16; ++mt) {
-        unsigned short v[8];
+      for (int mt = 0; mt < COT / 16; ++mt)
+        __builtin_memcpy(&a[mt], dz16 + (mt * 16 + row) * WDS + r * CTX + xs, 16);
+      // input channel ci at hx = xs .. xs + 9 of (dy, dz) row g: the strip
+      // for dx = -1, 0, 1, as the operand for shift d
+      auto strip = [&](int g, int ct, u32x4& lo, unsigned int& hi) {
+        const int hrow = (tz + g / 3) * CHY + (ty + g % 3);
+        const unsigned short* src = tin16 + (ct * 16 + row) * WCS + hrow * WXS + xs;
+        __builtin_memcpy(&lo, src, 16);
+        __builtin_memcpy(&hi, src + 8, 4);
+      };
+      auto shifted = [](int d, const u32x4& lo, unsigned int hi) {
+        u32x4 w;
+        if (d == 0) {
+          w = lo;
+        } else if (d == 1) {
+          w[0] = __builtin_amdgcn_alignbyte(lo[1], lo[0], 2);
+          w[1] = __builtin_amdgcn_alignbyte(lo[2], lo[1], 2);
+          w[2] = __builtin_amdgcn_alignbyte(lo[3], lo[2], 2);
+          w[3] = __builtin_amdgcn_alignbyte(hi, lo[3], 2);
+        } else {
+          w[0] = lo[1];
+          w[1] = lo[2];
+          w[2] = lo[3];
+          w[3] = hi;
+        }
+        bf16x8 bv;
+        __builtin_memcpy(&bv, &w, 16);
+        return bv;
+      };
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = dzt16[(r * CTX + xs + j) * COT + mt * 16 + row];
-        __builtin_memcpy(&a[mt], v, 16);
-      }
-#pragma unroll
-      for (int gg = 0; gg < WROWS; ++gg) {
+      for (int gg = 0; gg < 2; ++gg) {
         const int g = wave + 4 * gg;  // (dy, dz) row: dy = g % 3 - 1, dz = g / 3 - 1
-        if (g < 9) {
-          const int hrow = ((tz + 1 + g / 3 - 1) * CHY + (ty + 1 + g % 3 - 1)) * CHX;
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            const int ci = ct * 16 + row;
-            // input channel ci at hx = xs .. xs + 9: the strip for dx = -1, 0, 1
-            unsigned short v[10];
+        for (int ct = 0; ct < 2; ++ct) {
+          u32x4 lo;
+          unsigned int hi;
+          strip(g, ct, lo, hi);
 #pragma unroll
-            for (int m = 0; m < 10; ++m) {
-              const int hx = xs + m;
-              v[m] = tile16[cslot(hrow + hx, hx, ci >> 3) * 8 + (ci & 7)];
-            }
+          for (int d = XPACK ? 1 : 0; d < (XPACK ? 2 : 3); ++d) {
+            const bf16x8 bv = shifted(d, lo, hi);
 #pragma unroll
-            for (int d = XPACK ? 1 : 0; d < (XPACK ? 2 : 3); ++d) {
-              bf16x8 bv;
-              __builtin_memcpy(&bv, v + d, 16);
-#pragma unroll
-              for (int mt = 0; mt < COT / 16; ++mt)
-                acc[gg][d][mt][ct] =
-                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc[gg][d][mt][ct], 0, 0, 0);
-            }
+            for (int mt = 0; mt < COT / 16; ++mt)
+              acc[gg][d][mt][ct] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc[gg][d][mt][ct], 0, 0, 0);
           }
-        } else if (g == 11) {
-          // wave 3's empty third row: the bias gradient, sum over cells of dz,
-          // as one more product with a B operand of ones (column 0 is kept)
-          bf16x8 ones;
-          const unsigned short one[8] = {0x3F80, 0x3F80, 0x3F80, 0x3F80,
-                                         0x3F80, 0x3F80, 0x3F80, 0x3F80};
-          __builtin_memcpy(&ones, one, 16);
+        }
+      }
+      if (wave < 3 && (!XPACK || wave == 1)) {
+        // row 8 at the x shift dx = wave - 1 (a packed input has only dx = 0)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          u32x4 lo;
+          unsigned int hi;
+          strip(8, ct, lo, hi);
+          const bf16x8 bv = wave == 0 ? shifted(0, lo, hi)
+                                      : (wave == 1 ? shifted(1, lo, hi) : shifted(2, lo, hi));
 #pragma unroll
           for (int mt = 0; mt < COT / 16; ++mt)
-            acc[gg][0][mt][0] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], ones, acc[gg][0][mt][0], 0, 0, 0);
+            acc8[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc8[mt][ct], 0, 0, 0);
         }
+      } else if (wave == 3) {
+        // the bias gradient, sum over cells of dz, as one more product with a
+        // B operand of ones (column 0 is kept)
+        bf16x8 ones;
+        const unsigned short one[8] = {0x3F80, 0x3F80, 0x3F80, 0x3F80,
+                                       0x3F80, 0x3F80, 0x3F80, 0x3F80};
+        __builtin_memcpy(&ones, one, 16);
+#pragma unroll
+        for (int mt = 0; mt < COT / 16; ++mt)
+          acc8[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], ones, acc8[mt][0], 0, 0, 0);
       }
     }
     __syncthreads();
   }
+  auto put = [&](int tap, const f32x4 (&ac)[COT / 16][2]) {
 #pragma unroll
-  for (int gg = 0; gg < WROWS; ++gg) {
-    const int g = wave + 4 * gg;
-    if (g < 9 || g == 11) {
+    for (int mt = 0; mt < COT / 16; ++mt)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int tap = g < 9 ? 3 * g + d : 27;
-        if (g == 11 && d > 0) continue;
-        if (XPACK && g < 9 && d != 1) continue;  // packed input: only the x shift 0
+      for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-        for (int mt = 0; mt < COT / 16; ++mt)
+        for (int q = 0; q < 4; ++q) {
+          const int co = mt * 16 + 4 * grp + q, ci = ct * 16 + row;
+          partial[(((long long)blockIdx.x * 28 + tap) * COT + co) * 32 + ci] = ac[mt][ct][q];
+        }
+  };
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct)
+  for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int co = mt * 16 + 4 * grp + q, ci = ct * 16 + row;
-              partial[(((long long)blockIdx.x * 28 + tap) * COT + co) * 32 + ci] =
-                  acc[gg][d][mt][ct][q];
-            }
-      }
-    }
-  }
+    for (int d = 0; d < 3; ++d)
+      if (!XPACK || d == 1) put(3 * (wave + 4 * gg) + d, acc[gg][d]);  // packed: dx = 0 only
+  if (wave == 3) put(27, acc8);
+  else if (!XPACK || wave == 1) put(24 + wave, acc8);
 }
 
 // gtheta[off + (co * ci_real + ci) * 27 + tap] += sum of the nwg partials
