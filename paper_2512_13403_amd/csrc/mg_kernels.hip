@@ -132,8 +132,14 @@ __global__ __launch_bounds__(256) void k_residual(int n, T ih2, const T* __restr
   r[q] = F[q] - (nb6(phi, n, i, j, k) - T(6) * phi[q]) * ih2;
 }
 
+// restriction of the residual, F_c = average over the 8 children of
+// F - A phi (the arithmetic of k_residual, summed in child order): each
+// coarse cell forms its children's residuals in registers, so the fine
+// residual is never stored
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(int nc, const T* __restrict__ rf, T* __restrict__ rc) {
+__global__ __launch_bounds__(256) void k_residual_restrict(int nc, T ih2, const T* __restrict__ phi,
+                                                           const T* __restrict__ F,
+                                                           T* __restrict__ rc) {
   const long long Nc = (long long)nc * nc * nc;
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   if (q >= Nc) return;
@@ -143,8 +149,11 @@ __global__ __launch_bounds__(256) void k_restrict(int nc, const T* __restrict__ 
   T s = T(0);
   for (int c = 0; c < 2; ++c)
     for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < 2; ++a)
-        s += rf[(long long)(2 * K + c) * nf2 + (long long)(2 * J + b) * nf + (2 * I + a)];
+      for (int a = 0; a < 2; ++a) {
+        const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+        const long long f = (long long)k * nf2 + (long long)j * nf + i;
+        s += F[f] - (nb6(phi, nf, i, j, k) - T(6) * phi[f]) * ih2;
+      }
   rc[q] = T(0.125) * s;
 }
 
@@ -265,6 +274,33 @@ __device__ void tail_sweeps(T* pa, T* pb, const T* ff, int o, int n, T h2, int s
   }
 }
 
+// The same sweeps on a level of at most 64 cells (the coarsest level): one
+// wave, a cell per lane, so no workgroup barrier is needed between sweeps
+// (a wave's LDS accesses complete in program order; the fences only keep the
+// compiler from moving them).  Same arithmetic as tail_sweeps.
+template <typename T>
+__device__ void tail_sweeps_wave(T* pa, T* pb, const T* ff, int o, int n, T h2, int sweeps,
+                                 int& cur) {
+  const int N = n * n * n;
+  const T w = T(2) / T(3);
+  if (threadIdx.x < 64) {
+    const int q = threadIdx.x;
+    const int i = q % n, j = (q / n) % n, k = q / (n * n);
+    int c = cur;
+    for (int it = 0; it < sweeps; ++it) {
+      const T* src = (c ? pb : pa) + o;
+      T* dst = (c ? pa : pb) + o;
+      if (q < N) dst[q] = (T(1) - w) * src[q] + (w / T(6)) * (nb6(src, n, i, j, k) - h2 * ff[o + q]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      c ^= 1;
+    }
+  }
+  __syncthreads();
+  cur ^= sweeps & 1;
+}
+
 template <typename T>
 __device__ void tail_rbgs(T* pa, T* pb, const T* ff, int o, int n, T h2, int sweeps, int cur) {
   const int N = n * n * n;
@@ -309,7 +345,8 @@ __global__ __launch_bounds__(MG_TAIL_THREADS) void k_mgcycle_tail(TailArgs<T> t)
         for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) pa[o + q] = T(0);
         cur[m] = 0;
         __syncthreads();
-        tail_sweeps(pa, pb, ff, o, n, t.h2[m], t.csweeps, cur[m]);
+        if (N <= 64) tail_sweeps_wave(pa, pb, ff, o, n, t.h2[m], t.csweeps, cur[m]);
+        else tail_sweeps(pa, pb, ff, o, n, t.h2[m], t.csweeps, cur[m]);
         T* phi = (cur[m] ? pb : pa) + o;
         double s = 0.0;
         for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) s += (double)phi[q];
@@ -527,11 +564,10 @@ hipError_t level_cycle(char* ws, MGLayout& L, const mh_physics_desc& p, int l, i
   MGLevel& lv = L.lev[l];
   const long long N = (long long)lv.n * lv.n * lv.n;
   smooth_level<T>(ws, lv, p.mg_pre, rbgs, cur[l], s);
-  hipLaunchKernelGGL((k_residual<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, (T)(1.0 / (lv.h * lv.h)),
-                     P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F), P<T>(ws, lv.r));
   MGLevel& cv = L.lev[l + 1];
   const long long Nc = (long long)cv.n * cv.n * cv.n;
-  hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(Nc)), dim3(256), 0, s, cv.n, P<T>(ws, lv.r),
+  hipLaunchKernelGGL((k_residual_restrict<T>), dim3(nblk(Nc)), dim3(256), 0, s, cv.n,
+                     (T)(1.0 / (lv.h * lv.h)), P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F),
                      P<T>(ws, cv.F));
   hipError_t e = remove_mean(P<T>(ws, cv.F), Nc, partial, mean_slot, s);
   if (e != hipSuccess) return e;
