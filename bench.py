@@ -180,10 +180,12 @@ def adjoint_probe(n=256, reps=10):
           f"forward step {1e3 * (t3 - t2) / reps:.3f} ms", flush=True)
 
 
-def stage_probe(n=512, steps=20):
+def stage_probe(n=512, steps=20, extra_schemes=False):
     """Short runs of the 512^3 fp32 step in configurations that differ by one
     phase of the method (slopes off, each source on or off, the van Leer
-    limiter), for per-kernel instruction counters: one text line each."""
+    limiter; with extra_schemes also MC, superbee, HLL and Rusanov), timed
+    side by side and for per-kernel instruction counters: one text line
+    each."""
     import torch
 
     import paper_2512_13403_amd as mh
@@ -191,15 +193,22 @@ def stage_probe(n=512, steps=20):
     base = dict(cool=(0.3, 1e-2, 1e-3, 1e-4), ou_seed=0, ou_tau=0.5, ou_arms=1.0, ou_zeta=1.0,
                 ou_kmin=1.0, ou_kmax=2.0)
     F, C = mh.SRC_FORCING, mh.SRC_COOLING
-    cases = (("minmod, forcing + cooling", mh.LIM_MINMOD, F | C),
-             ("first order, forcing + cooling", mh.LIM_NONE, F | C),
-             ("minmod, no sources", mh.LIM_MINMOD, 0),
-             ("minmod, forcing", mh.LIM_MINMOD, F),
-             ("minmod, cooling", mh.LIM_MINMOD, C),
-             ("van Leer, forcing + cooling", mh.LIM_VANLEER, F | C))
-    for name, lim, flags in cases:
+    H = mh.RS_HLLC
+    cases = (("minmod, forcing + cooling", mh.LIM_MINMOD, H, F | C),
+             ("first order, forcing + cooling", mh.LIM_NONE, H, F | C),
+             ("minmod, no sources", mh.LIM_MINMOD, H, 0),
+             ("minmod, forcing", mh.LIM_MINMOD, H, F),
+             ("minmod, cooling", mh.LIM_MINMOD, H, C),
+             ("van Leer, forcing + cooling", mh.LIM_VANLEER, H, F | C))
+    if extra_schemes:
+        # the kernels that take the limiter and the solver at run time
+        cases += (("MC + HLLC, forcing + cooling", mh.LIM_MC, H, F | C),
+                  ("superbee + HLLC, forcing + cooling", mh.LIM_SUPERBEE, H, F | C),
+                  ("minmod + HLL, forcing + cooling", mh.LIM_MINMOD, mh.RS_HLL, F | C),
+                  ("minmod + Rusanov, forcing + cooling", mh.LIM_MINMOD, mh.RS_RUSANOV, F | C))
+    for name, lim, rs, flags in cases:
         s = mh.Solver(mh.grid_desc((n,) * 3, (1.0 / n,) * 3, dtype="f32", gamma=GAMMA, cfl=0.4,
-                                   limiter=lim), mh.physics_desc(flags=flags, **base))
+                                   limiter=lim, riemann=rs), mh.physics_desc(flags=flags, **base))
         s.set_state(rest_state_device(n, "f32"))
         s.step(1, 0.0)
         s.set_timing(True)
@@ -474,6 +483,9 @@ def main():
                          "text line each")
     ap.add_argument("--probe-steps", type=int, default=20,
                     help="timed steps per configuration of --stage-probe")
+    ap.add_argument("--probe-schemes", action="store_true",
+                    help="--stage-probe also times MC, superbee, HLL and Rusanov (the "
+                         "run-time scheme kernels)")
     ap.add_argument("--corrector-probe", action="store_true",
                     help="instead: corrector forward passes and training steps at 4 x 64^3, "
                          "one text line")
@@ -508,7 +520,7 @@ def main():
     if args.c4_probe:
         return c4_probe()
     if args.stage_probe:
-        return stage_probe(steps=args.probe_steps)
+        return stage_probe(steps=args.probe_steps, extra_schemes=args.probe_schemes)
     if args.corrector_probe:
         return corrector_probe()
 

@@ -344,7 +344,9 @@ mh_status mh_corr_get_grad(mh_corr *c, float *grad, int where);
 /* Copies an activation of the last forward pass: 0 x (bf16, [cells][32]:
  * channel c < 5 holds hi = bf16(x_c), channel 5 + c holds bf16(x_c - hi)),
  * 1 z1 (fp32, [cells][32]), 2 h1 (bf16), 3 z2 (fp32), 4 h2 (bf16),
- * 5 y (fp32, [cells][16]); or a gradient of the last reverse pass
+ * 5 y (fp32, [cells][16]; stored by the training forward only: mh_corr_apply
+ * and mh_step_corrected write the residual update from the last layer's
+ * epilogue and leave y as it was); or a gradient of the last reverse pass
  * (mh_corr_backward, mh_corr_loss_grad): 6 dY = bf16(scale dL/dU')
  * (bf16, [cells][16], channels >= 5 zero), 7 dZ2 (bf16, [cells][32]),
  * 8 dZ1 (bf16, [cells][32]), 9 the first layer's transposed convolution of

@@ -85,7 +85,17 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return fmaf(z, q.phi, q.Phi);
 }
 
-enum : int { EPI_GELU = 0, EPI_LINEAR = 1, EPI_GELU_BWD = 2, EPI_RAW = 3 };
+enum : int { EPI_GELU = 0, EPI_LINEAR = 1, EPI_GELU_BWD = 2, EPI_RAW = 3, EPI_RESIDUAL = 4 };
+
+// the last layer's epilogue in inference: out = U + scale * (y + bias) for the
+// five fields of each cell (the residual update, written field-major like U)
+template <typename TU>
+struct ResArgs {
+  const TU* U;
+  TU* out;
+  double scale[5];
+  long long n3;  // cells per sample
+};
 
 // Halo tile of the tiled convolution: 16 cells along x (the MFMA rows) by
 // CTY x CTZ rows in (y, z), with a one-cell periodic halo, staged in LDS.
@@ -107,13 +117,14 @@ __device__ __forceinline__ int cslot(int h, int hx, int c) { return h * 4 + (c ^
 // [NT][COT][32]), loaded once per tap and prefetched CPD taps ahead.  NT = 9
 // for an input whose 32 channels already hold the three x neighbours (the
 // first layer: 3 x 10 input parts): the taps then run over (dy, dz) only.
-template <int COT, int EPI, int NT = 27>
+template <int COT, int EPI, int NT = 27, typename TU = float>
 __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restrict__ in,
                                               const unsigned short* __restrict__ w,
                                               const float* __restrict__ bias, int nbias, int n,
                                               const float* __restrict__ zin,
                                               float* __restrict__ fout,
-                                              unsigned short* __restrict__ hout, int ntiles) {
+                                              unsigned short* __restrict__ hout, int ntiles,
+                                              ResArgs<TU> ra) {
   __shared__ u32x4 tile[CNH * 4];
   constexpr int NLD = (CNH * 4 + 255) / 256;  // 16-byte halo chunks per thread
   const int ntx = n / CTX, nty = n / CTY, ntz = n / CTZ;
@@ -248,6 +259,20 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
 #pragma unroll
           for (int q = 0; q < 4; ++q) y[q] = v[q] + (co + q < nbias ? bias[co + q] : 0.f);
           *(f32x4*)(fout + o) = y;
+        } else if (EPI == EPI_RESIDUAL) {
+          // lanes of channel groups 0 and 1 hold fields 0-3 and 4; the
+          // arithmetic of k_residual
+          const long long b = cell / ra.n3, q = cell - b * ra.n3;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int c = co + k;
+            if (c < 5) {
+              const float y = v[k] + bias[c];
+              const TU d = (TU)(ra.scale[c] * (double)y);
+              const long long f = (b * 5 + c) * ra.n3 + q;
+              ra.out[f] = ra.U[f] + d;
+            }
+          }
         } else if (EPI == EPI_GELU_BWD) {
           const f32x4 zi = *(const f32x4*)(zin + o);
           unsigned short hv[4];
@@ -916,13 +941,23 @@ hipError_t corr_forward(const CorrBuffers& B, const CorrStats& st, int n, int ba
                      B.x0);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU, 9>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.x0, B.w1,
                      B.theta + CORR_OFF_B1, 32, n, (const float*)nullptr,
-                     store_z ? B.z1 : (float*)nullptr, B.h1, (int)conv_blocks);
+                     store_z ? B.z1 : (float*)nullptr, B.h1, (int)conv_blocks, ResArgs<float>{});
   hipLaunchKernelGGL((k_conv<32, EPI_GELU>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.h1, B.w2,
                      B.theta + CORR_OFF_B2, 32, n, (const float*)nullptr,
-                     store_z ? B.z2 : (float*)nullptr, B.h2, (int)conv_blocks);
+                     store_z ? B.z2 : (float*)nullptr, B.h2, (int)conv_blocks, ResArgs<float>{});
+  if (out && add_u && !store_z) {
+    // inference: the residual update in the last layer's epilogue (y is
+    // not stored)
+    ResArgs<T> ra{U, out, {}, (long long)n * n * n};
+    for (int c = 0; c < 5; ++c) ra.scale[c] = st.scale[c];
+    hipLaunchKernelGGL((k_conv<16, EPI_RESIDUAL, 27, T>), dim3(conv_wgs(conv_blocks)), dim3(256), 0,
+                       s, B.h2, B.w3, B.theta + CORR_OFF_B3, 5, n, (const float*)nullptr,
+                       (float*)nullptr, (unsigned short*)nullptr, (int)conv_blocks, ra);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_conv<16, EPI_LINEAR>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.h2, B.w3,
                      B.theta + CORR_OFF_B3, 5, n, (const float*)nullptr, B.y,
-                     (unsigned short*)nullptr, (int)conv_blocks);
+                     (unsigned short*)nullptr, (int)conv_blocks, ResArgs<float>{});
   if (out)
     hipLaunchKernelGGL((k_residual<T>), dim3(blocks(cells, 256)), dim3(256), 0, s, U, B.y, n, cells,
                        st, out, (int)add_u);
@@ -964,13 +999,13 @@ hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int b
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 16 * 32, 64)), dim3(256), 0, s, B.wpart,
                      16, nwg, 5, 32, 0, 0, B.grad + CORR_OFF_W3, B.grad + CORR_OFF_B3);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dy32, B.w3t,
-                     (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2, (int)conv_blocks);
+                     (const float*)nullptr, 0, n, B.z2, (float*)nullptr, B.dz2, (int)conv_blocks, ResArgs<float>{});
   // layer 2
   hipLaunchKernelGGL((k_wgrad<32>), dim3(nwg), dim3(256), 0, s, B.dz2, B.h1, n, nblk, B.wpart);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(28 * 32 * 32, 64)), dim3(256), 0, s,
                      B.wpart, 32, nwg, 32, 32, 0, 0, B.grad + CORR_OFF_W2, B.grad + CORR_OFF_B2);
   hipLaunchKernelGGL((k_conv<32, EPI_GELU_BWD>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz2, B.w2t,
-                     (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1, (int)conv_blocks);
+                     (const float*)nullptr, 0, n, B.z1, (float*)nullptr, B.dz1, (int)conv_blocks, ResArgs<float>{});
   // layer 1
   hipLaunchKernelGGL((k_wgrad<32, true>), dim3(nwg), dim3(256), 0, s, B.dz1, B.x0, n, nblk,
                      B.wpart);
@@ -979,7 +1014,7 @@ hipError_t corr_backward(const CorrBuffers& B, const CorrStats& st, int n, int b
   if (gU) {
     hipLaunchKernelGGL((k_conv<16, EPI_RAW>), dim3(conv_wgs(conv_blocks)), dim3(256), 0, s, B.dz1, B.w1t,
                        (const float*)nullptr, 0, n, (const float*)nullptr, B.gx,
-                       (unsigned short*)nullptr, (int)conv_blocks);
+                       (unsigned short*)nullptr, (int)conv_blocks, ResArgs<float>{});
     hipLaunchKernelGGL((k_input_grad<T>), dim3(lb), dim3(256), 0, s, B.gx, n, cells, st, gU);
   }
   return hipGetLastError();

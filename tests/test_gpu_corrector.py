@@ -126,9 +126,9 @@ def test_forward_layers(dtype, n, batch):
     Ud = torch_dev(U, dtype)
     out, nfl, fb = c.apply(Ud)
     out = out.cpu().numpy()
-    h1_apply, y_apply = c.activation(2), c.activation(5)
-    c.loss_grad(Ud, Ud)  # the training forward also stores z1 and z2
-    assert np.array_equal(c.activation(2), h1_apply) and np.array_equal(c.activation(5), y_apply)
+    h1_apply = c.activation(2)
+    c.loss_grad(Ud, Ud)  # the training forward also stores z1, z2 and y
+    assert np.array_equal(c.activation(2), h1_apply)
     p = {k: oc.bf16_round(v) if k.startswith("W") else v for k, v in oc.unpack(th).items()}
     # network input, both bf16 parts: bitwise
     x0 = c.activation(0)
@@ -155,6 +155,17 @@ def test_forward_layers(dtype, n, batch):
     assert nfl == nref == 0 and not fb and not bad
     tol = 1e-15 if dtype == "f64" else 2e-7
     assert rel_inf(out, ref) < tol
+    # inference writes U + scale y from the last layer's epilogue, from the
+    # same y as the training forward: in fp32 bitwise the residual kernel's
+    # rounding (the product in fp64, rounded to fp32, then the sum); in fp64
+    # the product and the sum may fuse into one rounding
+    td = np.float64 if dtype == "f64" else np.float32
+    d = (scale.reshape(1, 5, 1, 1, 1) * np.moveaxis(to_oracle(y[:, :5], batch, n), -1, 1)
+         .astype(np.float64)).astype(td)
+    if dtype == "f32":
+        assert np.array_equal(out, U.astype(td) + d)
+    else:
+        assert np.all(np.abs(out - (U + d)) <= 2.3e-16 * (np.abs(U) + np.abs(d)))
     # end to end against the oracle's own forward: the correction agrees in norm
     oref, _ = oc.forward(U, th, mean, std, scale)
     dc, dr = out - U, oref - U
@@ -366,6 +377,8 @@ def test_floor_and_fallback(dtype):
     # no fallback: the floored state against the oracle floor on the GPU's y
     c, th, mean, std, _ = make(n, batch, dtype, U, scale=scale, fallback_frac=1.0)
     out, nfl, fb = c.apply(torch_dev(U, dtype))
+    # y from the training forward (inference does not store it)
+    c.loss_grad(torch_dev(U, dtype), torch_dev(U, dtype))
     y = c.activation(5)[:, :5]
     Uc = U + np.moveaxis(to_oracle(y, batch, n), -1, 1) * scale.reshape(1, 5, 1, 1, 1)
     Uc = as_input(Uc, dtype)
@@ -427,6 +440,7 @@ def test_flux_mode_output_and_gradients(dtype):
     cs = mh.Corrector(ds)
     cs.set_params(th)
     outs, _, _ = cs.apply(Ud)
+    cs.loss_grad(Ud, Ud)  # the training forward stores y (inference does not)
     assert np.array_equal(cs.activation(5), c.activation(5))
     tol = 1e-15 if dtype == "f64" else 2e-7
     assert rel_inf(outs.cpu().numpy(), U + out.cpu().numpy()) < tol
