@@ -146,7 +146,8 @@ def corrector_study():
 
 def adjoint_probe(n=256, reps=10):
     """Adjoint steps of the hydro step with forcing and cooling (no gravity)
-    from a smooth random state, against forward steps of the same solver."""
+    from a smooth random state, recomputing the step's stages and from the
+    stages kept by mh_step_keep, against forward steps of the same solver."""
     import torch
 
     import paper_2512_13403_amd as mh
@@ -170,6 +171,20 @@ def adjoint_probe(n=256, reps=10):
         s.adjoint_step(Un, dt, k0, lam, ou_ahat=ahat)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same adjoint step from the stages kept by the forward step
+    s.set_state(Un)
+    s.set_clock(0.0, k0)
+    s.set_ou_state(ahat)
+    U1, Ub = s.new_state_tensor(), s.new_state_tensor()
+    s.step_keep(dt, U1, Ub)
+    for _ in range(2):
+        s.adjoint_step(Un, dt, k0, lam, ou_ahat=ahat, kept=(U1, Ub))
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(reps):
+        s.adjoint_step(Un, dt, k0, lam, ou_ahat=ahat, kept=(U1, Ub))
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
     s.set_state(Un)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -177,6 +192,7 @@ def adjoint_probe(n=256, reps=10):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     print(f"adjoint probe {n}^3 f32: adjoint step {1e3 * (t1 - t0) / reps:.3f} ms, "
+          f"from kept stages {1e3 * (t5 - t4) / reps:.3f} ms, "
           f"forward step {1e3 * (t3 - t2) / reps:.3f} ms", flush=True)
 
 

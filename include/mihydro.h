@@ -252,6 +252,30 @@ mh_status mh_adjoint_step(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace
                           const void *U_n, double dt, int64_t step, const double *ou_ahat,
                           const void *phi_n, const void *lam_np1, void *lam_n);
 
+/* Store instead of recompute (paper Sec. 2.3: a checkpointed rollout trades
+ * memory for recomputation).  mh_step_keep advances ONE SSP-RK2 step like
+ * mh_step(ctx, 1, dt, +INFINITY, dt_out, NULL) and also keeps, in device
+ * memory the caller owns ([5][nz][ny][nx] each, the state's dtype, distinct),
+ *   U1_out  the first stage U^n + dt L(U^n),
+ *   Ub_out  the state after the last stage and its forcing kick, before
+ *           gravity and cooling;
+ * the state it leaves is bitwise the one mh_step leaves (the cooling and the
+ * CFL/health epilogue run from Ub in a second kernel with the fused stage's
+ * arithmetic; with gravity or tabulated cooling Ub is copied to the state
+ * and those kernels follow as usual).  Enqueued on the context stream;
+ * dt_out (one double, optional) synchronises.
+ * mh_adjoint_step_kept is mh_adjoint_step for that step given U1 and Ub: it
+ * skips recomputing the two stages (it still solves the adjoint potential
+ * with gravity); the result is bitwise mh_adjoint_step's.
+ * Errors: MH_E_INVALID (null or equal buffers, an integrator other than
+ * MH_RK_SSP2, ou_ahat missing with forcing on, bad dt or step),
+ * MH_E_WORKSPACE, MH_E_DEVICE. */
+mh_status mh_step_keep(mh_ctx *ctx, double dt, void *U1_out, void *Ub_out, double *dt_out);
+mh_status mh_adjoint_step_kept(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace_bytes,
+                               const void *U_n, const void *U1, const void *Ub, double dt,
+                               int64_t step, const double *ou_ahat, const void *phi_n,
+                               const void *lam_np1, void *lam_n);
+
 /* ------------------------------------------------------------------------ */
 /* Learned state corrector (solver in the loop, paper Sec. 8)               */
 /* ------------------------------------------------------------------------ */

@@ -46,6 +46,7 @@ EXPORTED = [
     "mh_corr_destroy", "mh_block_average", "mh_corr_zero_grad", "mh_corr_backward",
     "mh_corr_adam_step", "mh_corr_get_grad", "mh_set_graphs", "mh_fft3_query_workspace",
     "mh_fft3", "mh_set_flux_correction", "mh_fft3_noalloc", "mh_step_corrected", "mh_adam",
+    "mh_step_keep", "mh_adjoint_step_kept",
 ]
 TIME_STAGE1, TIME_STAGE2, TIME_PROLOGUE, TIME_OTHER = range(4)
 
@@ -130,6 +131,9 @@ def load_library():
             "mh_query_adjoint_workspace": [vp, ctypes.POINTER(ctypes.c_size_t)],
             "mh_adjoint_step": [vp, vp, ctypes.c_size_t, vp, ctypes.c_double, ctypes.c_int64, dp,
                                 vp, vp, vp],
+            "mh_step_keep": [vp, ctypes.c_double, vp, vp, dp],
+            "mh_adjoint_step_kept": [vp, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_double,
+                                     ctypes.c_int64, dp, vp, vp, vp],
             "mh_corr_query_workspace": [ctypes.POINTER(CorrDesc), ctypes.POINTER(ctypes.c_size_t)],
             "mh_corr_init": [ctypes.POINTER(CorrDesc), vp, ctypes.c_size_t, vp,
                              ctypes.POINTER(vp)],
@@ -299,6 +303,10 @@ class Solver:
                     "mh_get_state")
         return out
 
+    def new_state_tensor(self):
+        """An uninitialised CUDA tensor of the state's shape and dtype."""
+        return self._torch.empty((5,) + self.shape, dtype=self.torch_dtype, device=self.device)
+
     def get_state_device(self):
         torch = self._torch
         out = torch.empty((5,) + self.shape, dtype=self.torch_dtype, device=self.device)
@@ -317,6 +325,21 @@ class Solver:
                               None)
         self._check(st, "mh_step")
         return dts[:nsteps] if record else None
+
+    def step_keep(self, dt: float, U1_out, Ub_out, record: bool = False):
+        """One SSP-RK2 step (dt > 0 fixed, else CFL) that also writes its first
+        stage to U1_out and its state after the forcing kick to Ub_out (CUDA
+        tensors of the state's shape and dtype), for adjoint_step(kept=...).
+        With record=True returns the step's dt (synchronises)."""
+        d = np.zeros(1) if record else None
+        U1_out, Ub_out = U1_out.contiguous(), Ub_out.contiguous()
+        self._keep_step = (U1_out, Ub_out)
+        st = self.lib.mh_step_keep(self.ctx, dt, ctypes.c_void_p(U1_out.data_ptr()),
+                                   ctypes.c_void_p(Ub_out.data_ptr()),
+                                   d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if record
+                                   else None)
+        self._check(st, "mh_step_keep")
+        return d if record else None
 
     def run_to(self, t_stop: float, max_steps: int = 1_000_000):
         """Steps under CFL until the clock reaches t_stop; returns the dt list."""
@@ -419,12 +442,14 @@ class Solver:
                     "mh_get_potential")
         return out
 
-    def adjoint_step(self, U_n, dt: float, step: int, lam, ou_ahat=None, phi_n=None, out=None):
+    def adjoint_step(self, U_n, dt: float, step: int, lam, ou_ahat=None, phi_n=None, out=None,
+                     kept=None):
         """lam_n = (dU^{n+1}/dU^n)^T lam for the step from U_n (CUDA tensors of
         the solver's shape and dtype) with fixed dt at global index `step`;
         ou_ahat: OU amplitudes before the step (host), phi_n: potential before
-        the step (CUDA tensor) or None.  Returns lam_n (a new tensor unless
-        `out` is given; `out` may be `lam`)."""
+        the step (CUDA tensor) or None; kept: (U1, Ub) written by step_keep for
+        this step, which spares recomputing the two stages.  Returns lam_n (a
+        new tensor unless `out` is given; `out` may be `lam`)."""
         torch = self._torch
         if getattr(self, "_adj_ws", None) is None:
             n = ctypes.c_size_t(0)
@@ -442,8 +467,18 @@ class Solver:
             # kept alive on self until the next call: the copy is enqueued
             self._keep_ahat = np.ascontiguousarray(ou_ahat, dtype=np.float64)
             ah = self._keep_ahat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        self._keep_adj = (U_n, lam, phi_n)
+        self._keep_adj = (U_n, lam, phi_n, kept)
         ph = ctypes.c_void_p(phi_n.contiguous().data_ptr()) if phi_n is not None else None
+        if kept is not None:
+            U1, Ub = kept
+            st = self.lib.mh_adjoint_step_kept(self.ctx, ctypes.c_void_p(base), self._adj_bytes,
+                                               ctypes.c_void_p(U_n.data_ptr()),
+                                               ctypes.c_void_p(U1.data_ptr()),
+                                               ctypes.c_void_p(Ub.data_ptr()), dt, step, ah, ph,
+                                               ctypes.c_void_p(lam.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()))
+            self._check(st, "mh_adjoint_step_kept")
+            return out
         st = self.lib.mh_adjoint_step(self.ctx, ctypes.c_void_p(base), self._adj_bytes,
                                       ctypes.c_void_p(U_n.data_ptr()), dt, step, ah, ph,
                                       ctypes.c_void_p(lam.data_ptr()),

@@ -427,9 +427,15 @@ static StageArgs<T> base_stage_args(const mh_ctx* c, DevClock* clk, T* ou_rows) 
 
 // dt_sched (device, or null): the steps take their dt from this schedule,
 // entry clk->sched_pos * sched_stride, instead of `dt`
+// keep_u1, keep_ub (device, or null; SSP-RK2 only): the first stage writes
+// its result to keep_u1 instead of the workspace, and the last stage writes
+// its state after the forcing kick to keep_ub, from which the cooling and the
+// CFL / health epilogue (or the gravity and tabulated-cooling kernels) finish
+// the step; the state left behind is bitwise the plain step's
 template <typename T>
 static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, double* dt_out,
-                           const double* dt_sched = nullptr, long long sched_stride = 0) {
+                           const double* dt_sched = nullptr, long long sched_stride = 0,
+                           T* keep_u1 = nullptr, T* keep_ub = nullptr) {
   const mh_grid_desc& g = c->g;
   const mh_physics_desc& p = c->p;
   StageGeom geom{g.n[0], g.n[1], g.n[2], {g.bc[0], g.bc[1], g.bc[2]}};
@@ -478,10 +484,11 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
                                      c->at<T>(c->L.ou_rows), c->stream));
     time_end(c, tk);
     // all stages but the last
+    T* U1s = keep_u1 ? keep_u1 : U1;
     if (g.integrator != MH_RK_EULER) {
       a.uin = U;
       a.un = nullptr;
-      a.uout = U1;
+      a.uout = U1s;
       tk = time_begin(c, MH_TIME_STAGE1);
       MH_HIP(c, launch_stage<T>(1, g.limiter, false, false, a, geom, c->stream));
       time_end(c, tk);
@@ -507,12 +514,26 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
       a.ca = T(0);
       a.cb = T(1);
     } else {
-      a.uin = U1;
+      a.uin = U1s;
       a.un = U;
       a.uout = U;
     }
     // the last stage, with the sources
-    if (grav) {
+    if (keep_ub) {
+      // the state after the forcing kick is kept; cooling and the epilogue
+      // (or the sources kernels after it) finish the step from it
+      StageArgs<T> ak = a;
+      ak.uout = keep_ub;
+      ak.epilogue = 0;
+      tk = time_begin(c, MH_TIME_STAGE2);
+      MH_HIP(c, launch_stage<T>(2, g.limiter, force, false, ak, geom, c->stream));
+      if (grav || table)
+        MH_HIP(c, hipMemcpyAsync(U, keep_ub, 5 * (size_t)c->cells() * sizeof(T),
+                                 hipMemcpyDeviceToDevice, c->stream));
+      else
+        MH_HIP(c, launch_stage2_finish<T>(cool, a, keep_ub, geom, c->stream));
+      time_end(c, tk);
+    } else if (grav) {
       // forcing fused into the last stage; gravity needs the new density
       // everywhere first, then the kick, cooling and CFL run in the sources
       // kernel
@@ -549,6 +570,20 @@ static mh_status step_impl(mh_ctx* c, int32_t nsteps, double dt, double t_stop, 
     }
   }
   return MH_OK;
+}
+
+extern "C" mh_status mh_step_keep(mh_ctx* c, double dt, void* U1_out, void* Ub_out,
+                                  double* dt_out) {
+  if (!c || !U1_out || !Ub_out || U1_out == Ub_out) return MH_E_INVALID;
+  if (std::isnan(dt)) return set_err(c, MH_E_INVALID, "mh_step_keep: NaN dt");
+  if (c->g.integrator != MH_RK_SSP2)
+    return set_err(c, MH_E_INVALID, "mh_step_keep: the kept stages are those of SSP-RK2");
+  mh_status s = c->g.dtype == MH_F64
+                    ? step_impl<double>(c, 1, dt, INFINITY, dt_out, nullptr, 0,
+                                        static_cast<double*>(U1_out), static_cast<double*>(Ub_out))
+                    : step_impl<float>(c, 1, dt, INFINITY, dt_out, nullptr, 0,
+                                       static_cast<float*>(U1_out), static_cast<float*>(Ub_out));
+  return s;
 }
 
 extern "C" mh_status mh_step(mh_ctx* c, int32_t nsteps, double dt, double t_stop,
@@ -884,10 +919,14 @@ extern "C" mh_status mh_query_adjoint_workspace(mh_ctx* c, size_t* bytes) {
   return MH_OK;
 }
 
+// kept_u1, kept_ub (or null): the step's first-stage result and its state
+// after the forcing kick, kept by mh_step_keep; the recomputation of the two
+// stages is skipped
 template <typename T>
 static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, double dt,
                               int64_t step, const double* ou_ahat, const T* phi_n,
-                              const T* lam_np1, T* lam_n) {
+                              const T* lam_np1, T* lam_n, const T* kept_u1 = nullptr,
+                              const T* kept_ub = nullptr) {
   const mh_grid_desc& g = c->g;
   const mh_physics_desc& p = c->p;
   const bool force = (p.flags & MH_SRC_FORCING) != 0;
@@ -934,7 +973,12 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   // forward recomputation: U1 (and U2), Ua (the RK update), Ub (after the
   // forcing kick), Uc (after the gravity kick)
   T* U2 = g.integrator == MH_RK_SSP3 ? at(A.U2) : nullptr;
-  if (g.integrator == MH_RK_EULER) {
+  if (kept_u1) {
+    // the stages kept by the forward step (SSP-RK2): U1 and the state after
+    // the forcing kick, read only
+    U1 = const_cast<T*>(kept_u1);
+    Ua = const_cast<T*>(kept_ub);
+  } else if (g.integrator == MH_RK_EULER) {
     a.uin = Un;
     a.un = Un;
     a.ca = T(0);
@@ -956,11 +1000,13 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
     a.ca = T(1.0 / 3.0);
     a.cb = T(2.0 / 3.0);
   }
-  a.uout = Ua;
   // the last stage applies the forcing kick as the forward step does (the RK
   // update itself is not read again), so Ua is the state after forcing,
   // bitwise; only gravity needs the states before (Ub) and after (Uc) a kick
-  MH_HIP(c, launch_stage<T>(2, g.limiter, force, false, a, geom, c->stream));
+  if (!kept_u1) {
+    a.uout = Ua;
+    MH_HIP(c, launch_stage<T>(2, g.limiter, force, false, a, geom, c->stream));
+  }
   Ub = Ua;
   Uc = Ub;
   if (grav) {
@@ -1060,6 +1106,35 @@ extern "C" mh_status mh_adjoint_step(mh_ctx* c, void* adj_workspace, size_t adj_
                                 (const double*)phi_n, (const double*)lam_np1, (double*)lam_n);
   return adjoint_impl<float>(c, ws, A, (const float*)U_n, dt, step, ou_ahat, (const float*)phi_n,
                              (const float*)lam_np1, (float*)lam_n);
+}
+
+extern "C" mh_status mh_adjoint_step_kept(mh_ctx* c, void* adj_workspace,
+                                          size_t adj_workspace_bytes, const void* U_n,
+                                          const void* U1, const void* Ub, double dt, int64_t step,
+                                          const double* ou_ahat, const void* phi_n,
+                                          const void* lam_np1, void* lam_n) {
+  if (!c) return MH_E_INVALID;
+  if (!U_n || !U1 || !Ub || !lam_np1 || !lam_n)
+    return set_err(c, MH_E_INVALID, "mh_adjoint_step_kept: null state or adjoint pointer");
+  if (c->g.integrator != MH_RK_SSP2)
+    return set_err(c, MH_E_INVALID, "mh_adjoint_step_kept: the kept stages are those of SSP-RK2");
+  if ((c->p.flags & MH_SRC_FORCING) && !ou_ahat)
+    return set_err(c, MH_E_INVALID, "mh_adjoint_step_kept: forcing is on but ou_ahat is NULL");
+  if (!(dt >= 0.0) || step < 0)
+    return set_err(c, MH_E_INVALID, "mh_adjoint_step_kept: bad dt or step");
+  AdjLayout A = make_adj_layout(c->g, c->p);
+  A.mg.graphs = &c->adj_graphs;
+  if (!adj_workspace || adj_workspace_bytes < A.total || ((uintptr_t)adj_workspace % ALIGN) != 0)
+    return set_err(c, MH_E_WORKSPACE,
+                   "mh_adjoint_step_kept: adjoint workspace too small or misaligned");
+  char* ws = (char*)adj_workspace;
+  if (c->g.dtype == MH_F64)
+    return adjoint_impl<double>(c, ws, A, (const double*)U_n, dt, step, ou_ahat,
+                                (const double*)phi_n, (const double*)lam_np1, (double*)lam_n,
+                                (const double*)U1, (const double*)Ub);
+  return adjoint_impl<float>(c, ws, A, (const float*)U_n, dt, step, ou_ahat, (const float*)phi_n,
+                             (const float*)lam_np1, (float*)lam_n, (const float*)U1,
+                             (const float*)Ub);
 }
 
 extern "C" mh_status mh_set_timing(mh_ctx* c, int enable) {

@@ -585,6 +585,59 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
   }
 }
 
+// The end of the last stage for a step that keeps its state after the
+// forcing kick (`ub`, written by k_stage<2> with the cooling and the epilogue
+// left out): the exact cooling and the CFL / health epilogue of k_stage<2>,
+// the same arithmetic from the stored state instead of registers, so the
+// result is bitwise the fused stage's.  One thread per cell.
+template <typename T, bool COOL>
+__global__ __launch_bounds__(256) void k_stage2_finish(const StageArgs<T> a,
+                                                       const T* __restrict__ ub) {
+  __shared__ T sRed[4];
+  const long long N = a.ncell;
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int tid = threadIdx.x;
+  const T gamma = a.gamma, gm1 = a.gm1, gm1inv = a.gm1inv;
+  const T dt = (T)a.clk->dt;
+  T smax = T(0);
+  unsigned nbad = 0;
+  if (q < N) {
+    T un[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) un[f] = ub[f * N + q];
+    const T ir = dev_rcp(un[0]);
+    const T vx = un[1] * ir, vy = un[2] * ir, vz = un[3] * ir;
+    const T ek = (T(0.5) * un[0]) * fmad(vx, vx, fmad(vy, vy, vz * vz));
+    T pn = gm1 * (un[4] - ek);
+    if (COOL) {
+      const T Tn = cool_T(un[0], pn * ir, dt, a.cool);
+      un[4] = fmad(un[0] * Tn, gm1inv, ek);
+      pn = gm1 * (un[4] - ek);
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) a.uout[f * N + q] = un[f];
+    const T cs = sound_speed(gamma * pn, un[0]);
+    const T sp = fmax(fmax((fabs(vx) + cs) * a.ihx, (fabs(vy) + cs) * a.ihy),
+                      (fabs(vz) + cs) * a.ihz);
+    smax = sp;
+    const bool ok = (un[0] > T(0)) && (pn > T(0)) && isfinite(un[1]) && isfinite(un[2]) &&
+                    isfinite(un[3]) && isfinite(un[4]) && isfinite(sp);
+    if (!ok) nbad = 1;
+  }
+  const T m = wave_max(smax);
+  if ((tid & 63) == 0) sRed[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    T bm = sRed[0];
+    for (int i = 1; i < 4; ++i) bm = fmax(bm, sRed[i]);
+    atomicMax(&a.clk->smax, pos_bits(bm));
+  }
+  if (nbad) {
+    atomicAdd(&a.clk->bad_count, 1ull);
+    atomicMin(&a.clk->bad_first, (unsigned long long)q);
+  }
+}
+
 // Forcing row records, once per step.  The OU acceleration
 //   a_c(x, y, z) = sum_m Re(coef_{m,c} X_{n_x}(x) Y_{n_y}(y) Z_{n_z}(z)),
 // coef = 2 * scale * ahat and X_n(x) = exp(2 pi i n (x + 1/2) / n_x) (the
@@ -752,6 +805,16 @@ hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs
 }
 
 template <typename T>
+hipError_t launch_stage2_finish(bool cool, StageArgs<T> a, const T* ub, const StageGeom& g,
+                                hipStream_t s) {
+  fill_geom(a, g);
+  const unsigned blocks = (unsigned)((a.ncell + 255) / 256);
+  if (cool) hipLaunchKernelGGL((k_stage2_finish<T, true>), dim3(blocks), dim3(256), 0, s, a, ub);
+  else hipLaunchKernelGGL((k_stage2_finish<T, false>), dim3(blocks), dim3(256), 0, s, a, ub);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_smax(const T* U, const StageGeom& g, T gamma, const double* ih, DevClock* clk,
                        hipStream_t s) {
   const long long N = (long long)g.nx * g.ny * g.nz;
@@ -777,6 +840,10 @@ template hipError_t launch_stage<float>(int, int, bool, bool, StageArgs<float>, 
                                         hipStream_t);
 template hipError_t launch_stage<double>(int, int, bool, bool, StageArgs<double>, const StageGeom&,
                                          hipStream_t);
+template hipError_t launch_stage2_finish<float>(bool, StageArgs<float>, const float*,
+                                                const StageGeom&, hipStream_t);
+template hipError_t launch_stage2_finish<double>(bool, StageArgs<double>, const double*,
+                                                 const StageGeom&, hipStream_t);
 template hipError_t launch_smax<float>(const float*, const StageGeom&, float, const double*,
                                        DevClock*, hipStream_t);
 template hipError_t launch_smax<double>(const double*, const StageGeom&, double, const double*,

@@ -69,6 +69,11 @@ hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs
 template <typename T>
 hipError_t launch_force_rows(const T* coef, const int* nvec, int nmodes, const T* tabY,
                              const T* tabZ, int ny, int nz, int R, T* rows, hipStream_t s);
+// cooling and the CFL / health epilogue of the last stage from its stored
+// state after the forcing kick (a step that keeps that state)
+template <typename T>
+hipError_t launch_stage2_finish(bool cool, StageArgs<T> a, const T* ub, const StageGeom& g,
+                                hipStream_t s);
 template <typename T>
 hipError_t launch_smax(const T* U, const StageGeom& g, T gamma, const double* ih, DevClock* clk,
                        hipStream_t s);

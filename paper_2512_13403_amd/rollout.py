@@ -64,24 +64,41 @@ def rollout_forward(s: Solver, U0, nsteps: int, K: int, dts=None):
     return s.get_state_device(), np.array(used), cks
 
 
-def rollout_backward(s: Solver, cks, dts, K: int, lam):
-    """lam_0 = (dU_final/dU_0)^T lam for the run recorded by rollout_forward."""
+def rollout_backward(s: Solver, cks, dts, K: int, lam, keep=None):
+    """lam_0 = (dU_final/dU_0)^T lam for the run recorded by rollout_forward.
+
+    keep: the segment replay also keeps each step's first stage and its state
+    after the forcing kick (mh_step_keep), two more states per step of a
+    segment, and the adjoint steps use them instead of recomputing the stages
+    (the gradient is bitwise the same).  Default: on for SSP-RK2."""
+    from . import RK_SSP2
+
     K = max(1, int(K))
     nsteps = len(dts)
+    if keep is None:
+        keep = s.grid.integrator == RK_SSP2
     lam = lam.contiguous().clone()
     for seg in range(len(cks) - 1, -1, -1):
         k0 = seg * K
         k1 = min(k0 + K, nsteps)
         _restore(s, cks[seg])
         inputs = []
+        kept = []
         for k in range(k0, k1):
             snap = _snapshot(s)
             inputs.append(snap)
-            s.step(1, float(dts[k]))
+            if keep:
+                U1, Ub = s.new_state_tensor(), s.new_state_tensor()
+                s.step_keep(float(dts[k]), U1, Ub)
+                kept.append((U1, Ub))
+            else:
+                s.step(1, float(dts[k]))
         for k in range(k1 - 1, k0 - 1, -1):
             snap = inputs[k - k0]
             s.adjoint_step(snap.U, float(dts[k]), snap.step, lam, ou_ahat=snap.ahat,
-                           phi_n=snap.phi, out=lam)
+                           phi_n=snap.phi, out=lam, kept=kept[k - k0] if keep else None)
+            if keep:
+                kept[k - k0] = None  # free the step's kept stages
     return lam
 
 
