@@ -111,7 +111,7 @@ def _oracle_rate(n, steps):
     return n ** 3 * steps / dt, dt
 
 
-def cpu_baseline(n=256, steps=2, n1=128, steps1=2):
+def cpu_baseline(n=256, steps=6, n1=128, steps1=2):
     """The FP64 oracle on the headline physics (forcing + cooling from rest):
     n^3 for `steps` steps on all of the job's OpenMP threads, and n1^3 for
     `steps1` steps on one thread."""

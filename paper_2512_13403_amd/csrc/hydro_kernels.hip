@@ -71,7 +71,8 @@ template <typename T, int LIM>
 __device__ __forceinline__ T limited_slope(T wm, T w0, T wp, int rl = 0) {
   if (LIM == LIM_NONE) return T(0);
   if (LIM == LIM_GENERIC) return slope_of(rl, wp - w0, w0 - wm);
-  if (LIM == LIM_VANLEER) return slope_of(LIM_VANLEER, wp - w0, w0 - wm);
+  if (LIM == LIM_VANLEER || LIM == LIM_MC || LIM == LIM_SUPERBEE)
+    return slope_of(LIM, wp - w0, w0 - wm);
   return minmod(wp - w0, w0 - wm);
 }
 
@@ -789,15 +790,15 @@ hipError_t launch_stage(int stage, int limiter, bool force, bool cool, StageArgs
   fill_geom(a, g);
   dim3 block(TX, TY);
   dim3 grid(8 * a.nb_per_xcd);
-  // minmod, van Leer (the paper's fiducial limiter) or none with HLLC: the
-  // specialised kernels; any other limiter or solver, or a flux-correction
-  // field: the kernel that reads them at run time
-  if (a.rs != RS_HLLC || a.dflux ||
-      (limiter != LIM_MINMOD && limiter != LIM_NONE && limiter != LIM_VANLEER))
-    limiter = LIM_GENERIC;
+  // every limiter with HLLC: the specialised kernels; another solver, or a
+  // flux-correction field: the kernel that reads them at run time
+  if (a.rs != RS_HLLC || a.dflux) limiter = LIM_GENERIC;
   if (limiter == LIM_NONE) launch_stage_lim<T, LIM_NONE>(stage, force, cool, a, grid, block, s);
   else if (limiter == LIM_VANLEER)
     launch_stage_lim<T, LIM_VANLEER>(stage, force, cool, a, grid, block, s);
+  else if (limiter == LIM_MC) launch_stage_lim<T, LIM_MC>(stage, force, cool, a, grid, block, s);
+  else if (limiter == LIM_SUPERBEE)
+    launch_stage_lim<T, LIM_SUPERBEE>(stage, force, cool, a, grid, block, s);
   else if (limiter == LIM_GENERIC)
     launch_stage_lim<T, LIM_GENERIC>(stage, force, cool, a, grid, block, s);
   else launch_stage_lim<T, LIM_MINMOD>(stage, force, cool, a, grid, block, s);
