@@ -302,12 +302,13 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
 
 def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256, r: int = 4,
               t_spinup: float = 1.0, nsteps: int = 100, iters: int = 500, batch: int = 4,
-              schedule=((0.1, 1), (0.3, 8), (0.6, 32)), log=print) -> dict:
+              schedule=((0.1, 1), (0.3, 16), (0.6, 64)), log=print, lr0: float = 1e-3,
+              lr1: float = 1e-4, loss_w=(16.0, 1.0, 1.0, 1.0, 1.0)) -> dict:
     nc = nf // r
     t0 = time.perf_counter()
     trajs = [record_trajectory(s, nf, r, t_spinup, nsteps) for s in train_seeds]
     log(f"[sil] recorded {len(trajs)} training trajectories in {time.perf_counter() - t0:.1f} s")
-    res = train(trajs, nc, iters, batch, schedule=schedule)
+    res = train(trajs, nc, iters, batch, lr0=lr0, lr1=lr1, loss_w=loss_w, schedule=schedule)
     log(f"[sil] trained {iters} iterations in {res.seconds:.1f} s: loss {res.losses[0]:.4g} -> "
         f"{np.mean(res.losses[-20:]):.4g}")
     del trajs
@@ -336,8 +337,8 @@ def run_study(train_seeds=range(0, 12), eval_seeds=range(12, 16), nf: int = 256,
                                loss_last=float(np.mean(seg[-min(20, len(seg)):]))))
         it0 += k
     return dict(
-        fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch,
-        schedule=[list(p) for p in schedule], train_phases=phases,
+        fine=nf, coarse=nc, steps=nsteps, iters=iters, batch=batch, lr=[lr0, lr1],
+        loss_w=list(loss_w), schedule=[list(p) for p in schedule], train_phases=phases,
         rho_rel_l2_plain=plain, rho_rel_l2_corrected=corrected,
         error_ratio=corrected / plain,
         rho_rel_l2_plain_mean_over_steps=plain_avg,
@@ -365,7 +366,10 @@ if __name__ == "__main__":
     ap.add_argument("--train-seeds", type=int, default=12)
     ap.add_argument("--eval-seeds", type=int, default=4)
     ap.add_argument("--spinup", type=float, default=1.0)
-    ap.add_argument("--unroll", type=int, default=32,
+    ap.add_argument("--lr0", type=float, default=1e-3, help="first learning rate")
+    ap.add_argument("--lr1", type=float, default=1e-4, help="last learning rate")
+    ap.add_argument("--wrho", type=float, default=16.0, help="density weight of the loss")
+    ap.add_argument("--unroll", type=int, default=64,
                     help="longest unroll: 10 %% of the iterations on pairs, 30 %% at "
                          "unroll/4, 60 %% at unroll")
     a = ap.parse_args()
@@ -373,5 +377,6 @@ if __name__ == "__main__":
                     a.fine, a.ratio, a.spinup, a.steps, a.iters, a.batch,
                     ((0.1, 1), (0.3, max(a.unroll // 4, 1)), (0.6, a.unroll))
                     if a.unroll > 1 else ((1.0, 1),),
-                    log=lambda m: print(m, flush=True))
+                    log=lambda m: print(m, flush=True), lr0=a.lr0, lr1=a.lr1,
+                    loss_w=(a.wrho, 1.0, 1.0, 1.0, 1.0))
     print(json.dumps(out))
