@@ -22,7 +22,6 @@ struct MGLevel {
   double h;
   size_t phi[2];  // ping-pong buffers of the Jacobi sweeps
   size_t F;       // right-hand side
-  size_t r;       // residual
 };
 
 // V-cycles replayed from captured HIP graphs: one V-cycle is ~60 small

@@ -98,10 +98,10 @@ __global__ __launch_bounds__(256) void k_zero(T* y, long long n) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_jacobi(int n, T h2, const T* __restrict__ phi,
                                                 const T* __restrict__ F, T* __restrict__ out) {
-  const long long N = (long long)n * n * n;
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= N) return;
-  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
+  const int p = blockIdx.x * 256 + threadIdx.x;  // launched by plane_grid(n * n, n)
+  if (p >= n * n) return;
+  const int k = blockIdx.y, j = p / n, i = p - j * n;
+  const long long q = (long long)k * n * n + p;
   const T w = T(2) / T(3);
   out[q] = (T(1) - w) * phi[q] + (w / T(6)) * (nb6(phi, n, i, j, k) - h2 * F[q]);
 }
@@ -113,57 +113,87 @@ __global__ __launch_bounds__(256) void k_jacobi(int n, T h2, const T* __restrict
 template <typename T>
 __global__ __launch_bounds__(256) void k_rbgs(int n, T h2, T* phi, const T* __restrict__ F,
                                               int colour) {
-  const long long N = (long long)n * n * n;
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= N) return;
-  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
-  if (((i + j + k) & 1) != colour) return;
+  // one thread per cell of the colour: the n/2 cells of a row with
+  // (i + j + k) mod 2 = colour, launched by plane_grid(n / 2 * n, n)
+  const int nh = n >> 1;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= nh * n) return;
+  const int k = blockIdx.y, j = p / nh, i = 2 * (p - j * nh) + ((j + k + colour) & 1);
+  const long long q = ((long long)k * n + j) * n + i;
   phi[q] = (nb6(phi, n, i, j, k) - h2 * F[q]) / T(6);
 }
 
-// r = F - A phi
+// the residual F - A phi at cell q = (i, j, k) of an n^3 grid
 template <typename T>
-__global__ __launch_bounds__(256) void k_residual(int n, T ih2, const T* __restrict__ phi,
-                                                  const T* __restrict__ F, T* __restrict__ r) {
-  const long long N = (long long)n * n * n;
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= N) return;
-  const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((long long)n * n));
-  r[q] = F[q] - (nb6(phi, n, i, j, k) - T(6) * phi[q]) * ih2;
+__device__ __forceinline__ T residual_at(const T* __restrict__ phi, const T* __restrict__ F, int n,
+                                         T ih2, int i, int j, int k, long long q) {
+  return F[q] - (nb6(phi, n, i, j, k) - T(6) * phi[q]) * ih2;
+}
+
+// |F - A phi|^2 summed per block in the order of k_sum_partial<T, true>
+// over the residual array (the same grid, cells and per-block tree), without
+// storing the residual (cells are indexed in 32 bits: a grid holds at most
+// 2^31 cells)
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_norm2(int n, T ih2, const T* __restrict__ phi,
+                                                        const T* __restrict__ F,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const unsigned n2 = (unsigned)n * (unsigned)n, N = n2 * (unsigned)n;
+  double acc = 0.0;
+  for (unsigned q = blockIdx.x * 256 + threadIdx.x; q < N; q += gridDim.x * 256) {
+    const int k = (int)(q / n2), rem = (int)(q - (unsigned)k * n2), j = rem / n, i = rem - j * n;
+    const T r = residual_at(phi, F, n, ih2, i, j, k, (long long)q);
+    const double v = (double)r;
+    acc += v * v;
+  }
+  const double b = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = b;
 }
 
 // restriction of the residual, F_c = average over the 8 children of
-// F - A phi (the arithmetic of k_residual, summed in child order): each
+// F - A phi (residual_at, summed in child order): each
 // coarse cell forms its children's residuals in registers, so the fine
-// residual is never stored
+// residual is never stored.  The coarse cells are visited in the order of
+// k_sum_partial<T, false> over F_c (same grid, cells and per-block tree), and
+// each block's sum of its F_c values is written to `partial`, so the mean of
+// F_c needs only k_sum_final.
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual_restrict(int nc, T ih2, const T* __restrict__ phi,
                                                            const T* __restrict__ F,
-                                                           T* __restrict__ rc) {
-  const long long Nc = (long long)nc * nc * nc;
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= Nc) return;
-  const int I = (int)(q % nc), J = (int)((q / nc) % nc), K = (int)(q / ((long long)nc * nc));
+                                                           T* __restrict__ rc,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const unsigned nc2 = (unsigned)nc * (unsigned)nc, Nc = nc2 * (unsigned)nc;
   const int nf = 2 * nc;
   const long long nf2 = (long long)nf * nf;
-  T s = T(0);
-  for (int c = 0; c < 2; ++c)
-    for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < 2; ++a) {
-        const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
-        const long long f = (long long)k * nf2 + (long long)j * nf + i;
-        s += F[f] - (nb6(phi, nf, i, j, k) - T(6) * phi[f]) * ih2;
-      }
-  rc[q] = T(0.125) * s;
+  double acc = 0.0;
+  for (unsigned q = blockIdx.x * 256 + threadIdx.x; q < Nc; q += gridDim.x * 256) {
+    const int K = (int)(q / nc2), rem = (int)(q - (unsigned)K * nc2), J = rem / nc,
+              I = rem - J * nc;
+    T s = T(0);
+    for (int c = 0; c < 2; ++c)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          const int i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+          const long long f = (long long)k * nf2 + (long long)j * nf + i;
+          s += residual_at(phi, F, nf, ih2, i, j, k, f);
+        }
+    const T v = T(0.125) * s;
+    rc[q] = v;
+    acc += (double)v;
+  }
+  const double b = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = b;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_add(int nc, const T* __restrict__ ec, T* __restrict__ phif) {
   const int nf = 2 * nc;
-  const long long Nf = (long long)nf * nf * nf;
-  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= Nf) return;
-  const int i = (int)(q % nf), j = (int)((q / nf) % nf), k = (int)(q / ((long long)nf * nf));
+  const int p = blockIdx.x * 256 + threadIdx.x;  // launched by plane_grid(nf * nf, nf)
+  if (p >= nf * nf) return;
+  const int k = blockIdx.y, j = p / nf, i = p - j * nf;
+  const long long q = (long long)k * nf * nf + p;
   const int I = i >> 1, J = j >> 1, K = k >> 1;
   const int I2 = wrapi(I + ((i & 1) ? 1 : -1), nc);
   const int J2 = wrapi(J + ((j & 1) ? 1 : -1), nc);
@@ -495,14 +525,21 @@ __global__ void k_set_cycles(DevClock* clk, int cycles) {
 }
 
 inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+// a launch over `planes` z-planes of `m` cells each: blockIdx.y is the plane
+inline dim3 plane_grid(long long m, int planes) { return dim3(nblk(m), (unsigned)planes); }
 // grid of a grid-stride kernel that ends in one clock atomic per block
 inline unsigned nblk_capped(long long n) { return nblk(n) < 4096u ? nblk(n) : 4096u; }
+
+// blocks of a two-stage reduction over n values (k_sum_partial's grid)
+inline int sum_blocks(long long n) {
+  const int nb = (int)((n + 255) / 256);
+  return nb < MG_PARTIALS ? nb : MG_PARTIALS;
+}
 
 template <typename T>
 hipError_t sum_to(const T* x, long long n, bool square, double* partial, double scale, double* out,
                   hipStream_t s) {
-  int nb = (int)((n + 255) / 256);
-  if (nb > MG_PARTIALS) nb = MG_PARTIALS;
+  const int nb = sum_blocks(n);
   if (square) hipLaunchKernelGGL((k_sum_partial<T, true>), dim3(nb), dim3(256), 0, s, x, n, partial);
   else hipLaunchKernelGGL((k_sum_partial<T, false>), dim3(nb), dim3(256), 0, s, x, n, partial);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, scale, out);
@@ -531,10 +568,12 @@ void smooth_level(char* ws, MGLevel& lv, int sweeps, int rbgs, int& cur, hipStre
   for (int it = 0; it < sweeps; ++it) {
     if (rbgs) {
       for (int colour = 0; colour < 2; ++colour)
-        hipLaunchKernelGGL((k_rbgs<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
+        hipLaunchKernelGGL((k_rbgs<T>), plane_grid((long long)(lv.n / 2) * lv.n, lv.n),
+                           dim3(256), 0, s, lv.n, h2,
                            P<T>(ws, lv.phi[cur]), P<T>(ws, lv.F), colour);
     } else {
-      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, lv.n, h2,
+      hipLaunchKernelGGL((k_jacobi<T>), plane_grid((long long)lv.n * lv.n, lv.n), dim3(256), 0,
+                         s, lv.n, h2,
                          P<T>(ws, lv.phi[cur]), P<T>(ws, lv.F), P<T>(ws, lv.phi[1 - cur]));
       cur = 1 - cur;
     }
@@ -566,10 +605,16 @@ hipError_t level_cycle(char* ws, MGLayout& L, const mh_physics_desc& p, int l, i
   smooth_level<T>(ws, lv, p.mg_pre, rbgs, cur[l], s);
   MGLevel& cv = L.lev[l + 1];
   const long long Nc = (long long)cv.n * cv.n * cv.n;
-  hipLaunchKernelGGL((k_residual_restrict<T>), dim3(nblk(Nc)), dim3(256), 0, s, cv.n,
+  // F_c and its block sums in one pass, then its mean removed
+  const int nbc = sum_blocks(Nc);
+  hipLaunchKernelGGL((k_residual_restrict<T>), dim3(nbc), dim3(256), 0, s, cv.n,
                      (T)(1.0 / (lv.h * lv.h)), P<T>(ws, lv.phi[cur[l]]), P<T>(ws, lv.F),
-                     P<T>(ws, cv.F));
-  hipError_t e = remove_mean(P<T>(ws, cv.F), Nc, partial, mean_slot, s);
+                     P<T>(ws, cv.F), partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nbc, 1.0 / (double)Nc,
+                     mean_slot);
+  hipLaunchKernelGGL((k_sub_mean<T>), dim3(nblk(Nc)), dim3(256), 0, s, P<T>(ws, cv.F), Nc,
+                     mean_slot);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int mu = (p.mg_cycle == MH_MG_W && l + 1 < nl - 1) ? 2 : 1;
   if (l + 1 == l0) {
@@ -609,7 +654,8 @@ hipError_t level_cycle(char* ws, MGLayout& L, const mh_physics_desc& p, int l, i
       if (e != hipSuccess) return e;
     }
   }
-  hipLaunchKernelGGL((k_prolong_add<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n,
+  hipLaunchKernelGGL((k_prolong_add<T>), plane_grid((long long)lv.n * lv.n, lv.n), dim3(256),
+                     0, s, cv.n,
                      P<T>(ws, cv.phi[cur[l + 1]]), P<T>(ws, lv.phi[cur[l]]));
   smooth_level<T>(ws, lv, p.mg_post, rbgs, cur[l], s);
   return hipGetLastError();
@@ -628,7 +674,8 @@ hipError_t vcycle(char* ws, MGLayout& L, const mh_physics_desc& p, double* parti
     MGLevel& cv = L.lev[0];
     const long long N = (long long)cv.n * cv.n * cv.n;
     for (int it = 0; it < p.mg_coarse_sweeps; ++it) {
-      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(N)), dim3(256), 0, s, cv.n, (T)(cv.h * cv.h),
+      hipLaunchKernelGGL((k_jacobi<T>), plane_grid((long long)cv.n * cv.n, cv.n), dim3(256), 0,
+                         s, cv.n, (T)(cv.h * cv.h),
                          P<T>(ws, cv.phi[cur[0]]), P<T>(ws, cv.F), P<T>(ws, cv.phi[1 - cur[0]]));
       cur[0] = 1 - cur[0];
     }
@@ -714,7 +761,6 @@ size_t mg_layout(const mh_grid_desc* g, const mh_physics_desc* p, size_t off, si
     lv.phi[0] = take(bytes);
     lv.phi[1] = take(bytes);
     lv.F = take(bytes);
-    lv.r = take(bytes);
     return fft_layout(n, off, es, L);
   }
   for (;;) {
@@ -725,7 +771,6 @@ size_t mg_layout(const mh_grid_desc* g, const mh_physics_desc* p, size_t off, si
     lv.phi[0] = take(bytes);
     lv.phi[1] = take(bytes);
     lv.F = take(bytes);
-    lv.r = take(bytes);
     if (n <= p->mg_coarsest || (n % 2) != 0 || L.nlev == MG_MAX_LEVELS) break;
     n /= 2;
     h *= 2.0;
@@ -738,7 +783,7 @@ hipError_t mg_init(char* ws, const MGLayout& L, const mh_grid_desc* g, hipStream
   for (int l = 0; l < L.nlev; ++l) {
     const MGLevel& lv = L.lev[l];
     const long long N = (long long)lv.n * lv.n * lv.n;
-    const size_t offs[4] = {lv.phi[0], lv.phi[1], lv.F, lv.r};
+    const size_t offs[3] = {lv.phi[0], lv.phi[1], lv.F};
     for (size_t o : offs) {
       if (f64) hipLaunchKernelGGL((k_zero<double>), dim3(nblk(N)), dim3(256), 0, s, P<double>(ws, o), N);
       else hipLaunchKernelGGL((k_zero<float>), dim3(nblk(N)), dim3(256), 0, s, P<float>(ws, o), N);
@@ -847,9 +892,12 @@ hipError_t mg_solve(char* ws, MGLayout& L, const mh_physics_desc& p, DevClock* c
   int cycles = 0;
   double prev = INFINITY;
   for (;;) {
-    hipLaunchKernelGGL((k_residual<T>), dim3(nblk(N)), dim3(256), 0, s, n, (T)(1.0 / (f.h * f.h)),
-                       P<T>(ws, f.phi[L.cur0]), P<T>(ws, f.F), P<T>(ws, f.r));
-    MG_CHECK(sum_to(P<T>(ws, f.r), N, true, partial, 1.0, &clk->mg_rnorm2, s));
+    // |r|^2 without storing r: the sum k_sum_partial would form over it
+    const int nbr = sum_blocks(N);
+    hipLaunchKernelGGL((k_residual_norm2<T>), dim3(nbr), dim3(256), 0, s, n,
+                       (T)(1.0 / (f.h * f.h)), P<T>(ws, f.phi[L.cur0]), P<T>(ws, f.F), partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nbr, 1.0,
+                       &clk->mg_rnorm2);
     double norms[2];
     MG_CHECK(hipMemcpyAsync(norms, &clk->mg_fnorm2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     MG_CHECK(hipStreamSynchronize(s));
