@@ -275,15 +275,26 @@ struct TailArgs {
   int warm;                  // start the first level from phi0
 };
 
+// the sum of v over the workgroup, returned to every thread: a fixed tree
+// inside each wave (lane l adds lane l + s for s = 32, 16, ..., 1), then the
+// same over the 16 wave sums
+__device__ __forceinline__ double wave_tree_sum(double v) {
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
+  return v;
+}
 __device__ __forceinline__ double block_sum1024(double v, double* sh) {
+  static_assert(MG_TAIL_THREADS == 1024, "16 waves");
   const int t = threadIdx.x;
-  sh[t] = v;
+  v = wave_tree_sum(v);
+  if ((t & 63) == 0) sh[t >> 6] = v;
   __syncthreads();
-  for (int s = MG_TAIL_THREADS / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
+  if (t < 64) {
+    double w = t < 16 ? sh[t] : 0.0;
+    for (int s = 8; s > 0; s >>= 1) w += __shfl_down(w, s, 64);
+    if (t == 0) sh[16] = w;
   }
-  const double r = sh[0];
+  __syncthreads();
+  const double r = sh[16];
   __syncthreads();
   return r;
 }
@@ -331,15 +342,19 @@ __device__ void tail_sweeps_wave(T* pa, T* pb, const T* ff, int o, int n, T h2, 
   cur ^= sweeps & 1;
 }
 
+// red-black sweeps of a tail level (n even): per colour, a thread per cell
+// of the colour, the arithmetic of k_rbgs
 template <typename T>
 __device__ void tail_rbgs(T* pa, T* pb, const T* ff, int o, int n, T h2, int sweeps, int cur) {
-  const int N = n * n * n;
+  const int nh = n >> 1, Nh = nh * n * n;
   T* phi = (cur ? pb : pa) + o;
   for (int it = 0; it < sweeps; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      for (int q = threadIdx.x; q < N; q += MG_TAIL_THREADS) {
-        const int i = q % n, j = (q / n) % n, k = q / (n * n);
-        if (((i + j + k) & 1) == colour) phi[q] = (nb6(phi, n, i, j, k) - h2 * ff[o + q]) / T(6);
+      for (int p = threadIdx.x; p < Nh; p += MG_TAIL_THREADS) {
+        const int r = p / nh, j = r % n, k = r / n;
+        const int i = 2 * (p - r * nh) + ((j + k + colour) & 1);
+        const int q = (k * n + j) * n + i;
+        phi[q] = (nb6(phi, n, i, j, k) - h2 * ff[o + q]) / T(6);
       }
       __syncthreads();
     }
