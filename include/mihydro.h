@@ -265,8 +265,13 @@ mh_status mh_adjoint_step(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace
  * and those kernels follow as usual).  Enqueued on the context stream;
  * dt_out (one double, optional) synchronises.
  * mh_adjoint_step_kept is mh_adjoint_step for that step given U1 and Ub: it
- * skips recomputing the two stages (it still solves the adjoint potential
- * with gravity); the result is bitwise mh_adjoint_step's.
+ * skips recomputing the two stages.  With multigrid gravity, phi_np1 (device,
+ * [nz][ny][nx], or NULL) may give the potential the step solved for -- the
+ * context's potential right after the step (mh_get_potential) -- and the
+ * forward Poisson solve from phi_n is skipped too (it would return those
+ * bits); the adjoint potential is still solved.  phi_np1 is ignored without
+ * gravity and with the spectral solver.  The result is bitwise
+ * mh_adjoint_step's.
  * Errors: MH_E_INVALID (null or equal buffers, an integrator other than
  * MH_RK_SSP2, ou_ahat missing with forcing on, bad dt or step),
  * MH_E_WORKSPACE, MH_E_DEVICE. */
@@ -274,7 +279,7 @@ mh_status mh_step_keep(mh_ctx *ctx, double dt, void *U1_out, void *Ub_out, doubl
 mh_status mh_adjoint_step_kept(mh_ctx *ctx, void *adj_workspace, size_t adj_workspace_bytes,
                                const void *U_n, const void *U1, const void *Ub, double dt,
                                int64_t step, const double *ou_ahat, const void *phi_n,
-                               const void *lam_np1, void *lam_n);
+                               const void *phi_np1, const void *lam_np1, void *lam_n);
 
 /* ------------------------------------------------------------------------ */
 /* Learned state corrector (solver in the loop, paper Sec. 8)               */

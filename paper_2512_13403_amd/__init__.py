@@ -133,7 +133,7 @@ def load_library():
                                 vp, vp, vp],
             "mh_step_keep": [vp, ctypes.c_double, vp, vp, dp],
             "mh_adjoint_step_kept": [vp, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_double,
-                                     ctypes.c_int64, dp, vp, vp, vp],
+                                     ctypes.c_int64, dp, vp, vp, vp, vp],
             "mh_corr_query_workspace": [ctypes.POINTER(CorrDesc), ctypes.POINTER(ctypes.c_size_t)],
             "mh_corr_init": [ctypes.POINTER(CorrDesc), vp, ctypes.c_size_t, vp,
                              ctypes.POINTER(vp)],
@@ -448,8 +448,10 @@ class Solver:
         the solver's shape and dtype) with fixed dt at global index `step`;
         ou_ahat: OU amplitudes before the step (host), phi_n: potential before
         the step (CUDA tensor) or None; kept: (U1, Ub) written by step_keep for
-        this step, which spares recomputing the two stages.  Returns lam_n (a
-        new tensor unless `out` is given; `out` may be `lam`)."""
+        this step, which spares recomputing the two stages, or (U1, Ub,
+        phi_np1) with the potential right after the step, which with
+        multigrid gravity also spares the step's Poisson solve.  Returns lam_n
+        (a new tensor unless `out` is given; `out` may be `lam`)."""
         torch = self._torch
         if getattr(self, "_adj_ws", None) is None:
             n = ctypes.c_size_t(0)
@@ -467,15 +469,20 @@ class Solver:
             # kept alive on self until the next call: the copy is enqueued
             self._keep_ahat = np.ascontiguousarray(ou_ahat, dtype=np.float64)
             ah = self._keep_ahat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if phi_n is not None:
+            phi_n = phi_n.contiguous()
+        ph = ctypes.c_void_p(phi_n.data_ptr()) if phi_n is not None else None
         self._keep_adj = (U_n, lam, phi_n, kept)
-        ph = ctypes.c_void_p(phi_n.contiguous().data_ptr()) if phi_n is not None else None
         if kept is not None:
-            U1, Ub = kept
+            U1, Ub = kept[0], kept[1]
+            phi_np1 = kept[2].contiguous() if len(kept) > 2 and kept[2] is not None else None
+            self._keep_adj += (phi_np1,)
+            p1 = ctypes.c_void_p(phi_np1.data_ptr()) if phi_np1 is not None else None
             st = self.lib.mh_adjoint_step_kept(self.ctx, ctypes.c_void_p(base), self._adj_bytes,
                                                ctypes.c_void_p(U_n.data_ptr()),
                                                ctypes.c_void_p(U1.data_ptr()),
                                                ctypes.c_void_p(Ub.data_ptr()), dt, step, ah, ph,
-                                               ctypes.c_void_p(lam.data_ptr()),
+                                               p1, ctypes.c_void_p(lam.data_ptr()),
                                                ctypes.c_void_p(out.data_ptr()))
             self._check(st, "mh_adjoint_step_kept")
             return out

@@ -921,12 +921,13 @@ extern "C" mh_status mh_query_adjoint_workspace(mh_ctx* c, size_t* bytes) {
 
 // kept_u1, kept_ub (or null): the step's first-stage result and its state
 // after the forcing kick, kept by mh_step_keep; the recomputation of the two
-// stages is skipped
+// stages is skipped.  kept_phi (or null): the potential the step's multigrid
+// solve returned; the solve is skipped
 template <typename T>
 static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, double dt,
                               int64_t step, const double* ou_ahat, const T* phi_n,
                               const T* lam_np1, T* lam_n, const T* kept_u1 = nullptr,
-                              const T* kept_ub = nullptr) {
+                              const T* kept_ub = nullptr, const T* kept_phi = nullptr) {
   const mh_grid_desc& g = c->g;
   const mh_physics_desc& p = c->p;
   const bool force = (p.flags & MH_SRC_FORCING) != 0;
@@ -1015,9 +1016,14 @@ static mh_status adjoint_impl(mh_ctx* c, char* ws, AdjLayout& A, const T* Un, do
   }
   const T* phi_sol = nullptr;
   if (grav) {
-    MH_HIP(c, mg_set_guess<T>(ws, A.mg, phi_n, c->stream));
-    MH_HIP(c, mg_set_rhs<T>(ws, A.mg, Ub, 4.0 * M_PI * p.grav_G, aclk, c->stream));
-    MH_HIP(c, mg_solve<T>(ws, A.mg, p, aclk, nullptr, c->stream));
+    if (kept_phi && !A.mg.fft) {
+      // the solve from phi_n on Ub would return these bits
+      MH_HIP(c, mg_set_guess<T>(ws, A.mg, kept_phi, c->stream));
+    } else {
+      MH_HIP(c, mg_set_guess<T>(ws, A.mg, phi_n, c->stream));
+      MH_HIP(c, mg_set_rhs<T>(ws, A.mg, Ub, 4.0 * M_PI * p.grav_G, aclk, c->stream));
+      MH_HIP(c, mg_solve<T>(ws, A.mg, p, aclk, nullptr, c->stream));
+    }
     MH_HIP(c, mg_kick<T>(ws, A.mg, g, Uc, aclk, c->stream));
     phi_sol = reinterpret_cast<const T*>(ws + mg_phi_offset(A.mg));
   }
@@ -1112,7 +1118,8 @@ extern "C" mh_status mh_adjoint_step_kept(mh_ctx* c, void* adj_workspace,
                                           size_t adj_workspace_bytes, const void* U_n,
                                           const void* U1, const void* Ub, double dt, int64_t step,
                                           const double* ou_ahat, const void* phi_n,
-                                          const void* lam_np1, void* lam_n) {
+                                          const void* phi_np1, const void* lam_np1,
+                                          void* lam_n) {
   if (!c) return MH_E_INVALID;
   if (!U_n || !U1 || !Ub || !lam_np1 || !lam_n)
     return set_err(c, MH_E_INVALID, "mh_adjoint_step_kept: null state or adjoint pointer");
@@ -1131,10 +1138,10 @@ extern "C" mh_status mh_adjoint_step_kept(mh_ctx* c, void* adj_workspace,
   if (c->g.dtype == MH_F64)
     return adjoint_impl<double>(c, ws, A, (const double*)U_n, dt, step, ou_ahat,
                                 (const double*)phi_n, (const double*)lam_np1, (double*)lam_n,
-                                (const double*)U1, (const double*)Ub);
+                                (const double*)U1, (const double*)Ub, (const double*)phi_np1);
   return adjoint_impl<float>(c, ws, A, (const float*)U_n, dt, step, ou_ahat, (const float*)phi_n,
                              (const float*)lam_np1, (float*)lam_n, (const float*)U1,
-                             (const float*)Ub);
+                             (const float*)Ub, (const float*)phi_np1);
 }
 
 extern "C" mh_status mh_set_timing(mh_ctx* c, int enable) {

@@ -69,8 +69,10 @@ def rollout_backward(s: Solver, cks, dts, K: int, lam, keep=None):
 
     keep: the segment replay also keeps each step's first stage and its state
     after the forcing kick (mh_step_keep), two more states per step of a
-    segment, and the adjoint steps use them instead of recomputing the stages
-    (the gradient is bitwise the same).  Default: on for SSP-RK2."""
+    segment, and the adjoint steps use them, and with gravity the potential
+    each step solved for (the next step's snapshot), instead of recomputing
+    the stages and the forward Poisson solve (the gradient is bitwise the
+    same).  Default: on for SSP-RK2."""
     from . import RK_SSP2
 
     K = max(1, int(K))
@@ -93,10 +95,15 @@ def rollout_backward(s: Solver, cks, dts, K: int, lam, keep=None):
                 kept.append((U1, Ub))
             else:
                 s.step(1, float(dts[k]))
+        # the potential each replayed step solved for: the next step's
+        # starting one, and the solver's after the last
+        phi_after = [snap.phi for snap in inputs[1:]] + [
+            s.potential_device() if _gravity_on(s) else None]
         for k in range(k1 - 1, k0 - 1, -1):
             snap = inputs[k - k0]
+            kk = (kept[k - k0] + (phi_after[k - k0],)) if keep else None
             s.adjoint_step(snap.U, float(dts[k]), snap.step, lam, ou_ahat=snap.ahat,
-                           phi_n=snap.phi, out=lam, kept=kept[k - k0] if keep else None)
+                           phi_n=snap.phi, out=lam, kept=kk)
             if keep:
                 kept[k - k0] = None  # free the step's kept stages
     return lam

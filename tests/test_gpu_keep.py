@@ -1,9 +1,10 @@
 """Store instead of recompute (Sec. 2.3): mh_step_keep keeps a step's first
 stage and its state after the forcing kick, and mh_adjoint_step_kept uses
-them instead of recomputing the two stages.  Both must be bitwise the plain
-calls: the state, clock and next CFL dt after the step, and the adjoint;
-the checkpointed rollout gradient with and without keeping; argument
-errors."""
+them, and with gravity the potential the step solved for, instead of
+recomputing the two stages and the forward Poisson solve.  Both must be
+bitwise the plain calls: the state, clock and next CFL dt after the step,
+and the adjoint; the checkpointed rollout gradient with and without keeping;
+argument errors."""
 import numpy as np
 import pytest
 
@@ -81,6 +82,7 @@ def test_keep_step_and_kept_adjoint_are_bitwise(case, dtype):
     d1 = s1.step(1, 0.0, record=True)
     U1, Ub = s2.new_state_tensor(), s2.new_state_tensor()
     d2 = s2.step_keep(0.0, U1, Ub, record=True)
+    phi1 = s2.potential_device() if kw["flags"] & G else None
     assert d1[0] == d2[0] > 0
     assert torch.equal(s1.get_state_device(), s2.get_state_device())
     assert s1.clock() == s2.clock()
@@ -93,14 +95,21 @@ def test_keep_step_and_kept_adjoint_are_bitwise(case, dtype):
     a1 = s1.adjoint_step(U0, float(d1[0]), 0, lam, ou_ahat=ahat, phi_n=phi)
     a2 = s1.adjoint_step(U0, float(d1[0]), 0, lam, ou_ahat=ahat, phi_n=phi, kept=(U1, Ub))
     assert torch.equal(a1, a2), (a1 - a2).abs().max().item()
+    if kw["flags"] & G:
+        # and the potential the step solved for (the multigrid solve skipped;
+        # ignored by the spectral solver)
+        a3 = s1.adjoint_step(U0, float(d1[0]), 0, lam, ou_ahat=ahat, phi_n=phi,
+                             kept=(U1, Ub, phi1))
+        assert torch.equal(a1, a3), (a1 - a3).abs().max().item()
 
 
-@pytest.mark.parametrize("flags", [F | C, G | C])
-def test_rollout_gradient_with_kept_stages(flags):
+@pytest.mark.parametrize("case", ["forcing+cooling", "gravity-mg+cooling", "gravity-fft+forcing"])
+def test_rollout_gradient_with_kept_stages(case):
     import torch
 
     n = 16
-    kw = CASES["forcing+cooling"] if flags == F | C else CASES["gravity-mg+cooling"]
+    kw = CASES[case]
+    flags = kw["flags"]
     U0 = grav_state(n, seed=9) if flags & G else wl.random_state((n, n, n), seed=22, vmax=0.5)
     s, _ = pair((n, n, n), (1 / n,) * 3, dtype="f64", **kw)
     nsteps, K = 7, 3

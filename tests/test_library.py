@@ -145,7 +145,7 @@ def test_null_arguments():
     assert lib.mh_step(None, 1, 0.0, 1.0, None, None) == mh.E_INVALID
     assert lib.mh_step_keep(None, 0.0, None, None, None) == mh.E_INVALID
     assert lib.mh_adjoint_step_kept(None, None, 0, None, None, None, 0.0, 0, None, None, None,
-                                    None) == mh.E_INVALID
+                                    None, None) == mh.E_INVALID
     assert lib.mh_set_state(None, None, 0) == mh.E_INVALID
     assert lib.mh_last_error(None) == b""
     lib.mh_destroy(None)
