@@ -39,16 +39,21 @@ __device__ __forceinline__ T nb6(const T* __restrict__ p, int n, int i, int j, i
          p[(long long)kp * n2 + (long long)j * n + i];
 }
 
-// block sum in double with a fixed tree (blockDim = 256)
+// a fixed tree inside each wave: lane l adds lane l + s for s = 32, 16, ...,
+// 1 (lane 0 holds the wave's sum)
+__device__ __forceinline__ double wave_tree_sum(double v) {
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
+  return v;
+}
+
+// the sum of v over a 256-thread block, returned to every thread: the four
+// wave sums added pairwise
 __device__ __forceinline__ double block_sum256(double v, double* sh) {
   const int t = threadIdx.x;
-  sh[t] = v;
+  v = wave_tree_sum(v);
+  if ((t & 63) == 0) sh[t >> 6] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
-  }
-  return sh[0];
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 template <typename T, bool SQUARE>
@@ -276,12 +281,7 @@ struct TailArgs {
 };
 
 // the sum of v over the workgroup, returned to every thread: a fixed tree
-// inside each wave (lane l adds lane l + s for s = 32, 16, ..., 1), then the
-// same over the 16 wave sums
-__device__ __forceinline__ double wave_tree_sum(double v) {
-  for (int s = 32; s > 0; s >>= 1) v += __shfl_down(v, s, 64);
-  return v;
-}
+// inside each wave, then the same over the 16 wave sums
 __device__ __forceinline__ double block_sum1024(double v, double* sh) {
   static_assert(MG_TAIL_THREADS == 1024, "16 waves");
   const int t = threadIdx.x;
