@@ -17,7 +17,9 @@
 //
 // Data movement per stage (fp32): each cell is read once from HBM for its own
 // column and written once; the x/y stencil halos of a 64 x 8 tile come from
-// neighbouring tiles through L2.  Primitive variables of the current z-plane
+// neighbouring tiles through L2 (the outputs and the last stage's U^n, which
+// no other tile reads, go through non-temporal stores and loads so as not to
+// displace them).  Primitive variables of the current z-plane
 // live in LDS (with a 2-cell x/y halo); the z-stencil is a register ring of
 // four planes per thread, so the kernel marches along z and touches each
 // plane once.  Every face flux is computed exactly once per tile: x faces by
@@ -244,7 +246,10 @@ __device__ __forceinline__ uint32_t lane_off(uint32_t off) {
   asm volatile("" : "+v"(off));
   return off;
 }
-template <typename T>
+// STREAM: a non-temporal load, for data read once (U^n of the last stage),
+// so that it does not displace from L2 the halo rows the neighbouring tiles
+// read again
+template <typename T, bool STREAM = false>
 __device__ __forceinline__ void load_lane(const T* __restrict__ base, long long N, uint32_t off,
                                           T (&u)[5]) {
   typedef __attribute__((address_space(1))) const char gchar;
@@ -254,9 +259,12 @@ __device__ __forceinline__ void load_lane(const T* __restrict__ base, long long 
   for (int f = 0; f < 5; ++f) {
     gchar* b = (gchar*)(base + f * N);
     asm volatile("" : "+s"(b));
-    u[f] = *(gT*)(b + o);
+    if (STREAM) u[f] = __builtin_nontemporal_load((gT*)(b + o));
+    else u[f] = *(gT*)(b + o);
   }
 }
+// the stage's output, written once and not read again by this launch:
+// non-temporal stores, which keep L2 for the halo rows
 template <typename T>
 __device__ __forceinline__ void store_lane(T* __restrict__ base, long long N, uint32_t off,
                                            const T (&u)[5]) {
@@ -267,7 +275,7 @@ __device__ __forceinline__ void store_lane(T* __restrict__ base, long long N, ui
   for (int f = 0; f < 5; ++f) {
     gchar* b = (gchar*)(base + f * N);
     asm volatile("" : "+s"(b));
-    *(gT*)(b + o) = u[f];
+    __builtin_nontemporal_store(u[f], (gT*)(b + o));
   }
 }
 
@@ -494,7 +502,7 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
     const long long q = (long long)z * plane + col;
     if (STAGE != 1) {
       T u0[5];
-      if (inside) load_lane(a.un + (long long)z * plane, N, col_b, u0);
+      if (inside) load_lane<T, true>(a.un + (long long)z * plane, N, col_b, u0);
       else {
 #pragma unroll
         for (int f = 0; f < 5; ++f) u0[f] = u[0][f];
