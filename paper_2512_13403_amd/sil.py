@@ -231,8 +231,9 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
     each; the corrected rollout is one call of the library's corrected step
     (mh_step_corrected: the plain steps and one batched corrector pass per
     step, replayed from a captured HIP graph, the step sizes from a device
-    schedule).  Cost = wall clock of the batched rollout; the fine cost is the
-    summed wall clock of the same trajectories' fine groups."""
+    schedule).  Cost = wall clock of the batched rollout (after one untimed
+    step of each kind); the fine cost is the summed wall clock of the same
+    trajectories' fine groups."""
     import torch
 
     from . import step_corrected
@@ -267,6 +268,13 @@ def evaluate(trajs, nc: int, res: TrainResult, nsteps: int | None = None) -> dic
     out = {}
     for mode in ("plain", "corrected"):
         corrected = mode == "corrected"
+        # one untimed step first (code objects loaded, the capture path run
+        # once), then the timed rollout from the start
+        reset()
+        if corrected:
+            step_corrected(solvers, corr, 1, dts[0:1].contiguous(), use_graph=True, stage=stage)
+        else:
+            advance(0, False, False)
         reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
