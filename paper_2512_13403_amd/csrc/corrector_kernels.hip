@@ -151,19 +151,20 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
     int x0, y0, z0;
     long long base;
     origin(t, x0, y0, z0, base);
-    int tid = threadIdx.x;
+    unsigned tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
+    const unsigned short* ib = in + base * 32;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
       // lanes past the last chunk load the last chunk again (unused): every
       // load is unconditional
-      const int i = min(tid + 256 * k, CNH * 4 - 1);
-      const int h = i >> 2, c = i & 3;
-      const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
-      const long long src = base +
-                            ((long long)wrap(z0 - 1 + hz, n) * n + wrap(y0 - 1 + hy, n)) * n +
-                            wrap(x0 - 1 + hx, n);
-      __builtin_memcpy(&pre[k], in + src * 32 + c * 8, 16);
+      const unsigned i = min(tid + 256u * k, (unsigned)(CNH * 4 - 1));
+      const unsigned h = i >> 2, c = i & 3;
+      const unsigned hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
+      const unsigned zy = (unsigned)wrap(z0 - 1 + (int)hz, n) * (unsigned)n +
+                          (unsigned)wrap(y0 - 1 + (int)hy, n);
+      const size_t src = (size_t)zy * (unsigned)n + (unsigned)wrap(x0 - 1 + (int)hx, n);
+      __builtin_memcpy(&pre[k], ib + src * 32 + c * 8, 16);
     }
   };
   fetch(blockIdx.x);
@@ -184,6 +185,14 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
     origin(t, x0, y0, z0, base);
     const int lane = tid & 63, wave = tid >> 6;  // (tid: opaque, see above)
     const int row = lane & 15, grp = lane >> 4;
+    // the wave's rows (y0 + r, z0 + wave) for r < CROWS = CTY: the halo slab
+    // hz = wave + 1 + dz starts at wtile; lslot: the lane's slot offset for
+    // dx = -1, 0, 1 (cslot of hx = row + 1 + dx, channel chunk grp)
+    static_assert(CROWS == CTY, "a wave's rows are one z-row of the tile");
+    const u32x4* wtile = tile + ((wave + 1) * CHY) * CHX * 4;
+    int lslot[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lslot[d] = cslot(0, row + d, grp) + (row + d) * 4;
     f32x4 acc[CROWS][COT / 16];
 #pragma unroll
     for (int r = 0; r < CROWS; ++r)
@@ -215,12 +224,11 @@ __global__ __launch_bounds__(256, 3) void k_conv(const unsigned short* __restric
       const int dx = NT == 27 ? tap % 3 - 1 : 0;
       const int dy = NT == 27 ? (tap / 3) % 3 - 1 : tap % 3 - 1;
       const int dz = NT == 27 ? tap / 9 - 1 : tap / 3 - 1;
-      const int hx = row + 1 + dx;
 #pragma unroll
       for (int r = 0; r < CROWS; ++r) {
-        const int j = wave * CROWS + r;
-        const int hy = j % CTY + 1 + dy, hz = j / CTY + 1 + dz;
-        const u32x4 raw = tile[cslot((hz * CHY + hy) * CHX + hx, hx, grp)];
+        // row r of the wave: hy = r + 1 + dy, hz = wave + 1 + dz; the lane's
+        // part of the slot depends on dx only, the rest is a constant
+        const u32x4 raw = wtile[lslot[dx + 1] + ((dz * CHY + r + 1 + dy) * CHX) * 4];
         bf16x8 a;
         __builtin_memcpy(&a, &raw, 16);
 #pragma unroll
