@@ -97,8 +97,8 @@ def rollout_backward(s: Solver, cks, dts, K: int, lam, keep=None):
                 s.step(1, float(dts[k]))
         # the potential each replayed step solved for: the next step's
         # starting one, and the solver's after the last
-        phi_after = [snap.phi for snap in inputs[1:]] + [
-            s.potential_device() if _gravity_on(s) else None]
+        phi_after = ([snap.phi for snap in inputs[1:]] +
+                     [s.potential_device() if _gravity_on(s) else None]) if keep else None
         for k in range(k1 - 1, k0 - 1, -1):
             snap = inputs[k - k0]
             kk = (kept[k - k0] + (phi_after[k - k0],)) if keep else None
