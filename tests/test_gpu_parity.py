@@ -381,6 +381,22 @@ def test_gravity_wcycle_host_levels_64(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gravity_non_power_of_two_levels(dtype):
+    """48^3: host-launched levels 48 and 24 (colour passes with 24 and 12
+    cells of a colour per row), the single-workgroup tail from 12^3 down to
+    an odd 3^3 coarsest grid (the one-wave sweeps), red-black V-cycles."""
+    n = 48
+    U0 = wl.grf_density_state(n, seed=4)
+    s, sim = run_both((n, n, n), (1 / n,) * 3, U0, dtype, 2,
+                      flags=oracle.SRC_GRAVITY | oracle.SRC_COOLING, grav_G=wl.JEANS_G,
+                      mg_tol=0.0, mg_max_cycles=3)
+    assert s.mg_cycles() == 3
+    assert rel_err(s.get_state(), sim.U) < TOL[dtype]
+    phi = s.potential().astype(np.float64)
+    assert np.abs(phi - sim.phi).max() < 10 * TOL[dtype] * np.abs(sim.phi).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n", [16, 32])
 def test_gravity_spectral_solver(dtype, n):
     """The spectral Poisson solve and gradient of Sec. 6.1 (own FFT kernels)
