@@ -23,8 +23,10 @@
 // live in LDS (with a 2-cell x/y halo); the z-stencil is a register ring of
 // four planes per thread, so the kernel marches along z and touches each
 // plane once.  Every face flux is computed exactly once per tile: x faces by
-// the thread on their left (plus the tile's left edge), y faces likewise, z
-// faces by the column's thread, carried from one plane to the next.
+// the thread on their left, which takes the limited x slope of the cell on
+// the right from the next lane of its wave (the tile's left and right edges by
+// lanes of one wave), y faces by the thread below (plus the tile's lower
+// edge), z faces by the column's thread, carried from one plane to the next.
 // Floating-point contraction is off in this file and every fused multiply-add
 // is written out: the compiler may not fuse a product into a sum at one call
 // site of the face flux and not at another, so each face gets bit-identical
@@ -279,9 +281,23 @@ __device__ __forceinline__ void store_lane(T* __restrict__ base, long long N, ui
   }
 }
 
-// Each row of the tile (fixed ty) is exactly one wave, so the lower-edge
-// faces below can be given to whole waves.
-static_assert(TX == 64 && TY <= TX, "one wave per tile row");
+// the value this quantity has in lane + 1 of the wave (a DPP wave shift
+// left by one lane); lane 63 receives 0
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_next_lane(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xf, 0xf, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Each row of the tile (fixed ty) is exactly one wave, so a lane's x
+// neighbour is the next lane and the edge faces below can be given to whole
+// waves.
+static_assert(TX == 64 && 2 * TY <= TX, "one wave per tile row; the edge wave takes 2 TY x faces");
 
 template <typename T, int STAGE, int LIM, bool FORCE, bool COOL>
 __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(const StageArgs<T> a) {
@@ -423,33 +439,39 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
 
     {
       T c0[5], c1[5], c2[5], c3[5], F[5];
-      // x face at x + 1/2
+      // x face at x + 1/2: the limited x slope of this lane's cell (its W is
+      // w[1]), and that of the next cell taken from lane + 1, which computed it
+      // as its own; lane 63's face is the tile's right edge, taken below
+      {
+        T dx0[5], dx1[5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        c0[f] = sW[f][ty + 2][tx + 1];
-        c1[f] = sW[f][ty + 2][tx + 2];
-        c2[f] = sW[f][ty + 2][tx + 3];
-        c3[f] = sW[f][ty + 2][tx + 4];
+        for (int f = 0; f < 5; ++f) {
+          c0[f] = sW[f][ty + 2][tx + 1];
+          c2[f] = sW[f][ty + 2][tx + 3];
+          dx0[f] = limited_slope<T, LIM>(c0[f], w[1][f], c2[f], a.lim);
+          dx1[f] = LIM == LIM_NONE ? T(0) : from_next_lane(dx0[f]);
+        }
+        face_flux_sl<T, 0, LIM>(w[1], dx0, c2, dx1, gamma, gm1inv, a.rs, F);
       }
-      face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
       if (LIM == LIM_GENERIC && a.dflux) add_dflux(a.dflux, N, (long long)z * plane + col, F);
+      if (tx < TX - 1) {
 #pragma unroll
-      for (int f = 0; f < 5; ++f) sFx[f][ty][tx + 1] = F[f];
+        for (int f = 0; f < 5; ++f) sFx[f][ty][tx + 1] = F[f];
+      }
       // y face at y + 1/2
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
         c0[f] = sW[f][ty + 1][tx + 2];
-        c1[f] = sW[f][ty + 2][tx + 2];
         c2[f] = sW[f][ty + 3][tx + 2];
         c3[f] = sW[f][ty + 4][tx + 2];
       }
-      face_flux<T, LIM, 1>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
+      face_flux<T, LIM, 1>(c0, w[1], c2, c3, gamma, gm1inv, a.lim, a.rs, F);
       if (LIM == LIM_GENERIC && a.dflux) add_dflux(a.dflux, N, (long long)z * plane + col, F);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sFy[f][ty + 1][tx] = F[f];
-      // the tile's lower-edge faces: the TX y faces at y0 - 1/2 by the wave
-      // of row 0, the TY x faces at x0 - 1/2 by lanes of the wave of row 1,
-      // so two waves (not every wave) carry the extra flux
+      // the tile's edge faces: the TX y faces at y0 - 1/2 by the wave of row
+      // 0; the TY x faces at x0 - 1/2 and the TY at x0 + TX - 1/2 by lanes of
+      // the wave of row 1, so two waves (not every wave) carry the extra flux
       if (ty == 0) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
@@ -466,22 +488,25 @@ __global__ __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) void k_stage(cons
                     F);
 #pragma unroll
         for (int f = 0; f < 5; ++f) sFy[f][0][tx] = F[f];
-      } else if (ty == 1 && tx < TY) {
+      } else if (ty == 1 && tx < 2 * TY) {
+        // lane r < TY: row r's face at x0 - 1/2 (LDS columns 0..3); lane
+        // TY + r: its face at x0 + TX - 1/2 (columns TX..TX+3)
+        const int r = tx < TY ? tx : tx - TY, xc = tx < TY ? 0 : TX;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          c0[f] = sW[f][tx + 2][0];
-          c1[f] = sW[f][tx + 2][1];
-          c2[f] = sW[f][tx + 2][2];
-          c3[f] = sW[f][tx + 2][3];
+          c0[f] = sW[f][r + 2][xc];
+          c1[f] = sW[f][r + 2][xc + 1];
+          c2[f] = sW[f][r + 2][xc + 2];
+          c3[f] = sW[f][r + 2][xc + 3];
         }
         face_flux<T, LIM, 0>(c0, c1, c2, c3, gamma, gm1inv, a.lim, a.rs, F);
         if (LIM == LIM_GENERIC && a.dflux)
           add_dflux(a.dflux, N,
-                    (long long)z * plane + (long long)bc_map(y0 + tx, a.ny, a.bcy) * a.nx +
-                        bc_map(x0 - 1, a.nx, a.bcx),
+                    (long long)z * plane + (long long)bc_map(y0 + r, a.ny, a.bcy) * a.nx +
+                        bc_map(x0 - 1 + xc, a.nx, a.bcx),
                     F);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) sFx[f][tx][0] = F[f];
+        for (int f = 0; f < 5; ++f) sFx[f][r][xc] = F[f];
       }
     }
     T fzp[5], dz2[5];
